@@ -1,0 +1,191 @@
+"""SupPCG benchmark on one MI355X.
+
+Workload: 512x512 image, 720 angles over [0, pi), 725 unit bins; random-ellipse
+phantom (20 ellipses, seed 1) with 0.5% Gaussian noise; K = 1, a = 0.5,
+gamma = 0.5 (first trial step 0.5^k), ramp-Hamming preconditioner
+(mu = 1e-5, rho = 0.8).  One step = one SupPCG iteration (S_TV + U_PCG: two
+projections R, two backprojections R^T, one preconditioner apply, TV work and
+the CG updates).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(name="ct512", rows=512, cols=512, n_angles=720, n_bins=725, ellipses=20, seed=1,
+                noise=0.005)
+NNZ_CT512 = 240_840_942          # rays x pixels with nonzero intersection length (computed)
+PEAK_HBM = 8.0e12                # B/s
+# Non-packed FP32 VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz.  The published
+# 157.3 TFLOP/s counts an FMA as 2 flops on 2-wide packed lanes.
+PEAK_VALU_OPS = 256 * 64 * 2.4e9
+OPS_PER_NNZ = 4                  # offset fma, weight fma, clamp, accumulate fma
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--reps", type=int, default=20, help="timed calls per operator")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--eager", action="store_true", help="launch the loop eagerly, no graph")
+    return ap.parse_args()
+
+
+def cpu_baseline(img, b):
+    """The float64 oracle on the host: R and R^T on a sample of angles (CSR built
+    outside the timed region, as the oracle caches it), M, S_TV and the CG vector
+    work at full size; one iteration extrapolated."""
+    import scipy.sparse as sps
+
+    from oracle import closed_form, precond, suppcg, tv
+    from oracle.geometry import Geometry as OG
+
+    og = OG(WORKLOAD["rows"], WORKLOAD["cols"], WORKLOAD["n_angles"], WORKLOAD["n_bins"])
+    n_sample = 36
+    angles = np.linspace(0, og.n_angles - 1, n_sample).astype(int)
+    blocks = [closed_form.angle_block(og, int(a)) for a in angles]
+    Rs = sps.vstack(blocks, format="csr")
+    RsT = Rs.T.tocsr()
+    x = img.astype(np.float64).ravel()
+    y = b.astype(np.float64).reshape(og.n_angles, og.n_bins)[angles].ravel()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        Rs @ x
+    t_r = (time.perf_counter() - t0) / reps * (og.n_angles / n_sample)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        RsT @ y
+    t_rt = (time.perf_counter() - t0) / reps * (og.n_angles / n_sample)
+    xi = img.astype(np.float64)
+    t0 = time.perf_counter()
+    precond.apply(xi, 1e-5, 0.8)
+    t_m = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    suppcg.s_tv(xi, 0, suppcg.TVParams(1, 0.5, 0.5))
+    t_stv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(5):
+        v = x * 0.5 + x
+        float(v @ x)
+    t_vec = (time.perf_counter() - t0) / 5 * 2
+    t_it = 2 * t_r + 2 * t_rt + t_m + t_stv + t_vec
+    return {"value": 1.0 / t_it, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+            "sample": (f"float64 NumPy/SciPy oracle, one thread: R and R^T SpMV on {n_sample} of "
+                       f"{og.n_angles} angles scaled to all angles, M, S_TV and vector work at full "
+                       f"size; one iteration = 2 R + 2 R^T + M + S_TV + vector work; "
+                       f"R {t_r*1e3:.0f} ms, R^T {t_rt*1e3:.0f} ms, M {t_m*1e3:.0f} ms, "
+                       f"S_TV {t_stv*1e3:.0f} ms")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of "
+              "this path is a design note, not a measured configuration.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1807_10151_amd as sp
+    from synth import noisy_data, random_ellipses, unit_noise
+
+    dev = torch.device("cuda:0")
+    w = WORKLOAD
+    g = sp.Geometry(w["rows"], w["cols"], w["n_angles"], w["n_bins"])
+    img, rng = random_ellipses(w["rows"], w["cols"], w["ellipses"], w["seed"])
+    x_true = torch.from_numpy(img.astype(np.float32)).to(dev)
+    b_exact = sp.sp_project(g, x_true)
+    noise = unit_noise(rng, g.m)
+    b_np = noisy_data(b_exact.cpu().numpy().ravel(), noise, w["noise"]).astype(np.float32)
+    b = torch.from_numpy(b_np.reshape(g.n_angles, g.n_bins)).to(dev)
+    torch.cuda.synchronize()
+
+    # --- operator timings (HIP events on the library's stream = torch's current stream)
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    yout = torch.empty((g.n_angles, g.n_bins), device=dev)
+    xout = torch.empty((g.rows, g.cols), device=dev)
+    ms_R = timed(lambda: sp.sp_project(g, x_true, yout), args.reps)
+    ms_RT = timed(lambda: sp.sp_backproject(g, b, xout), args.reps)
+    ms_M = timed(lambda: sp.sp_precond_apply(g, xout, 1e-5, 0.8), args.reps)
+
+    # --- SupPCG iterations
+    kw = dict(K=1, a=0.5, gamma=0.5, mu=1e-5, rho=0.8, graph=not args.eager, trace=True)
+    if args.warmup > 0:
+        sp.sp_suppcg_solve(g, b, None, max_iter=args.warmup, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    res = sp.sp_suppcg_solve(g, b, None, max_iter=args.steps, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    value = args.steps / (ms_total / 1e3)
+
+    bytes_equiv = 8 * NNZ_CT512 + 4 * g.n + 4 * g.m
+    dom_name, dom_ms = ("backproject", ms_RT) if ms_RT >= ms_R else ("project", ms_R)
+    achieved = OPS_PER_NNZ * NNZ_CT512 / (dom_ms / 1e3)
+    out = {
+        "metric": "SupPCG iterations/s at 512^2 x 720 angles x 725 bins",
+        "value": round(value, 3),
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 data, f64 CG scalars and reductions",
+        "data": "synthetic random-ellipse phantom (20 ellipses, seed 1), 0.5% Gaussian noise",
+        "config": {"workload": "ct512: 512x512 image, 720 angles over [0,pi), 725 bins, "
+                               "SupPCG K=1 a=0.5 gamma=0.5, ramp-Hamming M mu=1e-5 rho=0.8",
+                   "iterations": args.steps, "graph": not args.eager},
+        "roofline": {"bound": "alu", "kernel": dom_name,
+                     "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_OPS / 1e12, 4),
+                     "unit": "Tops/s (FP32 VALU lane-ops)",
+                     "frac": round(achieved / PEAK_VALU_OPS, 4), "traffic": None},
+        "operators_ms": {"project": round(ms_R, 4), "backproject": round(ms_RT, 4),
+                         "precond": round(ms_M, 4)},
+        "gbps_equiv": {"project": round(bytes_equiv / (ms_R / 1e3) / 1e9, 1),
+                       "backproject": round(bytes_equiv / (ms_RT / 1e3) / 1e9, 1),
+                       "frac_of_8TBps_project": round(bytes_equiv / (ms_R / 1e3) / PEAK_HBM, 3),
+                       "frac_of_8TBps_backproject": round(bytes_equiv / (ms_RT / 1e3) / PEAK_HBM, 3)},
+        "solve": {"k": res.k, "status": res.status_name, "wall_s": round(wall, 4),
+                  "f_last": float(res.trace["f_half"][-1]) if len(res.trace["f_half"]) else None,
+                  "ell_last": int(res.trace["ell"][-1]) if len(res.trace["ell"]) else None},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(img, b_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

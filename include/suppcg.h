@@ -1,0 +1,193 @@
+/*
+ * suppcg.h -- C ABI of the MI355X (gfx950) SupPCG library, libsuppcg.so.
+ *
+ * Superiorized preconditioned conjugate gradients for least-squares
+ * tomography (Helou, Herman, Lin, Zibetti).  The library solves R x ~ b in the
+ * least-squares sense (Section 2, eq. 2.1) through the normal equations
+ * R^T R x = R^T b (eq. 2.2) with Algorithm 3 (SupPCG): each iteration perturbs
+ * the iterate with Algorithm 1 (S_TV, total-variation superiorization,
+ * Section 3.1) and then takes one Algorithm 2 (U_PCG) step, preconditioned by
+ * M = F^-1 D F with the ramp-Hamming window of eq. (3.2).
+ *
+ * Conventions shared by every call:
+ *  - Pointers to float/double/int32 data are DEVICE pointers (HBM of the
+ *    context's GPU) unless a comment says "host".  The caller owns every data
+ *    buffer; the library never frees caller memory.  The context owns its
+ *    workspace (padded copies, FFT scratch, reduction partials, scalars), sized
+ *    per geometry on first use and freed by sp_ctx_destroy.
+ *  - Images are float32 [rows][cols], row-major: pixel (i, j) (0-based, row 0
+ *    at the top) is element i*cols + j, as in the paper's TV definition
+ *    (Section 3.1).  Its centre is x_j = (j - (cols-1)/2) * pixel,
+ *    y_i = ((rows-1)/2 - i) * pixel.
+ *  - Data (sinograms) are float32 [n_angles][n_bins], angle-major: ray (a, k)
+ *    is element a*n_bins + k.  Ray (a, k) is the line
+ *    x cos(theta_a) + y sin(theta_a) = s_k with theta_a = theta0 + a*dtheta and
+ *    s_k = (k - (n_bins-1)/2) * bin_spacing + bin_offset (Section 4.1 uses
+ *    equally spaced angles in [0, pi) and equally spaced parallel rays).
+ *  - R[(a,k),(i,j)] is the length of ray (a, k) inside pixel (i, j); a ray
+ *    running exactly along a pixel edge gives each adjacent pixel half a pixel.
+ *  - Every call enqueues work on the context's stream and returns before it
+ *    finishes, except where noted.  Arguments are validated before anything is
+ *    enqueued; on error nothing is enqueued and sp_last_error() describes it.
+ *  - Calls on one context are not thread-safe; use one context per thread.
+ *  - Accumulation: data are float32; every dot product, norm, TV value and CG
+ *    scalar (alpha, beta, p^T h, f) is accumulated and kept in float64, with
+ *    fixed-order (deterministic) reductions.
+ */
+#ifndef SUPPCG_H
+#define SUPPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    SP_OK = 0,
+    SP_ERR_ARG = 1,          /* invalid argument (message in sp_last_error)      */
+    SP_ERR_NOT_SPD = 2,      /* preconditioner parameters give an indefinite M   */
+    SP_ERR_NONFINITE = 3,    /* a NaN/Inf reached a CG scalar                    */
+    SP_ERR_HIP = 4,          /* HIP runtime error                                */
+    SP_ERR_ALLOC = 5,        /* device allocation failed                         */
+    /* informational results of sp_suppcg_solve (the outputs are valid):        */
+    SP_MAXITER = 16,         /* max_iter loop bodies ran, f(x_{k-1/2}) > eps     */
+    SP_CONVERGED = 17,       /* stopped because f(x_{k-1/2}) <= eps (Alg. 3)     */
+    SP_BREAKDOWN_CONVERGED = 18, /* p^T h == 0: p = 0, the CG step is exact    */
+    SP_TRIALS_EXHAUSTED = 19 /* some S_TV inner step accepted no trial          */
+};
+
+typedef struct sp_ctx sp_ctx;
+typedef struct sp_learned sp_learned;
+
+/* Parallel-beam geometry (Section 4.1).  dtheta <= 0 selects pi / n_angles.
+ * Limits: 1 <= rows, cols <= 8192; 1 <= n_angles, n_bins <= 65536;
+ * pixel > 0; bin_spacing >= 0.375 pixel. */
+typedef struct {
+    int32_t rows, cols;
+    double pixel;
+    int32_t n_angles;
+    double theta0, dtheta;
+    int32_t n_bins;
+    double bin_spacing, bin_offset;
+} sp_geometry;
+
+/* Algorithm 1 parameters: K nonascending steps, step-length factor a in (0,1),
+ * starting step gamma > 0.  The paper's repeat-until loop has no bound; here
+ * an inner step tries at most max_trials step lengths (0 -> 100) and, if none
+ * is accepted, leaves the image unchanged while keeping every increment of l.
+ * Limits: 0 <= K <= 1000, 0 <= max_trials <= 10000. */
+typedef struct {
+    int32_t K;
+    double a, gamma;
+    int32_t max_trials;
+} sp_tv_params;
+
+/* Preconditioner (Section 3.2).  SP_PRECOND_RAMP: M = E^T F^-1 D F E with
+ * D = h(|omega|), h(w) = (|w| + mu)(rho + (1 - rho) cos w) (eq. 3.2), on the
+ * radial frequency of a zero-padded P x P grid, P = 2^ceil(log2(2 max(rows,
+ * cols))); requires mu > 0 and 1/2 < rho <= 1 (else SP_ERR_NOT_SPD) and
+ * images of at most 2048 pixels a side.
+ * SP_PRECOND_NONE: M = I (plain CG).  SP_PRECOND_LEARNED: the network `net`. */
+enum { SP_PRECOND_NONE = 0, SP_PRECOND_RAMP = 1, SP_PRECOND_LEARNED = 2 };
+typedef struct {
+    int32_t kind;
+    double mu, rho;
+    const sp_learned* net;
+} sp_precond;
+
+/* Solver controls.  eps: Algorithm 3's termination level (eps <= 0 disables
+ * the test and runs exactly max_iter loop bodies).  flags: SP_FLAG_REPLAY makes
+ * each S_TV inner step accept exactly after replay_trials[k*K + i] trials
+ * (host array, max_iter*K entries; a value > max_trials means "no trial
+ * accepted") instead of testing TV -- used to separate arithmetic differences
+ * from control-flow differences. SP_FLAG_GRAPH captures one loop body in a
+ * HIP graph and replays it. */
+enum { SP_FLAG_REPLAY = 1u, SP_FLAG_GRAPH = 2u };
+typedef struct {
+    double eps;
+    int32_t max_iter;
+    uint32_t flags;
+    const int32_t* replay_trials; /* host; nullable unless SP_FLAG_REPLAY */
+} sp_solve_params;
+
+/* Per-iteration trace (all HOST arrays, capacity `cap` iterations; any pointer
+ * may be NULL).  Entry k-1 belongs to loop body k: f_half = f(x_{k+1/2}),
+ * tv_half = TV(x_{k+1/2}) as evaluated by the accepted trial, ell = l_{k+1},
+ * alpha/beta of U_PCG, s_norm = ||s_k||; trials has cap*K entries. */
+typedef struct {
+    double* f_half;
+    double* tv_half;
+    double* alpha;
+    double* beta;
+    double* s_norm;
+    int32_t* ell;
+    int32_t* trials;
+    int32_t cap;
+    double f0;      /* out: f(x_0) */
+    double alpha0;  /* out: alpha of the initial step (Alg. 3, step 6) */
+} sp_trace;
+
+/* ---- context ------------------------------------------------------------ */
+/* Creates a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+int sp_ctx_create(int device, void* hip_stream, sp_ctx** out);
+int sp_ctx_destroy(sp_ctx* ctx);
+/* Changes the stream later calls enqueue on. */
+int sp_ctx_set_stream(sp_ctx* ctx, void* hip_stream);
+/* Host string describing the last failure on ctx; valid until the next call. */
+const char* sp_last_error(const sp_ctx* ctx);
+/* Library version string (host, static). */
+const char* sp_version(void);
+
+/* ---- operators ------------------------------------------------------------ */
+/* y = R x (Section 2: the projection matrix applied to image x).
+ * x: [rows][cols] float32 (device, read); y: [n_angles][n_bins] (device, written). */
+int sp_project(sp_ctx* ctx, const sp_geometry* g, const float* x, float* y);
+
+/* x = R^T y, the exact transpose of sp_project's weights (same weight for
+ * every (ray, pixel) pair, bit for bit), pixel-driven, no atomics (eq. 2.2).
+ * y: [n_angles][n_bins] (device, read); x: [rows][cols] (device, written). */
+int sp_backproject(sp_ctx* ctx, const sp_geometry* g, const float* y, float* x);
+
+/* r = R x - b and *f = ||r||^2 (float64, device scalar) -- the primary
+ * criterion f(x) = ||Rx - b||^2 of Section 2.  r may equal NULL. */
+int sp_residual(sp_ctx* ctx, const sp_geometry* g, const float* x, const float* b,
+                float* r, double* f);
+
+/* z = M g with the preconditioner of Section 3.2 (see sp_precond).
+ * g, z: [rows][cols] (device); g and z may alias. */
+int sp_precond_apply(sp_ctx* ctx, const sp_geometry* g, const sp_precond* pc,
+                     const float* gin, float* z);
+
+/* *tv = TV(x) (Section 3.1), float64 device scalar. */
+int sp_tv(sp_ctx* ctx, const sp_geometry* g, const float* x, double* tv);
+
+/* t_bar = minus the gradient of TV where defined, 0 elsewhere (Section 3.1);
+ * *norm2 = ||t_bar||^2 (float64 device scalar, nullable). */
+int sp_tv_grad(sp_ctx* ctx, const sp_geometry* g, const float* x, float* tbar, double* norm2);
+
+/* Algorithm 1: (s, l) = S_TV(x, l, a, gamma, K); writes x_half = x + s.
+ * ell: device int32, read and updated in place.  tv_half: device float64,
+ * TV(x_half) (nullable).  trials: device int32[K], trials used by each inner
+ * step, max_trials + 1 when none was accepted (nullable). */
+int sp_tv_perturb(sp_ctx* ctx, const sp_geometry* g, const sp_tv_params* p, const float* x,
+                  int32_t* ell, float* x_half, double* tv_half, int32_t* trials);
+
+/* ---- solver ----------------------------------------------------------------- */
+/* Algorithm 3, SupPCG(x0, a, gamma, K, eps).  tv = NULL or K = 0 gives plain
+ * PCG (CG with SP_PRECOND_NONE).  b: [n_angles][n_bins]; x0: [rows][cols]
+ * (NULL = zero image).  x_out receives x_{k-1/2}, the paper's output;
+ * x_last (nullable) receives x_k.  *k_out (host) receives k.  Blocks until
+ * the run has finished.  Returns SP_MAXITER, SP_CONVERGED,
+ * SP_BREAKDOWN_CONVERGED or SP_TRIALS_EXHAUSTED on success (outputs valid),
+ * an SP_ERR_* code otherwise. */
+int sp_suppcg_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const float* x0,
+                    const sp_tv_params* tv, const sp_precond* pc, const sp_solve_params* sp,
+                    float* x_out, float* x_last, int32_t* k_out, sp_trace* trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUPPCG_H */

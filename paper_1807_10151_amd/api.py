@@ -1,0 +1,270 @@
+"""Thin PyTorch binding over libsuppcg (same names as the C ABI).
+
+PyTorch provides device memory and the stream; every step runs in the HIP
+library.  Tensors must be float32, contiguous and on the context's GPU;
+outputs are allocated here when not given.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class SupPCGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{L.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+@dataclass(frozen=True)
+class Geometry:
+    """Parallel-beam geometry; dtheta = None means pi / n_angles."""
+    rows: int
+    cols: int
+    n_angles: int
+    n_bins: int
+    pixel: float = 1.0
+    theta0: float = 0.0
+    dtheta: float | None = None
+    bin_spacing: float = 1.0
+    bin_offset: float = 0.0
+
+    @property
+    def n(self):
+        return self.rows * self.cols
+
+    @property
+    def m(self):
+        return self.n_angles * self.n_bins
+
+    def c(self):
+        return L.sp_geometry(self.rows, self.cols, self.pixel, self.n_angles, self.theta0,
+                             -1.0 if self.dtheta is None else self.dtheta, self.n_bins,
+                             self.bin_spacing, self.bin_offset)
+
+
+class Context:
+    """Owns one sp_ctx on a GPU; calls enqueue on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream(device).cuda_stream
+            rc = self.lib.sp_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(h))
+        if rc != L.SP_OK:
+            raise SupPCGError(rc, "sp_ctx_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.sp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.sp_ctx_set_stream(self.h, ctypes.c_void_p(s))
+
+    def _check(self, rc, ok=(L.SP_OK,)):
+        if rc not in ok:
+            raise SupPCGError(rc, self.lib.sp_last_error(self.h).decode())
+        return rc
+
+
+_CTX: dict = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _CTX:
+        _CTX[device] = Context(device)
+    return _CTX[device]
+
+
+def _dev(t: torch.Tensor, n: int, name: str, device: int):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, context is on cuda:{device}")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} elements (got {tuple(t.shape)})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _out(t, shape, device):
+    if t is None:
+        return torch.empty(shape, dtype=torch.float32, device=f"cuda:{device}")
+    return t
+
+
+def sp_project(g: Geometry, x: torch.Tensor, y: torch.Tensor | None = None, ctx: Context | None = None):
+    """y = R x: [rows, cols] -> [n_angles, n_bins]."""
+    ctx = ctx or context(x.device.index or 0)
+    y = _out(y, (g.n_angles, g.n_bins), ctx.device)
+    ctx._stream()
+    gc = g.c()
+    ctx._check(ctx.lib.sp_project(ctx.h, ctypes.byref(gc), _dev(x, g.n, "x", ctx.device),
+                                  _dev(y, g.m, "y", ctx.device)))
+    return y
+
+
+def sp_backproject(g: Geometry, y: torch.Tensor, x: torch.Tensor | None = None, ctx: Context | None = None):
+    """x = R^T y: [n_angles, n_bins] -> [rows, cols]."""
+    ctx = ctx or context(y.device.index or 0)
+    x = _out(x, (g.rows, g.cols), ctx.device)
+    ctx._stream()
+    gc = g.c()
+    ctx._check(ctx.lib.sp_backproject(ctx.h, ctypes.byref(gc), _dev(y, g.m, "y", ctx.device),
+                                      _dev(x, g.n, "x", ctx.device)))
+    return x
+
+
+def sp_residual(g: Geometry, x: torch.Tensor, b: torch.Tensor, ctx: Context | None = None):
+    """(r, f): r = R x - b and f = ||r||^2 (float64, 0-d CUDA tensor)."""
+    ctx = ctx or context(x.device.index or 0)
+    r = _out(None, (g.n_angles, g.n_bins), ctx.device)
+    f = torch.empty((), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    ctx._stream()
+    gc = g.c()
+    ctx._check(ctx.lib.sp_residual(ctx.h, ctypes.byref(gc), _dev(x, g.n, "x", ctx.device),
+                                   _dev(b, g.m, "b", ctx.device), _dev(r, g.m, "r", ctx.device),
+                                   ctypes.c_void_p(f.data_ptr())))
+    return r, f
+
+
+def _precond(kind, mu, rho):
+    k = {"ramp": L.SP_PRECOND_RAMP, "none": L.SP_PRECOND_NONE}[kind] if isinstance(kind, str) else kind
+    return L.sp_precond(k, mu, rho, None)
+
+
+def sp_precond_apply(g: Geometry, gin: torch.Tensor, mu: float = 1e-5, rho: float = 0.8,
+                     kind="ramp", z: torch.Tensor | None = None, ctx: Context | None = None):
+    """z = M g with the ramp-Hamming Fourier preconditioner (or M = I)."""
+    ctx = ctx or context(gin.device.index or 0)
+    z = _out(z, (g.rows, g.cols), ctx.device)
+    ctx._stream()
+    gc = g.c()
+    pc = _precond(kind, mu, rho)
+    ctx._check(ctx.lib.sp_precond_apply(ctx.h, ctypes.byref(gc), ctypes.byref(pc),
+                                        _dev(gin, g.n, "g", ctx.device), _dev(z, g.n, "z", ctx.device)))
+    return z
+
+
+def sp_tv(g: Geometry, x: torch.Tensor, ctx: Context | None = None):
+    """TV(x) as a float64 0-d CUDA tensor."""
+    ctx = ctx or context(x.device.index or 0)
+    out = torch.empty((), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    ctx._stream()
+    gc = g.c()
+    ctx._check(ctx.lib.sp_tv(ctx.h, ctypes.byref(gc), _dev(x, g.n, "x", ctx.device),
+                             ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def sp_tv_grad(g: Geometry, x: torch.Tensor, ctx: Context | None = None):
+    """(t_bar, ||t_bar||^2)."""
+    ctx = ctx or context(x.device.index or 0)
+    tb = _out(None, (g.rows, g.cols), ctx.device)
+    n2 = torch.empty((), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    ctx._stream()
+    gc = g.c()
+    ctx._check(ctx.lib.sp_tv_grad(ctx.h, ctypes.byref(gc), _dev(x, g.n, "x", ctx.device),
+                                  _dev(tb, g.n, "tbar", ctx.device), ctypes.c_void_p(n2.data_ptr())))
+    return tb, n2
+
+
+def sp_tv_perturb(g: Geometry, x: torch.Tensor, ell: int, K: int, a: float, gamma: float,
+                  max_trials: int = 100, ctx: Context | None = None):
+    """Algorithm 1.  Returns (x_half, ell, TV(x_half), trials per inner step)."""
+    ctx = ctx or context(x.device.index or 0)
+    dev = f"cuda:{ctx.device}"
+    xh = torch.empty((g.rows, g.cols), dtype=torch.float32, device=dev)
+    ell_t = torch.tensor([ell], dtype=torch.int32, device=dev)
+    tvh = torch.empty((), dtype=torch.float64, device=dev)
+    trials = torch.zeros(max(K, 1), dtype=torch.int32, device=dev)
+    ctx._stream()
+    gc = g.c()
+    p = L.sp_tv_params(K, a, gamma, max_trials)
+    ctx._check(ctx.lib.sp_tv_perturb(ctx.h, ctypes.byref(gc), ctypes.byref(p),
+                                     _dev(x, g.n, "x", ctx.device), ctypes.c_void_p(ell_t.data_ptr()),
+                                     _dev(xh, g.n, "x_half", ctx.device),
+                                     ctypes.c_void_p(tvh.data_ptr()),
+                                     ctypes.c_void_p(trials.data_ptr())))
+    return xh, int(ell_t.item()), float(tvh.item()), trials[:K].cpu().tolist()
+
+
+@dataclass
+class SolveResult:
+    k: int
+    x_half: torch.Tensor
+    x_last: torch.Tensor
+    status: int
+    trace: dict = field(default_factory=dict)
+
+    @property
+    def status_name(self):
+        return L.STATUS_NAMES.get(self.status, str(self.status))
+
+
+def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None, *,
+                    K: int = 1, a: float = 0.5, gamma: float = 0.5, max_trials: int = 100,
+                    precond="ramp", mu: float = 1e-5, rho: float = 0.8, max_iter: int = 20,
+                    eps: float = 0.0, graph: bool = False, replay=None, trace: bool = True,
+                    x_half: torch.Tensor | None = None, x_last: torch.Tensor | None = None,
+                    ctx: Context | None = None) -> SolveResult:
+    """Algorithm 3 (SupPCG); K = 0 gives plain PCG, precond="none" gives CG."""
+    ctx = ctx or context(b.device.index or 0)
+    dev = ctx.device
+    x_half = _out(x_half, (g.rows, g.cols), dev)
+    x_last = _out(x_last, (g.rows, g.cols), dev)
+    gc = g.c()
+    tvp = L.sp_tv_params(K, a, gamma, max_trials)
+    pc = _precond(precond, mu, rho)
+    flags = (L.SP_FLAG_GRAPH if graph else 0)
+    rep_arr = None
+    if replay is not None:
+        flags |= L.SP_FLAG_REPLAY
+        rep = np.ascontiguousarray(np.asarray(replay, dtype=np.int32).reshape(-1))
+        if rep.size < max_iter * max(K, 1):
+            raise ValueError("replay needs max_iter * K entries")
+        rep_arr = (ctypes.c_int32 * rep.size)(*rep.tolist())
+    sp = L.sp_solve_params(eps, max_iter, flags,
+                           ctypes.cast(rep_arr, ctypes.POINTER(ctypes.c_int32)) if rep_arr is not None else None)
+    cap = max(max_iter, 1)
+    tr = None
+    arrs = {}
+    if trace:
+        arrs = {"f_half": np.zeros(cap), "tv_half": np.zeros(cap), "alpha": np.zeros(cap),
+                "beta": np.zeros(cap), "s_norm": np.zeros(cap),
+                "ell": np.zeros(cap, dtype=np.int32), "trials": np.zeros(cap * max(K, 1), dtype=np.int32)}
+        dp = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        ip = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        tr = L.sp_trace(dp(arrs["f_half"]), dp(arrs["tv_half"]), dp(arrs["alpha"]), dp(arrs["beta"]),
+                        dp(arrs["s_norm"]), ip(arrs["ell"]), ip(arrs["trials"]), cap, 0.0, 0.0)
+    k_out = ctypes.c_int32(0)
+    ctx._stream()
+    rc = ctx.lib.sp_suppcg_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
+                                 _dev(x0, g.n, "x0", dev) if x0 is not None else None,
+                                 ctypes.byref(tvp), ctypes.byref(pc), ctypes.byref(sp),
+                                 _dev(x_half, g.n, "x_half", dev), _dev(x_last, g.n, "x_last", dev),
+                                 ctypes.byref(k_out), ctypes.byref(tr) if tr is not None else None)
+    ctx._check(rc, ok=(L.SP_MAXITER, L.SP_CONVERGED, L.SP_BREAKDOWN_CONVERGED, L.SP_TRIALS_EXHAUSTED))
+    out = {}
+    if trace:
+        done = min(max(k_out.value - 1, 0), cap)
+        out = {key: v[:done] if key != "trials" else v[:done * max(K, 1)].reshape(done, max(K, 1))
+               for key, v in arrs.items()}
+        out["f0"] = tr.f0
+        out["alpha0"] = tr.alpha0
+    return SolveResult(k_out.value, x_half, x_last, rc, out)

@@ -1,0 +1,757 @@
+// Host side of libsuppcg: argument validation, geometry tables, workspace
+// management and the SupPCG driver (Algorithm 3) behind the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/suppcg.h"
+#include "sp_internal.h"
+
+using namespace sp;
+
+namespace {
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct sp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // geometry cache
+    bool have_geom = false;
+    sp_geometry geom{};
+    GeomDev G{};
+    std::vector<AngleDev> ang_h;
+    DevBuf ang, xp, xTp, yp;
+
+    // preconditioner cache
+    int fftP = 0;
+    DevBuf tw, S;
+
+    // solver vectors and scratch
+    DevBuf vx, vp, vh, vg, vz, vtb, vtmp;
+    DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc;
+    DevBuf scal, trace_d, replay_d, trials_tmp;
+    Scalars sc_h{};
+    hipStream_t own = nullptr;   // capture stream used when the caller's stream is null
+};
+
+namespace {
+
+int fail(sp_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), SP_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+// Grows `b` to at least `bytes` (contents are not preserved); zero-fills new storage.
+int ensure(sp_ctx* c, DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes && b.ptr) return SP_OK;
+    if (b.ptr) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    bytes = std::max<size_t>(bytes, 256);
+    if (hipMalloc(&b.ptr, bytes) != hipSuccess) {
+        b.ptr = nullptr;
+        return fail(c, SP_ERR_ALLOC, "hipMalloc of %zu bytes failed", bytes);
+    }
+    b.bytes = bytes;
+    HIP_TRY(c, hipMemsetAsync(b.ptr, 0, bytes, c->stream));
+    return SP_OK;
+}
+
+void release(DevBuf& b) {
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+template <class T>
+T* dptr(DevBuf& b) { return static_cast<T*>(b.ptr); }
+
+bool same_geom(const sp_geometry& a, const sp_geometry& b) {
+    return std::memcmp(&a, &b, sizeof a) == 0;
+}
+
+int validate_geometry(sp_ctx* c, const sp_geometry* g) {
+    if (!g) return fail(c, SP_ERR_ARG, "geometry is NULL");
+    if (g->rows < 1 || g->cols < 1 || g->rows > 8192 || g->cols > 8192)
+        return fail(c, SP_ERR_ARG, "rows/cols must be in [1, 8192] (got %d x %d)", g->rows, g->cols);
+    if (g->n_angles < 1 || g->n_angles > 65536)
+        return fail(c, SP_ERR_ARG, "n_angles must be in [1, 65536] (got %d)", g->n_angles);
+    if (g->n_bins < 1 || g->n_bins > 65536)
+        return fail(c, SP_ERR_ARG, "n_bins must be in [1, 65536] (got %d)", g->n_bins);
+    if (!(g->pixel > 0.0) || !std::isfinite(g->pixel))
+        return fail(c, SP_ERR_ARG, "pixel must be positive and finite");
+    if (!(g->bin_spacing > 0.0) || !std::isfinite(g->bin_spacing))
+        return fail(c, SP_ERR_ARG, "bin_spacing must be positive and finite");
+    if (!std::isfinite(g->theta0) || !std::isfinite(g->dtheta) || !std::isfinite(g->bin_offset))
+        return fail(c, SP_ERR_ARG, "theta0, dtheta and bin_offset must be finite");
+    const double ds = g->bin_spacing / g->pixel;
+    if (ds < 0.375) return fail(c, SP_ERR_ARG, "bin_spacing below 0.375 pixel is not supported");
+    const double pitchB = (double)g->n_bins + 2 * PAD;
+    if ((double)g->n_angles * pitchB > 2.0e9) return fail(c, SP_ERR_ARG, "sinogram too large");
+    return SP_OK;
+}
+
+// cos/sin of angle index a, exact at multiples of pi/4.
+void angle_cos_sin(const sp_geometry& g, int a, double& co, double& si) {
+    const double dth = g.dtheta > 0.0 ? g.dtheta : M_PI / g.n_angles;
+    const double th = g.theta0 + a * dth;
+    const double q = th / (M_PI / 4.0);
+    const double m = std::nearbyint(q);
+    if (std::fabs(q - m) < 1e-12) {
+        static const double h = std::sqrt(0.5);
+        static const double tc[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
+        static const double ts[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
+        long long mi = (long long)m % 8;
+        if (mi < 0) mi += 8;
+        co = tc[mi];
+        si = ts[mi];
+    } else {
+        co = std::cos(th);
+        si = std::sin(th);
+    }
+}
+
+int setup_geometry(sp_ctx* c, const sp_geometry* g) {
+    int rc = validate_geometry(c, g);
+    if (rc) return rc;
+    if (c->have_geom && same_geom(c->geom, *g)) return SP_OK;
+    GeomDev G{};
+    G.rows = g->rows;
+    G.cols = g->cols;
+    G.nA = g->n_angles;
+    G.nB = g->n_bins;
+    G.xoff = (g->cols - 1) / 2.0;
+    G.yoff = (g->rows - 1) / 2.0;
+    const double ds = g->bin_spacing / g->pixel;
+    const double s0 = (-(g->n_bins - 1) / 2.0 * g->bin_spacing + g->bin_offset) / g->pixel;
+    G.ds = ds;
+    G.s0 = s0;
+    G.inv_ds = 1.0 / ds;
+    G.pixel = g->pixel;
+    G.xoff_f = (float)G.xoff;
+    G.yoff_f = (float)G.yoff;
+    G.ds_f = (float)ds;
+    G.s0_f = (float)s0;
+    G.pitchX = g->cols + 2 * PAD;
+    G.pitchXT = g->rows + 2 * PAD;
+    G.pitchB = g->n_bins + 2 * PAD;
+    const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
+    std::vector<AngleDev> tab(g->n_angles);
+    for (int a = 0; a < g->n_angles; ++a) {
+        double co, si;
+        angle_cos_sin(*g, a, co, si);
+        AngleDev A{};
+        A.c = co;
+        A.s = si;
+        const double ac = std::fabs(co), as = std::fabs(si);
+        const bool axis = ac == 0.0 || as == 0.0;
+        const bool horiz = as > ac;
+        const double e = 0.5 * (ac + as);
+        const double inv = axis ? 0.0 : 1.0 / (ac * as);
+        A.inv = inv;
+        A.einv = e * inv;
+        A.wmax = 1.0 / std::max(ac, as);
+        A.slope = horiz ? co / si : si / co;
+        const double hw = e / std::max(ac, as) + margin;
+        A.hw = (float)hw;
+        A.nc = (int)std::ceil(2.0 * hw);
+        const double hb = (e + margin) / ds;
+        A.nb = (int)std::ceil(2.0 * hb);
+        A.kb = -s0 / ds - hb;
+        A.row = a;
+        A.flags = (axis ? ANG_AXIS : 0) | (horiz ? ANG_HORIZ : 0);
+        if (A.nc < 2 || A.nc > 3 || A.nb < 1 || A.nb > 4)
+            return fail(c, SP_ERR_ARG, "unsupported geometry at angle %d (nc=%d nb=%d)", a, A.nc, A.nb);
+        tab[a] = A;
+    }
+    // Sort into the classes the backprojector loops over: vertical oblique,
+    // horizontal oblique, vertical axis-parallel, horizontal axis-parallel.
+    auto cls_of = [](const AngleDev& A) {
+        const bool axis = A.flags & ANG_AXIS, horiz = A.flags & ANG_HORIZ;
+        return (axis ? 2 : 0) + (horiz ? 1 : 0);
+    };
+    std::stable_sort(tab.begin(), tab.end(),
+                     [&](const AngleDev& x, const AngleDev& y) { return cls_of(x) < cls_of(y); });
+    G.nbmax = 1;
+    for (int q = 0; q <= 4; ++q) G.cls[q] = 0;
+    for (const AngleDev& A : tab) {
+        G.nbmax = std::max(G.nbmax, A.nb);
+        G.cls[cls_of(A) + 1] += 1;
+    }
+    for (int q = 1; q <= 4; ++q) G.cls[q] += G.cls[q - 1];
+    const size_t nX = (size_t)g->rows * G.pitchX, nXT = (size_t)g->cols * G.pitchXT;
+    const size_t nY = (size_t)g->n_angles * G.pitchB;
+    // Padded buffers must have zero pads: re-zero when the layout changes.
+    if ((rc = ensure(c, c->ang, tab.size() * sizeof(AngleDev)))) return rc;
+    const bool relayout = !c->have_geom || c->G.pitchX != G.pitchX || c->G.pitchXT != G.pitchXT ||
+                          c->G.pitchB != G.pitchB || c->G.rows != G.rows || c->G.cols != G.cols ||
+                          c->G.nA != G.nA;
+    if ((rc = ensure(c, c->xp, nX * 4))) return rc;
+    if ((rc = ensure(c, c->xTp, nXT * 4))) return rc;
+    if ((rc = ensure(c, c->yp, nY * 4))) return rc;
+    if (relayout) {
+        HIP_TRY(c, hipMemsetAsync(c->xp.ptr, 0, c->xp.bytes, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->xTp.ptr, 0, c->xTp.bytes, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->yp.ptr, 0, c->yp.bytes, c->stream));
+    }
+    c->ang_h = tab;
+    HIP_TRY(c, hipMemcpyAsync(c->ang.ptr, tab.data(), tab.size() * sizeof(AngleDev),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));  // host table must outlive the copy
+    c->G = G;
+    c->geom = *g;
+    c->have_geom = true;
+    return SP_OK;
+}
+
+int pad_size(int rows, int cols) {
+    int P = 1;
+    while (P < 2 * std::max(rows, cols)) P <<= 1;
+    return P;
+}
+
+int setup_fft(sp_ctx* c, FFTPlan& F) {
+    const sp_geometry& g = c->geom;
+    const int P = pad_size(g.rows, g.cols);
+    if (P > 4096) return fail(c, SP_ERR_ARG, "preconditioner supports images up to 2048 pixels a side");
+    int rc;
+    if (c->fftP != P) {
+        std::vector<double2> tw(P / 2);
+        for (int k = 0; k < P / 2; ++k) {
+            const double ang = -2.0 * M_PI * (double)k / (double)P;
+            tw[k] = make_double2(std::cos(ang), std::sin(ang));
+        }
+        if ((rc = ensure(c, c->tw, tw.size() * sizeof(double2)))) return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->tw.ptr, tw.data(), tw.size() * sizeof(double2),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->fftP = P;
+    }
+    const int SP = P / 2 + 1;
+    if ((rc = ensure(c, c->S, (size_t)g.rows * SP * sizeof(double2)))) return rc;
+    F.P = P;
+    F.logP = 0;
+    while ((1 << F.logP) < P) ++F.logP;
+    F.SP = SP;
+    F.rows = g.rows;
+    F.cols = g.cols;
+    F.CB = std::max(1, 2048 / P);
+    F.S = dptr<double2>(c->S);
+    F.tw = dptr<double2>(c->tw);
+    return SP_OK;
+}
+
+int check_precond(sp_ctx* c, const sp_precond* pc) {
+    if (!pc) return fail(c, SP_ERR_ARG, "preconditioner is NULL");
+    if (pc->kind == SP_PRECOND_NONE) return SP_OK;
+    if (pc->kind == SP_PRECOND_RAMP) {
+        if (!std::isfinite(pc->mu) || !std::isfinite(pc->rho))
+            return fail(c, SP_ERR_ARG, "mu and rho must be finite");
+        if (!(pc->mu > 0.0) || !(pc->rho > 0.5) || pc->rho > 1.0)
+            return fail(c, SP_ERR_NOT_SPD,
+                        "M is positive definite only for mu > 0 and 1/2 < rho <= 1 (mu=%g rho=%g)",
+                        pc->mu, pc->rho);
+        return SP_OK;
+    }
+    if (pc->kind == SP_PRECOND_LEARNED) return fail(c, SP_ERR_ARG, "learned preconditioner not available");
+    return fail(c, SP_ERR_ARG, "unknown preconditioner kind %d", pc->kind);
+}
+
+int check_tv(sp_ctx* c, const sp_tv_params* p) {
+    if (!p) return SP_OK;
+    if (p->K < 0 || p->K > 1000) return fail(c, SP_ERR_ARG, "K must be in [0, 1000]");
+    if (p->K == 0) return SP_OK;
+    if (!(p->a > 0.0 && p->a < 1.0)) return fail(c, SP_ERR_ARG, "a must be in (0, 1)");
+    if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return fail(c, SP_ERR_ARG, "gamma must be positive");
+    if (p->max_trials < 0 || p->max_trials > 10000) return fail(c, SP_ERR_ARG, "max_trials must be in [0, 10000]");
+    return SP_OK;
+}
+
+int ensure_vectors(sp_ctx* c, size_t n) {
+    int rc;
+    for (DevBuf* b : {&c->vx, &c->vp, &c->vh, &c->vg, &c->vz, &c->vtb, &c->vtmp})
+        if ((rc = ensure(c, *b, n * sizeof(float)))) return rc;
+    return SP_OK;
+}
+
+int ensure_partials(sp_ctx* c) {
+    const GeomDev& G = c->G;
+    const int n = G.rows * G.cols;
+    int rc;
+    if ((rc = ensure(c, c->part_f, (size_t)project_blocks(G) * 8))) return rc;
+    if ((rc = ensure(c, c->part_ph, (size_t)backproject_blocks(G) * 8))) return rc;
+    if ((rc = ensure(c, c->part_zh, (size_t)std::max((G.rows + 1) / 2, vec_blocks(n)) * 8))) return rc;
+    if ((rc = ensure(c, c->part_gp, (size_t)vec_blocks(n) * 8))) return rc;
+    if ((rc = ensure(c, c->part_g, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
+    if ((rc = ensure(c, c->part_t, (size_t)tv_blocks(G.rows, G.cols) * 9 * 8))) return rc;
+    if ((rc = ensure(c, c->part_s, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
+    if ((rc = ensure(c, c->scal, sizeof(Scalars)))) return rc;
+    return SP_OK;
+}
+
+int upload_scalars(sp_ctx* c) {
+    HIP_TRY(c, hipMemcpyAsync(c->scal.ptr, &c->sc_h, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SP_OK;
+}
+
+int check_launch(sp_ctx* c) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, SP_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return SP_OK;
+}
+
+// One S_TV call (Algorithm 1) from x into xh, K inner steps.
+void enqueue_stv(sp_ctx* c, int K, const float* x, float* xh, bool snorm, TraceDev tr,
+                 int32_t* trials_out) {
+    const GeomDev& G = c->G;
+    const int n = G.rows * G.cols;
+    Scalars* sc = dptr<Scalars>(c->scal);
+    const int* halt = &sc->halt;
+    const int nb = tv_blocks(G.rows, G.cols);
+    for (int i = 0; i < K; ++i) {
+        const float* src = i == 0 ? x : xh;
+        launch_tv_grad(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), halt);
+        launch_tv_trials(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), nb,
+                         sc, 8, dptr<double>(c->part_t), halt);
+        launch_tv_decide(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), nb,
+                         dptr<double>(c->part_t), nb, 8, sc, tr, trials_out, halt);
+        const bool last = i == K - 1;
+        launch_tv_apply(c->stream, n, src, xh, dptr<float>(c->vtb), sc, (last && snorm) ? x : nullptr,
+                        dptr<double>(c->part_s), halt);
+    }
+    if (snorm) launch_scalar(c->stream, OP_SNORM, sc, tr, dptr<double>(c->part_s), nb, nullptr, 0);
+}
+
+// z = M g with the partial dots z^T dotv (dotv nullable).
+int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, const float* dotv,
+                    double* partials, int& nparts) {
+    const GeomDev& G = c->G;
+    const int n = G.rows * G.cols;
+    const int* halt = &dptr<Scalars>(c->scal)->halt;
+    if (pc->kind == SP_PRECOND_NONE) {
+        if (g != z) launch_copy(c->stream, n, g, z, halt);
+        if (dotv) launch_dot(c->stream, n, z, dotv, partials, halt);
+        nparts = vec_blocks(n);
+        return SP_OK;
+    }
+    FFTPlan F{};
+    int rc = setup_fft(c, F);
+    if (rc) return rc;
+    launch_precond(c->stream, F, pc->mu, pc->rho, g, z, dotv, partials, halt);
+    nparts = precond_dot_blocks(F);
+    return SP_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* sp_version(void) { return "suppcg-gfx950 0.1"; }
+
+int sp_ctx_create(int device, void* hip_stream, sp_ctx** out) {
+    if (!out) return SP_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return SP_ERR_HIP;
+    if (device < 0 || device >= count) return SP_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SP_ERR_HIP;
+    sp_ctx* c = new sp_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return SP_OK;
+}
+
+int sp_ctx_destroy(sp_ctx* c) {
+    if (!c) return SP_ERR_ARG;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf* b : {&c->ang, &c->xp, &c->xTp, &c->yp, &c->tw, &c->S, &c->vx, &c->vp, &c->vh,
+                      &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
+                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
+                      &c->trace_d, &c->replay_d, &c->trials_tmp})
+        release(*b);
+    if (c->own) (void)hipStreamDestroy(c->own);
+    delete c;
+    return SP_OK;
+}
+
+int sp_ctx_set_stream(sp_ctx* c, void* hip_stream) {
+    if (!c) return SP_ERR_ARG;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return SP_OK;
+}
+
+const char* sp_last_error(const sp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !y) return fail(c, SP_ERR_ARG, "x and y must be device pointers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    const GeomDev& G = c->G;
+    launch_prep(c->stream, G, x, dptr<float>(c->xp), dptr<float>(c->xTp), nullptr);
+    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->xp), dptr<float>(c->xTp), nullptr, y,
+                   G.nB, 0, nullptr, nullptr);
+    return check_launch(c);
+}
+
+int sp_backproject(sp_ctx* c, const sp_geometry* g, const float* y, float* x) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !y) return fail(c, SP_ERR_ARG, "x and y must be device pointers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    const GeomDev& G = c->G;
+    launch_pad_sino(c->stream, G, y, dptr<float>(c->yp));
+    launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp), x, nullptr, nullptr, nullptr);
+    return check_launch(c);
+}
+
+int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b, float* r, double* f) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !b || !f) return fail(c, SP_ERR_ARG, "x, b and f must be device pointers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    const GeomDev& G = c->G;
+    launch_prep(c->stream, G, x, dptr<float>(c->xp), dptr<float>(c->xTp), nullptr);
+    float* out = r ? r : dptr<float>(c->yp) + PAD;
+    const int pitch = r ? G.nB : G.pitchB;
+    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->xp), dptr<float>(c->xTp), b, out,
+                   pitch, 0, dptr<double>(c->part_f), nullptr);
+    launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
+    return check_launch(c);
+}
+
+int sp_precond_apply(sp_ctx* c, const sp_geometry* g, const sp_precond* pc, const float* gin, float* z) {
+    if (!c) return SP_ERR_ARG;
+    if (!gin || !z) return fail(c, SP_ERR_ARG, "g and z must be device pointers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = check_precond(c, pc))) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    int np = 0;
+    if ((rc = enqueue_precond(c, pc, gin, z, nullptr, nullptr, np))) return rc;
+    return check_launch(c);
+}
+
+int sp_tv(sp_ctx* c, const sp_geometry* g, const float* x, double* tv) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !tv) return fail(c, SP_ERR_ARG, "x and tv must be device pointers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    launch_tv_value(c->stream, g->rows, g->cols, x, dptr<double>(c->part_g), nullptr);
+    launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), tv);
+    return check_launch(c);
+}
+
+int sp_tv_grad(sp_ctx* c, const sp_geometry* g, const float* x, float* tbar, double* norm2) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !tbar) return fail(c, SP_ERR_ARG, "x and tbar must be device pointers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    launch_tv_grad(c->stream, g->rows, g->cols, x, tbar, dptr<double>(c->part_g), nullptr);
+    if (norm2) launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), norm2);
+    return check_launch(c);
+}
+
+int sp_tv_perturb(sp_ctx* c, const sp_geometry* g, const sp_tv_params* p, const float* x,
+                  int32_t* ell, float* x_half, double* tv_half, int32_t* trials) {
+    if (!c) return SP_ERR_ARG;
+    if (!p || !x || !ell || !x_half) return fail(c, SP_ERR_ARG, "p, x, ell and x_half are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = check_tv(c, p))) return rc;
+    const size_t n = (size_t)g->rows * g->cols;
+    if ((rc = ensure_vectors(c, n))) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    Scalars& s = c->sc_h;
+    s = Scalars{};
+    s.a = p->a;
+    s.gamma = p->gamma;
+    s.K = p->K;
+    s.max_trials = p->max_trials > 0 ? p->max_trials : 100;
+    if ((rc = upload_scalars(c))) return rc;
+    Scalars* sc = dptr<Scalars>(c->scal);
+    HIP_TRY(c, hipMemcpyAsync(&sc->ell, ell, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    TraceDev tr{};
+    if (p->K == 0) {
+        launch_copy(c->stream, (int)n, x, x_half, nullptr);
+    } else {
+        enqueue_stv(c, p->K, x, x_half, false, tr, trials);
+    }
+    HIP_TRY(c, hipMemcpyAsync(ell, &sc->ell, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    if (tv_half) {
+        if (p->K == 0) {
+            launch_tv_value(c->stream, g->rows, g->cols, x_half, dptr<double>(c->part_g), nullptr);
+            launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), tv_half);
+        } else {
+            HIP_TRY(c, hipMemcpyAsync(tv_half, &sc->tv_new, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    return check_launch(c);
+}
+
+int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0,
+                    const sp_tv_params* tv, const sp_precond* pc, const sp_solve_params* sp,
+                    float* x_out, float* x_last, int32_t* k_out, sp_trace* trace) {
+    if (!c) return SP_ERR_ARG;
+    if (!b || !x_out || !k_out || !sp) return fail(c, SP_ERR_ARG, "b, x_out, k_out and params are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((sp->flags & SP_FLAG_GRAPH) && c->stream == nullptr) {
+        // The null stream cannot be captured: run the whole solve on an owned
+        // stream, ordered after the caller's prior work (the call blocks anyway).
+        if (!c->own) HIP_TRY(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+        HIP_TRY(c, hipStreamSynchronize(nullptr));
+        c->stream = c->own;
+        int r = sp_suppcg_solve(c, g, b, x0, tv, pc, sp, x_out, x_last, k_out, trace);
+        (void)hipStreamSynchronize(c->own);
+        c->stream = nullptr;
+        return r;
+    }
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = check_precond(c, pc))) return rc;
+    if ((rc = check_tv(c, tv))) return rc;
+    if (sp->max_iter < 0) return fail(c, SP_ERR_ARG, "max_iter must be >= 0");
+    if (!std::isfinite(sp->eps)) return fail(c, SP_ERR_ARG, "eps must be finite");
+    const int K = (tv && tv->K > 0) ? tv->K : 0;
+    const bool replay = (sp->flags & SP_FLAG_REPLAY) != 0;
+    if (replay && !sp->replay_trials) return fail(c, SP_ERR_ARG, "SP_FLAG_REPLAY needs replay_trials");
+    const GeomDev& G = c->G;
+    const int n = G.rows * G.cols;
+    if ((rc = ensure_vectors(c, n))) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    if (pc->kind == SP_PRECOND_RAMP) {
+        FFTPlan F{};
+        if ((rc = setup_fft(c, F))) return rc;
+    }
+    const int cap = std::max(sp->max_iter, 1);
+    // trace arrays: 5 double arrays + ell + trials
+    const size_t tr_bytes = (size_t)cap * (5 * 8 + 4) + (size_t)cap * std::max(K, 1) * 4 + 64;
+    if ((rc = ensure(c, c->trace_d, tr_bytes))) return rc;
+    HIP_TRY(c, hipMemsetAsync(c->trace_d.ptr, 0, tr_bytes, c->stream));
+    TraceDev tr{};
+    {
+        char* base = dptr<char>(c->trace_d);
+        tr.f_half = reinterpret_cast<double*>(base);
+        tr.tv_half = tr.f_half + cap;
+        tr.alpha = tr.tv_half + cap;
+        tr.beta = tr.alpha + cap;
+        tr.s_norm = tr.beta + cap;
+        tr.ell = reinterpret_cast<int32_t*>(tr.s_norm + cap);
+        tr.trials = tr.ell + cap;
+        tr.cap = cap;
+    }
+    if (replay && K > 0) {
+        const size_t bytes = (size_t)sp->max_iter * K * sizeof(int32_t);
+        if ((rc = ensure(c, c->replay_d, bytes))) return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->replay_d.ptr, sp->replay_trials, bytes, hipMemcpyHostToDevice, c->stream));
+        tr.replay = dptr<int32_t>(c->replay_d);
+    }
+    Scalars& s = c->sc_h;
+    s = Scalars{};
+    s.eps = sp->eps;
+    s.a = K ? tv->a : 0.5;
+    s.gamma = K ? tv->gamma : 0.0;
+    s.K = K;
+    s.max_trials = K ? (tv->max_trials > 0 ? tv->max_trials : 100) : 0;
+    s.max_iter = sp->max_iter;
+    s.replay = replay ? 1 : 0;
+    s.first = 1;
+    if ((rc = upload_scalars(c))) return rc;
+
+    hipStream_t st = c->stream;
+    Scalars* sc = dptr<Scalars>(c->scal);
+    const int* halt = &sc->halt;
+    float* xh = x_out;                                   // x_{k+1/2} lives in the output buffer
+    float* x = x_last ? x_last : dptr<float>(c->vx);        // x_k
+    float* p = dptr<float>(c->vp);
+    float* h = dptr<float>(c->vh);
+    float* gv = dptr<float>(c->vg);
+    float* z = dptr<float>(c->vz);
+    float* xp = dptr<float>(c->xp);
+    float* xTp = dptr<float>(c->xTp);
+    float* rp = dptr<float>(c->yp);
+    const AngleDev* ang = dptr<AngleDev>(c->ang);
+    double* pf = dptr<double>(c->part_f);
+    double* pzh = dptr<double>(c->part_zh);
+    double* pgp = dptr<double>(c->part_gp);
+    double* pph = dptr<double>(c->part_ph);
+    const int nf = project_blocks(G), nph = backproject_blocks(G), ngp = vec_blocks(n);
+
+    if (x0) {
+        launch_copy(st, n, x0, xh, nullptr);
+        launch_copy(st, n, x0, x, nullptr);
+    } else {
+        HIP_TRY(c, hipMemsetAsync(xh, 0, (size_t)n * 4, st));
+        HIP_TRY(c, hipMemsetAsync(x, 0, (size_t)n * 4, st));
+    }
+    // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
+    // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
+    launch_prep(st, G, xh, xp, xTp, halt);
+    launch_project(st, G, ang, xp, xTp, b, rp + PAD, G.pitchB, 0, pf, halt);
+    launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
+    launch_backproject(st, G, ang, rp, gv, nullptr, nullptr, halt);
+    int nzh = 0;
+    if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh))) return rc;
+    launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
+    launch_update_p(st, n, z, p, gv, sc, pgp, halt);
+    launch_prep(st, G, p, xp, xTp, halt);
+    launch_project(st, G, ang, xp, xTp, nullptr, rp + PAD, G.pitchB, 0, nullptr, halt);
+    launch_backproject(st, G, ang, rp, h, p, pph, halt);
+    launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
+    launch_update_x(st, n, xh, p, x, sc, halt);
+    if ((rc = check_launch(c))) return rc;
+
+    // One loop body (steps 11-14); every launch reads device state only, so
+    // the body can be replayed from a captured graph.
+    auto body = [&]() -> int {
+        if (K > 0) {
+            enqueue_stv(c, K, x, xh, true, tr, nullptr);            // S_TV -> x_{k+1/2}
+        } else {
+            launch_copy(st, n, x, xh, halt);
+        }
+        // U_PCG(x_{k+1/2}, p_{k-1}, h_{k-1})
+        launch_prep(st, G, xh, xp, xTp, halt);
+        launch_project(st, G, ang, xp, xTp, b, rp + PAD, G.pitchB, 0, pf, halt);   // r = R x - b
+        launch_scalar(st, OP_F, sc, tr, pf, nf, nullptr, 0);                      // f(x_{k+1/2})
+        launch_backproject(st, G, ang, rp, gv, nullptr, nullptr, halt);            // g = R^T r
+        int nz = 0;
+        int r2 = enqueue_precond(c, pc, gv, z, h, pzh, nz);                        // z = M g
+        if (r2) return r2;
+        launch_scalar(st, OP_BETA, sc, tr, pzh, nz, nullptr, 0);                  // beta
+        launch_update_p(st, n, z, p, gv, sc, pgp, halt);                          // p = -z + beta p
+        launch_prep(st, G, p, xp, xTp, halt);
+        launch_project(st, G, ang, xp, xTp, nullptr, rp + PAD, G.pitchB, 0, nullptr, halt);
+        launch_backproject(st, G, ang, rp, h, p, pph, halt);                      // h = A p
+        launch_scalar(st, OP_ALPHA, sc, tr, pph, nph, pgp, ngp);                  // alpha
+        launch_update_x(st, n, xh, p, x, sc, halt);                               // x = x + alpha p
+        return check_launch(c);
+    };
+
+    const bool poll = sp->eps > 0.0;
+    if ((sp->flags & SP_FLAG_GRAPH) && sp->max_iter > 0) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int brc = body();
+        hipError_t ec = hipStreamEndCapture(st, &graph);
+        if (brc) {
+            if (graph) hipGraphDestroy(graph);
+            return brc;
+        }
+        if (ec != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            hipGraphDestroy(graph);
+            return fail(c, SP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        }
+        int32_t hh = 0;
+        for (int it = 0; it < sp->max_iter; ++it) {
+            hipError_t el = hipGraphLaunch(exec, st);
+            if (el != hipSuccess) {
+                hipGraphExecDestroy(exec);
+                hipGraphDestroy(graph);
+                return fail(c, SP_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(el));
+            }
+            if (poll && (it & 7) == 7) {
+                hipMemcpyAsync(&hh, &sc->halt, 4, hipMemcpyDeviceToHost, st);
+                hipStreamSynchronize(st);
+                if (hh) break;
+            }
+        }
+        hipStreamSynchronize(st);
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+    } else {
+        int32_t hh = 0;
+        for (int it = 0; it < sp->max_iter; ++it) {
+            if ((rc = body())) return rc;
+            if (poll && (it & 7) == 7) {
+                HIP_TRY(c, hipMemcpyAsync(&hh, &sc->halt, 4, hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipStreamSynchronize(st));
+                if (hh) break;
+            }
+        }
+    }
+    Scalars out{};
+    HIP_TRY(c, hipMemcpyAsync(&out, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    *k_out = out.k;
+    int status = SP_MAXITER;
+    if (out.halt) status = out.halt;
+    else if (out.exhausted) status = SP_TRIALS_EXHAUSTED;
+    if (out.halt == SP_BREAKDOWN_CONVERGED && out.k > 1) {
+        // the step could not be formed: x_k = x_{k-1/2}
+        launch_copy(st, n, xh, x, nullptr);
+    }
+    if (trace) {
+        const int cnt = std::min(trace->cap, cap);
+        std::vector<char> host(tr_bytes);
+        HIP_TRY(c, hipMemcpyAsync(host.data(), c->trace_d.ptr, tr_bytes, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        const double* hf = reinterpret_cast<const double*>(host.data());
+        const double* htv = hf + cap;
+        const double* hal = htv + cap;
+        const double* hbe = hal + cap;
+        const double* hsn = hbe + cap;
+        const int32_t* hell = reinterpret_cast<const int32_t*>(hsn + cap);
+        const int32_t* htr = hell + cap;
+        const int done = std::min(cnt, out.iter);
+        if (trace->f_half) std::copy(hf, hf + done, trace->f_half);
+        if (trace->tv_half) std::copy(htv, htv + done, trace->tv_half);
+        if (trace->alpha) std::copy(hal, hal + done, trace->alpha);
+        if (trace->beta) std::copy(hbe, hbe + done, trace->beta);
+        if (trace->s_norm) std::copy(hsn, hsn + done, trace->s_norm);
+        if (trace->ell) std::copy(hell, hell + done, trace->ell);
+        if (trace->trials && K > 0) std::copy(htr, htr + (size_t)done * K, trace->trials);
+        trace->f0 = out.f0;
+        trace->alpha0 = out.alpha0;
+    }
+    if (out.halt == SP_ERR_NONFINITE) return fail(c, SP_ERR_NONFINITE, "non-finite value in a CG scalar");
+    return status;
+}
+
+}  // extern "C"

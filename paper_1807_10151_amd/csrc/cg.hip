@@ -1,0 +1,170 @@
+// Conjugate-gradient vector updates and the float64 scalar recurrence of
+// Algorithm 2 (U_PCG):  beta = z^T h / p^T h,  p <- -z + beta p,
+// alpha = -g^T p / p^T h,  x <- x + alpha p.
+//
+// Dot products are float64 partial sums per workgroup (fixed order); a single
+// workgroup (k_scalar) sums them and updates the device-resident scalars, so a
+// loop body needs no host synchronisation and can be captured in a graph.
+#include "sp_internal.h"
+#include "sp_reduce.h"
+#include "../../include/suppcg.h"
+
+namespace sp {
+
+int vec_blocks(int n) {
+    const int b = (n + 255) / 256;
+    return b < 2048 ? b : 2048;
+}
+
+__global__ __launch_bounds__(256) void k_dot(int n, const float* __restrict__ a,
+                                             const float* __restrict__ b,
+                                             double* __restrict__ partials,
+                                             const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256)
+        acc += (double)a[p] * (double)b[p];
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* partials,
+                const int* halt) {
+    hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(256), 0, st, n, a, b, partials, halt);
+}
+
+// p <- -z + beta p (beta from the scalars), partials of g^T p (new p).
+__global__ __launch_bounds__(256) void k_update_p(int n, const float* __restrict__ z,
+                                                  float* __restrict__ p,
+                                                  const float* __restrict__ g,
+                                                  const Scalars* __restrict__ sc,
+                                                  double* __restrict__ partials,
+                                                  const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    const double beta = sc->beta;
+    double acc = 0.0;
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) {
+        const float v = (float)(-(double)z[q] + beta * (double)p[q]);
+        p[q] = v;
+        acc += (double)g[q] * (double)v;
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+void launch_update_p(hipStream_t st, int n, const float* z, float* p, const float* g,
+                     const Scalars* sc, double* partials, const int* halt) {
+    hipLaunchKernelGGL(k_update_p, dim3(vec_blocks(n)), dim3(256), 0, st, n, z, p, g, sc, partials,
+                       halt);
+}
+
+// x <- xh + alpha p
+__global__ __launch_bounds__(256) void k_update_x(int n, const float* __restrict__ xh,
+                                                  const float* __restrict__ p,
+                                                  float* __restrict__ x,
+                                                  const Scalars* __restrict__ sc,
+                                                  const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    const double alpha = sc->alpha;
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256)
+        x[q] = (float)((double)xh[q] + alpha * (double)p[q]);
+}
+
+void launch_update_x(hipStream_t st, int n, const float* xh, const float* p, float* x,
+                     const Scalars* sc, const int* halt) {
+    hipLaunchKernelGGL(k_update_x, dim3(vec_blocks(n)), dim3(256), 0, st, n, xh, p, x, sc, halt);
+}
+
+__global__ __launch_bounds__(256) void k_copy(int n, const float* __restrict__ src,
+                                              float* __restrict__ dst, const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) dst[q] = src[q];
+}
+
+void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int* halt) {
+    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst, halt);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int np,
+                                                double* __restrict__ out) {
+    __shared__ double red[4];
+    const double tot = reduce_partials(partials, np, red);
+    if (threadIdx.x == 0) *out = tot;
+}
+
+void launch_reduce(hipStream_t st, const double* partials, int np, double* out) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partials, np, out);
+}
+
+__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
+
+__global__ __launch_bounds__(256) void k_scalar(int op, Scalars* __restrict__ sc, TraceDev tr,
+                                                const double* __restrict__ pa, int na,
+                                                const double* __restrict__ pb, int nb) {
+    if (sc->halt) return;
+    __shared__ double red[4];
+    const double A = pa ? reduce_partials(pa, na, red) : 0.0;
+    const double B = pb ? reduce_partials(pb, nb, red) : 0.0;
+    if (threadIdx.x != 0) return;
+    const int it = sc->iter;
+    const bool rec = it < tr.cap;
+    switch (op) {
+    case OP_F0:
+        sc->f = A;
+        sc->f0 = A;
+        if (!finite(A)) sc->halt = SP_ERR_NONFINITE;
+        break;
+    case OP_F:
+        sc->f = A;
+        if (rec && tr.f_half) tr.f_half[it] = A;
+        if (!finite(A)) sc->halt = SP_ERR_NONFINITE;
+        break;
+    case OP_BETA: {
+        const double beta = sc->first ? 0.0 : A / sc->pth;
+        sc->beta = beta;
+        if (!sc->first && rec && tr.beta) tr.beta[it] = beta;
+        if (!finite(beta)) sc->halt = SP_ERR_NONFINITE;
+        break;
+    }
+    case OP_ALPHA0:
+    case OP_ALPHA: {
+        const double pth = A;
+        const double gp = B;
+        double alpha = 0.0;
+        if (pth == 0.0) {
+            sc->halt = SP_BREAKDOWN_CONVERGED;
+        } else {
+            alpha = -gp / pth;
+            if (!finite(alpha) || !finite(pth)) sc->halt = SP_ERR_NONFINITE;
+        }
+        sc->alpha = alpha;
+        sc->pth = pth;
+        if (op == OP_ALPHA0) {
+            sc->alpha0 = alpha;
+            sc->k = 1;
+            sc->first = 0;
+        } else {
+            if (rec && tr.alpha) tr.alpha[it] = alpha;
+            sc->iter = it + 1;
+            sc->k = sc->k + 1;
+        }
+        sc->inner = 0;
+        if (sc->halt == 0 && sc->eps > 0.0 && !(sc->f > sc->eps)) sc->halt = SP_CONVERGED;
+        break;
+    }
+    case OP_SNORM:
+        if (rec && tr.s_norm) tr.s_norm[it] = sqrt(A);
+        break;
+    default:
+        break;
+    }
+}
+
+void launch_scalar(hipStream_t st, int op, Scalars* sc, TraceDev tr, const double* pa, int na,
+                   const double* pb, int nb) {
+    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, st, op, sc, tr, pa, na, pb, nb);
+}
+
+}  // namespace sp

@@ -1,0 +1,280 @@
+// Matrix-free parallel-beam projector R (ray-driven gather) and its exact
+// transpose R^T (pixel-driven gather, no atomics).
+//
+// R[(a,k),(i,j)] is the length of ray (a,k) inside pixel (i,j) (the projection
+// matrix of Section 2, rays as in Section 4.1).  Both operators evaluate the
+// weight with the same float64 instruction sequence (projection t of the pixel
+// centre, offset d = s_k - t, chord_w), so R^T uses bit-identical weights and is
+// the exact adjoint up to summation order.  Data are float32; offsets, weights
+// and sums are float64 (FP64 FMA issues at the non-packed FP32 rate on CDNA4,
+// and float32 angles alone would move a ray by ~1e-5 pixel at radius 256).
+//
+// Canonical projection of pixel centre (xj, yi) on the normal of angle a:
+//   |c| >= |s| ("vertical" angles):   t = fma(xj, c, yi * s)
+//   |s| >  |c| ("horizontal" angles): t = fma(yi, s, xj * c)
+// The product outside the fma is the one a forward walk shares between the
+// candidates of one step.
+//
+// Forward walk.  For a vertical angle a ray crosses every image row; at row i
+// its nonzero pixels lie within hw columns of the crossing point, which moves
+// by `slope` columns per row.  A lane owns one ray; the 64 lanes of a wave hold
+// consecutive rays of one angle and walk the union of their row ranges
+// together, so each step gathers consecutive addresses of one row.  Candidate
+// columns outside the image are clamped into a zero pad and contribute 0.
+// Horizontal angles walk columns of a zero-padded transposed copy.
+//
+// Backward gather.  A lane owns one pixel and loops over the angles, which are
+// sorted into four classes (vertical/horizontal x oblique/axis-parallel) so
+// the inner loop has no branch; at each angle the pixel's nonzero bins are the
+// NB bins after floor(kf - hb), read from a zero-padded sinogram.
+#include "sp_internal.h"
+#include "sp_reduce.h"
+
+namespace sp {
+
+__global__ __launch_bounds__(256) void k_prep(GeomDev G, const float* __restrict__ x,
+                                              float* __restrict__ xp, float* __restrict__ xTp,
+                                              const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ float tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int j = blockIdx.x * 32 + tx;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int i = blockIdx.y * 32 + ty + r;
+        float v = 0.0f;
+        if (i < G.rows && j < G.cols) {
+            v = x[(size_t)i * G.cols + j];
+            xp[(size_t)i * G.pitchX + PAD + j] = v;
+        }
+        tile[ty + r][tx] = v;
+    }
+    __syncthreads();
+    const int ii = blockIdx.y * 32 + tx;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int jj = blockIdx.x * 32 + ty + r;
+        if (ii < G.rows && jj < G.cols) xTp[(size_t)jj * G.pitchXT + PAD + ii] = tile[tx][ty + r];
+    }
+}
+
+void launch_prep(hipStream_t st, const GeomDev& G, const float* x, float* xp, float* xTp,
+                 const int* halt) {
+    dim3 grid((G.cols + 31) / 32, (G.rows + 31) / 32);
+    hipLaunchKernelGGL(k_prep, grid, dim3(256), 0, st, G, x, xp, xTp, halt);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Major-axis steps [lo, hi) of [0, n) where base + m * slope lies in [vlo, vhi],
+// widened by one step on each side (candidate selection only).
+__device__ __forceinline__ void step_range(double base, double slope, double vlo, double vhi, int n,
+                                           int& lo, int& hi) {
+    if (slope == 0.0) {
+        const bool in = base >= vlo && base <= vhi;
+        lo = 0;
+        hi = in ? n : 0;
+        return;
+    }
+    const double t0 = (vlo - base) / slope, t1 = (vhi - base) / slope;
+    double tmin = fmin(t0, t1) - 1.0, tmax = fmax(t0, t1) + 2.0;
+    tmin = fmin(fmax(tmin, 0.0), (double)n);
+    tmax = fmin(fmax(tmax, 0.0), (double)n);
+    lo = (int)floor(tmin);
+    hi = (int)ceil(tmax);
+    if (hi < lo) hi = lo;
+}
+
+// One ray's sum.  HORIZ = walk columns of the transposed copy.  img points at
+// element PAD of row 0 of the padded copy.
+template <bool HORIZ, bool AXIS, int NC>
+__device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, double sk,
+                                          const float* __restrict__ img, bool valid) {
+    const int nmaj = HORIZ ? G.cols : G.rows;
+    const int nmin = HORIZ ? G.rows : G.cols;
+    const int pitch = HORIZ ? G.pitchXT : G.pitchX;
+    const double fM = HORIZ ? A.c : A.s;   // factor of the shared (major) product
+    const double fm = HORIZ ? A.s : A.c;   // factor of the per-candidate fma
+    // fractional minor index of the ray's crossing at major step 0, minus hw
+    const double start = (HORIZ ? G.yoff - (sk + G.xoff * A.c) / A.s
+                                : (sk - G.yoff * A.s) / A.c + G.xoff) - (double)A.hw;
+    int lo, hi;
+    step_range(start, A.slope, -(double)(NC + 1), (double)(nmin + 1), nmaj, lo, hi);
+    if (!valid) {
+        lo = nmaj;
+        hi = 0;
+    }
+    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
+    double acc = 0.0;
+    double nf = fma((double)lo, A.slope, start);
+    for (int m = lo; m < hi; ++m) {
+        const double nfl = floor(nf);
+        nf += A.slope;
+        int n0 = (int)nfl + 1;
+        const double cm0 = HORIZ ? G.yoff - (nfl + 1.0) : (nfl + 1.0) - G.xoff;
+        n0 = min(max(n0, -PAD), nmin + PAD - 3);
+        const float* px = img + (size_t)m * pitch + n0;
+        float v[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) v[q] = px[q];
+        const double P = (HORIZ ? ((double)m - G.xoff) : (G.yoff - (double)m)) * fM;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const double cm = HORIZ ? cm0 - (double)q : cm0 + (double)q;
+            const double d = sk - fma(cm, fm, P);
+            acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[q], acc);
+        }
+    }
+    return acc;
+}
+
+template <bool HORIZ, bool AXIS>
+__device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A, double sk,
+                                             const float* __restrict__ img, bool valid) {
+    return A.nc == 3 ? ray_sum<HORIZ, AXIS, 3>(G, A, sk, img, valid)
+                     : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, valid);
+}
+
+// out[row*out_pitch + out_pad + k] = (R x)_{row,k}, or the residual (R x - b)
+// with its float64 squared norm per workgroup in partials when b != nullptr.
+// blockIdx.x indexes the class-sorted angle table.
+__global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
+                                                 const float* __restrict__ xp,
+                                                 const float* __restrict__ xTp,
+                                                 const float* __restrict__ b,
+                                                 float* __restrict__ out, int out_pitch,
+                                                 int out_pad, double* __restrict__ partials,
+                                                 const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    const AngleDev A = ang[blockIdx.x];
+    const int a = A.row;
+    const int k = blockIdx.y * 256 + threadIdx.x;
+    const bool valid = k < G.nB;
+    const double sk = bin_pos((double)k, G);
+    const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
+    double acc;
+    if (!horiz) {
+        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, valid)
+                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, valid);
+    } else {
+        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, valid)
+                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid);
+    }
+    double r2 = 0.0;
+    if (valid) {
+        float val;
+        if (b) {
+            val = (float)(fma(acc, G.pixel, -(double)b[(size_t)a * G.nB + k]));
+            r2 = (double)val * (double)val;
+        } else {
+            val = (float)(acc * G.pixel);
+        }
+        out[(size_t)a * out_pitch + out_pad + k] = val;
+    }
+    if (b) {
+        const double tot = block_sum(r2, red);
+        if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    }
+}
+
+int project_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
+
+void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* xp,
+                    const float* xTp, const float* b, float* out, int out_pitch, int out_pad,
+                    double* partials, const int* halt) {
+    dim3 grid(G.nA, (G.nB + 255) / 256);
+    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
+                       out_pad, partials, halt);
+}
+
+__global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const float* __restrict__ y,
+                                                  float* __restrict__ yp) {
+    const int a = blockIdx.x;
+    for (int k = threadIdx.x; k < G.nB; k += 256)
+        yp[(size_t)a * G.pitchB + PAD + k] = y[(size_t)a * G.nB + k];
+}
+
+void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp) {
+    hipLaunchKernelGGL(k_pad_sino, dim3(G.nA), dim3(256), 0, st, G, y, yp);
+}
+
+// Sum over the angles [beg, end) of one class for pixel (xj, yi).
+template <bool HORIZ, bool AXIS, int NB>
+__device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
+                                           int beg, int end, const float* __restrict__ yp,
+                                           double xj, double yi, double acc) {
+#pragma unroll 2
+    for (int a = beg; a < end; ++a) {
+        const AngleDev A = ang[a];
+        const double t = HORIZ ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
+        const double kfl = floor(fma(t, G.inv_ds, A.kb));
+        int k0 = (int)kfl + 1;
+        k0 = min(max(k0, -PAD), G.nB + PAD - NB);
+        const float* pr = yp + (size_t)A.row * G.pitchB + PAD + k0;
+        float v[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) v[q] = pr[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const double d = bin_pos(kfl + (double)(1 + q), G) - t;
+            acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[q], acc);
+        }
+    }
+    return acc;
+}
+
+// out[i][j] = (R^T y)_{ij} from the padded sinogram yp; with dotv != nullptr
+// also the float64 partial sum of out * dotv per workgroup.
+template <int NB>
+__global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
+                                                     const float* __restrict__ yp,
+                                                     float* __restrict__ out,
+                                                     const float* __restrict__ dotv,
+                                                     double* __restrict__ partials,
+                                                     const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+    const bool valid = i < G.rows && j < G.cols;
+    const double xj = (double)j - G.xoff;
+    const double yi = G.yoff - (double)i;
+    double acc = 0.0;
+    acc = bp_class<false, false, NB>(G, ang, G.cls[0], G.cls[1], yp, xj, yi, acc);
+    acc = bp_class<true, false, NB>(G, ang, G.cls[1], G.cls[2], yp, xj, yi, acc);
+    acc = bp_class<false, true, NB>(G, ang, G.cls[2], G.cls[3], yp, xj, yi, acc);
+    acc = bp_class<true, true, NB>(G, ang, G.cls[3], G.cls[4], yp, xj, yi, acc);
+    const float val = (float)(acc * G.pixel);
+    if (valid) out[(size_t)i * G.cols + j] = val;
+    if (dotv) {
+        const double v = valid ? (double)val * (double)dotv[(size_t)i * G.cols + j] : 0.0;
+        const double tot = block_sum(v, red);
+        if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    }
+}
+
+int backproject_blocks(const GeomDev& G) { return ((G.cols + 15) / 16) * ((G.rows + 15) / 16); }
+
+void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
+                        float* out, const float* dotv, double* partials, const int* halt) {
+    dim3 grid((G.cols + 15) / 16, (G.rows + 15) / 16);
+    switch (G.nbmax) {
+    case 1: hipLaunchKernelGGL(k_backproject<1>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
+    case 2: hipLaunchKernelGGL(k_backproject<2>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
+    case 3: hipLaunchKernelGGL(k_backproject<3>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
+    default: hipLaunchKernelGGL(k_backproject<4>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
+    }
+}
+
+}  // namespace sp

@@ -1,0 +1,168 @@
+// Internal declarations of libsuppcg: device-side structs, kernel launchers
+// and the canonical chord-weight evaluation shared by the projector and the
+// backprojector.  Not part of the public ABI (see include/suppcg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sp {
+
+// Zero columns kept on each side of every padded image row and sinogram row.
+// Candidate indices are clamped into [-PAD, len + PAD) and the pad holds
+// zeros, so a clamped candidate contributes exactly 0.
+constexpr int PAD = 4;
+constexpr int BLOCK = 256;
+
+// Per-angle constants, in pixel units (coordinates divided by the pixel size).
+// The chord weight is evaluated in float64 from float64 cos/sin: rounding the
+// angle to float32 alone would move a ray by ~1e-5 pixel at radius 256.
+struct alignas(16) AngleDev {
+    double c, s;      // cos(theta), sin(theta)
+    double einv;      // e * inv with e = (|c| + |s|) / 2
+    double inv;       // 1 / (|c| |s|)   (0 for axis-parallel angles)
+    double wmax;      // 1 / max(|c|, |s|)
+    double slope;     // forward walk: minor index per major step (selection only)
+    double kb;        // backprojection: -s0/ds - hb, hb = e/ds + margin (selection only)
+    float hw;         // forward walk: half-width of the nonzero band on the minor axis + margin
+    int32_t row;      // sinogram row of this angle (the table is sorted by class)
+    int32_t flags;    // bit0 axis-parallel, bit1 walk columns (|s| > |c|)
+    int32_t nc;       // forward candidates per major step
+    int32_t nb;       // backprojection candidate bins
+    int32_t pad_;
+};
+constexpr int ANG_AXIS = 1;
+constexpr int ANG_HORIZ = 2;
+
+struct GeomDev {
+    int rows, cols, nA, nB;
+    double xoff, yoff;  // (cols-1)/2, (rows-1)/2
+    double ds, s0;      // bin spacing and position of bin 0, pixel units
+    double inv_ds;
+    double pixel;       // weights are in pixel units; outputs are scaled by this
+    float xoff_f, yoff_f, ds_f, s0_f;   // float copies for candidate selection
+    int pitchX;         // cols + 2 PAD: row pitch of the padded image copy
+    int pitchXT;        // rows + 2 PAD: row pitch of the padded transposed copy
+    int pitchB;         // nB + 2 PAD: row pitch of the padded sinogram
+    int nbmax;          // max backprojection candidates over the angles
+    int cls[5];         // angle-table class boundaries: vertical, horizontal,
+                        // vertical axis, horizontal axis
+};
+
+// Device-resident solver state.  Written only by single-workgroup kernels
+// (scalar, decide), read by every solver kernel.
+struct Scalars {
+    double f;         // f of the last residual computed
+    double pth;       // p^T h of the carried (p, h)
+    double beta;
+    double alpha;
+    double lam;       // accepted S_TV step divided by ||t_bar||
+    double tv_new;    // TV of the accepted trial
+    double eps;
+    double a, gamma;  // S_TV parameters
+    double f0;        // f(x_0)
+    double alpha0;    // alpha of the initial step
+    int32_t ell;      // l of Algorithm 1
+    int32_t k;        // k of Algorithm 3
+    int32_t halt;     // 0: running; else the SP_* status that stopped the run
+    int32_t exhausted;
+    int32_t iter;     // index of the current loop body
+    int32_t inner;    // index of the current S_TV inner step
+    int32_t K;
+    int32_t max_trials;
+    int32_t max_iter;
+    int32_t replay;   // 1: accept after replay[iter*K+inner] trials
+    int32_t first;    // 1 while computing the initial direction (beta = 0)
+    int32_t pad_;
+};
+
+struct TraceDev {
+    double* f_half;
+    double* tv_half;
+    double* alpha;
+    double* beta;
+    double* s_norm;
+    int32_t* ell;
+    int32_t* trials;
+    const int32_t* replay;
+    int32_t cap;
+};
+
+// Canonical evaluation of the weight of pixel centre (xj, yi) for ray sk,
+// shared by the projector and the backprojector so both use bit-identical
+// weights.  Projection of the pixel centre on the ray normal:
+//   |c| >= |s|:  t = fma(xj, c, yi * s)      |s| > |c|:  t = fma(yi, s, xj * c)
+// (the product outside the fma is the one a forward walk shares between
+// candidates); offset d = sk - t; weight = chord length through the pixel.
+template <bool AXIS>
+__device__ __forceinline__ double chord_w(double d, double einv, double inv, double wmax) {
+    const double ad = fabs(d);
+    if (AXIS) return ad < 0.5 ? 1.0 : (ad == 0.5 ? 0.5 : 0.0);
+    return fmin(fmax(fma(-ad, inv, einv), 0.0), wmax);
+}
+
+__device__ __forceinline__ double bin_pos(double k, const GeomDev& G) { return fma(k, G.ds, G.s0); }
+
+// ---- kernel launchers (all enqueue on `st`) ----------------------------------
+// projector.hip
+void launch_prep(hipStream_t st, const GeomDev& G, const float* x, float* xp, float* xTp,
+                 const int* halt);
+void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* xp,
+                    const float* xTp, const float* b, float* out, int out_pitch, int out_pad,
+                    double* partials, const int* halt);
+int project_blocks(const GeomDev& G);
+void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp);
+void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
+                        float* out, const float* dotv, double* partials, const int* halt);
+int backproject_blocks(const GeomDev& G);
+
+// fft.hip
+struct FFTPlan {
+    int P, logP, SP, rows, cols, CB;
+    double2* S;           // [rows][SP] complex float64 scratch
+    const double2* tw;    // [P/2] twiddles exp(-2 pi i k / P)
+};
+void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, const float* g,
+                    float* z, const float* dotv, double* partials, const int* halt);
+int precond_dot_blocks(const FFTPlan& F);
+
+// tv.hip
+void launch_tv_grad(hipStream_t st, int rows, int cols, const float* y, float* tb, double* partials,
+                    const int* halt);
+int tv_blocks(int rows, int cols);
+void launch_tv_trials(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+                      const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
+                      const int* halt);
+void launch_tv_decide(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+                      const double* gpart, int ngpart, const double* tpart, int ntpart, int J,
+                      Scalars* sc, TraceDev tr, int32_t* trials_out, const int* halt);
+void launch_tv_apply(hipStream_t st, int n, const float* src, float* dst, const float* tb,
+                     const Scalars* sc, const float* xk, double* partials, const int* halt);
+void launch_tv_value(hipStream_t st, int rows, int cols, const float* y, double* partials,
+                     const int* halt);
+
+// cg.hip
+int vec_blocks(int n);
+void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* partials,
+                const int* halt);
+void launch_update_p(hipStream_t st, int n, const float* z, float* p, const float* g,
+                     const Scalars* sc, double* partials, const int* halt);
+void launch_update_x(hipStream_t st, int n, const float* xh, const float* p, float* x,
+                     const Scalars* sc, const int* halt);
+void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int* halt);
+void launch_reduce(hipStream_t st, const double* partials, int np, double* out);
+
+enum ScalarOp : int {
+    OP_F = 0,        // f = sum(pa); trace / non-finite check
+    OP_F0 = 1,       // f(x_0) at initialisation
+    OP_BETA = 2,     // beta = sum(pa) / pth (0 on the first direction)
+    OP_ALPHA = 3,    // pth = sum(pa); alpha = -sum(pb) / pth; k++, iter++; eps test
+    OP_ALPHA0 = 4,   // same for the initial step (k = 1)
+    OP_SNORM = 5,    // ||s_k|| into the trace
+};
+void launch_scalar(hipStream_t st, int op, Scalars* sc, TraceDev tr, const double* pa, int na,
+                   const double* pb, int nb);
+
+}  // namespace sp

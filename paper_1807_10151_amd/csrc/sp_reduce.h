@@ -1,0 +1,35 @@
+// Deterministic float64 reductions for 256-thread workgroups (4 wave64s).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sp {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup; the result is valid in every thread.  `lds` must
+// hold 4 doubles.  Fixed reduction order: lanes by xor-butterfly, then waves
+// 0..3 in order.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    return ((lds[0] + lds[1]) + lds[2]) + lds[3];
+}
+
+// Sums `np` partials in a fixed order with one workgroup: thread t adds
+// entries t, t+256, ...; then block_sum.  Every thread gets the result.
+__device__ __forceinline__ double reduce_partials(const double* p, int np, double* lds) {
+    double v = 0.0;
+    for (int q = threadIdx.x; q < np; q += 256) v += p[q];
+    return block_sum(v, lds);
+}
+
+}  // namespace sp

@@ -1,0 +1,324 @@
+// Total-variation superiorization (Section 3.1, Algorithm 1) on the GPU.
+//
+// One S_TV inner step is four launches:
+//   k_tv_grad    t_bar (minus the TV gradient where defined, 0 elsewhere) and
+//                per-workgroup partials of ||t_bar||^2;
+//   k_tv_trials  TV(y) and TV(y + lam_j t_bar) for the next J trial step
+//                lengths lam_j = gamma a^(l + j) / ||t_bar|| in one pass, each as
+//                per-workgroup float64 partials;
+//   k_tv_decide  one workgroup: sums the partials in a fixed order, takes the
+//                first trial with TV(trial) <= TV(y) (Algorithm 1's "until"),
+//                advances l by the trials used, records the step; if none of the
+//                J is accepted it evaluates further batches itself;
+//   k_tv_apply   y <- y + lam t_bar (and ||s_k||^2 partials on the last step).
+// Trial TVs are evaluated in float64 directly on y + lam t_bar (the trial image
+// is never rounded to float32), so the acceptance test sees the step itself.
+#include "sp_internal.h"
+#include "sp_reduce.h"
+
+namespace sp {
+
+constexpr int TVJ = 8;
+
+// t_bar at pixel p = (i, j) of a rows x cols float32 image (reading: the
+// partial derivative is undefined when a square-root term it enters is zero).
+__device__ __forceinline__ float tv_neg_grad(const float* __restrict__ y, int rows, int cols,
+                                             int i, int j, size_t p) {
+    const float v = y[p];
+    float gsum = 0.0f;
+    bool bad = false;
+    if (i < rows - 1 && j < cols - 1) {          // T_{i,j}
+        const float dv = v - y[p + cols], dh = v - y[p + 1];
+        if (dv == 0.0f && dh == 0.0f) bad = true;
+        else gsum += (dv + dh) / sqrtf(dv * dv + dh * dh);
+    }
+    if (i >= 1 && j < cols - 1) {                // T_{i-1,j}
+        const float u = y[p - cols];
+        const float dv = u - v, dh = u - y[p - cols + 1];
+        if (dv == 0.0f && dh == 0.0f) bad = true;
+        else gsum -= dv / sqrtf(dv * dv + dh * dh);
+    }
+    if (i < rows - 1 && j >= 1) {                // T_{i,j-1}
+        const float u = y[p - 1];
+        const float dv = u - y[p - 1 + cols], dh = u - v;
+        if (dv == 0.0f && dh == 0.0f) bad = true;
+        else gsum -= dh / sqrtf(dv * dv + dh * dh);
+    }
+    return bad ? 0.0f : -gsum;
+}
+
+__global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const float* __restrict__ y,
+                                                 float* __restrict__ tb,
+                                                 double* __restrict__ partials,
+                                                 const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    const size_t n = (size_t)rows * cols;
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double sq = 0.0;
+    if (p < n) {
+        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+        const float t = tv_neg_grad(y, rows, cols, i, j, p);
+        tb[p] = t;
+        sq = (double)t * (double)t;
+    }
+    const double tot = block_sum(sq, red);
+    if (partials && threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+int tv_blocks(int rows, int cols) { return (int)(((size_t)rows * cols + 255) / 256); }
+
+void launch_tv_grad(hipStream_t st, int rows, int cols, const float* y, float* tb, double* partials,
+                    const int* halt) {
+    hipLaunchKernelGGL(k_tv_grad, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
+                       partials, halt);
+}
+
+// TV terms of pixel p for the base image (q = 0) and nq trial steps lam[0..nq).
+template <int NQ>
+__device__ __forceinline__ void tv_terms(const float* __restrict__ y, const float* __restrict__ tb,
+                                         int cols, size_t p, const double* lam, int nq,
+                                         double* acc) {
+    const double dv = (double)y[p] - (double)y[p + cols];
+    const double dh = (double)y[p] - (double)y[p + 1];
+    const double ev = (double)tb[p] - (double)tb[p + cols];
+    const double eh = (double)tb[p] - (double)tb[p + 1];
+    acc[0] += sqrt(dv * dv + dh * dh);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (q < nq) {
+            const double a = fma(lam[q], ev, dv);
+            const double b = fma(lam[q], eh, dh);
+            acc[q + 1] += sqrt(a * a + b * b);
+        }
+    }
+}
+
+__device__ __forceinline__ double trial_lambda(const Scalars* sc, int trial, double tn) {
+    // trial = 0-based index from the current l: step gamma * a^(l + trial)
+    return tn > 0.0 ? sc->gamma * pow(sc->a, (double)(sc->ell + trial)) / tn : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const float* __restrict__ y,
+                                                   const float* __restrict__ tb,
+                                                   const double* __restrict__ gpart, int ngpart,
+                                                   const Scalars* __restrict__ sc,
+                                                   double* __restrict__ tpart,
+                                                   const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    __shared__ double lam[TVJ];
+    const double tn = sqrt(reduce_partials(gpart, ngpart, red));
+    if (threadIdx.x < TVJ) lam[threadIdx.x] = trial_lambda(sc, threadIdx.x, tn);
+    __syncthreads();
+    double lam_r[TVJ];
+#pragma unroll
+    for (int q = 0; q < TVJ; ++q) lam_r[q] = lam[q];
+    double acc[TVJ + 1];
+#pragma unroll
+    for (int q = 0; q <= TVJ; ++q) acc[q] = 0.0;
+    const size_t n = (size_t)rows * cols;
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) {
+        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+        if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam_r, TVJ, acc);
+    }
+#pragma unroll
+    for (int q = 0; q <= TVJ; ++q) {
+        const double tot = block_sum(acc[q], red);
+        if (threadIdx.x == 0) tpart[(size_t)blockIdx.x * (TVJ + 1) + q] = tot;
+    }
+}
+
+void launch_tv_trials(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+                      const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
+                      const int* halt) {
+    (void)J;
+    hipLaunchKernelGGL(k_tv_trials, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
+                       gpart, ngpart, sc, tpart, halt);
+}
+
+// One workgroup evaluates TV(y) and TV(y + lam_q t_bar), q < nq, over the whole
+// image (the rare path of k_tv_decide).  out[0] = TV(y), out[1 + q] = trials.
+__device__ void tv_trials_wg(const float* __restrict__ y, const float* __restrict__ tb, int rows,
+                             int cols, const double* lam, int nq, double* out, double* red) {
+    double acc[TVJ + 1];
+#pragma unroll
+    for (int q = 0; q <= TVJ; ++q) acc[q] = 0.0;
+    const size_t n = (size_t)rows * cols;
+    for (size_t p = threadIdx.x; p < n; p += 256) {
+        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+        if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam, nq, acc);
+    }
+    for (int q = 0; q <= TVJ; ++q) {
+        const double tot = block_sum(acc[q], red);
+        if (threadIdx.x == 0) out[q] = tot;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_tv_decide(int rows, int cols, const float* __restrict__ y,
+                                                   const float* __restrict__ tb,
+                                                   const double* __restrict__ gpart, int ngpart,
+                                                   const double* __restrict__ tpart, int ntpart,
+                                                   Scalars* __restrict__ sc, TraceDev tr,
+                                                   int32_t* __restrict__ trials_out,
+                                                   const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    __shared__ double tv[TVJ + 1];
+    __shared__ double lam[TVJ];
+    __shared__ int chosen_s;
+    __shared__ double tvc_s;
+    const double tn = sqrt(reduce_partials(gpart, ngpart, red));
+    for (int q = 0; q <= TVJ; ++q) {
+        double v = 0.0;
+        for (int bidx = threadIdx.x; bidx < ntpart; bidx += 256) v += tpart[(size_t)bidx * (TVJ + 1) + q];
+        const double tot = block_sum(v, red);
+        if (threadIdx.x == 0) tv[q] = tot;
+    }
+    __syncthreads();
+    const int max_trials = sc->max_trials;
+    if (threadIdx.x == 0) {
+        chosen_s = -1;
+        tvc_s = tv[0];
+        if (sc->replay) {
+            const int want = tr.replay[(size_t)sc->iter * sc->K + sc->inner];
+            if (want >= 1 && want <= max_trials) {
+                chosen_s = want;
+                tvc_s = want <= TVJ ? tv[want] : -1.0;   // -1: evaluate below
+            }
+        } else {
+            const int first = max_trials < TVJ ? max_trials : TVJ;
+            for (int q = 0; q < first; ++q) {
+                if (tv[q + 1] <= tv[0]) {
+                    chosen_s = q + 1;
+                    tvc_s = tv[q + 1];
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // Rare path: more trials than the first batch, evaluated by this workgroup.
+    if (!sc->replay && chosen_s < 0 && max_trials > TVJ) {
+        __shared__ double out[TVJ + 1];
+        for (int start = TVJ; start < max_trials && chosen_s < 0; start += TVJ) {
+            const int nq = min(TVJ, max_trials - start);
+            if (threadIdx.x < TVJ) lam[threadIdx.x] = threadIdx.x < nq ? trial_lambda(sc, start + threadIdx.x, tn) : 0.0;
+            __syncthreads();
+            tv_trials_wg(y, tb, rows, cols, lam, nq, out, red);
+            if (threadIdx.x == 0) {
+                for (int q = 0; q < nq; ++q) {
+                    if (out[q + 1] <= out[0]) {
+                        chosen_s = start + q + 1;
+                        tvc_s = out[q + 1];
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (sc->replay && chosen_s > TVJ) {
+        __shared__ double out[TVJ + 1];
+        if (threadIdx.x == 0) lam[0] = trial_lambda(sc, chosen_s - 1, tn);
+        __syncthreads();
+        tv_trials_wg(y, tb, rows, cols, lam, 1, out, red);
+        if (threadIdx.x == 0) tvc_s = out[1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int chosen = chosen_s;
+        const int ell0 = sc->ell;
+        const int slot = sc->inner;
+        int used;
+        if (chosen > 0) {
+            sc->lam = trial_lambda(sc, chosen - 1, tn);
+            sc->ell = ell0 + chosen;
+            sc->tv_new = tvc_s;
+            used = chosen;
+        } else {
+            sc->lam = 0.0;
+            sc->ell = ell0 + max_trials;
+            sc->tv_new = tv[0];
+            sc->exhausted = 1;
+            used = max_trials + 1;
+        }
+        if (trials_out) trials_out[slot] = used;
+        if (tr.trials && sc->iter < tr.cap) tr.trials[(size_t)sc->iter * sc->K + slot] = used;
+        if (slot == sc->K - 1 && sc->iter < tr.cap) {
+            if (tr.ell) tr.ell[sc->iter] = sc->ell;
+            if (tr.tv_half) tr.tv_half[sc->iter] = sc->tv_new;
+        }
+        sc->inner = slot + 1;
+    }
+}
+
+void launch_tv_decide(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+                      const double* gpart, int ngpart, const double* tpart, int ntpart, int J,
+                      Scalars* sc, TraceDev tr, int32_t* trials_out, const int* halt) {
+    (void)J;
+    hipLaunchKernelGGL(k_tv_decide, dim3(1), dim3(256), 0, st, rows, cols, y, tb, gpart, ngpart,
+                       tpart, ntpart, sc, tr, trials_out, halt);
+}
+
+__global__ __launch_bounds__(256) void k_tv_apply(int n, const float* __restrict__ src,
+                                                  float* __restrict__ dst,
+                                                  const float* __restrict__ tb,
+                                                  const Scalars* __restrict__ sc,
+                                                  const float* __restrict__ xk,
+                                                  double* __restrict__ partials,
+                                                  const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    const double lam = sc->lam;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    double s2 = 0.0;
+    if (p < n) {
+        const float v = (float)((double)src[p] + lam * (double)tb[p]);
+        dst[p] = v;
+        if (xk) {
+            const double s = (double)v - (double)xk[p];
+            s2 = s * s;
+        }
+    }
+    if (xk) {
+        const double tot = block_sum(s2, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    }
+}
+
+void launch_tv_apply(hipStream_t st, int n, const float* src, float* dst, const float* tb,
+                     const Scalars* sc, const float* xk, double* partials, const int* halt) {
+    hipLaunchKernelGGL(k_tv_apply, dim3((n + 255) / 256), dim3(256), 0, st, n, src, dst, tb, sc, xk,
+                       partials, halt);
+}
+
+__global__ __launch_bounds__(256) void k_tv_value(int rows, int cols, const float* __restrict__ y,
+                                                  double* __restrict__ partials,
+                                                  const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    const size_t n = (size_t)rows * cols;
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double acc = 0.0;
+    if (p < n) {
+        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+        if (i < rows - 1 && j < cols - 1) {
+            const double dv = (double)y[p] - (double)y[p + cols];
+            const double dh = (double)y[p] - (double)y[p + 1];
+            acc = sqrt(dv * dv + dh * dh);
+        }
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+void launch_tv_value(hipStream_t st, int rows, int cols, const float* y, double* partials,
+                     const int* halt) {
+    hipLaunchKernelGGL(k_tv_value, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y,
+                       partials, halt);
+}
+
+}  // namespace sp

@@ -1,0 +1,132 @@
+"""GPU parity of the whole SupPCG run (Algorithm 3) against the CPU oracle.
+
+Bar: the reconstructed image at a fixed iteration count within 1e-3 relative
+L2 of the float64 oracle, and an identical l trace.
+"""
+import numpy as np
+import pytest
+
+from oracle import suppcg as osup
+from oracle import projector as oproj
+from tests._problems import A, GAMMA, K, MU, RHO, oracle_precond, rel_l2, workload_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1807_10151_amd as sp_mod
+    return sp_mod
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def geom(sp, og):
+    return sp.Geometry(og.rows, og.cols, og.n_angles, og.n_bins)
+
+
+@pytest.fixture(scope="module")
+def small():
+    og, img, b = workload_problem("small64")
+    R, _ = oproj.matrix(og)
+    prob = osup.Problem(R, b.astype(np.float64), (og.rows, og.cols), oracle_precond)
+    return og, img, b, R, prob
+
+
+@pytest.fixture(scope="module")
+def small_ref(small):
+    og, img, b, R, prob = small
+    return osup.suppcg(prob, np.zeros(og.n), osup.TVParams(K, A, GAMMA), n_iter=20)
+
+
+def test_suppcg_small64_20_iterations(sp, small, small_ref):
+    og, img, b, R, prob = small
+    ref = small_ref
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                             max_iter=20)
+    assert res.k == ref.k == 21
+    assert list(res.trace["ell"]) == ref.trace["ell"]
+    assert res.trace["trials"].ravel().tolist() == [t for tt in ref.trace["trials"] for t in tt]
+    assert rel_l2(res.x_half.cpu().numpy(), ref.x_half) <= 1e-3
+    assert rel_l2(res.x_last.cpu().numpy(), ref.x_last) <= 1e-3
+    np.testing.assert_allclose(res.trace["f_half"], ref.trace["f_half"], rtol=1e-3)
+    np.testing.assert_allclose(res.trace["tv_half"], ref.trace["tv_half"], rtol=1e-3)
+    assert res.trace["f0"] == pytest.approx(ref.trace["f0"], rel=1e-5)
+
+
+def test_pcg_and_cg_small64(sp, small):
+    og, img, b, R, prob = small
+    ref = osup.suppcg(prob, np.zeros(og.n), None, n_iter=15)
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=0, mu=MU, rho=RHO, max_iter=15)
+    assert rel_l2(res.x_half.cpu().numpy(), ref.x_half) <= 1e-3
+    prob_cg = osup.Problem(R, b.astype(np.float64), (og.rows, og.cols), None)
+    ref_cg = osup.suppcg(prob_cg, np.zeros(og.n), osup.TVParams(K, A, GAMMA), n_iter=15)
+    res_cg = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=K, a=A, gamma=GAMMA,
+                                precond="none", max_iter=15)
+    assert list(res_cg.trace["ell"]) == ref_cg.trace["ell"]
+    assert rel_l2(res_cg.x_half.cpu().numpy(), ref_cg.x_half) <= 1e-3
+
+
+def test_nonzero_start_and_paper_preset(sp, small):
+    og, img, b, R, prob = small
+    x0 = 0.5 * img
+    p = osup.TVParams(K=4, a=1 - 1e-3, gamma=1e-2)
+    ref = osup.suppcg(prob, x0.astype(np.float64).ravel(), p, n_iter=6)
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), cuda(x0), K=4, a=1 - 1e-3, gamma=1e-2,
+                             mu=MU, rho=RHO, max_iter=6)
+    assert list(res.trace["ell"]) == ref.trace["ell"]
+    assert rel_l2(res.x_half.cpu().numpy(), ref.x_half) <= 1e-3
+
+
+def test_graph_equals_eager_and_deterministic(sp, small):
+    og, img, b, R, prob = small
+    kw = dict(K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO, max_iter=12)
+    r1 = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, **kw)
+    r2 = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, **kw)
+    r3 = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, graph=True, **kw)
+    for r in (r2, r3):
+        assert torch.equal(r1.x_half, r.x_half) and torch.equal(r1.x_last, r.x_last)
+        assert np.array_equal(r1.trace["f_half"], r.trace["f_half"])
+
+
+def test_eps_termination_matches_oracle(sp, small, small_ref):
+    og, img, b, R, prob = small
+    f = small_ref.trace["f_half"]
+    eps = 0.5 * (f[5] + f[6])
+    ref = osup.suppcg(prob, np.zeros(og.n), osup.TVParams(K, A, GAMMA), n_iter=50, eps=eps)
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                             max_iter=50, eps=eps)
+    assert ref.status == "converged" and res.status_name == "converged"
+    assert res.k == ref.k
+    assert rel_l2(res.x_half.cpu().numpy(), ref.x_half) <= 1e-3
+
+
+def test_replay_reproduces_trials(sp, small, small_ref):
+    og, img, b, R, prob = small
+    rep = [tt[0] for tt in small_ref.trace["trials"]]
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                             max_iter=20, replay=rep)
+    assert list(res.trace["ell"]) == small_ref.trace["ell"]
+
+
+def test_breakdown_on_zero_data(sp, small):
+    og = small[0]
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(np.zeros((og.n_angles, og.n_bins))), None,
+                             K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO, max_iter=5)
+    assert res.status_name.startswith("breakdown") and res.k == 1
+
+
+def test_nonfinite_data_reported(sp, small):
+    og, img, b, R, prob = small
+    bad = b.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(sp.SupPCGError) as e:
+        sp.sp_suppcg_solve(geom(sp, og), cuda(bad), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                           max_iter=3)
+    assert e.value.code == 3
