@@ -113,30 +113,42 @@ def main():
     b = torch.from_numpy(b_np.reshape(g.n_angles, g.n_bins)).to(dev)
     torch.cuda.synchronize()
 
-    # --- operator timings (HIP events on the library's stream = torch's current stream)
-    def timed(fn, reps):
+    ctx = sp.context(0)
+    L = sp.api.L
+
+    # plain 64 MiB device copy: reference dispatch for scaling the FETCH_SIZE /
+    # WRITE_SIZE hardware counters of a profiled run
+    calib_src = torch.ones(16 * 1024 * 1024, device=dev)
+    calib_dst = torch.empty_like(calib_src)
+    calib_dst.copy_(calib_src)
+    torch.cuda.synchronize()
+    del calib_src, calib_dst
+
+    # --- operator timings: HIP events around each kernel, recorded by the library
+    # on its stream (torch's current stream)
+    def op_ms(fn, kind, reps):
         fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
+        ctx.profile_enable(True)
         for _ in range(reps):
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        ms, n = ctx.profile_read(kind)
+        ctx.profile_enable(False)
+        return ms / max(n, 1)
 
     yout = torch.empty((g.n_angles, g.n_bins), device=dev)
     xout = torch.empty((g.rows, g.cols), device=dev)
-    ms_R = timed(lambda: sp.sp_project(g, x_true, yout), args.reps)
-    ms_RT = timed(lambda: sp.sp_backproject(g, b, xout), args.reps)
-    ms_M = timed(lambda: sp.sp_precond_apply(g, xout, 1e-5, 0.8), args.reps)
+    ms_R = op_ms(lambda: sp.sp_project(g, x_true, yout), L.SP_PROF_PROJECT, args.reps)
+    ms_RT = op_ms(lambda: sp.sp_backproject(g, b, xout), L.SP_PROF_BACKPROJECT, args.reps)
+    ms_M = op_ms(lambda: sp.sp_precond_apply(g, xout, 1e-5, 0.8), L.SP_PROF_PRECOND, args.reps)
 
-    # --- SupPCG iterations
-    kw = dict(K=1, a=0.5, gamma=0.5, mu=1e-5, rho=0.8, graph=not args.eager, trace=True)
+    # --- SupPCG iterations (timed region).  Every R, R^T, M and S_TV launch of the
+    # timed solve is bracketed by HIP events in the library; the loop then runs
+    # eagerly (a captured graph cannot time its nodes one by one).
+    kw = dict(K=1, a=0.5, gamma=0.5, mu=1e-5, rho=0.8, trace=True)
     if args.warmup > 0:
-        sp.sp_suppcg_solve(g, b, None, max_iter=args.warmup, **kw)
+        sp.sp_suppcg_solve(g, b, None, max_iter=args.warmup, graph=not args.eager, **kw)
     torch.cuda.synchronize()
+    ctx.profile_enable(True)
     t0 = time.perf_counter()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -148,9 +160,23 @@ def main():
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / args.steps
     value = args.steps / (ms_total / 1e3)
+    solve_ms = {name: ctx.profile_read(kind) for name, kind in
+                (("project", L.SP_PROF_PROJECT), ("backproject", L.SP_PROF_BACKPROJECT),
+                 ("precond", L.SP_PROF_PRECOND), ("s_tv", L.SP_PROF_TV),
+                 ("iteration", L.SP_PROF_ITERATION))}
+    ctx.profile_enable(False)
+    # the same solve replayed from a captured graph (context only)
+    torch.cuda.synchronize()
+    e0.record()
+    sp.sp_suppcg_solve(g, b, None, max_iter=args.steps, graph=True, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    graph_value = args.steps / (e0.elapsed_time(e1) / 1e3)
 
     bytes_equiv = 8 * NNZ_CT512 + 4 * g.n + 4 * g.m
-    dom_name, dom_ms = ("backproject", ms_RT) if ms_RT >= ms_R else ("project", ms_R)
+    avg = {k: v[0] / max(v[1], 1) for k, v in solve_ms.items()}
+    dom_name = "backproject" if avg["backproject"] >= avg["project"] else "project"
+    dom_ms = avg[dom_name]
     achieved = OPS_PER_NNZ * NNZ_CT512 / (dom_ms / 1e3)
     out = {
         "metric": "SupPCG iterations/s at 512^2 x 720 angles x 725 bins",
@@ -167,17 +193,21 @@ def main():
         "data": "synthetic random-ellipse phantom (20 ellipses, seed 1), 0.5% Gaussian noise",
         "config": {"workload": "ct512: 512x512 image, 720 angles over [0,pi), 725 bins, "
                                "SupPCG K=1 a=0.5 gamma=0.5, ramp-Hamming M mu=1e-5 rho=0.8",
-                   "iterations": args.steps, "graph": not args.eager},
+                   "iterations": args.steps, "timed_loop": "eager, event-timed kernels",
+                   "graph_iterations_per_s": round(graph_value, 3)},
         "roofline": {"bound": "alu", "kernel": dom_name,
                      "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_OPS / 1e12, 4),
-                     "unit": "Tops/s (FP32 VALU lane-ops)",
-                     "frac": round(achieved / PEAK_VALU_OPS, 4), "traffic": None},
+                     "unit": "Tops/s (VALU lane-ops, 4 per nonzero weight)",
+                     "frac": round(achieved / PEAK_VALU_OPS, 4), "traffic": None,
+                     "kernel_ms": round(dom_ms, 4), "launches": solve_ms[dom_name][1]},
+        "in_solve_ms": {k: round(v, 4) for k, v in avg.items()},
         "operators_ms": {"project": round(ms_R, 4), "backproject": round(ms_RT, 4),
                          "precond": round(ms_M, 4)},
-        "gbps_equiv": {"project": round(bytes_equiv / (ms_R / 1e3) / 1e9, 1),
-                       "backproject": round(bytes_equiv / (ms_RT / 1e3) / 1e9, 1),
-                       "frac_of_8TBps_project": round(bytes_equiv / (ms_R / 1e3) / PEAK_HBM, 3),
-                       "frac_of_8TBps_backproject": round(bytes_equiv / (ms_RT / 1e3) / PEAK_HBM, 3)},
+        "gbps_equiv": {"bytes_per_call": bytes_equiv,
+                       "project": round(bytes_equiv / (avg["project"] / 1e3) / 1e9, 1),
+                       "backproject": round(bytes_equiv / (avg["backproject"] / 1e3) / 1e9, 1),
+                       "frac_of_8TBps_project": round(bytes_equiv / (avg["project"] / 1e3) / PEAK_HBM, 3),
+                       "frac_of_8TBps_backproject": round(bytes_equiv / (avg["backproject"] / 1e3) / PEAK_HBM, 3)},
         "solve": {"k": res.k, "status": res.status_name, "wall_s": round(wall, 4),
                   "f_last": float(res.trace["f_half"][-1]) if len(res.trace["f_half"]) else None,
                   "ell_last": int(res.trace["ell"][-1]) if len(res.trace["ell"]) else None},

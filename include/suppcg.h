@@ -187,6 +187,19 @@ int sp_suppcg_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const flo
                     const sp_tv_params* tv, const sp_precond* pc, const sp_solve_params* sp,
                     float* x_out, float* x_last, int32_t* k_out, sp_trace* trace);
 
+/* ---- instrumentation --------------------------------------------------------- */
+/* While profiling is enabled on a context, every projector, backprojector,
+ * preconditioner, S_TV and loop-body launch made through it is bracketed by
+ * HIP events on the context's stream, and sp_suppcg_solve runs its loop
+ * eagerly (SP_FLAG_GRAPH is ignored).  sp_profile_read synchronises the stream
+ * and returns the summed milliseconds and the number of timed launches of one
+ * kind since profiling was last enabled.  Events are created on the host; no
+ * device memory is allocated. */
+enum { SP_PROF_PROJECT = 0, SP_PROF_BACKPROJECT = 1, SP_PROF_PRECOND = 2, SP_PROF_TV = 3,
+       SP_PROF_ITERATION = 4, SP_PROF_KINDS = 5 };
+int sp_profile_enable(sp_ctx* ctx, int on);
+int sp_profile_read(sp_ctx* ctx, int kind, double* total_ms, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,6 +32,12 @@ SP_PRECOND_LEARNED = 2
 SP_FLAG_REPLAY = 1
 SP_FLAG_GRAPH = 2
 
+SP_PROF_PROJECT = 0
+SP_PROF_BACKPROJECT = 1
+SP_PROF_PRECOND = 2
+SP_PROF_TV = 3
+SP_PROF_ITERATION = 4
+
 STATUS_NAMES = {
     SP_OK: "ok", SP_ERR_ARG: "invalid argument", SP_ERR_NOT_SPD: "preconditioner not SPD",
     SP_ERR_NONFINITE: "non-finite value", SP_ERR_HIP: "HIP error", SP_ERR_ALLOC: "allocation failed",
@@ -84,6 +90,8 @@ _SIGS = {
     "sp_suppcg_solve": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p,
                                 POINTER(sp_tv_params), POINTER(sp_precond), POINTER(sp_solve_params),
                                 c_void_p, c_void_p, POINTER(c_int32), POINTER(sp_trace)]),
+    "sp_profile_enable": (c_int, [c_void_p, c_int]),
+    "sp_profile_read": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int32)]),
 }
 
 _lib = None

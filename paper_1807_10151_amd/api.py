@@ -77,6 +77,20 @@ class Context:
         s = torch.cuda.current_stream(self.device).cuda_stream
         self.lib.sp_ctx_set_stream(self.h, ctypes.c_void_p(s))
 
+    def profile_enable(self, on: bool = True):
+        """Time every projector/backprojector/preconditioner/S_TV launch with HIP
+        events (the solver then runs its loop eagerly)."""
+        self._stream()
+        self._check(self.lib.sp_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self, kind: int):
+        """(total_ms, launches) of one SP_PROF_* kind since profile_enable."""
+        self._stream()
+        ms = ctypes.c_double()
+        n = ctypes.c_int32()
+        self._check(self.lib.sp_profile_read(self.h, kind, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def _check(self, rc, ok=(L.SP_OK,)):
         if rc not in ok:
             raise SupPCGError(rc, self.lib.sp_last_error(self.h).decode())

@@ -46,6 +46,16 @@ struct sp_ctx {
     DevBuf scal, trace_d, replay_d, trials_tmp;
     Scalars sc_h{};
     hipStream_t own = nullptr;   // capture stream used when the caller's stream is null
+
+    // instrumentation: event pairs around launches (sp_profile_enable)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct ProfRec {
+        int kind;
+        size_t e0, e1;
+    };
+    std::vector<ProfRec> prof_recs;
 };
 
 namespace {
@@ -331,6 +341,32 @@ int check_launch(sp_ctx* c) {
     return SP_OK;
 }
 
+size_t prof_mark(sp_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return (size_t)-1;
+        c->ev_pool.push_back(e);
+    }
+    (void)hipEventRecord(c->ev_pool[c->ev_used], c->stream);
+    return c->ev_used++;
+}
+
+// Brackets the launches made in its scope with events when profiling is on.
+struct ProfScope {
+    sp_ctx* c;
+    int kind;
+    size_t e0 = (size_t)-1;
+    ProfScope(sp_ctx* c_, int k) : c(c_), kind(k) {
+        if (c->prof) e0 = prof_mark(c);
+    }
+    ~ProfScope() {
+        if (c->prof && e0 != (size_t)-1) {
+            const size_t e1 = prof_mark(c);
+            if (e1 != (size_t)-1) c->prof_recs.push_back({kind, e0, e1});
+        }
+    }
+};
+
 // One S_TV call (Algorithm 1) from x into xh, K inner steps.
 void enqueue_stv(sp_ctx* c, int K, const float* x, float* xh, bool snorm, TraceDev tr,
                  int32_t* trials_out) {
@@ -339,6 +375,7 @@ void enqueue_stv(sp_ctx* c, int K, const float* x, float* xh, bool snorm, TraceD
     Scalars* sc = dptr<Scalars>(c->scal);
     const int* halt = &sc->halt;
     const int nb = tv_blocks(G.rows, G.cols);
+    ProfScope ps(c, SP_PROF_TV);
     for (int i = 0; i < K; ++i) {
         const float* src = i == 0 ? x : xh;
         launch_tv_grad(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), halt);
@@ -368,7 +405,10 @@ int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, c
     FFTPlan F{};
     int rc = setup_fft(c, F);
     if (rc) return rc;
-    launch_precond(c->stream, F, pc->mu, pc->rho, g, z, dotv, partials, halt);
+    {
+        ProfScope ps(c, SP_PROF_PRECOND);
+        launch_precond(c->stream, F, pc->mu, pc->rho, g, z, dotv, partials, halt);
+    }
     nparts = precond_dot_blocks(F);
     return SP_OK;
 }
@@ -404,6 +444,7 @@ int sp_ctx_destroy(sp_ctx* c) {
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
         release(*b);
     if (c->own) (void)hipStreamDestroy(c->own);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return SP_OK;
 }
@@ -416,6 +457,34 @@ int sp_ctx_set_stream(sp_ctx* c, void* hip_stream) {
 
 const char* sp_last_error(const sp_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+int sp_profile_enable(sp_ctx* c, int on) {
+    if (!c) return SP_ERR_ARG;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->prof = on != 0;
+    c->prof_recs.clear();
+    c->ev_used = 0;
+    return SP_OK;
+}
+
+int sp_profile_read(sp_ctx* c, int kind, double* total_ms, int32_t* count) {
+    if (!c) return SP_ERR_ARG;
+    if (kind < 0 || kind >= SP_PROF_KINDS || !total_ms || !count)
+        return fail(c, SP_ERR_ARG, "sp_profile_read: bad kind or null output");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    int32_t n = 0;
+    for (const auto& r : c->prof_recs) {
+        if (r.kind != kind) continue;
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[r.e0], c->ev_pool[r.e1]));
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *count = n;
+    return SP_OK;
+}
+
 int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
     if (!c) return SP_ERR_ARG;
     if (!x || !y) return fail(c, SP_ERR_ARG, "x and y must be device pointers");
@@ -424,8 +493,11 @@ int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
     if (rc) return rc;
     const GeomDev& G = c->G;
     launch_prep(c->stream, G, x, dptr<float>(c->xp), dptr<float>(c->xTp), nullptr);
-    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->xp), dptr<float>(c->xTp), nullptr, y,
-                   G.nB, 0, nullptr, nullptr);
+    {
+        ProfScope ps(c, SP_PROF_PROJECT);
+        launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->xp), dptr<float>(c->xTp),
+                       nullptr, y, G.nB, 0, nullptr, nullptr);
+    }
     return check_launch(c);
 }
 
@@ -437,7 +509,11 @@ int sp_backproject(sp_ctx* c, const sp_geometry* g, const float* y, float* x) {
     if (rc) return rc;
     const GeomDev& G = c->G;
     launch_pad_sino(c->stream, G, y, dptr<float>(c->yp));
-    launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp), x, nullptr, nullptr, nullptr);
+    {
+        ProfScope ps(c, SP_PROF_BACKPROJECT);
+        launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp), x, nullptr,
+                           nullptr, nullptr);
+    }
     return check_launch(c);
 }
 
@@ -539,7 +615,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     if (!c) return SP_ERR_ARG;
     if (!b || !x_out || !k_out || !sp) return fail(c, SP_ERR_ARG, "b, x_out, k_out and params are required");
     HIP_TRY(c, hipSetDevice(c->device));
-    if ((sp->flags & SP_FLAG_GRAPH) && c->stream == nullptr) {
+    if ((sp->flags & SP_FLAG_GRAPH) && c->stream == nullptr && !c->prof) {
         // The null stream cannot be captured: run the whole solve on an owned
         // stream, ordered after the caller's prior work (the call blocks anyway).
         if (!c->own) HIP_TRY(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
@@ -647,7 +723,16 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
 
     // One loop body (steps 11-14); every launch reads device state only, so
     // the body can be replayed from a captured graph.
+    auto project = [&](const float* bb, double* parts) {
+        ProfScope ps(c, SP_PROF_PROJECT);
+        launch_project(st, G, ang, xp, xTp, bb, rp + PAD, G.pitchB, 0, parts, halt);
+    };
+    auto backproject = [&](float* out, const float* dotv, double* parts) {
+        ProfScope ps(c, SP_PROF_BACKPROJECT);
+        launch_backproject(st, G, ang, rp, out, dotv, parts, halt);
+    };
     auto body = [&]() -> int {
+        ProfScope ps(c, SP_PROF_ITERATION);
         if (K > 0) {
             enqueue_stv(c, K, x, xh, true, tr, nullptr);            // S_TV -> x_{k+1/2}
         } else {
@@ -655,24 +740,24 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         }
         // U_PCG(x_{k+1/2}, p_{k-1}, h_{k-1})
         launch_prep(st, G, xh, xp, xTp, halt);
-        launch_project(st, G, ang, xp, xTp, b, rp + PAD, G.pitchB, 0, pf, halt);   // r = R x - b
+        project(b, pf);                                                           // r = R x - b
         launch_scalar(st, OP_F, sc, tr, pf, nf, nullptr, 0);                      // f(x_{k+1/2})
-        launch_backproject(st, G, ang, rp, gv, nullptr, nullptr, halt);            // g = R^T r
+        backproject(gv, nullptr, nullptr);                                        // g = R^T r
         int nz = 0;
         int r2 = enqueue_precond(c, pc, gv, z, h, pzh, nz);                        // z = M g
         if (r2) return r2;
         launch_scalar(st, OP_BETA, sc, tr, pzh, nz, nullptr, 0);                  // beta
         launch_update_p(st, n, z, p, gv, sc, pgp, halt);                          // p = -z + beta p
         launch_prep(st, G, p, xp, xTp, halt);
-        launch_project(st, G, ang, xp, xTp, nullptr, rp + PAD, G.pitchB, 0, nullptr, halt);
-        launch_backproject(st, G, ang, rp, h, p, pph, halt);                      // h = A p
+        project(nullptr, nullptr);
+        backproject(h, p, pph);                                                   // h = A p
         launch_scalar(st, OP_ALPHA, sc, tr, pph, nph, pgp, ngp);                  // alpha
         launch_update_x(st, n, xh, p, x, sc, halt);                               // x = x + alpha p
         return check_launch(c);
     };
 
     const bool poll = sp->eps > 0.0;
-    if ((sp->flags & SP_FLAG_GRAPH) && sp->max_iter > 0) {
+    if ((sp->flags & SP_FLAG_GRAPH) && sp->max_iter > 0 && !c->prof) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));

@@ -116,24 +116,54 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
     hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     double acc = 0.0;
+    if (lo >= hi) return acc;
+    // Candidate n of step m is minor index floor(nf_m) + 1 + q, clamped so that
+    // the NC reads stay inside the padded row (clamped reads hit zero pads).
+    // Offsets are kept relative to the start of the padded row (>= 0).
+    const float* row = img - PAD;
+    // minor coordinate of candidate 0 = floor(nf) + c1 (exact: small half-integers)
+    const double c1 = HORIZ ? G.yoff - 1.0 : 1.0 - G.xoff;
+    const double dM = HORIZ ? 1.0 : -1.0;                     // major coordinate step
+    double cM = HORIZ ? (double)lo - G.xoff : G.yoff - (double)lo;
     double nf = fma((double)lo, A.slope, start);
-    for (int m = lo; m < hi; ++m) {
-        const double nfl = floor(nf);
-        nf += A.slope;
-        int n0 = (int)nfl + 1;
-        const double cm0 = HORIZ ? G.yoff - (nfl + 1.0) : (nfl + 1.0) - G.xoff;
-        n0 = min(max(n0, -PAD), nmin + PAD - 3);
-        const float* px = img + (size_t)m * pitch + n0;
-        float v[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) v[q] = px[q];
-        const double P = (HORIZ ? ((double)m - G.xoff) : (G.yoff - (double)m)) * fM;
+    const int omax = nmin + 2 * PAD - NC;
+    const float* rp = row + (size_t)lo * pitch;
+    // one major step: gather is issued by the caller, weights and sum here
+    auto step = [&](const float* v, double nfl, double cMv) {
+        const double P = cMv * fM;
+        const double cm0 = HORIZ ? c1 - nfl : nfl + c1;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const double cm = HORIZ ? cm0 - (double)q : cm0 + (double)q;
             const double d = sk - fma(cm, fm, P);
             acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[q], acc);
         }
+    };
+    int m = lo;
+    // two steps per iteration: both gathers are in flight before either step's math
+    for (; m + 1 < hi; m += 2) {
+        const double nfl0 = floor(nf);
+        const double nfl1 = floor(nf + A.slope);
+        const float* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
+        const float* p1 = rp + pitch + min(max((int)nfl1 + 1 + PAD, 0), omax);
+        float v0[NC], v1[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) v0[q] = p0[q];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) v1[q] = p1[q];
+        step(v0, nfl0, cM);
+        step(v1, nfl1, cM + dM);
+        nf += 2.0 * A.slope;
+        cM += 2.0 * dM;
+        rp += 2 * pitch;
+    }
+    if (m < hi) {
+        const double nfl0 = floor(nf);
+        const float* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
+        float v0[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) v0[q] = p0[q];
+        step(v0, nfl0, cM);
     }
     return acc;
 }
@@ -209,22 +239,25 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp
     hipLaunchKernelGGL(k_pad_sino, dim3(G.nA), dim3(256), 0, st, G, y, yp);
 }
 
-// Sum over the angles [beg, end) of one class for pixel (xj, yi).
+// Sum over the angles [beg, end) of one class for pixel (xj, yi).  The angle
+// and its sinogram row are wave-uniform (scalar loads); lanes differ only in
+// the pixel.
 template <bool HORIZ, bool AXIS, int NB>
 __device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
                                            int beg, int end, const float* __restrict__ yp,
                                            double xj, double yi, double acc) {
+    const int kmax = G.nB + 2 * PAD - NB;        // last padded start index
 #pragma unroll 2
     for (int a = beg; a < end; ++a) {
         const AngleDev A = ang[a];
         const double t = HORIZ ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
         const double kfl = floor(fma(t, G.inv_ds, A.kb));
-        int k0 = (int)kfl + 1;
-        k0 = min(max(k0, -PAD), G.nB + PAD - NB);
-        const float* pr = yp + (size_t)A.row * G.pitchB + PAD + k0;
+        // padded index of candidate bin floor(kf) + 1, clamped into the zero pads
+        const unsigned o = (unsigned)min(max((int)kfl + 1 + PAD, 0), kmax);
+        const float* pr = yp + (size_t)A.row * G.pitchB;
         float v[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) v[q] = pr[q];
+        for (int q = 0; q < NB; ++q) v[q] = pr[o + q];
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const double d = bin_pos(kfl + (double)(1 + q), G) - t;
@@ -234,8 +267,19 @@ __device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __r
     return acc;
 }
 
+constexpr int BP_TILE = 8;      // 8 x 8 pixels per wave
+constexpr int BP_SPLIT = 4;     // waves per workgroup, each over a quarter of the angles
+
+__device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int& e) {
+    const int len = end - beg;
+    b = beg + (len * w) / BP_SPLIT;
+    e = beg + (len * (w + 1)) / BP_SPLIT;
+}
+
 // out[i][j] = (R^T y)_{ij} from the padded sinogram yp; with dotv != nullptr
-// also the float64 partial sum of out * dotv per workgroup.
+// also the float64 partial sum of out * dotv per workgroup.  A workgroup owns
+// an 8 x 8 pixel tile; its wave w sums the w-th quarter of every angle class,
+// and the four partial sums are added in wave order through LDS.
 template <int NB>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
                                                      const float* __restrict__ yp,
@@ -244,31 +288,49 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
                                                      double* __restrict__ partials,
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
+    __shared__ double part[BP_SPLIT][64];
     __shared__ double red[4];
-    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
-    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
-    const bool valid = i < G.rows && j < G.cols;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = blockIdx.y * BP_TILE + (lane >> 3);
+    const int j = blockIdx.x * BP_TILE + (lane & 7);
     const double xj = (double)j - G.xoff;
     const double yi = G.yoff - (double)i;
     double acc = 0.0;
-    acc = bp_class<false, false, NB>(G, ang, G.cls[0], G.cls[1], yp, xj, yi, acc);
-    acc = bp_class<true, false, NB>(G, ang, G.cls[1], G.cls[2], yp, xj, yi, acc);
-    acc = bp_class<false, true, NB>(G, ang, G.cls[2], G.cls[3], yp, xj, yi, acc);
-    acc = bp_class<true, true, NB>(G, ang, G.cls[3], G.cls[4], yp, xj, yi, acc);
-    const float val = (float)(acc * G.pixel);
-    if (valid) out[(size_t)i * G.cols + j] = val;
+    int b, e;
+    split_range(G.cls[0], G.cls[1], w, b, e);
+    acc = bp_class<false, false, NB>(G, ang, b, e, yp, xj, yi, acc);
+    split_range(G.cls[1], G.cls[2], w, b, e);
+    acc = bp_class<true, false, NB>(G, ang, b, e, yp, xj, yi, acc);
+    split_range(G.cls[2], G.cls[3], w, b, e);
+    acc = bp_class<false, true, NB>(G, ang, b, e, yp, xj, yi, acc);
+    split_range(G.cls[3], G.cls[4], w, b, e);
+    acc = bp_class<true, true, NB>(G, ang, b, e, yp, xj, yi, acc);
+    part[w][lane] = acc;
+    __syncthreads();
+    double v = 0.0;
+    if (w == 0) {
+        const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        const float val = (float)(tot * G.pixel);
+        const bool valid = i < G.rows && j < G.cols;
+        if (valid) {
+            out[(size_t)i * G.cols + j] = val;
+            if (dotv) v = (double)val * (double)dotv[(size_t)i * G.cols + j];
+        }
+    }
     if (dotv) {
-        const double v = valid ? (double)val * (double)dotv[(size_t)i * G.cols + j] : 0.0;
         const double tot = block_sum(v, red);
         if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
     }
 }
 
-int backproject_blocks(const GeomDev& G) { return ((G.cols + 15) / 16) * ((G.rows + 15) / 16); }
+int backproject_blocks(const GeomDev& G) {
+    return ((G.cols + BP_TILE - 1) / BP_TILE) * ((G.rows + BP_TILE - 1) / BP_TILE);
+}
 
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
                         float* out, const float* dotv, double* partials, const int* halt) {
-    dim3 grid((G.cols + 15) / 16, (G.rows + 15) / 16);
+    dim3 grid((G.cols + BP_TILE - 1) / BP_TILE, (G.rows + BP_TILE - 1) / BP_TILE);
     switch (G.nbmax) {
     case 1: hipLaunchKernelGGL(k_backproject<1>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
     case 2: hipLaunchKernelGGL(k_backproject<2>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
