@@ -127,6 +127,8 @@ typedef struct {
     int32_t cap;
     double f0;      /* out: f(x_0) */
     double alpha0;  /* out: alpha of the initial step (Alg. 3, step 6) */
+    int32_t fallbacks; /* out: 1 if a learned preconditioner was replaced by the
+                          Fourier one during the run, else 0 */
 } sp_trace;
 
 /* ---- context ------------------------------------------------------------ */
@@ -186,6 +188,41 @@ int sp_tv_perturb(sp_ctx* ctx, const sp_geometry* g, const sp_tv_params* p, cons
 int sp_suppcg_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const float* x0,
                     const sp_tv_params* tv, const sp_precond* pc, const sp_solve_params* sp,
                     float* x_out, float* x_last, int32_t* k_out, sp_trace* trace);
+
+/* ---- learned preconditioner ---------------------------------------------------
+ * M = C^T diag(softplus(d)) C, with C a stack of `layers` linear 3x3
+ * convolutions without bias (cross-correlation, zero "same" padding),
+ * 1 -> channels -> ... -> channels, and C^T its exact adjoint; M is symmetric
+ * positive semi-definite by construction.  Not in the paper: it replaces the
+ * Fourier preconditioner of Section 3.2 in step 2 of Algorithm 2 when passed
+ * as sp_precond{SP_PRECOND_LEARNED, mu, rho, net}; (mu, rho) then define the
+ * Fourier preconditioner the solver switches to, for the rest of the run, as
+ * soon as g^T z <= 0 or g^T z is not finite.
+ * Parameters theta (float32, num_params values): W_1 [channels][1][3][3],
+ * W_2..W_L [channels][channels][3][3], d [channels]; tap (ky, kx) reads the
+ * input at offset (ky - 1, kx - 1).  Supported: channels = 16,
+ * 1 <= layers <= 8.  The object owns its parameters, Adam moments and
+ * workspace (device memory of the context's GPU). */
+int sp_lp_create(sp_ctx* ctx, int32_t layers, int32_t channels, sp_learned** out);
+int sp_lp_destroy(sp_learned* net);
+int64_t sp_lp_num_params(const sp_learned* net);
+/* Copies count = num_params float32 values from / to HOST memory. */
+int sp_lp_set_params(sp_ctx* ctx, sp_learned* net, const float* theta, int64_t count);
+int sp_lp_get_params(sp_ctx* ctx, const sp_learned* net, float* theta, int64_t count);
+/* z = M u for `batch` images u, z: [batch][rows][cols] float32 (device). */
+int sp_lp_apply(sp_ctx* ctx, sp_learned* net, int32_t batch, int32_t rows, int32_t cols,
+                const float* u, float* z);
+/* Training loss over the minibatch idx[0..batch) (device int32, values in
+ * [0, nprobe)) of probe pairs Av, v ([nprobe][rows][cols], device):
+ * loss = mean_b ||M(Av_b) - v_b||^2 / ||v_b||^2 -> *loss (device float64);
+ * grad (device float32, num_params) = d loss / d theta. */
+int sp_lp_loss_grad(sp_ctx* ctx, sp_learned* net, int32_t rows, int32_t cols, const float* Av,
+                    const float* v, int32_t nprobe, const int32_t* idx, int32_t batch,
+                    double* loss, float* grad);
+/* One Adam step theta -= lr * mhat / (sqrt(vhat) + eps) with gradient grad
+ * (device float32); step counts from 1. */
+int sp_lp_adam_step(sp_ctx* ctx, sp_learned* net, const float* grad, double lr, double beta1,
+                    double beta2, double eps, int32_t step);
 
 /* ---- instrumentation --------------------------------------------------------- */
 /* While profiling is enabled on a context, every projector, backprojector,

@@ -70,7 +70,7 @@ class sp_trace(ctypes.Structure):
                 ("alpha", POINTER(c_double)), ("beta", POINTER(c_double)),
                 ("s_norm", POINTER(c_double)), ("ell", POINTER(c_int32)),
                 ("trials", POINTER(c_int32)), ("cap", c_int32),
-                ("f0", c_double), ("alpha0", c_double)]
+                ("f0", c_double), ("alpha0", c_double), ("fallbacks", c_int32)]
 
 
 _SIGS = {
@@ -90,6 +90,16 @@ _SIGS = {
     "sp_suppcg_solve": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p,
                                 POINTER(sp_tv_params), POINTER(sp_precond), POINTER(sp_solve_params),
                                 c_void_p, c_void_p, POINTER(c_int32), POINTER(sp_trace)]),
+    "sp_lp_create": (c_int, [c_void_p, c_int32, c_int32, POINTER(c_void_p)]),
+    "sp_lp_destroy": (c_int, [c_void_p]),
+    "sp_lp_num_params": (ctypes.c_int64, [c_void_p]),
+    "sp_lp_set_params": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]),
+    "sp_lp_get_params": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]),
+    "sp_lp_apply": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "sp_lp_loss_grad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32,
+                                c_void_p, c_int32, c_void_p, c_void_p]),
+    "sp_lp_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double,
+                                c_double, c_int32]),
     "sp_profile_enable": (c_int, [c_void_p, c_int]),
     "sp_profile_read": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int32)]),
 }

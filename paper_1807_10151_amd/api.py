@@ -157,19 +157,96 @@ def sp_residual(g: Geometry, x: torch.Tensor, b: torch.Tensor, ctx: Context | No
     return r, f
 
 
-def _precond(kind, mu, rho):
-    k = {"ramp": L.SP_PRECOND_RAMP, "none": L.SP_PRECOND_NONE}[kind] if isinstance(kind, str) else kind
-    return L.sp_precond(k, mu, rho, None)
+class LearnedPrecond:
+    """M = C^T diag(softplus(d)) C (sp_lp_* calls); parameters live on the GPU."""
+
+    def __init__(self, layers: int = 4, channels: int = 16, ctx: Context | None = None):
+        self.ctx = ctx or context(0)
+        h = ctypes.c_void_p()
+        self.ctx._check(self.ctx.lib.sp_lp_create(self.ctx.h, layers, channels, ctypes.byref(h)))
+        self.h = h
+        self.layers = layers
+        self.channels = channels
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.sp_lp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(self.ctx.lib.sp_lp_num_params(self.h))
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).ravel())
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_lp_set_params(
+            self.ctx.h, self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.num_params, dtype=np.float32)
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_lp_get_params(
+            self.ctx.h, self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+        return a
+
+    def apply(self, u: torch.Tensor, z: torch.Tensor | None = None):
+        """z = M u for u of shape [B, H, W] or [H, W]."""
+        shape = tuple(u.shape)
+        B, H, W = (1,) + shape if len(shape) == 2 else shape
+        z = _out(z, shape, self.ctx.device)
+        self.ctx._stream()
+        n = B * H * W
+        self.ctx._check(self.ctx.lib.sp_lp_apply(self.ctx.h, self.h, B, H, W,
+                                                 _dev(u, n, "u", self.ctx.device),
+                                                 _dev(z, n, "z", self.ctx.device)))
+        return z
+
+    def loss_grad(self, Av: torch.Tensor, v: torch.Tensor, idx: torch.Tensor,
+                  grad: torch.Tensor | None = None):
+        """(loss [float64 0-d], grad [num_params]) on the minibatch idx of (Av, v)."""
+        N, H, W = Av.shape
+        if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
+            raise TypeError("idx must be a contiguous int32 CUDA tensor")
+        dev = f"cuda:{self.ctx.device}"
+        loss = torch.empty((), dtype=torch.float64, device=dev)
+        grad = _out(grad, (self.num_params,), self.ctx.device)
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_lp_loss_grad(
+            self.ctx.h, self.h, H, W, _dev(Av, N * H * W, "Av", self.ctx.device),
+            _dev(v, N * H * W, "v", self.ctx.device), N, ctypes.c_void_p(idx.data_ptr()),
+            idx.numel(), ctypes.c_void_p(loss.data_ptr()),
+            _dev(grad, self.num_params, "grad", self.ctx.device)))
+        return loss, grad
+
+    def adam_step(self, grad: torch.Tensor, lr: float, step: int, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_lp_adam_step(
+            self.ctx.h, self.h, _dev(grad, self.num_params, "grad", self.ctx.device), lr, beta1,
+            beta2, eps, step))
+
+
+def _precond(kind, mu, rho, net=None):
+    k = {"ramp": L.SP_PRECOND_RAMP, "none": L.SP_PRECOND_NONE,
+         "learned": L.SP_PRECOND_LEARNED}[kind] if isinstance(kind, str) else kind
+    return L.sp_precond(k, mu, rho, net.h if net is not None else None)
 
 
 def sp_precond_apply(g: Geometry, gin: torch.Tensor, mu: float = 1e-5, rho: float = 0.8,
-                     kind="ramp", z: torch.Tensor | None = None, ctx: Context | None = None):
+                     kind="ramp", z: torch.Tensor | None = None, net=None,
+                     ctx: Context | None = None):
     """z = M g with the ramp-Hamming Fourier preconditioner (or M = I)."""
     ctx = ctx or context(gin.device.index or 0)
     z = _out(z, (g.rows, g.cols), ctx.device)
     ctx._stream()
     gc = g.c()
-    pc = _precond(kind, mu, rho)
+    pc = _precond(kind, mu, rho, net)
     ctx._check(ctx.lib.sp_precond_apply(ctx.h, ctypes.byref(gc), ctypes.byref(pc),
                                         _dev(gin, g.n, "g", ctx.device), _dev(z, g.n, "z", ctx.device)))
     return z
@@ -236,6 +313,7 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
                     precond="ramp", mu: float = 1e-5, rho: float = 0.8, max_iter: int = 20,
                     eps: float = 0.0, graph: bool = False, replay=None, trace: bool = True,
                     x_half: torch.Tensor | None = None, x_last: torch.Tensor | None = None,
+                    net: "LearnedPrecond | None" = None,
                     ctx: Context | None = None) -> SolveResult:
     """Algorithm 3 (SupPCG); K = 0 gives plain PCG, precond="none" gives CG."""
     ctx = ctx or context(b.device.index or 0)
@@ -244,7 +322,7 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
     x_last = _out(x_last, (g.rows, g.cols), dev)
     gc = g.c()
     tvp = L.sp_tv_params(K, a, gamma, max_trials)
-    pc = _precond(precond, mu, rho)
+    pc = _precond(precond, mu, rho, net)
     flags = (L.SP_FLAG_GRAPH if graph else 0)
     rep_arr = None
     if replay is not None:
@@ -281,4 +359,5 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
                for key, v in arrs.items()}
         out["f0"] = tr.f0
         out["alpha0"] = tr.alpha0
+        out["fallbacks"] = tr.fallbacks
     return SolveResult(k_out.value, x_half, x_last, rc, out)

@@ -58,6 +58,18 @@ struct sp_ctx {
     std::vector<ProfRec> prof_recs;
 };
 
+// Learned preconditioner: parameters, Adam moments and workspace.
+struct sp_learned {
+    int device = 0;
+    int layers = 0, channels = 16, nparams = 0;
+    DevBuf theta, adam_m, adam_v, spsg;   // spsg: softplus(d) [16], sigmoid(d) [16]
+    size_t cap_pix = 0;                   // pixels the activation buffers hold
+    std::vector<DevBuf> act;              // training: a_1..a_L, b_1..b_L, e_1..e_L
+    DevBuf a0, z, e0, ping, pong, partial, lpart, gdpart;
+    int woff(int l) const { return l == 1 ? 0 : 144 + (l - 2) * 2304; }   // W_l offset
+    int doff() const { return 144 + (layers - 1) * 2304; }
+};
+
 namespace {
 
 int fail(sp_ctx* c, int code, const char* fmt, ...) {
@@ -293,7 +305,15 @@ int check_precond(sp_ctx* c, const sp_precond* pc) {
                         pc->mu, pc->rho);
         return SP_OK;
     }
-    if (pc->kind == SP_PRECOND_LEARNED) return fail(c, SP_ERR_ARG, "learned preconditioner not available");
+    if (pc->kind == SP_PRECOND_LEARNED) {
+        if (!pc->net) return fail(c, SP_ERR_ARG, "SP_PRECOND_LEARNED needs a network");
+        if (pc->net->device != c->device) return fail(c, SP_ERR_ARG, "network lives on another GPU");
+        if (!std::isfinite(pc->mu) || !std::isfinite(pc->rho) || !(pc->mu > 0.0) ||
+            !(pc->rho > 0.5) || pc->rho > 1.0)
+            return fail(c, SP_ERR_NOT_SPD,
+                        "the fallback Fourier preconditioner needs mu > 0 and 1/2 < rho <= 1");
+        return SP_OK;
+    }
     return fail(c, SP_ERR_ARG, "unknown preconditioner kind %d", pc->kind);
 }
 
@@ -325,6 +345,7 @@ int ensure_partials(sp_ctx* c) {
     if ((rc = ensure(c, c->part_g, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
     if ((rc = ensure(c, c->part_t, (size_t)tv_blocks(G.rows, G.cols) * 9 * 8))) return rc;
     if ((rc = ensure(c, c->part_s, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
+    if ((rc = ensure(c, c->part_misc, (size_t)vec_blocks(n) * 8))) return rc;
     if ((rc = ensure(c, c->scal, sizeof(Scalars)))) return rc;
     return SP_OK;
 }
@@ -391,11 +412,67 @@ void enqueue_stv(sp_ctx* c, int K, const float* x, float* xh, bool snorm, TraceD
 }
 
 // z = M g with the partial dots z^T dotv (dotv nullable).
+// Sizes the learned preconditioner's workspace for npix pixels (training
+// buffers only when `train`).
+int lp_reserve(sp_ctx* c, sp_learned* net, size_t npix, bool train, int B, int H, int W) {
+    int rc;
+    const size_t a16 = npix * 16 * sizeof(float);
+    if ((rc = ensure(c, net->ping, a16))) return rc;
+    if ((rc = ensure(c, net->pong, a16))) return rc;
+    if ((rc = ensure(c, net->spsg, 64 * sizeof(float)))) return rc;
+    if (!train) return SP_OK;
+    if (net->act.size() != (size_t)(3 * net->layers)) net->act.resize(3 * net->layers);
+    for (auto& b : net->act)
+        if ((rc = ensure(c, b, a16))) return rc;
+    for (DevBuf* b : {&net->a0, &net->z, &net->e0})
+        if ((rc = ensure(c, *b, npix * sizeof(float)))) return rc;
+    if ((rc = ensure(c, net->partial, (size_t)lp_wgrad_blocks(B, H, W) * 2304 * sizeof(float)))) return rc;
+    if ((rc = ensure(c, net->lpart, (size_t)B * sizeof(double)))) return rc;
+    if ((rc = ensure(c, net->gdpart, (size_t)lp_gd_blocks() * 16 * sizeof(double)))) return rc;
+    return SP_OK;
+}
+
+// z = M u for B images of H x W (u, z device).  Gated by halt / run (nullable).
+int lp_enqueue_apply(sp_ctx* c, sp_learned* net, int B, int H, int W, const float* u, float* z,
+                     const int* halt, const int* run) {
+    const size_t npix = (size_t)B * H * W;
+    int rc = lp_reserve(c, net, npix, false, B, H, W);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    const float* th = dptr<float>(net->theta);
+    float* sps = dptr<float>(net->spsg);
+    const int L = net->layers;
+    float* cur = dptr<float>(net->ping);
+    float* nxt = dptr<float>(net->pong);
+    lp_softplus(st, th + net->doff(), sps, sps + 16);
+    lp_conv_in(st, B, H, W, u, nullptr, B, cur, th + net->woff(1), halt, run);
+    if (L == 1) {
+        lp_scale(st, (long)npix, cur, sps, nxt);
+        std::swap(cur, nxt);
+    }
+    for (int l = 2; l <= L; ++l) {
+        const bool last = l == L;   // b_L = softplus(d) * a_L is all the back path needs
+        lp_conv_mid(st, false, B, H, W, cur, last ? nullptr : nxt, th + net->woff(l),
+                    last ? sps : nullptr, last ? nxt : nullptr, halt, run);
+        std::swap(cur, nxt);
+    }
+    for (int l = L; l >= 2; --l) {
+        lp_conv_mid(st, true, B, H, W, cur, nxt, th + net->woff(l), nullptr, nullptr, halt, run);
+        std::swap(cur, nxt);
+    }
+    lp_conv_out(st, B, H, W, cur, z, th + net->woff(1), halt, run);
+    return SP_OK;
+}
+
+// z = M g (partial dots z^T dotv when dotv != NULL).  In the solver
+// (solver = true) every launch honours the halt flag, and a learned M is
+// checked (g^T z > 0 and finite) with the Fourier M as fallback.
 int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, const float* dotv,
-                    double* partials, int& nparts) {
+                    double* partials, int& nparts, bool solver) {
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
-    const int* halt = &dptr<Scalars>(c->scal)->halt;
+    Scalars* sc = dptr<Scalars>(c->scal);
+    const int* halt = solver ? &sc->halt : nullptr;
     if (pc->kind == SP_PRECOND_NONE) {
         if (g != z) launch_copy(c->stream, n, g, z, halt);
         if (dotv) launch_dot(c->stream, n, z, dotv, partials, halt);
@@ -405,6 +482,23 @@ int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, c
     FFTPlan F{};
     int rc = setup_fft(c, F);
     if (rc) return rc;
+    if (pc->kind == SP_PRECOND_LEARNED) {
+        sp_learned* net = const_cast<sp_learned*>(pc->net);
+        ProfScope ps(c, SP_PROF_PRECOND);
+        if ((rc = lp_enqueue_apply(c, net, 1, G.rows, G.cols, g, z, halt,
+                                   solver ? &sc->gate_learned : nullptr)))
+            return rc;
+        if (solver) {
+            double* pg = dptr<double>(c->part_misc);
+            launch_dot(c->stream, n, g, z, pg, halt);
+            TraceDev none{};
+            launch_scalar(c->stream, OP_LCHECK, sc, none, pg, vec_blocks(n), nullptr, 0);
+            launch_precond(c->stream, F, pc->mu, pc->rho, g, z, nullptr, nullptr, halt, &sc->gate_ramp);
+        }
+        if (dotv) launch_dot(c->stream, n, z, dotv, partials, halt);
+        nparts = vec_blocks(n);
+        return SP_OK;
+    }
     {
         ProfScope ps(c, SP_PROF_PRECOND);
         launch_precond(c->stream, F, pc->mu, pc->rho, g, z, dotv, partials, halt);
@@ -464,6 +558,152 @@ int sp_profile_enable(sp_ctx* c, int on) {
     c->prof_recs.clear();
     c->ev_used = 0;
     return SP_OK;
+}
+
+int sp_lp_create(sp_ctx* c, int32_t layers, int32_t channels, sp_learned** out) {
+    if (!c || !out) return SP_ERR_ARG;
+    *out = nullptr;
+    if (channels != 16) return fail(c, SP_ERR_ARG, "only 16 channels are supported");
+    if (layers < 1 || layers > 8) return fail(c, SP_ERR_ARG, "layers must be in [1, 8]");
+    HIP_TRY(c, hipSetDevice(c->device));
+    sp_learned* net = new sp_learned();
+    net->device = c->device;
+    net->layers = layers;
+    net->channels = channels;
+    net->nparams = 144 + (layers - 1) * 2304 + 16;
+    int rc;
+    for (DevBuf* b : {&net->theta, &net->adam_m, &net->adam_v})
+        if ((rc = ensure(c, *b, (size_t)net->nparams * sizeof(float)))) {
+            delete net;
+            return rc;
+        }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *out = net;
+    return SP_OK;
+}
+
+int sp_lp_destroy(sp_learned* net) {
+    if (!net) return SP_ERR_ARG;
+    (void)hipSetDevice(net->device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf* b : {&net->theta, &net->adam_m, &net->adam_v, &net->spsg, &net->a0, &net->z,
+                      &net->e0, &net->ping, &net->pong, &net->partial, &net->lpart, &net->gdpart})
+        release(*b);
+    for (auto& b : net->act) release(b);
+    delete net;
+    return SP_OK;
+}
+
+int64_t sp_lp_num_params(const sp_learned* net) { return net ? net->nparams : -1; }
+
+int sp_lp_set_params(sp_ctx* c, sp_learned* net, const float* theta, int64_t count) {
+    if (!c) return SP_ERR_ARG;
+    if (!net || !theta || count != net->nparams)
+        return fail(c, SP_ERR_ARG, "sp_lp_set_params: need num_params host values");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(net->theta.ptr, theta, (size_t)count * sizeof(float),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(net->adam_m.ptr, 0, net->adam_m.bytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(net->adam_v.ptr, 0, net->adam_v.bytes, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SP_OK;
+}
+
+int sp_lp_get_params(sp_ctx* c, const sp_learned* net, float* theta, int64_t count) {
+    if (!c) return SP_ERR_ARG;
+    if (!net || !theta || count != net->nparams)
+        return fail(c, SP_ERR_ARG, "sp_lp_get_params: need num_params host values");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemcpyAsync(theta, net->theta.ptr, (size_t)count * sizeof(float),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SP_OK;
+}
+
+int sp_lp_apply(sp_ctx* c, sp_learned* net, int32_t batch, int32_t rows, int32_t cols,
+                const float* u, float* z) {
+    if (!c) return SP_ERR_ARG;
+    if (!net || !u || !z) return fail(c, SP_ERR_ARG, "sp_lp_apply: null argument");
+    if (batch < 1 || rows < 1 || cols < 1 || (double)batch * rows * cols > 1.0e9)
+        return fail(c, SP_ERR_ARG, "sp_lp_apply: bad sizes");
+    if (net->device != c->device) return fail(c, SP_ERR_ARG, "network lives on another GPU");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = lp_enqueue_apply(c, net, batch, rows, cols, u, z, nullptr, nullptr);
+    if (rc) return rc;
+    return check_launch(c);
+}
+
+int sp_lp_loss_grad(sp_ctx* c, sp_learned* net, int32_t rows, int32_t cols, const float* Av,
+                    const float* v, int32_t nprobe, const int32_t* idx, int32_t batch, double* loss,
+                    float* grad) {
+    if (!c) return SP_ERR_ARG;
+    if (!net || !Av || !v || !idx || !loss || !grad)
+        return fail(c, SP_ERR_ARG, "sp_lp_loss_grad: null argument");
+    if (rows < 1 || cols < 1 || nprobe < 1 || batch < 1 || (double)batch * rows * cols > 2.0e8)
+        return fail(c, SP_ERR_ARG, "sp_lp_loss_grad: bad sizes");
+    if (net->device != c->device) return fail(c, SP_ERR_ARG, "network lives on another GPU");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int B = batch, H = rows, W = cols, L = net->layers;
+    const size_t npix = (size_t)B * H * W;
+    int rc = lp_reserve(c, net, npix, true, B, H, W);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    const float* th = dptr<float>(net->theta);
+    float* sps = dptr<float>(net->spsg);
+    float* sg = sps + 16;
+    auto A = [&](int l) { return l == 0 ? dptr<float>(net->a0) : dptr<float>(net->act[l - 1]); };
+    auto Bb = [&](int l) { return dptr<float>(net->act[L + l - 1]); };
+    auto E = [&](int l) { return l == 0 ? dptr<float>(net->e0) : dptr<float>(net->act[2 * L + l - 1]); };
+    float* Z = dptr<float>(net->z);
+    float* part = dptr<float>(net->partial);
+    const int nwb = lp_wgrad_blocks(B, H, W);
+    lp_softplus(st, th + net->doff(), sps, sg);
+    // forward chain a_l = C_l a_{l-1}, b_L = softplus(d) a_L, back chain b_{l-1} = C_l^T b_l
+    lp_gather(st, B, H * W, Av, idx, nprobe, A(0));
+    lp_conv_in(st, B, H, W, A(0), nullptr, B, A(1), th + net->woff(1), nullptr, nullptr);
+    for (int l = 2; l <= L; ++l)
+        lp_conv_mid(st, false, B, H, W, A(l - 1), A(l), th + net->woff(l),
+                    l == L ? sps : nullptr, l == L ? Bb(L) : nullptr, nullptr, nullptr);
+    if (L == 1) lp_scale(st, (long)npix, A(1), sps, Bb(1));
+    for (int l = L; l >= 2; --l)
+        lp_conv_mid(st, true, B, H, W, Bb(l), Bb(l - 1), th + net->woff(l), nullptr, nullptr, nullptr, nullptr);
+    lp_conv_out(st, B, H, W, Bb(1), Z, th + net->woff(1), nullptr, nullptr);
+    // loss and e_0 = d loss / dz
+    lp_loss(st, B, H * W, Z, v, idx, nprobe, E(0), dptr<double>(net->lpart));
+    launch_reduce(st, dptr<double>(net->lpart), B, loss);
+    // e_l = C_l e_{l-1}; the back chain contributes wgrad(b_l, e_{l-1}) to W_l
+    lp_conv_in(st, B, H, W, E(0), nullptr, B, E(1), th + net->woff(1), nullptr, nullptr);
+    for (int l = 2; l <= L; ++l)
+        lp_conv_mid(st, false, B, H, W, E(l - 1), E(l), th + net->woff(l), nullptr, nullptr, nullptr, nullptr);
+    for (int l = 1; l <= L; ++l) {
+        const int fi = l == 1 ? 1 : 16;
+        lp_wgrad(st, fi, B, H, W, Bb(l), E(l - 1), part);
+        lp_reduce(st, nwb, 16 * fi * 9, part, false, grad + net->woff(l));
+    }
+    // d: sigmoid(d) * sum e_L a_L; then f_L = softplus(d) e_L (into b_L's buffer)
+    lp_gd(st, (long)npix, E(L), A(L), dptr<double>(net->gdpart), sg, grad + net->doff());
+    lp_scale(st, (long)npix, E(L), sps, Bb(L));
+    // forward chain: wgrad(f_l, a_{l-1}) into W_l, f_{l-1} = C_l^T f_l
+    for (int l = L; l >= 1; --l) {
+        const int fi = l == 1 ? 1 : 16;
+        lp_wgrad(st, fi, B, H, W, Bb(l), A(l - 1), part);
+        lp_reduce(st, nwb, 16 * fi * 9, part, true, grad + net->woff(l));
+        if (l >= 2)
+            lp_conv_mid(st, true, B, H, W, Bb(l), Bb(l - 1), th + net->woff(l), nullptr, nullptr, nullptr, nullptr);
+    }
+    return check_launch(c);
+}
+
+int sp_lp_adam_step(sp_ctx* c, sp_learned* net, const float* grad, double lr, double beta1,
+                    double beta2, double eps, int32_t step) {
+    if (!c) return SP_ERR_ARG;
+    if (!net || !grad || step < 1 || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) ||
+        !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return fail(c, SP_ERR_ARG, "sp_lp_adam_step: bad argument");
+    HIP_TRY(c, hipSetDevice(c->device));
+    lp_adam(c->stream, net->nparams, dptr<float>(net->theta), dptr<float>(net->adam_m),
+            dptr<float>(net->adam_v), grad, lr, beta1, beta2, eps, step);
+    return check_launch(c);
 }
 
 int sp_profile_read(sp_ctx* c, int kind, double* total_ms, int32_t* count) {
@@ -543,7 +783,7 @@ int sp_precond_apply(sp_ctx* c, const sp_geometry* g, const sp_precond* pc, cons
     if ((rc = check_precond(c, pc))) return rc;
     if ((rc = ensure_partials(c))) return rc;
     int np = 0;
-    if ((rc = enqueue_precond(c, pc, gin, z, nullptr, nullptr, np))) return rc;
+    if ((rc = enqueue_precond(c, pc, gin, z, nullptr, nullptr, np, false))) return rc;
     return check_launch(c);
 }
 
@@ -676,6 +916,8 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     s.max_iter = sp->max_iter;
     s.replay = replay ? 1 : 0;
     s.first = 1;
+    s.gate_learned = pc->kind == SP_PRECOND_LEARNED ? 1 : 0;
+    s.gate_ramp = 0;
     if ((rc = upload_scalars(c))) return rc;
 
     hipStream_t st = c->stream;
@@ -711,7 +953,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
     launch_backproject(st, G, ang, rp, gv, nullptr, nullptr, halt);
     int nzh = 0;
-    if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh))) return rc;
+    if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
     launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
     launch_update_p(st, n, z, p, gv, sc, pgp, halt);
     launch_prep(st, G, p, xp, xTp, halt);
@@ -744,7 +986,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         launch_scalar(st, OP_F, sc, tr, pf, nf, nullptr, 0);                      // f(x_{k+1/2})
         backproject(gv, nullptr, nullptr);                                        // g = R^T r
         int nz = 0;
-        int r2 = enqueue_precond(c, pc, gv, z, h, pzh, nz);                        // z = M g
+        int r2 = enqueue_precond(c, pc, gv, z, h, pzh, nz, true);                    // z = M g
         if (r2) return r2;
         launch_scalar(st, OP_BETA, sc, tr, pzh, nz, nullptr, 0);                  // beta
         launch_update_p(st, n, z, p, gv, sc, pgp, halt);                          // p = -z + beta p
@@ -834,6 +1076,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         if (trace->trials && K > 0) std::copy(htr, htr + (size_t)done * K, trace->trials);
         trace->f0 = out.f0;
         trace->alpha0 = out.alpha0;
+        trace->fallbacks = out.fallbacks > 0 ? 1 : 0;
     }
     if (out.halt == SP_ERR_NONFINITE) return fail(c, SP_ERR_NONFINITE, "non-finite value in a CG scalar");
     return status;

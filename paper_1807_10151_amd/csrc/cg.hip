@@ -157,6 +157,13 @@ __global__ __launch_bounds__(256) void k_scalar(int op, Scalars* __restrict__ sc
     case OP_SNORM:
         if (rec && tr.s_norm) tr.s_norm[it] = sqrt(A);
         break;
+    case OP_LCHECK:
+        if (sc->gate_learned && !(A > 0.0 && finite(A))) {
+            sc->gate_learned = 0;
+            sc->gate_ramp = 1;
+            sc->fallbacks += 1;
+        }
+        break;
     default:
         break;
     }

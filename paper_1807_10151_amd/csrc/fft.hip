@@ -82,9 +82,10 @@ __device__ void fft_dif(double2* buf, int P, int logP, int ncol, const double2* 
     }
 }
 
-__global__ __launch_bounds__(256) void k_rows_fwd(FFTPlan F, const float* __restrict__ g,
+__global__ __launch_bounds__(256) void k_rows_fwd(FFTPlan F, const float* __restrict__ g, const int* __restrict__ run,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
+    if (run && !*run) return;
     extern __shared__ double2 buf[];
     const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
     for (int nidx = threadIdx.x; nidx < F.P; nidx += blockDim.x) {
@@ -112,9 +113,10 @@ __device__ __forceinline__ double window_h(double w, double mu, double rho) {
     return (w + mu) * (rho + (1.0 - rho) * cos(w));
 }
 
-__global__ __launch_bounds__(256) void k_cols(FFTPlan F, double mu, double rho,
+__global__ __launch_bounds__(256) void k_cols(FFTPlan F, double mu, double rho, const int* __restrict__ run,
                                               const int* __restrict__ halt) {
     if (halt && *halt) return;
+    if (run && !*run) return;
     extern __shared__ double2 buf[];
     const int u0 = blockIdx.x * F.CB;
     const int total = F.CB * F.P;
@@ -144,11 +146,12 @@ __global__ __launch_bounds__(256) void k_cols(FFTPlan F, double mu, double rho,
     }
 }
 
-__global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__ z,
+__global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__ z, const int* __restrict__ run,
                                                   const float* __restrict__ dotv,
                                                   double* __restrict__ partials,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
+    if (run && !*run) return;
     extern __shared__ double2 buf[];
     double* red = reinterpret_cast<double*>(buf);   // reused after the transform is read
     const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
@@ -193,13 +196,13 @@ __global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__
 int precond_dot_blocks(const FFTPlan& F) { return (F.rows + 1) / 2; }
 
 void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, const float* g,
-                    float* z, const float* dotv, double* partials, const int* halt) {
+                    float* z, const float* dotv, double* partials, const int* halt, const int* run) {
     const int nrow = (F.rows + 1) / 2;
     const size_t row_lds = (size_t)F.P * sizeof(double2);
-    hipLaunchKernelGGL(k_rows_fwd, dim3(nrow), dim3(256), row_lds, st, F, g, halt);
+    hipLaunchKernelGGL(k_rows_fwd, dim3(nrow), dim3(256), row_lds, st, F, g, run, halt);
     const int ncb = (F.SP + F.CB - 1) / F.CB;
-    hipLaunchKernelGGL(k_cols, dim3(ncb), dim3(256), (size_t)F.CB * row_lds, st, F, mu, rho, halt);
-    hipLaunchKernelGGL(k_rows_inv, dim3(nrow), dim3(256), row_lds, st, F, z, dotv, partials, halt);
+    hipLaunchKernelGGL(k_cols, dim3(ncb), dim3(256), (size_t)F.CB * row_lds, st, F, mu, rho, run, halt);
+    hipLaunchKernelGGL(k_rows_inv, dim3(nrow), dim3(256), row_lds, st, F, z, run, dotv, partials, halt);
 }
 
 }  // namespace sp

@@ -1,0 +1,401 @@
+// Learned SPD preconditioner M = C^T diag(softplus(d)) C (used in Algorithm 2,
+// step 2, in place of the Fourier preconditioner of Section 3.2).
+//
+// C is a stack of L linear 3x3 cross-correlations without bias with zero
+// "same" padding: 1 -> 16 channels, then 16 -> 16.  C^T applies, in reverse
+// layer order, each layer's adjoint: the correlation with the spatially
+// flipped kernel and swapped channel roles.  d has one entry per channel.
+//
+// Layout: activations are channels-last float32 [B][H][W][16]; images are
+// [B][H][W].  Parameters theta (float32) = W_1 [16][1][3][3], W_2..W_L
+// [16][16][3][3], d [16]; tap t = 3 ky + kx reads the input at offset
+// (ky - 1, kx - 1).
+//
+// The 16 -> 16 layers run as implicit GEMM on MFMA: a wave computes 16
+// consecutive pixels of one image row for all 16 output channels with
+// v_mfma_f32_16x16x4f32 (A = 16 pixels x 4 input channels of one tap,
+// B = 4 input channels x 16 output channels), 9 taps x 4 channel groups =
+// 36 MFMAs per tile; the weights stay in registers.  The 1 <-> 16 layers, the
+// weight gradients, the loss and Adam are plain VALU kernels.
+#include "sp_internal.h"
+#include "sp_reduce.h"
+
+namespace sp {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int LF = 16;   // channels
+
+__device__ __forceinline__ bool in_img(int h, int w, int H, int W) {
+    return h >= 0 && h < H && w >= 0 && w < W;
+}
+
+// ---- 16 -> 16 correlation on MFMA --------------------------------------------
+// out[b,h,w,j] = sum_{t, ci} in[b, h+dy_t, w+dx_t, ci] * K[j][ci][t], with
+// K = W (TRANS = false) or K[j][ci][t] = W[ci][j][8 - t] (TRANS: the adjoint).
+// If scale != nullptr, out2 = scale[j] * out as well.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
+                                                     const float* __restrict__ in,
+                                                     float* __restrict__ out,
+                                                     const float* __restrict__ Wl,
+                                                     const float* __restrict__ scale,
+                                                     float* __restrict__ out2,
+                                                     const int* __restrict__ halt,
+                                                     const int* __restrict__ run) {
+    if (halt && *halt) return;
+    if (run && !*run) return;
+    const int lane = threadIdx.x & 63;
+    const int wtiles = (W + 15) >> 4;
+    const long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= (long)B * H * wtiles) return;       // whole wave; no barriers below
+    const int wt = (int)(tile % wtiles);
+    const long bh = tile / wtiles;
+    const int h = (int)(bh % H);
+    const int b = (int)(bh / H);
+    const int w0 = wt * 16;
+    const int i = lane & 15;     // A row (pixel) / B column (out channel)
+    const int kq = lane >> 4;    // A column / B row within a group of 4 input channels
+    float wr[36];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+#pragma unroll
+        for (int cg = 0; cg < 4; ++cg) {
+            const int ci = 4 * cg + kq;
+            wr[t * 4 + cg] = TRANS ? Wl[(ci * LF + i) * 9 + (8 - t)] : Wl[(i * LF + ci) * 9 + t];
+        }
+    }
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int hh = h + t / 3 - 1;
+        const int ww = w0 + i + t % 3 - 1;
+        const bool ok = in_img(hh, ww, H, W);
+        const float* p = in + (((size_t)b * H + (ok ? hh : 0)) * W + (ok ? ww : 0)) * LF + kq;
+#pragma unroll
+        for (int cg = 0; cg < 4; ++cg) {
+            const float a = ok ? p[4 * cg] : 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wr[t * 4 + cg], acc, 0, 0, 0);
+        }
+    }
+    // lane holds D[4*(lane>>4) + r][lane & 15]: pixel w0 + 4*kq + r, channel i
+    const float sc = scale ? scale[i] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int px = w0 + 4 * kq + r;
+        if (px < W) {
+            const size_t o = (((size_t)b * H + h) * W + px) * LF + i;
+            if (out) out[o] = acc[r];
+            if (out2) out2[o] = acc[r] * sc;
+        }
+    }
+}
+
+// ---- 1 -> 16 (first layer) and its adjoint 16 -> 1 ------------------------------
+// out[b,h,w,co] = sum_t W1[co][t] * in[src(b), h+dy, w+dx]; src(b) = idx[b] if idx.
+__global__ __launch_bounds__(256) void k_lp_conv_in(int B, int H, int W, const float* __restrict__ in,
+                                                    const int32_t* __restrict__ idx, int nsrc,
+                                                    float* __restrict__ out,
+                                                    const float* __restrict__ W1,
+                                                    const int* __restrict__ halt,
+                                                    const int* __restrict__ run) {
+    if (halt && *halt) return;
+    if (run && !*run) return;
+    __shared__ float w[LF * 9];
+    for (int q = threadIdx.x; q < LF * 9; q += 256) w[q] = W1[q];
+    __syncthreads();
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (long)B * H * W) return;
+    const int x = (int)(p % W);
+    const long bh = p / W;
+    const int y = (int)(bh % H);
+    const int b = (int)(bh / H);
+    const int src = idx ? min(max(idx[b], 0), nsrc - 1) : b;
+    float v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        v[t] = in_img(yy, xx, H, W) ? in[((size_t)src * H + yy) * W + xx] : 0.0f;
+    }
+    float* o = out + (size_t)p * LF;
+#pragma unroll
+    for (int co = 0; co < LF; ++co) {
+        float s = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) s = fmaf(w[co * 9 + t], v[t], s);
+        o[co] = s;
+    }
+}
+
+// out[b,h,w] = sum_co sum_t W1[co][t] * in[b, h-dy, w-dx, co]   (adjoint of k_lp_conv_in)
+__global__ __launch_bounds__(256) void k_lp_conv_out(int B, int H, int W, const float* __restrict__ in,
+                                                     float* __restrict__ out,
+                                                     const float* __restrict__ W1,
+                                                     const int* __restrict__ halt,
+                                                     const int* __restrict__ run) {
+    if (halt && *halt) return;
+    if (run && !*run) return;
+    __shared__ float w[LF * 9];
+    for (int q = threadIdx.x; q < LF * 9; q += 256) w[q] = W1[q];
+    __syncthreads();
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (long)B * H * W) return;
+    const int x = (int)(p % W);
+    const long bh = p / W;
+    const int y = (int)(bh % H);
+    const int b = (int)(bh / H);
+    float s = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
+        if (!in_img(yy, xx, H, W)) continue;
+        const float4* q = reinterpret_cast<const float4*>(in + (((size_t)b * H + yy) * W + xx) * LF);
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+            const float4 u = q[c4];
+            s = fmaf(w[(4 * c4 + 0) * 9 + t], u.x, s);
+            s = fmaf(w[(4 * c4 + 1) * 9 + t], u.y, s);
+            s = fmaf(w[(4 * c4 + 2) * 9 + t], u.z, s);
+            s = fmaf(w[(4 * c4 + 3) * 9 + t], u.w, s);
+        }
+    }
+    out[p] = s;
+}
+
+// out = scale[c] * in, channels-last
+__global__ __launch_bounds__(256) void k_lp_scale(long n16, const float* __restrict__ in,
+                                                  const float* __restrict__ scale,
+                                                  float* __restrict__ out) {
+    const long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q < n16) out[q] = in[q] * scale[q & (LF - 1)];
+}
+
+// softplus(d) and sigmoid(d) into sc[0..15], sg[0..15]
+__global__ void k_lp_softplus(const float* __restrict__ d, float* __restrict__ sp_out,
+                              float* __restrict__ sg_out) {
+    const int c = threadIdx.x;
+    if (c < LF) {
+        const double x = d[c];
+        sp_out[c] = (float)(x > 20.0 ? x : log1p(exp(x)));
+        if (sg_out) sg_out[c] = (float)(1.0 / (1.0 + exp(-x)));
+    }
+}
+
+// ---- loss ---------------------------------------------------------------------
+// One workgroup per sample b: nv = ||v||^2, lb = ||z - v||^2 / nv,
+// e0 = (2 / B) (z - v) / nv; loss partial lb / B.
+__global__ __launch_bounds__(256) void k_lp_loss(int B, int HW, const float* __restrict__ z,
+                                                 const float* __restrict__ v,
+                                                 const int32_t* __restrict__ idx, int nsrc,
+                                                 float* __restrict__ e0,
+                                                 double* __restrict__ lpart) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const float* vb = v + (size_t)(idx ? min(max(idx[b], 0), nsrc - 1) : b) * HW;
+    const float* zb = z + (size_t)b * HW;
+    double nv = 0.0;
+    for (int q = threadIdx.x; q < HW; q += 256) nv += (double)vb[q] * (double)vb[q];
+    nv = block_sum(nv, red);
+    const double sc = nv > 0.0 ? 2.0 / ((double)B * nv) : 0.0;
+    double r2 = 0.0;
+    for (int q = threadIdx.x; q < HW; q += 256) {
+        const double r = (double)zb[q] - (double)vb[q];
+        r2 += r * r;
+        e0[(size_t)b * HW + q] = (float)(sc * r);
+    }
+    r2 = block_sum(r2, red);
+    if (threadIdx.x == 0) lpart[b] = nv > 0.0 ? r2 / nv / (double)B : 0.0;
+}
+
+// ---- weight gradient ----------------------------------------------------------
+// partial[blk][o][i][t] = sum over the block's pixels p of G[p][o] * X[p + t][i]
+// (X zero outside the image).  G: [B][H][W][16]; X: [B][H][W][FI] with FI in
+// {1, 16}.  A block covers a 16 x 16 pixel tile of one image, staged in LDS.
+template <int FI>
+__global__ __launch_bounds__(256) void k_lp_wgrad(int B, int H, int W, const float* __restrict__ G,
+                                                  const float* __restrict__ X,
+                                                  float* __restrict__ partial) {
+    __shared__ float gs[256 * LF];
+    __shared__ float xs[18 * 18 * FI];
+    const int tx = (W + 15) / 16, ty = (H + 15) / 16;
+    const int blk = blockIdx.x;
+    const int b = blk / (tx * ty);
+    const int rem = blk - b * tx * ty;
+    const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
+    for (int q = threadIdx.x; q < 256 * LF; q += 256) {
+        const int p = q / LF, c = q - p * LF;
+        const int yy = y0 + p / 16, xx = x0 + p % 16;
+        gs[q] = in_img(yy, xx, H, W) ? G[(((size_t)b * H + yy) * W + xx) * LF + c] : 0.0f;
+    }
+    for (int q = threadIdx.x; q < 18 * 18 * FI; q += 256) {
+        const int p = q / FI, c = q - p * FI;
+        const int yy = y0 - 1 + p / 18, xx = x0 - 1 + p % 18;
+        xs[q] = in_img(yy, xx, H, W) ? X[(((size_t)b * H + yy) * W + xx) * FI + c] : 0.0f;
+    }
+    __syncthreads();
+    const int nout = LF * FI * 9;
+    float* dst = partial + (size_t)blk * nout;
+    if (FI == LF) {
+        const int o = threadIdx.x / LF, i = threadIdx.x % LF;
+        float acc[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+        for (int p = 0; p < 256; ++p) {
+            const float gv = gs[p * LF + o];
+            const int py = p / 16, px = p % 16;
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                acc[t] = fmaf(gv, xs[((py + t / 3) * 18 + px + t % 3) * FI + i], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) dst[(o * FI + i) * 9 + t] = acc[t];
+    } else {
+        if (threadIdx.x < nout) {
+            const int o = threadIdx.x / 9, t = threadIdx.x % 9;
+            float acc = 0.0f;
+            for (int p = 0; p < 256; ++p) {
+                const int py = p / 16, px = p % 16;
+                acc = fmaf(gs[p * LF + o], xs[((py + t / 3) * 18 + px + t % 3) * FI], acc);
+            }
+            dst[threadIdx.x] = acc;
+        }
+    }
+}
+
+// out[q] (+)= sum over blocks of pa[blk][q]; float64 sums in a fixed order.
+__global__ __launch_bounds__(256) void k_lp_reduce(int nblk, int nout, const float* __restrict__ pa,
+                                                   int accumulate, float* __restrict__ out) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= nout) return;
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += (double)pa[(size_t)k * nout + q];
+    out[q] = (float)(accumulate ? (double)out[q] + s : s);
+}
+
+// gd partials: part[blk][c] = sum over the block's pixels of E[p][c] * A[p][c]
+__global__ __launch_bounds__(256) void k_lp_gd_part(long npix, const float* __restrict__ E,
+                                                    const float* __restrict__ A,
+                                                    double* __restrict__ part) {
+    __shared__ double red[256];
+    const int c = threadIdx.x & (LF - 1);
+    const int lane_pix = threadIdx.x >> 4;   // 16 pixels per pass
+    double s = 0.0;
+    for (long p = (long)blockIdx.x * 16 + lane_pix; p < npix; p += (long)gridDim.x * 16)
+        s += (double)E[p * LF + c] * (double)A[p * LF + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < LF) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += red[k * LF + threadIdx.x];
+        part[(size_t)blockIdx.x * LF + threadIdx.x] = t;
+    }
+}
+
+__global__ void k_lp_gd_final(int nblk, const double* __restrict__ part, const float* __restrict__ sg,
+                              float* __restrict__ gd) {
+    const int c = threadIdx.x;
+    if (c < LF) {
+        double t = 0.0;
+        for (int k = 0; k < nblk; ++k) t += part[(size_t)k * LF + c];
+        gd[c] = (float)(t * (double)sg[c]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lp_adam(int n, float* __restrict__ theta,
+                                                 float* __restrict__ m, float* __restrict__ v,
+                                                 const float* __restrict__ g, double lr, double b1,
+                                                 double b2, double eps, double c1, double c2) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const double gq = g[q];
+    const double mq = b1 * (double)m[q] + (1.0 - b1) * gq;
+    const double vq = b2 * (double)v[q] + (1.0 - b2) * gq * gq;
+    m[q] = (float)mq;
+    v[q] = (float)vq;
+    theta[q] = (float)((double)theta[q] - lr * (mq / c1) / (sqrt(vq / c2) + eps));
+}
+
+// ---- launchers ------------------------------------------------------------------
+static inline unsigned nblk(long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
+                 const float* Wl, const float* scale, float* out2, const int* halt, const int* run) {
+    const long tiles = (long)B * H * ((W + 15) / 16);
+    const unsigned g = nblk(tiles, 4);
+    if (trans)
+        hipLaunchKernelGGL(k_lp_conv_mid<true>, dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
+    else
+        hipLaunchKernelGGL(k_lp_conv_mid<false>, dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
+}
+
+void lp_conv_in(hipStream_t st, int B, int H, int W, const float* in, const int32_t* idx, int nsrc,
+                float* out, const float* W1, const int* halt, const int* run) {
+    hipLaunchKernelGGL(k_lp_conv_in, dim3(nblk((long)B * H * W, 256)), dim3(256), 0, st, B, H, W, in,
+                       idx, nsrc, out, W1, halt, run);
+}
+
+__global__ __launch_bounds__(256) void k_lp_gather(int B, int HW, const float* __restrict__ src,
+                                                   const int32_t* __restrict__ idx, int nsrc,
+                                                   float* __restrict__ dst) {
+    const long q = (long)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (long)B * HW) return;
+    const int b = (int)(q / HW);
+    const int s = min(max(idx[b], 0), nsrc - 1);
+    dst[q] = src[(size_t)s * HW + (q - (long)b * HW)];
+}
+
+void lp_gather(hipStream_t st, int B, int HW, const float* src, const int32_t* idx, int nsrc, float* dst) {
+    hipLaunchKernelGGL(k_lp_gather, dim3(nblk((long)B * HW, 256)), dim3(256), 0, st, B, HW, src, idx,
+                       nsrc, dst);
+}
+
+void lp_conv_out(hipStream_t st, int B, int H, int W, const float* in, float* out, const float* W1,
+                 const int* halt, const int* run) {
+    hipLaunchKernelGGL(k_lp_conv_out, dim3(nblk((long)B * H * W, 256)), dim3(256), 0, st, B, H, W,
+                       in, out, W1, halt, run);
+}
+
+void lp_scale(hipStream_t st, long npix, const float* in, const float* scale, float* out) {
+    hipLaunchKernelGGL(k_lp_scale, dim3(nblk(npix * LF, 256)), dim3(256), 0, st, npix * LF, in, scale, out);
+}
+
+void lp_softplus(hipStream_t st, const float* d, float* sp_out, float* sg_out) {
+    hipLaunchKernelGGL(k_lp_softplus, dim3(1), dim3(64), 0, st, d, sp_out, sg_out);
+}
+
+void lp_loss(hipStream_t st, int B, int HW, const float* z, const float* v, const int32_t* idx,
+             int nsrc, float* e0, double* lpart) {
+    hipLaunchKernelGGL(k_lp_loss, dim3(B), dim3(256), 0, st, B, HW, z, v, idx, nsrc, e0, lpart);
+}
+
+int lp_wgrad_blocks(int B, int H, int W) { return B * ((W + 15) / 16) * ((H + 15) / 16); }
+
+void lp_wgrad(hipStream_t st, int fi, int B, int H, int W, const float* G, const float* X, float* partial) {
+    const unsigned g = (unsigned)lp_wgrad_blocks(B, H, W);
+    if (fi == LF)
+        hipLaunchKernelGGL(k_lp_wgrad<LF>, dim3(g), dim3(256), 0, st, B, H, W, G, X, partial);
+    else
+        hipLaunchKernelGGL(k_lp_wgrad<1>, dim3(g), dim3(256), 0, st, B, H, W, G, X, partial);
+}
+
+void lp_reduce(hipStream_t st, int nb, int nout, const float* pa, bool accumulate, float* out) {
+    hipLaunchKernelGGL(k_lp_reduce, dim3(nblk(nout, 256)), dim3(256), 0, st, nb, nout, pa,
+                       accumulate ? 1 : 0, out);
+}
+
+int lp_gd_blocks() { return 512; }
+
+void lp_gd(hipStream_t st, long npix, const float* E, const float* A, double* part, const float* sg,
+           float* gd) {
+    hipLaunchKernelGGL(k_lp_gd_part, dim3(lp_gd_blocks()), dim3(256), 0, st, npix, E, A, part);
+    hipLaunchKernelGGL(k_lp_gd_final, dim3(1), dim3(64), 0, st, lp_gd_blocks(), part, sg, gd);
+}
+
+void lp_adam(hipStream_t st, int n, float* theta, float* m, float* v, const float* g, double lr,
+             double b1, double b2, double eps, int step) {
+    const double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
+    hipLaunchKernelGGL(k_lp_adam, dim3(nblk(n, 256)), dim3(256), 0, st, n, theta, m, v, g, lr, b1, b2,
+                       eps, c1, c2);
+}
+
+}  // namespace sp

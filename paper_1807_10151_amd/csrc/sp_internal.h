@@ -75,6 +75,9 @@ struct Scalars {
     int32_t max_iter;
     int32_t replay;   // 1: accept after replay[iter*K+inner] trials
     int32_t first;    // 1 while computing the initial direction (beta = 0)
+    int32_t gate_learned;   // 1: the learned preconditioner runs
+    int32_t gate_ramp;      // 1: the Fourier preconditioner runs (fallback)
+    int32_t fallbacks;      // loop bodies in which the learned M was rejected
     int32_t pad_;
 };
 
@@ -125,7 +128,8 @@ struct FFTPlan {
     const double2* tw;    // [P/2] twiddles exp(-2 pi i k / P)
 };
 void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, const float* g,
-                    float* z, const float* dotv, double* partials, const int* halt);
+                    float* z, const float* dotv, double* partials, const int* halt,
+                    const int* run = nullptr);
 int precond_dot_blocks(const FFTPlan& F);
 
 // tv.hip
@@ -154,6 +158,27 @@ void launch_update_x(hipStream_t st, int n, const float* xh, const float* p, flo
 void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int* halt);
 void launch_reduce(hipStream_t st, const double* partials, int np, double* out);
 
+// learned.hip (learned preconditioner C^T diag(softplus(d)) C)
+void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
+                 const float* Wl, const float* scale, float* out2, const int* halt, const int* run);
+void lp_conv_in(hipStream_t st, int B, int H, int W, const float* in, const int32_t* idx, int nsrc,
+                float* out, const float* W1, const int* halt, const int* run);
+void lp_conv_out(hipStream_t st, int B, int H, int W, const float* in, float* out, const float* W1,
+                 const int* halt, const int* run);
+void lp_gather(hipStream_t st, int B, int HW, const float* src, const int32_t* idx, int nsrc, float* dst);
+void lp_scale(hipStream_t st, long npix, const float* in, const float* scale, float* out);
+void lp_softplus(hipStream_t st, const float* d, float* sp_out, float* sg_out);
+void lp_loss(hipStream_t st, int B, int HW, const float* z, const float* v, const int32_t* idx,
+             int nsrc, float* e0, double* lpart);
+int lp_wgrad_blocks(int B, int H, int W);
+void lp_wgrad(hipStream_t st, int fi, int B, int H, int W, const float* G, const float* X, float* partial);
+void lp_reduce(hipStream_t st, int nb, int nout, const float* pa, bool accumulate, float* out);
+int lp_gd_blocks();
+void lp_gd(hipStream_t st, long npix, const float* E, const float* A, double* part, const float* sg,
+           float* gd);
+void lp_adam(hipStream_t st, int n, float* theta, float* m, float* v, const float* g, double lr,
+             double b1, double b2, double eps, int step);
+
 enum ScalarOp : int {
     OP_F = 0,        // f = sum(pa); trace / non-finite check
     OP_F0 = 1,       // f(x_0) at initialisation
@@ -161,6 +186,7 @@ enum ScalarOp : int {
     OP_ALPHA = 3,    // pth = sum(pa); alpha = -sum(pb) / pth; k++, iter++; eps test
     OP_ALPHA0 = 4,   // same for the initial step (k = 1)
     OP_SNORM = 5,    // ||s_k|| into the trace
+    OP_LCHECK = 6,   // learned M accepted iff g^T z = sum(pa) > 0 and finite; else fall back
 };
 void launch_scalar(hipStream_t st, int op, Scalars* sc, TraceDev tr, const double* pa, int na,
                    const double* pb, int nb);
