@@ -129,6 +129,12 @@ typedef struct {
     double alpha0;  /* out: alpha of the initial step (Alg. 3, step 6) */
     int32_t fallbacks; /* out: 1 if a learned preconditioner was replaced by the
                           Fourier one during the run, else 0 */
+    /* DEVICE float32 [g_snap_count][rows][cols] or NULL: row k-1 receives
+     * g_{k+1/2} = R^T (R x_{k+1/2} - b), the gradient that loop body k hands to
+     * the preconditioner (Algorithm 2, step 1), for k = 1 .. g_snap_count.
+     * Rows of bodies that did not run are left untouched. */
+    float* g_snap;
+    int32_t g_snap_count;
 } sp_trace;
 
 /* ---- context ------------------------------------------------------------ */

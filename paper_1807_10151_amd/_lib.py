@@ -70,7 +70,8 @@ class sp_trace(ctypes.Structure):
                 ("alpha", POINTER(c_double)), ("beta", POINTER(c_double)),
                 ("s_norm", POINTER(c_double)), ("ell", POINTER(c_int32)),
                 ("trials", POINTER(c_int32)), ("cap", c_int32),
-                ("f0", c_double), ("alpha0", c_double), ("fallbacks", c_int32)]
+                ("f0", c_double), ("alpha0", c_double), ("fallbacks", c_int32),
+                ("g_snap", c_void_p), ("g_snap_count", c_int32)]
 
 
 _SIGS = {

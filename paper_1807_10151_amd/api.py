@@ -313,11 +313,20 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
                     precond="ramp", mu: float = 1e-5, rho: float = 0.8, max_iter: int = 20,
                     eps: float = 0.0, graph: bool = False, replay=None, trace: bool = True,
                     x_half: torch.Tensor | None = None, x_last: torch.Tensor | None = None,
-                    net: "LearnedPrecond | None" = None,
+                    net: "LearnedPrecond | None" = None, g_snap: torch.Tensor | None = None,
                     ctx: Context | None = None) -> SolveResult:
-    """Algorithm 3 (SupPCG); K = 0 gives plain PCG, precond="none" gives CG."""
+    """Algorithm 3 (SupPCG); K = 0 gives plain PCG, precond="none" gives CG.
+
+    g_snap (optional, float32 device tensor [count, rows, cols]): receives the
+    gradient g_{k+1/2} that loop body k hands to the preconditioner."""
     ctx = ctx or context(b.device.index or 0)
     dev = ctx.device
+    snap_count = 0
+    if g_snap is not None:
+        if g_snap.dim() != 3 or tuple(g_snap.shape[1:]) != (g.rows, g.cols):
+            raise ValueError("g_snap must have shape [count, rows, cols]")
+        snap_count = int(g_snap.shape[0])
+        _dev(g_snap, snap_count * g.n, "g_snap", dev)
     x_half = _out(x_half, (g.rows, g.cols), dev)
     x_last = _out(x_last, (g.rows, g.cols), dev)
     gc = g.c()
@@ -336,14 +345,16 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
     cap = max(max_iter, 1)
     tr = None
     arrs = {}
-    if trace:
+    if trace or g_snap is not None:
         arrs = {"f_half": np.zeros(cap), "tv_half": np.zeros(cap), "alpha": np.zeros(cap),
                 "beta": np.zeros(cap), "s_norm": np.zeros(cap),
                 "ell": np.zeros(cap, dtype=np.int32), "trials": np.zeros(cap * max(K, 1), dtype=np.int32)}
         dp = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         ip = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         tr = L.sp_trace(dp(arrs["f_half"]), dp(arrs["tv_half"]), dp(arrs["alpha"]), dp(arrs["beta"]),
-                        dp(arrs["s_norm"]), ip(arrs["ell"]), ip(arrs["trials"]), cap, 0.0, 0.0)
+                        dp(arrs["s_norm"]), ip(arrs["ell"]), ip(arrs["trials"]), cap, 0.0, 0.0, 0,
+                        ctypes.c_void_p(g_snap.data_ptr()) if g_snap is not None else None,
+                        snap_count)
     k_out = ctypes.c_int32(0)
     ctx._stream()
     rc = ctx.lib.sp_suppcg_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
@@ -353,7 +364,7 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
                                  ctypes.byref(k_out), ctypes.byref(tr) if tr is not None else None)
     ctx._check(rc, ok=(L.SP_MAXITER, L.SP_CONVERGED, L.SP_BREAKDOWN_CONVERGED, L.SP_TRIALS_EXHAUSTED))
     out = {}
-    if trace:
+    if tr is not None:
         done = min(max(k_out.value - 1, 0), cap)
         out = {key: v[:done] if key != "trials" else v[:done * max(K, 1)].reshape(done, max(K, 1))
                for key, v in arrs.items()}

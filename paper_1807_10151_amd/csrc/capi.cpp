@@ -65,7 +65,7 @@ struct sp_learned {
     DevBuf theta, adam_m, adam_v, spsg;   // spsg: softplus(d) [16], sigmoid(d) [16]
     size_t cap_pix = 0;                   // pixels the activation buffers hold
     std::vector<DevBuf> act;              // training: a_1..a_L, b_1..b_L, e_1..e_L
-    DevBuf a0, z, e0, ping, pong, partial, lpart, gdpart;
+    DevBuf a0, z, e0, ping, pong, partial, rtmp, lpart, gdpart;
     int woff(int l) const { return l == 1 ? 0 : 144 + (l - 2) * 2304; }   // W_l offset
     int doff() const { return 144 + (layers - 1) * 2304; }
 };
@@ -427,6 +427,9 @@ int lp_reserve(sp_ctx* c, sp_learned* net, size_t npix, bool train, int B, int H
     for (DevBuf* b : {&net->a0, &net->z, &net->e0})
         if ((rc = ensure(c, *b, npix * sizeof(float)))) return rc;
     if ((rc = ensure(c, net->partial, (size_t)lp_wgrad_blocks(B, H, W) * 2304 * sizeof(float)))) return rc;
+    if ((rc = ensure(c, net->rtmp,
+                     (size_t)lp_reduce_chunks(lp_wgrad_blocks(B, H, W)) * 2304 * sizeof(double))))
+        return rc;
     if ((rc = ensure(c, net->lpart, (size_t)B * sizeof(double)))) return rc;
     if ((rc = ensure(c, net->gdpart, (size_t)lp_gd_blocks() * 16 * sizeof(double)))) return rc;
     return SP_OK;
@@ -587,7 +590,8 @@ int sp_lp_destroy(sp_learned* net) {
     (void)hipSetDevice(net->device);
     (void)hipDeviceSynchronize();
     for (DevBuf* b : {&net->theta, &net->adam_m, &net->adam_v, &net->spsg, &net->a0, &net->z,
-                      &net->e0, &net->ping, &net->pong, &net->partial, &net->lpart, &net->gdpart})
+                      &net->e0, &net->ping, &net->pong, &net->partial, &net->rtmp, &net->lpart,
+                      &net->gdpart})
         release(*b);
     for (auto& b : net->act) release(b);
     delete net;
@@ -656,6 +660,7 @@ int sp_lp_loss_grad(sp_ctx* c, sp_learned* net, int32_t rows, int32_t cols, cons
     auto E = [&](int l) { return l == 0 ? dptr<float>(net->e0) : dptr<float>(net->act[2 * L + l - 1]); };
     float* Z = dptr<float>(net->z);
     float* part = dptr<float>(net->partial);
+    double* rtmp = dptr<double>(net->rtmp);
     const int nwb = lp_wgrad_blocks(B, H, W);
     lp_softplus(st, th + net->doff(), sps, sg);
     // forward chain a_l = C_l a_{l-1}, b_L = softplus(d) a_L, back chain b_{l-1} = C_l^T b_l
@@ -678,7 +683,7 @@ int sp_lp_loss_grad(sp_ctx* c, sp_learned* net, int32_t rows, int32_t cols, cons
     for (int l = 1; l <= L; ++l) {
         const int fi = l == 1 ? 1 : 16;
         lp_wgrad(st, fi, B, H, W, Bb(l), E(l - 1), part);
-        lp_reduce(st, nwb, 16 * fi * 9, part, false, grad + net->woff(l));
+        lp_reduce(st, nwb, 16 * fi * 9, part, false, grad + net->woff(l), rtmp);
     }
     // d: sigmoid(d) * sum e_L a_L; then f_L = softplus(d) e_L (into b_L's buffer)
     lp_gd(st, (long)npix, E(L), A(L), dptr<double>(net->gdpart), sg, grad + net->doff());
@@ -687,7 +692,7 @@ int sp_lp_loss_grad(sp_ctx* c, sp_learned* net, int32_t rows, int32_t cols, cons
     for (int l = L; l >= 1; --l) {
         const int fi = l == 1 ? 1 : 16;
         lp_wgrad(st, fi, B, H, W, Bb(l), A(l - 1), part);
-        lp_reduce(st, nwb, 16 * fi * 9, part, true, grad + net->woff(l));
+        lp_reduce(st, nwb, 16 * fi * 9, part, true, grad + net->woff(l), rtmp);
         if (l >= 2)
             lp_conv_mid(st, true, B, H, W, Bb(l), Bb(l - 1), th + net->woff(l), nullptr, nullptr, nullptr, nullptr);
     }
@@ -963,6 +968,8 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     launch_update_x(st, n, xh, p, x, sc, halt);
     if ((rc = check_launch(c))) return rc;
 
+    float* snap = (trace && trace->g_snap && trace->g_snap_count > 0) ? trace->g_snap : nullptr;
+    const int snap_count = snap ? trace->g_snap_count : 0;
     // One loop body (steps 11-14); every launch reads device state only, so
     // the body can be replayed from a captured graph.
     auto project = [&](const float* bb, double* parts) {
@@ -985,6 +992,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         project(b, pf);                                                           // r = R x - b
         launch_scalar(st, OP_F, sc, tr, pf, nf, nullptr, 0);                      // f(x_{k+1/2})
         backproject(gv, nullptr, nullptr);                                        // g = R^T r
+        if (snap) launch_snap(st, n, gv, snap, snap_count, sc);
         int nz = 0;
         int r2 = enqueue_precond(c, pc, gv, z, h, pzh, nz, true);                    // z = M g
         if (r2) return r2;

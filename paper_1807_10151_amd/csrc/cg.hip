@@ -87,6 +87,22 @@ void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int*
     hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst, halt);
 }
 
+// dst[iter][:] = src for the loop body index iter held in the scalars, while
+// iter < count.
+__global__ __launch_bounds__(256) void k_snap(int n, const float* __restrict__ src,
+                                              float* __restrict__ dst, int count,
+                                              const Scalars* __restrict__ sc) {
+    if (sc->halt) return;
+    const int it = sc->iter;
+    if (it < 0 || it >= count) return;
+    float* d = dst + (size_t)it * n;
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) d[q] = src[q];
+}
+
+void launch_snap(hipStream_t st, int n, const float* src, float* dst, int count, const Scalars* sc) {
+    hipLaunchKernelGGL(k_snap, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst, count, sc);
+}
+
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int np,
                                                 double* __restrict__ out) {
     __shared__ double red[4];

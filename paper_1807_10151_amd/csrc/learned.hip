@@ -262,13 +262,26 @@ __global__ __launch_bounds__(256) void k_lp_wgrad(int B, int H, int W, const flo
     }
 }
 
-// out[q] (+)= sum over blocks of pa[blk][q]; float64 sums in a fixed order.
-__global__ __launch_bounds__(256) void k_lp_reduce(int nblk, int nout, const float* __restrict__ pa,
-                                                   int accumulate, float* __restrict__ out) {
+// Two-level fixed-order float64 sum over blocks: tmp[chunk][q] sums the
+// partials of 64 consecutive blocks, then out[q] (+)= sum over chunks.
+constexpr int LP_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void k_lp_reduce1(int nblk, int nout, const float* __restrict__ pa,
+                                                    double* __restrict__ tmp) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= nout) return;
+    const int k0 = blockIdx.y * LP_CHUNK, k1 = min(nblk, k0 + LP_CHUNK);
+    double s = 0.0;
+    for (int k = k0; k < k1; ++k) s += (double)pa[(size_t)k * nout + q];
+    tmp[(size_t)blockIdx.y * nout + q] = s;
+}
+
+__global__ __launch_bounds__(256) void k_lp_reduce2(int nchunk, int nout, const double* __restrict__ tmp,
+                                                    int accumulate, float* __restrict__ out) {
     const int q = blockIdx.x * 256 + threadIdx.x;
     if (q >= nout) return;
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += (double)pa[(size_t)k * nout + q];
+    for (int k = 0; k < nchunk; ++k) s += tmp[(size_t)k * nout + q];
     out[q] = (float)(accumulate ? (double)out[q] + s : s);
 }
 
@@ -378,8 +391,13 @@ void lp_wgrad(hipStream_t st, int fi, int B, int H, int W, const float* G, const
         hipLaunchKernelGGL(k_lp_wgrad<1>, dim3(g), dim3(256), 0, st, B, H, W, G, X, partial);
 }
 
-void lp_reduce(hipStream_t st, int nb, int nout, const float* pa, bool accumulate, float* out) {
-    hipLaunchKernelGGL(k_lp_reduce, dim3(nblk(nout, 256)), dim3(256), 0, st, nb, nout, pa,
+int lp_reduce_chunks(int nb) { return (nb + LP_CHUNK - 1) / LP_CHUNK; }
+
+void lp_reduce(hipStream_t st, int nb, int nout, const float* pa, bool accumulate, float* out,
+               double* tmp) {
+    const int nch = lp_reduce_chunks(nb);
+    hipLaunchKernelGGL(k_lp_reduce1, dim3(nblk(nout, 256), nch), dim3(256), 0, st, nb, nout, pa, tmp);
+    hipLaunchKernelGGL(k_lp_reduce2, dim3(nblk(nout, 256)), dim3(256), 0, st, nch, nout, tmp,
                        accumulate ? 1 : 0, out);
 }
 

@@ -156,6 +156,7 @@ void launch_update_p(hipStream_t st, int n, const float* z, float* p, const floa
 void launch_update_x(hipStream_t st, int n, const float* xh, const float* p, float* x,
                      const Scalars* sc, const int* halt);
 void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int* halt);
+void launch_snap(hipStream_t st, int n, const float* src, float* dst, int count, const Scalars* sc);
 void launch_reduce(hipStream_t st, const double* partials, int np, double* out);
 
 // learned.hip (learned preconditioner C^T diag(softplus(d)) C)
@@ -172,7 +173,9 @@ void lp_loss(hipStream_t st, int B, int HW, const float* z, const float* v, cons
              int nsrc, float* e0, double* lpart);
 int lp_wgrad_blocks(int B, int H, int W);
 void lp_wgrad(hipStream_t st, int fi, int B, int H, int W, const float* G, const float* X, float* partial);
-void lp_reduce(hipStream_t st, int nb, int nout, const float* pa, bool accumulate, float* out);
+int lp_reduce_chunks(int nb);
+void lp_reduce(hipStream_t st, int nb, int nout, const float* pa, bool accumulate, float* out,
+               double* tmp);
 int lp_gd_blocks();
 void lp_gd(hipStream_t st, long npix, const float* E, const float* A, double* part, const float* sg,
            float* gd);

@@ -122,3 +122,37 @@ def test_solver_falls_back_to_fourier_preconditioner(sp, small, bad):
     assert res.trace["fallbacks"] == 1
     assert list(res.trace["ell"]) == list(ref.trace["ell"])
     assert rel_l2(res.x_half.cpu().numpy(), ref.x_half.cpu().numpy()) <= 1e-6
+
+
+def test_training_gain(sp):
+    # The recipe's 2000 Adam steps on 2048 Gaussian + 2048 Krylov probes at the
+    # 64x64 / 90-angle geometry.  The trained network must (1) lower the loss
+    # from its scaled start by 2x, and (2) reach the plain run's f(x_{100+1/2})
+    # in at most half the loop bodies that the untrained network and M = I
+    # need.  The paper's Fourier M is printed beside it for the record: this
+    # loss does not beat it here (about 112 against 100 bodies).
+    from paper_1807_10151_amd import learned_train as lt
+    g = sp.Geometry(64, 64, 90, 91)
+    cfg = lt.TrainConfig()
+    res = lt.train(g, cfg, log_every=500)
+    first, last = res.losses[0][1], res.losses[-1][1]
+    print(f"loss {first:.4f} -> {last:.4f}; train {res.seconds:.2f} s", flush=True)
+    assert last <= 0.5 * first
+    net0 = sp.LearnedPrecond(4)
+    th = lt.init_theta(4, 16, cfg.seed)
+    net0.set_params(th)
+    lt.scale_init(net0, th, res.extra["V"], res.extra["AV"], 16)
+    seeds = [100, 101, 102, 103]
+    trained = lt.time_to_target(g, res.net, seeds, cfg, max_iters=400, reps=0)
+    untrained = lt.time_to_target(g, net0, seeds, cfg, max_iters=400, reps=0)
+    kw = dict(K=cfg.K, a=cfg.a, gamma=cfg.gamma, mu=cfg.mu, rho=cfg.rho, graph=True)
+    for r_t, r_u in zip(trained, untrained):
+        _, b = lt.phantom_data(g, r_t["seed"], cfg.n_ellipses, cfg.noise)
+        plain_cg = sp.sp_suppcg_solve(g, b, None, precond="none", max_iter=400, **kw)
+        hit = np.nonzero(plain_cg.trace["f_half"] <= r_t["f_star"])[0]
+        k_cg = int(hit[0]) + 1 if hit.size else 10 ** 6
+        k_u = r_u["k_f"] or 10 ** 6
+        print(f"seed {r_t['seed']}: bodies to f*: trained {r_t['k_f']}, untrained {r_u['k_f']}, "
+              f"M=I {k_cg}, Fourier M 100", flush=True)
+        assert r_t["fallbacks"] == 0
+        assert r_t["k_f"] is not None and 2 * r_t["k_f"] <= min(k_u, k_cg)

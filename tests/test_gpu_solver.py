@@ -130,3 +130,27 @@ def test_nonfinite_data_reported(sp, small):
         sp.sp_suppcg_solve(geom(sp, og), cuda(bad), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
                            max_iter=3)
     assert e.value.code == 3
+
+
+def test_gradient_snapshots(sp, small):
+    # g_snap row k-1 = g_{k+1/2} = R^T (R x_{k+1/2} - b): against the oracle's
+    # x_{k+1/2} run through the oracle's R, and bitwise against the library's
+    # own R^T (R x - b) at the last body; rows past the last body stay untouched
+    og, img, b, R, prob = small
+    n_it = 6
+    ref = osup.suppcg(prob, np.zeros(og.n), osup.TVParams(K, A, GAMMA), n_iter=n_it,
+                      record_vectors=True)
+    g = geom(sp, og)
+    snap = torch.full((n_it + 2, og.rows, og.cols), 7.0, dtype=torch.float32, device="cuda")
+    res = sp.sp_suppcg_solve(g, cuda(b), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO, max_iter=n_it,
+                             g_snap=snap, trace=False)
+    got = snap.cpu().numpy().astype(np.float64)
+    bb = b.astype(np.float64).ravel()
+    for k in range(1, n_it + 1):
+        xk = ref.trace["x_half_v"][k]
+        want = R.T @ (R @ xk - bb)
+        assert rel_l2(got[k - 1].ravel(), want) <= 1e-3, (k, rel_l2(got[k - 1].ravel(), want))
+    assert np.all(got[n_it:] == 7.0)
+    r, _ = sp.sp_residual(g, res.x_half, cuda(b))
+    own = sp.sp_backproject(g, r).cpu().numpy()
+    np.testing.assert_array_equal(got[n_it - 1], own)
