@@ -31,6 +31,11 @@ PEAK_HBM = 8.0e12                # B/s
 # 157.3 TFLOP/s counts an FMA as 2 flops on 2-wide packed lanes.
 PEAK_VALU_OPS = 256 * 64 * 2.4e9
 OPS_PER_NNZ = 4                  # offset fma, weight fma, clamp, accumulate fma
+# Bytes moved between L2 and the memory fabric per launch of the projector
+# kernels at this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE averages scaled
+# by the counts of a 64 MiB device copy (profiles/counters_ct512.md).  They are
+# tied to the kernels as profiled; re-measure after changing them.
+TRAFFIC_BYTES = {"project": 20.53e6, "backproject": 18.73e6}
 
 
 def parse():
@@ -198,7 +203,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom_name,
                      "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_OPS / 1e12, 4),
                      "unit": "Tops/s (VALU lane-ops, 4 per nonzero weight)",
-                     "frac": round(achieved / PEAK_VALU_OPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_VALU_OPS, 4),
+                     "traffic": TRAFFIC_BYTES[dom_name],
                      "kernel_ms": round(dom_ms, 4), "launches": solve_ms[dom_name][1]},
         "in_solve_ms": {k: round(v, 4) for k, v in avg.items()},
         "operators_ms": {"project": round(ms_R, 4), "backproject": round(ms_RT, 4),
