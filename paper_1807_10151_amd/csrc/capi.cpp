@@ -163,11 +163,9 @@ void angle_cos_sin(const sp_geometry& g, int a, double& co, double& si) {
     }
 }
 
-int setup_geometry(sp_ctx* c, const sp_geometry* g) {
-    int rc = validate_geometry(c, g);
-    if (rc) return rc;
-    if (c->have_geom && same_geom(c->geom, *g)) return SP_OK;
-    GeomDev G{};
+// Device geometry and the class-sorted angle table of a validated geometry.
+int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<AngleDev>& tab) {
+    G = GeomDev{};
     G.rows = g->rows;
     G.cols = g->cols;
     G.nA = g->n_angles;
@@ -188,7 +186,7 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     G.pitchXT = g->rows + 2 * PAD;
     G.pitchB = g->n_bins + 2 * PAD;
     const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
-    std::vector<AngleDev> tab(g->n_angles);
+    tab.assign(g->n_angles, AngleDev{});
     for (int a = 0; a < g->n_angles; ++a) {
         double co, si;
         angle_cos_sin(*g, a, co, si);
@@ -231,6 +229,16 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
         G.cls[cls_of(A) + 1] += 1;
     }
     for (int q = 1; q <= 4; ++q) G.cls[q] += G.cls[q - 1];
+    return SP_OK;
+}
+
+int setup_geometry(sp_ctx* c, const sp_geometry* g) {
+    int rc = validate_geometry(c, g);
+    if (rc) return rc;
+    if (c->have_geom && same_geom(c->geom, *g)) return SP_OK;
+    GeomDev G{};
+    std::vector<AngleDev> tab;
+    if ((rc = build_geometry(c, g, G, tab))) return rc;
     const size_t nX = (size_t)g->rows * G.pitchX, nXT = (size_t)g->cols * G.pitchXT;
     const size_t nY = (size_t)g->n_angles * G.pitchB;
     // Padded buffers must have zero pads: re-zero when the layout changes.

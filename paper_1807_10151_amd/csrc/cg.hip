@@ -16,6 +16,11 @@ int vec_blocks(int n) {
     return b < 2048 ? b : 2048;
 }
 
+__device__ __forceinline__ int vec_blocks_dev(int n) {
+    const int b = (n + 255) / 256;
+    return b < 2048 ? b : 2048;
+}
+
 __global__ __launch_bounds__(256) void k_dot(int n, const float* __restrict__ a,
                                              const float* __restrict__ b,
                                              double* __restrict__ partials,
@@ -35,6 +40,23 @@ void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* p
 }
 
 // p <- -z + beta p (beta from the scalars), partials of g^T p (new p).
+// Virtual block bx of a grid of gx blocks (grid-stride over n).
+__device__ __forceinline__ void update_p_body(int n, const float* __restrict__ z,
+                                              float* __restrict__ p, const float* __restrict__ g,
+                                              const Scalars* __restrict__ sc,
+                                              double* __restrict__ partials, int bx, int gx) {
+    __shared__ double red[4];
+    const double beta = sc->beta;
+    double acc = 0.0;
+    for (int q = bx * 256 + threadIdx.x; q < n; q += gx * 256) {
+        const float v = (float)(-(double)z[q] + beta * (double)p[q]);
+        p[q] = v;
+        acc += (double)g[q] * (double)v;
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[bx] = tot;
+}
+
 __global__ __launch_bounds__(256) void k_update_p(int n, const float* __restrict__ z,
                                                   float* __restrict__ p,
                                                   const float* __restrict__ g,
@@ -42,16 +64,7 @@ __global__ __launch_bounds__(256) void k_update_p(int n, const float* __restrict
                                                   double* __restrict__ partials,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
-    __shared__ double red[4];
-    const double beta = sc->beta;
-    double acc = 0.0;
-    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) {
-        const float v = (float)(-(double)z[q] + beta * (double)p[q]);
-        p[q] = v;
-        acc += (double)g[q] * (double)v;
-    }
-    const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    update_p_body(n, z, p, g, sc, partials, blockIdx.x, gridDim.x);
 }
 
 void launch_update_p(hipStream_t st, int n, const float* z, float* p, const float* g,
@@ -61,15 +74,21 @@ void launch_update_p(hipStream_t st, int n, const float* z, float* p, const floa
 }
 
 // x <- xh + alpha p
+__device__ __forceinline__ void update_x_body(int n, const float* __restrict__ xh,
+                                              const float* __restrict__ p, float* __restrict__ x,
+                                              const Scalars* __restrict__ sc, int bx, int gx) {
+    const double alpha = sc->alpha;
+    for (int q = bx * 256 + threadIdx.x; q < n; q += gx * 256)
+        x[q] = (float)((double)xh[q] + alpha * (double)p[q]);
+}
+
 __global__ __launch_bounds__(256) void k_update_x(int n, const float* __restrict__ xh,
                                                   const float* __restrict__ p,
                                                   float* __restrict__ x,
                                                   const Scalars* __restrict__ sc,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
-    const double alpha = sc->alpha;
-    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256)
-        x[q] = (float)((double)xh[q] + alpha * (double)p[q]);
+    update_x_body(n, xh, p, x, sc, blockIdx.x, gridDim.x);
 }
 
 void launch_update_x(hipStream_t st, int n, const float* xh, const float* p, float* x,
@@ -116,10 +135,9 @@ void launch_reduce(hipStream_t st, const double* partials, int np, double* out) 
 
 __device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
 
-__global__ __launch_bounds__(256) void k_scalar(int op, Scalars* __restrict__ sc, TraceDev tr,
-                                                const double* __restrict__ pa, int na,
-                                                const double* __restrict__ pb, int nb) {
-    if (sc->halt) return;
+__device__ __forceinline__ void scalar_body(int op, Scalars* __restrict__ sc, const TraceDev& tr,
+                                            const double* __restrict__ pa, int na,
+                                            const double* __restrict__ pb, int nb) {
     __shared__ double red[4];
     const double A = pa ? reduce_partials(pa, na, red) : 0.0;
     const double B = pb ? reduce_partials(pb, nb, red) : 0.0;
@@ -185,9 +203,111 @@ __global__ __launch_bounds__(256) void k_scalar(int op, Scalars* __restrict__ sc
     }
 }
 
+__global__ __launch_bounds__(256) void k_scalar(int op, Scalars* __restrict__ sc, TraceDev tr,
+                                                const double* __restrict__ pa, int na,
+                                                const double* __restrict__ pb, int nb) {
+    if (sc->halt) return;
+    scalar_body(op, sc, tr, pa, na, pb, nb);
+}
+
 void launch_scalar(hipStream_t st, int op, Scalars* sc, TraceDev tr, const double* pa, int na,
                    const double* pb, int nb) {
     hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, st, op, sc, tr, pa, na, pb, nb);
+}
+
+// ---- batched forms (one item table entry per virtual block of each slice) ----
+__global__ __launch_bounds__(256) void kb_copy(const SliceDev* __restrict__ sl, ItemTable t, int src,
+                                               int dst) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const float* a = batch_vec(S, src);
+        float* d = batch_vec(S, dst);
+        const int gx = vec_blocks_dev(S.n);
+        for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) d[q] = a[q];
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_init(const SliceDev* __restrict__ sl, ItemTable t) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        const int gx = vec_blocks_dev(S.n);
+        for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) {
+            const float v = S.x0 ? S.x0[q] : 0.0f;
+            S.xh[q] = v;
+            S.x[q] = v;
+        }
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_update_p(const SliceDev* __restrict__ sl, ItemTable t) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        update_p_body(S.n, S.z, S.p, S.g, S.sc, S.pgp, lin, vec_blocks_dev(S.n));
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_update_x(const SliceDev* __restrict__ sl, ItemTable t) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        update_x_body(S.n, S.xh, S.p, S.x, S.sc, lin, vec_blocks_dev(S.n));
+    });
+}
+
+// M = I: z = g and the partials of z^T h.
+__global__ __launch_bounds__(256) void kb_dot_zh(const SliceDev* __restrict__ sl, ItemTable t) {
+    __shared__ double red[4];
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const int gx = vec_blocks_dev(S.n);
+        double acc = 0.0;
+        for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) {
+            const float v = S.g[q];
+            S.z[q] = v;
+            acc += (double)v * (double)S.h[q];
+        }
+        const double tot = block_sum(acc, red);
+        if (threadIdx.x == 0) S.pzh[lin] = tot;
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_scalar(const SliceDev* __restrict__ sl, ItemTable t, int op) {
+    for_items(t, [&](int s, int) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const TraceDev tr = S.tr;
+        switch (op) {
+        case OP_F0:
+        case OP_F: scalar_body(op, S.sc, tr, S.pf, S.nf, nullptr, 0); break;
+        case OP_BETA: scalar_body(op, S.sc, tr, S.pzh, S.nzh, nullptr, 0); break;
+        case OP_ALPHA0:
+        case OP_ALPHA: scalar_body(op, S.sc, tr, S.pph, S.nph, S.pgp, S.ngp); break;
+        case OP_SNORM: scalar_body(op, S.sc, tr, S.pts, S.ntv, nullptr, 0); break;
+        default: break;
+        }
+    });
+}
+
+void launch_copy_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, int dst) {
+    hipLaunchKernelGGL(kb_copy, dim3(t.grid), dim3(256), 0, st, sl, t, src, dst);
+}
+void launch_init_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
+    hipLaunchKernelGGL(kb_init, dim3(t.grid), dim3(256), 0, st, sl, t);
+}
+void launch_update_p_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
+    hipLaunchKernelGGL(kb_update_p, dim3(t.grid), dim3(256), 0, st, sl, t);
+}
+void launch_update_x_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
+    hipLaunchKernelGGL(kb_update_x, dim3(t.grid), dim3(256), 0, st, sl, t);
+}
+void launch_dot_zh_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
+    hipLaunchKernelGGL(kb_dot_zh, dim3(t.grid), dim3(256), 0, st, sl, t);
+}
+void launch_scalar_b(hipStream_t st, const SliceDev* sl, ItemTable t, int op) {
+    hipLaunchKernelGGL(kb_scalar, dim3(t.grid), dim3(256), 0, st, sl, t, op);
 }
 
 }  // namespace sp

@@ -82,12 +82,9 @@ __device__ void fft_dif(double2* buf, int P, int logP, int ncol, const double2* 
     }
 }
 
-__global__ __launch_bounds__(256) void k_rows_fwd(FFTPlan F, const float* __restrict__ g, const int* __restrict__ run,
-                                                  const int* __restrict__ halt) {
-    if (halt && *halt) return;
-    if (run && !*run) return;
-    extern __shared__ double2 buf[];
-    const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
+__device__ __forceinline__ void rows_fwd_body(const FFTPlan& F, const float* __restrict__ g,
+                                              double2* buf, int bx) {
+    const int r0 = 2 * bx, r1 = r0 + 1;
     for (int nidx = threadIdx.x; nidx < F.P; nidx += blockDim.x) {
         float re = 0.0f, im = 0.0f;
         if (nidx < F.cols) {
@@ -109,16 +106,21 @@ __global__ __launch_bounds__(256) void k_rows_fwd(FFTPlan F, const float* __rest
     }
 }
 
+__global__ __launch_bounds__(256) void k_rows_fwd(FFTPlan F, const float* __restrict__ g, const int* __restrict__ run,
+                                                  const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    if (run && !*run) return;
+    extern __shared__ double2 buf[];
+    rows_fwd_body(F, g, buf, blockIdx.x);
+}
+
 __device__ __forceinline__ double window_h(double w, double mu, double rho) {
     return (w + mu) * (rho + (1.0 - rho) * cos(w));
 }
 
-__global__ __launch_bounds__(256) void k_cols(FFTPlan F, double mu, double rho, const int* __restrict__ run,
-                                              const int* __restrict__ halt) {
-    if (halt && *halt) return;
-    if (run && !*run) return;
-    extern __shared__ double2 buf[];
-    const int u0 = blockIdx.x * F.CB;
+__device__ __forceinline__ void cols_body(const FFTPlan& F, double mu, double rho, double2* buf,
+                                          int bx) {
+    const int u0 = bx * F.CB;
     const int total = F.CB * F.P;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int r = idx / F.CB, cc = idx - r * F.CB;
@@ -146,15 +148,19 @@ __global__ __launch_bounds__(256) void k_cols(FFTPlan F, double mu, double rho, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__ z, const int* __restrict__ run,
-                                                  const float* __restrict__ dotv,
-                                                  double* __restrict__ partials,
-                                                  const int* __restrict__ halt) {
+__global__ __launch_bounds__(256) void k_cols(FFTPlan F, double mu, double rho, const int* __restrict__ run,
+                                              const int* __restrict__ halt) {
     if (halt && *halt) return;
     if (run && !*run) return;
     extern __shared__ double2 buf[];
+    cols_body(F, mu, rho, buf, blockIdx.x);
+}
+
+__device__ __forceinline__ void rows_inv_body(const FFTPlan& F, float* __restrict__ z,
+                                              const float* __restrict__ dotv,
+                                              double* __restrict__ partials, double2* buf, int bx) {
     double* red = reinterpret_cast<double*>(buf);   // reused after the transform is read
-    const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
+    const int r0 = 2 * bx, r1 = r0 + 1;
     const bool has1 = r1 < F.rows;
     for (int u = threadIdx.x; u < F.P; u += blockDim.x) {
         double2 X0, X1 = make_double2(0.0f, 0.0f);
@@ -189,8 +195,57 @@ __global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__
     }
     if (dotv) {
         const double tot = block_sum(dot, red);
-        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+        if (threadIdx.x == 0) partials[bx] = tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__ z, const int* __restrict__ run,
+                                                  const float* __restrict__ dotv,
+                                                  double* __restrict__ partials,
+                                                  const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    if (run && !*run) return;
+    extern __shared__ double2 buf[];
+    rows_inv_body(F, z, dotv, partials, buf, blockIdx.x);
+}
+
+// Batched: z = M g per slice, partials of z^T h into pzh.
+__global__ __launch_bounds__(256) void kb_rows_fwd(const SliceDev* __restrict__ sl, ItemTable t) {
+    extern __shared__ double2 buf[];
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const FFTPlan F = S.F;
+        rows_fwd_body(F, S.g, buf, lin);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_cols(const SliceDev* __restrict__ sl, ItemTable t, double mu,
+                                               double rho) {
+    extern __shared__ double2 buf[];
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const FFTPlan F = S.F;
+        cols_body(F, mu, rho, buf, lin);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_rows_inv(const SliceDev* __restrict__ sl, ItemTable t) {
+    extern __shared__ double2 buf[];
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const FFTPlan F = S.F;
+        rows_inv_body(F, S.z, S.h, S.pzh, buf, lin);
+    });
+}
+
+void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTable cols,
+                      size_t lds_rows, size_t lds_cols, double mu, double rho) {
+    hipLaunchKernelGGL(kb_rows_fwd, dim3(rows.grid), dim3(256), lds_rows, st, sl, rows);
+    hipLaunchKernelGGL(kb_cols, dim3(cols.grid), dim3(256), lds_cols, st, sl, cols, mu, rho);
+    hipLaunchKernelGGL(kb_rows_inv, dim3(rows.grid), dim3(256), lds_rows, st, sl, rows);
 }
 
 int precond_dot_blocks(const FFTPlan& F) { return (F.rows + 1) / 2; }

@@ -32,16 +32,16 @@
 
 namespace sp {
 
-__global__ __launch_bounds__(256) void k_prep(GeomDev G, const float* __restrict__ x,
-                                              float* __restrict__ xp, float* __restrict__ xTp,
-                                              const int* __restrict__ halt) {
-    if (halt && *halt) return;
+// 32 x 32 tile (bx, by): padded copy and padded transposed copy.
+__device__ __forceinline__ void prep_body(const GeomDev& G, const float* __restrict__ x,
+                                          float* __restrict__ xp, float* __restrict__ xTp, int bx,
+                                          int by) {
     __shared__ float tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int j = blockIdx.x * 32 + tx;
+    const int j = bx * 32 + tx;
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
-        const int i = blockIdx.y * 32 + ty + r;
+        const int i = by * 32 + ty + r;
         float v = 0.0f;
         if (i < G.rows && j < G.cols) {
             v = x[(size_t)i * G.cols + j];
@@ -50,12 +50,33 @@ __global__ __launch_bounds__(256) void k_prep(GeomDev G, const float* __restrict
         tile[ty + r][tx] = v;
     }
     __syncthreads();
-    const int ii = blockIdx.y * 32 + tx;
+    const int ii = by * 32 + tx;
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
-        const int jj = blockIdx.x * 32 + ty + r;
+        const int jj = bx * 32 + ty + r;
         if (ii < G.rows && jj < G.cols) xTp[(size_t)jj * G.pitchXT + PAD + ii] = tile[tx][ty + r];
     }
+}
+
+__global__ __launch_bounds__(256) void k_prep(GeomDev G, const float* __restrict__ x,
+                                              float* __restrict__ xp, float* __restrict__ xTp,
+                                              const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    prep_body(G, x, xp, xTp, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void kb_prep(const SliceDev* __restrict__ sl, ItemTable t, int which) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const GeomDev G = S.G;
+        const int gx = (G.cols + 31) / 32;
+        prep_body(G, batch_vec(S, which), S.xp, S.xTp, lin % gx, lin / gx);
+    });
+}
+
+void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which) {
+    hipLaunchKernelGGL(kb_prep, dim3(t.grid), dim3(256), 0, st, sl, t, which);
 }
 
 void launch_prep(hipStream_t st, const GeomDev& G, const float* x, float* xp, float* xTp,
@@ -177,19 +198,17 @@ __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A
 
 // out[row*out_pitch + out_pad + k] = (R x)_{row,k}, or the residual (R x - b)
 // with its float64 squared norm per workgroup in partials when b != nullptr.
-// blockIdx.x indexes the class-sorted angle table.
-__global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
-                                                 const float* __restrict__ xp,
-                                                 const float* __restrict__ xTp,
-                                                 const float* __restrict__ b,
-                                                 float* __restrict__ out, int out_pitch,
-                                                 int out_pad, double* __restrict__ partials,
-                                                 const int* __restrict__ halt) {
-    if (halt && *halt) return;
+// Block bx indexes the class-sorted angle table, by the 256-bin chunk.
+__device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* __restrict__ ang,
+                                             const float* __restrict__ xp,
+                                             const float* __restrict__ xTp,
+                                             const float* __restrict__ b, float* __restrict__ out,
+                                             int out_pitch, int out_pad,
+                                             double* __restrict__ partials, int bx, int by, int gx) {
     __shared__ double red[4];
-    const AngleDev A = ang[blockIdx.x];
+    const AngleDev A = ang[bx];
     const int a = A.row;
-    const int k = blockIdx.y * 256 + threadIdx.x;
+    const int k = by * 256 + threadIdx.x;
     const bool valid = k < G.nB;
     const double sk = bin_pos((double)k, G);
     const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
@@ -214,8 +233,37 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
     }
     if (b) {
         const double tot = block_sum(r2, red);
-        if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        if (threadIdx.x == 0) partials[by * gx + bx] = tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
+                                                 const float* __restrict__ xp,
+                                                 const float* __restrict__ xTp,
+                                                 const float* __restrict__ b,
+                                                 float* __restrict__ out, int out_pitch,
+                                                 int out_pad, double* __restrict__ partials,
+                                                 const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    project_body(G, ang, xp, xTp, b, out, out_pitch, out_pad, partials, blockIdx.x, blockIdx.y,
+                 gridDim.x);
+}
+
+// residual: rp = R xh - b with f partials; else rp = R p.
+__global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
+                                                  int residual) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const GeomDev G = S.G;
+        const int gx = G.nA;
+        project_body(G, S.ang, S.xp, S.xTp, residual ? S.b : nullptr, S.rp + PAD, G.pitchB, 0,
+                     residual ? S.pf : nullptr, lin % gx, lin / gx, gx);
+    });
+}
+
+void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, bool residual) {
+    hipLaunchKernelGGL(kb_project, dim3(t.grid), dim3(256), 0, st, sl, t, residual ? 1 : 0);
 }
 
 int project_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
@@ -281,19 +329,18 @@ __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int
 // an 8 x 8 pixel tile; its wave w sums the w-th quarter of every angle class,
 // and the four partial sums are added in wave order through LDS.
 template <int NB>
-__global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
-                                                     const float* __restrict__ yp,
-                                                     float* __restrict__ out,
-                                                     const float* __restrict__ dotv,
-                                                     double* __restrict__ partials,
-                                                     const int* __restrict__ halt) {
-    if (halt && *halt) return;
+__device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDev* __restrict__ ang,
+                                                 const float* __restrict__ yp,
+                                                 float* __restrict__ out,
+                                                 const float* __restrict__ dotv,
+                                                 double* __restrict__ partials, int bx, int by,
+                                                 int gx) {
     __shared__ double part[BP_SPLIT][64];
     __shared__ double red[4];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int i = blockIdx.y * BP_TILE + (lane >> 3);
-    const int j = blockIdx.x * BP_TILE + (lane & 7);
+    const int i = by * BP_TILE + (lane >> 3);
+    const int j = bx * BP_TILE + (lane & 7);
     const double xj = (double)j - G.xoff;
     const double yi = G.yoff - (double)i;
     double acc = 0.0;
@@ -320,7 +367,43 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
     }
     if (dotv) {
         const double tot = block_sum(v, red);
-        if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        if (threadIdx.x == 0) partials[by * gx + bx] = tot;
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
+                                                     const float* __restrict__ yp,
+                                                     float* __restrict__ out,
+                                                     const float* __restrict__ dotv,
+                                                     double* __restrict__ partials,
+                                                     const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    backproject_body<NB>(G, ang, yp, out, dotv, partials, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// normal: h = R^T rp with the partials of h^T p; else g = R^T rp.  NB is the
+// largest candidate count of the batch (extra candidates weigh exactly 0).
+template <int NB>
+__global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, ItemTable t,
+                                                      int normal) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const GeomDev G = S.G;
+        const int gx = (G.cols + BP_TILE - 1) / BP_TILE;
+        backproject_body<NB>(G, S.ang, S.rp, normal ? S.h : S.g, normal ? S.p : nullptr,
+                             normal ? S.pph : nullptr, lin % gx, lin / gx, gx);
+    });
+}
+
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal) {
+    const int nm = normal ? 1 : 0;
+    switch (nbmax) {
+    case 1: hipLaunchKernelGGL(kb_backproject<1>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
+    case 2: hipLaunchKernelGGL(kb_backproject<2>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
+    case 3: hipLaunchKernelGGL(kb_backproject<3>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
+    default: hipLaunchKernelGGL(kb_backproject<4>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
     }
 }
 

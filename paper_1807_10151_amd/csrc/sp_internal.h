@@ -182,6 +182,75 @@ void lp_gd(hipStream_t st, long npix, const float* E, const float* A, double* pa
 void lp_adam(hipStream_t st, int n, float* theta, float* m, float* v, const float* g, double lr,
              double b1, double b2, double eps, int step);
 
+// ---- batched solve: many slices advance through one launch per stage --------
+// Every stage kernel has a batched form that walks a table of work items
+// (slice << ITEM_SHIFT | linear virtual block) with a grid-stride loop: a grid
+// of one workgroup per item is the flat form, a smaller grid the persistent
+// form.  A slice's virtual block runs the same body, with the same partial
+// indices, as the single-slice launch, so results are bitwise identical.
+constexpr int ITEM_SHIFT = 20;
+constexpr uint32_t ITEM_MASK = (1u << ITEM_SHIFT) - 1u;
+constexpr int MAX_BATCH = 4096;
+
+struct SliceDev {
+    GeomDev G;
+    FFTPlan F;
+    const AngleDev* ang;
+    const float* b;
+    const float* x0;   // nullable: zero start
+    float *xh, *x, *p, *h, *g, *z, *tb, *xp, *xTp, *rp;
+    double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
+    Scalars* sc;
+    TraceDev tr;
+    int n, nf, nph, ngp, nzh, ntv;
+};
+
+// Stage selectors of the batched kernels.
+enum BatchVec : int { BV_XH = 0, BV_X = 1, BV_P = 2 };
+enum BatchStage : int {
+    BS_PREP = 0, BS_PROJECT, BS_BACKPROJECT, BS_ROWS, BS_COLS, BS_TV, BS_VEC, BS_SLICE, BS_COUNT
+};
+struct ItemTable {
+    const uint32_t* items;
+    int n;
+    int grid;   // workgroups launched: n (flat) or fewer (persistent)
+};
+
+// Runs fn(slice, virtual block) for the items of this workgroup; the barrier
+// after each item keeps LDS reuse ordered.
+template <class Fn>
+__device__ __forceinline__ void for_items(const ItemTable& t, Fn&& fn) {
+    for (int w = blockIdx.x; w < t.n; w += gridDim.x) {
+        const uint32_t it = t.items[w];
+        fn((int)(it >> ITEM_SHIFT), (int)(it & ITEM_MASK));
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ float* batch_vec(const SliceDev& S, int which) {
+    return which == BV_XH ? S.xh : (which == BV_X ? S.x : S.p);
+}
+
+// projector.hip
+void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which);
+void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, bool residual);
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal);
+// fft.hip (z = M g; with the partials of z^T h into pzh)
+void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTable cols,
+                      size_t lds_rows, size_t lds_cols, double mu, double rho);
+// tv.hip
+void launch_tv_grad_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src);
+void launch_tv_trials_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src);
+void launch_tv_decide_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src);
+void launch_tv_apply_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, bool snorm);
+// cg.hip
+void launch_copy_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, int dst);
+void launch_init_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // xh = x = x0 (or 0)
+void launch_update_p_b(hipStream_t st, const SliceDev* sl, ItemTable t);
+void launch_update_x_b(hipStream_t st, const SliceDev* sl, ItemTable t);
+void launch_dot_zh_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // g -> z copy + z^T h
+void launch_scalar_b(hipStream_t st, const SliceDev* sl, ItemTable t, int op);
+
 enum ScalarOp : int {
     OP_F = 0,        // f = sum(pa); trace / non-finite check
     OP_F0 = 1,       // f(x_0) at initialisation

@@ -47,14 +47,12 @@ __device__ __forceinline__ float tv_neg_grad(const float* __restrict__ y, int ro
     return bad ? 0.0f : -gsum;
 }
 
-__global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const float* __restrict__ y,
-                                                 float* __restrict__ tb,
-                                                 double* __restrict__ partials,
-                                                 const int* __restrict__ halt) {
-    if (halt && *halt) return;
+__device__ __forceinline__ void tv_grad_body(int rows, int cols, const float* __restrict__ y,
+                                             float* __restrict__ tb, double* __restrict__ partials,
+                                             int bx) {
     __shared__ double red[4];
     const size_t n = (size_t)rows * cols;
-    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t p = (size_t)bx * 256 + threadIdx.x;
     double sq = 0.0;
     if (p < n) {
         const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
@@ -63,7 +61,15 @@ __global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const float
         sq = (double)t * (double)t;
     }
     const double tot = block_sum(sq, red);
-    if (partials && threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (partials && threadIdx.x == 0) partials[bx] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const float* __restrict__ y,
+                                                 float* __restrict__ tb,
+                                                 double* __restrict__ partials,
+                                                 const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    tv_grad_body(rows, cols, y, tb, partials, blockIdx.x);
 }
 
 int tv_blocks(int rows, int cols) { return (int)(((size_t)rows * cols + 255) / 256); }
@@ -99,13 +105,11 @@ __device__ __forceinline__ double trial_lambda(const Scalars* sc, int trial, dou
     return tn > 0.0 ? sc->gamma * pow(sc->a, (double)(sc->ell + trial)) / tn : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const float* __restrict__ y,
-                                                   const float* __restrict__ tb,
-                                                   const double* __restrict__ gpart, int ngpart,
-                                                   const Scalars* __restrict__ sc,
-                                                   double* __restrict__ tpart,
-                                                   const int* __restrict__ halt) {
-    if (halt && *halt) return;
+__device__ __forceinline__ void tv_trials_body(int rows, int cols, const float* __restrict__ y,
+                                               const float* __restrict__ tb,
+                                               const double* __restrict__ gpart, int ngpart,
+                                               const Scalars* __restrict__ sc,
+                                               double* __restrict__ tpart, int bx) {
     __shared__ double red[4];
     __shared__ double lam[TVJ];
     const double tn = sqrt(reduce_partials(gpart, ngpart, red));
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const flo
 #pragma unroll
     for (int q = 0; q <= TVJ; ++q) acc[q] = 0.0;
     const size_t n = (size_t)rows * cols;
-    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t p = (size_t)bx * 256 + threadIdx.x;
     if (p < n) {
         const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
         if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam_r, TVJ, acc);
@@ -126,8 +130,18 @@ __global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const flo
 #pragma unroll
     for (int q = 0; q <= TVJ; ++q) {
         const double tot = block_sum(acc[q], red);
-        if (threadIdx.x == 0) tpart[(size_t)blockIdx.x * (TVJ + 1) + q] = tot;
+        if (threadIdx.x == 0) tpart[(size_t)bx * (TVJ + 1) + q] = tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const float* __restrict__ y,
+                                                   const float* __restrict__ tb,
+                                                   const double* __restrict__ gpart, int ngpart,
+                                                   const Scalars* __restrict__ sc,
+                                                   double* __restrict__ tpart,
+                                                   const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    tv_trials_body(rows, cols, y, tb, gpart, ngpart, sc, tpart, blockIdx.x);
 }
 
 void launch_tv_trials(hipStream_t st, int rows, int cols, const float* y, const float* tb,
@@ -157,14 +171,12 @@ __device__ void tv_trials_wg(const float* __restrict__ y, const float* __restric
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_tv_decide(int rows, int cols, const float* __restrict__ y,
-                                                   const float* __restrict__ tb,
-                                                   const double* __restrict__ gpart, int ngpart,
-                                                   const double* __restrict__ tpart, int ntpart,
-                                                   Scalars* __restrict__ sc, TraceDev tr,
-                                                   int32_t* __restrict__ trials_out,
-                                                   const int* __restrict__ halt) {
-    if (halt && *halt) return;
+__device__ __forceinline__ void tv_decide_body(int rows, int cols, const float* __restrict__ y,
+                                               const float* __restrict__ tb,
+                                               const double* __restrict__ gpart, int ngpart,
+                                               const double* __restrict__ tpart, int ntpart,
+                                               Scalars* __restrict__ sc, const TraceDev& tr,
+                                               int32_t* __restrict__ trials_out) {
     __shared__ double red[4];
     __shared__ double tv[TVJ + 1];
     __shared__ double lam[TVJ];
@@ -255,6 +267,17 @@ __global__ __launch_bounds__(256) void k_tv_decide(int rows, int cols, const flo
     }
 }
 
+__global__ __launch_bounds__(256) void k_tv_decide(int rows, int cols, const float* __restrict__ y,
+                                                   const float* __restrict__ tb,
+                                                   const double* __restrict__ gpart, int ngpart,
+                                                   const double* __restrict__ tpart, int ntpart,
+                                                   Scalars* __restrict__ sc, TraceDev tr,
+                                                   int32_t* __restrict__ trials_out,
+                                                   const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    tv_decide_body(rows, cols, y, tb, gpart, ngpart, tpart, ntpart, sc, tr, trials_out);
+}
+
 void launch_tv_decide(hipStream_t st, int rows, int cols, const float* y, const float* tb,
                       const double* gpart, int ngpart, const double* tpart, int ntpart, int J,
                       Scalars* sc, TraceDev tr, int32_t* trials_out, const int* halt) {
@@ -263,17 +286,14 @@ void launch_tv_decide(hipStream_t st, int rows, int cols, const float* y, const 
                        tpart, ntpart, sc, tr, trials_out, halt);
 }
 
-__global__ __launch_bounds__(256) void k_tv_apply(int n, const float* __restrict__ src,
-                                                  float* __restrict__ dst,
-                                                  const float* __restrict__ tb,
-                                                  const Scalars* __restrict__ sc,
-                                                  const float* __restrict__ xk,
-                                                  double* __restrict__ partials,
-                                                  const int* __restrict__ halt) {
-    if (halt && *halt) return;
+__device__ __forceinline__ void tv_apply_body(int n, const float* __restrict__ src,
+                                              float* __restrict__ dst, const float* __restrict__ tb,
+                                              const Scalars* __restrict__ sc,
+                                              const float* __restrict__ xk,
+                                              double* __restrict__ partials, int bx) {
     __shared__ double red[4];
     const double lam = sc->lam;
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int p = bx * 256 + threadIdx.x;
     double s2 = 0.0;
     if (p < n) {
         const float v = (float)((double)src[p] + lam * (double)tb[p]);
@@ -285,8 +305,19 @@ __global__ __launch_bounds__(256) void k_tv_apply(int n, const float* __restrict
     }
     if (xk) {
         const double tot = block_sum(s2, red);
-        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+        if (threadIdx.x == 0) partials[bx] = tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_tv_apply(int n, const float* __restrict__ src,
+                                                  float* __restrict__ dst,
+                                                  const float* __restrict__ tb,
+                                                  const Scalars* __restrict__ sc,
+                                                  const float* __restrict__ xk,
+                                                  double* __restrict__ partials,
+                                                  const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    tv_apply_body(n, src, dst, tb, sc, xk, partials, blockIdx.x);
 }
 
 void launch_tv_apply(hipStream_t st, int n, const float* src, float* dst, const float* tb,
@@ -319,6 +350,55 @@ void launch_tv_value(hipStream_t st, int rows, int cols, const float* y, double*
                      const int* halt) {
     hipLaunchKernelGGL(k_tv_value, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y,
                        partials, halt);
+}
+
+// ---- batched S_TV inner step: src selects x (first inner step) or x_half ----
+__global__ __launch_bounds__(256) void kb_tv_grad(const SliceDev* __restrict__ sl, ItemTable t, int src) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        tv_grad_body(S.G.rows, S.G.cols, batch_vec(S, src), S.tb, S.ptg, lin);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_tv_trials(const SliceDev* __restrict__ sl, ItemTable t, int src) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        tv_trials_body(S.G.rows, S.G.cols, batch_vec(S, src), S.tb, S.ptg, S.ntv, S.sc, S.ptt, lin);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_tv_decide(const SliceDev* __restrict__ sl, ItemTable t, int src) {
+    for_items(t, [&](int s, int) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        const TraceDev tr = S.tr;
+        tv_decide_body(S.G.rows, S.G.cols, batch_vec(S, src), S.tb, S.ptg, S.ntv, S.ptt, S.ntv,
+                       S.sc, tr, nullptr);
+    });
+}
+
+__global__ __launch_bounds__(256) void kb_tv_apply(const SliceDev* __restrict__ sl, ItemTable t, int src,
+                                                   int snorm) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (S.sc->halt) return;
+        tv_apply_body(S.n, batch_vec(S, src), S.xh, S.tb, S.sc, snorm ? S.x : nullptr, S.pts, lin);
+    });
+}
+
+void launch_tv_grad_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src) {
+    hipLaunchKernelGGL(kb_tv_grad, dim3(t.grid), dim3(256), 0, st, sl, t, src);
+}
+void launch_tv_trials_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src) {
+    hipLaunchKernelGGL(kb_tv_trials, dim3(t.grid), dim3(256), 0, st, sl, t, src);
+}
+void launch_tv_decide_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src) {
+    hipLaunchKernelGGL(kb_tv_decide, dim3(t.grid), dim3(256), 0, st, sl, t, src);
+}
+void launch_tv_apply_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, bool snorm) {
+    hipLaunchKernelGGL(kb_tv_apply, dim3(t.grid), dim3(256), 0, st, sl, t, src, snorm ? 1 : 0);
 }
 
 }  // namespace sp
