@@ -104,7 +104,7 @@ typedef struct {
  * accepted") instead of testing TV -- used to separate arithmetic differences
  * from control-flow differences. SP_FLAG_GRAPH captures one loop body in a
  * HIP graph and replays it. */
-enum { SP_FLAG_REPLAY = 1u, SP_FLAG_GRAPH = 2u };
+enum { SP_FLAG_REPLAY = 1u, SP_FLAG_GRAPH = 2u, SP_FLAG_AUTOTUNE = 4u };
 typedef struct {
     double eps;
     int32_t max_iter;
@@ -194,6 +194,48 @@ int sp_tv_perturb(sp_ctx* ctx, const sp_geometry* g, const sp_tv_params* p, cons
 int sp_suppcg_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const float* x0,
                     const sp_tv_params* tv, const sp_precond* pc, const sp_solve_params* sp,
                     float* x_out, float* x_last, int32_t* k_out, sp_trace* trace);
+
+/* ---- batched solver -----------------------------------------------------------
+ * Algorithm 3 on n independent slices of any mix of geometries, advanced in
+ * lockstep: every stage of the loop body is ONE launch whose workgroups walk a
+ * table of (slice, block) work items covering all slices, so slices of uneven
+ * size share the GPU without a launch per slice.  Per slice the arithmetic,
+ * the partial sums and their order are those of sp_suppcg_solve, so every
+ * slice's result equals its single-slice solve bit for bit.  Each slice halts
+ * on its own (breakdown, non-finite value, eps); the others continue.
+ *   geoms[n], b[n] (device [n_angles][n_bins]), x_out[n] (device, x_{k-1/2}):
+ *     per-slice arrays of host pointers; x0 (NULL, or n entries each NULL =
+ *     zero image) and x_last (NULL, or n entries) likewise.
+ *   pc: SP_PRECOND_RAMP or SP_PRECOND_NONE, shared by all slices.
+ *   sp->flags: SP_FLAG_GRAPH captures one loop body in a HIP graph and replays
+ *     it; SP_FLAG_AUTOTUNE times the launch shapes of the heavy stages (item
+ *     order: slice-major or grouped by XCD; grid: one workgroup per item or a
+ *     persistent 2/4/8 workgroups per CU) once per batch layout and keeps the
+ *     fastest; SP_FLAG_REPLAY is not supported here.
+ *   k_out: host [n].  trace (nullable): host arrays [n][cap] and status[n].
+ * Limits: 1 <= n <= 4096; each slice within the single-slice limits.
+ * Returns SP_OK when every slice ended without error (per-slice SP_MAXITER /
+ * SP_CONVERGED / SP_BREAKDOWN_CONVERGED / SP_TRIALS_EXHAUSTED in
+ * trace->status), else the first slice's SP_ERR_* code. */
+typedef struct {
+    double* f_half;   /* [n][cap] f(x_{k+1/2}) of loop body k */
+    double* tv_half;  /* [n][cap] TV(x_{k+1/2}) */
+    int32_t* ell;     /* [n][cap] l_{k+1} */
+    int32_t cap;
+    int32_t* status;  /* [n] */
+} sp_batch_trace;
+
+int sp_suppcg_solve_batched(sp_ctx* ctx, int32_t n, const sp_geometry* geoms,
+                            const float* const* b, const float* const* x0,
+                            const sp_tv_params* tv, const sp_precond* pc,
+                            const sp_solve_params* sp, float* const* x_out,
+                            float* const* x_last, int32_t* k_out, sp_batch_trace* trace);
+
+/* Launch shapes in use by the batched solver, per stage (prep, project,
+ * backproject, FFT rows, FFT columns, TV, vector, per-slice): out[2 s] = item
+ * order (0 slice-major, 1 grouped by XCD), out[2 s + 1] = workgroups per CU of
+ * the persistent grid (0 = one workgroup per item).  count >= 16. */
+int sp_batch_tuning(sp_ctx* ctx, int32_t* out, int32_t count);
 
 /* ---- learned preconditioner ---------------------------------------------------
  * M = C^T diag(softplus(d)) C, with C a stack of `layers` linear 3x3

@@ -4,10 +4,11 @@ tomography on AMD Instinct MI355X (gfx950).
 The computation lives in ``libsuppcg.so`` (hand-written HIP kernels behind the
 C ABI of ``include/suppcg.h``); this package is its PyTorch binding.
 """
-from .api import (Context, Geometry, LearnedPrecond, SolveResult, SupPCGError, context, sp_backproject,
-                  sp_precond_apply, sp_project, sp_residual, sp_suppcg_solve, sp_tv, sp_tv_grad,
-                  sp_tv_perturb)
+from .api import (Context, Geometry, LearnedPrecond, SolveResult, SupPCGError, batch_tuning, context,
+                  sp_backproject, sp_precond_apply, sp_project, sp_residual, sp_suppcg_solve,
+                  sp_suppcg_solve_batched, sp_tv, sp_tv_grad, sp_tv_perturb)
 
-__all__ = ["Context", "Geometry", "LearnedPrecond", "SolveResult", "SupPCGError", "context", "sp_backproject",
+__all__ = ["Context", "Geometry", "LearnedPrecond", "SolveResult", "SupPCGError", "batch_tuning", "context",
+           "sp_suppcg_solve_batched", "sp_backproject",
            "sp_precond_apply", "sp_project", "sp_residual", "sp_suppcg_solve", "sp_tv",
            "sp_tv_grad", "sp_tv_perturb"]

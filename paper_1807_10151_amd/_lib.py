@@ -31,6 +31,7 @@ SP_PRECOND_LEARNED = 2
 
 SP_FLAG_REPLAY = 1
 SP_FLAG_GRAPH = 2
+SP_FLAG_AUTOTUNE = 4
 
 SP_PROF_PROJECT = 0
 SP_PROF_BACKPROJECT = 1
@@ -74,6 +75,11 @@ class sp_trace(ctypes.Structure):
                 ("g_snap", c_void_p), ("g_snap_count", c_int32)]
 
 
+class sp_batch_trace(ctypes.Structure):
+    _fields_ = [("f_half", POINTER(c_double)), ("tv_half", POINTER(c_double)),
+                ("ell", POINTER(c_int32)), ("cap", c_int32), ("status", POINTER(c_int32))]
+
+
 _SIGS = {
     "sp_version": (c_char_p, []),
     "sp_ctx_create": (c_int, [c_int, c_void_p, POINTER(c_void_p)]),
@@ -91,6 +97,11 @@ _SIGS = {
     "sp_suppcg_solve": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p,
                                 POINTER(sp_tv_params), POINTER(sp_precond), POINTER(sp_solve_params),
                                 c_void_p, c_void_p, POINTER(c_int32), POINTER(sp_trace)]),
+    "sp_suppcg_solve_batched": (c_int, [c_void_p, c_int32, POINTER(sp_geometry), POINTER(c_void_p),
+                                        POINTER(c_void_p), POINTER(sp_tv_params), POINTER(sp_precond),
+                                        POINTER(sp_solve_params), POINTER(c_void_p), POINTER(c_void_p),
+                                        POINTER(c_int32), POINTER(sp_batch_trace)]),
+    "sp_batch_tuning": (c_int, [c_void_p, POINTER(c_int32), c_int32]),
     "sp_lp_create": (c_int, [c_void_p, c_int32, c_int32, POINTER(c_void_p)]),
     "sp_lp_destroy": (c_int, [c_void_p]),
     "sp_lp_num_params": (ctypes.c_int64, [c_void_p]),

@@ -157,6 +157,66 @@ def sp_residual(g: Geometry, x: torch.Tensor, b: torch.Tensor, ctx: Context | No
     return r, f
 
 
+def sp_suppcg_solve_batched(geoms, bs, x0s=None, *, K: int = 1, a: float = 0.5, gamma: float = 0.5,
+                            max_trials: int = 100, precond="ramp", mu: float = 1e-5,
+                            rho: float = 0.8, max_iter: int = 20, eps: float = 0.0,
+                            graph: bool = True, autotune: bool = False, trace: bool = True,
+                            x_half=None, x_last=None, ctx: Context | None = None):
+    """Algorithm 3 on a batch of slices in lockstep (one launch per stage for
+    all slices).  geoms, bs (and optional x0s, x_half, x_last): per-slice lists.
+    Returns one SolveResult per slice (trace: f_half, tv_half, ell)."""
+    n = len(geoms)
+    if n < 1 or len(bs) != n:
+        raise ValueError("need one data tensor per geometry")
+    ctx = ctx or context(bs[0].device.index or 0)
+    dev = ctx.device
+    x_half = list(x_half) if x_half is not None else [None] * n
+    x_last = list(x_last) if x_last is not None else [None] * n
+    for i, g in enumerate(geoms):
+        x_half[i] = _out(x_half[i], (g.rows, g.cols), dev)
+        x_last[i] = _out(x_last[i], (g.rows, g.cols), dev)
+    garr = (L.sp_geometry * n)(*[g.c() for g in geoms])
+    ptrs = lambda ts, size, name: (ctypes.c_void_p * n)(
+        *[_dev(t, sz, name, dev).value if t is not None else None for t, sz in zip(ts, size)])
+    b_arr = ptrs(bs, [g.m for g in geoms], "b")
+    x0_arr = ptrs(x0s, [g.n for g in geoms], "x0") if x0s is not None else None
+    xh_arr = ptrs(x_half, [g.n for g in geoms], "x_half")
+    xl_arr = ptrs(x_last, [g.n for g in geoms], "x_last")
+    tvp = L.sp_tv_params(K, a, gamma, max_trials)
+    pc = _precond(precond, mu, rho, None)
+    flags = (L.SP_FLAG_GRAPH if graph else 0) | (L.SP_FLAG_AUTOTUNE if autotune else 0)
+    sp = L.sp_solve_params(eps, max_iter, flags, None)
+    cap = max(max_iter, 1)
+    k_out = (ctypes.c_int32 * n)()
+    status = np.zeros(n, dtype=np.int32)
+    f_half = np.zeros((n, cap))
+    tv_half = np.zeros((n, cap))
+    ell = np.zeros((n, cap), dtype=np.int32)
+    dp = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ip = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    tr = L.sp_batch_trace(dp(f_half), dp(tv_half), ip(ell), cap, ip(status))
+    ctx._stream()
+    rc = ctx.lib.sp_suppcg_solve_batched(
+        ctx.h, n, garr, b_arr, x0_arr, ctypes.byref(tvp), ctypes.byref(pc), ctypes.byref(sp), xh_arr,
+        xl_arr, k_out, ctypes.byref(tr))
+    ctx._check(rc)
+    out = []
+    for i in range(n):
+        done = min(max(k_out[i] - 1, 0), cap)
+        tr_i = {"f_half": f_half[i, :done], "tv_half": tv_half[i, :done], "ell": ell[i, :done]} if trace else {}
+        out.append(SolveResult(int(k_out[i]), x_half[i], x_last[i], int(status[i]), tr_i))
+    return out
+
+
+def batch_tuning(ctx: Context | None = None) -> dict:
+    """Launch shapes the batched solver uses, per stage: (order, workgroups per CU)."""
+    ctx = ctx or context(0)
+    arr = (ctypes.c_int32 * 16)()
+    ctx._check(ctx.lib.sp_batch_tuning(ctx.h, arr, 16))
+    names = ["prep", "project", "backproject", "fft_rows", "fft_cols", "tv", "vector", "per_slice"]
+    return {nm: ("xcd" if arr[2 * i] else "slice", int(arr[2 * i + 1])) for i, nm in enumerate(names)}
+
+
 class LearnedPrecond:
     """M = C^T diag(softplus(d)) C (sp_lp_* calls); parameters live on the GPU."""
 

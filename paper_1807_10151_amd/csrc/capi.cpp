@@ -22,6 +22,23 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Batched solve: per-slice tables and buffers of one batch layout (the
+// geometries and preconditioner kind), cached across calls.
+struct BatchState {
+    std::vector<sp_geometry> geoms;
+    int kind = -1;
+    int nbmax = 1;
+    size_t lds_rows = 0, lds_cols = 0;
+    std::vector<SliceDev> hs;        // host copies; per-call pointers filled in each call
+    std::vector<char*> own_x;        // per slice: x_k storage used when x_last is NULL
+    DevBuf arena, sl, items, scal, trace_d;
+    size_t off[BS_COUNT][2] = {};    // item-table offsets (entries) per stage and order
+    int count[BS_COUNT][2] = {};
+    int order[BS_COUNT] = {};        // chosen order (0 slice-major, 1 grouped by XCD)
+    int wpc[BS_COUNT] = {};          // chosen workgroups per CU (0: one per item)
+    bool tuned = false;
+};
+
 }  // namespace
 
 struct sp_ctx {
@@ -46,6 +63,8 @@ struct sp_ctx {
     DevBuf scal, trace_d, replay_d, trials_tmp;
     Scalars sc_h{};
     hipStream_t own = nullptr;   // capture stream used when the caller's stream is null
+    BatchState* batch = nullptr;
+    int n_cu = 0;
 
     // instrumentation: event pairs around launches (sp_profile_enable)
     bool prof = false;
@@ -518,6 +537,304 @@ int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, c
     return SP_OK;
 }
 
+
+// ---- batched solve -----------------------------------------------------------
+
+constexpr int XCDS = 8;              // workgroup w is dispatched to XCD w % 8
+constexpr int TUNE_STAGES[] = {BS_PREP, BS_PROJECT, BS_BACKPROJECT, BS_ROWS, BS_TV, BS_VEC};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Virtual blocks of slice S in a stage (the single-slice grid of that stage).
+int stage_blocks(const SliceDev& S, int stage) {
+    const GeomDev& G = S.G;
+    switch (stage) {
+    case BS_PREP: return ((G.cols + 31) / 32) * ((G.rows + 31) / 32);
+    case BS_PROJECT: return project_blocks(G);
+    case BS_BACKPROJECT: return backproject_blocks(G);
+    case BS_ROWS: return (G.rows + 1) / 2;
+    case BS_COLS: return S.F.P ? (S.F.SP + S.F.CB - 1) / S.F.CB : 0;
+    case BS_TV: return tv_blocks(G.rows, G.cols);
+    case BS_VEC: return vec_blocks(S.n);
+    default: return 1;
+    }
+}
+
+// Relative cost of one item of the stage for slice S (load balance only).
+double item_cost(const SliceDev& S, int stage) {
+    const GeomDev& G = S.G;
+    switch (stage) {
+    case BS_PROJECT: return (double)std::max(G.rows, G.cols);
+    case BS_BACKPROJECT: return (double)G.nA;
+    case BS_ROWS:
+    case BS_COLS: return S.F.P ? (double)S.F.P * S.F.logP : 0.0;
+    case BS_VEC: return (double)S.n / std::max(1, vec_blocks(S.n));
+    default: return 1.0;
+    }
+}
+
+// Item tables of a stage.  Order 0: slices by decreasing work, each slice's
+// blocks consecutive.  Order 1: slices assigned to the 8 XCDs by decreasing
+// work to the least-loaded XCD, and entry 8 j + q holding the j-th item of XCD
+// q's queue (shorter queues padded with ITEM_NONE), so a slice's blocks share
+// one XCD's L2 under the round-robin dispatch of workgroups to XCDs.
+void stage_items(const std::vector<SliceDev>& hs, int stage, std::vector<uint32_t>& o0,
+                 std::vector<uint32_t>& o1) {
+    const int n = (int)hs.size();
+    std::vector<int> idx(n);
+    std::vector<double> work(n);
+    for (int s = 0; s < n; ++s) {
+        idx[s] = s;
+        work[s] = stage_blocks(hs[s], stage) * item_cost(hs[s], stage);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[a] > work[b]; });
+    o0.clear();
+    for (int s : idx)
+        for (int b = 0, nb = stage_blocks(hs[s], stage); b < nb; ++b)
+            o0.push_back(((uint32_t)s << ITEM_SHIFT) | (uint32_t)b);
+    std::vector<std::vector<uint32_t>> q(XCDS);
+    std::vector<double> load(XCDS, 0.0);
+    for (int s : idx) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += work[s];
+        for (int b = 0, nb = stage_blocks(hs[s], stage); b < nb; ++b)
+            q[x].push_back(((uint32_t)s << ITEM_SHIFT) | (uint32_t)b);
+    }
+    size_t len = 0;
+    for (auto& v : q) len = std::max(len, v.size());
+    o1.assign(len * XCDS, ITEM_NONE);
+    for (int x = 0; x < XCDS; ++x)
+        for (size_t j = 0; j < q[x].size(); ++j) o1[j * XCDS + x] = q[x][j];
+}
+
+ItemTable table(sp_ctx* c, int stage, int order = -1, int wpc = -1) {
+    BatchState& B = *c->batch;
+    if (order < 0) order = B.order[stage];
+    if (wpc < 0) wpc = B.wpc[stage];
+    ItemTable t;
+    t.items = dptr<uint32_t>(B.items) + B.off[stage][order];
+    t.n = B.count[stage][order];
+    const long want = wpc > 0 ? (long)wpc * c->n_cu : (long)t.n;
+    t.grid = (int)std::max(1L, std::min<long>(t.n, want));
+    return t;
+}
+
+// (Re)builds the batch layout: geometry tables, one device arena holding every
+// slice's padded copies, vectors, FFT scratch, twiddles and partials, and the
+// item tables.  Kept while the geometries and preconditioner kind repeat.
+int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
+    if (c->batch && c->batch->kind == kind && (int)c->batch->geoms.size() == n &&
+        std::memcmp(c->batch->geoms.data(), geoms, sizeof(sp_geometry) * (size_t)n) == 0)
+        return SP_OK;
+    if (!c->batch) c->batch = new BatchState();
+    BatchState& B = *c->batch;
+    B.geoms.clear();     // the cache is valid only once the setup has completed
+    B.kind = kind;
+    B.tuned = false;
+    for (int s = 0; s < BS_COUNT; ++s) B.order[s] = B.wpc[s] = 0;
+    B.hs.assign(n, SliceDev{});
+    B.own_x.assign(n, nullptr);
+    B.nbmax = 1;
+    B.lds_rows = B.lds_cols = 0;
+    std::vector<std::vector<AngleDev>> tabs(n);
+    // sizes
+    struct Off {
+        size_t ang, xp, xTp, rp, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
+    };
+    std::vector<Off> off(n);
+    size_t total = 0;
+    int rc;
+    for (int s = 0; s < n; ++s) {
+        SliceDev& S = B.hs[s];
+        if ((rc = build_geometry(c, &geoms[s], S.G, tabs[s]))) return fail(c, rc, "slice %d: %s", s, c->err.c_str());
+        const GeomDev& G = S.G;
+        B.nbmax = std::max(B.nbmax, G.nbmax);
+        S.n = G.rows * G.cols;
+        S.F = FFTPlan{};
+        if (kind == SP_PRECOND_RAMP) {
+            const int P = pad_size(G.rows, G.cols);
+            if (P > 4096) return fail(c, SP_ERR_ARG, "slice %d: preconditioner supports up to 2048 pixels a side", s);
+            S.F.P = P;
+            while ((1 << S.F.logP) < P) ++S.F.logP;
+            S.F.SP = P / 2 + 1;
+            S.F.rows = G.rows;
+            S.F.cols = G.cols;
+            S.F.CB = std::max(1, 2048 / P);
+            B.lds_rows = std::max(B.lds_rows, (size_t)P * sizeof(double2));
+            B.lds_cols = std::max(B.lds_cols, (size_t)S.F.CB * P * sizeof(double2));
+        }
+        S.nf = project_blocks(G);
+        S.nph = backproject_blocks(G);
+        S.ngp = vec_blocks(S.n);
+        S.ntv = tv_blocks(G.rows, G.cols);
+        S.nzh = kind == SP_PRECOND_RAMP ? (G.rows + 1) / 2 : vec_blocks(S.n);
+        Off& o = off[s];
+        auto take = [&](size_t bytes) {
+            const size_t at = total;
+            total += align256(bytes);
+            return at;
+        };
+        o.ang = take(tabs[s].size() * sizeof(AngleDev));
+        o.xp = take((size_t)G.rows * G.pitchX * 4);
+        o.xTp = take((size_t)G.cols * G.pitchXT * 4);
+        o.rp = take((size_t)G.nA * G.pitchB * 4);
+        o.vec = take((size_t)S.n * 4 * 6);   // x, p, h, g, z, t_bar
+        o.S = kind == SP_PRECOND_RAMP ? take((size_t)G.rows * S.F.SP * sizeof(double2)) : 0;
+        o.tw = kind == SP_PRECOND_RAMP ? take((size_t)(S.F.P / 2) * sizeof(double2)) : 0;
+        o.pf = take((size_t)S.nf * 8);
+        o.pzh = take((size_t)std::max(S.nzh, S.ngp) * 8);
+        o.pgp = take((size_t)S.ngp * 8);
+        o.pph = take((size_t)S.nph * 8);
+        o.ptg = take((size_t)S.ntv * 8);
+        o.ptt = take((size_t)S.ntv * 9 * 8);
+        o.pts = take((size_t)S.ntv * 8);
+    }
+    if (B.lds_cols > 65536) return fail(c, SP_ERR_ARG, "FFT column tile exceeds the LDS");
+    // a fresh zero-filled arena: the pads of the padded copies must be zero
+    release(B.arena);
+    if ((rc = ensure(c, B.arena, total))) return rc;
+    if ((rc = ensure(c, B.scal, sizeof(Scalars) * (size_t)n))) return rc;
+    if ((rc = ensure(c, B.sl, sizeof(SliceDev) * (size_t)n))) return rc;
+    char* base = dptr<char>(B.arena);
+    std::vector<double2> tw;
+    for (int s = 0; s < n; ++s) {
+        SliceDev& S = B.hs[s];
+        const Off& o = off[s];
+        S.ang = reinterpret_cast<const AngleDev*>(base + o.ang);
+        S.xp = reinterpret_cast<float*>(base + o.xp);
+        S.xTp = reinterpret_cast<float*>(base + o.xTp);
+        S.rp = reinterpret_cast<float*>(base + o.rp);
+        float* v = reinterpret_cast<float*>(base + o.vec);
+        B.own_x[s] = reinterpret_cast<char*>(v);
+        S.p = v + (size_t)S.n;
+        S.h = v + 2 * (size_t)S.n;
+        S.g = v + 3 * (size_t)S.n;
+        S.z = v + 4 * (size_t)S.n;
+        S.tb = v + 5 * (size_t)S.n;
+        if (kind == SP_PRECOND_RAMP) {
+            S.F.S = reinterpret_cast<double2*>(base + o.S);
+            S.F.tw = reinterpret_cast<const double2*>(base + o.tw);
+            tw.resize(S.F.P / 2);
+            for (int k = 0; k < S.F.P / 2; ++k) {
+                const double ang = -2.0 * M_PI * (double)k / (double)S.F.P;
+                tw[k] = make_double2(std::cos(ang), std::sin(ang));
+            }
+            HIP_TRY(c, hipMemcpyAsync(base + o.tw, tw.data(), tw.size() * sizeof(double2),
+                                      hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+        S.pf = reinterpret_cast<double*>(base + o.pf);
+        S.pzh = reinterpret_cast<double*>(base + o.pzh);
+        S.pgp = reinterpret_cast<double*>(base + o.pgp);
+        S.pph = reinterpret_cast<double*>(base + o.pph);
+        S.ptg = reinterpret_cast<double*>(base + o.ptg);
+        S.ptt = reinterpret_cast<double*>(base + o.ptt);
+        S.pts = reinterpret_cast<double*>(base + o.pts);
+        S.sc = dptr<Scalars>(B.scal) + s;
+        HIP_TRY(c, hipMemcpyAsync(base + o.ang, tabs[s].data(), tabs[s].size() * sizeof(AngleDev),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));   // host table must outlive the copy
+    }
+    for (int s = 0; s < n; ++s)
+        for (int st = 0; st < BS_COUNT; ++st)
+            if (stage_blocks(B.hs[s], st) > (int)ITEM_MASK) {
+                B.geoms.clear();
+                return fail(c, SP_ERR_ARG, "slice %d: too many work items for a batch", s);
+            }
+    // item tables
+    std::vector<uint32_t> all, o0, o1;
+    for (int st = 0; st < BS_COUNT; ++st) {
+        if (st == BS_COLS && kind != SP_PRECOND_RAMP) continue;
+        stage_items(B.hs, st, o0, o1);
+        B.off[st][0] = all.size();
+        B.count[st][0] = (int)o0.size();
+        all.insert(all.end(), o0.begin(), o0.end());
+        B.off[st][1] = all.size();
+        B.count[st][1] = (int)o1.size();
+        all.insert(all.end(), o1.begin(), o1.end());
+    }
+    if ((rc = ensure(c, B.items, all.size() * sizeof(uint32_t)))) return rc;
+    HIP_TRY(c, hipMemcpyAsync(B.items.ptr, all.data(), all.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    B.geoms.assign(geoms, geoms + n);
+    return SP_OK;
+}
+
+// One batched stage group, as timed by the tuner and run by the solver.
+void batch_stage(sp_ctx* c, int stage, int order, int wpc, double mu, double rho) {
+    BatchState& B = *c->batch;
+    const SliceDev* sl = dptr<SliceDev>(B.sl);
+    hipStream_t st = c->stream;
+    const ItemTable t = table(c, stage, order, wpc);
+    switch (stage) {
+    case BS_PREP: launch_prep_b(st, sl, t, BV_XH); break;
+    case BS_PROJECT: launch_project_b(st, sl, t, true); break;
+    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, false); break;
+    case BS_ROWS:
+        launch_precond_b(st, sl, t, table(c, BS_COLS, order, wpc), B.lds_rows, B.lds_cols, mu, rho);
+        break;
+    case BS_TV:
+        launch_tv_grad_b(st, sl, t, BV_X);
+        launch_tv_trials_b(st, sl, t, BV_X);
+        break;
+    case BS_VEC: launch_update_x_b(st, sl, t); break;
+    default: break;
+    }
+}
+
+// Times every (order, grid) choice of the heavy stages and keeps the fastest.
+// Runs on the live buffers before the initial steps, which overwrite all that
+// the timed kernels write.
+int batch_tune(sp_ctx* c, double mu, double rho) {
+    BatchState& B = *c->batch;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    const int grids[] = {0, 2, 4, 8};
+    for (int stage : TUNE_STAGES) {
+        if (stage == BS_ROWS && B.kind != SP_PRECOND_RAMP) continue;
+        float best = 1e30f;
+        for (int order = 0; order < 2; ++order)
+            for (int wpc : grids) {
+                batch_stage(c, stage, order, wpc, mu, rho);   // warm
+                float tmin = 1e30f;
+                for (int r = 0; r < 3; ++r) {
+                    (void)hipEventRecord(e0, c->stream);
+                    batch_stage(c, stage, order, wpc, mu, rho);
+                    (void)hipEventRecord(e1, c->stream);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.0f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    tmin = std::min(tmin, ms);
+                }
+                if (tmin < best * 0.98f) {
+                    best = tmin;
+                    B.order[stage] = order;
+                    B.wpc[stage] = wpc;
+                }
+            }
+        if (stage == BS_ROWS) {
+            B.order[BS_COLS] = B.order[BS_ROWS];
+            B.wpc[BS_COLS] = B.wpc[BS_ROWS];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B.tuned = true;
+    return check_launch(c);
+}
+
+// Preconditioner stage of the batched solver: z = M g with z^T h partials.
+void batch_precond(sp_ctx* c, double mu, double rho) {
+    BatchState& B = *c->batch;
+    const SliceDev* sl = dptr<SliceDev>(B.sl);
+    if (B.kind == SP_PRECOND_RAMP)
+        launch_precond_b(c->stream, sl, table(c, BS_ROWS), table(c, BS_COLS), B.lds_rows, B.lds_cols,
+                         mu, rho);
+    else
+        launch_dot_zh_b(c->stream, sl, table(c, BS_VEC));
+}
 }  // namespace
 
 // ============================================================================
@@ -535,6 +852,9 @@ int sp_ctx_create(int device, void* hip_stream, sp_ctx** out) {
     sp_ctx* c = new sp_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        c->n_cu < 1)
+        c->n_cu = 256;
     *out = c;
     return SP_OK;
 }
@@ -550,6 +870,12 @@ int sp_ctx_destroy(sp_ctx* c) {
         release(*b);
     if (c->own) (void)hipStreamDestroy(c->own);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->batch) {
+        for (DevBuf* b : {&c->batch->arena, &c->batch->sl, &c->batch->items, &c->batch->scal,
+                          &c->batch->trace_d})
+            release(*b);
+        delete c->batch;
+    }
     delete c;
     return SP_OK;
 }
@@ -1096,6 +1422,225 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     }
     if (out.halt == SP_ERR_NONFINITE) return fail(c, SP_ERR_NONFINITE, "non-finite value in a CG scalar");
     return status;
+}
+
+int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, const float* const* b,
+                            const float* const* x0, const sp_tv_params* tv, const sp_precond* pc,
+                            const sp_solve_params* sp, float* const* x_out, float* const* x_last,
+                            int32_t* k_out, sp_batch_trace* trace) {
+    if (!c) return SP_ERR_ARG;
+    if (n < 1 || n > MAX_BATCH) return fail(c, SP_ERR_ARG, "n must be in [1, %d]", MAX_BATCH);
+    if (!geoms || !b || !x_out || !k_out || !sp || !pc)
+        return fail(c, SP_ERR_ARG, "geoms, b, x_out, k_out, params and preconditioner are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((sp->flags & SP_FLAG_GRAPH) && c->stream == nullptr) {
+        if (!c->own) HIP_TRY(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+        HIP_TRY(c, hipStreamSynchronize(nullptr));
+        c->stream = c->own;
+        int r = sp_suppcg_solve_batched(c, n, geoms, b, x0, tv, pc, sp, x_out, x_last, k_out, trace);
+        (void)hipStreamSynchronize(c->own);
+        c->stream = nullptr;
+        return r;
+    }
+    int rc;
+    for (int s = 0; s < n; ++s) {
+        if ((rc = validate_geometry(c, &geoms[s]))) return fail(c, rc, "slice %d: %s", s, c->err.c_str());
+        if (!b[s] || !x_out[s]) return fail(c, SP_ERR_ARG, "slice %d: b and x_out are required", s);
+    }
+    if (pc->kind != SP_PRECOND_RAMP && pc->kind != SP_PRECOND_NONE)
+        return fail(c, SP_ERR_ARG, "the batched solver supports the Fourier preconditioner and M = I");
+    if ((rc = check_precond(c, pc))) return rc;
+    if ((rc = check_tv(c, tv))) return rc;
+    if (sp->flags & SP_FLAG_REPLAY) return fail(c, SP_ERR_ARG, "SP_FLAG_REPLAY is not supported by the batched solver");
+    if (sp->max_iter < 0) return fail(c, SP_ERR_ARG, "max_iter must be >= 0");
+    if (!std::isfinite(sp->eps)) return fail(c, SP_ERR_ARG, "eps must be finite");
+    if ((rc = batch_setup(c, n, geoms, pc->kind))) return rc;
+    BatchState& B = *c->batch;
+    const int K = (tv && tv->K > 0) ? tv->K : 0;
+    const int cap = std::max(sp->max_iter, 1);
+    const size_t tr_slice = align256((size_t)cap * (5 * 8 + 4));
+    if ((rc = ensure(c, B.trace_d, tr_slice * (size_t)n))) return rc;
+    HIP_TRY(c, hipMemsetAsync(B.trace_d.ptr, 0, tr_slice * (size_t)n, c->stream));
+    std::vector<Scalars> sc(n);
+    for (int s = 0; s < n; ++s) {
+        SliceDev& S = B.hs[s];
+        S.b = b[s];
+        S.x0 = x0 ? x0[s] : nullptr;
+        S.xh = x_out[s];
+        S.x = (x_last && x_last[s]) ? x_last[s] : reinterpret_cast<float*>(B.own_x[s]);
+        char* t = dptr<char>(B.trace_d) + tr_slice * s;
+        S.tr = TraceDev{};
+        S.tr.f_half = reinterpret_cast<double*>(t);
+        S.tr.tv_half = S.tr.f_half + cap;
+        S.tr.alpha = S.tr.tv_half + cap;
+        S.tr.beta = S.tr.alpha + cap;
+        S.tr.s_norm = S.tr.beta + cap;
+        S.tr.ell = reinterpret_cast<int32_t*>(S.tr.s_norm + cap);
+        S.tr.cap = cap;
+        Scalars& q = sc[s];
+        q = Scalars{};
+        q.eps = sp->eps;
+        q.a = K ? tv->a : 0.5;
+        q.gamma = K ? tv->gamma : 0.0;
+        q.K = K;
+        q.max_trials = K ? (tv->max_trials > 0 ? tv->max_trials : 100) : 0;
+        q.max_iter = sp->max_iter;
+        q.first = 1;
+    }
+    hipStream_t st = c->stream;
+    HIP_TRY(c, hipMemcpyAsync(B.sl.ptr, B.hs.data(), sizeof(SliceDev) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipMemcpyAsync(B.scal.ptr, sc.data(), sizeof(Scalars) * (size_t)n, hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipStreamSynchronize(st));   // host arrays must outlive the copies
+    const SliceDev* sl = dptr<SliceDev>(B.sl);
+    const double mu = pc->mu, rho = pc->rho;
+
+    launch_init_b(st, sl, table(c, BS_VEC));                       // x_{1/2} = x_0
+    if ((sp->flags & SP_FLAG_AUTOTUNE) && !B.tuned && (rc = batch_tune(c, mu, rho))) return rc;
+    // Algorithm 3, steps 1-9, every slice in each launch
+    const ItemTable tprep = table(c, BS_PREP), tproj = table(c, BS_PROJECT),
+                    tbp = table(c, BS_BACKPROJECT), tvec = table(c, BS_VEC), ttv = table(c, BS_TV),
+                    tone = table(c, BS_SLICE, 0, 0);
+    launch_prep_b(st, sl, tprep, BV_XH);
+    launch_project_b(st, sl, tproj, true);
+    launch_scalar_b(st, sl, tone, OP_F0);
+    launch_backproject_b(st, sl, tbp, B.nbmax, false);
+    batch_precond(c, mu, rho);
+    launch_scalar_b(st, sl, tone, OP_BETA);
+    launch_update_p_b(st, sl, tvec);
+    launch_prep_b(st, sl, tprep, BV_P);
+    launch_project_b(st, sl, tproj, false);
+    launch_backproject_b(st, sl, tbp, B.nbmax, true);
+    launch_scalar_b(st, sl, tone, OP_ALPHA0);
+    launch_update_x_b(st, sl, tvec);
+    if ((rc = check_launch(c))) return rc;
+
+    // loop body (steps 11-14)
+    auto body = [&]() {
+        if (K > 0) {
+            for (int i = 0; i < K; ++i) {
+                const int src = i == 0 ? BV_X : BV_XH;
+                launch_tv_grad_b(st, sl, ttv, src);
+                launch_tv_trials_b(st, sl, ttv, src);
+                launch_tv_decide_b(st, sl, tone, src);
+                launch_tv_apply_b(st, sl, ttv, src, i == K - 1);
+            }
+            launch_scalar_b(st, sl, tone, OP_SNORM);
+        } else {
+            launch_copy_b(st, sl, tvec, BV_X, BV_XH);
+        }
+        launch_prep_b(st, sl, tprep, BV_XH);
+        launch_project_b(st, sl, tproj, true);
+        launch_scalar_b(st, sl, tone, OP_F);
+        launch_backproject_b(st, sl, tbp, B.nbmax, false);
+        batch_precond(c, mu, rho);
+        launch_scalar_b(st, sl, tone, OP_BETA);
+        launch_update_p_b(st, sl, tvec);
+        launch_prep_b(st, sl, tprep, BV_P);
+        launch_project_b(st, sl, tproj, false);
+        launch_backproject_b(st, sl, tbp, B.nbmax, true);
+        launch_scalar_b(st, sl, tone, OP_ALPHA);
+        launch_update_x_b(st, sl, tvec);
+    };
+    const bool poll = sp->eps > 0.0;
+    std::vector<Scalars> out(n);
+    auto all_halted = [&]() -> int {
+        HIP_TRY(c, hipMemcpyAsync(out.data(), B.scal.ptr, sizeof(Scalars) * (size_t)n,
+                                  hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        for (const Scalars& q : out)
+            if (!q.halt) return 0;
+        return 1;
+    };
+    if ((sp->flags & SP_FLAG_GRAPH) && sp->max_iter > 0) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        body();
+        hipError_t ec = hipStreamEndCapture(st, &graph);
+        if (ec != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            hipGraphDestroy(graph);
+            return fail(c, SP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        }
+        for (int it = 0; it < sp->max_iter; ++it) {
+            hipError_t el = hipGraphLaunch(exec, st);
+            if (el != hipSuccess) {
+                hipGraphExecDestroy(exec);
+                hipGraphDestroy(graph);
+                return fail(c, SP_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(el));
+            }
+            if (poll && (it & 7) == 7) {
+                const int h = all_halted();
+                if (h < 0 || h > 1) {
+                    hipGraphExecDestroy(exec);
+                    hipGraphDestroy(graph);
+                    return h;
+                }
+                if (h) break;
+            }
+        }
+        (void)hipStreamSynchronize(st);
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+    } else {
+        for (int it = 0; it < sp->max_iter; ++it) {
+            body();
+            if ((rc = check_launch(c))) return rc;
+            if (poll && (it & 7) == 7) {
+                const int h = all_halted();
+                if (h > 1) return h;
+                if (h) break;
+            }
+        }
+    }
+    HIP_TRY(c, hipMemcpyAsync(out.data(), B.scal.ptr, sizeof(Scalars) * (size_t)n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    int first_err = SP_OK;
+    std::vector<char> host;
+    if (trace) {
+        host.resize(tr_slice * (size_t)n);
+        HIP_TRY(c, hipMemcpyAsync(host.data(), B.trace_d.ptr, host.size(), hipMemcpyDeviceToHost, st));
+    }
+    for (int s = 0; s < n; ++s) {
+        const Scalars& q = out[s];
+        k_out[s] = q.k;
+        int status = SP_MAXITER;
+        if (q.halt) status = q.halt;
+        else if (q.exhausted) status = SP_TRIALS_EXHAUSTED;
+        if (q.halt == SP_BREAKDOWN_CONVERGED && q.k > 1)
+            HIP_TRY(c, hipMemcpyAsync(B.hs[s].x, B.hs[s].xh, (size_t)B.hs[s].n * 4, hipMemcpyDeviceToDevice, st));
+        if (status < 16 && first_err == SP_OK) {
+            first_err = status;
+            fail(c, status, "slice %d: non-finite value in a CG scalar", s);
+        }
+        if (trace && trace->status) trace->status[s] = status;
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (trace && trace->cap > 0) {
+        for (int s = 0; s < n; ++s) {
+            const char* t = host.data() + tr_slice * s;
+            const double* hf = reinterpret_cast<const double*>(t);
+            const double* htv = hf + cap;
+            const int32_t* hell = reinterpret_cast<const int32_t*>(htv + 4 * (size_t)cap);
+            const int done = std::min(std::min(trace->cap, cap), out[s].iter);
+            const size_t o = (size_t)s * trace->cap;
+            if (trace->f_half) std::copy(hf, hf + done, trace->f_half + o);
+            if (trace->tv_half) std::copy(htv, htv + done, trace->tv_half + o);
+            if (trace->ell) std::copy(hell, hell + done, trace->ell + o);
+        }
+    }
+    return first_err;
+}
+
+int sp_batch_tuning(sp_ctx* c, int32_t* out, int32_t count) {
+    if (!c) return SP_ERR_ARG;
+    if (!out || count < 2 * BS_SLICE) return fail(c, SP_ERR_ARG, "sp_batch_tuning: need 16 entries");
+    for (int s = 0; s < BS_SLICE; ++s) {
+        out[2 * s] = c->batch ? c->batch->order[s] : 0;
+        out[2 * s + 1] = c->batch ? c->batch->wpc[s] : 0;
+    }
+    return SP_OK;
 }
 
 }  // extern "C"

@@ -217,12 +217,14 @@ struct ItemTable {
 };
 
 // Runs fn(slice, virtual block) for the items of this workgroup; the barrier
-// after each item keeps LDS reuse ordered.
+// after each item keeps LDS reuse ordered.  ITEM_NONE entries pad the queues
+// of the XCD-grouped order and are skipped.
+constexpr uint32_t ITEM_NONE = 0xFFFFFFFFu;
 template <class Fn>
 __device__ __forceinline__ void for_items(const ItemTable& t, Fn&& fn) {
     for (int w = blockIdx.x; w < t.n; w += gridDim.x) {
         const uint32_t it = t.items[w];
-        fn((int)(it >> ITEM_SHIFT), (int)(it & ITEM_MASK));
+        if (it != ITEM_NONE) fn((int)(it >> ITEM_SHIFT), (int)(it & ITEM_MASK));
         __syncthreads();
     }
 }
