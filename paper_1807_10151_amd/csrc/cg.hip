@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void kb_copy(const SliceDev* __restrict__ sl, 
                                                int dst) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
+        if (gmem(S.sc)->halt) return;
         const float* a = batch_vec(S, src);
         float* d = batch_vec(S, dst);
         const int gx = vec_blocks_dev(S.n);
@@ -233,9 +233,9 @@ __global__ __launch_bounds__(256) void kb_init(const SliceDev* __restrict__ sl, 
         const SliceDev& S = sl[s];
         const int gx = vec_blocks_dev(S.n);
         for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) {
-            const float v = S.x0 ? S.x0[q] : 0.0f;
-            S.xh[q] = v;
-            S.x[q] = v;
+            const float v = S.x0 ? gmem(S.x0)[q] : 0.0f;
+            gmem(S.xh)[q] = v;
+            gmem(S.x)[q] = v;
         }
     });
 }
@@ -243,16 +243,17 @@ __global__ __launch_bounds__(256) void kb_init(const SliceDev* __restrict__ sl, 
 __global__ __launch_bounds__(256) void kb_update_p(const SliceDev* __restrict__ sl, ItemTable t) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        update_p_body(S.n, S.z, S.p, S.g, S.sc, S.pgp, lin, vec_blocks_dev(S.n));
+        if (gmem(S.sc)->halt) return;
+        update_p_body(S.n, gmem(S.z), gmem(S.p), gmem(S.g), gmem(S.sc), gmem(S.pgp), lin,
+                      vec_blocks_dev(S.n));
     });
 }
 
 __global__ __launch_bounds__(256) void kb_update_x(const SliceDev* __restrict__ sl, ItemTable t) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        update_x_body(S.n, S.xh, S.p, S.x, S.sc, lin, vec_blocks_dev(S.n));
+        if (gmem(S.sc)->halt) return;
+        update_x_body(S.n, gmem(S.xh), gmem(S.p), gmem(S.x), gmem(S.sc), lin, vec_blocks_dev(S.n));
     });
 }
 
@@ -261,31 +262,35 @@ __global__ __launch_bounds__(256) void kb_dot_zh(const SliceDev* __restrict__ sl
     __shared__ double red[4];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
+        if (gmem(S.sc)->halt) return;
         const int gx = vec_blocks_dev(S.n);
+        const float* g = gmem(S.g);
+        const float* h = gmem(S.h);
+        float* z = gmem(S.z);
         double acc = 0.0;
         for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) {
-            const float v = S.g[q];
-            S.z[q] = v;
-            acc += (double)v * (double)S.h[q];
+            const float v = g[q];
+            z[q] = v;
+            acc += (double)v * (double)h[q];
         }
         const double tot = block_sum(acc, red);
-        if (threadIdx.x == 0) S.pzh[lin] = tot;
+        if (threadIdx.x == 0) gmem(S.pzh)[lin] = tot;
     });
 }
 
 __global__ __launch_bounds__(256) void kb_scalar(const SliceDev* __restrict__ sl, ItemTable t, int op) {
     for_items(t, [&](int s, int) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
+        Scalars* sc = gmem(S.sc);
+        if (sc->halt) return;
         const TraceDev tr = S.tr;
         switch (op) {
         case OP_F0:
-        case OP_F: scalar_body(op, S.sc, tr, S.pf, S.nf, nullptr, 0); break;
-        case OP_BETA: scalar_body(op, S.sc, tr, S.pzh, S.nzh, nullptr, 0); break;
+        case OP_F: scalar_body(op, sc, tr, gmem(S.pf), S.nf, nullptr, 0); break;
+        case OP_BETA: scalar_body(op, sc, tr, gmem(S.pzh), S.nzh, nullptr, 0); break;
         case OP_ALPHA0:
-        case OP_ALPHA: scalar_body(op, S.sc, tr, S.pph, S.nph, S.pgp, S.ngp); break;
-        case OP_SNORM: scalar_body(op, S.sc, tr, S.pts, S.ntv, nullptr, 0); break;
+        case OP_ALPHA: scalar_body(op, sc, tr, gmem(S.pph), S.nph, gmem(S.pgp), S.ngp); break;
+        case OP_SNORM: scalar_body(op, sc, tr, gmem(S.pts), S.ntv, nullptr, 0); break;
         default: break;
         }
     });

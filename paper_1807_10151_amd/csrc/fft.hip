@@ -214,9 +214,11 @@ __global__ __launch_bounds__(256) void kb_rows_fwd(const SliceDev* __restrict__ 
     extern __shared__ double2 buf[];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        const FFTPlan F = S.F;
-        rows_fwd_body(F, S.g, buf, lin);
+        if (gmem(S.sc)->halt) return;
+        FFTPlan F = S.F;
+        F.S = gmem(F.S);
+        F.tw = cmem(F.tw);
+        rows_fwd_body(F, gmem(S.g), buf, lin);
     });
 }
 
@@ -225,8 +227,10 @@ __global__ __launch_bounds__(256) void kb_cols(const SliceDev* __restrict__ sl, 
     extern __shared__ double2 buf[];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        const FFTPlan F = S.F;
+        if (gmem(S.sc)->halt) return;
+        FFTPlan F = S.F;
+        F.S = gmem(F.S);
+        F.tw = cmem(F.tw);
         cols_body(F, mu, rho, buf, lin);
     });
 }
@@ -235,9 +239,11 @@ __global__ __launch_bounds__(256) void kb_rows_inv(const SliceDev* __restrict__ 
     extern __shared__ double2 buf[];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        const FFTPlan F = S.F;
-        rows_inv_body(F, S.z, S.h, S.pzh, buf, lin);
+        if (gmem(S.sc)->halt) return;
+        FFTPlan F = S.F;
+        F.S = gmem(F.S);
+        F.tw = cmem(F.tw);
+        rows_inv_body(F, gmem(S.z), gmem(S.h), gmem(S.pzh), buf, lin);
     });
 }
 

@@ -68,10 +68,10 @@ __global__ __launch_bounds__(256) void k_prep(GeomDev G, const float* __restrict
 __global__ __launch_bounds__(256) void kb_prep(const SliceDev* __restrict__ sl, ItemTable t, int which) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
+        if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = (G.cols + 31) / 32;
-        prep_body(G, batch_vec(S, which), S.xp, S.xTp, lin % gx, lin / gx);
+        prep_body(G, batch_vec(S, which), gmem(S.xp), gmem(S.xTp), lin % gx, lin / gx);
     });
 }
 
@@ -254,11 +254,12 @@ __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ s
                                                   int residual) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
+        if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = G.nA;
-        project_body(G, S.ang, S.xp, S.xTp, residual ? S.b : nullptr, S.rp + PAD, G.pitchB, 0,
-                     residual ? S.pf : nullptr, lin % gx, lin / gx, gx);
+        project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), residual ? gmem(S.b) : nullptr,
+                     gmem(S.rp) + PAD, G.pitchB, 0, residual ? gmem(S.pf) : nullptr, lin % gx,
+                     lin / gx, gx);
     });
 }
 
@@ -389,11 +390,12 @@ __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict
                                                       int normal) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
+        if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = (G.cols + BP_TILE - 1) / BP_TILE;
-        backproject_body<NB>(G, S.ang, S.rp, normal ? S.h : S.g, normal ? S.p : nullptr,
-                             normal ? S.pph : nullptr, lin % gx, lin / gx, gx);
+        backproject_body<NB>(G, cmem(S.ang), gmem(S.rp), gmem(normal ? S.h : S.g),
+                             normal ? gmem(S.p) : nullptr, normal ? gmem(S.pph) : nullptr,
+                             lin % gx, lin / gx, gx);
     });
 }
 

@@ -229,8 +229,21 @@ __device__ __forceinline__ void for_items(const ItemTable& t, Fn&& fn) {
     }
 }
 
+// Pointers read from a slice descriptor are generic (flat) to the compiler,
+// which would access them with flat instructions.  gmem re-types one as global
+// memory; cmem re-types a table that no kernel writes as constant memory, so
+// that wave-uniform reads of it become scalar loads.
+template <class T>
+__device__ __forceinline__ T* gmem(T* p) {
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+template <class T>
+__device__ __forceinline__ const T* cmem(const T* p) {
+    return (const T*)(__attribute__((address_space(4))) const T*)(uintptr_t)p;
+}
+
 __device__ __forceinline__ float* batch_vec(const SliceDev& S, int which) {
-    return which == BV_XH ? S.xh : (which == BV_X ? S.x : S.p);
+    return gmem(which == BV_XH ? S.xh : (which == BV_X ? S.x : S.p));
 }
 
 // projector.hip

@@ -356,26 +356,27 @@ void launch_tv_value(hipStream_t st, int rows, int cols, const float* y, double*
 __global__ __launch_bounds__(256) void kb_tv_grad(const SliceDev* __restrict__ sl, ItemTable t, int src) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        tv_grad_body(S.G.rows, S.G.cols, batch_vec(S, src), S.tb, S.ptg, lin);
+        if (gmem(S.sc)->halt) return;
+        tv_grad_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), lin);
     });
 }
 
 __global__ __launch_bounds__(256) void kb_tv_trials(const SliceDev* __restrict__ sl, ItemTable t, int src) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        tv_trials_body(S.G.rows, S.G.cols, batch_vec(S, src), S.tb, S.ptg, S.ntv, S.sc, S.ptt, lin);
+        if (gmem(S.sc)->halt) return;
+        tv_trials_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), S.ntv,
+                       gmem(S.sc), gmem(S.ptt), lin);
     });
 }
 
 __global__ __launch_bounds__(256) void kb_tv_decide(const SliceDev* __restrict__ sl, ItemTable t, int src) {
     for_items(t, [&](int s, int) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
+        if (gmem(S.sc)->halt) return;
         const TraceDev tr = S.tr;
-        tv_decide_body(S.G.rows, S.G.cols, batch_vec(S, src), S.tb, S.ptg, S.ntv, S.ptt, S.ntv,
-                       S.sc, tr, nullptr);
+        tv_decide_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), S.ntv,
+                       gmem(S.ptt), S.ntv, gmem(S.sc), tr, nullptr);
     });
 }
 
@@ -383,8 +384,9 @@ __global__ __launch_bounds__(256) void kb_tv_apply(const SliceDev* __restrict__ 
                                                    int snorm) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (S.sc->halt) return;
-        tv_apply_body(S.n, batch_vec(S, src), S.xh, S.tb, S.sc, snorm ? S.x : nullptr, S.pts, lin);
+        if (gmem(S.sc)->halt) return;
+        tv_apply_body(S.n, batch_vec(S, src), gmem(S.xh), gmem(S.tb), gmem(S.sc),
+                      snorm ? gmem(S.x) : nullptr, gmem(S.pts), lin);
     });
 }
 
