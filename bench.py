@@ -38,6 +38,10 @@ OPS_PER_NNZ = 4                  # offset fma, weight fma, clamp, accumulate fma
 TRAFFIC_BYTES = {"project": 20.53e6, "backproject": 18.73e6}
 
 
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,7 +50,73 @@ def parse():
     ap.add_argument("--reps", type=int, default=20, help="timed calls per operator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--eager", action="store_true", help="launch the loop eagerly, no graph")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched run")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the learned preconditioner and its time-to-target")
+    ap.add_argument("--batch-iters", type=int, default=20)
     return ap.parse_args()
+
+
+def batched_run(sp, torch, iters):
+    """64 mixed slices (sides 256..1024, 1.4 x side angles, ceil(side sqrt 2) + 1
+    bins) in one batched solve, against the same slices solved one by one."""
+    from synth import batched_slices, random_ellipses
+    work = batched_slices(64, seed=2)
+    geoms = [sp.Geometry(w.rows, w.cols, w.n_angles, w.n_bins) for w in work]
+    bs = []
+    for w, g in zip(work, geoms):
+        img, rng = random_ellipses(w.rows, w.cols, w.n_ellipses, w.seed)
+        x = torch.from_numpy(img.astype(np.float32)).cuda()
+        b = sp.sp_project(g, x)
+        noise = torch.from_numpy(rng.standard_normal(g.m).astype(np.float32)).cuda()
+        bs.append((b + w.noise_frac * float(b.max()) * noise.reshape(b.shape)).contiguous())
+    kw = dict(K=1, a=0.5, gamma=0.5, mu=1e-5, rho=0.8)
+    sp.sp_suppcg_solve_batched(geoms, bs, graph=True, autotune=True, max_iter=2, **kw)  # layout + tuning
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    res = sp.sp_suppcg_solve_batched(geoms, bs, graph=True, max_iter=iters, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    e0.record()
+    for g, b in zip(geoms, bs):
+        sp.sp_suppcg_solve(g, b, None, graph=True, max_iter=iters, trace=False, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1) / 1e3
+    return {"workload": "64 slices, sides {256,384,512,768,1024} (seed 2), 1.4 x side angles, "
+                        "ceil(side sqrt 2)+1 bins, SupPCG K=1, ramp-Hamming M",
+            "iterations": iters, "slice_iterations_per_s": round(64 * iters / t_batch, 2),
+            "one_by_one_slice_iterations_per_s": round(64 * iters / t_seq, 2),
+            "speedup_vs_one_by_one": round(t_seq / t_batch, 3),
+            "all_k": sorted(set(r.k for r in res)), "tuning": sp.batch_tuning()}
+
+
+def learned_run(sp):
+    """Train M = C^T diag(softplus(d)) C on the 64x64 / 90-angle geometry and
+    compare its time to the plain (Fourier M) run's f and TV at loop body 100."""
+    from paper_1807_10151_amd import learned_train as lt
+    g = sp.Geometry(64, 64, 90, 91)
+    cfg = lt.TrainConfig()
+    res = lt.train(g, cfg, log_every=500)
+    rows = lt.time_to_target(g, res.net, list(range(100, 132)), cfg, reps=1)
+    kf = [r["k_f"] for r in rows]
+    kb = [r["k_both"] for r in rows]
+    reached = [r for r in rows if r["k_both"] is not None]
+    return {"workload": "64x64, 90 angles, 91 bins, 5 ellipses, 1% noise; eval seeds 100-131",
+            "train_s": round(res.seconds, 3), "probe_s": round(res.probe_seconds, 3),
+            "loss_first_last": [round(res.losses[0][1], 5), round(res.losses[-1][1], 5)],
+            "plain_iterations": 100,
+            "learned_iterations_to_f_median": float(np.median([k if k else 10 ** 6 for k in kf])),
+            "learned_reached_f_and_tv_within_400": f"{len(reached)}/{len(rows)}",
+            "learned_iterations_to_both_median": (float(np.median([r["k_both"] for r in reached]))
+                                                  if reached else None),
+            "plain_ms_median": round(1e3 * float(np.median([r["plain_s"] for r in rows])), 3),
+            "learned_ms_to_both_median": (round(1e3 * float(np.median([r["learned_s"] for r in reached])), 3)
+                                          if reached else None),
+            "fallbacks": int(sum(r["fallbacks"] for r in rows))}
 
 
 def cpu_baseline(img, b):
@@ -184,7 +254,7 @@ def main():
     dom_ms = avg[dom_name]
     achieved = OPS_PER_NNZ * NNZ_CT512 / (dom_ms / 1e3)
     out = {
-        "metric": "SupPCG iterations/s at 512^2 x 720 angles x 725 bins",
+        "metric": "SupPCG iterations/s + R/R^T GB/s at 512\u00b2x720; time-to-target, learned vs plain",
         "value": round(value, 3),
         "unit": "iterations/s",
         "n_gpus": 1,
@@ -218,8 +288,16 @@ def main():
                   "f_last": float(res.trace["f_half"][-1]) if len(res.trace["f_half"]) else None,
                   "ell_last": int(res.trace["ell"][-1]) if len(res.trace["ell"]) else None},
     }
+    log("main solve done")
+    if not args.no_batch:
+        out["batched"] = batched_run(sp, torch, args.batch_iters)
+        log("batched run done")
+    if not args.no_learned:
+        out["time_to_target"] = learned_run(sp)
+        log("learned preconditioner trained and timed")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(img, b_np)
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
