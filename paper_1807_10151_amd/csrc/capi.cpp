@@ -28,6 +28,7 @@ struct BatchState {
     std::vector<sp_geometry> geoms;
     int kind = -1;
     int nbmax = 1;
+    int max_bins = 1;
     size_t lds_rows = 0, lds_cols = 0;
     std::vector<SliceDev> hs;        // host copies; per-call pointers filled in each call
     std::vector<char*> own_x;        // per slice: x_k storage used when x_last is NULL
@@ -51,7 +52,7 @@ struct sp_ctx {
     sp_geometry geom{};
     GeomDev G{};
     std::vector<AngleDev> ang_h;
-    DevBuf ang, xp, xTp, yp;
+    DevBuf ang, skp, xp, xTp, yp;
 
     // preconditioner cache
     int fftP = 0;
@@ -226,7 +227,7 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
         A.nc = (int)std::ceil(2.0 * hw);
         const double hb = (e + margin) / ds;
         A.nb = (int)std::ceil(2.0 * hb);
-        A.kb = -s0 / ds - hb;
+        A.kb = -s0 / ds - hb + 1.0 + PAD;
         A.row = a;
         A.flags = (axis ? ANG_AXIS : 0) | (horiz ? ANG_HORIZ : 0);
         if (A.nc < 2 || A.nc > 3 || A.nb < 1 || A.nb > 4)
@@ -251,6 +252,14 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
     return SP_OK;
 }
 
+// Bin positions of the padded bin range, t[PAD + k] = s_k for
+// k = -PAD .. n_bins + PAD - 1, with the fma the kernels use.
+std::vector<double> bin_sk_table(const GeomDev& G) {
+    std::vector<double> t((size_t)G.nB + 2 * PAD);
+    for (int k = -PAD; k < G.nB + PAD; ++k) t[(size_t)(k + PAD)] = std::fma((double)k, G.ds, G.s0);
+    return t;
+}
+
 int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     int rc = validate_geometry(c, g);
     if (rc) return rc;
@@ -265,8 +274,8 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     const bool relayout = !c->have_geom || c->G.pitchX != G.pitchX || c->G.pitchXT != G.pitchXT ||
                           c->G.pitchB != G.pitchB || c->G.rows != G.rows || c->G.cols != G.cols ||
                           c->G.nA != G.nA;
-    if ((rc = ensure(c, c->xp, nX * 4))) return rc;
-    if ((rc = ensure(c, c->xTp, nXT * 4))) return rc;
+    if ((rc = ensure(c, c->xp, nX * 8))) return rc;
+    if ((rc = ensure(c, c->xTp, nXT * 8))) return rc;
     if ((rc = ensure(c, c->yp, nY * 4))) return rc;
     if (relayout) {
         HIP_TRY(c, hipMemsetAsync(c->xp.ptr, 0, c->xp.bytes, c->stream));
@@ -274,6 +283,10 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
         HIP_TRY(c, hipMemsetAsync(c->yp.ptr, 0, c->yp.bytes, c->stream));
     }
     c->ang_h = tab;
+    const std::vector<double> skt = bin_sk_table(G);
+    if ((rc = ensure(c, c->skp, skt.size() * sizeof(double)))) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->skp.ptr, skt.data(), skt.size() * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->ang.ptr, tab.data(), tab.size() * sizeof(AngleDev),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));  // host table must outlive the copy
@@ -635,11 +648,12 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
     B.hs.assign(n, SliceDev{});
     B.own_x.assign(n, nullptr);
     B.nbmax = 1;
+    B.max_bins = 1;
     B.lds_rows = B.lds_cols = 0;
     std::vector<std::vector<AngleDev>> tabs(n);
     // sizes
     struct Off {
-        size_t ang, xp, xTp, rp, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
+        size_t ang, skp, xp, xTp, rp, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
     };
     std::vector<Off> off(n);
     size_t total = 0;
@@ -649,6 +663,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         if ((rc = build_geometry(c, &geoms[s], S.G, tabs[s]))) return fail(c, rc, "slice %d: %s", s, c->err.c_str());
         const GeomDev& G = S.G;
         B.nbmax = std::max(B.nbmax, G.nbmax);
+        B.max_bins = std::max(B.max_bins, G.nB);
         S.n = G.rows * G.cols;
         S.F = FFTPlan{};
         if (kind == SP_PRECOND_RAMP) {
@@ -675,8 +690,9 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
             return at;
         };
         o.ang = take(tabs[s].size() * sizeof(AngleDev));
-        o.xp = take((size_t)G.rows * G.pitchX * 4);
-        o.xTp = take((size_t)G.cols * G.pitchXT * 4);
+        o.skp = take(((size_t)G.nB + 2 * PAD) * sizeof(double));
+        o.xp = take((size_t)G.rows * G.pitchX * 8);
+        o.xTp = take((size_t)G.cols * G.pitchXT * 8);
         o.rp = take((size_t)G.nA * G.pitchB * 4);
         o.vec = take((size_t)S.n * 4 * 6);   // x, p, h, g, z, t_bar
         o.S = kind == SP_PRECOND_RAMP ? take((size_t)G.rows * S.F.SP * sizeof(double2)) : 0;
@@ -701,8 +717,13 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         SliceDev& S = B.hs[s];
         const Off& o = off[s];
         S.ang = reinterpret_cast<const AngleDev*>(base + o.ang);
-        S.xp = reinterpret_cast<float*>(base + o.xp);
-        S.xTp = reinterpret_cast<float*>(base + o.xTp);
+        S.skp = reinterpret_cast<const double*>(base + o.skp);
+        const std::vector<double> skt = bin_sk_table(S.G);
+        HIP_TRY(c, hipMemcpyAsync(base + o.skp, skt.data(), skt.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        S.xp = reinterpret_cast<double*>(base + o.xp);
+        S.xTp = reinterpret_cast<double*>(base + o.xTp);
         S.rp = reinterpret_cast<float*>(base + o.rp);
         float* v = reinterpret_cast<float*>(base + o.vec);
         B.own_x[s] = reinterpret_cast<char*>(v);
@@ -770,7 +791,7 @@ void batch_stage(sp_ctx* c, int stage, int order, int wpc, double mu, double rho
     switch (stage) {
     case BS_PREP: launch_prep_b(st, sl, t, BV_XH); break;
     case BS_PROJECT: launch_project_b(st, sl, t, true); break;
-    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, false); break;
+    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, B.max_bins, false); break;
     case BS_ROWS:
         launch_precond_b(st, sl, t, table(c, BS_COLS, order, wpc), B.lds_rows, B.lds_cols, mu, rho);
         break;
@@ -863,7 +884,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     if (!c) return SP_ERR_ARG;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ang, &c->xp, &c->xTp, &c->yp, &c->tw, &c->S, &c->vx, &c->vp, &c->vh,
+    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->tw, &c->S, &c->vx, &c->vp, &c->vh,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
                       &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
@@ -1071,11 +1092,11 @@ int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
     int rc = setup_geometry(c, g);
     if (rc) return rc;
     const GeomDev& G = c->G;
-    launch_prep(c->stream, G, x, dptr<float>(c->xp), dptr<float>(c->xTp), nullptr);
+    launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
     {
         ProfScope ps(c, SP_PROF_PROJECT);
-        launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->xp), dptr<float>(c->xTp),
-                       nullptr, y, G.nB, 0, nullptr, nullptr);
+        launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp),
+                       nullptr, y, G.nB, nullptr, nullptr, nullptr);
     }
     return check_launch(c);
 }
@@ -1090,8 +1111,8 @@ int sp_backproject(sp_ctx* c, const sp_geometry* g, const float* y, float* x) {
     launch_pad_sino(c->stream, G, y, dptr<float>(c->yp));
     {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
-        launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp), x, nullptr,
-                           nullptr, nullptr);
+        launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp),
+                           dptr<double>(c->skp), x, nullptr, nullptr, nullptr);
     }
     return check_launch(c);
 }
@@ -1104,11 +1125,9 @@ int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b,
     if (rc) return rc;
     if ((rc = ensure_partials(c))) return rc;
     const GeomDev& G = c->G;
-    launch_prep(c->stream, G, x, dptr<float>(c->xp), dptr<float>(c->xTp), nullptr);
-    float* out = r ? r : dptr<float>(c->yp) + PAD;
-    const int pitch = r ? G.nB : G.pitchB;
-    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->xp), dptr<float>(c->xTp), b, out,
-                   pitch, 0, dptr<double>(c->part_f), nullptr);
+    launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
+    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp), b, r,
+                   G.nB, nullptr, dptr<double>(c->part_f), nullptr);
     launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
     return check_launch(c);
 }
@@ -1268,9 +1287,10 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     float* h = dptr<float>(c->vh);
     float* gv = dptr<float>(c->vg);
     float* z = dptr<float>(c->vz);
-    float* xp = dptr<float>(c->xp);
-    float* xTp = dptr<float>(c->xTp);
+    double* xp = dptr<double>(c->xp);
+    double* xTp = dptr<double>(c->xTp);
     float* rp = dptr<float>(c->yp);
+    const double* skp = dptr<double>(c->skp);
     const AngleDev* ang = dptr<AngleDev>(c->ang);
     double* pf = dptr<double>(c->part_f);
     double* pzh = dptr<double>(c->part_zh);
@@ -1288,16 +1308,16 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
     // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
     launch_prep(st, G, xh, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, b, rp + PAD, G.pitchB, 0, pf, halt);
+    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, rp, pf, halt);
     launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
-    launch_backproject(st, G, ang, rp, gv, nullptr, nullptr, halt);
+    launch_backproject(st, G, ang, rp, skp, gv, nullptr, nullptr, halt);
     int nzh = 0;
     if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
     launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
     launch_update_p(st, n, z, p, gv, sc, pgp, halt);
     launch_prep(st, G, p, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, nullptr, rp + PAD, G.pitchB, 0, nullptr, halt);
-    launch_backproject(st, G, ang, rp, h, p, pph, halt);
+    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, halt);
+    launch_backproject(st, G, ang, rp, skp, h, p, pph, halt);
     launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
     launch_update_x(st, n, xh, p, x, sc, halt);
     if ((rc = check_launch(c))) return rc;
@@ -1308,11 +1328,11 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     // the body can be replayed from a captured graph.
     auto project = [&](const float* bb, double* parts) {
         ProfScope ps(c, SP_PROF_PROJECT);
-        launch_project(st, G, ang, xp, xTp, bb, rp + PAD, G.pitchB, 0, parts, halt);
+        launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, rp, parts, halt);
     };
     auto backproject = [&](float* out, const float* dotv, double* parts) {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
-        launch_backproject(st, G, ang, rp, out, dotv, parts, halt);
+        launch_backproject(st, G, ang, rp, skp, out, dotv, parts, halt);
     };
     auto body = [&]() -> int {
         ProfScope ps(c, SP_PROF_ITERATION);
@@ -1503,13 +1523,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     launch_prep_b(st, sl, tprep, BV_XH);
     launch_project_b(st, sl, tproj, true);
     launch_scalar_b(st, sl, tone, OP_F0);
-    launch_backproject_b(st, sl, tbp, B.nbmax, false);
+    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false);
     batch_precond(c, mu, rho);
     launch_scalar_b(st, sl, tone, OP_BETA);
     launch_update_p_b(st, sl, tvec);
     launch_prep_b(st, sl, tprep, BV_P);
     launch_project_b(st, sl, tproj, false);
-    launch_backproject_b(st, sl, tbp, B.nbmax, true);
+    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true);
     launch_scalar_b(st, sl, tone, OP_ALPHA0);
     launch_update_x_b(st, sl, tvec);
     if ((rc = check_launch(c))) return rc;
@@ -1531,13 +1551,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         launch_prep_b(st, sl, tprep, BV_XH);
         launch_project_b(st, sl, tproj, true);
         launch_scalar_b(st, sl, tone, OP_F);
-        launch_backproject_b(st, sl, tbp, B.nbmax, false);
+        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false);
         batch_precond(c, mu, rho);
         launch_scalar_b(st, sl, tone, OP_BETA);
         launch_update_p_b(st, sl, tvec);
         launch_prep_b(st, sl, tprep, BV_P);
         launch_project_b(st, sl, tproj, false);
-        launch_backproject_b(st, sl, tbp, B.nbmax, true);
+        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true);
         launch_scalar_b(st, sl, tone, OP_ALPHA);
         launch_update_x_b(st, sl, tvec);
     };

@@ -34,7 +34,7 @@ namespace sp {
 
 // 32 x 32 tile (bx, by): padded copy and padded transposed copy.
 __device__ __forceinline__ void prep_body(const GeomDev& G, const float* __restrict__ x,
-                                          float* __restrict__ xp, float* __restrict__ xTp, int bx,
+                                          double* __restrict__ xp, double* __restrict__ xTp, int bx,
                                           int by) {
     __shared__ float tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -45,7 +45,7 @@ __device__ __forceinline__ void prep_body(const GeomDev& G, const float* __restr
         float v = 0.0f;
         if (i < G.rows && j < G.cols) {
             v = x[(size_t)i * G.cols + j];
-            xp[(size_t)i * G.pitchX + PAD + j] = v;
+            xp[(size_t)i * G.pitchX + PAD + j] = (double)v;
         }
         tile[ty + r][tx] = v;
     }
@@ -54,12 +54,13 @@ __device__ __forceinline__ void prep_body(const GeomDev& G, const float* __restr
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int jj = bx * 32 + ty + r;
-        if (ii < G.rows && jj < G.cols) xTp[(size_t)jj * G.pitchXT + PAD + ii] = tile[tx][ty + r];
+        if (ii < G.rows && jj < G.cols)
+            xTp[(size_t)jj * G.pitchXT + PAD + ii] = (double)tile[tx][ty + r];
     }
 }
 
 __global__ __launch_bounds__(256) void k_prep(GeomDev G, const float* __restrict__ x,
-                                              float* __restrict__ xp, float* __restrict__ xTp,
+                                              double* __restrict__ xp, double* __restrict__ xTp,
                                               const int* __restrict__ halt) {
     if (halt && *halt) return;
     prep_body(G, x, xp, xTp, blockIdx.x, blockIdx.y);
@@ -79,7 +80,7 @@ void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which) {
     hipLaunchKernelGGL(kb_prep, dim3(t.grid), dim3(256), 0, st, sl, t, which);
 }
 
-void launch_prep(hipStream_t st, const GeomDev& G, const float* x, float* xp, float* xTp,
+void launch_prep(hipStream_t st, const GeomDev& G, const float* x, double* xp, double* xTp,
                  const int* halt) {
     dim3 grid((G.cols + 31) / 32, (G.rows + 31) / 32);
     hipLaunchKernelGGL(k_prep, grid, dim3(256), 0, st, G, x, xp, xTp, halt);
@@ -119,7 +120,7 @@ __device__ __forceinline__ void step_range(double base, double slope, double vlo
 // element PAD of row 0 of the padded copy.
 template <bool HORIZ, bool AXIS, int NC>
 __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, double sk,
-                                          const float* __restrict__ img, bool valid) {
+                                          const double* __restrict__ img, bool valid) {
     const int nmaj = HORIZ ? G.cols : G.rows;
     const int nmin = HORIZ ? G.rows : G.cols;
     const int pitch = HORIZ ? G.pitchXT : G.pitchX;
@@ -141,23 +142,23 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     // Candidate n of step m is minor index floor(nf_m) + 1 + q, clamped so that
     // the NC reads stay inside the padded row (clamped reads hit zero pads).
     // Offsets are kept relative to the start of the padded row (>= 0).
-    const float* row = img - PAD;
+    const double* row = img - PAD;
     // minor coordinate of candidate 0 = floor(nf) + c1 (exact: small half-integers)
     const double c1 = HORIZ ? G.yoff - 1.0 : 1.0 - G.xoff;
     const double dM = HORIZ ? 1.0 : -1.0;                     // major coordinate step
     double cM = HORIZ ? (double)lo - G.xoff : G.yoff - (double)lo;
     double nf = fma((double)lo, A.slope, start);
     const int omax = nmin + 2 * PAD - NC;
-    const float* rp = row + (size_t)lo * pitch;
+    const double* rp = row + (size_t)lo * pitch;
     // one major step: gather is issued by the caller, weights and sum here
-    auto step = [&](const float* v, double nfl, double cMv) {
+    auto step = [&](const double* v, double nfl, double cMv) {
         const double P = cMv * fM;
         const double cm0 = HORIZ ? c1 - nfl : nfl + c1;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const double cm = HORIZ ? cm0 - (double)q : cm0 + (double)q;
             const double d = sk - fma(cm, fm, P);
-            acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[q], acc);
+            acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), v[q], acc);
         }
     };
     int m = lo;
@@ -165,9 +166,9 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     for (; m + 1 < hi; m += 2) {
         const double nfl0 = floor(nf);
         const double nfl1 = floor(nf + A.slope);
-        const float* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
-        const float* p1 = rp + pitch + min(max((int)nfl1 + 1 + PAD, 0), omax);
-        float v0[NC], v1[NC];
+        const double* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
+        const double* p1 = rp + pitch + min(max((int)nfl1 + 1 + PAD, 0), omax);
+        double v0[NC], v1[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
 #pragma unroll
@@ -180,8 +181,8 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     }
     if (m < hi) {
         const double nfl0 = floor(nf);
-        const float* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
-        float v0[NC];
+        const double* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
+        double v0[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
         step(v0, nfl0, cM);
@@ -191,19 +192,21 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
 
 template <bool HORIZ, bool AXIS>
 __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A, double sk,
-                                             const float* __restrict__ img, bool valid) {
+                                             const double* __restrict__ img, bool valid) {
     return A.nc == 3 ? ray_sum<HORIZ, AXIS, 3>(G, A, sk, img, valid)
                      : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, valid);
 }
 
-// out[row*out_pitch + out_pad + k] = (R x)_{row,k}, or the residual (R x - b)
-// with its float64 squared norm per workgroup in partials when b != nullptr.
-// Block bx indexes the class-sorted angle table, by the 256-bin chunk.
+// (R x)_{row,k}, or the residual (R x - b) with its float64 squared norm per
+// workgroup in partials when b != nullptr, rounded to float32 and stored to
+// out[row*out_pitch + k] (nullable) and to the padded sinogram
+// outp[row*pitchB + PAD + k] (nullable).  Block bx indexes the class-sorted
+// angle table, by the 256-bin chunk.
 __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* __restrict__ ang,
-                                             const float* __restrict__ xp,
-                                             const float* __restrict__ xTp,
+                                             const double* __restrict__ xp,
+                                             const double* __restrict__ xTp,
                                              const float* __restrict__ b, float* __restrict__ out,
-                                             int out_pitch, int out_pad,
+                                             int out_pitch, float* __restrict__ outp,
                                              double* __restrict__ partials, int bx, int by, int gx) {
     __shared__ double red[4];
     const AngleDev A = ang[bx];
@@ -229,7 +232,8 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
         } else {
             val = (float)(acc * G.pixel);
         }
-        out[(size_t)a * out_pitch + out_pad + k] = val;
+        if (out) out[(size_t)a * out_pitch + k] = val;
+        if (outp) outp[(size_t)a * G.pitchB + PAD + k] = val;
     }
     if (b) {
         const double tot = block_sum(r2, red);
@@ -238,14 +242,15 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
 }
 
 __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
-                                                 const float* __restrict__ xp,
-                                                 const float* __restrict__ xTp,
+                                                 const double* __restrict__ xp,
+                                                 const double* __restrict__ xTp,
                                                  const float* __restrict__ b,
                                                  float* __restrict__ out, int out_pitch,
-                                                 int out_pad, double* __restrict__ partials,
+                                                 float* __restrict__ outp,
+                                                 double* __restrict__ partials,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, out_pad, partials, blockIdx.x, blockIdx.y,
+    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, partials, blockIdx.x, blockIdx.y,
                  gridDim.x);
 }
 
@@ -258,8 +263,8 @@ __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ s
         const GeomDev G = S.G;
         const int gx = G.nA;
         project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), residual ? gmem(S.b) : nullptr,
-                     gmem(S.rp) + PAD, G.pitchB, 0, residual ? gmem(S.pf) : nullptr, lin % gx,
-                     lin / gx, gx);
+                     nullptr, 0, gmem(S.rp), residual ? gmem(S.pf) : nullptr, lin % gx, lin / gx,
+                     gx);
     });
 }
 
@@ -269,12 +274,12 @@ void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, bool resi
 
 int project_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
 
-void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* xp,
-                    const float* xTp, const float* b, float* out, int out_pitch, int out_pad,
+void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
+                    const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* partials, const int* halt) {
     dim3 grid(G.nA, (G.nB + 255) / 256);
     hipLaunchKernelGGL(k_project, grid, dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
-                       out_pad, partials, halt);
+                       outp, partials, halt);
 }
 
 __global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const float* __restrict__ y,
@@ -290,26 +295,39 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp
 
 // Sum over the angles [beg, end) of one class for pixel (xj, yi).  The angle
 // and its sinogram row are wave-uniform (scalar loads); lanes differ only in
-// the pixel.
-template <bool HORIZ, bool AXIS, int NB>
+// the pixel.  sk[PAD + k] = s_k = bin_pos(k) for the padded bin range (the
+// float64 values the projector computes per ray), read from LDS (LSK) or from
+// global memory, so a candidate's offset d is one subtraction.
+//
+// Candidate window: bins floor(kf) + 1 .. floor(kf) + NB, kf = t / ds + kb
+// (A.kb also carries the + 1 + PAD of the padded index).  Truncation equals
+// floor for kf >= 0; a negative kf truncates to a value that, read as
+// unsigned, is either 0 or huge, and the clamp to kmax then points at zero
+// pads -- in both cases every true candidate lies outside the detector.  A
+// candidate that reads a pad gets a weight evaluated at the pad's position and
+// multiplies 0.
+template <bool HORIZ, bool AXIS, int NB, bool LSK>
 __device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
                                            int beg, int end, const float* __restrict__ yp,
+                                           const double* __restrict__ skg, const double* sks,
                                            double xj, double yi, double acc) {
-    const int kmax = G.nB + 2 * PAD - NB;        // last padded start index
+    const unsigned kmax = (unsigned)(G.nB + 2 * PAD - NB);   // last padded start index
 #pragma unroll 2
     for (int a = beg; a < end; ++a) {
         const AngleDev A = ang[a];
         const double t = HORIZ ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
-        const double kfl = floor(fma(t, G.inv_ds, A.kb));
-        // padded index of candidate bin floor(kf) + 1, clamped into the zero pads
-        const unsigned o = (unsigned)min(max((int)kfl + 1 + PAD, 0), kmax);
-        const float* pr = yp + (size_t)A.row * G.pitchB;
+        const unsigned o = min((unsigned)(int)fma(t, G.inv_ds, A.kb), kmax);
+        const float* pv = yp + (size_t)A.row * G.pitchB + o;
+        const double* ps = LSK ? sks + o : skg + o;
         float v[NB];
+        double sk[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) v[q] = pr[o + q];
+        for (int q = 0; q < NB; ++q) v[q] = pv[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) sk[q] = ps[q];
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const double d = bin_pos(kfl + (double)(1 + q), G) - t;
+            const double d = sk[q] - t;
             acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[q], acc);
         }
     }
@@ -318,6 +336,8 @@ __device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __r
 
 constexpr int BP_TILE = 8;      // 8 x 8 pixels per wave
 constexpr int BP_SPLIT = 4;     // waves per workgroup, each over a quarter of the angles
+// The bin-position table goes to LDS when it takes at most this many bytes.
+constexpr size_t BP_LDS_SK_MAX = 24 * 1024;
 
 __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int& e) {
     const int len = end - beg;
@@ -328,16 +348,22 @@ __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int
 // out[i][j] = (R^T y)_{ij} from the padded sinogram yp; with dotv != nullptr
 // also the float64 partial sum of out * dotv per workgroup.  A workgroup owns
 // an 8 x 8 pixel tile; its wave w sums the w-th quarter of every angle class,
-// and the four partial sums are added in wave order through LDS.
-template <int NB>
+// and the four partial sums are added in wave order through LDS.  With LSK the
+// workgroup first writes the bin-position table into the dynamic LDS `sks`.
+template <int NB, bool LSK>
 __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDev* __restrict__ ang,
                                                  const float* __restrict__ yp,
+                                                 const double* __restrict__ skg, double* sks,
                                                  float* __restrict__ out,
                                                  const float* __restrict__ dotv,
                                                  double* __restrict__ partials, int bx, int by,
                                                  int gx) {
     __shared__ double part[BP_SPLIT][64];
     __shared__ double red[4];
+    if (LSK) {
+        for (int k = threadIdx.x; k < G.nB + 2 * PAD; k += 256) sks[k] = bin_pos((double)(k - PAD), G);
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = by * BP_TILE + (lane >> 3);
@@ -347,13 +373,13 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     double acc = 0.0;
     int b, e;
     split_range(G.cls[0], G.cls[1], w, b, e);
-    acc = bp_class<false, false, NB>(G, ang, b, e, yp, xj, yi, acc);
+    acc = bp_class<false, false, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[1], G.cls[2], w, b, e);
-    acc = bp_class<true, false, NB>(G, ang, b, e, yp, xj, yi, acc);
+    acc = bp_class<true, false, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[2], G.cls[3], w, b, e);
-    acc = bp_class<false, true, NB>(G, ang, b, e, yp, xj, yi, acc);
+    acc = bp_class<false, true, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[3], G.cls[4], w, b, e);
-    acc = bp_class<true, true, NB>(G, ang, b, e, yp, xj, yi, acc);
+    acc = bp_class<true, true, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     part[w][lane] = acc;
     __syncthreads();
     double v = 0.0;
@@ -372,56 +398,82 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     }
 }
 
-template <int NB>
+template <int NB, bool LSK>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
                                                      const float* __restrict__ yp,
+                                                     const double* __restrict__ skg,
                                                      float* __restrict__ out,
                                                      const float* __restrict__ dotv,
                                                      double* __restrict__ partials,
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
-    backproject_body<NB>(G, ang, yp, out, dotv, partials, blockIdx.x, blockIdx.y, gridDim.x);
+    extern __shared__ double sks[];
+    backproject_body<NB, LSK>(G, ang, yp, skg, sks, out, dotv, partials, blockIdx.x, blockIdx.y,
+                              gridDim.x);
 }
 
 // normal: h = R^T rp with the partials of h^T p; else g = R^T rp.  NB is the
 // largest candidate count of the batch (extra candidates weigh exactly 0).
-template <int NB>
+template <int NB, bool LSK>
 __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, ItemTable t,
                                                       int normal) {
+    extern __shared__ double sks[];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = (G.cols + BP_TILE - 1) / BP_TILE;
-        backproject_body<NB>(G, cmem(S.ang), gmem(S.rp), gmem(normal ? S.h : S.g),
-                             normal ? gmem(S.p) : nullptr, normal ? gmem(S.pph) : nullptr,
-                             lin % gx, lin / gx, gx);
+        backproject_body<NB, LSK>(G, cmem(S.ang), gmem(S.rp), gmem(S.skp), sks,
+                                  gmem(normal ? S.h : S.g), normal ? gmem(S.p) : nullptr,
+                                  normal ? gmem(S.pph) : nullptr, lin % gx, lin / gx, gx);
     });
 }
 
-void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal) {
-    const int nm = normal ? 1 : 0;
+size_t bp_lds_bytes(int nbins) {
+    const size_t b = ((size_t)nbins + 2 * PAD) * sizeof(double);
+    return b <= BP_LDS_SK_MAX ? b : 0;
+}
+
+template <bool LSK>
+void launch_bp_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int nm, size_t lds) {
     switch (nbmax) {
-    case 1: hipLaunchKernelGGL(kb_backproject<1>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
-    case 2: hipLaunchKernelGGL(kb_backproject<2>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
-    case 3: hipLaunchKernelGGL(kb_backproject<3>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
-    default: hipLaunchKernelGGL(kb_backproject<4>, dim3(t.grid), dim3(256), 0, st, sl, t, nm); break;
+    case 1: hipLaunchKernelGGL((kb_backproject<1, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
+    case 2: hipLaunchKernelGGL((kb_backproject<2, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
+    case 3: hipLaunchKernelGGL((kb_backproject<3, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
+    default: hipLaunchKernelGGL((kb_backproject<4, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
     }
+}
+
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
+                          bool normal) {
+    const size_t lds = bp_lds_bytes(max_bins);
+    if (lds) launch_bp_b<true>(st, sl, t, nbmax, normal ? 1 : 0, lds);
+    else launch_bp_b<false>(st, sl, t, nbmax, normal ? 1 : 0, 0);
 }
 
 int backproject_blocks(const GeomDev& G) {
     return ((G.cols + BP_TILE - 1) / BP_TILE) * ((G.rows + BP_TILE - 1) / BP_TILE);
 }
 
-void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
-                        float* out, const float* dotv, double* partials, const int* halt) {
+template <bool LSK>
+void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
+               const double* skp, float* out, const float* dotv, double* partials, const int* halt,
+               size_t lds) {
     dim3 grid((G.cols + BP_TILE - 1) / BP_TILE, (G.rows + BP_TILE - 1) / BP_TILE);
     switch (G.nbmax) {
-    case 1: hipLaunchKernelGGL(k_backproject<1>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
-    case 2: hipLaunchKernelGGL(k_backproject<2>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
-    case 3: hipLaunchKernelGGL(k_backproject<3>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
-    default: hipLaunchKernelGGL(k_backproject<4>, grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, halt); break;
+    case 1: hipLaunchKernelGGL((k_backproject<1, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    case 2: hipLaunchKernelGGL((k_backproject<2, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    case 3: hipLaunchKernelGGL((k_backproject<3, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    default: hipLaunchKernelGGL((k_backproject<4, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
     }
+}
+
+void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
+                        const double* skp, float* out, const float* dotv, double* partials,
+                        const int* halt) {
+    const size_t lds = bp_lds_bytes(G.nB);
+    if (lds) launch_bp<true>(st, G, ang, yp, skp, out, dotv, partials, halt, lds);
+    else launch_bp<false>(st, G, ang, yp, skp, out, dotv, partials, halt, 0);
 }
 
 }  // namespace sp

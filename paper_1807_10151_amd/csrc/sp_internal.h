@@ -25,7 +25,7 @@ struct alignas(16) AngleDev {
     double inv;       // 1 / (|c| |s|)   (0 for axis-parallel angles)
     double wmax;      // 1 / max(|c|, |s|)
     double slope;     // forward walk: minor index per major step (selection only)
-    double kb;        // backprojection: -s0/ds - hb, hb = e/ds + margin (selection only)
+    double kb;        // backprojection: -s0/ds - hb + 1 + PAD, hb = e/ds + margin (selection only)
     float hw;         // forward walk: half-width of the nonzero band on the minor axis + margin
     int32_t row;      // sinogram row of this angle (the table is sorted by class)
     int32_t flags;    // bit0 axis-parallel, bit1 walk columns (|s| > |c|)
@@ -110,15 +110,22 @@ __device__ __forceinline__ double bin_pos(double k, const GeomDev& G) { return f
 
 // ---- kernel launchers (all enqueue on `st`) ----------------------------------
 // projector.hip
-void launch_prep(hipStream_t st, const GeomDev& G, const float* x, float* xp, float* xTp,
+// The padded copies of the image (xp, xTp) are float64 widenings of the
+// float32 image: the forward gathers then feed the float64 FMAs without a
+// conversion per candidate.  The padded sinogram (yp) stays float32.
+void launch_prep(hipStream_t st, const GeomDev& G, const float* x, double* xp, double* xTp,
                  const int* halt);
-void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* xp,
-                    const float* xTp, const float* b, float* out, int out_pitch, int out_pad,
+void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
+                    const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* partials, const int* halt);
 int project_blocks(const GeomDev& G);
 void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp);
+// skp: float64 bin positions of the padded bin range, skp[PAD + k] = s_k
+// (bin_sk_table fills it on the host with the same fma as bin_pos); used when
+// the table is too large for the backprojector's LDS copy.
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
-                        float* out, const float* dotv, double* partials, const int* halt);
+                        const double* skp, float* out, const float* dotv, double* partials,
+                        const int* halt);
 int backproject_blocks(const GeomDev& G);
 
 // fft.hip
@@ -196,9 +203,12 @@ struct SliceDev {
     GeomDev G;
     FFTPlan F;
     const AngleDev* ang;
+    const double* skp;  // padded bin positions
     const float* b;
     const float* x0;   // nullable: zero start
-    float *xh, *x, *p, *h, *g, *z, *tb, *xp, *xTp, *rp;
+    float *xh, *x, *p, *h, *g, *z, *tb;
+    double *xp, *xTp;   // float64 padded copies
+    float* rp;          // padded sinogram
     double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
     Scalars* sc;
     TraceDev tr;
@@ -249,7 +259,8 @@ __device__ __forceinline__ float* batch_vec(const SliceDev& S, int which) {
 // projector.hip
 void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which);
 void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, bool residual);
-void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal);
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
+                          bool normal);
 // fft.hip (z = M g; with the partials of z^T h into pzh)
 void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTable cols,
                       size_t lds_rows, size_t lds_cols, double mu, double rho);
