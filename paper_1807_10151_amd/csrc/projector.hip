@@ -116,6 +116,13 @@ __device__ __forceinline__ void step_range(double base, double slope, double vlo
     if (hi < lo) hi = lo;
 }
 
+// base + o for a wave-uniform base and a 32-bit element index: the byte offset
+// is formed in 32 bits so the load can use the scalar-base addressing form.
+template <class T>
+__device__ __forceinline__ const T* at(const T* base, unsigned o) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + o * (unsigned)sizeof(T));
+}
+
 // One ray's sum.  HORIZ = walk columns of the transposed copy.  img points at
 // element PAD of row 0 of the padded copy.
 template <bool HORIZ, bool AXIS, int NC>
@@ -139,21 +146,26 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
     double acc = 0.0;
     if (lo >= hi) return acc;
-    // Candidate n of step m is minor index floor(nf_m) + 1 + q, clamped so that
-    // the NC reads stay inside the padded row (clamped reads hit zero pads).
-    // Offsets are kept relative to the start of the padded row (>= 0).
+    // Candidate q of step m is minor index floor(nf_m) + 1 + q.  nf carries the
+    // + 1 + PAD of the padded index, so the first candidate's padded index is
+    // trunc(nf) where nf >= 0.  A negative value (read as unsigned) or one past
+    // the row is clamped to omax: every read of that step then hits zero pads
+    // and, as all true candidates lie outside the image, the step contributes
+    // exactly 0.  The minor coordinate of candidate q is taken from the index
+    // actually read -- (o + q - PAD) - xoff for columns, yoff - (o + q - PAD)
+    // for rows, exact small half-integers -- which is the candidate's own
+    // coordinate whenever the read is not clamped.
     const double* row = img - PAD;
-    // minor coordinate of candidate 0 = floor(nf) + c1 (exact: small half-integers)
-    const double c1 = HORIZ ? G.yoff - 1.0 : 1.0 - G.xoff;
+    const double c2 = HORIZ ? G.yoff + (double)PAD : -(double)PAD - G.xoff;
     const double dM = HORIZ ? 1.0 : -1.0;                     // major coordinate step
     double cM = HORIZ ? (double)lo - G.xoff : G.yoff - (double)lo;
-    double nf = fma((double)lo, A.slope, start);
-    const int omax = nmin + 2 * PAD - NC;
+    double nf = fma((double)lo, A.slope, start + (double)(1 + PAD));
+    const unsigned omax = (unsigned)(nmin + 2 * PAD - NC);
     const double* rp = row + (size_t)lo * pitch;
     // one major step: gather is issued by the caller, weights and sum here
-    auto step = [&](const double* v, double nfl, double cMv) {
+    auto step = [&](const double* v, unsigned o, double cMv) {
         const double P = cMv * fM;
-        const double cm0 = HORIZ ? c1 - nfl : nfl + c1;
+        const double cm0 = HORIZ ? c2 - (double)o : (double)o + c2;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const double cm = HORIZ ? cm0 - (double)q : cm0 + (double)q;
@@ -164,28 +176,28 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     int m = lo;
     // two steps per iteration: both gathers are in flight before either step's math
     for (; m + 1 < hi; m += 2) {
-        const double nfl0 = floor(nf);
-        const double nfl1 = floor(nf + A.slope);
-        const double* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
-        const double* p1 = rp + pitch + min(max((int)nfl1 + 1 + PAD, 0), omax);
+        const unsigned o0 = min((unsigned)(int)nf, omax);
+        const unsigned o1 = min((unsigned)(int)(nf + A.slope), omax);
+        const double* p0 = at(rp, o0);
+        const double* p1 = at(rp + pitch, o1);
         double v0[NC], v1[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v1[q] = p1[q];
-        step(v0, nfl0, cM);
-        step(v1, nfl1, cM + dM);
+        step(v0, o0, cM);
+        step(v1, o1, cM + dM);
         nf += 2.0 * A.slope;
         cM += 2.0 * dM;
         rp += 2 * pitch;
     }
     if (m < hi) {
-        const double nfl0 = floor(nf);
-        const double* p0 = rp + min(max((int)nfl0 + 1 + PAD, 0), omax);
+        const unsigned o0 = min((unsigned)(int)nf, omax);
+        const double* p0 = at(rp, o0);
         double v0[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
-        step(v0, nfl0, cM);
+        step(v0, o0, cM);
     }
     return acc;
 }
@@ -317,7 +329,7 @@ __device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __r
         const AngleDev A = ang[a];
         const double t = HORIZ ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
         const unsigned o = min((unsigned)(int)fma(t, G.inv_ds, A.kb), kmax);
-        const float* pv = yp + (size_t)A.row * G.pitchB + o;
+        const float* pv = at(yp + (size_t)A.row * G.pitchB, o);
         const double* ps = LSK ? sks + o : skg + o;
         float v[NB];
         double sk[NB];
