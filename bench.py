@@ -35,7 +35,7 @@ OPS_PER_NNZ = 4                  # offset fma, weight fma, clamp, accumulate fma
 # kernels at this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE averages scaled
 # by the counts of a 64 MiB device copy (profiles/counters_ct512.md).  They are
 # tied to the kernels as profiled; re-measure after changing them.
-TRAFFIC_BYTES = {"project": 20.53e6, "backproject": 18.73e6}
+TRAFFIC_BYTES = {"project": 40.73e6, "backproject": 18.72e6}
 
 
 def log(msg):

@@ -1368,32 +1368,37 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         int brc = body();
         hipError_t ec = hipStreamEndCapture(st, &graph);
         if (brc) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return brc;
         }
         if (ec != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
         hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (ei != hipSuccess) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             return fail(c, SP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
         }
         int32_t hh = 0;
         for (int it = 0; it < sp->max_iter; ++it) {
             hipError_t el = hipGraphLaunch(exec, st);
             if (el != hipSuccess) {
-                hipGraphExecDestroy(exec);
-                hipGraphDestroy(graph);
+                (void)hipGraphExecDestroy(exec);
+                (void)hipGraphDestroy(graph);
                 return fail(c, SP_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(el));
             }
             if (poll && (it & 7) == 7) {
-                hipMemcpyAsync(&hh, &sc->halt, 4, hipMemcpyDeviceToHost, st);
-                hipStreamSynchronize(st);
+                if (hipMemcpyAsync(&hh, &sc->halt, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess) {
+                    (void)hipGraphExecDestroy(exec);
+                    (void)hipGraphDestroy(graph);
+                    return fail(c, SP_ERR_HIP, "polling the halt flag failed");
+                }
                 if (hh) break;
             }
         }
-        hipStreamSynchronize(st);
-        hipGraphExecDestroy(exec);
-        hipGraphDestroy(graph);
+        const hipError_t es = hipStreamSynchronize(st);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (es != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
     } else {
         int32_t hh = 0;
         for (int it = 0; it < sp->max_iter; ++it) {
@@ -1580,29 +1585,29 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         if (ec != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
         hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (ei != hipSuccess) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             return fail(c, SP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
         }
         for (int it = 0; it < sp->max_iter; ++it) {
             hipError_t el = hipGraphLaunch(exec, st);
             if (el != hipSuccess) {
-                hipGraphExecDestroy(exec);
-                hipGraphDestroy(graph);
+                (void)hipGraphExecDestroy(exec);
+                (void)hipGraphDestroy(graph);
                 return fail(c, SP_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(el));
             }
             if (poll && (it & 7) == 7) {
                 const int h = all_halted();
                 if (h < 0 || h > 1) {
-                    hipGraphExecDestroy(exec);
-                    hipGraphDestroy(graph);
+                    (void)hipGraphExecDestroy(exec);
+                    (void)hipGraphDestroy(graph);
                     return h;
                 }
                 if (h) break;
             }
         }
         (void)hipStreamSynchronize(st);
-        hipGraphExecDestroy(exec);
-        hipGraphDestroy(graph);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
     } else {
         for (int it = 0; it < sp->max_iter; ++it) {
             body();

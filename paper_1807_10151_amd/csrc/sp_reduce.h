@@ -25,10 +25,20 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 }
 
 // Sums `np` partials in a fixed order with one workgroup: thread t adds
-// entries t, t+256, ...; then block_sum.  Every thread gets the result.
+// entries t, t+256, ... in that order; then block_sum.  Every thread gets the
+// result.  Eight loads are issued before their adds so that one memory
+// latency covers them (the order of the additions is unchanged).
 __device__ __forceinline__ double reduce_partials(const double* p, int np, double* lds) {
     double v = 0.0;
-    for (int q = threadIdx.x; q < np; q += 256) v += p[q];
+    int q = threadIdx.x;
+    for (; q + 7 * 256 < np; q += 8 * 256) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = p[q + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += a[u];
+    }
+    for (; q < np; q += 256) v += p[q];
     return block_sum(v, lds);
 }
 
