@@ -24,6 +24,25 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     return ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
+// N independent block sums with one pair of barriers: v[i] becomes exactly
+// block_sum(v[i]) (same lane butterfly, same wave order) in every thread.
+// `lds` must hold 4 * N doubles.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double* v, double* lds) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[w * N + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = ((lds[i] + lds[N + i]) + lds[2 * N + i]) + lds[3 * N + i];
+}
+
 // Sums `np` partials in a fixed order with one workgroup: thread t adds
 // entries t, t+256, ... in that order; then block_sum.  Every thread gets the
 // result.  Eight loads are issued before their adds so that one memory

@@ -127,10 +127,11 @@ __device__ __forceinline__ void tv_trials_body(int rows, int cols, const float* 
         const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
         if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam_r, TVJ, acc);
     }
+    __shared__ double redn[4 * (TVJ + 1)];
+    block_sum_n<TVJ + 1>(acc, redn);
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q <= TVJ; ++q) {
-        const double tot = block_sum(acc[q], red);
-        if (threadIdx.x == 0) tpart[(size_t)bx * (TVJ + 1) + q] = tot;
+        for (int q = 0; q <= TVJ; ++q) tpart[(size_t)bx * (TVJ + 1) + q] = acc[q];
     }
 }
 
@@ -164,9 +165,11 @@ __device__ void tv_trials_wg(const float* __restrict__ y, const float* __restric
         const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
         if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam, nq, acc);
     }
-    for (int q = 0; q <= TVJ; ++q) {
-        const double tot = block_sum(acc[q], red);
-        if (threadIdx.x == 0) out[q] = tot;
+    __shared__ double redn[4 * (TVJ + 1)];
+    (void)red;
+    block_sum_n<TVJ + 1>(acc, redn);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q <= TVJ; ++q) out[q] = acc[q];
     }
     __syncthreads();
 }
@@ -183,11 +186,22 @@ __device__ __forceinline__ void tv_decide_body(int rows, int cols, const float* 
     __shared__ int chosen_s;
     __shared__ double tvc_s;
     const double tn = sqrt(reduce_partials(gpart, ngpart, red));
-    for (int q = 0; q <= TVJ; ++q) {
-        double v = 0.0;
-        for (int bidx = threadIdx.x; bidx < ntpart; bidx += 256) v += tpart[(size_t)bidx * (TVJ + 1) + q];
-        const double tot = block_sum(v, red);
-        if (threadIdx.x == 0) tv[q] = tot;
+    {
+        // per q, thread t adds entries t, t+256, ... in order (the q's interleaved)
+        double v[TVJ + 1];
+#pragma unroll
+        for (int q = 0; q <= TVJ; ++q) v[q] = 0.0;
+        for (int bidx = threadIdx.x; bidx < ntpart; bidx += 256) {
+            const double* row = tpart + (size_t)bidx * (TVJ + 1);
+#pragma unroll
+            for (int q = 0; q <= TVJ; ++q) v[q] += row[q];
+        }
+        __shared__ double redn[4 * (TVJ + 1)];
+        block_sum_n<TVJ + 1>(v, redn);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q <= TVJ; ++q) tv[q] = v[q];
+        }
     }
     __syncthreads();
     const int max_trials = sc->max_trials;
