@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = dict(name="ct512", rows=512, cols=512, n_angles=720, n_bins=725, ellipses=20, seed=1,
                 noise=0.005)
-NNZ_CT512 = 240_840_942          # rays x pixels with nonzero intersection length (computed)
+# Nonzero entries of R (strictly positive chord lengths), counted with the
+# oracle's closed form by tests/golden/count_nnz.py.
+NNZ_CT512 = 240_840_802
+NNZ_2048 = 10_945_428_176
 PEAK_HBM = 8.0e12                # B/s
 # Non-packed FP32 VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz.  The published
 # 157.3 TFLOP/s counts an FMA as 2 flops on 2-wide packed lanes.
@@ -54,6 +57,9 @@ def parse():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training the learned preconditioner and its time-to-target")
     ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--large", action="store_true",
+                    help="also run 8 slices of 2048^2 x 2048 x 2899 (about a minute of phantom setup)")
+    ap.add_argument("--large-iters", type=int, default=20)
     return ap.parse_args()
 
 
@@ -92,6 +98,57 @@ def batched_run(sp, torch, iters):
             "one_by_one_slice_iterations_per_s": round(64 * iters / t_seq, 2),
             "speedup_vs_one_by_one": round(t_seq / t_batch, 3),
             "all_k": sorted(set(r.k for r in res)), "tuning": sp.batch_tuning()}
+
+
+def large_run(sp, torch, iters):
+    """8 slices of 2048^2 x 2048 angles x 2899 bins in one batched solve, plus
+    standalone R and R^T timings at that geometry."""
+    from synth import large_batch, noisy_data, random_ellipses, unit_noise
+    work = large_batch(8)
+    geoms = [sp.Geometry(w.rows, w.cols, w.n_angles, w.n_bins) for w in work]
+    bs = []
+    for w, g in zip(work, geoms):
+        img, rng = random_ellipses(w.rows, w.cols, w.n_ellipses, w.seed)
+        x = torch.from_numpy(img.astype(np.float32)).cuda()
+        b_exact = sp.sp_project(g, x).cpu().numpy().ravel()
+        b = noisy_data(b_exact, unit_noise(rng, g.m), w.noise_frac).astype(np.float32)
+        bs.append(torch.from_numpy(b.reshape(g.n_angles, g.n_bins)).cuda())
+        log(f"large slice {w.name} ready")
+    ctx = sp.context(0)
+    L = sp.api.L
+    x = torch.from_numpy(random_ellipses(2048, 2048, 50, 5000)[0].astype(np.float32)).cuda()
+    y = torch.empty((2048, 2899), device="cuda")
+    xo = torch.empty((2048, 2048), device="cuda")
+    def op_ms(fn, kind):
+        fn()
+        ctx.profile_enable(True)
+        for _ in range(3):
+            fn()
+        ms, n = ctx.profile_read(kind)
+        ctx.profile_enable(False)
+        return ms / max(n, 1)
+    ms_r = op_ms(lambda: sp.sp_project(geoms[0], x, y), L.SP_PROF_PROJECT)
+    ms_rt = op_ms(lambda: sp.sp_backproject(geoms[0], bs[0], xo), L.SP_PROF_BACKPROJECT)
+    kw = dict(K=1, a=0.5, gamma=0.5, mu=1e-5, rho=0.8)
+    sp.sp_suppcg_solve_batched(geoms, bs, graph=True, autotune=True, max_iter=2, **kw)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    res = sp.sp_suppcg_solve_batched(geoms, bs, graph=True, max_iter=iters, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    n, m = 2048 * 2048, 2048 * 2899
+    eq = 8 * NNZ_2048 + 4 * n + 4 * m
+    return {"workload": "8 slices 2048x2048, 2048 angles, 2899 bins, 50 ellipses (seeds 5000-5007), "
+                        "noise 0.25-2%, SupPCG K=1, ramp-Hamming M",
+            "iterations": iters, "batch_iterations_per_s": round(iters / t, 3),
+            "slice_iterations_per_s": round(8 * iters / t, 3),
+            "R_ms": round(ms_r, 3), "RT_ms": round(ms_rt, 3), "nnz_per_slice": NNZ_2048,
+            "R_gbps_equiv": round(eq / (ms_r / 1e3) / 1e9, 1),
+            "RT_gbps_equiv": round(eq / (ms_rt / 1e3) / 1e9, 1),
+            "all_k": sorted(set(r.k for r in res))}
 
 
 def learned_run(sp):
@@ -292,6 +349,9 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_run(sp, torch, args.batch_iters)
         log("batched run done")
+    if args.large:
+        out["large"] = large_run(sp, torch, args.large_iters)
+        log("2048^2 batch done")
     if not args.no_learned:
         out["time_to_target"] = learned_run(sp)
         log("learned preconditioner trained and timed")

@@ -26,6 +26,7 @@ __all__ = [
     "noisy_data",
     "WORKLOADS",
     "batched_slices",
+    "large_batch",
 ]
 
 
@@ -129,3 +130,12 @@ def batched_slices(count: int = 64, seed: int = 2):
         B = int(math.ceil(side * math.sqrt(2.0))) + 1
         out.append(Workload(f"slice{i}", side, side, A, B, 20, 1000 + i, frac, 50))
     return out
+
+
+def large_batch(count: int = 8):
+    """2048 x 2048 slices, 2048 angles over [0, pi), 2899 bins, 50 ellipses
+    (scale 32), phantom seeds 5000 + i, noise fractions 0.25%, 0.25%, 0.5%,
+    0.5%, 1%, 1%, 2%, 2% (two slices each), 200 iterations."""
+    fracs = [0.0025, 0.0025, 0.005, 0.005, 0.01, 0.01, 0.02, 0.02]
+    return [Workload(f"large{i}", 2048, 2048, 2048, 2899, 50, 5000 + i, fracs[i % len(fracs)], 200)
+            for i in range(count)]
