@@ -116,13 +116,23 @@ def apply(Ws, d, u):
     return b[0, 0] if single else b[:, 0]
 
 
-def loss_and_grad(Ws, d, Av, v):
-    """Loss mean_b ||M(Av_b) - v_b||^2 / ||v_b||^2 and its gradient.
+def interior(shape, margin: int):
+    """1 on pixels at least `margin` away from every image edge, else 0."""
+    H, W = shape[-2], shape[-1]
+    m = np.zeros((H, W))
+    m[margin:H - margin, margin:W - margin] = 1.0
+    return m
+
+
+def loss_and_grad(Ws, d, Av, v, margin: int = 0):
+    """Loss mean_b ||P (M(Av_b) - v_b)||^2 / ||P v_b||^2 and its gradient, with
+    P the restriction to the interior pixels (margin 0: the whole image).
 
     Returns (loss, [dL/dW_l], dL/dd)."""
     Av = np.asarray(Av, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
     B = Av.shape[0]
+    P = interior(v.shape, margin)
     sig = softplus(d)
     acts = [Av[:, None]]                       # a_0 .. a_L (forward chain)
     for W in Ws:
@@ -132,8 +142,8 @@ def loss_and_grad(Ws, d, Av, v):
         back.append(conv_t(back[-1], W))
     back = back[::-1]                          # back[l] = b_l, l = 0..L
     z = back[0][:, 0]
-    nv = np.sum(v * v, axis=(1, 2))
-    r = z - v
+    nv = np.sum((P * v) ** 2, axis=(1, 2))
+    r = P * (z - v)
     loss = float(np.mean(np.sum(r * r, axis=(1, 2)) / nv))
     L = len(Ws)
     gW = [np.zeros_like(W) for W in Ws]

@@ -71,6 +71,47 @@ def test_loss_gradient_matches_finite_differences():
     assert loss == pytest.approx(want, rel=1e-13)
 
 
+def test_margin_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(14)
+    Ws, d = ol.init_params(layers=2, channels=3, seed=15)
+    Av = rng.standard_normal((2, 9, 10))
+    v = rng.standard_normal((2, 9, 10))
+    loss, gW, gd = ol.loss_and_grad(Ws, d, Av, v, margin=2)
+    g = ol.flatten(gW, gd)
+    theta = ol.flatten(Ws, d)
+    h = 1e-6
+    for q in rng.choice(theta.size, 30, replace=False):
+        tp = theta.copy()
+        tm = theta.copy()
+        tp[q] += h
+        tm[q] -= h
+        fd = (ol.loss_and_grad(*ol.unflatten(tp, 2, 3), Av, v, margin=2)[0] -
+              ol.loss_and_grad(*ol.unflatten(tm, 2, 3), Av, v, margin=2)[0]) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-6 * max(1.0, abs(fd)), (q, fd, g[q])
+    z = ol.apply(Ws, d, Av)
+    want = np.mean([np.sum((z[b] - v[b])[2:7, 2:8] ** 2) / np.sum(v[b][2:7, 2:8] ** 2) for b in range(2)])
+    assert loss == pytest.approx(want, rel=1e-13)
+
+
+def test_crop_interior_equals_full_image():
+    # M = C^T D C with L 3x3 layers reaches L pixels each way through C and L
+    # through C^T: 2L in all.  On a crop whose interior keeps 2L pixels from the
+    # crop's edges, M(crop) equals M(full image) on that interior, so the
+    # margin-2L loss on crops is the full-size loss on those pixels.
+    rng = np.random.default_rng(16)
+    L = 3
+    Ws, d = ol.init_params(layers=L, channels=4, seed=17)
+    u = rng.standard_normal((40, 44))
+    full = ol.apply(Ws, d, u)
+    r0, c0, h, w = 9, 11, 20, 22
+    crop = ol.apply(Ws, d, u[r0:r0 + h, c0:c0 + w])
+    m = 2 * L
+    np.testing.assert_allclose(crop[m:h - m, m:w - m], full[r0 + m:r0 + h - m, c0 + m:c0 + w - m],
+                               rtol=0, atol=1e-12)
+    # one pixel less of margin and the zero padding shows
+    assert np.max(np.abs(crop[m - 1, m:w - m] - full[r0 + m - 1, c0 + m:c0 + w - m])) > 1e-6
+
+
 def test_adam_first_step_is_signed_lr():
     p = [np.array([1.0, -2.0, 3.0])]
     g = [np.array([0.5, -4.0, 1e-3])]
