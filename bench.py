@@ -141,8 +141,23 @@ def large_run(sp, torch, iters):
     t = e0.elapsed_time(e1) / 1e3
     n, m = 2048 * 2048, 2048 * 2899
     eq = 8 * NNZ_2048 + 4 * n + 4 * m
+    # learned preconditioner retrained at this geometry on crop interiors, then
+    # time to the plain run's f and TV at loop body 200 on the first slice
+    from paper_1807_10151_amd import learned_train as lt
+    cfg = lt.TrainConfig(n_ellipses=50, noise=0.005)
+    tr = lt.train_crops(geoms[0], cfg, lt.CropConfig(), log_every=500)
+    log("learned preconditioner trained at 2048^2")
+    ttt = lt.time_to_target(geoms[0], tr.net, [5000], cfg, plain_iters=200, max_iters=400, reps=1)[0]
+    learned = {"train_s": round(tr.seconds, 2), "probe_s": round(tr.probe_seconds, 2),
+               "loss_first_last": [round(tr.losses[0][1], 4), round(tr.losses[-1][1], 4)],
+               "plain_iterations": 200, "plain_s": round(ttt["plain_s"], 3),
+               "learned_iterations_to_f": ttt["k_f"], "learned_iterations_to_tv": ttt["k_tv"],
+               "learned_iterations_to_both": ttt["k_both"],
+               "learned_s_to_both": (round(ttt["learned_s"], 3) if ttt["learned_s"] else None),
+               "learned_f_at_200_over_target": round(ttt["learned_f_at_plain_iters"] / ttt["f_star"], 4)}
     return {"workload": "8 slices 2048x2048, 2048 angles, 2899 bins, 50 ellipses (seeds 5000-5007), "
                         "noise 0.25-2%, SupPCG K=1, ramp-Hamming M",
+            "time_to_target_seed_5000": learned,
             "iterations": iters, "batch_iterations_per_s": round(iters / t, 3),
             "slice_iterations_per_s": round(8 * iters / t, 3),
             "R_ms": round(ms_r, 3), "RT_ms": round(ms_rt, 3), "nnz_per_slice": NNZ_2048,

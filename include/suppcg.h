@@ -262,11 +262,15 @@ int sp_lp_apply(sp_ctx* ctx, sp_learned* net, int32_t batch, int32_t rows, int32
                 const float* u, float* z);
 /* Training loss over the minibatch idx[0..batch) (device int32, values in
  * [0, nprobe)) of probe pairs Av, v ([nprobe][rows][cols], device):
- * loss = mean_b ||M(Av_b) - v_b||^2 / ||v_b||^2 -> *loss (device float64);
- * grad (device float32, num_params) = d loss / d theta. */
+ * loss = mean_b ||P(M(Av_b) - v_b)||^2 / ||P v_b||^2 -> *loss (device
+ * float64), P = restriction to the pixels at least `margin` from every edge
+ * (0: all pixels; M reaches 2 * layers pixels, so with that margin the loss on
+ * crops of larger images equals the full-size loss on the crop interiors);
+ * grad (device float32, num_params) = d loss / d theta.
+ * Requires 0 <= margin and 2 * margin < min(rows, cols). */
 int sp_lp_loss_grad(sp_ctx* ctx, sp_learned* net, int32_t rows, int32_t cols, const float* Av,
                     const float* v, int32_t nprobe, const int32_t* idx, int32_t batch,
-                    double* loss, float* grad);
+                    int32_t margin, double* loss, float* grad);
 /* One Adam step theta -= lr * mhat / (sqrt(vhat) + eps) with gradient grad
  * (device float32); step counts from 1. */
 int sp_lp_adam_step(sp_ctx* ctx, sp_learned* net, const float* grad, double lr, double beta1,

@@ -109,7 +109,7 @@ _SIGS = {
     "sp_lp_get_params": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]),
     "sp_lp_apply": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "sp_lp_loss_grad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32,
-                                c_void_p, c_int32, c_void_p, c_void_p]),
+                                c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "sp_lp_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double,
                                 c_double, c_int32]),
     "sp_profile_enable": (c_int, [c_void_p, c_int]),

@@ -269,8 +269,9 @@ class LearnedPrecond:
         return z
 
     def loss_grad(self, Av: torch.Tensor, v: torch.Tensor, idx: torch.Tensor,
-                  grad: torch.Tensor | None = None):
-        """(loss [float64 0-d], grad [num_params]) on the minibatch idx of (Av, v)."""
+                  grad: torch.Tensor | None = None, margin: int = 0):
+        """(loss [float64 0-d], grad [num_params]) on the minibatch idx of (Av, v),
+        the loss taken over pixels at least `margin` from every edge."""
         N, H, W = Av.shape
         if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
             raise TypeError("idx must be a contiguous int32 CUDA tensor")
@@ -281,7 +282,7 @@ class LearnedPrecond:
         self.ctx._check(self.ctx.lib.sp_lp_loss_grad(
             self.ctx.h, self.h, H, W, _dev(Av, N * H * W, "Av", self.ctx.device),
             _dev(v, N * H * W, "v", self.ctx.device), N, ctypes.c_void_p(idx.data_ptr()),
-            idx.numel(), ctypes.c_void_p(loss.data_ptr()),
+            idx.numel(), int(margin), ctypes.c_void_p(loss.data_ptr()),
             _dev(grad, self.num_params, "grad", self.ctx.device)))
         return loss, grad
 

@@ -993,13 +993,15 @@ int sp_lp_apply(sp_ctx* c, sp_learned* net, int32_t batch, int32_t rows, int32_t
 }
 
 int sp_lp_loss_grad(sp_ctx* c, sp_learned* net, int32_t rows, int32_t cols, const float* Av,
-                    const float* v, int32_t nprobe, const int32_t* idx, int32_t batch, double* loss,
-                    float* grad) {
+                    const float* v, int32_t nprobe, const int32_t* idx, int32_t batch,
+                    int32_t margin, double* loss, float* grad) {
     if (!c) return SP_ERR_ARG;
     if (!net || !Av || !v || !idx || !loss || !grad)
         return fail(c, SP_ERR_ARG, "sp_lp_loss_grad: null argument");
     if (rows < 1 || cols < 1 || nprobe < 1 || batch < 1 || (double)batch * rows * cols > 2.0e8)
         return fail(c, SP_ERR_ARG, "sp_lp_loss_grad: bad sizes");
+    if (margin < 0 || 2 * margin >= std::min(rows, cols))
+        return fail(c, SP_ERR_ARG, "sp_lp_loss_grad: margin must leave interior pixels");
     if (net->device != c->device) return fail(c, SP_ERR_ARG, "network lives on another GPU");
     HIP_TRY(c, hipSetDevice(c->device));
     const int B = batch, H = rows, W = cols, L = net->layers;
@@ -1029,7 +1031,7 @@ int sp_lp_loss_grad(sp_ctx* c, sp_learned* net, int32_t rows, int32_t cols, cons
         lp_conv_mid(st, true, B, H, W, Bb(l), Bb(l - 1), th + net->woff(l), nullptr, nullptr, nullptr, nullptr);
     lp_conv_out(st, B, H, W, Bb(1), Z, th + net->woff(1), nullptr, nullptr);
     // loss and e_0 = d loss / dz
-    lp_loss(st, B, H * W, Z, v, idx, nprobe, E(0), dptr<double>(net->lpart));
+    lp_loss(st, B, H, W, margin, Z, v, idx, nprobe, E(0), dptr<double>(net->lpart));
     launch_reduce(st, dptr<double>(net->lpart), B, loss);
     // e_l = C_l e_{l-1}; the back chain contributes wgrad(b_l, e_{l-1}) to W_l
     lp_conv_in(st, B, H, W, E(0), nullptr, B, E(1), th + net->woff(1), nullptr, nullptr);

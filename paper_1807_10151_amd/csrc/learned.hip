@@ -184,22 +184,31 @@ __global__ void k_lp_softplus(const float* __restrict__ d, float* __restrict__ s
 // ---- loss ---------------------------------------------------------------------
 // One workgroup per sample b: nv = ||v||^2, lb = ||z - v||^2 / nv,
 // e0 = (2 / B) (z - v) / nv; loss partial lb / B.
-__global__ __launch_bounds__(256) void k_lp_loss(int B, int HW, const float* __restrict__ z,
+// Per sample b: loss over the pixels at least `margin` from every edge,
+// e0 = d loss / dz (zero on the margin).
+__global__ __launch_bounds__(256) void k_lp_loss(int B, int H, int W, int margin,
+                                                 const float* __restrict__ z,
                                                  const float* __restrict__ v,
                                                  const int32_t* __restrict__ idx, int nsrc,
                                                  float* __restrict__ e0,
                                                  double* __restrict__ lpart) {
     __shared__ double red[4];
     const int b = blockIdx.x;
+    const int HW = H * W;
     const float* vb = v + (size_t)(idx ? min(max(idx[b], 0), nsrc - 1) : b) * HW;
     const float* zb = z + (size_t)b * HW;
+    auto inside = [&](int q) {
+        const int y = q / W, x = q - (q / W) * W;
+        return y >= margin && y < H - margin && x >= margin && x < W - margin;
+    };
     double nv = 0.0;
-    for (int q = threadIdx.x; q < HW; q += 256) nv += (double)vb[q] * (double)vb[q];
+    for (int q = threadIdx.x; q < HW; q += 256)
+        if (inside(q)) nv += (double)vb[q] * (double)vb[q];
     nv = block_sum(nv, red);
     const double sc = nv > 0.0 ? 2.0 / ((double)B * nv) : 0.0;
     double r2 = 0.0;
     for (int q = threadIdx.x; q < HW; q += 256) {
-        const double r = (double)zb[q] - (double)vb[q];
+        const double r = inside(q) ? (double)zb[q] - (double)vb[q] : 0.0;
         r2 += r * r;
         e0[(size_t)b * HW + q] = (float)(sc * r);
     }
@@ -376,9 +385,10 @@ void lp_softplus(hipStream_t st, const float* d, float* sp_out, float* sg_out) {
     hipLaunchKernelGGL(k_lp_softplus, dim3(1), dim3(64), 0, st, d, sp_out, sg_out);
 }
 
-void lp_loss(hipStream_t st, int B, int HW, const float* z, const float* v, const int32_t* idx,
-             int nsrc, float* e0, double* lpart) {
-    hipLaunchKernelGGL(k_lp_loss, dim3(B), dim3(256), 0, st, B, HW, z, v, idx, nsrc, e0, lpart);
+void lp_loss(hipStream_t st, int B, int H, int W, int margin, const float* z, const float* v,
+             const int32_t* idx, int nsrc, float* e0, double* lpart) {
+    hipLaunchKernelGGL(k_lp_loss, dim3(B), dim3(256), 0, st, B, H, W, margin, z, v, idx, nsrc, e0,
+                       lpart);
 }
 
 int lp_wgrad_blocks(int B, int H, int W) { return B * ((W + 15) / 16) * ((H + 15) / 16); }

@@ -176,8 +176,8 @@ void lp_conv_out(hipStream_t st, int B, int H, int W, const float* in, float* ou
 void lp_gather(hipStream_t st, int B, int HW, const float* src, const int32_t* idx, int nsrc, float* dst);
 void lp_scale(hipStream_t st, long npix, const float* in, const float* scale, float* out);
 void lp_softplus(hipStream_t st, const float* d, float* sp_out, float* sg_out);
-void lp_loss(hipStream_t st, int B, int HW, const float* z, const float* v, const int32_t* idx,
-             int nsrc, float* e0, double* lpart);
+void lp_loss(hipStream_t st, int B, int H, int W, int margin, const float* z, const float* v,
+             const int32_t* idx, int nsrc, float* e0, double* lpart);
 int lp_wgrad_blocks(int B, int H, int W);
 void lp_wgrad(hipStream_t st, int fi, int B, int H, int W, const float* G, const float* X, float* partial);
 int lp_reduce_chunks(int nb);

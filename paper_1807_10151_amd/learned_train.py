@@ -30,8 +30,9 @@ import torch
 
 from . import api
 
-__all__ = ["TrainConfig", "phantom_data", "gaussian_probes", "krylov_probes", "normal_op",
-           "init_theta", "scale_init", "train", "time_to_target"]
+__all__ = ["TrainConfig", "CropConfig", "phantom_data", "gaussian_probes", "krylov_probes",
+           "normal_op", "crop_probes", "init_theta", "scale_init", "train", "train_crops",
+           "time_to_target"]
 
 
 @dataclass
@@ -159,7 +160,7 @@ class TrainResult:
 
 
 def train(g: api.Geometry, cfg: TrainConfig = TrainConfig(), ctx: api.Context | None = None,
-          log_every: int = 100, probes=None) -> TrainResult:
+          log_every: int = 100, probes=None, margin: int = 0) -> TrainResult:
     """Build the probes, then run cfg.steps Adam steps on the GPU."""
     ctx = ctx or api.context(0)
     dev = f"cuda:{ctx.device}"
@@ -192,7 +193,7 @@ def train(g: api.Geometry, cfg: TrainConfig = TrainConfig(), ctx: api.Context | 
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for step in range(1, cfg.steps + 1):
-        loss, _ = net.loss_grad(AV, V, idx[step - 1], grad)
+        loss, _ = net.loss_grad(AV, V, idx[step - 1], grad, margin=margin)
         net.adam_step(grad, cfg.lr, step)
         if step % log_every == 0 or step == 1 or step == cfg.steps:
             pending.append((step, loss))
@@ -202,6 +203,80 @@ def train(g: api.Geometry, cfg: TrainConfig = TrainConfig(), ctx: api.Context | 
     if not all(math.isfinite(l) for _, l in losses):
         raise RuntimeError("training diverged (non-finite loss)")
     return TrainResult(net, losses, t3 - t2, t1 - t0, n, {"V": V, "AV": AV})
+
+
+@dataclass
+class CropConfig:
+    """Training on crops of large images: M reaches 2 * layers pixels, so the
+    loss on crop interiors with that margin is the full-size loss there."""
+    crop: int = 96
+    margin: int = 8
+    crops_per_image: int = 64
+    n_gauss_images: int = 32
+    krylov_seeds: tuple = (5100, 5101)
+    krylov_per_seed: int = 16
+    n_ellipses: int = 50
+    noise: float = 0.005
+    seed: int = 0
+
+
+def _crops(img: torch.Tensor, other: torch.Tensor, rng, cc: CropConfig):
+    """Random crops (same positions) of two [H, W] device images, scaled so the
+    first crop's interior has unit norm."""
+    H, W = img.shape
+    c, m = cc.crop, cc.margin
+    ys = rng.integers(0, H - c + 1, cc.crops_per_image)
+    xs = rng.integers(0, W - c + 1, cc.crops_per_image)
+    a = torch.stack([img[y:y + c, x:x + c] for y, x in zip(ys, xs)])
+    b = torch.stack([other[y:y + c, x:x + c] for y, x in zip(ys, xs)])
+    nrm = a[:, m:c - m, m:c - m].double().flatten(1).norm(dim=1).clamp_min(1e-30)
+    return (a.double() / nrm[:, None, None]).float(), (b.double() / nrm[:, None, None]).float()
+
+
+def crop_probes(g: api.Geometry, cfg: TrainConfig, cc: CropConfig, ctx: api.Context | None = None):
+    """(V, AV) crops [N, crop, crop] from full-size Gaussian images and from the
+    gradients g_{k+1/2} of plain runs, with A v = R^T R v computed at full size."""
+    ctx = ctx or api.context(0)
+    dev = f"cuda:{ctx.device}"
+    rng = np.random.default_rng(cc.seed + 7)
+    y = torch.empty((g.n_angles, g.n_bins), dtype=torch.float32, device=dev)
+    av = torch.empty((g.rows, g.cols), dtype=torch.float32, device=dev)
+    Vs, AVs = [], []
+    for i in range(cc.n_gauss_images):
+        v = torch.from_numpy(np.random.default_rng(cc.seed + 1000 + i).standard_normal(
+            (g.rows, g.cols)).astype(np.float32)).to(dev)
+        api.sp_project(g, v, y, ctx=ctx)
+        api.sp_backproject(g, y, av, ctx=ctx)
+        a, b = _crops(v, av, rng, cc)
+        Vs.append(a)
+        AVs.append(b)
+    for seed in cc.krylov_seeds:
+        _, bdat = phantom_data(g, seed, cc.n_ellipses, cc.noise, ctx)
+        snap = torch.empty((cc.krylov_per_seed, g.rows, g.cols), dtype=torch.float32, device=dev)
+        api.sp_suppcg_solve(g, bdat, None, K=cfg.K, a=cfg.a, gamma=cfg.gamma, precond="ramp",
+                            mu=cfg.mu, rho=cfg.rho, max_iter=cc.krylov_per_seed, graph=True,
+                            trace=False, g_snap=snap, ctx=ctx)
+        for j in range(cc.krylov_per_seed):
+            api.sp_project(g, snap[j], y, ctx=ctx)
+            api.sp_backproject(g, y, av, ctx=ctx)
+            a, b = _crops(snap[j], av, rng, cc)
+            Vs.append(a)
+            AVs.append(b)
+        del snap
+    return torch.cat(Vs).contiguous(), torch.cat(AVs).contiguous()
+
+
+def train_crops(g: api.Geometry, cfg: TrainConfig = TrainConfig(), cc: CropConfig = CropConfig(),
+                ctx: api.Context | None = None, log_every: int = 100) -> TrainResult:
+    """train() on crop probes of a large geometry, loss over the crop interiors."""
+    ctx = ctx or api.context(0)
+    t0 = time.perf_counter()
+    V, AV = crop_probes(g, cfg, cc, ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = train(g, cfg, ctx, log_every, probes=(V, AV), margin=cc.margin)
+    res.probe_seconds = t1 - t0
+    return res
 
 
 def _first(arr, target):

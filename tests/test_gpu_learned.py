@@ -46,7 +46,8 @@ def test_apply_matches_oracle(sp, shape, layers):
     assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
 
 
-def test_loss_grad_matches_oracle(sp):
+@pytest.mark.parametrize("margin", [0, 8])
+def test_loss_grad_matches_oracle(sp, margin):
     Ws, d = params(3)
     theta = ol.flatten(Ws, d).astype(np.float32).astype(np.float64)
     Ws, d = ol.unflatten(theta, 4, 16)
@@ -54,10 +55,11 @@ def test_loss_grad_matches_oracle(sp):
     Av = rng.standard_normal((6, 24, 40)).astype(np.float32)
     v = rng.standard_normal((6, 24, 40)).astype(np.float32)
     idx = np.array([5, 0, 3, 3], dtype=np.int32)
-    loss, gW, gd = ol.loss_and_grad(Ws, d, Av[idx].astype(np.float64), v[idx].astype(np.float64))
+    loss, gW, gd = ol.loss_and_grad(Ws, d, Av[idx].astype(np.float64), v[idx].astype(np.float64),
+                                    margin=margin)
     net = sp.LearnedPrecond(4)
     net.set_params(theta)
-    gl, gg = net.loss_grad(cuda(Av), cuda(v), cuda(idx, np.int32))
+    gl, gg = net.loss_grad(cuda(Av), cuda(v), cuda(idx, np.int32), margin=margin)
     assert float(gl.item()) == pytest.approx(loss, rel=1e-5)
     want = ol.flatten(gW, gd)
     got = gg.cpu().numpy().astype(np.float64)
