@@ -1583,8 +1583,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         hipGraphExec_t exec = nullptr;
         HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         body();
+        const hipError_t el0 = hipGetLastError();
         hipError_t ec = hipStreamEndCapture(st, &graph);
-        if (ec != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        if (ec == hipSuccess && el0 != hipSuccess) ec = el0;
+        if (ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(c, SP_ERR_HIP, "capturing the batched loop body: %s", hipGetErrorString(ec));
+        }
         hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (ei != hipSuccess) {
             (void)hipGraphDestroy(graph);
@@ -1607,9 +1612,10 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
                 if (h) break;
             }
         }
-        (void)hipStreamSynchronize(st);
+        const hipError_t es = hipStreamSynchronize(st);
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
+        if (es != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
     } else {
         for (int it = 0; it < sp->max_iter; ++it) {
             body();
