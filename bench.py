@@ -44,7 +44,7 @@ OPS_PER_NNZ = 4
 # kernels at this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE averages scaled
 # by the counts of a 64 MiB device copy (profiles/counters_ct512.md).  They are
 # tied to the kernels as profiled; re-measure after changing them.
-TRAFFIC_BYTES = {"project": 40.73e6, "backproject": 18.72e6}
+TRAFFIC_BYTES = {"project": None, "backproject": None}
 
 
 def log(msg):
@@ -343,7 +343,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 data, f64 CG scalars and reductions",
+        "dtype": "f32 data; f64 iterate, search direction, CG scalars and reductions",
         "data": "synthetic random-ellipse phantom (20 ellipses, seed 1), 0.5% Gaussian noise",
         "config": {"workload": "ct512: 512x512 image, 720 angles over [0,pi), 725 bins, "
                                "SupPCG K=1 a=0.5 gamma=0.5, ramp-Hamming M mu=1e-5 rho=0.8",

@@ -32,7 +32,12 @@
  *  - Calls on one context are not thread-safe; use one context per thread.
  *  - Accumulation: data are float32; every dot product, norm, TV value and CG
  *    scalar (alpha, beta, p^T h, f) is accumulated and kept in float64, with
- *    fixed-order (deterministic) reductions.
+ *    fixed-order (deterministic) reductions.  Inside the solvers the iterate
+ *    x_k, x_{k+1/2} and the search direction p are float64 vectors (their
+ *    float32 rounding, repeated every iteration, is what moves a float32
+ *    iterate away from the float64 one); the gradient g, M g, h = A p, the
+ *    TV direction and every sinogram-sized vector are float32.  Images passed
+ *    in and out are float32.
  */
 #ifndef SUPPCG_H
 #define SUPPCG_H
@@ -176,7 +181,8 @@ int sp_tv(sp_ctx* ctx, const sp_geometry* g, const float* x, double* tv);
  * *norm2 = ||t_bar||^2 (float64 device scalar, nullable). */
 int sp_tv_grad(sp_ctx* ctx, const sp_geometry* g, const float* x, float* tbar, double* norm2);
 
-/* Algorithm 1: (s, l) = S_TV(x, l, a, gamma, K); writes x_half = x + s.
+/* Algorithm 1: (s, l) = S_TV(x, l, a, gamma, K); writes x_half = x + s
+ * (evaluated in float64 on the float32 x, rounded to float32 once).
  * ell: device int32, read and updated in place.  tv_half: device float64,
  * TV(x_half) (nullable).  trials: device int32[K], trials used by each inner
  * step, max_trials + 1 when none was accepted (nullable). */

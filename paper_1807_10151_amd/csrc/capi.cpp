@@ -31,7 +31,6 @@ struct BatchState {
     int max_bins = 1;
     size_t lds_rows = 0, lds_cols = 0;
     std::vector<SliceDev> hs;        // host copies; per-call pointers filled in each call
-    std::vector<char*> own_x;        // per slice: x_k storage used when x_last is NULL
     DevBuf arena, sl, items, scal, trace_d;
     size_t off[BS_COUNT][2] = {};    // item-table offsets (entries) per stage and order
     int count[BS_COUNT][2] = {};
@@ -52,14 +51,15 @@ struct sp_ctx {
     sp_geometry geom{};
     GeomDev G{};
     std::vector<AngleDev> ang_h;
-    DevBuf ang, skp, xp, xTp, yp;
+    DevBuf ang, skp, xp, xTp, yp, seg;
 
     // preconditioner cache
     int fftP = 0;
     DevBuf tw, S;
 
     // solver vectors and scratch
-    DevBuf vx, vp, vh, vg, vz, vtb, vtmp;
+    DevBuf vx, vxh, vp;                   // float64 x_k, x_{k+1/2}, p
+    DevBuf vh, vg, vz, vtb, vtmp;
     DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc;
     DevBuf scal, trace_d, replay_d, trials_tmp;
     Scalars sc_h{};
@@ -205,6 +205,7 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
     G.pitchX = g->cols + 2 * PAD;
     G.pitchXT = g->rows + 2 * PAD;
     G.pitchB = g->n_bins + 2 * PAD;
+    G.parts = project_parts(g->rows, g->cols);
     const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
     tab.assign(g->n_angles, AngleDev{});
     for (int a = 0; a < g->n_angles; ++a) {
@@ -277,6 +278,8 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     if ((rc = ensure(c, c->xp, nX * 8))) return rc;
     if ((rc = ensure(c, c->xTp, nXT * 8))) return rc;
     if ((rc = ensure(c, c->yp, nY * 4))) return rc;
+    if (G.parts > 1 && (rc = ensure(c, c->seg, (size_t)G.parts * g->n_angles * g->n_bins * 8)))
+        return rc;
     if (relayout) {
         HIP_TRY(c, hipMemsetAsync(c->xp.ptr, 0, c->xp.bytes, c->stream));
         HIP_TRY(c, hipMemsetAsync(c->xTp.ptr, 0, c->xTp.bytes, c->stream));
@@ -369,8 +372,10 @@ int check_tv(sp_ctx* c, const sp_tv_params* p) {
 
 int ensure_vectors(sp_ctx* c, size_t n) {
     int rc;
-    for (DevBuf* b : {&c->vx, &c->vp, &c->vh, &c->vg, &c->vz, &c->vtb, &c->vtmp})
+    for (DevBuf* b : {&c->vh, &c->vg, &c->vz, &c->vtb, &c->vtmp})
         if ((rc = ensure(c, *b, n * sizeof(float)))) return rc;
+    for (DevBuf* b : {&c->vx, &c->vxh, &c->vp})
+        if ((rc = ensure(c, *b, n * sizeof(double)))) return rc;
     return SP_OK;
 }
 
@@ -429,7 +434,7 @@ struct ProfScope {
 };
 
 // One S_TV call (Algorithm 1) from x into xh, K inner steps.
-void enqueue_stv(sp_ctx* c, int K, const float* x, float* xh, bool snorm, TraceDev tr,
+void enqueue_stv(sp_ctx* c, int K, const double* x, double* xh, bool snorm, TraceDev tr,
                  int32_t* trials_out) {
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
@@ -438,7 +443,7 @@ void enqueue_stv(sp_ctx* c, int K, const float* x, float* xh, bool snorm, TraceD
     const int nb = tv_blocks(G.rows, G.cols);
     ProfScope ps(c, SP_PROF_TV);
     for (int i = 0; i < K; ++i) {
-        const float* src = i == 0 ? x : xh;
+        const double* src = i == 0 ? x : xh;
         launch_tv_grad(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), halt);
         launch_tv_trials(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), nb,
                          sc, 8, dptr<double>(c->part_t), halt);
@@ -563,7 +568,8 @@ int stage_blocks(const SliceDev& S, int stage) {
     const GeomDev& G = S.G;
     switch (stage) {
     case BS_PREP: return ((G.cols + 31) / 32) * ((G.rows + 31) / 32);
-    case BS_PROJECT: return project_blocks(G);
+    case BS_PROJECT: return project_blocks(G) * G.parts;
+    case BS_PROJ_COMB: return G.parts > 1 ? project_blocks(G) : 0;
     case BS_BACKPROJECT: return backproject_blocks(G);
     case BS_ROWS: return (G.rows + 1) / 2;
     case BS_COLS: return S.F.P ? (S.F.SP + S.F.CB - 1) / S.F.CB : 0;
@@ -577,7 +583,8 @@ int stage_blocks(const SliceDev& S, int stage) {
 double item_cost(const SliceDev& S, int stage) {
     const GeomDev& G = S.G;
     switch (stage) {
-    case BS_PROJECT: return (double)std::max(G.rows, G.cols);
+    case BS_PROJECT: return (double)std::max(G.rows, G.cols) / G.parts;
+    case BS_PROJ_COMB: return (double)G.parts;
     case BS_BACKPROJECT: return (double)G.nA;
     case BS_ROWS:
     case BS_COLS: return S.F.P ? (double)S.F.P * S.F.logP : 0.0;
@@ -646,14 +653,13 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
     B.tuned = false;
     for (int s = 0; s < BS_COUNT; ++s) B.order[s] = B.wpc[s] = 0;
     B.hs.assign(n, SliceDev{});
-    B.own_x.assign(n, nullptr);
     B.nbmax = 1;
     B.max_bins = 1;
     B.lds_rows = B.lds_cols = 0;
     std::vector<std::vector<AngleDev>> tabs(n);
     // sizes
     struct Off {
-        size_t ang, skp, xp, xTp, rp, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
+        size_t ang, skp, xp, xTp, rp, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
     };
     std::vector<Off> off(n);
     size_t total = 0;
@@ -694,7 +700,9 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         o.xp = take((size_t)G.rows * G.pitchX * 8);
         o.xTp = take((size_t)G.cols * G.pitchXT * 8);
         o.rp = take((size_t)G.nA * G.pitchB * 4);
-        o.vec = take((size_t)S.n * 4 * 6);   // x, p, h, g, z, t_bar
+        o.seg = take(G.parts > 1 ? (size_t)G.parts * G.nA * G.nB * 8 : 0);
+        o.dvec = take((size_t)S.n * 8 * 3);  // x, x_half, p (float64)
+        o.vec = take((size_t)S.n * 4 * 4);   // h, g, z, t_bar
         o.S = kind == SP_PRECOND_RAMP ? take((size_t)G.rows * S.F.SP * sizeof(double2)) : 0;
         o.tw = kind == SP_PRECOND_RAMP ? take((size_t)(S.F.P / 2) * sizeof(double2)) : 0;
         o.pf = take((size_t)S.nf * 8);
@@ -725,13 +733,16 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         S.xp = reinterpret_cast<double*>(base + o.xp);
         S.xTp = reinterpret_cast<double*>(base + o.xTp);
         S.rp = reinterpret_cast<float*>(base + o.rp);
+        S.seg = S.G.parts > 1 ? reinterpret_cast<double*>(base + o.seg) : nullptr;
+        double* dv = reinterpret_cast<double*>(base + o.dvec);
+        S.x = dv;
+        S.xh = dv + (size_t)S.n;
+        S.p = dv + 2 * (size_t)S.n;
         float* v = reinterpret_cast<float*>(base + o.vec);
-        B.own_x[s] = reinterpret_cast<char*>(v);
-        S.p = v + (size_t)S.n;
-        S.h = v + 2 * (size_t)S.n;
-        S.g = v + 3 * (size_t)S.n;
-        S.z = v + 4 * (size_t)S.n;
-        S.tb = v + 5 * (size_t)S.n;
+        S.h = v;
+        S.g = v + (size_t)S.n;
+        S.z = v + 2 * (size_t)S.n;
+        S.tb = v + 3 * (size_t)S.n;
         if (kind == SP_PRECOND_RAMP) {
             S.F.S = reinterpret_cast<double2*>(base + o.S);
             S.F.tw = reinterpret_cast<const double2*>(base + o.tw);
@@ -790,7 +801,7 @@ void batch_stage(sp_ctx* c, int stage, int order, int wpc, double mu, double rho
     const ItemTable t = table(c, stage, order, wpc);
     switch (stage) {
     case BS_PREP: launch_prep_b(st, sl, t, BV_XH); break;
-    case BS_PROJECT: launch_project_b(st, sl, t, true); break;
+    case BS_PROJECT: launch_project_b(st, sl, t, table(c, BS_PROJ_COMB, order, 0), true); break;
     case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, B.max_bins, false); break;
     case BS_ROWS:
         launch_precond_b(st, sl, t, table(c, BS_COLS, order, wpc), B.lds_rows, B.lds_cols, mu, rho);
@@ -884,7 +895,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     if (!c) return SP_ERR_ARG;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->tw, &c->S, &c->vx, &c->vp, &c->vh,
+    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->seg, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
                       &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
@@ -1098,7 +1109,7 @@ int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
     {
         ProfScope ps(c, SP_PROF_PROJECT);
         launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp),
-                       nullptr, y, G.nB, nullptr, nullptr, nullptr);
+                       nullptr, y, G.nB, nullptr, nullptr, dptr<double>(c->seg), nullptr);
     }
     return check_launch(c);
 }
@@ -1129,7 +1140,7 @@ int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b,
     const GeomDev& G = c->G;
     launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
     launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp), b, r,
-                   G.nB, nullptr, dptr<double>(c->part_f), nullptr);
+                   G.nB, nullptr, dptr<double>(c->part_f), dptr<double>(c->seg), nullptr);
     launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
     return check_launch(c);
 }
@@ -1154,7 +1165,9 @@ int sp_tv(sp_ctx* c, const sp_geometry* g, const float* x, double* tv) {
     int rc = setup_geometry(c, g);
     if (rc) return rc;
     if ((rc = ensure_partials(c))) return rc;
-    launch_tv_value(c->stream, g->rows, g->cols, x, dptr<double>(c->part_g), nullptr);
+    if ((rc = ensure_vectors(c, (size_t)g->rows * g->cols))) return rc;
+    launch_widen(c->stream, g->rows * g->cols, x, dptr<double>(c->vx));
+    launch_tv_value(c->stream, g->rows, g->cols, dptr<double>(c->vx), dptr<double>(c->part_g), nullptr);
     launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), tv);
     return check_launch(c);
 }
@@ -1166,7 +1179,9 @@ int sp_tv_grad(sp_ctx* c, const sp_geometry* g, const float* x, float* tbar, dou
     int rc = setup_geometry(c, g);
     if (rc) return rc;
     if ((rc = ensure_partials(c))) return rc;
-    launch_tv_grad(c->stream, g->rows, g->cols, x, tbar, dptr<double>(c->part_g), nullptr);
+    if ((rc = ensure_vectors(c, (size_t)g->rows * g->cols))) return rc;
+    launch_widen(c->stream, g->rows * g->cols, x, dptr<double>(c->vx));
+    launch_tv_grad(c->stream, g->rows, g->cols, dptr<double>(c->vx), tbar, dptr<double>(c->part_g), nullptr);
     if (norm2) launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), norm2);
     return check_launch(c);
 }
@@ -1192,15 +1207,19 @@ int sp_tv_perturb(sp_ctx* c, const sp_geometry* g, const sp_tv_params* p, const 
     Scalars* sc = dptr<Scalars>(c->scal);
     HIP_TRY(c, hipMemcpyAsync(&sc->ell, ell, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
     TraceDev tr{};
+    double* xd = dptr<double>(c->vx);
+    double* xhd = dptr<double>(c->vxh);
+    launch_widen(c->stream, (int)n, x, xd);
     if (p->K == 0) {
-        launch_copy(c->stream, (int)n, x, x_half, nullptr);
+        launch_copy(c->stream, (int)n, xd, xhd, nullptr);
     } else {
-        enqueue_stv(c, p->K, x, x_half, false, tr, trials);
+        enqueue_stv(c, p->K, xd, xhd, false, tr, trials);
     }
+    launch_narrow(c->stream, (int)n, xhd, x_half);
     HIP_TRY(c, hipMemcpyAsync(ell, &sc->ell, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
     if (tv_half) {
         if (p->K == 0) {
-            launch_tv_value(c->stream, g->rows, g->cols, x_half, dptr<double>(c->part_g), nullptr);
+            launch_tv_value(c->stream, g->rows, g->cols, xhd, dptr<double>(c->part_g), nullptr);
             launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), tv_half);
         } else {
             HIP_TRY(c, hipMemcpyAsync(tv_half, &sc->tv_new, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1283,14 +1302,15 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     hipStream_t st = c->stream;
     Scalars* sc = dptr<Scalars>(c->scal);
     const int* halt = &sc->halt;
-    float* xh = x_out;                                   // x_{k+1/2} lives in the output buffer
-    float* x = x_last ? x_last : dptr<float>(c->vx);        // x_k
-    float* p = dptr<float>(c->vp);
+    double* xh = dptr<double>(c->vxh);                  // x_{k+1/2}
+    double* x = dptr<double>(c->vx);                    // x_k
+    double* p = dptr<double>(c->vp);
     float* h = dptr<float>(c->vh);
     float* gv = dptr<float>(c->vg);
     float* z = dptr<float>(c->vz);
     double* xp = dptr<double>(c->xp);
     double* xTp = dptr<double>(c->xTp);
+    double* seg = dptr<double>(c->seg);
     float* rp = dptr<float>(c->yp);
     const double* skp = dptr<double>(c->skp);
     const AngleDev* ang = dptr<AngleDev>(c->ang);
@@ -1300,17 +1320,12 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     double* pph = dptr<double>(c->part_ph);
     const int nf = project_blocks(G), nph = backproject_blocks(G), ngp = vec_blocks(n);
 
-    if (x0) {
-        launch_copy(st, n, x0, xh, nullptr);
-        launch_copy(st, n, x0, x, nullptr);
-    } else {
-        HIP_TRY(c, hipMemsetAsync(xh, 0, (size_t)n * 4, st));
-        HIP_TRY(c, hipMemsetAsync(x, 0, (size_t)n * 4, st));
-    }
+    launch_widen(st, n, x0, xh);
+    launch_widen(st, n, x0, x);
     // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
     // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
     launch_prep(st, G, xh, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, rp, pf, halt);
+    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, rp, pf, seg, halt);
     launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
     launch_backproject(st, G, ang, rp, skp, gv, nullptr, nullptr, halt);
     int nzh = 0;
@@ -1318,7 +1333,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
     launch_update_p(st, n, z, p, gv, sc, pgp, halt);
     launch_prep(st, G, p, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, halt);
+    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, seg, halt);
     launch_backproject(st, G, ang, rp, skp, h, p, pph, halt);
     launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
     launch_update_x(st, n, xh, p, x, sc, halt);
@@ -1330,9 +1345,9 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     // the body can be replayed from a captured graph.
     auto project = [&](const float* bb, double* parts) {
         ProfScope ps(c, SP_PROF_PROJECT);
-        launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, rp, parts, halt);
+        launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, rp, parts, seg, halt);
     };
-    auto backproject = [&](float* out, const float* dotv, double* parts) {
+    auto backproject = [&](float* out, const double* dotv, double* parts) {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
         launch_backproject(st, G, ang, rp, skp, out, dotv, parts, halt);
     };
@@ -1423,6 +1438,10 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         // the step could not be formed: x_k = x_{k-1/2}
         launch_copy(st, n, xh, x, nullptr);
     }
+    launch_narrow(st, n, xh, x_out);
+    if (x_last) launch_narrow(st, n, x, x_last);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(st));
     if (trace) {
         const int cnt = std::min(trace->cap, cap);
         std::vector<char> host(tr_bytes);
@@ -1493,8 +1512,6 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         SliceDev& S = B.hs[s];
         S.b = b[s];
         S.x0 = x0 ? x0[s] : nullptr;
-        S.xh = x_out[s];
-        S.x = (x_last && x_last[s]) ? x_last[s] : reinterpret_cast<float*>(B.own_x[s]);
         char* t = dptr<char>(B.trace_d) + tr_slice * s;
         S.tr = TraceDev{};
         S.tr.f_half = reinterpret_cast<double*>(t);
@@ -1526,16 +1543,17 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     // Algorithm 3, steps 1-9, every slice in each launch
     const ItemTable tprep = table(c, BS_PREP), tproj = table(c, BS_PROJECT),
                     tbp = table(c, BS_BACKPROJECT), tvec = table(c, BS_VEC), ttv = table(c, BS_TV),
-                    tone = table(c, BS_SLICE, 0, 0);
+                    tone = table(c, BS_SLICE, 0, 0),
+                    tcomb = table(c, BS_PROJ_COMB, B.order[BS_PROJECT], 0);
     launch_prep_b(st, sl, tprep, BV_XH);
-    launch_project_b(st, sl, tproj, true);
+    launch_project_b(st, sl, tproj, tcomb, true);
     launch_scalar_b(st, sl, tone, OP_F0);
     launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false);
     batch_precond(c, mu, rho);
     launch_scalar_b(st, sl, tone, OP_BETA);
     launch_update_p_b(st, sl, tvec);
     launch_prep_b(st, sl, tprep, BV_P);
-    launch_project_b(st, sl, tproj, false);
+    launch_project_b(st, sl, tproj, tcomb, false);
     launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true);
     launch_scalar_b(st, sl, tone, OP_ALPHA0);
     launch_update_x_b(st, sl, tvec);
@@ -1556,14 +1574,14 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
             launch_copy_b(st, sl, tvec, BV_X, BV_XH);
         }
         launch_prep_b(st, sl, tprep, BV_XH);
-        launch_project_b(st, sl, tproj, true);
+        launch_project_b(st, sl, tproj, tcomb, true);
         launch_scalar_b(st, sl, tone, OP_F);
         launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false);
         batch_precond(c, mu, rho);
         launch_scalar_b(st, sl, tone, OP_BETA);
         launch_update_p_b(st, sl, tvec);
         launch_prep_b(st, sl, tprep, BV_P);
-        launch_project_b(st, sl, tproj, false);
+        launch_project_b(st, sl, tproj, tcomb, false);
         launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true);
         launch_scalar_b(st, sl, tone, OP_ALPHA);
         launch_update_x_b(st, sl, tvec);
@@ -1642,7 +1660,9 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         if (q.halt) status = q.halt;
         else if (q.exhausted) status = SP_TRIALS_EXHAUSTED;
         if (q.halt == SP_BREAKDOWN_CONVERGED && q.k > 1)
-            HIP_TRY(c, hipMemcpyAsync(B.hs[s].x, B.hs[s].xh, (size_t)B.hs[s].n * 4, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(c, hipMemcpyAsync(B.hs[s].x, B.hs[s].xh, (size_t)B.hs[s].n * 8, hipMemcpyDeviceToDevice, st));
+        launch_narrow(st, B.hs[s].n, B.hs[s].xh, x_out[s]);
+        if (x_last && x_last[s]) launch_narrow(st, B.hs[s].n, B.hs[s].x, x_last[s]);
         if (status < 16 && first_err == SP_OK) {
             first_err = status;
             fail(c, status, "slice %d: non-finite value in a CG scalar", s);

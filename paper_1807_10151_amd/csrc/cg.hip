@@ -2,7 +2,9 @@
 // Algorithm 2 (U_PCG):  beta = z^T h / p^T h,  p <- -z + beta p,
 // alpha = -g^T p / p^T h,  x <- x + alpha p.
 //
-// Dot products are float64 partial sums per workgroup (fixed order); a single
+// The iterate x, x_{k+1/2} and the direction p are float64 vectors; g, z and
+// h are float32.  Dot products are float64 partial sums per workgroup (fixed
+// order); a single
 // workgroup (k_scalar) sums them and updates the device-resident scalars, so a
 // loop body needs no host synchronisation and can be captured in a graph.
 #include "sp_internal.h"
@@ -42,23 +44,23 @@ void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* p
 // p <- -z + beta p (beta from the scalars), partials of g^T p (new p).
 // Virtual block bx of a grid of gx blocks (grid-stride over n).
 __device__ __forceinline__ void update_p_body(int n, const float* __restrict__ z,
-                                              float* __restrict__ p, const float* __restrict__ g,
+                                              double* __restrict__ p, const float* __restrict__ g,
                                               const Scalars* __restrict__ sc,
                                               double* __restrict__ partials, int bx, int gx) {
     __shared__ double red[4];
     const double beta = sc->beta;
     double acc = 0.0;
     for (int q = bx * 256 + threadIdx.x; q < n; q += gx * 256) {
-        const float v = (float)(-(double)z[q] + beta * (double)p[q]);
+        const double v = fma(beta, p[q], -(double)z[q]);
         p[q] = v;
-        acc += (double)g[q] * (double)v;
+        acc += (double)g[q] * v;
     }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) partials[bx] = tot;
 }
 
 __global__ __launch_bounds__(256) void k_update_p(int n, const float* __restrict__ z,
-                                                  float* __restrict__ p,
+                                                  double* __restrict__ p,
                                                   const float* __restrict__ g,
                                                   const Scalars* __restrict__ sc,
                                                   double* __restrict__ partials,
@@ -67,43 +69,67 @@ __global__ __launch_bounds__(256) void k_update_p(int n, const float* __restrict
     update_p_body(n, z, p, g, sc, partials, blockIdx.x, gridDim.x);
 }
 
-void launch_update_p(hipStream_t st, int n, const float* z, float* p, const float* g,
+void launch_update_p(hipStream_t st, int n, const float* z, double* p, const float* g,
                      const Scalars* sc, double* partials, const int* halt) {
     hipLaunchKernelGGL(k_update_p, dim3(vec_blocks(n)), dim3(256), 0, st, n, z, p, g, sc, partials,
                        halt);
 }
 
 // x <- xh + alpha p
-__device__ __forceinline__ void update_x_body(int n, const float* __restrict__ xh,
-                                              const float* __restrict__ p, float* __restrict__ x,
+__device__ __forceinline__ void update_x_body(int n, const double* __restrict__ xh,
+                                              const double* __restrict__ p, double* __restrict__ x,
                                               const Scalars* __restrict__ sc, int bx, int gx) {
     const double alpha = sc->alpha;
     for (int q = bx * 256 + threadIdx.x; q < n; q += gx * 256)
-        x[q] = (float)((double)xh[q] + alpha * (double)p[q]);
+        x[q] = fma(alpha, p[q], xh[q]);
 }
 
-__global__ __launch_bounds__(256) void k_update_x(int n, const float* __restrict__ xh,
-                                                  const float* __restrict__ p,
-                                                  float* __restrict__ x,
+__global__ __launch_bounds__(256) void k_update_x(int n, const double* __restrict__ xh,
+                                                  const double* __restrict__ p,
+                                                  double* __restrict__ x,
                                                   const Scalars* __restrict__ sc,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
     update_x_body(n, xh, p, x, sc, blockIdx.x, gridDim.x);
 }
 
-void launch_update_x(hipStream_t st, int n, const float* xh, const float* p, float* x,
+void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, double* x,
                      const Scalars* sc, const int* halt) {
     hipLaunchKernelGGL(k_update_x, dim3(vec_blocks(n)), dim3(256), 0, st, n, xh, p, x, sc, halt);
 }
 
-__global__ __launch_bounds__(256) void k_copy(int n, const float* __restrict__ src,
-                                              float* __restrict__ dst, const int* __restrict__ halt) {
+template <class T>
+__global__ __launch_bounds__(256) void k_copy(int n, const T* __restrict__ src, T* __restrict__ dst,
+                                              const int* __restrict__ halt) {
     if (halt && *halt) return;
     for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) dst[q] = src[q];
 }
 
 void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int* halt) {
-    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst, halt);
+    hipLaunchKernelGGL(k_copy<float>, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst, halt);
+}
+
+void launch_copy(hipStream_t st, int n, const double* src, double* dst, const int* halt) {
+    hipLaunchKernelGGL(k_copy<double>, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst, halt);
+}
+
+__global__ __launch_bounds__(256) void k_widen(int n, const float* __restrict__ src,
+                                               double* __restrict__ dst) {
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256)
+        dst[q] = src ? (double)src[q] : 0.0;
+}
+
+void launch_widen(hipStream_t st, int n, const float* src, double* dst) {
+    hipLaunchKernelGGL(k_widen, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst);
+}
+
+__global__ __launch_bounds__(256) void k_narrow(int n, const double* __restrict__ src,
+                                                float* __restrict__ dst) {
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) dst[q] = (float)src[q];
+}
+
+void launch_narrow(hipStream_t st, int n, const double* src, float* dst) {
+    hipLaunchKernelGGL(k_narrow, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst);
 }
 
 // dst[iter][:] = src for the loop body index iter held in the scalars, while
@@ -221,8 +247,8 @@ __global__ __launch_bounds__(256) void kb_copy(const SliceDev* __restrict__ sl, 
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
-        const float* a = batch_vec(S, src);
-        float* d = batch_vec(S, dst);
+        const double* a = batch_vec(S, src);
+        double* d = batch_vec(S, dst);
         const int gx = vec_blocks_dev(S.n);
         for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) d[q] = a[q];
     });
@@ -233,7 +259,7 @@ __global__ __launch_bounds__(256) void kb_init(const SliceDev* __restrict__ sl, 
         const SliceDev& S = sl[s];
         const int gx = vec_blocks_dev(S.n);
         for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) {
-            const float v = S.x0 ? gmem(S.x0)[q] : 0.0f;
+            const double v = S.x0 ? (double)gmem(S.x0)[q] : 0.0;
             gmem(S.xh)[q] = v;
             gmem(S.x)[q] = v;
         }

@@ -32,17 +32,19 @@
 
 namespace sp {
 
-// 32 x 32 tile (bx, by): padded copy and padded transposed copy.
-__device__ __forceinline__ void prep_body(const GeomDev& G, const float* __restrict__ x,
+// 32 x 32 tile (bx, by): padded copy and padded transposed copy of a float32
+// image or of a float64 iterate.
+template <class T>
+__device__ __forceinline__ void prep_body(const GeomDev& G, const T* __restrict__ x,
                                           double* __restrict__ xp, double* __restrict__ xTp, int bx,
                                           int by) {
-    __shared__ float tile[32][33];
+    __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int j = bx * 32 + tx;
 #pragma unroll
     for (int r = 0; r < 32; r += 8) {
         const int i = by * 32 + ty + r;
-        float v = 0.0f;
+        T v = 0;
         if (i < G.rows && j < G.cols) {
             v = x[(size_t)i * G.cols + j];
             xp[(size_t)i * G.pitchX + PAD + j] = (double)v;
@@ -59,7 +61,8 @@ __device__ __forceinline__ void prep_body(const GeomDev& G, const float* __restr
     }
 }
 
-__global__ __launch_bounds__(256) void k_prep(GeomDev G, const float* __restrict__ x,
+template <class T>
+__global__ __launch_bounds__(256) void k_prep(GeomDev G, const T* __restrict__ x,
                                               double* __restrict__ xp, double* __restrict__ xTp,
                                               const int* __restrict__ halt) {
     if (halt && *halt) return;
@@ -83,7 +86,13 @@ void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which) {
 void launch_prep(hipStream_t st, const GeomDev& G, const float* x, double* xp, double* xTp,
                  const int* halt) {
     dim3 grid((G.cols + 31) / 32, (G.rows + 31) / 32);
-    hipLaunchKernelGGL(k_prep, grid, dim3(256), 0, st, G, x, xp, xTp, halt);
+    hipLaunchKernelGGL(k_prep<float>, grid, dim3(256), 0, st, G, x, xp, xTp, halt);
+}
+
+void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, double* xTp,
+                 const int* halt) {
+    dim3 grid((G.cols + 31) / 32, (G.rows + 31) / 32);
+    hipLaunchKernelGGL(k_prep<double>, grid, dim3(256), 0, st, G, x, xp, xTp, halt);
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -123,11 +132,14 @@ __device__ __forceinline__ const T* at(const T* base, unsigned o) {
     return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + o * (unsigned)sizeof(T));
 }
 
-// One ray's sum.  HORIZ = walk columns of the transposed copy.  img points at
-// element PAD of row 0 of the padded copy.
+// One ray's sum, or part `part` of nparts of it.  HORIZ = walk columns of the
+// transposed copy.  img points at element PAD of row 0 of the padded copy.  A
+// part covers the steps [lo + len*part/nparts, lo + len*(part+1)/nparts) of
+// the wave's common step range [lo, lo + len).
 template <bool HORIZ, bool AXIS, int NC>
 __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, double sk,
-                                          const double* __restrict__ img, bool valid) {
+                                          const double* __restrict__ img, bool valid, int part,
+                                          int nparts) {
     const int nmaj = HORIZ ? G.cols : G.rows;
     const int nmin = HORIZ ? G.rows : G.cols;
     const int pitch = HORIZ ? G.pitchXT : G.pitchX;
@@ -144,6 +156,12 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     }
     lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
     hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
+    if (nparts > 1 && hi > lo) {
+        const int len = hi - lo;
+        const int l0 = lo + len * part / nparts;
+        hi = lo + len * (part + 1) / nparts;
+        lo = l0;
+    }
     double acc = 0.0;
     if (lo >= hi) return acc;
     // Candidate q of step m is minor index floor(nf_m) + 1 + q.  nf carries the
@@ -204,37 +222,22 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
 
 template <bool HORIZ, bool AXIS>
 __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A, double sk,
-                                             const double* __restrict__ img, bool valid) {
-    return A.nc == 3 ? ray_sum<HORIZ, AXIS, 3>(G, A, sk, img, valid)
-                     : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, valid);
+                                             const double* __restrict__ img, bool valid,
+                                             int part, int nparts) {
+    return A.nc == 3 ? ray_sum<HORIZ, AXIS, 3>(G, A, sk, img, valid, part, nparts)
+                     : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, valid, part, nparts);
 }
 
-// (R x)_{row,k}, or the residual (R x - b) with its float64 squared norm per
-// workgroup in partials when b != nullptr, rounded to float32 and stored to
-// out[row*out_pitch + k] (nullable) and to the padded sinogram
-// outp[row*pitchB + PAD + k] (nullable).  Block bx indexes the class-sorted
-// angle table, by the 256-bin chunk.
-__device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* __restrict__ ang,
-                                             const double* __restrict__ xp,
-                                             const double* __restrict__ xTp,
-                                             const float* __restrict__ b, float* __restrict__ out,
-                                             int out_pitch, float* __restrict__ outp,
-                                             double* __restrict__ partials, int bx, int by, int gx) {
+// Stores ray (row a, bin k) of the workgroup's 256-bin chunk: (R x)_{a,k}, or
+// the residual (R x - b) with its float64 squared norm per workgroup in
+// partials[by * gx + bx] when b != nullptr, rounded to float32 and stored to
+// out[a*out_pitch + k] (nullable) and to the padded sinogram
+// outp[a*pitchB + PAD + k] (nullable).
+__device__ __forceinline__ void project_store(const GeomDev& G, int a, int k, bool valid, double acc,
+                                              const float* __restrict__ b, float* __restrict__ out,
+                                              int out_pitch, float* __restrict__ outp,
+                                              double* __restrict__ partials, int bx, int by, int gx) {
     __shared__ double red[4];
-    const AngleDev A = ang[bx];
-    const int a = A.row;
-    const int k = by * 256 + threadIdx.x;
-    const bool valid = k < G.nB;
-    const double sk = bin_pos((double)k, G);
-    const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
-    double acc;
-    if (!horiz) {
-        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, valid)
-                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, valid);
-    } else {
-        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, valid)
-                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid);
-    }
     double r2 = 0.0;
     if (valid) {
         float val;
@@ -253,6 +256,62 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
     }
 }
 
+// Rays of block (bx, by): bx indexes the class-sorted angle table, by the
+// 256-bin chunk.  With seg == nullptr each ray is summed whole and stored by
+// project_store.  Otherwise (G.parts > 1) only part `part` of each ray is
+// summed and its float64 value goes to seg[(part*nA + bx)*nB + k]; the
+// combine step adds the parts in order.  Splitting the rays keeps the image
+// rows that the resident waves read close together and makes the work items
+// shorter and more even.
+__device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* __restrict__ ang,
+                                             const double* __restrict__ xp,
+                                             const double* __restrict__ xTp,
+                                             const float* __restrict__ b, float* __restrict__ out,
+                                             int out_pitch, float* __restrict__ outp,
+                                             double* __restrict__ partials,
+                                             double* __restrict__ seg, int bx, int by, int part,
+                                             int gx) {
+    const AngleDev A = ang[bx];
+    const int k = by * 256 + threadIdx.x;
+    const bool valid = k < G.nB;
+    const double sk = bin_pos((double)k, G);
+    const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
+    const int np = seg ? G.parts : 1;
+    double acc;
+    if (!horiz) {
+        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, valid, part, np)
+                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, valid, part, np);
+    } else {
+        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, valid, part, np)
+                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid, part, np);
+    }
+    if (seg) {
+        if (valid) seg[((size_t)part * G.nA + bx) * G.nB + k] = acc;
+        return;
+    }
+    project_store(G, A.row, k, valid, acc, b, out, out_pitch, outp, partials, bx, by, gx);
+}
+
+// Sum of the parts of the rays of block (bx, by), then the store.
+__device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleDev* __restrict__ ang,
+                                                  const double* __restrict__ seg,
+                                                  const float* __restrict__ b,
+                                                  float* __restrict__ out, int out_pitch,
+                                                  float* __restrict__ outp,
+                                                  double* __restrict__ partials, int bx, int by,
+                                                  int gx) {
+    const int a = ang[bx].row;
+    const int k = by * 256 + threadIdx.x;
+    const bool valid = k < G.nB;
+    double acc = 0.0;
+    if (valid) {
+        const double* v = seg + (size_t)bx * G.nB + k;
+        const size_t stride = (size_t)G.nA * G.nB;
+        for (int j = 0; j < G.parts; ++j) acc += v[j * stride];
+    }
+    project_store(G, a, k, valid, acc, b, out, out_pitch, outp, partials, bx, by, gx);
+}
+
 __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
                                                  const double* __restrict__ xp,
                                                  const double* __restrict__ xTp,
@@ -262,11 +321,35 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, partials, blockIdx.x, blockIdx.y,
-                 gridDim.x);
+    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, partials, nullptr, blockIdx.x,
+                 blockIdx.y, 0, gridDim.x);
 }
 
-// residual: rp = R xh - b with f partials; else rp = R p.
+// grid (nA, chunks, parts): blockIdx.z is the part, so the parts run in order.
+__global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev* __restrict__ ang,
+                                                      const double* __restrict__ xp,
+                                                      const double* __restrict__ xTp,
+                                                      double* __restrict__ seg,
+                                                      const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, seg, blockIdx.x,
+                 blockIdx.y, blockIdx.z, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev* __restrict__ ang,
+                                                      const double* __restrict__ seg,
+                                                      const float* __restrict__ b,
+                                                      float* __restrict__ out, int out_pitch,
+                                                      float* __restrict__ outp,
+                                                      double* __restrict__ partials,
+                                                      const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    project_comb_body(G, ang, seg, b, out, out_pitch, outp, partials, blockIdx.x, blockIdx.y,
+                      gridDim.x);
+}
+
+// residual: rp = R xh - b with f partials; else rp = R p.  Virtual block
+// lin = (part * chunks + by) * nA + bx.
 __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
                                                   int residual) {
     for_items(t, [&](int s, int lin) {
@@ -274,22 +357,60 @@ __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ s
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = G.nA;
-        project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), residual ? gmem(S.b) : nullptr,
-                     nullptr, 0, gmem(S.rp), residual ? gmem(S.pf) : nullptr, lin % gx, lin / gx,
-                     gx);
+        const int bx = lin % gx, r = lin / gx;
+        if (G.parts > 1) {
+            const int chunks = (G.nB + 255) / 256;
+            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, nullptr,
+                         nullptr, gmem(S.seg), bx, r % chunks, r / chunks, gx);
+        } else {
+            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), residual ? gmem(S.b) : nullptr,
+                         nullptr, 0, gmem(S.rp), residual ? gmem(S.pf) : nullptr, nullptr, bx, r, 0,
+                         gx);
+        }
     });
 }
 
-void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, bool residual) {
+// The combine step of the slices with G.parts > 1; virtual block by * nA + bx.
+__global__ __launch_bounds__(256) void kb_project_comb(const SliceDev* __restrict__ sl, ItemTable t,
+                                                       int residual) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (gmem(S.sc)->halt) return;
+        const GeomDev G = S.G;
+        const int gx = G.nA;
+        project_comb_body(G, cmem(S.ang), gmem(S.seg), residual ? gmem(S.b) : nullptr, nullptr, 0,
+                          gmem(S.rp), residual ? gmem(S.pf) : nullptr, lin % gx, lin / gx, gx);
+    });
+}
+
+void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable tc,
+                      bool residual) {
     hipLaunchKernelGGL(kb_project, dim3(t.grid), dim3(256), 0, st, sl, t, residual ? 1 : 0);
+    if (tc.n > 0)
+        hipLaunchKernelGGL(kb_project_comb, dim3(tc.grid), dim3(256), 0, st, sl, tc,
+                           residual ? 1 : 0);
 }
 
 int project_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
 
+int project_parts(int rows, int cols) {
+    const int side = rows > cols ? rows : cols;
+    if (side < 192) return 1;
+    const int p = (side + 128) / 256;
+    return p < 3 ? 3 : (p > 8 ? 8 : p);
+}
+
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* partials, const int* halt) {
+                    double* partials, double* seg, const int* halt) {
     dim3 grid(G.nA, (G.nB + 255) / 256);
+    if (G.parts > 1) {
+        hipLaunchKernelGGL(k_project_part, dim3(G.nA, (G.nB + 255) / 256, G.parts), dim3(256), 0,
+                           st, G, ang, xp, xTp, seg, halt);
+        hipLaunchKernelGGL(k_project_comb, grid, dim3(256), 0, st, G, ang, (const double*)seg, b,
+                           out, out_pitch, outp, partials, halt);
+        return;
+    }
     hipLaunchKernelGGL(k_project, grid, dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
                        outp, partials, halt);
 }
@@ -367,7 +488,7 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
                                                  const float* __restrict__ yp,
                                                  const double* __restrict__ skg, double* sks,
                                                  float* __restrict__ out,
-                                                 const float* __restrict__ dotv,
+                                                 const double* __restrict__ dotv,
                                                  double* __restrict__ partials, int bx, int by,
                                                  int gx) {
     __shared__ double part[BP_SPLIT][64];
@@ -401,7 +522,7 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
         const bool valid = i < G.rows && j < G.cols;
         if (valid) {
             out[(size_t)i * G.cols + j] = val;
-            if (dotv) v = (double)val * (double)dotv[(size_t)i * G.cols + j];
+            if (dotv) v = (double)val * dotv[(size_t)i * G.cols + j];
         }
     }
     if (dotv) {
@@ -415,7 +536,7 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
                                                      const float* __restrict__ yp,
                                                      const double* __restrict__ skg,
                                                      float* __restrict__ out,
-                                                     const float* __restrict__ dotv,
+                                                     const double* __restrict__ dotv,
                                                      double* __restrict__ partials,
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
@@ -469,7 +590,7 @@ int backproject_blocks(const GeomDev& G) {
 
 template <bool LSK>
 void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
-               const double* skp, float* out, const float* dotv, double* partials, const int* halt,
+               const double* skp, float* out, const double* dotv, double* partials, const int* halt,
                size_t lds) {
     dim3 grid((G.cols + BP_TILE - 1) / BP_TILE, (G.rows + BP_TILE - 1) / BP_TILE);
     switch (G.nbmax) {
@@ -481,7 +602,7 @@ void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const floa
 }
 
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
-                        const double* skp, float* out, const float* dotv, double* partials,
+                        const double* skp, float* out, const double* dotv, double* partials,
                         const int* halt) {
     const size_t lds = bp_lds_bytes(G.nB);
     if (lds) launch_bp<true>(st, G, ang, yp, skp, out, dotv, partials, halt, lds);

@@ -47,6 +47,7 @@ struct GeomDev {
     int pitchXT;        // rows + 2 PAD: row pitch of the padded transposed copy
     int pitchB;         // nB + 2 PAD: row pitch of the padded sinogram
     int nbmax;          // max backprojection candidates over the angles
+    int parts;          // parts each ray's step range is split into by R (1: whole rays)
     int cls[5];         // angle-table class boundaries: vertical, horizontal,
                         // vertical axis, horizontal axis
 };
@@ -115,16 +116,23 @@ __device__ __forceinline__ double bin_pos(double k, const GeomDev& G) { return f
 // conversion per candidate.  The padded sinogram (yp) stays float32.
 void launch_prep(hipStream_t st, const GeomDev& G, const float* x, double* xp, double* xTp,
                  const int* halt);
+void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, double* xTp,
+                 const int* halt);
+// With G.parts > 1, seg (parts * nA * nB float64) receives the per-part sums
+// before they are combined.
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* partials, const int* halt);
+                    double* partials, double* seg, const int* halt);
 int project_blocks(const GeomDev& G);
+// Parts R splits each ray's step range into, chosen from the image size (both
+// the single-slice and the batched solver use it, so their sums agree).
+int project_parts(int rows, int cols);
 void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp);
 // skp: float64 bin positions of the padded bin range, skp[PAD + k] = s_k
 // (bin_sk_table fills it on the host with the same fma as bin_pos); used when
 // the table is too large for the backprojector's LDS copy.
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
-                        const double* skp, float* out, const float* dotv, double* partials,
+                        const double* skp, float* out, const double* dotv, double* partials,
                         const int* halt);
 int backproject_blocks(const GeomDev& G);
 
@@ -139,30 +147,34 @@ void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, con
                     const int* run = nullptr);
 int precond_dot_blocks(const FFTPlan& F);
 
-// tv.hip
-void launch_tv_grad(hipStream_t st, int rows, int cols, const float* y, float* tb, double* partials,
+// tv.hip (images y, x_{k+1/2} and x_k in float64; t_bar float32)
+void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
                     const int* halt);
 int tv_blocks(int rows, int cols);
-void launch_tv_trials(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+void launch_tv_trials(hipStream_t st, int rows, int cols, const double* y, const float* tb,
                       const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
                       const int* halt);
-void launch_tv_decide(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+void launch_tv_decide(hipStream_t st, int rows, int cols, const double* y, const float* tb,
                       const double* gpart, int ngpart, const double* tpart, int ntpart, int J,
                       Scalars* sc, TraceDev tr, int32_t* trials_out, const int* halt);
-void launch_tv_apply(hipStream_t st, int n, const float* src, float* dst, const float* tb,
-                     const Scalars* sc, const float* xk, double* partials, const int* halt);
-void launch_tv_value(hipStream_t st, int rows, int cols, const float* y, double* partials,
+void launch_tv_apply(hipStream_t st, int n, const double* src, double* dst, const float* tb,
+                     const Scalars* sc, const double* xk, double* partials, const int* halt);
+void launch_tv_value(hipStream_t st, int rows, int cols, const double* y, double* partials,
                      const int* halt);
 
-// cg.hip
+// cg.hip (p, x and x_{k+1/2} in float64; g, z, h float32)
 int vec_blocks(int n);
 void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* partials,
                 const int* halt);
-void launch_update_p(hipStream_t st, int n, const float* z, float* p, const float* g,
+void launch_update_p(hipStream_t st, int n, const float* z, double* p, const float* g,
                      const Scalars* sc, double* partials, const int* halt);
-void launch_update_x(hipStream_t st, int n, const float* xh, const float* p, float* x,
+void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, double* x,
                      const Scalars* sc, const int* halt);
 void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int* halt);
+void launch_copy(hipStream_t st, int n, const double* src, double* dst, const int* halt);
+// dst = src widened to float64 (src == nullptr: zeros); dst = src rounded to float32
+void launch_widen(hipStream_t st, int n, const float* src, double* dst);
+void launch_narrow(hipStream_t st, int n, const double* src, float* dst);
 void launch_snap(hipStream_t st, int n, const float* src, float* dst, int count, const Scalars* sc);
 void launch_reduce(hipStream_t st, const double* partials, int np, double* out);
 
@@ -206,9 +218,11 @@ struct SliceDev {
     const double* skp;  // padded bin positions
     const float* b;
     const float* x0;   // nullable: zero start
-    float *xh, *x, *p, *h, *g, *z, *tb;
+    double *xh, *x, *p;  // iterate, x_{k+1/2} and search direction (float64)
+    float *h, *g, *z, *tb;
     double *xp, *xTp;   // float64 padded copies
     float* rp;          // padded sinogram
+    double* seg;        // R's per-part ray sums, [parts][nA][nB] (G.parts > 1)
     double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
     Scalars* sc;
     TraceDev tr;
@@ -218,7 +232,8 @@ struct SliceDev {
 // Stage selectors of the batched kernels.
 enum BatchVec : int { BV_XH = 0, BV_X = 1, BV_P = 2 };
 enum BatchStage : int {
-    BS_PREP = 0, BS_PROJECT, BS_BACKPROJECT, BS_ROWS, BS_COLS, BS_TV, BS_VEC, BS_SLICE, BS_COUNT
+    BS_PREP = 0, BS_PROJECT, BS_BACKPROJECT, BS_ROWS, BS_COLS, BS_TV, BS_VEC, BS_SLICE, BS_PROJ_COMB,
+    BS_COUNT
 };
 struct ItemTable {
     const uint32_t* items;
@@ -252,13 +267,13 @@ __device__ __forceinline__ const T* cmem(const T* p) {
     return (const T*)(__attribute__((address_space(4))) const T*)(uintptr_t)p;
 }
 
-__device__ __forceinline__ float* batch_vec(const SliceDev& S, int which) {
+__device__ __forceinline__ double* batch_vec(const SliceDev& S, int which) {
     return gmem(which == BV_XH ? S.xh : (which == BV_X ? S.x : S.p));
 }
 
 // projector.hip
 void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which);
-void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, bool residual);
+void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable tc, bool residual);
 void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
                           bool normal);
 // fft.hip (z = M g; with the partials of z^T h into pzh)

@@ -20,34 +20,35 @@ namespace sp {
 
 constexpr int TVJ = 8;
 
-// t_bar at pixel p = (i, j) of a rows x cols float32 image (reading: the
-// partial derivative is undefined when a square-root term it enters is zero).
-__device__ __forceinline__ float tv_neg_grad(const float* __restrict__ y, int rows, int cols,
+// t_bar at pixel p = (i, j) of a rows x cols float64 image, evaluated in
+// float64 and rounded to float32 (reading: the partial derivative is
+// undefined when a square-root term it enters is zero).
+__device__ __forceinline__ float tv_neg_grad(const double* __restrict__ y, int rows, int cols,
                                              int i, int j, size_t p) {
-    const float v = y[p];
-    float gsum = 0.0f;
+    const double v = y[p];
+    double gsum = 0.0;
     bool bad = false;
     if (i < rows - 1 && j < cols - 1) {          // T_{i,j}
-        const float dv = v - y[p + cols], dh = v - y[p + 1];
-        if (dv == 0.0f && dh == 0.0f) bad = true;
-        else gsum += (dv + dh) / sqrtf(dv * dv + dh * dh);
+        const double dv = v - y[p + cols], dh = v - y[p + 1];
+        if (dv == 0.0 && dh == 0.0) bad = true;
+        else gsum += (dv + dh) / sqrt(dv * dv + dh * dh);
     }
     if (i >= 1 && j < cols - 1) {                // T_{i-1,j}
-        const float u = y[p - cols];
-        const float dv = u - v, dh = u - y[p - cols + 1];
-        if (dv == 0.0f && dh == 0.0f) bad = true;
-        else gsum -= dv / sqrtf(dv * dv + dh * dh);
+        const double u = y[p - cols];
+        const double dv = u - v, dh = u - y[p - cols + 1];
+        if (dv == 0.0 && dh == 0.0) bad = true;
+        else gsum -= dv / sqrt(dv * dv + dh * dh);
     }
     if (i < rows - 1 && j >= 1) {                // T_{i,j-1}
-        const float u = y[p - 1];
-        const float dv = u - y[p - 1 + cols], dh = u - v;
-        if (dv == 0.0f && dh == 0.0f) bad = true;
-        else gsum -= dh / sqrtf(dv * dv + dh * dh);
+        const double u = y[p - 1];
+        const double dv = u - y[p - 1 + cols], dh = u - v;
+        if (dv == 0.0 && dh == 0.0) bad = true;
+        else gsum -= dh / sqrt(dv * dv + dh * dh);
     }
-    return bad ? 0.0f : -gsum;
+    return bad ? 0.0f : (float)(-gsum);
 }
 
-__device__ __forceinline__ void tv_grad_body(int rows, int cols, const float* __restrict__ y,
+__device__ __forceinline__ void tv_grad_body(int rows, int cols, const double* __restrict__ y,
                                              float* __restrict__ tb, double* __restrict__ partials,
                                              int bx) {
     __shared__ double red[4];
@@ -64,7 +65,7 @@ __device__ __forceinline__ void tv_grad_body(int rows, int cols, const float* __
     if (partials && threadIdx.x == 0) partials[bx] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const float* __restrict__ y,
+__global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const double* __restrict__ y,
                                                  float* __restrict__ tb,
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ halt) {
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const float
 
 int tv_blocks(int rows, int cols) { return (int)(((size_t)rows * cols + 255) / 256); }
 
-void launch_tv_grad(hipStream_t st, int rows, int cols, const float* y, float* tb, double* partials,
+void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
                     const int* halt) {
     hipLaunchKernelGGL(k_tv_grad, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
                        partials, halt);
@@ -82,11 +83,11 @@ void launch_tv_grad(hipStream_t st, int rows, int cols, const float* y, float* t
 
 // TV terms of pixel p for the base image (q = 0) and nq trial steps lam[0..nq).
 template <int NQ>
-__device__ __forceinline__ void tv_terms(const float* __restrict__ y, const float* __restrict__ tb,
+__device__ __forceinline__ void tv_terms(const double* __restrict__ y, const float* __restrict__ tb,
                                          int cols, size_t p, const double* lam, int nq,
                                          double* acc) {
-    const double dv = (double)y[p] - (double)y[p + cols];
-    const double dh = (double)y[p] - (double)y[p + 1];
+    const double dv = y[p] - y[p + cols];
+    const double dh = y[p] - y[p + 1];
     const double ev = (double)tb[p] - (double)tb[p + cols];
     const double eh = (double)tb[p] - (double)tb[p + 1];
     acc[0] += sqrt(dv * dv + dh * dh);
@@ -105,7 +106,7 @@ __device__ __forceinline__ double trial_lambda(const Scalars* sc, int trial, dou
     return tn > 0.0 ? sc->gamma * pow(sc->a, (double)(sc->ell + trial)) / tn : 0.0;
 }
 
-__device__ __forceinline__ void tv_trials_body(int rows, int cols, const float* __restrict__ y,
+__device__ __forceinline__ void tv_trials_body(int rows, int cols, const double* __restrict__ y,
                                                const float* __restrict__ tb,
                                                const double* __restrict__ gpart, int ngpart,
                                                const Scalars* __restrict__ sc,
@@ -135,7 +136,7 @@ __device__ __forceinline__ void tv_trials_body(int rows, int cols, const float* 
     }
 }
 
-__global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const float* __restrict__ y,
+__global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const double* __restrict__ y,
                                                    const float* __restrict__ tb,
                                                    const double* __restrict__ gpart, int ngpart,
                                                    const Scalars* __restrict__ sc,
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(256) void k_tv_trials(int rows, int cols, const flo
     tv_trials_body(rows, cols, y, tb, gpart, ngpart, sc, tpart, blockIdx.x);
 }
 
-void launch_tv_trials(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+void launch_tv_trials(hipStream_t st, int rows, int cols, const double* y, const float* tb,
                       const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
                       const int* halt) {
     (void)J;
@@ -155,7 +156,7 @@ void launch_tv_trials(hipStream_t st, int rows, int cols, const float* y, const 
 
 // One workgroup evaluates TV(y) and TV(y + lam_q t_bar), q < nq, over the whole
 // image (the rare path of k_tv_decide).  out[0] = TV(y), out[1 + q] = trials.
-__device__ void tv_trials_wg(const float* __restrict__ y, const float* __restrict__ tb, int rows,
+__device__ void tv_trials_wg(const double* __restrict__ y, const float* __restrict__ tb, int rows,
                              int cols, const double* lam, int nq, double* out, double* red) {
     double acc[TVJ + 1];
 #pragma unroll
@@ -174,7 +175,7 @@ __device__ void tv_trials_wg(const float* __restrict__ y, const float* __restric
     __syncthreads();
 }
 
-__device__ __forceinline__ void tv_decide_body(int rows, int cols, const float* __restrict__ y,
+__device__ __forceinline__ void tv_decide_body(int rows, int cols, const double* __restrict__ y,
                                                const float* __restrict__ tb,
                                                const double* __restrict__ gpart, int ngpart,
                                                const double* __restrict__ tpart, int ntpart,
@@ -281,7 +282,7 @@ __device__ __forceinline__ void tv_decide_body(int rows, int cols, const float* 
     }
 }
 
-__global__ __launch_bounds__(256) void k_tv_decide(int rows, int cols, const float* __restrict__ y,
+__global__ __launch_bounds__(256) void k_tv_decide(int rows, int cols, const double* __restrict__ y,
                                                    const float* __restrict__ tb,
                                                    const double* __restrict__ gpart, int ngpart,
                                                    const double* __restrict__ tpart, int ntpart,
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(256) void k_tv_decide(int rows, int cols, const flo
     tv_decide_body(rows, cols, y, tb, gpart, ngpart, tpart, ntpart, sc, tr, trials_out);
 }
 
-void launch_tv_decide(hipStream_t st, int rows, int cols, const float* y, const float* tb,
+void launch_tv_decide(hipStream_t st, int rows, int cols, const double* y, const float* tb,
                       const double* gpart, int ngpart, const double* tpart, int ntpart, int J,
                       Scalars* sc, TraceDev tr, int32_t* trials_out, const int* halt) {
     (void)J;
@@ -300,20 +301,20 @@ void launch_tv_decide(hipStream_t st, int rows, int cols, const float* y, const 
                        tpart, ntpart, sc, tr, trials_out, halt);
 }
 
-__device__ __forceinline__ void tv_apply_body(int n, const float* __restrict__ src,
-                                              float* __restrict__ dst, const float* __restrict__ tb,
+__device__ __forceinline__ void tv_apply_body(int n, const double* __restrict__ src,
+                                              double* __restrict__ dst, const float* __restrict__ tb,
                                               const Scalars* __restrict__ sc,
-                                              const float* __restrict__ xk,
+                                              const double* __restrict__ xk,
                                               double* __restrict__ partials, int bx) {
     __shared__ double red[4];
     const double lam = sc->lam;
     const int p = bx * 256 + threadIdx.x;
     double s2 = 0.0;
     if (p < n) {
-        const float v = (float)((double)src[p] + lam * (double)tb[p]);
+        const double v = fma(lam, (double)tb[p], src[p]);
         dst[p] = v;
         if (xk) {
-            const double s = (double)v - (double)xk[p];
+            const double s = v - xk[p];
             s2 = s * s;
         }
     }
@@ -323,24 +324,24 @@ __device__ __forceinline__ void tv_apply_body(int n, const float* __restrict__ s
     }
 }
 
-__global__ __launch_bounds__(256) void k_tv_apply(int n, const float* __restrict__ src,
-                                                  float* __restrict__ dst,
+__global__ __launch_bounds__(256) void k_tv_apply(int n, const double* __restrict__ src,
+                                                  double* __restrict__ dst,
                                                   const float* __restrict__ tb,
                                                   const Scalars* __restrict__ sc,
-                                                  const float* __restrict__ xk,
+                                                  const double* __restrict__ xk,
                                                   double* __restrict__ partials,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
     tv_apply_body(n, src, dst, tb, sc, xk, partials, blockIdx.x);
 }
 
-void launch_tv_apply(hipStream_t st, int n, const float* src, float* dst, const float* tb,
-                     const Scalars* sc, const float* xk, double* partials, const int* halt) {
+void launch_tv_apply(hipStream_t st, int n, const double* src, double* dst, const float* tb,
+                     const Scalars* sc, const double* xk, double* partials, const int* halt) {
     hipLaunchKernelGGL(k_tv_apply, dim3((n + 255) / 256), dim3(256), 0, st, n, src, dst, tb, sc, xk,
                        partials, halt);
 }
 
-__global__ __launch_bounds__(256) void k_tv_value(int rows, int cols, const float* __restrict__ y,
+__global__ __launch_bounds__(256) void k_tv_value(int rows, int cols, const double* __restrict__ y,
                                                   double* __restrict__ partials,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
@@ -351,8 +352,8 @@ __global__ __launch_bounds__(256) void k_tv_value(int rows, int cols, const floa
     if (p < n) {
         const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
         if (i < rows - 1 && j < cols - 1) {
-            const double dv = (double)y[p] - (double)y[p + cols];
-            const double dh = (double)y[p] - (double)y[p + 1];
+            const double dv = y[p] - y[p + cols];
+            const double dh = y[p] - y[p + 1];
             acc = sqrt(dv * dv + dh * dh);
         }
     }
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(256) void k_tv_value(int rows, int cols, const floa
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-void launch_tv_value(hipStream_t st, int rows, int cols, const float* y, double* partials,
+void launch_tv_value(hipStream_t st, int rows, int cols, const double* y, double* partials,
                      const int* halt) {
     hipLaunchKernelGGL(k_tv_value, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y,
                        partials, halt);

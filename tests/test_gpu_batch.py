@@ -26,7 +26,8 @@ def sp():
 
 
 def mixed_batch(sp):
-    """Mixed shapes, angle sets and bin spacings; data = R x + noise (GPU R)."""
+    """Mixed shapes, angle sets and bin spacings, with whole-ray and split-ray R;
+    data = R x + noise (GPU R)."""
     from synth import random_ellipses
     geoms = [sp.Geometry(64, 64, 90, 91),
              sp.Geometry(48, 80, 60, 97),
@@ -34,7 +35,8 @@ def mixed_batch(sp):
              sp.Geometry(100, 70, 45, 123, theta0=0.1),
              sp.Geometry(16, 16, 8, 24),
              sp.Geometry(40, 56, 70, 100, bin_spacing=0.7, bin_offset=0.3),
-             sp.Geometry(130, 96, 128, 165, dtheta=np.pi / 160)]
+             sp.Geometry(130, 96, 128, 165, dtheta=np.pi / 160),
+             sp.Geometry(200, 150, 64, 251, theta0=0.05)]   # R in parts
     bs = []
     for i, g in enumerate(geoms):
         img, rng = random_ellipses(g.rows, g.cols, 5, 300 + i)

@@ -134,8 +134,11 @@ def test_nonfinite_data_reported(sp, small):
 
 def test_gradient_snapshots(sp, small):
     # g_snap row k-1 = g_{k+1/2} = R^T (R x_{k+1/2} - b): against the oracle's
-    # x_{k+1/2} run through the oracle's R, and bitwise against the library's
-    # own R^T (R x - b) at the last body; rows past the last body stay untouched
+    # x_{k+1/2} run through the oracle's R, and against the library's own
+    # R^T (R x - b) at the last body (the solver holds x_{k+1/2} in float64,
+    # the returned x_half is its float32 rounding, so the two agree to that
+    # rounding only; successive g differ at O(1)); rows past the last body
+    # stay untouched
     og, img, b, R, prob = small
     n_it = 6
     ref = osup.suppcg(prob, np.zeros(og.n), osup.TVParams(K, A, GAMMA), n_iter=n_it,
@@ -153,4 +156,7 @@ def test_gradient_snapshots(sp, small):
     assert np.all(got[n_it:] == 7.0)
     r, _ = sp.sp_residual(g, res.x_half, cuda(b))
     own = sp.sp_backproject(g, r).cpu().numpy()
-    np.testing.assert_array_equal(got[n_it - 1], own)
+    e_own = rel_l2(got[n_it - 1], own.astype(np.float64))
+    e_prev = rel_l2(got[n_it - 2], own.astype(np.float64))
+    print(f"snapshot vs own R^T(R x_half - b): {e_own:.3e} (previous body {e_prev:.3e})", flush=True)
+    assert e_own <= 1e-4 < e_prev
