@@ -51,7 +51,7 @@ struct sp_ctx {
     sp_geometry geom{};
     GeomDev G{};
     std::vector<AngleDev> ang_h;
-    DevBuf ang, skp, xp, xTp, yp, seg;
+    DevBuf ang, skp, xp, xTp, yp, ypd, seg;
 
     // preconditioner cache
     int fftP = 0;
@@ -278,12 +278,14 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     if ((rc = ensure(c, c->xp, nX * 8))) return rc;
     if ((rc = ensure(c, c->xTp, nXT * 8))) return rc;
     if ((rc = ensure(c, c->yp, nY * 4))) return rc;
+    if ((rc = ensure(c, c->ypd, nY * 8))) return rc;
     if (G.parts > 1 && (rc = ensure(c, c->seg, (size_t)G.parts * g->n_angles * g->n_bins * 8)))
         return rc;
     if (relayout) {
         HIP_TRY(c, hipMemsetAsync(c->xp.ptr, 0, c->xp.bytes, c->stream));
         HIP_TRY(c, hipMemsetAsync(c->xTp.ptr, 0, c->xTp.bytes, c->stream));
         HIP_TRY(c, hipMemsetAsync(c->yp.ptr, 0, c->yp.bytes, c->stream));
+        HIP_TRY(c, hipMemsetAsync(c->ypd.ptr, 0, c->ypd.bytes, c->stream));
     }
     c->ang_h = tab;
     const std::vector<double> skt = bin_sk_table(G);
@@ -659,7 +661,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
     std::vector<std::vector<AngleDev>> tabs(n);
     // sizes
     struct Off {
-        size_t ang, skp, xp, xTp, rp, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
+        size_t ang, skp, xp, xTp, rp, rpd, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
     };
     std::vector<Off> off(n);
     size_t total = 0;
@@ -700,6 +702,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         o.xp = take((size_t)G.rows * G.pitchX * 8);
         o.xTp = take((size_t)G.cols * G.pitchXT * 8);
         o.rp = take((size_t)G.nA * G.pitchB * 4);
+        o.rpd = take((size_t)G.nA * G.pitchB * 8);
         o.seg = take(G.parts > 1 ? (size_t)G.parts * G.nA * G.nB * 8 : 0);
         o.dvec = take((size_t)S.n * 8 * 3);  // x, x_half, p (float64)
         o.vec = take((size_t)S.n * 4 * 4);   // h, g, z, t_bar
@@ -733,6 +736,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         S.xp = reinterpret_cast<double*>(base + o.xp);
         S.xTp = reinterpret_cast<double*>(base + o.xTp);
         S.rp = reinterpret_cast<float*>(base + o.rp);
+        S.rpd = reinterpret_cast<double*>(base + o.rpd);
         S.seg = S.G.parts > 1 ? reinterpret_cast<double*>(base + o.seg) : nullptr;
         double* dv = reinterpret_cast<double*>(base + o.dvec);
         S.x = dv;
@@ -895,7 +899,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     if (!c) return SP_ERR_ARG;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->seg, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh,
+    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
                       &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
@@ -1109,7 +1113,7 @@ int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
     {
         ProfScope ps(c, SP_PROF_PROJECT);
         launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp),
-                       nullptr, y, G.nB, nullptr, nullptr, dptr<double>(c->seg), nullptr);
+                       nullptr, y, G.nB, nullptr, nullptr, nullptr, dptr<double>(c->seg), nullptr);
     }
     return check_launch(c);
 }
@@ -1140,7 +1144,7 @@ int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b,
     const GeomDev& G = c->G;
     launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
     launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp), b, r,
-                   G.nB, nullptr, dptr<double>(c->part_f), dptr<double>(c->seg), nullptr);
+                   G.nB, nullptr, nullptr, dptr<double>(c->part_f), dptr<double>(c->seg), nullptr);
     launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
     return check_launch(c);
 }
@@ -1312,6 +1316,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     double* xTp = dptr<double>(c->xTp);
     double* seg = dptr<double>(c->seg);
     float* rp = dptr<float>(c->yp);
+    double* rpd = dptr<double>(c->ypd);
     const double* skp = dptr<double>(c->skp);
     const AngleDev* ang = dptr<AngleDev>(c->ang);
     double* pf = dptr<double>(c->part_f);
@@ -1325,15 +1330,15 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
     // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
     launch_prep(st, G, xh, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, rp, pf, seg, halt);
+    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, halt);
     launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
-    launch_backproject(st, G, ang, rp, skp, gv, nullptr, nullptr, halt);
+    launch_backproject(st, G, ang, rpd, skp, gv, nullptr, nullptr, halt);
     int nzh = 0;
     if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
     launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
     launch_update_p(st, n, z, p, gv, sc, pgp, halt);
     launch_prep(st, G, p, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, seg, halt);
+    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, halt);
     launch_backproject(st, G, ang, rp, skp, h, p, pph, halt);
     launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
     launch_update_x(st, n, xh, p, x, sc, halt);
@@ -1343,13 +1348,16 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     const int snap_count = snap ? trace->g_snap_count : 0;
     // One loop body (steps 11-14); every launch reads device state only, so
     // the body can be replayed from a captured graph.
+    // r = R x - b goes to the float64 sinogram rpd, R p to the float32 rp
     auto project = [&](const float* bb, double* parts) {
         ProfScope ps(c, SP_PROF_PROJECT);
-        launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, rp, parts, seg, halt);
+        launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, bb ? nullptr : rp, bb ? rpd : nullptr,
+                       parts, seg, halt);
     };
     auto backproject = [&](float* out, const double* dotv, double* parts) {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
-        launch_backproject(st, G, ang, rp, skp, out, dotv, parts, halt);
+        if (dotv) launch_backproject(st, G, ang, rp, skp, out, dotv, parts, halt);
+        else launch_backproject(st, G, ang, rpd, skp, out, dotv, parts, halt);
     };
     auto body = [&]() -> int {
         ProfScope ps(c, SP_PROF_ITERATION);

@@ -229,26 +229,29 @@ __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A
 }
 
 // Stores ray (row a, bin k) of the workgroup's 256-bin chunk: (R x)_{a,k}, or
-// the residual (R x - b) with its float64 squared norm per workgroup in
-// partials[by * gx + bx] when b != nullptr, rounded to float32 and stored to
-// out[a*out_pitch + k] (nullable) and to the padded sinogram
-// outp[a*pitchB + PAD + k] (nullable).
+// the residual r = R x - b when b != nullptr, with the float64 sum of r^2 per
+// workgroup in partials[by * gx + bx].  The value goes, rounded to float32, to
+// out[a*out_pitch + k] and to the padded sinogram outp[a*pitchB + PAD + k],
+// and unrounded to the float64 padded sinogram outpd (each nullable).
 __device__ __forceinline__ void project_store(const GeomDev& G, int a, int k, bool valid, double acc,
                                               const float* __restrict__ b, float* __restrict__ out,
                                               int out_pitch, float* __restrict__ outp,
+                                              double* __restrict__ outpd,
                                               double* __restrict__ partials, int bx, int by, int gx) {
     __shared__ double red[4];
     double r2 = 0.0;
     if (valid) {
-        float val;
+        double v;
         if (b) {
-            val = (float)(fma(acc, G.pixel, -(double)b[(size_t)a * G.nB + k]));
-            r2 = (double)val * (double)val;
+            v = fma(acc, G.pixel, -(double)b[(size_t)a * G.nB + k]);
+            r2 = v * v;
         } else {
-            val = (float)(acc * G.pixel);
+            v = acc * G.pixel;
         }
+        const float val = (float)v;
         if (out) out[(size_t)a * out_pitch + k] = val;
         if (outp) outp[(size_t)a * G.pitchB + PAD + k] = val;
+        if (outpd) outpd[(size_t)a * G.pitchB + PAD + k] = v;
     }
     if (b) {
         const double tot = block_sum(r2, red);
@@ -268,6 +271,7 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                                              const double* __restrict__ xTp,
                                              const float* __restrict__ b, float* __restrict__ out,
                                              int out_pitch, float* __restrict__ outp,
+                                             double* __restrict__ outpd,
                                              double* __restrict__ partials,
                                              double* __restrict__ seg, int bx, int by, int part,
                                              int gx) {
@@ -289,7 +293,7 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
         if (valid) seg[((size_t)part * G.nA + bx) * G.nB + k] = acc;
         return;
     }
-    project_store(G, A.row, k, valid, acc, b, out, out_pitch, outp, partials, bx, by, gx);
+    project_store(G, A.row, k, valid, acc, b, out, out_pitch, outp, outpd, partials, bx, by, gx);
 }
 
 // Sum of the parts of the rays of block (bx, by), then the store.
@@ -298,6 +302,7 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
                                                   const float* __restrict__ b,
                                                   float* __restrict__ out, int out_pitch,
                                                   float* __restrict__ outp,
+                                                  double* __restrict__ outpd,
                                                   double* __restrict__ partials, int bx, int by,
                                                   int gx) {
     const int a = ang[bx].row;
@@ -309,7 +314,7 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
         const size_t stride = (size_t)G.nA * G.nB;
         for (int j = 0; j < G.parts; ++j) acc += v[j * stride];
     }
-    project_store(G, a, k, valid, acc, b, out, out_pitch, outp, partials, bx, by, gx);
+    project_store(G, a, k, valid, acc, b, out, out_pitch, outp, outpd, partials, bx, by, gx);
 }
 
 __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
@@ -318,10 +323,11 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
                                                  const float* __restrict__ b,
                                                  float* __restrict__ out, int out_pitch,
                                                  float* __restrict__ outp,
+                                                 double* __restrict__ outpd,
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, partials, nullptr, blockIdx.x,
+    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr, blockIdx.x,
                  blockIdx.y, 0, gridDim.x);
 }
 
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev*
                                                       double* __restrict__ seg,
                                                       const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, seg, blockIdx.x,
+    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg, blockIdx.x,
                  blockIdx.y, blockIdx.z, gridDim.x);
 }
 
@@ -341,14 +347,15 @@ __global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev*
                                                       const float* __restrict__ b,
                                                       float* __restrict__ out, int out_pitch,
                                                       float* __restrict__ outp,
+                                                      double* __restrict__ outpd,
                                                       double* __restrict__ partials,
                                                       const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_comb_body(G, ang, seg, b, out, out_pitch, outp, partials, blockIdx.x, blockIdx.y,
-                      gridDim.x);
+    project_comb_body(G, ang, seg, b, out, out_pitch, outp, outpd, partials, blockIdx.x,
+                      blockIdx.y, gridDim.x);
 }
 
-// residual: rp = R xh - b with f partials; else rp = R p.  Virtual block
+// residual: rpd = R xh - b (float64) with f partials; else rp = R p.  Virtual block
 // lin = (part * chunks + by) * nA + bx.
 __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
                                                   int residual) {
@@ -361,11 +368,13 @@ __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ s
         if (G.parts > 1) {
             const int chunks = (G.nB + 255) / 256;
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, nullptr,
-                         nullptr, gmem(S.seg), bx, r % chunks, r / chunks, gx);
+                         nullptr, nullptr, gmem(S.seg), bx, r % chunks, r / chunks, gx);
+        } else if (residual) {
+            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), gmem(S.b), nullptr, 0, nullptr,
+                         gmem(S.rpd), gmem(S.pf), nullptr, bx, r, 0, gx);
         } else {
-            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), residual ? gmem(S.b) : nullptr,
-                         nullptr, 0, gmem(S.rp), residual ? gmem(S.pf) : nullptr, nullptr, bx, r, 0,
-                         gx);
+            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, gmem(S.rp),
+                         nullptr, nullptr, nullptr, bx, r, 0, gx);
         }
     });
 }
@@ -378,8 +387,12 @@ __global__ __launch_bounds__(256) void kb_project_comb(const SliceDev* __restric
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = G.nA;
-        project_comb_body(G, cmem(S.ang), gmem(S.seg), residual ? gmem(S.b) : nullptr, nullptr, 0,
-                          gmem(S.rp), residual ? gmem(S.pf) : nullptr, lin % gx, lin / gx, gx);
+        if (residual)
+            project_comb_body(G, cmem(S.ang), gmem(S.seg), gmem(S.b), nullptr, 0, nullptr,
+                              gmem(S.rpd), gmem(S.pf), lin % gx, lin / gx, gx);
+        else
+            project_comb_body(G, cmem(S.ang), gmem(S.seg), nullptr, nullptr, 0, gmem(S.rp), nullptr,
+                              nullptr, lin % gx, lin / gx, gx);
     });
 }
 
@@ -402,17 +415,17 @@ int project_parts(int rows, int cols) {
 
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* partials, double* seg, const int* halt) {
+                    double* outpd, double* partials, double* seg, const int* halt) {
     dim3 grid(G.nA, (G.nB + 255) / 256);
     if (G.parts > 1) {
         hipLaunchKernelGGL(k_project_part, dim3(G.nA, (G.nB + 255) / 256, G.parts), dim3(256), 0,
                            st, G, ang, xp, xTp, seg, halt);
         hipLaunchKernelGGL(k_project_comb, grid, dim3(256), 0, st, G, ang, (const double*)seg, b,
-                           out, out_pitch, outp, partials, halt);
+                           out, out_pitch, outp, outpd, partials, halt);
         return;
     }
     hipLaunchKernelGGL(k_project, grid, dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
-                       outp, partials, halt);
+                       outp, outpd, partials, halt);
 }
 
 __global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const float* __restrict__ y,
@@ -439,9 +452,9 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp
 // pads -- in both cases every true candidate lies outside the detector.  A
 // candidate that reads a pad gets a weight evaluated at the pad's position and
 // multiplies 0.
-template <bool HORIZ, bool AXIS, int NB, bool LSK>
+template <bool HORIZ, bool AXIS, int NB, bool LSK, class TY>
 __device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
-                                           int beg, int end, const float* __restrict__ yp,
+                                           int beg, int end, const TY* __restrict__ yp,
                                            const double* __restrict__ skg, const double* sks,
                                            double xj, double yi, double acc) {
     const unsigned kmax = (unsigned)(G.nB + 2 * PAD - NB);   // last padded start index
@@ -450,9 +463,9 @@ __device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __r
         const AngleDev A = ang[a];
         const double t = HORIZ ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
         const unsigned o = min((unsigned)(int)fma(t, G.inv_ds, A.kb), kmax);
-        const float* pv = at(yp + (size_t)A.row * G.pitchB, o);
+        const TY* pv = at(yp + (size_t)A.row * G.pitchB, o);
         const double* ps = LSK ? sks + o : skg + o;
-        float v[NB];
+        TY v[NB];
         double sk[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) v[q] = pv[q];
@@ -483,9 +496,9 @@ __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int
 // an 8 x 8 pixel tile; its wave w sums the w-th quarter of every angle class,
 // and the four partial sums are added in wave order through LDS.  With LSK the
 // workgroup first writes the bin-position table into the dynamic LDS `sks`.
-template <int NB, bool LSK>
+template <int NB, bool LSK, class TY>
 __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDev* __restrict__ ang,
-                                                 const float* __restrict__ yp,
+                                                 const TY* __restrict__ yp,
                                                  const double* __restrict__ skg, double* sks,
                                                  float* __restrict__ out,
                                                  const double* __restrict__ dotv,
@@ -506,13 +519,13 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     double acc = 0.0;
     int b, e;
     split_range(G.cls[0], G.cls[1], w, b, e);
-    acc = bp_class<false, false, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    acc = bp_class<false, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[1], G.cls[2], w, b, e);
-    acc = bp_class<true, false, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    acc = bp_class<true, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[2], G.cls[3], w, b, e);
-    acc = bp_class<false, true, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    acc = bp_class<false, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[3], G.cls[4], w, b, e);
-    acc = bp_class<true, true, NB, LSK>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    acc = bp_class<true, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     part[w][lane] = acc;
     __syncthreads();
     double v = 0.0;
@@ -531,9 +544,9 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     }
 }
 
-template <int NB, bool LSK>
+template <int NB, bool LSK, class TY>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
-                                                     const float* __restrict__ yp,
+                                                     const TY* __restrict__ yp,
                                                      const double* __restrict__ skg,
                                                      float* __restrict__ out,
                                                      const double* __restrict__ dotv,
@@ -541,24 +554,28 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
     extern __shared__ double sks[];
-    backproject_body<NB, LSK>(G, ang, yp, skg, sks, out, dotv, partials, blockIdx.x, blockIdx.y,
-                              gridDim.x);
+    backproject_body<NB, LSK, TY>(G, ang, yp, skg, sks, out, dotv, partials, blockIdx.x,
+                                  blockIdx.y, gridDim.x);
 }
 
-// normal: h = R^T rp with the partials of h^T p; else g = R^T rp.  NB is the
-// largest candidate count of the batch (extra candidates weigh exactly 0).
-template <int NB, bool LSK>
-__global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, ItemTable t,
-                                                      int normal) {
+// TY = float: h = R^T rp (rp = R p) with the partials of h^T p; TY = double:
+// g = R^T rpd from the float64 residual.  NB is the largest candidate count of
+// the batch (extra candidates weigh exactly 0).
+template <int NB, bool LSK, class TY>
+__global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, ItemTable t) {
+    constexpr bool normal = sizeof(TY) == sizeof(float);
     extern __shared__ double sks[];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = (G.cols + BP_TILE - 1) / BP_TILE;
-        backproject_body<NB, LSK>(G, cmem(S.ang), gmem(S.rp), gmem(S.skp), sks,
-                                  gmem(normal ? S.h : S.g), normal ? gmem(S.p) : nullptr,
-                                  normal ? gmem(S.pph) : nullptr, lin % gx, lin / gx, gx);
+        const TY* yp;
+        if constexpr (normal) yp = gmem(S.rp);
+        else yp = gmem(S.rpd);
+        backproject_body<NB, LSK, TY>(G, cmem(S.ang), yp, gmem(S.skp), sks,
+                                      gmem(normal ? S.h : S.g), normal ? gmem(S.p) : nullptr,
+                                      normal ? gmem(S.pph) : nullptr, lin % gx, lin / gx, gx);
     });
 }
 
@@ -567,37 +584,42 @@ size_t bp_lds_bytes(int nbins) {
     return b <= BP_LDS_SK_MAX ? b : 0;
 }
 
-template <bool LSK>
-void launch_bp_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int nm, size_t lds) {
+template <bool LSK, class TY>
+void launch_bp_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, size_t lds) {
     switch (nbmax) {
-    case 1: hipLaunchKernelGGL((kb_backproject<1, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
-    case 2: hipLaunchKernelGGL((kb_backproject<2, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
-    case 3: hipLaunchKernelGGL((kb_backproject<3, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
-    default: hipLaunchKernelGGL((kb_backproject<4, LSK>), dim3(t.grid), dim3(256), lds, st, sl, t, nm); break;
+    case 1: hipLaunchKernelGGL((kb_backproject<1, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    case 2: hipLaunchKernelGGL((kb_backproject<2, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    case 3: hipLaunchKernelGGL((kb_backproject<3, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    default: hipLaunchKernelGGL((kb_backproject<4, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
     }
 }
 
 void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
                           bool normal) {
     const size_t lds = bp_lds_bytes(max_bins);
-    if (lds) launch_bp_b<true>(st, sl, t, nbmax, normal ? 1 : 0, lds);
-    else launch_bp_b<false>(st, sl, t, nbmax, normal ? 1 : 0, 0);
+    if (normal) {
+        if (lds) launch_bp_b<true, float>(st, sl, t, nbmax, lds);
+        else launch_bp_b<false, float>(st, sl, t, nbmax, 0);
+    } else {
+        if (lds) launch_bp_b<true, double>(st, sl, t, nbmax, lds);
+        else launch_bp_b<false, double>(st, sl, t, nbmax, 0);
+    }
 }
 
 int backproject_blocks(const GeomDev& G) {
     return ((G.cols + BP_TILE - 1) / BP_TILE) * ((G.rows + BP_TILE - 1) / BP_TILE);
 }
 
-template <bool LSK>
-void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
+template <bool LSK, class TY>
+void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp,
                const double* skp, float* out, const double* dotv, double* partials, const int* halt,
                size_t lds) {
     dim3 grid((G.cols + BP_TILE - 1) / BP_TILE, (G.rows + BP_TILE - 1) / BP_TILE);
     switch (G.nbmax) {
-    case 1: hipLaunchKernelGGL((k_backproject<1, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
-    case 2: hipLaunchKernelGGL((k_backproject<2, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
-    case 3: hipLaunchKernelGGL((k_backproject<3, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
-    default: hipLaunchKernelGGL((k_backproject<4, LSK>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    case 1: hipLaunchKernelGGL((k_backproject<1, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    case 2: hipLaunchKernelGGL((k_backproject<2, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    case 3: hipLaunchKernelGGL((k_backproject<3, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    default: hipLaunchKernelGGL((k_backproject<4, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
     }
 }
 
@@ -605,8 +627,16 @@ void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, c
                         const double* skp, float* out, const double* dotv, double* partials,
                         const int* halt) {
     const size_t lds = bp_lds_bytes(G.nB);
-    if (lds) launch_bp<true>(st, G, ang, yp, skp, out, dotv, partials, halt, lds);
-    else launch_bp<false>(st, G, ang, yp, skp, out, dotv, partials, halt, 0);
+    if (lds) launch_bp<true, float>(st, G, ang, yp, skp, out, dotv, partials, halt, lds);
+    else launch_bp<false, float>(st, G, ang, yp, skp, out, dotv, partials, halt, 0);
+}
+
+void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
+                        const double* skp, float* out, const double* dotv, double* partials,
+                        const int* halt) {
+    const size_t lds = bp_lds_bytes(G.nB);
+    if (lds) launch_bp<true, double>(st, G, ang, yp, skp, out, dotv, partials, halt, lds);
+    else launch_bp<false, double>(st, G, ang, yp, skp, out, dotv, partials, halt, 0);
 }
 
 }  // namespace sp

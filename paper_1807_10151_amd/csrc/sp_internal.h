@@ -119,10 +119,12 @@ void launch_prep(hipStream_t st, const GeomDev& G, const float* x, double* xp, d
 void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, double* xTp,
                  const int* halt);
 // With G.parts > 1, seg (parts * nA * nB float64) receives the per-part sums
-// before they are combined.
+// before they are combined.  outp / outpd: float32 / float64 padded sinograms
+// (nullable); the residual's float64 values feed R^T without a float32
+// rounding (its cancellation in R^T r amplifies that rounding).
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* partials, double* seg, const int* halt);
+                    double* outpd, double* partials, double* seg, const int* halt);
 int project_blocks(const GeomDev& G);
 // Parts R splits each ray's step range into, chosen from the image size (both
 // the single-slice and the batched solver use it, so their sums agree).
@@ -132,6 +134,9 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp
 // (bin_sk_table fills it on the host with the same fma as bin_pos); used when
 // the table is too large for the backprojector's LDS copy.
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
+                        const double* skp, float* out, const double* dotv, double* partials,
+                        const int* halt);
+void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
                         const double* skp, float* out, const double* dotv, double* partials,
                         const int* halt);
 int backproject_blocks(const GeomDev& G);
@@ -221,7 +226,8 @@ struct SliceDev {
     double *xh, *x, *p;  // iterate, x_{k+1/2} and search direction (float64)
     float *h, *g, *z, *tb;
     double *xp, *xTp;   // float64 padded copies
-    float* rp;          // padded sinogram
+    float* rp;          // padded sinogram (R p)
+    double* rpd;        // float64 padded sinogram (residual)
     double* seg;        // R's per-part ray sums, [parts][nA][nB] (G.parts > 1)
     double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
     Scalars* sc;
