@@ -205,7 +205,7 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
     G.pitchX = g->cols + 2 * PAD;
     G.pitchXT = g->rows + 2 * PAD;
     G.pitchB = g->n_bins + 2 * PAD;
-    G.parts = project_parts(g->rows, g->cols);
+    G.parts = project_parts(g->rows, g->cols, g->n_angles, g->n_bins, c->n_cu * 32);
     const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
     tab.assign(g->n_angles, AngleDev{});
     for (int a = 0; a < g->n_angles; ++a) {

@@ -406,11 +406,15 @@ void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable
 
 int project_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
 
-int project_parts(int rows, int cols) {
-    const int side = rows > cols ? rows : cols;
-    if (side < 192) return 1;
-    const int p = (side + 128) / 256;
-    return p < 3 ? 3 : (p > 8 ? 8 : p);
+int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_waves) {
+    // Large images: 8 parts keep the resident waves on a band of the float64
+    // copies (measured: 2048^2 x 2048 angles 9.3 -> 5.8 ms).
+    if ((long)rows * cols >= (1L << 21)) return 8;
+    // Otherwise split only a grid that would leave wave slots empty.
+    const long waves = (long)n_angles * ((n_bins + 63) / 64);
+    if (waves >= resident_waves) return 1;
+    const long p = (resident_waves + waves - 1) / waves;
+    return p > 4 ? 4 : (int)p;
 }
 
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,

@@ -126,9 +126,10 @@ void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* outpd, double* partials, double* seg, const int* halt);
 int project_blocks(const GeomDev& G);
-// Parts R splits each ray's step range into, chosen from the image size (both
-// the single-slice and the batched solver use it, so their sums agree).
-int project_parts(int rows, int cols);
+// Parts R splits each ray's step range into, chosen from the geometry and
+// the device's wave slots (both the single-slice and the batched solver use
+// it, so their sums agree).
+int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_waves);
 void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp);
 // skp: float64 bin positions of the padded bin range, skp[PAD + k] = s_k
 // (bin_sk_table fills it on the host with the same fma as bin_pos); used when

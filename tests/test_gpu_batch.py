@@ -26,8 +26,7 @@ def sp():
 
 
 def mixed_batch(sp):
-    """Mixed shapes, angle sets and bin spacings, with whole-ray and split-ray R;
-    data = R x + noise (GPU R)."""
+    """Mixed shapes, angle sets and bin spacings; data = R x + noise (GPU R)."""
     from synth import random_ellipses
     geoms = [sp.Geometry(64, 64, 90, 91),
              sp.Geometry(48, 80, 60, 97),
@@ -36,7 +35,7 @@ def mixed_batch(sp):
              sp.Geometry(16, 16, 8, 24),
              sp.Geometry(40, 56, 70, 100, bin_spacing=0.7, bin_offset=0.3),
              sp.Geometry(130, 96, 128, 165, dtheta=np.pi / 160),
-             sp.Geometry(200, 150, 64, 251, theta0=0.05)]   # R in parts
+             sp.Geometry(200, 150, 64, 251, theta0=0.05)]
     bs = []
     for i, g in enumerate(geoms):
         img, rng = random_ellipses(g.rows, g.cols, 5, 300 + i)
@@ -138,7 +137,9 @@ def test_batch_64_mixed_slices_sampled(sp):
     # The 64-slice batch: sides from {256, 384, 512, 768, 1024}, 1.4 x side
     # angles (multiple of 8), ceil(side sqrt 2) + 1 bins, 20-ellipse phantoms,
     # noise 0.2%-2%; 50 iterations in one batched solve.  One slice of each
-    # side is re-solved alone and must agree bit for bit.
+    # side is re-solved alone and must agree bit for bit.  R splits the rays
+    # of the 256^2 slices in 4 parts and of the 384^2 slices in 2 (their grids
+    # alone would not fill the GPU); larger slices run whole rays.
     from synth import batched_slices, random_ellipses
     work = batched_slices(64, seed=2)
     geoms = [sp.Geometry(w.rows, w.cols, w.n_angles, w.n_bins) for w in work]

@@ -48,9 +48,9 @@ RAGGED = [
     OG(1, 1, 4, 3),                          # single pixel
     OG(3, 70, 1, 5),                         # one angle, wide image
     OG(33, 33, 360, 47),                     # includes 45 and 135 degrees
-    OG(200, 150, 30, 251),                   # R sums each ray in parts (3)
-    OG(9, 300, 12, 301, theta0=0.3),         # parts on a thin, wide image
-    OG(260, 240, 16, 360, dtheta=0.19),      # parts, coarse angle steps
+    OG(200, 150, 30, 251),                   # larger, few angles
+    OG(9, 300, 12, 301, theta0=0.3),         # thin, wide image
+    OG(260, 240, 16, 360, dtheta=0.19),      # coarse angle steps
 ]
 
 
