@@ -43,8 +43,10 @@ OPS_PER_NNZ = 4
 # Bytes moved between L2 and the memory fabric per launch of the projector
 # kernels at this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE averages scaled
 # by the counts of a 64 MiB device copy (profiles/counters_ct512.md).  They are
-# tied to the kernels as profiled; re-measure after changing them.
-TRAFFIC_BYTES = {"project": None, "backproject": None}
+# tied to the kernels as profiled; re-measure after changing them.  R^T: mean of
+# its float32 (R p) and float64 (residual) sinogram forms, one of each per loop
+# body.
+TRAFFIC_BYTES = {"project": 41.55e6, "backproject": 25.43e6}
 
 
 def log(msg):
