@@ -683,8 +683,8 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
             S.F.rows = G.rows;
             S.F.cols = G.cols;
             S.F.CB = std::max(1, 2048 / P);
-            B.lds_rows = std::max(B.lds_rows, (size_t)P * sizeof(double2));
-            B.lds_cols = std::max(B.lds_cols, (size_t)S.F.CB * P * sizeof(double2));
+            B.lds_rows = std::max(B.lds_rows, fft_lds_bytes(P, 1));
+            B.lds_cols = std::max(B.lds_cols, fft_lds_bytes(P, S.F.CB));
         }
         S.nf = project_blocks(G);
         S.nph = backproject_blocks(G);

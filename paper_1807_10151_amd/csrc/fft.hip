@@ -1,6 +1,6 @@
 // The paper's preconditioner M = F^-1 D F (Section 3.2), applied to an l x c
 // image zero-embedded in a P x P grid, with D = h(|omega|) of eq. (3.2) on the
-// radial frequency.  Three kernels, all LDS-resident radix-2 FFTs:
+// radial frequency.  Three kernels, all LDS-resident radix-2 FFTs (two stages per LDS pass):
 //
 //  1. rows forward: two real rows are packed as one complex row (real and
 //     imaginary parts), transformed, and split into the two half spectra
@@ -29,62 +29,146 @@ __device__ __forceinline__ int bitrev(int v, int logP) {
     return (int)(__builtin_bitreverse32((unsigned)v) >> (32 - logP));
 }
 
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+    return make_double2(a.x - b.x, a.y - b.y);
+}
+
 // In-place decimation-in-time FFTs of `ncol` length-P arrays stored back to
 // back in LDS, input in bit-reversed order, output in natural order.
-// sign = -1: forward (exp(-2 pi i ...)); +1: inverse, unscaled.
-__device__ void fft_dit(double2* buf, int P, int logP, int ncol, const double2* __restrict__ tw,
-                        float sign) {
-    const int half_total = ncol * (P >> 1);
-    for (int s = 1; s <= logP; ++s) {
+// sign = -1: forward (exp(-2 pi i ...)); +1: inverse, unscaled.  tw[k] =
+// exp(-2 pi i k / P), k < P/2 (LDS or global).
+//
+// Radix-2 stages s = 1..logP, taken two per pass: a thread loads the four
+// elements i0 + {0, h, 2h, 3h} (h = 2^(s-1)) and applies to them exactly the
+// butterflies of stages s and s+1, so every value is the one the stage-by-
+// stage sequence produces, with half the LDS round trips and barriers.
+template <class TW>
+__device__ __forceinline__ void fft_dit(double2* buf, int P, int logP, int ncol, TW tw, float sign) {
+    const bool inv = sign > 0.0f;
+    auto twd = [&](int k) {
+        double2 w = tw[k];
+        if (inv) w.y = -w.y;   // inverse: conjugate twiddle
+        return w;
+    };
+    int s = 1;
+    for (; s + 1 <= logP; s += 2) {
+        const int half = 1 << (s - 1);
+        const int ts0 = P >> s, ts1 = P >> (s + 1);
+        const int quads = ncol * (P >> 2);
+        for (int q = threadIdx.x; q < quads; q += blockDim.x) {
+            const int col = q >> (logP - 2);
+            const int qq = q & ((P >> 2) - 1);
+            const int pos = qq & (half - 1);
+            const int e0 = col * P + (qq >> (s - 1)) * (half << 2) + pos;
+            const int e1 = e0 + half, e2 = e1 + half, e3 = e2 + half;
+            const double2 wa = twd(pos * ts0), wb = twd(pos * ts1), wc = twd((pos + half) * ts1);
+            const double2 x0 = buf[e0], x1 = buf[e1], x2 = buf[e2], x3 = buf[e3];
+            double2 v = cmul(x1, wa);                       // stage s: (e0, e1), (e2, e3)
+            const double2 y0 = cadd(x0, v), y1 = csub(x0, v);
+            v = cmul(x3, wa);
+            const double2 y2 = cadd(x2, v), y3 = csub(x2, v);
+            v = cmul(y2, wb);                               // stage s+1: (e0, e2), (e1, e3)
+            buf[e0] = cadd(y0, v);
+            buf[e2] = csub(y0, v);
+            v = cmul(y3, wc);
+            buf[e1] = cadd(y1, v);
+            buf[e3] = csub(y1, v);
+        }
+        __syncthreads();
+    }
+    if (s == logP) {   // odd logP: the last stage alone
         const int half = 1 << (s - 1);
         const int tstride = P >> s;
-        for (int bidx = threadIdx.x; bidx < half_total; bidx += blockDim.x) {
+        for (int bidx = threadIdx.x; bidx < ncol * (P >> 1); bidx += blockDim.x) {
             const int col = bidx >> (logP - 1);
             const int bb = bidx & ((P >> 1) - 1);
-            const int grp = bb >> (s - 1);
             const int pos = bb & (half - 1);
-            const int i0 = col * P + grp * (half << 1) + pos;
+            const int i0 = col * P + (bb >> (s - 1)) * (half << 1) + pos;
             const int i1 = i0 + half;
-            double2 w = tw[pos * tstride];   // exp(-2 pi i pos / len)
-            if (sign > 0.0f) w.y = -w.y;    // inverse: conjugate twiddle
             const double2 u = buf[i0];
-            const double2 v = cmul(buf[i1], w);
-            buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-            buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+            const double2 v = cmul(buf[i1], twd(pos * tstride));
+            buf[i0] = cadd(u, v);
+            buf[i1] = csub(u, v);
         }
         __syncthreads();
     }
 }
 
 // In-place decimation-in-frequency FFTs, input natural order, output
-// bit-reversed.
-__device__ void fft_dif(double2* buf, int P, int logP, int ncol, const double2* __restrict__ tw,
-                        float sign) {
-    const int half_total = ncol * (P >> 1);
-    for (int s = logP; s >= 1; --s) {
-        const int half = 1 << (s - 1);
-        const int tstride = P >> s;
-        for (int bidx = threadIdx.x; bidx < half_total; bidx += blockDim.x) {
+// bit-reversed.  Stages s = logP..1, two per pass (s and s-1 on the four
+// elements i0 + {0, q, 2q, 3q}, q = 2^(s-2)).
+template <class TW>
+__device__ __forceinline__ void fft_dif(double2* buf, int P, int logP, int ncol, TW tw, float sign) {
+    const bool inv = sign > 0.0f;
+    auto twd = [&](int k) {
+        double2 w = tw[k];
+        if (inv) w.y = -w.y;
+        return w;
+    };
+    int s = logP;
+    for (; s >= 2; s -= 2) {
+        const int q4 = 1 << (s - 2);
+        const int ts0 = P >> s, ts1 = P >> (s - 1);
+        const int quads = ncol * (P >> 2);
+        for (int q = threadIdx.x; q < quads; q += blockDim.x) {
+            const int col = q >> (logP - 2);
+            const int qq = q & ((P >> 2) - 1);
+            const int pos = qq & (q4 - 1);
+            const int a = col * P + (qq >> (s - 2)) * (q4 << 2) + pos;
+            const int b = a + q4, c = b + q4, d = c + q4;
+            const double2 w0 = twd(pos * ts0), w1 = twd((pos + q4) * ts0), w2 = twd(pos * ts1);
+            const double2 xa = buf[a], xb = buf[b], xc = buf[c], xd = buf[d];
+            const double2 ya = cadd(xa, xc), yc = cmul(csub(xa, xc), w0);   // stage s
+            const double2 yb = cadd(xb, xd), yd = cmul(csub(xb, xd), w1);
+            buf[a] = cadd(ya, yb);                                          // stage s-1
+            buf[b] = cmul(csub(ya, yb), w2);
+            buf[c] = cadd(yc, yd);
+            buf[d] = cmul(csub(yc, yd), w2);
+        }
+        __syncthreads();
+    }
+    if (s == 1) {   // odd logP: stage 1 alone
+        for (int bidx = threadIdx.x; bidx < ncol * (P >> 1); bidx += blockDim.x) {
             const int col = bidx >> (logP - 1);
             const int bb = bidx & ((P >> 1) - 1);
-            const int grp = bb >> (s - 1);
-            const int pos = bb & (half - 1);
-            const int i0 = col * P + grp * (half << 1) + pos;
-            const int i1 = i0 + half;
-            double2 w = tw[pos * tstride];
-            if (sign > 0.0f) w.y = -w.y;
+            const int i0 = col * P + bb * 2;
+            const int i1 = i0 + 1;
             const double2 u = buf[i0];
             const double2 v = buf[i1];
-            buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-            buf[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
+            buf[i0] = cadd(u, v);
+            buf[i1] = cmul(csub(u, v), twd(0));
         }
         __syncthreads();
     }
 }
 
+// The twiddles go to LDS after the ncol * P transform entries when both fit
+// in 64 KB (stage_twiddles returns the LDS copy), else they are read from
+// global memory.
+__host__ __device__ __forceinline__ bool tw_in_lds(int P, int ncol) {
+    return (size_t)(ncol * P + P / 2) * sizeof(double2) <= 65536;
+}
+
+__device__ __forceinline__ const double2* stage_twiddles(const FFTPlan& F, double2* buf, int ncol) {
+    double2* t = buf + (size_t)ncol * F.P;
+    for (int k = threadIdx.x; k < F.P / 2; k += blockDim.x) t[k] = F.tw[k];
+    return t;   // visible after the caller's next barrier
+}
+
+#define SP_FFT(kind, ncol, sign)                                                  \
+    do {                                                                          \
+        if (twl) kind(buf, F.P, F.logP, ncol, (const double2*)(buf + (size_t)(ncol) * F.P), sign); \
+        else kind(buf, F.P, F.logP, ncol, F.tw, sign);                            \
+    } while (0)
+
 __device__ __forceinline__ void rows_fwd_body(const FFTPlan& F, const float* __restrict__ g,
                                               double2* buf, int bx) {
     const int r0 = 2 * bx, r1 = r0 + 1;
+    const bool twl = tw_in_lds(F.P, 1);
+    if (twl) stage_twiddles(F, buf, 1);
     for (int nidx = threadIdx.x; nidx < F.P; nidx += blockDim.x) {
         float re = 0.0f, im = 0.0f;
         if (nidx < F.cols) {
@@ -94,7 +178,7 @@ __device__ __forceinline__ void rows_fwd_body(const FFTPlan& F, const float* __r
         buf[bitrev(nidx, F.logP)] = make_double2(re, im);
     }
     __syncthreads();
-    fft_dit(buf, F.P, F.logP, 1, F.tw, -1.0f);
+    SP_FFT(fft_dit, 1, -1.0f);
     for (int u = threadIdx.x; u <= F.P / 2; u += blockDim.x) {
         const double2 Z = buf[u];
         const double2 W = buf[(F.P - u) & (F.P - 1)];   // Z(-u); conj taken below
@@ -122,6 +206,8 @@ __device__ __forceinline__ void cols_body(const FFTPlan& F, double mu, double rh
                                           int bx) {
     const int u0 = bx * F.CB;
     const int total = F.CB * F.P;
+    const bool twl = tw_in_lds(F.P, F.CB);
+    if (twl) stage_twiddles(F, buf, F.CB);
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int r = idx / F.CB, cc = idx - r * F.CB;
         double2 v = make_double2(0.0f, 0.0f);
@@ -129,7 +215,7 @@ __device__ __forceinline__ void cols_body(const FFTPlan& F, double mu, double rh
         buf[cc * F.P + bitrev(r, F.logP)] = v;
     }
     __syncthreads();
-    fft_dit(buf, F.P, F.logP, F.CB, F.tw, -1.0f);
+    SP_FFT(fft_dit, F.CB, -1.0f);
     const double two_pi_over_P = 6.283185307179586 / (double)F.P;
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int cc = idx / F.P, v = idx - cc * F.P;
@@ -141,7 +227,7 @@ __device__ __forceinline__ void cols_body(const FFTPlan& F, double mu, double rh
         buf[idx] = make_double2(z.x * h, z.y * h);
     }
     __syncthreads();
-    fft_dif(buf, F.P, F.logP, F.CB, F.tw, 1.0f);
+    SP_FFT(fft_dif, F.CB, 1.0f);
     for (int idx = threadIdx.x; idx < F.rows * F.CB; idx += blockDim.x) {
         const int r = idx / F.CB, cc = idx - r * F.CB;
         if (u0 + cc < F.SP) F.S[(size_t)r * F.SP + u0 + cc] = buf[cc * F.P + bitrev(r, F.logP)];
@@ -162,6 +248,8 @@ __device__ __forceinline__ void rows_inv_body(const FFTPlan& F, float* __restric
     double* red = reinterpret_cast<double*>(buf);   // reused after the transform is read
     const int r0 = 2 * bx, r1 = r0 + 1;
     const bool has1 = r1 < F.rows;
+    const bool twl = tw_in_lds(F.P, 1);
+    if (twl) stage_twiddles(F, buf, 1);
     for (int u = threadIdx.x; u < F.P; u += blockDim.x) {
         double2 X0, X1 = make_double2(0.0f, 0.0f);
         if (u <= F.P / 2) {
@@ -179,7 +267,7 @@ __device__ __forceinline__ void rows_inv_body(const FFTPlan& F, float* __restric
         buf[bitrev(u, F.logP)] = make_double2(X0.x - X1.y, X0.y + X1.x);
     }
     __syncthreads();
-    fft_dit(buf, F.P, F.logP, 1, F.tw, 1.0f);
+    SP_FFT(fft_dit, 1, 1.0f);
     const double scale = 1.0 / ((double)F.P * (double)F.P);
     double dot = 0.0;
     for (int j = threadIdx.x; j < F.cols; j += blockDim.x) {
@@ -256,13 +344,18 @@ void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTa
 
 int precond_dot_blocks(const FFTPlan& F) { return (F.rows + 1) / 2; }
 
+size_t fft_lds_bytes(int P, int ncol) {
+    return ((size_t)ncol * P + (tw_in_lds(P, ncol) ? P / 2 : 0)) * sizeof(double2);
+}
+
 void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, const float* g,
                     float* z, const float* dotv, double* partials, const int* halt, const int* run) {
     const int nrow = (F.rows + 1) / 2;
-    const size_t row_lds = (size_t)F.P * sizeof(double2);
+    const size_t row_lds = fft_lds_bytes(F.P, 1);
     hipLaunchKernelGGL(k_rows_fwd, dim3(nrow), dim3(256), row_lds, st, F, g, run, halt);
     const int ncb = (F.SP + F.CB - 1) / F.CB;
-    hipLaunchKernelGGL(k_cols, dim3(ncb), dim3(256), (size_t)F.CB * row_lds, st, F, mu, rho, run, halt);
+    hipLaunchKernelGGL(k_cols, dim3(ncb), dim3(256), fft_lds_bytes(F.P, F.CB), st, F, mu, rho, run,
+                       halt);
     hipLaunchKernelGGL(k_rows_inv, dim3(nrow), dim3(256), row_lds, st, F, z, run, dotv, partials, halt);
 }
 

@@ -152,6 +152,9 @@ void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, con
                     float* z, const float* dotv, double* partials, const int* halt,
                     const int* run = nullptr);
 int precond_dot_blocks(const FFTPlan& F);
+// Dynamic LDS of an FFT workgroup holding ncol length-P transforms (plus the
+// twiddle table when it fits).
+size_t fft_lds_bytes(int P, int ncol);
 
 // tv.hip (images y, x_{k+1/2} and x_k in float64; t_bar float32)
 void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
