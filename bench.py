@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="also run 8 slices of 2048^2 x 2048 x 2899 (about a minute of phantom setup)")
     ap.add_argument("--large-iters", type=int, default=20)
+    ap.add_argument("--learned512", action="store_true",
+                    help="also train and judge the learned preconditioner at 512^2 x 720 x 725")
     return ap.parse_args()
 
 
@@ -172,6 +174,35 @@ def large_run(sp, torch, iters):
             "R_gbps_equiv": round(eq / (ms_r / 1e3) / 1e9, 1),
             "RT_gbps_equiv": round(eq / (ms_rt / 1e3) / 1e9, 1),
             "all_k": sorted(set(r.k for r in res))}
+
+
+def learned512_run(sp):
+    """The learned preconditioner at the 512^2 x 720 x 725 geometry: trained on
+    4,096 crop interiors (96^2, margin 8) of 64 Gaussian images and 64 gradient
+    snapshots g_{k+1/2} (k = 1..8, phantom seeds 10-17), then time to the plain
+    run's f and TV at loop body 100 on seeds 100-107."""
+    from paper_1807_10151_amd import learned_train as lt
+    g = sp.Geometry(512, 512, 720, 725)
+    cfg = lt.TrainConfig(n_ellipses=20, noise=0.005)
+    cc = lt.CropConfig(crops_per_image=32, n_gauss_images=64, krylov_seeds=tuple(range(10, 18)),
+                       krylov_per_seed=8, n_ellipses=20, noise=0.005)
+    tr = lt.train_crops(g, cfg, cc, log_every=500)
+    log("learned preconditioner trained at 512^2")
+    rows = lt.time_to_target(g, tr.net, list(range(100, 108)), cfg, reps=1)
+    reached = [r for r in rows if r["k_both"] is not None]
+    return {"workload": "512x512, 720 angles, 725 bins, 20 ellipses, 0.5% noise; eval seeds 100-107",
+            "train_s": round(tr.seconds, 2), "probe_s": round(tr.probe_seconds, 2),
+            "loss_first_last": [round(tr.losses[0][1], 4), round(tr.losses[-1][1], 4)],
+            "plain_iterations": 100,
+            "learned_iterations_to_f": [r["k_f"] for r in rows],
+            "learned_iterations_to_tv": [r["k_tv"] for r in rows],
+            "learned_reached_f_and_tv_within_400": f"{len(reached)}/{len(rows)}",
+            "learned_f_at_100_over_target": [round(r["learned_f_at_plain_iters"] / r["f_star"], 4)
+                                             for r in rows],
+            "plain_ms_median": round(1e3 * float(np.median([r["plain_s"] for r in rows])), 3),
+            "learned_ms_to_both_median": (round(1e3 * float(np.median([r["learned_s"] for r in reached])), 3)
+                                          if reached else None),
+            "fallbacks": int(sum(r["fallbacks"] for r in rows))}
 
 
 def learned_run(sp):
@@ -378,6 +409,9 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_run(sp, torch, args.batch_iters)
         log("batched run done")
+    if args.learned512:
+        out["learned_512"] = learned512_run(sp)
+        log("learned preconditioner at 512^2 judged")
     if args.large:
         out["large"] = large_run(sp, torch, args.large_iters)
         log("2048^2 batch done")
