@@ -11,12 +11,16 @@
 // [16][16][3][3], d [16]; tap t = 3 ky + kx reads the input at offset
 // (ky - 1, kx - 1).
 //
-// The 16 -> 16 layers run as implicit GEMM on MFMA: a wave computes 16
-// consecutive pixels of one image row for all 16 output channels with
+// The 16 -> 16 layers run as implicit GEMM on MFMA: a wave computes tiles of
+// 16 consecutive pixels of one image row for all 16 output channels with
 // v_mfma_f32_16x16x4f32 (A = 16 pixels x 4 input channels of one tap,
 // B = 4 input channels x 16 output channels), 9 taps x 4 channel groups =
-// 36 MFMAs per tile; the weights stay in registers.  The 1 <-> 16 layers, the
-// weight gradients, the loss and Adam are plain VALU kernels.
+// 36 MFMAs per tile.  MFMA cg takes input channel 4 kq + cg from lane group
+// kq, so each lane reads its 4 channels of a pixel as one 16-byte load; a wave
+// keeps the weights in registers over LP_TPW tiles with independent
+// accumulators.  The 16 -> 16 weight gradients are MFMA products over the
+// pixels of a tile; the 1 <-> 16 layers, the first layer's weight gradient,
+// the loss and Adam are plain VALU kernels.
 #include "sp_internal.h"
 #include "sp_reduce.h"
 
@@ -25,6 +29,7 @@ namespace sp {
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 constexpr int LF = 16;   // channels
+constexpr int LP_TPW = 4;  // 16-pixel tiles per wave in the 16 -> 16 layers
 
 __device__ __forceinline__ bool in_img(int h, int w, int H, int W) {
     return h >= 0 && h < H && w >= 0 && w < W;
@@ -47,13 +52,9 @@ __global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
     if (run && !*run) return;
     const int lane = threadIdx.x & 63;
     const int wtiles = (W + 15) >> 4;
-    const long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= (long)B * H * wtiles) return;       // whole wave; no barriers below
-    const int wt = (int)(tile % wtiles);
-    const long bh = tile / wtiles;
-    const int h = (int)(bh % H);
-    const int b = (int)(bh / H);
-    const int w0 = wt * 16;
+    const long ntiles = (long)B * H * wtiles;
+    const long tile0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * LP_TPW;
+    if (tile0 >= ntiles) return;                    // whole wave; no barriers below
     const int i = lane & 15;     // A row (pixel) / B column (out channel)
     const int kq = lane >> 4;    // A column / B row within a group of 4 input channels
     float wr[36];
@@ -61,32 +62,60 @@ __global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
     for (int t = 0; t < 9; ++t) {
 #pragma unroll
         for (int cg = 0; cg < 4; ++cg) {
-            const int ci = 4 * cg + kq;
+            const int ci = 4 * kq + cg;   // MFMA cg: lane kq supplies input channel 4 kq + cg
             wr[t * 4 + cg] = TRANS ? Wl[(ci * LF + i) * 9 + (8 - t)] : Wl[(i * LF + ci) * 9 + t];
         }
     }
-    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    // LP_TPW consecutive tiles per wave (weights loaded once, independent
+    // accumulators); tile j = (b, h, w0) of tile0 + j
+    int tb[LP_TPW], th[LP_TPW], tw0[LP_TPW];
+    bool tv[LP_TPW];
+#pragma unroll
+    for (int j = 0; j < LP_TPW; ++j) {
+        const long tile = tile0 + j;
+        tv[j] = tile < ntiles;
+        const long tt = tv[j] ? tile : tile0;
+        tw0[j] = (int)(tt % wtiles) * 16;
+        const long bh = tt / wtiles;
+        th[j] = (int)(bh % H);
+        tb[j] = (int)(bh / H);
+    }
+    f4v acc[LP_TPW];
+#pragma unroll
+    for (int j = 0; j < LP_TPW; ++j) acc[j] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        const int hh = h + t / 3 - 1;
-        const int ww = w0 + i + t % 3 - 1;
-        const bool ok = in_img(hh, ww, H, W);
-        const float* p = in + (((size_t)b * H + (ok ? hh : 0)) * W + (ok ? ww : 0)) * LF + kq;
+        f4v a[LP_TPW];
+#pragma unroll
+        for (int j = 0; j < LP_TPW; ++j) {
+            const int hh = th[j] + t / 3 - 1;
+            const int ww = tw0[j] + i + t % 3 - 1;
+            const bool ok = tv[j] && in_img(hh, ww, H, W);
+            // channels 4 kq .. 4 kq + 3 of the pixel: one 16-byte load
+            const f4v* p = reinterpret_cast<const f4v*>(
+                in + (((size_t)tb[j] * H + (ok ? hh : 0)) * W + (ok ? ww : 0)) * LF + 4 * kq);
+            a[j] = ok ? *p : f4v{0.0f, 0.0f, 0.0f, 0.0f};
+        }
 #pragma unroll
         for (int cg = 0; cg < 4; ++cg) {
-            const float a = ok ? p[4 * cg] : 0.0f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wr[t * 4 + cg], acc, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < LP_TPW; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j][cg], wr[t * 4 + cg], acc[j], 0, 0, 0);
         }
     }
     // lane holds D[4*(lane>>4) + r][lane & 15]: pixel w0 + 4*kq + r, channel i
     const float sc = scale ? scale[i] : 0.0f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int px = w0 + 4 * kq + r;
-        if (px < W) {
-            const size_t o = (((size_t)b * H + h) * W + px) * LF + i;
-            if (out) out[o] = acc[r];
-            if (out2) out2[o] = acc[r] * sc;
+    for (int j = 0; j < LP_TPW; ++j) {
+        if (!tv[j]) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int px = tw0[j] + 4 * kq + r;
+            if (px < W) {
+                const size_t o = (((size_t)tb[j] * H + th[j]) * W + px) * LF + i;
+                if (out) out[o] = acc[j][r];
+                if (out2) out2[o] = acc[j][r] * sc;
+            }
         }
     }
 }
@@ -216,16 +245,17 @@ __global__ __launch_bounds__(256) void k_lp_loss(int B, int H, int W, int margin
     if (threadIdx.x == 0) lpart[b] = nv > 0.0 ? r2 / nv / (double)B : 0.0;
 }
 
-// ---- weight gradient ----------------------------------------------------------
+// ---- weight gradients ----------------------------------------------------------
 // partial[blk][o][i][t] = sum over the block's pixels p of G[p][o] * X[p + t][i]
-// (X zero outside the image).  G: [B][H][W][16]; X: [B][H][W][FI] with FI in
-// {1, 16}.  A block covers a 16 x 16 pixel tile of one image, staged in LDS.
-template <int FI>
-__global__ __launch_bounds__(256) void k_lp_wgrad(int B, int H, int W, const float* __restrict__ G,
-                                                  const float* __restrict__ X,
-                                                  float* __restrict__ partial) {
+// (X zero outside the image).  G: [B][H][W][16]; X: [B][H][W][FI].  A block
+// covers a 16 x 16 pixel tile of one image, staged in LDS.
+//
+// First layer (FI = 1): 16 x 9 outputs, one thread each, on the VALU.
+__global__ __launch_bounds__(256) void k_lp_wgrad1(int B, int H, int W, const float* __restrict__ G,
+                                                   const float* __restrict__ X,
+                                                   float* __restrict__ partial) {
     __shared__ float gs[256 * LF];
-    __shared__ float xs[18 * 18 * FI];
+    __shared__ float xs[18 * 18];
     const int tx = (W + 15) / 16, ty = (H + 15) / 16;
     const int blk = blockIdx.x;
     const int b = blk / (tx * ty);
@@ -236,39 +266,69 @@ __global__ __launch_bounds__(256) void k_lp_wgrad(int B, int H, int W, const flo
         const int yy = y0 + p / 16, xx = x0 + p % 16;
         gs[q] = in_img(yy, xx, H, W) ? G[(((size_t)b * H + yy) * W + xx) * LF + c] : 0.0f;
     }
-    for (int q = threadIdx.x; q < 18 * 18 * FI; q += 256) {
-        const int p = q / FI, c = q - p * FI;
-        const int yy = y0 - 1 + p / 18, xx = x0 - 1 + p % 18;
-        xs[q] = in_img(yy, xx, H, W) ? X[(((size_t)b * H + yy) * W + xx) * FI + c] : 0.0f;
+    for (int q = threadIdx.x; q < 18 * 18; q += 256) {
+        const int yy = y0 - 1 + q / 18, xx = x0 - 1 + q % 18;
+        xs[q] = in_img(yy, xx, H, W) ? X[((size_t)b * H + yy) * W + xx] : 0.0f;
     }
     __syncthreads();
-    const int nout = LF * FI * 9;
-    float* dst = partial + (size_t)blk * nout;
-    if (FI == LF) {
-        const int o = threadIdx.x / LF, i = threadIdx.x % LF;
-        float acc[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+    if (threadIdx.x < LF * 9) {
+        const int o = threadIdx.x / 9, t = threadIdx.x % 9;
+        float acc = 0.0f;
         for (int p = 0; p < 256; ++p) {
-            const float gv = gs[p * LF + o];
             const int py = p / 16, px = p % 16;
-#pragma unroll
-            for (int t = 0; t < 9; ++t)
-                acc[t] = fmaf(gv, xs[((py + t / 3) * 18 + px + t % 3) * FI + i], acc[t]);
+            acc = fmaf(gs[p * LF + o], xs[(py + t / 3) * 18 + px + t % 3], acc);
         }
-#pragma unroll
-        for (int t = 0; t < 9; ++t) dst[(o * FI + i) * 9 + t] = acc[t];
-    } else {
-        if (threadIdx.x < nout) {
-            const int o = threadIdx.x / 9, t = threadIdx.x % 9;
-            float acc = 0.0f;
-            for (int p = 0; p < 256; ++p) {
-                const int py = p / 16, px = p % 16;
-                acc = fmaf(gs[p * LF + o], xs[((py + t / 3) * 18 + px + t % 3) * FI], acc);
-            }
-            dst[threadIdx.x] = acc;
-        }
+        partial[(size_t)blk * (LF * 9) + threadIdx.x] = acc;
     }
+}
+
+// The 16 -> 16 weight gradient on MFMA: per tap t, dW_t[o][ci] = sum_p
+// G[p][o] X[p + t][ci] is a [16 x 256] x [256 x 16] product over the tile's
+// pixels.  Nine waves per block, one per tap, each 64 v_mfma_f32_16x16x4f32
+// (A = G of 4 pixels, B = X of the same 4 pixels shifted by the tap) over the
+// LDS-staged tile; no cross-wave sum, so the partial of a block is written
+// once per output.
+constexpr int LP_WG_THREADS = 64 * 9;
+
+__global__ __launch_bounds__(LP_WG_THREADS) void k_lp_wgrad_mfma(int B, int H, int W,
+                                                               const float* __restrict__ G,
+                                                               const float* __restrict__ X,
+                                                               float* __restrict__ partial) {
+    __shared__ float gs[256 * LF];
+    __shared__ float xs[18 * 18 * LF];
+    const int tx = (W + 15) / 16, ty = (H + 15) / 16;
+    const int blk = blockIdx.x;
+    const int b = blk / (tx * ty);
+    const int rem = blk - b * tx * ty;
+    const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
+    for (int q = threadIdx.x; q < 256 * LF; q += LP_WG_THREADS) {
+        const int p = q / LF, c = q - p * LF;
+        const int yy = y0 + p / 16, xx = x0 + p % 16;
+        gs[q] = in_img(yy, xx, H, W) ? G[(((size_t)b * H + yy) * W + xx) * LF + c] : 0.0f;
+    }
+    for (int q = threadIdx.x; q < 18 * 18 * LF; q += LP_WG_THREADS) {
+        const int p = q / LF, c = q - p * LF;
+        const int yy = y0 - 1 + p / 18, xx = x0 - 1 + p % 18;
+        xs[q] = in_img(yy, xx, H, W) ? X[(((size_t)b * H + yy) * W + xx) * LF + c] : 0.0f;
+    }
+    __syncthreads();
+    const int t = threadIdx.x >> 6;          // tap of this wave
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, kq = lane >> 4;
+    const int dy = t / 3, dx = t % 3;
+    f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (int p0 = 0; p0 < 256; p0 += 4) {
+        const int p = p0 + kq;               // this lane's K slot: pixel p of the tile
+        const int py = p >> 4, px = p & 15;
+        const float a = gs[p * LF + i];                                  // A[o = i][k] = G[p][o]
+        const float bv = xs[((py + dy) * 18 + px + dx) * LF + i];         // B[k][ci = i] = X[p + t][ci]
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+    }
+    // lane holds D[4 kq + r][i] = dW_t[o = 4 kq + r][ci = i]
+    float* dst = partial + (size_t)blk * (LF * LF * 9);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[((4 * kq + r) * LF + i) * 9 + t] = acc[r];
 }
 
 // Two-level fixed-order float64 sum over blocks: tmp[chunk][q] sums the
@@ -343,7 +403,7 @@ static inline unsigned nblk(long n, int per) { return (unsigned)((n + per - 1) /
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
                  const float* Wl, const float* scale, float* out2, const int* halt, const int* run) {
     const long tiles = (long)B * H * ((W + 15) / 16);
-    const unsigned g = nblk(tiles, 4);
+    const unsigned g = nblk(tiles, 4 * LP_TPW);
     if (trans)
         hipLaunchKernelGGL(k_lp_conv_mid<true>, dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
     else
@@ -396,9 +456,9 @@ int lp_wgrad_blocks(int B, int H, int W) { return B * ((W + 15) / 16) * ((H + 15
 void lp_wgrad(hipStream_t st, int fi, int B, int H, int W, const float* G, const float* X, float* partial) {
     const unsigned g = (unsigned)lp_wgrad_blocks(B, H, W);
     if (fi == LF)
-        hipLaunchKernelGGL(k_lp_wgrad<LF>, dim3(g), dim3(256), 0, st, B, H, W, G, X, partial);
+        hipLaunchKernelGGL(k_lp_wgrad_mfma, dim3(g), dim3(LP_WG_THREADS), 0, st, B, H, W, G, X, partial);
     else
-        hipLaunchKernelGGL(k_lp_wgrad<1>, dim3(g), dim3(256), 0, st, B, H, W, G, X, partial);
+        hipLaunchKernelGGL(k_lp_wgrad1, dim3(g), dim3(256), 0, st, B, H, W, G, X, partial);
 }
 
 int lp_reduce_chunks(int nb) { return (nb + LP_CHUNK - 1) / LP_CHUNK; }

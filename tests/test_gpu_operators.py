@@ -109,6 +109,26 @@ def test_project_ct512_sampled_rays(sp):
     assert rel_l2(got[aa, kk], want) <= 1e-5
 
 
+@pytest.mark.parametrize("side,n_angles,n_bins", [(256, 360, 364), (384, 536, 545), (1536, 2152, 2174)])
+def test_project_split_rays_sampled(sp, side, n_angles, n_bins):
+    # geometries whose rays R sums in 4, 2 and 8 parts (an underfilled grid,
+    # a nearly full one, an image of more than 2^21 pixels), on 300 rays
+    # computed one by one by the oracle's crossing merge
+    og = OG(side, side, n_angles, n_bins)
+    from synth import random_ellipses
+    img, _ = random_ellipses(side, side, 20, 3)
+    img32 = img.astype(np.float32)
+    got = sp.sp_project(G(og), cuda(img32)).cpu().numpy()
+    rng = np.random.default_rng(side)
+    aa = rng.integers(0, n_angles, 300)
+    kk = rng.integers(0, n_bins, 300)
+    aa[:2] = [0, n_angles // 2]
+    kk[:2] = [n_bins // 2, n_bins // 2]
+    want = np.array([siddon.ray_sum(og, img32.astype(np.float64).ravel(), int(a), int(k))
+                     for a, k in zip(aa, kk)])
+    assert rel_l2(got[aa, kk], want) <= 1e-5
+
+
 def test_backproject_ct512_sampled_pixels(sp):
     og = OG(512, 512, 720, 725)
     rng = np.random.default_rng(23)
