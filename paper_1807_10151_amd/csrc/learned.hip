@@ -248,46 +248,75 @@ __global__ __launch_bounds__(256) void k_lp_loss(int B, int H, int W, int margin
 // ---- weight gradients ----------------------------------------------------------
 // partial[blk][o][i][t] = sum over the block's pixels p of G[p][o] * X[p + t][i]
 // (X zero outside the image).  G: [B][H][W][16]; X: [B][H][W][FI].  A block
-// covers a 16 x 16 pixel tile of one image, staged in LDS.
-//
+// covers LP_WG_TILES consecutive 16 x 16 pixel tiles of one tile row of one
+// image, each staged in LDS in turn.
+constexpr int LP_WG_TILES = 4;
+
+struct WgTile {
+    int b, y0, x0, ntile;   // image, tile row origin, first tile's column origin, tiles in the block
+};
+
+__device__ __forceinline__ WgTile wg_tile(int blk, int H, int W) {
+    const int tx = (W + 15) / 16, ty = (H + 15) / 16;
+    const int gx = (tx + LP_WG_TILES - 1) / LP_WG_TILES;
+    const int b = blk / (gx * ty);
+    const int rem = blk - b * gx * ty;
+    const int g = rem % gx;
+    WgTile T;
+    T.b = b;
+    T.y0 = (rem / gx) * 16;
+    T.x0 = g * LP_WG_TILES * 16;
+    T.ntile = min(LP_WG_TILES, tx - g * LP_WG_TILES);
+    return T;
+}
+
+// Stages tile j of the block: gs = G over the tile, xs = X over the tile and
+// a one-pixel halo (FI channels).
+template <int FI, int NT>
+__device__ __forceinline__ void wg_stage(const WgTile& T, int j, int H, int W, const float* __restrict__ G,
+                                         const float* __restrict__ X, float* gs, float* xs) {
+    const int x0 = T.x0 + 16 * j;
+    for (int q = threadIdx.x; q < 256 * LF; q += NT) {
+        const int p = q / LF, c = q - p * LF;
+        const int yy = T.y0 + p / 16, xx = x0 + p % 16;
+        gs[q] = in_img(yy, xx, H, W) ? G[(((size_t)T.b * H + yy) * W + xx) * LF + c] : 0.0f;
+    }
+    for (int q = threadIdx.x; q < 18 * 18 * FI; q += NT) {
+        const int p = q / FI, c = q - p * FI;
+        const int yy = T.y0 - 1 + p / 18, xx = x0 - 1 + p % 18;
+        xs[q] = in_img(yy, xx, H, W) ? X[(((size_t)T.b * H + yy) * W + xx) * FI + c] : 0.0f;
+    }
+}
+
 // First layer (FI = 1): 16 x 9 outputs, one thread each, on the VALU.
 __global__ __launch_bounds__(256) void k_lp_wgrad1(int B, int H, int W, const float* __restrict__ G,
                                                    const float* __restrict__ X,
                                                    float* __restrict__ partial) {
     __shared__ float gs[256 * LF];
     __shared__ float xs[18 * 18];
-    const int tx = (W + 15) / 16, ty = (H + 15) / 16;
-    const int blk = blockIdx.x;
-    const int b = blk / (tx * ty);
-    const int rem = blk - b * tx * ty;
-    const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
-    for (int q = threadIdx.x; q < 256 * LF; q += 256) {
-        const int p = q / LF, c = q - p * LF;
-        const int yy = y0 + p / 16, xx = x0 + p % 16;
-        gs[q] = in_img(yy, xx, H, W) ? G[(((size_t)b * H + yy) * W + xx) * LF + c] : 0.0f;
-    }
-    for (int q = threadIdx.x; q < 18 * 18; q += 256) {
-        const int yy = y0 - 1 + q / 18, xx = x0 - 1 + q % 18;
-        xs[q] = in_img(yy, xx, H, W) ? X[((size_t)b * H + yy) * W + xx] : 0.0f;
-    }
-    __syncthreads();
-    if (threadIdx.x < LF * 9) {
-        const int o = threadIdx.x / 9, t = threadIdx.x % 9;
-        float acc = 0.0f;
-        for (int p = 0; p < 256; ++p) {
-            const int py = p / 16, px = p % 16;
-            acc = fmaf(gs[p * LF + o], xs[(py + t / 3) * 18 + px + t % 3], acc);
+    const WgTile T = wg_tile(blockIdx.x, H, W);
+    const int o = threadIdx.x / 9, t = threadIdx.x % 9;
+    float acc = 0.0f;
+    for (int j = 0; j < T.ntile; ++j) {
+        if (j) __syncthreads();             // the previous tile's reads are done
+        wg_stage<1, 256>(T, j, H, W, G, X, gs, xs);
+        __syncthreads();
+        if (threadIdx.x < LF * 9) {
+            for (int p = 0; p < 256; ++p) {
+                const int py = p / 16, px = p % 16;
+                acc = fmaf(gs[p * LF + o], xs[(py + t / 3) * 18 + px + t % 3], acc);
+            }
         }
-        partial[(size_t)blk * (LF * 9) + threadIdx.x] = acc;
     }
+    if (threadIdx.x < LF * 9) partial[(size_t)blockIdx.x * (LF * 9) + threadIdx.x] = acc;
 }
 
 // The 16 -> 16 weight gradient on MFMA: per tap t, dW_t[o][ci] = sum_p
-// G[p][o] X[p + t][ci] is a [16 x 256] x [256 x 16] product over the tile's
+// G[p][o] X[p + t][ci] is a [16 x 256] x [256 x 16] product over a tile's
 // pixels.  Nine waves per block, one per tap, each 64 v_mfma_f32_16x16x4f32
-// (A = G of 4 pixels, B = X of the same 4 pixels shifted by the tap) over the
-// LDS-staged tile; no cross-wave sum, so the partial of a block is written
-// once per output.
+// per tile (A = G of 4 pixels, B = X of the same 4 pixels shifted by the tap)
+// over the LDS-staged tiles; no cross-wave sum, so the partial of a block is
+// written once per output.
 constexpr int LP_WG_THREADS = 64 * 9;
 
 __global__ __launch_bounds__(LP_WG_THREADS) void k_lp_wgrad_mfma(int B, int H, int W,
@@ -296,37 +325,27 @@ __global__ __launch_bounds__(LP_WG_THREADS) void k_lp_wgrad_mfma(int B, int H, i
                                                                float* __restrict__ partial) {
     __shared__ float gs[256 * LF];
     __shared__ float xs[18 * 18 * LF];
-    const int tx = (W + 15) / 16, ty = (H + 15) / 16;
-    const int blk = blockIdx.x;
-    const int b = blk / (tx * ty);
-    const int rem = blk - b * tx * ty;
-    const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
-    for (int q = threadIdx.x; q < 256 * LF; q += LP_WG_THREADS) {
-        const int p = q / LF, c = q - p * LF;
-        const int yy = y0 + p / 16, xx = x0 + p % 16;
-        gs[q] = in_img(yy, xx, H, W) ? G[(((size_t)b * H + yy) * W + xx) * LF + c] : 0.0f;
-    }
-    for (int q = threadIdx.x; q < 18 * 18 * LF; q += LP_WG_THREADS) {
-        const int p = q / LF, c = q - p * LF;
-        const int yy = y0 - 1 + p / 18, xx = x0 - 1 + p % 18;
-        xs[q] = in_img(yy, xx, H, W) ? X[(((size_t)b * H + yy) * W + xx) * LF + c] : 0.0f;
-    }
-    __syncthreads();
+    const WgTile T = wg_tile(blockIdx.x, H, W);
     const int t = threadIdx.x >> 6;          // tap of this wave
     const int lane = threadIdx.x & 63;
     const int i = lane & 15, kq = lane >> 4;
     const int dy = t / 3, dx = t % 3;
     f4v acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < T.ntile; ++j) {
+        if (j) __syncthreads();             // the previous tile's reads are done
+        wg_stage<LF, LP_WG_THREADS>(T, j, H, W, G, X, gs, xs);
+        __syncthreads();
 #pragma unroll 4
-    for (int p0 = 0; p0 < 256; p0 += 4) {
-        const int p = p0 + kq;               // this lane's K slot: pixel p of the tile
-        const int py = p >> 4, px = p & 15;
-        const float a = gs[p * LF + i];                                  // A[o = i][k] = G[p][o]
-        const float bv = xs[((py + dy) * 18 + px + dx) * LF + i];         // B[k][ci = i] = X[p + t][ci]
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+        for (int p0 = 0; p0 < 256; p0 += 4) {
+            const int p = p0 + kq;           // this lane's K slot: pixel p of the tile
+            const int py = p >> 4, px = p & 15;
+            const float a = gs[p * LF + i];                              // A[o = i][k] = G[p][o]
+            const float bv = xs[((py + dy) * 18 + px + dx) * LF + i];     // B[k][ci = i] = X[p + t][ci]
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+        }
     }
     // lane holds D[4 kq + r][i] = dW_t[o = 4 kq + r][ci = i]
-    float* dst = partial + (size_t)blk * (LF * LF * 9);
+    float* dst = partial + (size_t)blockIdx.x * (LF * LF * 9);
 #pragma unroll
     for (int r = 0; r < 4; ++r) dst[((4 * kq + r) * LF + i) * 9 + t] = acc[r];
 }
@@ -373,13 +392,21 @@ __global__ __launch_bounds__(256) void k_lp_gd_part(long npix, const float* __re
     }
 }
 
-__global__ void k_lp_gd_final(int nblk, const double* __restrict__ part, const float* __restrict__ sg,
-                              float* __restrict__ gd) {
-    const int c = threadIdx.x;
-    if (c < LF) {
+// 16 groups of threads per channel sum strided blocks, then the groups are
+// added in order.
+__global__ __launch_bounds__(256) void k_lp_gd_final(int nblk, const double* __restrict__ part,
+                                                     const float* __restrict__ sg,
+                                                     float* __restrict__ gd) {
+    __shared__ double red[256];
+    const int c = threadIdx.x & (LF - 1), grp = threadIdx.x >> 4;
+    double s = 0.0;
+    for (int k = grp; k < nblk; k += 16) s += part[(size_t)k * LF + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < LF) {
         double t = 0.0;
-        for (int k = 0; k < nblk; ++k) t += part[(size_t)k * LF + c];
-        gd[c] = (float)(t * (double)sg[c]);
+        for (int g = 0; g < 16; ++g) t += red[g * LF + threadIdx.x];
+        gd[threadIdx.x] = (float)(t * (double)sg[threadIdx.x]);
     }
 }
 
@@ -451,7 +478,9 @@ void lp_loss(hipStream_t st, int B, int H, int W, int margin, const float* z, co
                        lpart);
 }
 
-int lp_wgrad_blocks(int B, int H, int W) { return B * ((W + 15) / 16) * ((H + 15) / 16); }
+int lp_wgrad_blocks(int B, int H, int W) {
+    return B * ((H + 15) / 16) * (((W + 15) / 16 + LP_WG_TILES - 1) / LP_WG_TILES);
+}
 
 void lp_wgrad(hipStream_t st, int fi, int B, int H, int W, const float* G, const float* X, float* partial) {
     const unsigned g = (unsigned)lp_wgrad_blocks(B, H, W);
@@ -471,12 +500,12 @@ void lp_reduce(hipStream_t st, int nb, int nout, const float* pa, bool accumulat
                        accumulate ? 1 : 0, out);
 }
 
-int lp_gd_blocks() { return 512; }
+int lp_gd_blocks() { return 2048; }
 
 void lp_gd(hipStream_t st, long npix, const float* E, const float* A, double* part, const float* sg,
            float* gd) {
     hipLaunchKernelGGL(k_lp_gd_part, dim3(lp_gd_blocks()), dim3(256), 0, st, npix, E, A, part);
-    hipLaunchKernelGGL(k_lp_gd_final, dim3(1), dim3(64), 0, st, lp_gd_blocks(), part, sg, gd);
+    hipLaunchKernelGGL(k_lp_gd_final, dim3(1), dim3(256), 0, st, lp_gd_blocks(), part, sg, gd);
 }
 
 void lp_adam(hipStream_t st, int n, float* theta, float* m, float* v, const float* g, double lr,
