@@ -249,8 +249,9 @@ __global__ __launch_bounds__(256) void k_lp_loss(int B, int H, int W, int margin
 // partial[blk][o][i][t] = sum over the block's pixels p of G[p][o] * X[p + t][i]
 // (X zero outside the image).  G: [B][H][W][16]; X: [B][H][W][FI].  A block
 // covers LP_WG_TILES consecutive 16 x 16 pixel tiles of one tile row of one
-// image, each staged in LDS in turn.
-constexpr int LP_WG_TILES = 4;
+// image, each staged in LDS in turn (one: more blocks in flight outweigh the
+// smaller reduction that larger blocks leave).
+constexpr int LP_WG_TILES = 1;
 
 struct WgTile {
     int b, y0, x0, ntile;   // image, tile row origin, first tile's column origin, tiles in the block
