@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--eager", action="store_true", help="launch the loop eagerly, no graph")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-slice batched run")
+    ap.add_argument("--learned-steps", type=int, default=2000,
+                    help="Adam steps of the 64^2 learned preconditioner (shorter for profiling)")
+    ap.add_argument("--learned-seeds", type=int, default=32, help="evaluation seeds from 100")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training the learned preconditioner and its time-to-target")
     ap.add_argument("--batch-iters", type=int, default=20)
@@ -205,18 +208,19 @@ def learned512_run(sp):
             "fallbacks": int(sum(r["fallbacks"] for r in rows))}
 
 
-def learned_run(sp):
+def learned_run(sp, steps=2000, n_seeds=32):
     """Train M = C^T diag(softplus(d)) C on the 64x64 / 90-angle geometry and
     compare its time to the plain (Fourier M) run's f and TV at loop body 100."""
     from paper_1807_10151_amd import learned_train as lt
     g = sp.Geometry(64, 64, 90, 91)
-    cfg = lt.TrainConfig()
+    cfg = lt.TrainConfig(steps=steps)
     res = lt.train(g, cfg, log_every=500)
-    rows = lt.time_to_target(g, res.net, list(range(100, 132)), cfg, reps=1)
+    rows = lt.time_to_target(g, res.net, list(range(100, 100 + n_seeds)), cfg, reps=1)
     kf = [r["k_f"] for r in rows]
     kb = [r["k_both"] for r in rows]
     reached = [r for r in rows if r["k_both"] is not None]
-    return {"workload": "64x64, 90 angles, 91 bins, 5 ellipses, 1% noise; eval seeds 100-131",
+    return {"workload": f"64x64, 90 angles, 91 bins, 5 ellipses, 1% noise; eval seeds 100-{99 + n_seeds}",
+            "adam_steps": steps,
             "train_s": round(res.seconds, 3), "probe_s": round(res.probe_seconds, 3),
             "loss_first_last": [round(res.losses[0][1], 5), round(res.losses[-1][1], 5)],
             "plain_iterations": 100,
@@ -416,7 +420,7 @@ def main():
         out["large"] = large_run(sp, torch, args.large_iters)
         log("2048^2 batch done")
     if not args.no_learned:
-        out["time_to_target"] = learned_run(sp)
+        out["time_to_target"] = learned_run(sp, args.learned_steps, args.learned_seeds)
         log("learned preconditioner trained and timed")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(img, b_np)

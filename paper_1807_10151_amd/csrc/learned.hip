@@ -17,7 +17,8 @@
 // B = 4 input channels x 16 output channels), 9 taps x 4 channel groups =
 // 36 MFMAs per tile.  MFMA cg takes input channel 4 kq + cg from lane group
 // kq, so each lane reads its 4 channels of a pixel as one 16-byte load; a wave
-// keeps the weights in registers over LP_TPW tiles with independent
+// keeps the weights in registers over TPW tiles (4 for large grids, 1 for
+// small ones, which need the waves more) with independent
 // accumulators.  The 16 -> 16 weight gradients are MFMA products over the
 // pixels of a tile; the 1 <-> 16 layers, the first layer's weight gradient,
 // the loss and Adam are plain VALU kernels.
@@ -29,7 +30,6 @@ namespace sp {
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 constexpr int LF = 16;   // channels
-constexpr int LP_TPW = 4;  // 16-pixel tiles per wave in the 16 -> 16 layers
 
 __device__ __forceinline__ bool in_img(int h, int w, int H, int W) {
     return h >= 0 && h < H && w >= 0 && w < W;
@@ -39,7 +39,7 @@ __device__ __forceinline__ bool in_img(int h, int w, int H, int W) {
 // out[b,h,w,j] = sum_{t, ci} in[b, h+dy_t, w+dx_t, ci] * K[j][ci][t], with
 // K = W (TRANS = false) or K[j][ci][t] = W[ci][j][8 - t] (TRANS: the adjoint).
 // If scale != nullptr, out2 = scale[j] * out as well.
-template <bool TRANS>
+template <bool TRANS, int TPW>
 __global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
                                                      const float* __restrict__ in,
                                                      float* __restrict__ out,
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
     const int lane = threadIdx.x & 63;
     const int wtiles = (W + 15) >> 4;
     const long ntiles = (long)B * H * wtiles;
-    const long tile0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * LP_TPW;
+    const long tile0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * TPW;
     if (tile0 >= ntiles) return;                    // whole wave; no barriers below
     const int i = lane & 15;     // A row (pixel) / B column (out channel)
     const int kq = lane >> 4;    // A column / B row within a group of 4 input channels
@@ -66,12 +66,12 @@ __global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
             wr[t * 4 + cg] = TRANS ? Wl[(ci * LF + i) * 9 + (8 - t)] : Wl[(i * LF + ci) * 9 + t];
         }
     }
-    // LP_TPW consecutive tiles per wave (weights loaded once, independent
+    // TPW consecutive tiles per wave (weights loaded once, independent
     // accumulators); tile j = (b, h, w0) of tile0 + j
-    int tb[LP_TPW], th[LP_TPW], tw0[LP_TPW];
-    bool tv[LP_TPW];
+    int tb[TPW], th[TPW], tw0[TPW];
+    bool tv[TPW];
 #pragma unroll
-    for (int j = 0; j < LP_TPW; ++j) {
+    for (int j = 0; j < TPW; ++j) {
         const long tile = tile0 + j;
         tv[j] = tile < ntiles;
         const long tt = tv[j] ? tile : tile0;
@@ -80,14 +80,14 @@ __global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
         th[j] = (int)(bh % H);
         tb[j] = (int)(bh / H);
     }
-    f4v acc[LP_TPW];
+    f4v acc[TPW];
 #pragma unroll
-    for (int j = 0; j < LP_TPW; ++j) acc[j] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < TPW; ++j) acc[j] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        f4v a[LP_TPW];
+        f4v a[TPW];
 #pragma unroll
-        for (int j = 0; j < LP_TPW; ++j) {
+        for (int j = 0; j < TPW; ++j) {
             const int hh = th[j] + t / 3 - 1;
             const int ww = tw0[j] + i + t % 3 - 1;
             const bool ok = tv[j] && in_img(hh, ww, H, W);
@@ -99,14 +99,14 @@ __global__ __launch_bounds__(256) void k_lp_conv_mid(int B, int H, int W,
 #pragma unroll
         for (int cg = 0; cg < 4; ++cg) {
 #pragma unroll
-            for (int j = 0; j < LP_TPW; ++j)
+            for (int j = 0; j < TPW; ++j)
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j][cg], wr[t * 4 + cg], acc[j], 0, 0, 0);
         }
     }
     // lane holds D[4*(lane>>4) + r][lane & 15]: pixel w0 + 4*kq + r, channel i
     const float sc = scale ? scale[i] : 0.0f;
 #pragma unroll
-    for (int j = 0; j < LP_TPW; ++j) {
+    for (int j = 0; j < TPW; ++j) {
         if (!tv[j]) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -431,11 +431,20 @@ static inline unsigned nblk(long n, int per) { return (unsigned)((n + per - 1) /
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
                  const float* Wl, const float* scale, float* out2, const int* halt, const int* run) {
     const long tiles = (long)B * H * ((W + 15) / 16);
-    const unsigned g = nblk(tiles, 4 * LP_TPW);
-    if (trans)
-        hipLaunchKernelGGL(k_lp_conv_mid<true>, dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
-    else
-        hipLaunchKernelGGL(k_lp_conv_mid<false>, dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
+    // four tiles per wave once the grid has enough of them to fill the GPU
+    if (tiles >= 16384) {
+        const unsigned g = nblk(tiles, 16);
+        if (trans)
+            hipLaunchKernelGGL((k_lp_conv_mid<true, 4>), dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
+        else
+            hipLaunchKernelGGL((k_lp_conv_mid<false, 4>), dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
+    } else {
+        const unsigned g = nblk(tiles, 4);
+        if (trans)
+            hipLaunchKernelGGL((k_lp_conv_mid<true, 1>), dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
+        else
+            hipLaunchKernelGGL((k_lp_conv_mid<false, 1>), dim3(g), dim3(256), 0, st, B, H, W, in, out, Wl, scale, out2, halt, run);
+    }
 }
 
 void lp_conv_in(hipStream_t st, int B, int H, int W, const float* in, const int32_t* idx, int nsrc,
