@@ -456,35 +456,56 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp
 // pads -- in both cases every true candidate lies outside the detector.  A
 // candidate that reads a pad gets a weight evaluated at the pad's position and
 // multiplies 0.
+// Each lane sums two pixels of one row, (xj0, yi) and (xj1, yi): the angle's
+// uniform work (constants, yi s) is shared, the per-pixel sequence is the one
+// above.
 template <bool HORIZ, bool AXIS, int NB, bool LSK, class TY>
-__device__ __forceinline__ double bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
-                                           int beg, int end, const TY* __restrict__ yp,
-                                           const double* __restrict__ skg, const double* sks,
-                                           double xj, double yi, double acc) {
+__device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
+                                         int beg, int end, const TY* __restrict__ yp,
+                                         const double* __restrict__ skg, const double* sks,
+                                         double xj0, double xj1, double yi, double& acc0,
+                                         double& acc1) {
     const unsigned kmax = (unsigned)(G.nB + 2 * PAD - NB);   // last padded start index
 #pragma unroll 2
     for (int a = beg; a < end; ++a) {
         const AngleDev A = ang[a];
-        const double t = HORIZ ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
-        const unsigned o = min((unsigned)(int)fma(t, G.inv_ds, A.kb), kmax);
-        const TY* pv = at(yp + (size_t)A.row * G.pitchB, o);
-        const double* ps = LSK ? sks + o : skg + o;
-        TY v[NB];
-        double sk[NB];
+        const TY* row = yp + (size_t)A.row * G.pitchB;
+        double t[2];
+        if (HORIZ) {
+            t[0] = fma(yi, A.s, xj0 * A.c);
+            t[1] = fma(yi, A.s, xj1 * A.c);
+        } else {
+            const double ys = yi * A.s;
+            t[0] = fma(xj0, A.c, ys);
+            t[1] = fma(xj1, A.c, ys);
+        }
+        TY v[2][NB];
+        double sk[2][NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) v[q] = pv[q];
+        for (int u = 0; u < 2; ++u) {
+            const unsigned o = min((unsigned)(int)fma(t[u], G.inv_ds, A.kb), kmax);
+            const TY* pv = at(row, o);
+            const double* ps = LSK ? sks + o : skg + o;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) sk[q] = ps[q];
+            for (int q = 0; q < NB; ++q) v[u][q] = pv[q];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) sk[u][q] = ps[q];
+        }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const double d = sk[q] - t;
-            acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[q], acc);
+            const double d = sk[0][q] - t[0];
+            acc0 = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[0][q], acc0);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const double d = sk[1][q] - t[1];
+            acc1 = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[1][q], acc1);
         }
     }
-    return acc;
 }
 
-constexpr int BP_TILE = 8;      // 8 x 8 pixels per wave
+constexpr int BP_TILE = 8;      // 8 rows x 16 columns per wave (two pixels per lane)
+constexpr int BP_TW = 16;
 constexpr int BP_SPLIT = 4;     // waves per workgroup, each over a quarter of the angles
 // The bin-position table goes to LDS when it takes at most this many bytes.
 constexpr size_t BP_LDS_SK_MAX = 24 * 1024;
@@ -497,7 +518,8 @@ __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int
 
 // out[i][j] = (R^T y)_{ij} from the padded sinogram yp; with dotv != nullptr
 // also the float64 partial sum of out * dotv per workgroup.  A workgroup owns
-// an 8 x 8 pixel tile; its wave w sums the w-th quarter of every angle class,
+// an 8 x 16 pixel tile (two pixels, 8 columns apart, per lane); its wave w
+// sums the w-th quarter of every angle class,
 // and the four partial sums are added in wave order through LDS.  With LSK the
 // workgroup first writes the bin-position table into the dynamic LDS `sks`.
 template <int NB, bool LSK, class TY>
@@ -508,7 +530,7 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
                                                  const double* __restrict__ dotv,
                                                  double* __restrict__ partials, int bx, int by,
                                                  int gx) {
-    __shared__ double part[BP_SPLIT][64];
+    __shared__ double part[BP_SPLIT][2][64];
     __shared__ double red[4];
     if (LSK) {
         for (int k = threadIdx.x; k < G.nB + 2 * PAD; k += 256) sks[k] = bin_pos((double)(k - PAD), G);
@@ -517,29 +539,34 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = by * BP_TILE + (lane >> 3);
-    const int j = bx * BP_TILE + (lane & 7);
-    const double xj = (double)j - G.xoff;
+    const int j0 = bx * BP_TW + (lane & 7), j1 = j0 + 8;
     const double yi = G.yoff - (double)i;
-    double acc = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
+    const double xj0 = (double)j0 - G.xoff, xj1 = (double)j1 - G.xoff;
     int b, e;
     split_range(G.cls[0], G.cls[1], w, b, e);
-    acc = bp_class<false, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    bp_class<false, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
     split_range(G.cls[1], G.cls[2], w, b, e);
-    acc = bp_class<true, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    bp_class<true, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
     split_range(G.cls[2], G.cls[3], w, b, e);
-    acc = bp_class<false, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    bp_class<false, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
     split_range(G.cls[3], G.cls[4], w, b, e);
-    acc = bp_class<true, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
-    part[w][lane] = acc;
+    bp_class<true, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
+    part[w][0][lane] = acc0;
+    part[w][1][lane] = acc1;
     __syncthreads();
     double v = 0.0;
     if (w == 0) {
-        const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-        const float val = (float)(tot * G.pixel);
-        const bool valid = i < G.rows && j < G.cols;
-        if (valid) {
-            out[(size_t)i * G.cols + j] = val;
-            if (dotv) v = (double)val * dotv[(size_t)i * G.cols + j];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int j = u ? j1 : j0;
+            const double tot =
+                ((part[0][u][lane] + part[1][u][lane]) + part[2][u][lane]) + part[3][u][lane];
+            const float val = (float)(tot * G.pixel);
+            if (i < G.rows && j < G.cols) {
+                out[(size_t)i * G.cols + j] = val;
+                if (dotv) v += (double)val * dotv[(size_t)i * G.cols + j];
+            }
         }
     }
     if (dotv) {
@@ -573,7 +600,7 @@ __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
-        const int gx = (G.cols + BP_TILE - 1) / BP_TILE;
+        const int gx = (G.cols + BP_TW - 1) / BP_TW;
         const TY* yp;
         if constexpr (normal) yp = gmem(S.rp);
         else yp = gmem(S.rpd);
@@ -611,14 +638,14 @@ void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int n
 }
 
 int backproject_blocks(const GeomDev& G) {
-    return ((G.cols + BP_TILE - 1) / BP_TILE) * ((G.rows + BP_TILE - 1) / BP_TILE);
+    return ((G.cols + BP_TW - 1) / BP_TW) * ((G.rows + BP_TILE - 1) / BP_TILE);
 }
 
 template <bool LSK, class TY>
 void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp,
                const double* skp, float* out, const double* dotv, double* partials, const int* halt,
                size_t lds) {
-    dim3 grid((G.cols + BP_TILE - 1) / BP_TILE, (G.rows + BP_TILE - 1) / BP_TILE);
+    dim3 grid((G.cols + BP_TW - 1) / BP_TW, (G.rows + BP_TILE - 1) / BP_TILE);
     switch (G.nbmax) {
     case 1: hipLaunchKernelGGL((k_backproject<1, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
     case 2: hipLaunchKernelGGL((k_backproject<2, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
