@@ -23,10 +23,11 @@
 // columns outside the image are clamped into a zero pad and contribute 0.
 // Horizontal angles walk columns of a zero-padded transposed copy.
 //
-// Backward gather.  A lane owns one pixel and loops over the angles, which are
-// sorted into four classes (vertical/horizontal x oblique/axis-parallel) so
-// the inner loop has no branch; at each angle the pixel's nonzero bins are the
-// NB bins after floor(kf - hb), read from a zero-padded sinogram.
+// Backward gather.  A lane owns two pixels of one row and loops over the
+// angles, which are sorted into four classes (vertical/horizontal x
+// oblique/axis-parallel) so the inner loop has no branch; at each angle a
+// pixel's nonzero bins are the NB bins after floor(kf - hb), read from a
+// zero-padded sinogram (float32, or float64 for the solvers' residual).
 #include "sp_internal.h"
 #include "sp_reduce.h"
 

@@ -112,8 +112,9 @@ __device__ __forceinline__ double bin_pos(double k, const GeomDev& G) { return f
 // ---- kernel launchers (all enqueue on `st`) ----------------------------------
 // projector.hip
 // The padded copies of the image (xp, xTp) are float64 widenings of the
-// float32 image: the forward gathers then feed the float64 FMAs without a
-// conversion per candidate.  The padded sinogram (yp) stays float32.
+// float32 image or of the solvers' float64 vectors: the forward gathers then
+// feed the float64 FMAs without a conversion per candidate.  The padded
+// sinogram of R p (yp) is float32, that of the residual float64.
 void launch_prep(hipStream_t st, const GeomDev& G, const float* x, double* xp, double* xTp,
                  const int* halt);
 void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, double* xTp,
