@@ -190,7 +190,7 @@ __device__ __forceinline__ void rows_fwd_body(const FFTPlan& F, const float* __r
     }
 }
 
-__global__ __launch_bounds__(256) void k_rows_fwd(FFTPlan F, const float* __restrict__ g, const int* __restrict__ run,
+__global__ __launch_bounds__(512) void k_rows_fwd(FFTPlan F, const float* __restrict__ g, const int* __restrict__ run,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
     if (run && !*run) return;
@@ -234,7 +234,7 @@ __device__ __forceinline__ void cols_body(const FFTPlan& F, double mu, double rh
     }
 }
 
-__global__ __launch_bounds__(256) void k_cols(FFTPlan F, double mu, double rho, const int* __restrict__ run,
+__global__ __launch_bounds__(512) void k_cols(FFTPlan F, double mu, double rho, const int* __restrict__ run,
                                               const int* __restrict__ halt) {
     if (halt && *halt) return;
     if (run && !*run) return;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__
 }
 
 // Batched: z = M g per slice, partials of z^T h into pzh.
-__global__ __launch_bounds__(256) void kb_rows_fwd(const SliceDev* __restrict__ sl, ItemTable t) {
+__global__ __launch_bounds__(512) void kb_rows_fwd(const SliceDev* __restrict__ sl, ItemTable t) {
     extern __shared__ double2 buf[];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void kb_rows_fwd(const SliceDev* __restrict__ 
     });
 }
 
-__global__ __launch_bounds__(256) void kb_cols(const SliceDev* __restrict__ sl, ItemTable t, double mu,
+__global__ __launch_bounds__(512) void kb_cols(const SliceDev* __restrict__ sl, ItemTable t, double mu,
                                                double rho) {
     extern __shared__ double2 buf[];
     for_items(t, [&](int s, int lin) {
@@ -337,8 +337,8 @@ __global__ __launch_bounds__(256) void kb_rows_inv(const SliceDev* __restrict__ 
 
 void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTable cols,
                       size_t lds_rows, size_t lds_cols, double mu, double rho) {
-    hipLaunchKernelGGL(kb_rows_fwd, dim3(rows.grid), dim3(256), lds_rows, st, sl, rows);
-    hipLaunchKernelGGL(kb_cols, dim3(cols.grid), dim3(256), lds_cols, st, sl, cols, mu, rho);
+    hipLaunchKernelGGL(kb_rows_fwd, dim3(rows.grid), dim3(512), lds_rows, st, sl, rows);
+    hipLaunchKernelGGL(kb_cols, dim3(cols.grid), dim3(512), lds_cols, st, sl, cols, mu, rho);
     hipLaunchKernelGGL(kb_rows_inv, dim3(rows.grid), dim3(256), lds_rows, st, sl, rows);
 }
 
@@ -352,9 +352,9 @@ void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, con
                     float* z, const float* dotv, double* partials, const int* halt, const int* run) {
     const int nrow = (F.rows + 1) / 2;
     const size_t row_lds = fft_lds_bytes(F.P, 1);
-    hipLaunchKernelGGL(k_rows_fwd, dim3(nrow), dim3(256), row_lds, st, F, g, run, halt);
+    hipLaunchKernelGGL(k_rows_fwd, dim3(nrow), dim3(512), row_lds, st, F, g, run, halt);
     const int ncb = (F.SP + F.CB - 1) / F.CB;
-    hipLaunchKernelGGL(k_cols, dim3(ncb), dim3(256), fft_lds_bytes(F.P, F.CB), st, F, mu, rho, run,
+    hipLaunchKernelGGL(k_cols, dim3(ncb), dim3(512), fft_lds_bytes(F.P, F.CB), st, F, mu, rho, run,
                        halt);
     hipLaunchKernelGGL(k_rows_inv, dim3(nrow), dim3(256), row_lds, st, F, z, run, dotv, partials, halt);
 }
