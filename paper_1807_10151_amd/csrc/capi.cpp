@@ -448,9 +448,9 @@ void enqueue_stv(sp_ctx* c, int K, const double* x, double* xh, bool snorm, Trac
         const double* src = i == 0 ? x : xh;
         launch_tv_grad(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), halt);
         launch_tv_trials(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), nb,
-                         sc, 8, dptr<double>(c->part_t), halt);
+                         sc, 4, dptr<double>(c->part_t), halt);
         launch_tv_decide(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), nb,
-                         dptr<double>(c->part_t), nb, 8, sc, tr, trials_out, halt);
+                         dptr<double>(c->part_t), nb, 4, sc, tr, trials_out, halt);
         const bool last = i == K - 1;
         launch_tv_apply(c->stream, n, src, xh, dptr<float>(c->vtb), sc, (last && snorm) ? x : nullptr,
                         dptr<double>(c->part_s), halt);

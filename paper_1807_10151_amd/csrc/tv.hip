@@ -18,7 +18,7 @@
 
 namespace sp {
 
-constexpr int TVJ = 8;
+constexpr int TVJ = 4;   // trials evaluated per pass (the first is accepted in most loop bodies)
 
 // t_bar at pixel p = (i, j) of a rows x cols float64 image, evaluated in
 // float64 and rounded to float32 (reading: the partial derivative is
