@@ -33,11 +33,11 @@
  *  - Accumulation: data are float32; every dot product, norm, TV value and CG
  *    scalar (alpha, beta, p^T h, f) is accumulated and kept in float64, with
  *    fixed-order (deterministic) reductions.  Inside the solvers the iterate
- *    x_k, x_{k+1/2} and the search direction p are float64 vectors (their
- *    float32 rounding, repeated every iteration, is what moves a float32
- *    iterate away from the float64 one); the gradient g, M g, h = A p, the
- *    TV direction and every sinogram-sized vector are float32.  Images passed
- *    in and out are float32.
+ *    x_k, x_{k+1/2}, the search direction p and the residual r = R x - b are
+ *    float64 (their float32 rounding, repeated every iteration and amplified
+ *    by the cancellation in R^T r, is what moves a float32 iterate away from
+ *    the float64 one); the gradient g, M g, h = A p, the TV direction and
+ *    R p are float32.  Images passed in and out are float32.
  */
 #ifndef SUPPCG_H
 #define SUPPCG_H
