@@ -570,8 +570,8 @@ int stage_blocks(const SliceDev& S, int stage) {
     const GeomDev& G = S.G;
     switch (stage) {
     case BS_PREP: return ((G.cols + 31) / 32) * ((G.rows + 31) / 32);
-    case BS_PROJECT: return project_blocks(G) * G.parts;
-    case BS_PROJ_COMB: return G.parts > 1 ? project_blocks(G) : 0;
+    case BS_PROJECT: return project_ray_blocks(G) * G.parts;
+    case BS_PROJ_COMB: return G.parts > 1 ? project_comb_blocks(G) : 0;
     case BS_BACKPROJECT: return backproject_blocks(G);
     case BS_ROWS: return (G.rows + 1) / 2;
     case BS_COLS: return S.F.P ? (S.F.SP + S.F.CB - 1) / S.F.CB : 0;

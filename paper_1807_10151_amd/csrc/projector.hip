@@ -229,16 +229,16 @@ __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A
                      : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, valid, part, nparts);
 }
 
-// Stores ray (row a, bin k) of the workgroup's 256-bin chunk: (R x)_{a,k}, or
-// the residual r = R x - b when b != nullptr, with the float64 sum of r^2 per
-// workgroup in partials[by * gx + bx].  The value goes, rounded to float32, to
+// Stores ray (row a, bin k): (R x)_{a,k}, or the residual r = R x - b when
+// b != nullptr, with the float64 sum of r^2 over the workgroup in
+// partials[pidx].  The value goes, rounded to float32, to
 // out[a*out_pitch + k] and to the padded sinogram outp[a*pitchB + PAD + k],
 // and unrounded to the float64 padded sinogram outpd (each nullable).
 __device__ __forceinline__ void project_store(const GeomDev& G, int a, int k, bool valid, double acc,
                                               const float* __restrict__ b, float* __restrict__ out,
                                               int out_pitch, float* __restrict__ outp,
                                               double* __restrict__ outpd,
-                                              double* __restrict__ partials, int bx, int by, int gx) {
+                                              double* __restrict__ partials, int pidx) {
     __shared__ double red[4];
     double r2 = 0.0;
     if (valid) {
@@ -256,17 +256,28 @@ __device__ __forceinline__ void project_store(const GeomDev& G, int a, int k, bo
     }
     if (b) {
         const double tot = block_sum(r2, red);
-        if (threadIdx.x == 0) partials[by * gx + bx] = tot;
+        if (threadIdx.x == 0) partials[pidx] = tot;
     }
 }
 
-// Rays of block (bx, by): bx indexes the class-sorted angle table, by the
-// 256-bin chunk.  With seg == nullptr each ray is summed whole and stored by
-// project_store.  Otherwise (G.parts > 1) only part `part` of each ray is
-// summed and its float64 value goes to seg[(part*nA + bx)*nB + k]; the
-// combine step adds the parts in order.  Splitting the rays keeps the image
-// rows that the resident waves read close together and makes the work items
-// shorter and more even.
+// Ray workgroups.  Wave w of workgroup (ag, q) takes angle 4 ag + w of the
+// class-sorted table and the 64 bins of chunk q, so the four waves of a
+// workgroup hold rays of nearly the same length.  Virtual block
+// blk = qi * nag + ag walks the chunks from the centre of the bin range
+// outwards (q = c, c + 1, c - 1, c + 2, ... with c = (nq - 1) / 2): the long
+// central rays are dispatched first and the short edge chunks fill the end
+// of the launch.
+__device__ __forceinline__ int centre_first(int qi, int nq) {
+    const int c = (nq - 1) >> 1;
+    return (qi & 1) ? c + 1 + (qi >> 1) : c - (qi >> 1);
+}
+
+// Rays of virtual block blk (see above).  With seg == nullptr each ray is
+// summed whole and stored by project_store (partials index blk).  Otherwise
+// (G.parts > 1) only part `part` of each ray is summed and its float64 value
+// goes to seg[(part*nA + ai)*nB + k]; the combine step adds the parts in
+// order.  Splitting the rays keeps the image rows that the resident waves
+// read close together and makes the work items shorter and more even.
 __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* __restrict__ ang,
                                              const double* __restrict__ xp,
                                              const double* __restrict__ xTp,
@@ -274,11 +285,13 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                                              int out_pitch, float* __restrict__ outp,
                                              double* __restrict__ outpd,
                                              double* __restrict__ partials,
-                                             double* __restrict__ seg, int bx, int by, int part,
-                                             int gx) {
-    const AngleDev A = ang[bx];
-    const int k = by * 256 + threadIdx.x;
-    const bool valid = k < G.nB;
+                                             double* __restrict__ seg, int blk, int part) {
+    const int nag = (G.nA + 3) >> 2, nq = (G.nB + 63) >> 6;
+    const int ag = blk % nag, q = centre_first(blk / nag, nq);
+    const int ai = 4 * ag + (threadIdx.x >> 6);
+    const int k = q * 64 + (threadIdx.x & 63);
+    const bool valid = ai < G.nA && k < G.nB;
+    const AngleDev A = ang[ai < G.nA ? ai : G.nA - 1];
     const double sk = bin_pos((double)k, G);
     const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
     const int np = seg ? G.parts : 1;
@@ -291,13 +304,15 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                    : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid, part, np);
     }
     if (seg) {
-        if (valid) seg[((size_t)part * G.nA + bx) * G.nB + k] = acc;
+        if (valid) seg[((size_t)part * G.nA + ai) * G.nB + k] = acc;
         return;
     }
-    project_store(G, A.row, k, valid, acc, b, out, out_pitch, outp, outpd, partials, bx, by, gx);
+    project_store(G, A.row, k, valid, acc, b, out, out_pitch, outp, outpd, partials, blk);
 }
 
-// Sum of the parts of the rays of block (bx, by), then the store.
+// Sum of the parts of the rays of combine block (bx, by): angle bx of the
+// class-sorted table, 256-bin chunk by; then the store (partials index
+// by * gx + bx).
 __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleDev* __restrict__ ang,
                                                   const double* __restrict__ seg,
                                                   const float* __restrict__ b,
@@ -315,7 +330,7 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
         const size_t stride = (size_t)G.nA * G.nB;
         for (int j = 0; j < G.parts; ++j) acc += v[j * stride];
     }
-    project_store(G, a, k, valid, acc, b, out, out_pitch, outp, outpd, partials, bx, by, gx);
+    project_store(G, a, k, valid, acc, b, out, out_pitch, outp, outpd, partials, by * gx + bx);
 }
 
 __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
@@ -328,11 +343,10 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr, blockIdx.x,
-                 blockIdx.y, 0, gridDim.x);
+    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr, blockIdx.x, 0);
 }
 
-// grid (nA, chunks, parts): blockIdx.z is the part, so the parts run in order.
+// grid (ray blocks, parts): blockIdx.y is the part, so the parts run in order.
 __global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev* __restrict__ ang,
                                                       const double* __restrict__ xp,
                                                       const double* __restrict__ xTp,
@@ -340,7 +354,7 @@ __global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev*
                                                       const int* __restrict__ halt) {
     if (halt && *halt) return;
     project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg, blockIdx.x,
-                 blockIdx.y, blockIdx.z, gridDim.x);
+                 blockIdx.y);
 }
 
 __global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev* __restrict__ ang,
@@ -357,25 +371,23 @@ __global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev*
 }
 
 // residual: rpd = R xh - b (float64) with f partials; else rp = R p.  Virtual block
-// lin = (part * chunks + by) * nA + bx.
+// lin = part * project_ray_blocks(G) + blk.
 __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
                                                   int residual) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
-        const int gx = G.nA;
-        const int bx = lin % gx, r = lin / gx;
         if (G.parts > 1) {
-            const int chunks = (G.nB + 255) / 256;
+            const int nblk = project_ray_blocks(G);
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, nullptr,
-                         nullptr, nullptr, gmem(S.seg), bx, r % chunks, r / chunks, gx);
+                         nullptr, nullptr, gmem(S.seg), lin % nblk, lin / nblk);
         } else if (residual) {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), gmem(S.b), nullptr, 0, nullptr,
-                         gmem(S.rpd), gmem(S.pf), nullptr, bx, r, 0, gx);
+                         gmem(S.rpd), gmem(S.pf), nullptr, lin, 0);
         } else {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, gmem(S.rp),
-                         nullptr, nullptr, nullptr, bx, r, 0, gx);
+                         nullptr, nullptr, nullptr, lin, 0);
         }
     });
 }
@@ -405,7 +417,11 @@ void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable
                            residual ? 1 : 0);
 }
 
-int project_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
+int project_comb_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
+
+int project_blocks(const GeomDev& G) {
+    return G.parts > 1 ? project_comb_blocks(G) : project_ray_blocks(G);
+}
 
 int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_waves) {
     // Large images: 8 parts keep the resident waves on a band of the float64
@@ -421,15 +437,15 @@ int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_wav
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* outpd, double* partials, double* seg, const int* halt) {
-    dim3 grid(G.nA, (G.nB + 255) / 256);
+    const int nblk = project_ray_blocks(G);
     if (G.parts > 1) {
-        hipLaunchKernelGGL(k_project_part, dim3(G.nA, (G.nB + 255) / 256, G.parts), dim3(256), 0,
-                           st, G, ang, xp, xTp, seg, halt);
-        hipLaunchKernelGGL(k_project_comb, grid, dim3(256), 0, st, G, ang, (const double*)seg, b,
-                           out, out_pitch, outp, outpd, partials, halt);
+        hipLaunchKernelGGL(k_project_part, dim3(nblk, G.parts), dim3(256), 0, st, G, ang, xp, xTp,
+                           seg, halt);
+        hipLaunchKernelGGL(k_project_comb, dim3(G.nA, (G.nB + 255) / 256), dim3(256), 0, st, G,
+                           ang, (const double*)seg, b, out, out_pitch, outp, outpd, partials, halt);
         return;
     }
-    hipLaunchKernelGGL(k_project, grid, dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
+    hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
                        outp, outpd, partials, halt);
 }
 

@@ -126,6 +126,14 @@ void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, 
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* outpd, double* partials, double* seg, const int* halt);
+// Workgroups of one part of R: four angles by one 64-bin chunk each.
+__host__ __device__ inline int project_ray_blocks(const GeomDev& G) {
+    return ((G.nA + 3) / 4) * ((G.nB + 63) / 64);
+}
+// Combine workgroups (G.parts > 1): one angle by one 256-bin chunk each.
+int project_comb_blocks(const GeomDev& G);
+// Number of float64 f partials R's residual form writes: one per combine
+// workgroup when the rays are split in parts, else one per ray workgroup.
 int project_blocks(const GeomDev& G);
 // Parts R splits each ray's step range into, chosen from the geometry and
 // the device's wave slots (both the single-slice and the batched solver use
