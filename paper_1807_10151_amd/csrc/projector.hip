@@ -31,6 +31,10 @@
 #include "sp_internal.h"
 #include "sp_reduce.h"
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 namespace sp {
 
 // 32 x 32 tile (bx, by): padded copy and padded transposed copy of a float32
@@ -260,19 +264,13 @@ __device__ __forceinline__ void project_store(const GeomDev& G, int a, int k, bo
     }
 }
 
-// Ray workgroups.  Wave w of workgroup (ag, q) takes angle 4 ag + w of the
-// class-sorted table and the 64 bins of chunk q, so the four waves of a
-// workgroup hold rays of nearly the same length.  Virtual block
-// blk = qi * nag + ag walks the chunks from the centre of the bin range
-// outwards (q = c, c + 1, c - 1, c + 2, ... with c = (nq - 1) / 2): the long
-// central rays are dispatched first and the short edge chunks fill the end
-// of the launch.
-__device__ __forceinline__ int centre_first(int qi, int nq) {
-    const int c = (nq - 1) >> 1;
-    return (qi & 1) ? c + 1 + (qi >> 1) : c - (qi >> 1);
-}
+// Ray workgroups.  Wave w of virtual block blk = q * nag + ag takes angle
+// 4 ag + w of the class-sorted table and the 64 bins of chunk q, so the four
+// waves of a workgroup hold rays of nearly the same length.  Workgroup i of a
+// launch runs virtual block ord[i] (project_order: longest first, snaked over
+// the compute units).
 
-// Rays of virtual block blk (see above).  With seg == nullptr each ray is
+// Rays of virtual block blk.  With seg == nullptr each ray is
 // summed whole and stored by project_store (partials index blk).  Otherwise
 // (G.parts > 1) only part `part` of each ray is summed and its float64 value
 // goes to seg[(part*nA + ai)*nB + k]; the combine step adds the parts in
@@ -287,7 +285,7 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                                              double* __restrict__ partials,
                                              double* __restrict__ seg, int blk, int part) {
     const int nag = (G.nA + 3) >> 2, nq = (G.nB + 63) >> 6;
-    const int ag = blk % nag, q = centre_first(blk / nag, nq);
+    const int ag = blk % nag, q = blk / nag;
     const int ai = 4 * ag + (threadIdx.x >> 6);
     const int k = q * 64 + (threadIdx.x & 63);
     const bool valid = ai < G.nA && k < G.nB;
@@ -341,9 +339,11 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
                                                  float* __restrict__ outp,
                                                  double* __restrict__ outpd,
                                                  double* __restrict__ partials,
+                                                 const int* __restrict__ ord,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr, blockIdx.x, 0);
+    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr,
+                 ord[blockIdx.x], 0);
 }
 
 // grid (ray blocks, parts): blockIdx.y is the part, so the parts run in order.
@@ -351,10 +351,11 @@ __global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev*
                                                       const double* __restrict__ xp,
                                                       const double* __restrict__ xTp,
                                                       double* __restrict__ seg,
+                                                      const int* __restrict__ ord,
                                                       const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg, blockIdx.x,
-                 blockIdx.y);
+    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg,
+                 ord[blockIdx.x], blockIdx.y);
 }
 
 __global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev* __restrict__ ang,
@@ -370,8 +371,8 @@ __global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev*
                       blockIdx.y, gridDim.x);
 }
 
-// residual: rpd = R xh - b (float64) with f partials; else rp = R p.  Virtual block
-// lin = part * project_ray_blocks(G) + blk.
+// residual: rpd = R xh - b (float64) with f partials; else rp = R p.  Item
+// lin = part * project_ray_blocks(G) + i runs virtual block S.pord[i].
 __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
                                                   int residual) {
     for_items(t, [&](int s, int lin) {
@@ -381,13 +382,13 @@ __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ s
         if (G.parts > 1) {
             const int nblk = project_ray_blocks(G);
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, nullptr,
-                         nullptr, nullptr, gmem(S.seg), lin % nblk, lin / nblk);
+                         nullptr, nullptr, gmem(S.seg), cmem(S.pord)[lin % nblk], lin / nblk);
         } else if (residual) {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), gmem(S.b), nullptr, 0, nullptr,
-                         gmem(S.rpd), gmem(S.pf), nullptr, lin, 0);
+                         gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.pord)[lin], 0);
         } else {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, gmem(S.rp),
-                         nullptr, nullptr, nullptr, lin, 0);
+                         nullptr, nullptr, nullptr, cmem(S.pord)[lin], 0);
         }
     });
 }
@@ -434,19 +435,68 @@ int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_wav
     return p > 4 ? 4 : (int)p;
 }
 
+// Step count of one wave of R: the union of its lanes' step ranges, found as
+// the kernel finds it (a lane's range is monotone in the bin index, so the
+// two end lanes of the chunk bound it).
+static long wave_steps(const GeomDev& G, const AngleDev& A, int k0, int k1) {
+    const bool horiz = A.flags & ANG_HORIZ;
+    const int nmaj = horiz ? G.cols : G.rows, nmin = horiz ? G.rows : G.cols;
+    int lo = nmaj, hi = 0;
+    for (int k : {k0, k1}) {
+        const double sk = std::fma((double)k, G.ds, G.s0);
+        const double start = (horiz ? G.yoff - (sk + G.xoff * A.c) / A.s
+                                    : (sk - G.yoff * A.s) / A.c + G.xoff) - (double)A.hw;
+        const double vlo = -(double)(A.nc + 1), vhi = (double)(nmin + 1);
+        int l, h;
+        if (A.slope == 0.0) {
+            l = 0;
+            h = nmaj;   // an axis-parallel chunk may straddle the image: count it whole
+        } else {
+            const double t0 = (vlo - start) / A.slope, t1 = (vhi - start) / A.slope;
+            const double tmin = std::min(std::max(std::min(t0, t1) - 1.0, 0.0), (double)nmaj);
+            const double tmax = std::min(std::max(std::max(t0, t1) + 2.0, 0.0), (double)nmaj);
+            l = (int)std::floor(tmin);
+            h = std::max(l, (int)std::ceil(tmax));
+        }
+        lo = std::min(lo, l);
+        hi = std::max(hi, h);
+    }
+    return hi > lo ? (long)(hi - lo) * A.nc : 0;
+}
+
+std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>& tab,
+                                   int n_cu) {
+    const int nag = (G.nA + 3) / 4, nq = (G.nB + 63) / 64, nblk = nag * nq;
+    std::vector<long> cost((size_t)nblk, 0);
+    for (int q = 0; q < nq; ++q) {
+        const int k0 = q * 64, k1 = std::min(G.nB, k0 + 64) - 1;
+        for (int ai = 0; ai < G.nA; ++ai)
+            cost[(size_t)q * nag + ai / 4] += 16 + wave_steps(G, tab[(size_t)ai], k0, k1);
+    }
+    std::vector<int32_t> ord((size_t)nblk);
+    for (int b = 0; b < nblk; ++b) ord[(size_t)b] = b;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
+    const int band = std::max(1, n_cu);
+    for (int b0 = band, i = 1; b0 < nblk; b0 += band, ++i)
+        if (i & 1) std::reverse(ord.begin() + b0, ord.begin() + std::min(nblk, b0 + band));
+    return ord;
+}
+
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* outpd, double* partials, double* seg, const int* halt) {
+                    double* outpd, double* partials, double* seg, const int* ord,
+                    const int* halt) {
     const int nblk = project_ray_blocks(G);
     if (G.parts > 1) {
         hipLaunchKernelGGL(k_project_part, dim3(nblk, G.parts), dim3(256), 0, st, G, ang, xp, xTp,
-                           seg, halt);
+                           seg, ord, halt);
         hipLaunchKernelGGL(k_project_comb, dim3(G.nA, (G.nB + 255) / 256), dim3(256), 0, st, G,
                            ang, (const double*)seg, b, out, out_pitch, outp, outpd, partials, halt);
         return;
     }
     hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
-                       outp, outpd, partials, halt);
+                       outp, outpd, partials, ord, halt);
 }
 
 __global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const float* __restrict__ y,

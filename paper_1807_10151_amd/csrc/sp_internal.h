@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace sp {
 
@@ -122,10 +123,12 @@ void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, 
 // With G.parts > 1, seg (parts * nA * nB float64) receives the per-part sums
 // before they are combined.  outp / outpd: float32 / float64 padded sinograms
 // (nullable); the residual's float64 values feed R^T without a float32
-// rounding (its cancellation in R^T r amplifies that rounding).
+// rounding (its cancellation in R^T r amplifies that rounding).  ord: the
+// device copy of project_order(G, ...), the virtual block each workgroup runs.
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* outpd, double* partials, double* seg, const int* halt);
+                    double* outpd, double* partials, double* seg, const int* ord,
+                    const int* halt);
 // Workgroups of one part of R: four angles by one 64-bin chunk each.
 __host__ __device__ inline int project_ray_blocks(const GeomDev& G) {
     return ((G.nA + 3) / 4) * ((G.nB + 63) / 64);
@@ -139,6 +142,12 @@ int project_blocks(const GeomDev& G);
 // the device's wave slots (both the single-slice and the batched solver use
 // it, so their sums agree).
 int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_waves);
+// Dispatch order of R's ray workgroups (project_ray_blocks(G) entries, a
+// permutation): virtual blocks by decreasing step count, with every other
+// band of n_cu entries reversed so the first workgroups of each compute unit
+// sum to about the same work.  Only the order of the work changes; every sum
+// and its partials index stay the same.
+std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>& tab, int n_cu);
 void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp);
 // skp: float64 bin positions of the padded bin range, skp[PAD + k] = s_k
 // (bin_sk_table fills it on the host with the same fma as bin_pos); used when
@@ -242,6 +251,7 @@ struct SliceDev {
     float* rp;          // padded sinogram (R p)
     double* rpd;        // float64 padded sinogram (residual)
     double* seg;        // R's per-part ray sums, [parts][nA][nB] (G.parts > 1)
+    const int* pord;    // R's workgroup order (project_order)
     double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
     Scalars* sc;
     TraceDev tr;
