@@ -439,9 +439,11 @@ struct ProfScope {
     }
 };
 
-// One S_TV call (Algorithm 1) from x into xh, K inner steps.
+// One S_TV call (Algorithm 1) from x into xh, K inner steps.  With snorm the
+// partials of ||xh - x||^2 go to part_s, and unless ride_snorm (a later
+// kernel carries the step, see ScalarRide) the step norm is traced here.
 void enqueue_stv(sp_ctx* c, int K, const double* x, double* xh, bool snorm, TraceDev tr,
-                 int32_t* trials_out) {
+                 int32_t* trials_out, bool ride_snorm = false) {
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
     Scalars* sc = dptr<Scalars>(c->scal);
@@ -459,7 +461,8 @@ void enqueue_stv(sp_ctx* c, int K, const double* x, double* xh, bool snorm, Trac
         launch_tv_apply(c->stream, n, src, xh, dptr<float>(c->vtb), sc, (last && snorm) ? x : nullptr,
                         dptr<double>(c->part_s), halt);
     }
-    if (snorm) launch_scalar(c->stream, OP_SNORM, sc, tr, dptr<double>(c->part_s), nb, nullptr, 0);
+    if (snorm && !ride_snorm)
+        launch_scalar(c->stream, OP_SNORM, sc, tr, dptr<double>(c->part_s), nb, nullptr, 0);
 }
 
 // z = M g with the partial dots z^T dotv (dotv nullable).
@@ -1366,34 +1369,40 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, bb ? nullptr : rp, bb ? rpd : nullptr,
                        parts, seg, pord, halt);
     };
-    auto backproject = [&](float* out, const double* dotv, double* parts) {
+    auto backproject = [&](float* out, const double* dotv, double* parts,
+                           const ScalarRide& ride) {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
-        if (dotv) launch_backproject(st, G, ang, rp, skp, out, dotv, parts, halt);
-        else launch_backproject(st, G, ang, rpd, skp, out, dotv, parts, halt);
+        if (dotv) launch_backproject(st, G, ang, rp, skp, out, dotv, parts, halt, ride);
+        else launch_backproject(st, G, ang, rpd, skp, out, dotv, parts, halt, ride);
     };
+    // g = R^T r also carries f(x_{k+1/2}) (and the S_TV step norm when K > 0)
+    ScalarRide ride_f;
+    ride_f.sc = sc;
+    ride_f.tr = tr;
+    ride_f.pf = pf;
+    ride_f.nf = nf;
+    ride_f.ps = K > 0 ? dptr<double>(c->part_s) : nullptr;
+    ride_f.ns = tv_blocks(G.rows, G.cols);
     auto body = [&]() -> int {
         ProfScope ps(c, SP_PROF_ITERATION);
         if (K > 0) {
-            enqueue_stv(c, K, x, xh, true, tr, nullptr);            // S_TV -> x_{k+1/2}
+            enqueue_stv(c, K, x, xh, true, tr, nullptr, true);      // S_TV -> x_{k+1/2}
         } else {
             launch_copy(st, n, x, xh, halt);
         }
         // U_PCG(x_{k+1/2}, p_{k-1}, h_{k-1})
         launch_prep(st, G, xh, xp, xTp, halt);
         project(b, pf);                                                           // r = R x - b
-        launch_scalar(st, OP_F, sc, tr, pf, nf, nullptr, 0);                      // f(x_{k+1/2})
-        backproject(gv, nullptr, nullptr);                                        // g = R^T r
+        backproject(gv, nullptr, nullptr, ride_f);                    // g = R^T r, f(x_{k+1/2})
         if (snap) launch_snap(st, n, gv, snap, snap_count, sc);
         int nz = 0;
         int r2 = enqueue_precond(c, pc, gv, z, h, pzh, nz, true);                    // z = M g
         if (r2) return r2;
-        launch_scalar(st, OP_BETA, sc, tr, pzh, nz, nullptr, 0);                  // beta
-        launch_update_p(st, n, z, p, gv, sc, pgp, halt);                          // p = -z + beta p
+        launch_update_p_beta(st, n, z, p, gv, sc, tr, pzh, nz, pgp);       // beta; p = -z + beta p
         launch_prep(st, G, p, xp, xTp, halt);
         project(nullptr, nullptr);
-        backproject(h, p, pph);                                                   // h = A p
-        launch_scalar(st, OP_ALPHA, sc, tr, pph, nph, pgp, ngp);                  // alpha
-        launch_update_x(st, n, xh, p, x, sc, halt);                               // x = x + alpha p
+        backproject(h, p, pph, ScalarRide{});                                     // h = A p
+        launch_update_x_alpha(st, n, xh, p, x, sc, tr, pph, nph, pgp, ngp, OP_ALPHA);  // alpha; x += alpha p
         return check_launch(c);
     };
 

@@ -9,6 +9,7 @@
 // loop body needs no host synchronisation and can be captured in a graph.
 #include "sp_internal.h"
 #include "sp_reduce.h"
+#include "sp_scalar.h"
 #include "../../include/suppcg.h"
 
 namespace sp {
@@ -41,14 +42,13 @@ void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* p
     hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(256), 0, st, n, a, b, partials, halt);
 }
 
-// p <- -z + beta p (beta from the scalars), partials of g^T p (new p).
-// Virtual block bx of a grid of gx blocks (grid-stride over n).
+// p <- -z + beta p, partials of g^T p (new p).  Virtual block bx of a grid of
+// gx blocks (grid-stride over n).
 __device__ __forceinline__ void update_p_body(int n, const float* __restrict__ z,
                                               double* __restrict__ p, const float* __restrict__ g,
-                                              const Scalars* __restrict__ sc,
-                                              double* __restrict__ partials, int bx, int gx) {
+                                              double beta, double* __restrict__ partials, int bx,
+                                              int gx) {
     __shared__ double red[4];
-    const double beta = sc->beta;
     double acc = 0.0;
     for (int q = bx * 256 + threadIdx.x; q < n; q += gx * 256) {
         const double v = fma(beta, p[q], -(double)z[q]);
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_update_p(int n, const float* __restrict
                                                   double* __restrict__ partials,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
-    update_p_body(n, z, p, g, sc, partials, blockIdx.x, gridDim.x);
+    update_p_body(n, z, p, g, sc->beta, partials, blockIdx.x, gridDim.x);
 }
 
 void launch_update_p(hipStream_t st, int n, const float* z, double* p, const float* g,
@@ -75,11 +75,35 @@ void launch_update_p(hipStream_t st, int n, const float* z, double* p, const flo
                        halt);
 }
 
+// The beta step folded into the update: every workgroup sums the z^T h
+// partials in the same fixed order, so all use the beta that workgroup 0
+// commits to the scalars (and trace).  A non-finite beta halts without an
+// update, as the separate scalar step would.
+__global__ __launch_bounds__(256) void k_update_p_beta(int n, const float* __restrict__ z,
+                                                       double* __restrict__ p,
+                                                       const float* __restrict__ g,
+                                                       Scalars* __restrict__ sc, TraceDev tr,
+                                                       const double* __restrict__ pzh, int nz,
+                                                       double* __restrict__ partials) {
+    if (sc->halt) return;
+    __shared__ double red[4];
+    const double A = pzh ? reduce_partials(pzh, nz, red) : 0.0;
+    const double beta = beta_from(sc, A);
+    if (blockIdx.x == 0 && threadIdx.x == 0) scalar_commit(OP_BETA, sc, tr, A, 0.0);
+    if (!finite(beta)) return;
+    update_p_body(n, z, p, g, beta, partials, blockIdx.x, gridDim.x);
+}
+
+void launch_update_p_beta(hipStream_t st, int n, const float* z, double* p, const float* g,
+                          Scalars* sc, TraceDev tr, const double* pzh, int nz, double* partials) {
+    hipLaunchKernelGGL(k_update_p_beta, dim3(vec_blocks(n)), dim3(256), 0, st, n, z, p, g, sc, tr,
+                       pzh, nz, partials);
+}
+
 // x <- xh + alpha p
 __device__ __forceinline__ void update_x_body(int n, const double* __restrict__ xh,
                                               const double* __restrict__ p, double* __restrict__ x,
-                                              const Scalars* __restrict__ sc, int bx, int gx) {
-    const double alpha = sc->alpha;
+                                              double alpha, int bx, int gx) {
     for (int q = bx * 256 + threadIdx.x; q < n; q += gx * 256)
         x[q] = fma(alpha, p[q], xh[q]);
 }
@@ -90,12 +114,41 @@ __global__ __launch_bounds__(256) void k_update_x(int n, const double* __restric
                                                   const Scalars* __restrict__ sc,
                                                   const int* __restrict__ halt) {
     if (halt && *halt) return;
-    update_x_body(n, xh, p, x, sc, blockIdx.x, gridDim.x);
+    update_x_body(n, xh, p, x, sc->alpha, blockIdx.x, gridDim.x);
 }
 
 void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, double* x,
                      const Scalars* sc, const int* halt) {
     hipLaunchKernelGGL(k_update_x, dim3(vec_blocks(n)), dim3(256), 0, st, n, xh, p, x, sc, halt);
+}
+
+// The alpha step (op OP_ALPHA or OP_ALPHA0) folded into the update: every
+// workgroup sums the p^T h and g^T p partials in the same order and takes the
+// same halt decision (breakdown, non-finite, eps test) that workgroup 0
+// commits; on a halt no workgroup updates x.
+__global__ __launch_bounds__(256) void k_update_x_alpha(int n, const double* __restrict__ xh,
+                                                        const double* __restrict__ p,
+                                                        double* __restrict__ x,
+                                                        Scalars* __restrict__ sc, TraceDev tr,
+                                                        const double* __restrict__ pph, int nph,
+                                                        const double* __restrict__ pgp, int ngp,
+                                                        int op) {
+    if (sc->halt) return;
+    __shared__ double red[4];
+    const double pth = reduce_partials(pph, nph, red);
+    const double gp = reduce_partials(pgp, ngp, red);
+    double alpha;
+    const int code = alpha_from(pth, gp, sc->eps, sc->f, alpha);
+    if (blockIdx.x == 0 && threadIdx.x == 0) scalar_commit(op, sc, tr, pth, gp);
+    if (code) return;
+    update_x_body(n, xh, p, x, alpha, blockIdx.x, gridDim.x);
+}
+
+void launch_update_x_alpha(hipStream_t st, int n, const double* xh, const double* p, double* x,
+                           Scalars* sc, TraceDev tr, const double* pph, int nph, const double* pgp,
+                           int ngp, int op) {
+    hipLaunchKernelGGL(k_update_x_alpha, dim3(vec_blocks(n)), dim3(256), 0, st, n, xh, p, x, sc,
+                       tr, pph, nph, pgp, ngp, op);
 }
 
 template <class T>
@@ -159,76 +212,6 @@ void launch_reduce(hipStream_t st, const double* partials, int np, double* out) 
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partials, np, out);
 }
 
-__device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
-
-__device__ __forceinline__ void scalar_body(int op, Scalars* __restrict__ sc, const TraceDev& tr,
-                                            const double* __restrict__ pa, int na,
-                                            const double* __restrict__ pb, int nb) {
-    __shared__ double red[4];
-    const double A = pa ? reduce_partials(pa, na, red) : 0.0;
-    const double B = pb ? reduce_partials(pb, nb, red) : 0.0;
-    if (threadIdx.x != 0) return;
-    const int it = sc->iter;
-    const bool rec = it < tr.cap;
-    switch (op) {
-    case OP_F0:
-        sc->f = A;
-        sc->f0 = A;
-        if (!finite(A)) sc->halt = SP_ERR_NONFINITE;
-        break;
-    case OP_F:
-        sc->f = A;
-        if (rec && tr.f_half) tr.f_half[it] = A;
-        if (!finite(A)) sc->halt = SP_ERR_NONFINITE;
-        break;
-    case OP_BETA: {
-        const double beta = sc->first ? 0.0 : A / sc->pth;
-        sc->beta = beta;
-        if (!sc->first && rec && tr.beta) tr.beta[it] = beta;
-        if (!finite(beta)) sc->halt = SP_ERR_NONFINITE;
-        break;
-    }
-    case OP_ALPHA0:
-    case OP_ALPHA: {
-        const double pth = A;
-        const double gp = B;
-        double alpha = 0.0;
-        if (pth == 0.0) {
-            sc->halt = SP_BREAKDOWN_CONVERGED;
-        } else {
-            alpha = -gp / pth;
-            if (!finite(alpha) || !finite(pth)) sc->halt = SP_ERR_NONFINITE;
-        }
-        sc->alpha = alpha;
-        sc->pth = pth;
-        if (op == OP_ALPHA0) {
-            sc->alpha0 = alpha;
-            sc->k = 1;
-            sc->first = 0;
-        } else {
-            if (rec && tr.alpha) tr.alpha[it] = alpha;
-            sc->iter = it + 1;
-            sc->k = sc->k + 1;
-        }
-        sc->inner = 0;
-        if (sc->halt == 0 && sc->eps > 0.0 && !(sc->f > sc->eps)) sc->halt = SP_CONVERGED;
-        break;
-    }
-    case OP_SNORM:
-        if (rec && tr.s_norm) tr.s_norm[it] = sqrt(A);
-        break;
-    case OP_LCHECK:
-        if (sc->gate_learned && !(A > 0.0 && finite(A))) {
-            sc->gate_learned = 0;
-            sc->gate_ramp = 1;
-            sc->fallbacks += 1;
-        }
-        break;
-    default:
-        break;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_scalar(int op, Scalars* __restrict__ sc, TraceDev tr,
                                                 const double* __restrict__ pa, int na,
                                                 const double* __restrict__ pb, int nb) {
@@ -270,7 +253,7 @@ __global__ __launch_bounds__(256) void kb_update_p(const SliceDev* __restrict__ 
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
-        update_p_body(S.n, gmem(S.z), gmem(S.p), gmem(S.g), gmem(S.sc), gmem(S.pgp), lin,
+        update_p_body(S.n, gmem(S.z), gmem(S.p), gmem(S.g), gmem(S.sc)->beta, gmem(S.pgp), lin,
                       vec_blocks_dev(S.n));
     });
 }
@@ -279,7 +262,8 @@ __global__ __launch_bounds__(256) void kb_update_x(const SliceDev* __restrict__ 
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
-        update_x_body(S.n, gmem(S.xh), gmem(S.p), gmem(S.x), gmem(S.sc), lin, vec_blocks_dev(S.n));
+        update_x_body(S.n, gmem(S.xh), gmem(S.p), gmem(S.x), gmem(S.sc)->alpha, lin,
+                      vec_blocks_dev(S.n));
     });
 }
 

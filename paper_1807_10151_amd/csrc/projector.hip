@@ -30,6 +30,7 @@
 // zero-padded sinogram (float32, or float64 for the solvers' residual).
 #include "sp_internal.h"
 #include "sp_reduce.h"
+#include "sp_scalar.h"
 
 #include <algorithm>
 #include <cmath>
@@ -649,11 +650,16 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
                                                      float* __restrict__ out,
                                                      const double* __restrict__ dotv,
                                                      double* __restrict__ partials,
+                                                     ScalarRide ride,
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
     extern __shared__ double sks[];
     backproject_body<NB, LSK, TY>(G, ang, yp, skg, sks, out, dotv, partials, blockIdx.x,
                                   blockIdx.y, gridDim.x);
+    if (ride.sc && blockIdx.x == 0 && blockIdx.y == 0) {
+        if (ride.ps) scalar_body(OP_SNORM, ride.sc, ride.tr, ride.ps, ride.ns, nullptr, 0);
+        if (ride.pf) scalar_body(OP_F, ride.sc, ride.tr, ride.pf, ride.nf, nullptr, 0);
+    }
 }
 
 // TY = float: h = R^T rp (rp = R p) with the partials of h^T p; TY = double:
@@ -711,30 +717,30 @@ int backproject_blocks(const GeomDev& G) {
 template <bool LSK, class TY>
 void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp,
                const double* skp, float* out, const double* dotv, double* partials, const int* halt,
-               size_t lds) {
+               size_t lds, const ScalarRide& ride) {
     dim3 grid((G.cols + BP_TW - 1) / BP_TW, (G.rows + BP_TILE - 1) / BP_TILE);
     switch (G.nbmax) {
-    case 1: hipLaunchKernelGGL((k_backproject<1, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
-    case 2: hipLaunchKernelGGL((k_backproject<2, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
-    case 3: hipLaunchKernelGGL((k_backproject<3, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
-    default: hipLaunchKernelGGL((k_backproject<4, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, halt); break;
+    case 1: hipLaunchKernelGGL((k_backproject<1, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    case 2: hipLaunchKernelGGL((k_backproject<2, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    case 3: hipLaunchKernelGGL((k_backproject<3, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    default: hipLaunchKernelGGL((k_backproject<4, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
     }
 }
 
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
                         const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt) {
+                        const int* halt, const ScalarRide& ride) {
     const size_t lds = bp_lds_bytes(G.nB);
-    if (lds) launch_bp<true, float>(st, G, ang, yp, skp, out, dotv, partials, halt, lds);
-    else launch_bp<false, float>(st, G, ang, yp, skp, out, dotv, partials, halt, 0);
+    if (lds) launch_bp<true, float>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
+    else launch_bp<false, float>(st, G, ang, yp, skp, out, dotv, partials, halt, 0, ride);
 }
 
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
                         const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt) {
+                        const int* halt, const ScalarRide& ride) {
     const size_t lds = bp_lds_bytes(G.nB);
-    if (lds) launch_bp<true, double>(st, G, ang, yp, skp, out, dotv, partials, halt, lds);
-    else launch_bp<false, double>(st, G, ang, yp, skp, out, dotv, partials, halt, 0);
+    if (lds) launch_bp<true, double>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
+    else launch_bp<false, double>(st, G, ang, yp, skp, out, dotv, partials, halt, 0, ride);
 }
 
 }  // namespace sp

@@ -95,6 +95,19 @@ struct TraceDev {
     int32_t cap;
 };
 
+// Scalar steps a kernel runs in its workgroup (0, 0) after its own work, in
+// place of separate single-workgroup launches: the S_TV step norm from the
+// partials ps (when ps != nullptr), then f from the partials pf (when
+// pf != nullptr).  Inactive when sc == nullptr.
+struct ScalarRide {
+    Scalars* sc = nullptr;
+    TraceDev tr{};
+    const double* pf = nullptr;
+    int nf = 0;
+    const double* ps = nullptr;
+    int ns = 0;
+};
+
 // Canonical evaluation of the weight of pixel centre (xj, yi) for ray sk,
 // shared by the projector and the backprojector so both use bit-identical
 // weights.  Projection of the pixel centre on the ray normal:
@@ -152,12 +165,13 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp
 // skp: float64 bin positions of the padded bin range, skp[PAD + k] = s_k
 // (bin_sk_table fills it on the host with the same fma as bin_pos); used when
 // the table is too large for the backprojector's LDS copy.
+// ride: scalar steps workgroup (0, 0) runs after its tile (see ScalarRide).
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
                         const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt);
+                        const int* halt, const ScalarRide& ride = ScalarRide{});
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
                         const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt);
+                        const int* halt, const ScalarRide& ride = ScalarRide{});
 int backproject_blocks(const GeomDev& G);
 
 // fft.hip
@@ -197,6 +211,13 @@ void launch_update_p(hipStream_t st, int n, const float* z, double* p, const flo
                      const Scalars* sc, double* partials, const int* halt);
 void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, double* x,
                      const Scalars* sc, const int* halt);
+// Forms with the beta / alpha scalar step folded in (ops OP_BETA, OP_ALPHA or
+// OP_ALPHA0 of launch_scalar): one launch instead of two, same values.
+void launch_update_p_beta(hipStream_t st, int n, const float* z, double* p, const float* g,
+                          Scalars* sc, TraceDev tr, const double* pzh, int nz, double* partials);
+void launch_update_x_alpha(hipStream_t st, int n, const double* xh, const double* p, double* x,
+                           Scalars* sc, TraceDev tr, const double* pph, int nph, const double* pgp,
+                           int ngp, int op);
 void launch_copy(hipStream_t st, int n, const float* src, float* dst, const int* halt);
 void launch_copy(hipStream_t st, int n, const double* src, double* dst, const int* halt);
 // dst = src widened to float64 (src == nullptr: zeros); dst = src rounded to float32
