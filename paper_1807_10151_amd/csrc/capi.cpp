@@ -218,7 +218,7 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
         const bool axis = ac == 0.0 || as == 0.0;
         const bool horiz = as > ac;
         const double e = 0.5 * (ac + as);
-        const double inv = axis ? 0.0 : 1.0 / (ac * as);
+        const double inv = axis ? 0.0 : 1.0 / std::min(ac, as);
         A.inv = inv;
         A.einv = e * inv;
         A.wmax = 1.0 / std::max(ac, as);

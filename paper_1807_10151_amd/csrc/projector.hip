@@ -194,7 +194,7 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
         for (int q = 0; q < NC; ++q) {
             const double cm = HORIZ ? cm0 - (double)q : cm0 + (double)q;
             const double d = sk - fma(cm, fm, P);
-            acc = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), v[q], acc);
+            acc = fma(chord_u<AXIS>(d, A.einv, A.inv), v[q], acc);
         }
     };
     int m = lo;
@@ -302,6 +302,7 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
         acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, valid, part, np)
                    : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid, part, np);
     }
+    acc *= A.wmax;   // the ray sums u-weighted values (see chord_u)
     if (seg) {
         if (valid) seg[((size_t)part * G.nA + ai) * G.nB + k] = acc;
         return;
@@ -560,14 +561,14 @@ __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __res
             for (int q = 0; q < NB; ++q) sk[u][q] = ps[q];
         }
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const double d = sk[0][q] - t[0];
-            acc0 = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[0][q], acc0);
-        }
+        for (int px = 0; px < 2; ++px) {
+            // sum over the candidate bins of u * y, then the angle's factor wmax
+            double sum = chord_u<AXIS>(sk[px][0] - t[px], A.einv, A.inv) * (double)v[px][0];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const double d = sk[1][q] - t[1];
-            acc1 = fma(chord_w<AXIS>(d, A.einv, A.inv, A.wmax), (double)v[1][q], acc1);
+            for (int q = 1; q < NB; ++q)
+                sum = fma(chord_u<AXIS>(sk[px][q] - t[px], A.einv, A.inv), (double)v[px][q], sum);
+            double& acc = px ? acc1 : acc0;
+            acc = AXIS ? acc + sum : fma(A.wmax, sum, acc);
         }
     }
 }

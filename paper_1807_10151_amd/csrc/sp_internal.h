@@ -23,8 +23,8 @@ constexpr int BLOCK = 256;
 struct alignas(16) AngleDev {
     double c, s;      // cos(theta), sin(theta)
     double einv;      // e * inv with e = (|c| + |s|) / 2
-    double inv;       // 1 / (|c| |s|)   (0 for axis-parallel angles)
-    double wmax;      // 1 / max(|c|, |s|)
+    double inv;       // 1 / min(|c|, |s|)   (0 for axis-parallel angles)
+    double wmax;      // 1 / max(|c|, |s|): the largest chord, the factor of u
     double slope;     // forward walk: minor index per major step (selection only)
     double kb;        // backprojection: -s0/ds - hb + 1 + PAD, hb = e/ds + margin (selection only)
     float hw;         // forward walk: half-width of the nonzero band on the minor axis + margin
@@ -113,12 +113,18 @@ struct ScalarRide {
 // weights.  Projection of the pixel centre on the ray normal:
 //   |c| >= |s|:  t = fma(xj, c, yi * s)      |s| > |c|:  t = fma(yi, s, xj * c)
 // (the product outside the fma is the one a forward walk shares between
-// candidates); offset d = sk - t; weight = chord length through the pixel.
+// candidates); offset d = sk - t.  The chord length through the pixel is
+// w = wmax * u with the normalised trapezoid
+//   u = clamp((e - |d|) / min(|c|, |s|), 0, 1) = clamp(fma(-|d|, inv, einv), 0, 1),
+// which compiles to one float64 fma with the output clamp; both operators
+// apply the per-angle factor wmax once to a sum over u-weighted values.  For
+// axis-parallel angles wmax = 1 and u is 1 inside the pixel's column, 1/2 on
+// its edge and 0 outside.
 template <bool AXIS>
-__device__ __forceinline__ double chord_w(double d, double einv, double inv, double wmax) {
+__device__ __forceinline__ double chord_u(double d, double einv, double inv) {
     const double ad = fabs(d);
     if (AXIS) return ad < 0.5 ? 1.0 : (ad == 0.5 ? 0.5 : 0.0);
-    return fmin(fmax(fma(-ad, inv, einv), 0.0), wmax);
+    return fmin(fmax(fma(-ad, inv, einv), 0.0), 1.0);
 }
 
 __device__ __forceinline__ double bin_pos(double k, const GeomDev& G) { return fma(k, G.ds, G.s0); }
