@@ -144,12 +144,12 @@ __device__ __forceinline__ const T* at(const T* base, unsigned o) {
 // the wave's common step range [lo, lo + len).
 template <bool HORIZ, bool AXIS, int NC>
 __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, double sk,
-                                          const double* __restrict__ img, bool valid, int part,
+                                          const double* __restrict__ img,
+                                          const double* __restrict__ Pt, bool valid, int part,
                                           int nparts) {
     const int nmaj = HORIZ ? G.cols : G.rows;
     const int nmin = HORIZ ? G.rows : G.cols;
     const int pitch = HORIZ ? G.pitchXT : G.pitchX;
-    const double fM = HORIZ ? A.c : A.s;   // factor of the shared (major) product
     const double fm = HORIZ ? A.s : A.c;   // factor of the per-candidate fma
     // fractional minor index of the ray's crossing at major step 0, minus hw
     const double start = (HORIZ ? G.yoff - (sk + G.xoff * A.c) / A.s
@@ -181,14 +181,11 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     // coordinate whenever the read is not clamped.
     const double* row = img - PAD;
     const double c2 = HORIZ ? G.yoff + (double)PAD : -(double)PAD - G.xoff;
-    const double dM = HORIZ ? 1.0 : -1.0;                     // major coordinate step
-    double cM = HORIZ ? (double)lo - G.xoff : G.yoff - (double)lo;
     double nf = fma((double)lo, A.slope, start + (double)(1 + PAD));
     const unsigned omax = (unsigned)(nmin + 2 * PAD - NC);
     const double* rp = row + (size_t)lo * pitch;
     // one major step: gather is issued by the caller, weights and sum here
-    auto step = [&](const double* v, unsigned o, double cMv) {
-        const double P = cMv * fM;
+    auto step = [&](const double* v, unsigned o, double P) {
         const double cm0 = HORIZ ? c2 - (double)o : (double)o + c2;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -198,7 +195,10 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
         }
     };
     int m = lo;
-    // two steps per iteration: both gathers are in flight before either step's math
+    // two steps per iteration: both gathers are in flight before either step's
+    // math, and the next iteration's two products are loaded one iteration
+    // ahead (each table row carries two spare entries for the last prefetch)
+    double P0 = Pt[m], P1 = Pt[m + 1];
     for (; m + 1 < hi; m += 2) {
         const unsigned o0 = min((unsigned)(int)nf, omax);
         const unsigned o1 = min((unsigned)(int)(nf + A.slope), omax);
@@ -209,10 +209,12 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v1[q] = p1[q];
-        step(v0, o0, cM);
-        step(v1, o1, cM + dM);
+        const double N0 = Pt[m + 2], N1 = Pt[m + 3];
+        step(v0, o0, P0);
+        step(v1, o1, P1);
+        P0 = N0;
+        P1 = N1;
         nf += 2.0 * A.slope;
-        cM += 2.0 * dM;
         rp += 2 * pitch;
     }
     if (m < hi) {
@@ -221,17 +223,18 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
         double v0[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
-        step(v0, o0, cM);
+        step(v0, o0, P0);
     }
     return acc;
 }
 
 template <bool HORIZ, bool AXIS>
 __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A, double sk,
-                                             const double* __restrict__ img, bool valid,
+                                             const double* __restrict__ img,
+                                             const double* __restrict__ Pt, bool valid,
                                              int part, int nparts) {
-    return A.nc == 3 ? ray_sum<HORIZ, AXIS, 3>(G, A, sk, img, valid, part, nparts)
-                     : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, valid, part, nparts);
+    return A.nc == 3 ? ray_sum<HORIZ, AXIS, 3>(G, A, sk, img, Pt, valid, part, nparts)
+                     : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, Pt, valid, part, nparts);
 }
 
 // Stores ray (row a, bin k): (R x)_{a,k}, or the residual r = R x - b when
@@ -284,23 +287,29 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                                              int out_pitch, float* __restrict__ outp,
                                              double* __restrict__ outpd,
                                              double* __restrict__ partials,
-                                             double* __restrict__ seg, int blk, int part) {
+                                             double* __restrict__ seg,
+                                             const double* __restrict__ ptab, int blk, int part) {
     const int nag = (G.nA + 3) >> 2, nq = (G.nB + 63) >> 6;
     const int ag = blk % nag, q = blk / nag;
-    const int ai = 4 * ag + (threadIdx.x >> 6);
+    const int ai = 4 * ag + (threadIdx.x >> 6);   // one angle per wave
     const int k = q * 64 + (threadIdx.x & 63);
     const bool valid = ai < G.nA && k < G.nB;
-    const AngleDev A = ang[ai < G.nA ? ai : G.nA - 1];
+    const int ac = ai < G.nA ? ai : G.nA - 1;
+    // The angle's constants are read per lane (they feed the per-candidate
+    // FMAs as vector operands); its product row through a wave-uniform
+    // pointer (scalar loads).
+    const AngleDev A = ang[ac];
+    const double* Pt = ptab + (size_t)__builtin_amdgcn_readfirstlane(ac) * G.pitchP;
     const double sk = bin_pos((double)k, G);
     const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
     const int np = seg ? G.parts : 1;
     double acc;
     if (!horiz) {
-        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, valid, part, np)
-                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, valid, part, np);
+        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, Pt, valid, part, np)
+                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, Pt, valid, part, np);
     } else {
-        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, valid, part, np)
-                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid, part, np);
+        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, Pt, valid, part, np)
+                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, Pt, valid, part, np);
     }
     acc *= A.wmax;   // the ray sums u-weighted values (see chord_u)
     if (seg) {
@@ -342,9 +351,10 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
                                                  double* __restrict__ outpd,
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ ord,
+                                                 const double* __restrict__ ptab,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr,
+    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr, ptab,
                  ord[blockIdx.x], 0);
 }
 
@@ -354,9 +364,10 @@ __global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev*
                                                       const double* __restrict__ xTp,
                                                       double* __restrict__ seg,
                                                       const int* __restrict__ ord,
+                                                      const double* __restrict__ ptab,
                                                       const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg,
+    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg, ptab,
                  ord[blockIdx.x], blockIdx.y);
 }
 
@@ -384,13 +395,14 @@ __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ s
         if (G.parts > 1) {
             const int nblk = project_ray_blocks(G);
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, nullptr,
-                         nullptr, nullptr, gmem(S.seg), cmem(S.pord)[lin % nblk], lin / nblk);
+                         nullptr, nullptr, gmem(S.seg), cmem(S.ptab), cmem(S.pord)[lin % nblk],
+                         lin / nblk);
         } else if (residual) {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), gmem(S.b), nullptr, 0, nullptr,
-                         gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.pord)[lin], 0);
+                         gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.ptab), cmem(S.pord)[lin], 0);
         } else {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, gmem(S.rp),
-                         nullptr, nullptr, nullptr, cmem(S.pord)[lin], 0);
+                         nullptr, nullptr, nullptr, cmem(S.ptab), cmem(S.pord)[lin], 0);
         }
     });
 }
@@ -435,6 +447,19 @@ int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_wav
     if (waves >= resident_waves) return 1;
     const long p = (resident_waves + waves - 1) / waves;
     return p > 4 ? 4 : (int)p;
+}
+
+std::vector<double> project_ptab(const GeomDev& G, const std::vector<AngleDev>& tab) {
+    std::vector<double> t((size_t)G.nA * G.pitchP, 0.0);
+    for (int a = 0; a < G.nA; ++a) {
+        const AngleDev& A = tab[(size_t)a];
+        const bool horiz = A.flags & ANG_HORIZ;
+        const int nmaj = horiz ? G.cols : G.rows;
+        double* row = t.data() + (size_t)a * G.pitchP;
+        for (int m = 0; m < nmaj; ++m)
+            row[m] = horiz ? ((double)m - G.xoff) * A.c : (G.yoff - (double)m) * A.s;
+    }
+    return t;
 }
 
 // Step count of one wave of R: the union of its lanes' step ranges, found as
@@ -488,17 +513,17 @@ std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* outpd, double* partials, double* seg, const int* ord,
-                    const int* halt) {
+                    const double* ptab, const int* halt) {
     const int nblk = project_ray_blocks(G);
     if (G.parts > 1) {
         hipLaunchKernelGGL(k_project_part, dim3(nblk, G.parts), dim3(256), 0, st, G, ang, xp, xTp,
-                           seg, ord, halt);
+                           seg, ord, ptab, halt);
         hipLaunchKernelGGL(k_project_comb, dim3(G.nA, (G.nB + 255) / 256), dim3(256), 0, st, G,
                            ang, (const double*)seg, b, out, out_pitch, outp, outpd, partials, halt);
         return;
     }
     hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
-                       outp, outpd, partials, ord, halt);
+                       outp, outpd, partials, ord, ptab, halt);
 }
 
 __global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const float* __restrict__ y,
