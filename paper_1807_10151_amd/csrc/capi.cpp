@@ -1148,7 +1148,7 @@ int sp_backproject(sp_ctx* c, const sp_geometry* g, const float* y, float* x) {
     int rc = setup_geometry(c, g);
     if (rc) return rc;
     const GeomDev& G = c->G;
-    launch_pad_sino(c->stream, G, y, dptr<float>(c->yp));
+    launch_pad_sino(c->stream, G, dptr<AngleDev>(c->ang), y, dptr<float>(c->yp));
     {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
         launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp),

@@ -239,10 +239,12 @@ __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A
 
 // Stores ray (row a, bin k): (R x)_{a,k}, or the residual r = R x - b when
 // b != nullptr, with the float64 sum of r^2 over the workgroup in
-// partials[pidx].  The value goes, rounded to float32, to
-// out[a*out_pitch + k] and to the padded sinogram outp[a*pitchB + PAD + k],
-// and unrounded to the float64 padded sinogram outpd (each nullable).
-__device__ __forceinline__ void project_store(const GeomDev& G, int a, int k, bool valid, double acc,
+// partials[pidx].  The value goes, rounded to float32, to out[a*out_pitch + k];
+// the padded sinograms that feed R^T get it times the angle's wmax (see
+// bp_class), rounded to float32 in outp[a*pitchB + PAD + k] and unrounded in
+// the float64 outpd (each nullable).
+__device__ __forceinline__ void project_store(const GeomDev& G, int a, double wmax, int k,
+                                              bool valid, double acc,
                                               const float* __restrict__ b, float* __restrict__ out,
                                               int out_pitch, float* __restrict__ outp,
                                               double* __restrict__ outpd,
@@ -257,10 +259,10 @@ __device__ __forceinline__ void project_store(const GeomDev& G, int a, int k, bo
         } else {
             v = acc * G.pixel;
         }
-        const float val = (float)v;
-        if (out) out[(size_t)a * out_pitch + k] = val;
-        if (outp) outp[(size_t)a * G.pitchB + PAD + k] = val;
-        if (outpd) outpd[(size_t)a * G.pitchB + PAD + k] = v;
+        if (out) out[(size_t)a * out_pitch + k] = (float)v;
+        const double vs = v * wmax;
+        if (outp) outp[(size_t)a * G.pitchB + PAD + k] = (float)vs;
+        if (outpd) outpd[(size_t)a * G.pitchB + PAD + k] = vs;
     }
     if (b) {
         const double tot = block_sum(r2, red);
@@ -316,7 +318,7 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
         if (valid) seg[((size_t)part * G.nA + ai) * G.nB + k] = acc;
         return;
     }
-    project_store(G, A.row, k, valid, acc, b, out, out_pitch, outp, outpd, partials, blk);
+    project_store(G, A.row, A.wmax, k, valid, acc, b, out, out_pitch, outp, outpd, partials, blk);
 }
 
 // Sum of the parts of the rays of combine block (bx, by): angle bx of the
@@ -331,6 +333,7 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
                                                   double* __restrict__ partials, int bx, int by,
                                                   int gx) {
     const int a = ang[bx].row;
+    const double wmax = ang[bx].wmax;
     const int k = by * 256 + threadIdx.x;
     const bool valid = k < G.nB;
     double acc = 0.0;
@@ -339,7 +342,8 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
         const size_t stride = (size_t)G.nA * G.nB;
         for (int j = 0; j < G.parts; ++j) acc += v[j * stride];
     }
-    project_store(G, a, k, valid, acc, b, out, out_pitch, outp, outpd, partials, by * gx + bx);
+    project_store(G, a, wmax, k, valid, acc, b, out, out_pitch, outp, outpd, partials,
+                  by * gx + bx);
 }
 
 __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
@@ -526,22 +530,30 @@ void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const
                        outp, outpd, partials, ord, ptab, halt);
 }
 
-__global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const float* __restrict__ y,
+// Padded copy of a caller's sinogram for R^T, each row times its angle's wmax
+// (the scaling bp_class expects); one workgroup per entry of the angle table.
+__global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const AngleDev* __restrict__ ang,
+                                                  const float* __restrict__ y,
                                                   float* __restrict__ yp) {
-    const int a = blockIdx.x;
+    const int a = ang[blockIdx.x].row;
+    const double wmax = ang[blockIdx.x].wmax;
     for (int k = threadIdx.x; k < G.nB; k += 256)
-        yp[(size_t)a * G.pitchB + PAD + k] = y[(size_t)a * G.nB + k];
+        yp[(size_t)a * G.pitchB + PAD + k] = (float)((double)y[(size_t)a * G.nB + k] * wmax);
 }
 
-void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp) {
-    hipLaunchKernelGGL(k_pad_sino, dim3(G.nA), dim3(256), 0, st, G, y, yp);
+void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* y,
+                     float* yp) {
+    hipLaunchKernelGGL(k_pad_sino, dim3(G.nA), dim3(256), 0, st, G, ang, y, yp);
 }
 
 // Sum over the angles [beg, end) of one class for pixel (xj, yi).  The angle
 // and its sinogram row are wave-uniform (scalar loads); lanes differ only in
 // the pixel.  sk[PAD + k] = s_k = bin_pos(k) for the padded bin range (the
 // float64 values the projector computes per ray), read from LDS (LSK) or from
-// global memory, so a candidate's offset d is one subtraction.
+// global memory, so a candidate's offset d is one subtraction.  The padded
+// sinogram rows arrive multiplied by their angle's wmax (project_store,
+// k_pad_sino), so each candidate adds u * y' with the u of chord_u: the same
+// weights as the projector's wmax * u.
 //
 // Candidate window: bins floor(kf) + 1 .. floor(kf) + NB, kf = t / ds + kb
 // (A.kb also carries the + 1 + PAD of the padded index).  Truncation equals
@@ -560,6 +572,10 @@ __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __res
                                          double xj0, double xj1, double yi, double& acc0,
                                          double& acc1) {
     const unsigned kmax = (unsigned)(G.nB + 2 * PAD - NB);   // last padded start index
+    // 1/ds held in a vector register, so the index FMA's one scalar operand
+    // can be the angle's kb (an FMA reads at most one scalar register)
+    double ids = G.inv_ds;
+    asm volatile("" : "+v"(ids));
 #pragma unroll 2
     for (int a = beg; a < end; ++a) {
         const AngleDev A = ang[a];
@@ -577,7 +593,7 @@ __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __res
         double sk[2][NB];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const unsigned o = min((unsigned)(int)fma(t[u], G.inv_ds, A.kb), kmax);
+            const unsigned o = min((unsigned)(int)fma(t[u], ids, A.kb), kmax);
             const TY* pv = at(row, o);
             const double* ps = LSK ? sks + o : skg + o;
 #pragma unroll
@@ -586,15 +602,11 @@ __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __res
             for (int q = 0; q < NB; ++q) sk[u][q] = ps[q];
         }
 #pragma unroll
-        for (int px = 0; px < 2; ++px) {
-            // sum over the candidate bins of u * y, then the angle's factor wmax
-            double sum = chord_u<AXIS>(sk[px][0] - t[px], A.einv, A.inv) * (double)v[px][0];
+        for (int q = 0; q < NB; ++q)   // the sinogram rows carry wmax: y' = wmax y
+            acc0 = fma(chord_u<AXIS>(sk[0][q] - t[0], A.einv, A.inv), (double)v[0][q], acc0);
 #pragma unroll
-            for (int q = 1; q < NB; ++q)
-                sum = fma(chord_u<AXIS>(sk[px][q] - t[px], A.einv, A.inv), (double)v[px][q], sum);
-            double& acc = px ? acc1 : acc0;
-            acc = AXIS ? acc + sum : fma(A.wmax, sum, acc);
-        }
+        for (int q = 0; q < NB; ++q)
+            acc1 = fma(chord_u<AXIS>(sk[1][q] - t[1], A.einv, A.inv), (double)v[1][q], acc1);
     }
 }
 

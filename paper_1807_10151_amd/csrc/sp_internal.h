@@ -176,7 +176,9 @@ std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>
 // stay bit-identical.  The forward walk reads it with scalar loads instead of
 // a multiply per step.
 std::vector<double> project_ptab(const GeomDev& G, const std::vector<AngleDev>& tab);
-void launch_pad_sino(hipStream_t st, const GeomDev& G, const float* y, float* yp);
+// Padded copy of y for R^T with each row scaled by its angle's wmax.
+void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* y,
+                     float* yp);
 // skp: float64 bin positions of the padded bin range, skp[PAD + k] = s_k
 // (bin_sk_table fills it on the host with the same fma as bin_pos); used when
 // the table is too large for the backprojector's LDS copy.
