@@ -46,7 +46,7 @@ OPS_PER_NNZ = 4
 # tied to the kernels as profiled; re-measure after changing them.  R^T: mean of
 # its float32 (R p) and float64 (residual) sinogram forms, one of each per loop
 # body.
-TRAFFIC_BYTES = {"project": 44.78e6, "backproject": 23.14e6}
+TRAFFIC_BYTES = {"project": 71.95e6, "backproject": 23.14e6}
 
 
 def log(msg):
