@@ -36,6 +36,28 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) {
     return make_double2(a.x - b.x, a.y - b.y);
 }
 
+// LDS layout of the transform entries: logical entry i of the ncol * P
+// entries sits at i + (i >> sh).  With sh = 3 (one spare 16-byte slot after
+// every 8 entries, used when the padded buffer fits in 64 KB) the
+// power-of-two strides of the butterflies and of the bit-reversed scatter
+// spread over the LDS banks instead of piling onto a few; sh = 30 leaves the
+// layout dense.
+__host__ __device__ __forceinline__ int fft_lds_shift(int P, int ncol) {
+    const size_t n = (size_t)ncol * P;
+    return (n + (n >> 3)) * sizeof(double2) <= 65536 ? 3 : 30;
+}
+
+__host__ __device__ __forceinline__ size_t fft_data_len(int P, int ncol) {
+    const size_t n = (size_t)ncol * P;
+    return n + (n >> fft_lds_shift(P, ncol));
+}
+
+struct LdsBuf {
+    double2* p;
+    int sh;
+    __device__ __forceinline__ double2& operator[](int i) const { return p[i + (i >> sh)]; }
+};
+
 // In-place decimation-in-time FFTs of `ncol` length-P arrays stored back to
 // back in LDS, input in bit-reversed order, output in natural order.
 // sign = -1: forward (exp(-2 pi i ...)); +1: inverse, unscaled.  tw[k] =
@@ -46,7 +68,7 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) {
 // butterflies of stages s and s+1, so every value is the one the stage-by-
 // stage sequence produces, with half the LDS round trips and barriers.
 template <class TW>
-__device__ __forceinline__ void fft_dit(double2* buf, int P, int logP, int ncol, TW tw, float sign) {
+__device__ __forceinline__ void fft_dit(LdsBuf buf, int P, int logP, int ncol, TW tw, float sign) {
     const bool inv = sign > 0.0f;
     auto twd = [&](int k) {
         double2 w = tw[k];
@@ -101,7 +123,7 @@ __device__ __forceinline__ void fft_dit(double2* buf, int P, int logP, int ncol,
 // bit-reversed.  Stages s = logP..1, two per pass (s and s-1 on the four
 // elements i0 + {0, q, 2q, 3q}, q = 2^(s-2)).
 template <class TW>
-__device__ __forceinline__ void fft_dif(double2* buf, int P, int logP, int ncol, TW tw, float sign) {
+__device__ __forceinline__ void fft_dif(LdsBuf buf, int P, int logP, int ncol, TW tw, float sign) {
     const bool inv = sign > 0.0f;
     auto twd = [&](int k) {
         double2 w = tw[k];
@@ -145,30 +167,31 @@ __device__ __forceinline__ void fft_dif(double2* buf, int P, int logP, int ncol,
     }
 }
 
-// The twiddles go to LDS after the ncol * P transform entries when both fit
+// The twiddles go to LDS after the (padded) transform entries when both fit
 // in 64 KB (stage_twiddles returns the LDS copy), else they are read from
 // global memory.
 __host__ __device__ __forceinline__ bool tw_in_lds(int P, int ncol) {
-    return (size_t)(ncol * P + P / 2) * sizeof(double2) <= 65536;
+    return (fft_data_len(P, ncol) + P / 2) * sizeof(double2) <= 65536;
 }
 
-__device__ __forceinline__ const double2* stage_twiddles(const FFTPlan& F, double2* buf, int ncol) {
-    double2* t = buf + (size_t)ncol * F.P;
+__device__ __forceinline__ const double2* stage_twiddles(const FFTPlan& F, double2* raw, int ncol) {
+    double2* t = raw + fft_data_len(F.P, ncol);
     for (int k = threadIdx.x; k < F.P / 2; k += blockDim.x) t[k] = F.tw[k];
     return t;   // visible after the caller's next barrier
 }
 
 #define SP_FFT(kind, ncol, sign)                                                  \
     do {                                                                          \
-        if (twl) kind(buf, F.P, F.logP, ncol, (const double2*)(buf + (size_t)(ncol) * F.P), sign); \
+        if (twl) kind(buf, F.P, F.logP, ncol, (const double2*)(raw + fft_data_len(F.P, ncol)), sign); \
         else kind(buf, F.P, F.logP, ncol, F.tw, sign);                            \
     } while (0)
 
 __device__ __forceinline__ void rows_fwd_body(const FFTPlan& F, const float* __restrict__ g,
-                                              double2* buf, int bx) {
+                                              double2* raw, int bx) {
+    const LdsBuf buf{raw, fft_lds_shift(F.P, 1)};
     const int r0 = 2 * bx, r1 = r0 + 1;
     const bool twl = tw_in_lds(F.P, 1);
-    if (twl) stage_twiddles(F, buf, 1);
+    if (twl) stage_twiddles(F, raw, 1);
     for (int nidx = threadIdx.x; nidx < F.P; nidx += blockDim.x) {
         float re = 0.0f, im = 0.0f;
         if (nidx < F.cols) {
@@ -202,12 +225,13 @@ __device__ __forceinline__ double window_h(double w, double mu, double rho) {
     return (w + mu) * (rho + (1.0 - rho) * cos(w));
 }
 
-__device__ __forceinline__ void cols_body(const FFTPlan& F, double mu, double rho, double2* buf,
+__device__ __forceinline__ void cols_body(const FFTPlan& F, double mu, double rho, double2* raw,
                                           int bx) {
+    const LdsBuf buf{raw, fft_lds_shift(F.P, F.CB)};
     const int u0 = bx * F.CB;
     const int total = F.CB * F.P;
     const bool twl = tw_in_lds(F.P, F.CB);
-    if (twl) stage_twiddles(F, buf, F.CB);
+    if (twl) stage_twiddles(F, raw, F.CB);
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int r = idx / F.CB, cc = idx - r * F.CB;
         double2 v = make_double2(0.0f, 0.0f);
@@ -244,12 +268,13 @@ __global__ __launch_bounds__(512) void k_cols(FFTPlan F, double mu, double rho, 
 
 __device__ __forceinline__ void rows_inv_body(const FFTPlan& F, float* __restrict__ z,
                                               const float* __restrict__ dotv,
-                                              double* __restrict__ partials, double2* buf, int bx) {
-    double* red = reinterpret_cast<double*>(buf);   // reused after the transform is read
+                                              double* __restrict__ partials, double2* raw, int bx) {
+    const LdsBuf buf{raw, fft_lds_shift(F.P, 1)};
+    double* red = reinterpret_cast<double*>(raw);   // reused after the transform is read
     const int r0 = 2 * bx, r1 = r0 + 1;
     const bool has1 = r1 < F.rows;
     const bool twl = tw_in_lds(F.P, 1);
-    if (twl) stage_twiddles(F, buf, 1);
+    if (twl) stage_twiddles(F, raw, 1);
     for (int u = threadIdx.x; u < F.P; u += blockDim.x) {
         double2 X0, X1 = make_double2(0.0f, 0.0f);
         if (u <= F.P / 2) {
@@ -345,7 +370,7 @@ void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTa
 int precond_dot_blocks(const FFTPlan& F) { return (F.rows + 1) / 2; }
 
 size_t fft_lds_bytes(int P, int ncol) {
-    return ((size_t)ncol * P + (tw_in_lds(P, ncol) ? P / 2 : 0)) * sizeof(double2);
+    return (fft_data_len(P, ncol) + (tw_in_lds(P, ncol) ? P / 2 : 0)) * sizeof(double2);
 }
 
 void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, const float* g,
