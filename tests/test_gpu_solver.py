@@ -58,6 +58,12 @@ def test_suppcg_small64_20_iterations(sp, small, small_ref):
     np.testing.assert_allclose(res.trace["f_half"], ref.trace["f_half"], rtol=1e-3)
     np.testing.assert_allclose(res.trace["tv_half"], ref.trace["tv_half"], rtol=1e-3)
     assert res.trace["f0"] == pytest.approx(ref.trace["f0"], rel=1e-5)
+    # the scalar steps the loop body folds into other kernels: beta and alpha
+    # (inside the p and x updates) and the S_TV step norm (with f, carried by
+    # the g backprojection)
+    np.testing.assert_allclose(res.trace["alpha"], ref.trace["alpha"], rtol=1e-3)
+    np.testing.assert_allclose(res.trace["beta"], ref.trace["beta"], rtol=1e-3)
+    np.testing.assert_allclose(res.trace["s_norm"], ref.trace["s_norm"], rtol=1e-3)
 
 
 def test_pcg_and_cg_small64(sp, small):
