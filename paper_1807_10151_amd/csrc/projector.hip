@@ -4,8 +4,9 @@
 // R[(a,k),(i,j)] is the length of ray (a,k) inside pixel (i,j) (the projection
 // matrix of Section 2, rays as in Section 4.1).  Both operators evaluate the
 // weight with the same float64 instruction sequence (projection t of the pixel
-// centre, offset d = s_k - t, chord_w), so R^T uses bit-identical weights and is
-// the exact adjoint up to summation order.  Data are float32; offsets, weights
+// centre, offset d = s_k - t, the clamped trapezoid u of chord_u, times the
+// angle's wmax), so R^T uses bit-identical weights and is the exact adjoint up
+// to summation order.  Data are float32; offsets, weights
 // and sums are float64 (FP64 FMA issues at the non-packed FP32 rate on CDNA4,
 // and float32 angles alone would move a ray by ~1e-5 pixel at radius 256).
 //
@@ -13,13 +14,16 @@
 //   |c| >= |s| ("vertical" angles):   t = fma(xj, c, yi * s)
 //   |s| >  |c| ("horizontal" angles): t = fma(yi, s, xj * c)
 // The product outside the fma is the one a forward walk shares between the
-// candidates of one step.
+// candidates of one step; the walk reads it from a per-angle table of the
+// same float64 products (project_ptab).
 //
 // Forward walk.  For a vertical angle a ray crosses every image row; at row i
 // its nonzero pixels lie within hw columns of the crossing point, which moves
 // by `slope` columns per row.  A lane owns one ray; the 64 lanes of a wave hold
 // consecutive rays of one angle and walk the union of their row ranges
-// together, so each step gathers consecutive addresses of one row.  Candidate
+// together, so each step gathers consecutive addresses of one row.  A
+// workgroup's four waves take four consecutive angles and the same 64-bin
+// chunk, and the workgroups run in a host-computed order (project_order).  Candidate
 // columns outside the image are clamped into a zero pad and contribute 0.
 // Horizontal angles walk columns of a zero-padded transposed copy.
 //
@@ -27,7 +31,8 @@
 // angles, which are sorted into four classes (vertical/horizontal x
 // oblique/axis-parallel) so the inner loop has no branch; at each angle a
 // pixel's nonzero bins are the NB bins after floor(kf - hb), read from a
-// zero-padded sinogram (float32, or float64 for the solvers' residual).
+// zero-padded sinogram (float32, or float64 for the solvers' residual) whose
+// rows carry the angle's wmax.
 #include "sp_internal.h"
 #include "sp_reduce.h"
 #include "sp_scalar.h"
