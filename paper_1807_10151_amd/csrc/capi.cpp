@@ -51,7 +51,7 @@ struct sp_ctx {
     sp_geometry geom{};
     GeomDev G{};
     std::vector<AngleDev> ang_h;
-    DevBuf ang, skp, xp, xTp, yp, ypd, seg, pord, ptab;
+    DevBuf ang, skp, xp, xTp, yp, ypd, seg, pord;
 
     // preconditioner cache
     int fftP = 0;
@@ -206,7 +206,6 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
     G.pitchXT = g->rows + 2 * PAD;
     G.pitchB = g->n_bins + 2 * PAD;
     G.parts = project_parts(g->rows, g->cols, g->n_angles, g->n_bins, c->n_cu * 32);
-    G.pitchP = std::max(g->rows, g->cols) + 2;   // two spare entries per row (prefetch)
     const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
     tab.assign(g->n_angles, AngleDev{});
     for (int a = 0; a < g->n_angles; ++a) {
@@ -298,10 +297,6 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     const std::vector<int32_t> ord = project_order(G, tab, c->n_cu);
     if ((rc = ensure(c, c->pord, ord.size() * sizeof(int32_t)))) return rc;
     HIP_TRY(c, hipMemcpyAsync(c->pord.ptr, ord.data(), ord.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice, c->stream));
-    const std::vector<double> pt = project_ptab(G, tab);
-    if ((rc = ensure(c, c->ptab, pt.size() * sizeof(double)))) return rc;
-    HIP_TRY(c, hipMemcpyAsync(c->ptab.ptr, pt.data(), pt.size() * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));  // host tables must outlive the copies
     c->G = G;
@@ -673,7 +668,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
     std::vector<std::vector<AngleDev>> tabs(n);
     // sizes
     struct Off {
-        size_t ang, skp, pord, ptab, xp, xTp, rp, rpd, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
+        size_t ang, skp, pord, xp, xTp, rp, rpd, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
     };
     std::vector<Off> off(n);
     size_t total = 0;
@@ -712,7 +707,6 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         o.ang = take(tabs[s].size() * sizeof(AngleDev));
         o.skp = take(((size_t)G.nB + 2 * PAD) * sizeof(double));
         o.pord = take((size_t)project_ray_blocks(G) * sizeof(int32_t));
-        o.ptab = take((size_t)G.nA * G.pitchP * sizeof(double));
         o.xp = take((size_t)G.rows * G.pitchX * 8);
         o.xTp = take((size_t)G.cols * G.pitchXT * 8);
         o.rp = take((size_t)G.nA * G.pitchB * 4);
@@ -749,10 +743,6 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         const std::vector<int32_t> ord = project_order(S.G, tabs[s], c->n_cu);
         S.pord = reinterpret_cast<const int*>(base + o.pord);
         HIP_TRY(c, hipMemcpyAsync(base + o.pord, ord.data(), ord.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, c->stream));
-        const std::vector<double> pt = project_ptab(S.G, tabs[s]);
-        S.ptab = reinterpret_cast<const double*>(base + o.ptab);
-        HIP_TRY(c, hipMemcpyAsync(base + o.ptab, pt.data(), pt.size() * sizeof(double),
                                   hipMemcpyHostToDevice, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         S.xp = reinterpret_cast<double*>(base + o.xp);
@@ -921,7 +911,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     if (!c) return SP_ERR_ARG;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->ptab, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh,
+    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
                       &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
@@ -1136,7 +1126,7 @@ int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
         ProfScope ps(c, SP_PROF_PROJECT);
         launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp),
                        nullptr, y, G.nB, nullptr, nullptr, nullptr, dptr<double>(c->seg),
-                       dptr<int>(c->pord), dptr<double>(c->ptab), nullptr);
+                       dptr<int>(c->pord), nullptr);
     }
     return check_launch(c);
 }
@@ -1168,7 +1158,7 @@ int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b,
     launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
     launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp), b, r,
                    G.nB, nullptr, nullptr, dptr<double>(c->part_f), dptr<double>(c->seg),
-                   dptr<int>(c->pord), dptr<double>(c->ptab), nullptr);
+                   dptr<int>(c->pord), nullptr);
     launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
     return check_launch(c);
 }
@@ -1340,7 +1330,6 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     double* xTp = dptr<double>(c->xTp);
     double* seg = dptr<double>(c->seg);
     const int* pord = dptr<int>(c->pord);
-    const double* ptab = dptr<double>(c->ptab);
     float* rp = dptr<float>(c->yp);
     double* rpd = dptr<double>(c->ypd);
     const double* skp = dptr<double>(c->skp);
@@ -1356,7 +1345,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
     // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
     launch_prep(st, G, xh, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, pord, ptab, halt);
+    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, pord, halt);
     launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
     launch_backproject(st, G, ang, rpd, skp, gv, nullptr, nullptr, halt);
     int nzh = 0;
@@ -1364,7 +1353,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
     launch_update_p(st, n, z, p, gv, sc, pgp, halt);
     launch_prep(st, G, p, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, pord, ptab, halt);
+    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, pord, halt);
     launch_backproject(st, G, ang, rp, skp, h, p, pph, halt);
     launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
     launch_update_x(st, n, xh, p, x, sc, halt);
@@ -1378,7 +1367,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     auto project = [&](const float* bb, double* parts) {
         ProfScope ps(c, SP_PROF_PROJECT);
         launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, bb ? nullptr : rp, bb ? rpd : nullptr,
-                       parts, seg, pord, ptab, halt);
+                       parts, seg, pord, halt);
     };
     auto backproject = [&](float* out, const double* dotv, double* parts,
                            const ScalarRide& ride) {

@@ -2,24 +2,26 @@
 // transpose R^T (pixel-driven gather, no atomics).
 //
 // R[(a,k),(i,j)] is the length of ray (a,k) inside pixel (i,j) (the projection
-// matrix of Section 2, rays as in Section 4.1).  Both operators evaluate the
-// weight with the same float64 instruction sequence (projection t of the pixel
+// matrix of Section 2, rays as in Section 4.1).  R^T evaluates each weight as
+// the chord length of a line through a square (projection t of the pixel
 // centre, offset d = s_k - t, the clamped trapezoid u of chord_u, times the
-// angle's wmax), so R^T uses bit-identical weights and is the exact adjoint up
-// to summation order.  Data are float32; offsets, weights
-// and sums are float64 (FP64 FMA issues at the non-packed FP32 rate on CDNA4,
-// and float32 angles alone would move a ray by ~1e-5 pixel at radius 256).
+// angle's wmax).  R walks each ray band by band and splits a band's path
+// length at the pixel boundary it crosses (ray_split): the same lengths in
+// exact arithmetic, equal to rounding in float64, so R^T is the adjoint of R
+// to float64 rounding (axis-parallel angles use the trapezoid in both, bit for
+// bit).  Data are float32; coordinates, weights and sums are float64 (FP64
+// FMA issues at the non-packed FP32 rate on CDNA4, and float32 angles alone
+// would move a ray by ~1e-5 pixel at radius 256).
 //
 // Canonical projection of pixel centre (xj, yi) on the normal of angle a:
 //   |c| >= |s| ("vertical" angles):   t = fma(xj, c, yi * s)
 //   |s| >  |c| ("horizontal" angles): t = fma(yi, s, xj * c)
-// The product outside the fma is the one a forward walk shares between the
-// candidates of one step; the walk reads it from a per-angle table of the
-// same float64 products (project_ptab).
+// The product outside the fma is the one the axis-parallel forward walk
+// shares between the candidates of one step.
 //
-// Forward walk.  For a vertical angle a ray crosses every image row; at row i
-// its nonzero pixels lie within hw columns of the crossing point, which moves
-// by `slope` columns per row.  A lane owns one ray; the 64 lanes of a wave hold
+// Forward walk.  For a vertical angle a ray crosses every image row; within
+// row i it meets at most two pixels, as its crossing point moves by `slope`
+// (|slope| <= 1) columns per row.  A lane owns one ray; the 64 lanes of a wave hold
 // consecutive rays of one angle and walk the union of their row ranges
 // together, so each step gathers consecutive addresses of one row.  A
 // workgroup's four waves take four consecutive angles and the same 64-bin
@@ -149,8 +151,7 @@ __device__ __forceinline__ const T* at(const T* base, unsigned o) {
 // the wave's common step range [lo, lo + len).
 template <bool HORIZ, bool AXIS, int NC>
 __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, double sk,
-                                          const double* __restrict__ img,
-                                          const double* __restrict__ Pt, bool valid, int part,
+                                          const double* __restrict__ img, bool valid, int part,
                                           int nparts) {
     const int nmaj = HORIZ ? G.cols : G.rows;
     const int nmin = HORIZ ? G.rows : G.cols;
@@ -186,11 +187,15 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
     // coordinate whenever the read is not clamped.
     const double* row = img - PAD;
     const double c2 = HORIZ ? G.yoff + (double)PAD : -(double)PAD - G.xoff;
+    const double fM = HORIZ ? A.c : A.s;   // factor of the shared (major) product
+    const double dM = HORIZ ? 1.0 : -1.0;  // major coordinate step
+    double cM = HORIZ ? (double)lo - G.xoff : G.yoff - (double)lo;
     double nf = fma((double)lo, A.slope, start + (double)(1 + PAD));
     const unsigned omax = (unsigned)(nmin + 2 * PAD - NC);
     const double* rp = row + (size_t)lo * pitch;
     // one major step: gather is issued by the caller, weights and sum here
-    auto step = [&](const double* v, unsigned o, double P) {
+    auto step = [&](const double* v, unsigned o, double cMv) {
+        const double P = cMv * fM;
         const double cm0 = HORIZ ? c2 - (double)o : (double)o + c2;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
@@ -200,10 +205,7 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
         }
     };
     int m = lo;
-    // two steps per iteration: both gathers are in flight before either step's
-    // math, and the next iteration's two products are loaded one iteration
-    // ahead (each table row carries two spare entries for the last prefetch)
-    double P0 = Pt[m], P1 = Pt[m + 1];
+    // two steps per iteration: both gathers are in flight before either step's math
     for (; m + 1 < hi; m += 2) {
         const unsigned o0 = min((unsigned)(int)nf, omax);
         const unsigned o1 = min((unsigned)(int)(nf + A.slope), omax);
@@ -214,12 +216,10 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v1[q] = p1[q];
-        const double N0 = Pt[m + 2], N1 = Pt[m + 3];
-        step(v0, o0, P0);
-        step(v1, o1, P1);
-        P0 = N0;
-        P1 = N1;
+        step(v0, o0, cM);
+        step(v1, o1, cM + dM);
         nf += 2.0 * A.slope;
+        cM += 2.0 * dM;
         rp += 2 * pitch;
     }
     if (m < hi) {
@@ -228,18 +228,93 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
         double v0[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) v0[q] = p0[q];
-        step(v0, o0, P0);
+        step(v0, o0, cM);
     }
     return acc;
 }
 
+// One oblique ray's sum of u-weighted values, or part `part` of it, by
+// splitting each major step's band at the pixel boundary.  With |slope| <= 1
+// the ray crosses a band (an image row for vertical angles, a column of the
+// transposed copy for horizontal ones) over a minor-axis interval of length
+// |slope| starting at lp = b0 + m * slope (padded minor coordinate, pixel q
+// spanning [q, q + 1)), so it meets at most pixels floor(lp) and
+// floor(lp) + 1.  The share of the band's path length (wmax, applied by the
+// caller) in the first is f = clamp((floor(lp) + 1 - lp) / |slope|, 0, 1) and
+// the rest falls in the second: the exact chord lengths of the pixel model,
+// the same values chord_u * wmax gives up to rounding, with fewer operations
+// per step than evaluating the trapezoid per candidate.  Indices and the
+// step range are handled as in ray_sum: a truncated index below the row or
+// past it is clamped into the zero pads, where the pixels contribute 0.
+template <bool HORIZ>
+__device__ __forceinline__ double ray_split(const GeomDev& G, const AngleDev& A, double sk,
+                                            const double* __restrict__ img, bool valid, int part,
+                                            int nparts) {
+    const int nmaj = HORIZ ? G.cols : G.rows;
+    const int nmin = HORIZ ? G.rows : G.cols;
+    const int pitch = HORIZ ? G.pitchXT : G.pitchX;
+    const double start = (HORIZ ? G.yoff - (sk + G.xoff * A.c) / A.s
+                                : (sk - G.yoff * A.s) / A.c + G.xoff) - (double)A.hw;
+    int lo, hi;
+    step_range(start, A.slope, -(double)(A.nc + 1), (double)(nmin + 1), nmaj, lo, hi);
+    if (!valid) {
+        lo = nmaj;
+        hi = 0;
+    }
+    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
+    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
+    if (nparts > 1 && hi > lo) {
+        const int len = hi - lo;
+        const int l0 = lo + len * part / nparts;
+        hi = lo + len * (part + 1) / nparts;
+        lo = l0;
+    }
+    double acc = 0.0;
+    if (lo >= hi) return acc;
+    const double sig = A.slope;
+    const double isg = 1.0 / fabs(sig);
+    // minor coordinate where the ray enters band 0 on its lower side, padded
+    const double b0 = (HORIZ ? G.yoff + 0.5 - (sk + (G.xoff + 0.5) * A.c) / A.s
+                             : (sk - (G.yoff + 0.5) * A.s) / A.c + G.xoff + 0.5) +
+                      fmin(sig, 0.0) + (double)PAD;
+    const unsigned omax = (unsigned)(nmin + 2 * PAD - 2);
+    const double* rp = img - PAD + (size_t)lo * pitch;
+    auto step = [&](const double* v, int fl, double lpv) {
+        const double f = fmin(fmax(fma(lpv - (double)fl, -isg, isg), 0.0), 1.0);
+        acc += fma(f, v[0] - v[1], v[1]);
+    };
+    double dm = (double)lo;
+    int m = lo;
+    for (; m + 1 < hi; m += 2) {
+        const double lp0 = fma(dm, sig, b0), lp1 = lp0 + sig;
+        const int f0 = (int)lp0, f1 = (int)lp1;
+        const double* p0 = at(rp, min((unsigned)f0, omax));
+        const double* p1 = at(rp + pitch, min((unsigned)f1, omax));
+        const double v0[2] = {p0[0], p0[1]};
+        const double v1[2] = {p1[0], p1[1]};
+        step(v0, f0, lp0);
+        step(v1, f1, lp1);
+        dm += 2.0;
+        rp += 2 * pitch;
+    }
+    if (m < hi) {
+        const double lp0 = fma(dm, sig, b0);
+        const int f0 = (int)lp0;
+        const double* p0 = at(rp, min((unsigned)f0, omax));
+        const double v0[2] = {p0[0], p0[1]};
+        step(v0, f0, lp0);
+    }
+    return acc;
+}
+
+// Axis-parallel angles keep the per-candidate trapezoid (with its half weight
+// for a ray on a pixel edge); oblique ones split each band.
 template <bool HORIZ, bool AXIS>
 __device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A, double sk,
-                                             const double* __restrict__ img,
-                                             const double* __restrict__ Pt, bool valid,
+                                             const double* __restrict__ img, bool valid,
                                              int part, int nparts) {
-    return A.nc == 3 ? ray_sum<HORIZ, AXIS, 3>(G, A, sk, img, Pt, valid, part, nparts)
-                     : ray_sum<HORIZ, AXIS, 2>(G, A, sk, img, Pt, valid, part, nparts);
+    if (AXIS) return ray_sum<HORIZ, true, 2>(G, A, sk, img, valid, part, nparts);
+    return ray_split<HORIZ>(G, A, sk, img, valid, part, nparts);
 }
 
 // Stores ray (row a, bin k): (R x)_{a,k}, or the residual r = R x - b when
@@ -294,29 +369,23 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                                              int out_pitch, float* __restrict__ outp,
                                              double* __restrict__ outpd,
                                              double* __restrict__ partials,
-                                             double* __restrict__ seg,
-                                             const double* __restrict__ ptab, int blk, int part) {
+                                             double* __restrict__ seg, int blk, int part) {
     const int nag = (G.nA + 3) >> 2, nq = (G.nB + 63) >> 6;
     const int ag = blk % nag, q = blk / nag;
     const int ai = 4 * ag + (threadIdx.x >> 6);   // one angle per wave
     const int k = q * 64 + (threadIdx.x & 63);
     const bool valid = ai < G.nA && k < G.nB;
-    const int ac = ai < G.nA ? ai : G.nA - 1;
-    // The angle's constants are read per lane (they feed the per-candidate
-    // FMAs as vector operands); its product row through a wave-uniform
-    // pointer (scalar loads).
-    const AngleDev A = ang[ac];
-    const double* Pt = ptab + (size_t)__builtin_amdgcn_readfirstlane(ac) * G.pitchP;
+    const AngleDev A = ang[ai < G.nA ? ai : G.nA - 1];
     const double sk = bin_pos((double)k, G);
     const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
     const int np = seg ? G.parts : 1;
     double acc;
     if (!horiz) {
-        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, Pt, valid, part, np)
-                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, Pt, valid, part, np);
+        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, valid, part, np)
+                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, valid, part, np);
     } else {
-        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, Pt, valid, part, np)
-                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, Pt, valid, part, np);
+        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, valid, part, np)
+                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid, part, np);
     }
     acc *= A.wmax;   // the ray sums u-weighted values (see chord_u)
     if (seg) {
@@ -360,10 +429,9 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
                                                  double* __restrict__ outpd,
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ ord,
-                                                 const double* __restrict__ ptab,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr, ptab,
+    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr,
                  ord[blockIdx.x], 0);
 }
 
@@ -373,10 +441,9 @@ __global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev*
                                                       const double* __restrict__ xTp,
                                                       double* __restrict__ seg,
                                                       const int* __restrict__ ord,
-                                                      const double* __restrict__ ptab,
                                                       const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg, ptab,
+    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg,
                  ord[blockIdx.x], blockIdx.y);
 }
 
@@ -404,14 +471,13 @@ __global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ s
         if (G.parts > 1) {
             const int nblk = project_ray_blocks(G);
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, nullptr,
-                         nullptr, nullptr, gmem(S.seg), cmem(S.ptab), cmem(S.pord)[lin % nblk],
-                         lin / nblk);
+                         nullptr, nullptr, gmem(S.seg), cmem(S.pord)[lin % nblk], lin / nblk);
         } else if (residual) {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), gmem(S.b), nullptr, 0, nullptr,
-                         gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.ptab), cmem(S.pord)[lin], 0);
+                         gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.pord)[lin], 0);
         } else {
             project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, gmem(S.rp),
-                         nullptr, nullptr, nullptr, cmem(S.ptab), cmem(S.pord)[lin], 0);
+                         nullptr, nullptr, nullptr, cmem(S.pord)[lin], 0);
         }
     });
 }
@@ -456,19 +522,6 @@ int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_wav
     if (waves >= resident_waves) return 1;
     const long p = (resident_waves + waves - 1) / waves;
     return p > 4 ? 4 : (int)p;
-}
-
-std::vector<double> project_ptab(const GeomDev& G, const std::vector<AngleDev>& tab) {
-    std::vector<double> t((size_t)G.nA * G.pitchP, 0.0);
-    for (int a = 0; a < G.nA; ++a) {
-        const AngleDev& A = tab[(size_t)a];
-        const bool horiz = A.flags & ANG_HORIZ;
-        const int nmaj = horiz ? G.cols : G.rows;
-        double* row = t.data() + (size_t)a * G.pitchP;
-        for (int m = 0; m < nmaj; ++m)
-            row[m] = horiz ? ((double)m - G.xoff) * A.c : (G.yoff - (double)m) * A.s;
-    }
-    return t;
 }
 
 // Step count of one wave of R: the union of its lanes' step ranges, found as
@@ -522,17 +575,17 @@ std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* outpd, double* partials, double* seg, const int* ord,
-                    const double* ptab, const int* halt) {
+                    const int* halt) {
     const int nblk = project_ray_blocks(G);
     if (G.parts > 1) {
         hipLaunchKernelGGL(k_project_part, dim3(nblk, G.parts), dim3(256), 0, st, G, ang, xp, xTp,
-                           seg, ord, ptab, halt);
+                           seg, ord, halt);
         hipLaunchKernelGGL(k_project_comb, dim3(G.nA, (G.nB + 255) / 256), dim3(256), 0, st, G,
                            ang, (const double*)seg, b, out, out_pitch, outp, outpd, partials, halt);
         return;
     }
     hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
-                       outp, outpd, partials, ord, ptab, halt);
+                       outp, outpd, partials, ord, halt);
 }
 
 // Padded copy of a caller's sinogram for R^T, each row times its angle's wmax

@@ -49,7 +49,6 @@ struct GeomDev {
     int pitchB;         // nB + 2 PAD: row pitch of the padded sinogram
     int nbmax;          // max backprojection candidates over the angles
     int parts;          // parts each ray's step range is split into by R (1: whole rays)
-    int pitchP;         // max(rows, cols) + 2: row pitch of R's per-step product table
     int cls[5];         // angle-table class boundaries: vertical, horizontal,
                         // vertical axis, horizontal axis
 };
@@ -109,16 +108,18 @@ struct ScalarRide {
     int ns = 0;
 };
 
-// Canonical evaluation of the weight of pixel centre (xj, yi) for ray sk,
-// shared by the projector and the backprojector so both use bit-identical
-// weights.  Projection of the pixel centre on the ray normal:
+// Canonical evaluation of the weight of pixel centre (xj, yi) for ray sk: the
+// backprojector's weight for every angle and the projector's for
+// axis-parallel angles (oblique rays are split band by band, see ray_split,
+// which gives the same lengths to rounding).  Projection of the pixel centre
+// on the ray normal:
 //   |c| >= |s|:  t = fma(xj, c, yi * s)      |s| > |c|:  t = fma(yi, s, xj * c)
 // (the product outside the fma is the one a forward walk shares between
 // candidates); offset d = sk - t.  The chord length through the pixel is
 // w = wmax * u with the normalised trapezoid
 //   u = clamp((e - |d|) / min(|c|, |s|), 0, 1) = clamp(fma(-|d|, inv, einv), 0, 1),
-// which compiles to one float64 fma with the output clamp; both operators
-// apply the per-angle factor wmax once to a sum over u-weighted values.  For
+// which compiles to one float64 fma with the output clamp; the per-angle
+// factor wmax is applied once to a sum over u-weighted values.  For
 // axis-parallel angles wmax = 1 and u is 1 inside the pixel's column, 1/2 on
 // its edge and 0 outside.
 template <bool AXIS>
@@ -144,12 +145,11 @@ void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, 
 // before they are combined.  outp / outpd: float32 / float64 padded sinograms
 // (nullable); the residual's float64 values feed R^T without a float32
 // rounding (its cancellation in R^T r amplifies that rounding).  ord: the
-// device copy of project_order(G, ...), the virtual block each workgroup runs;
-// ptab: the device copy of project_ptab(G, ...).
+// device copy of project_order(G, ...), the virtual block each workgroup runs.
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
                     const double* xTp, const float* b, float* out, int out_pitch, float* outp,
                     double* outpd, double* partials, double* seg, const int* ord,
-                    const double* ptab, const int* halt);
+                    const int* halt);
 // Workgroups of one part of R: four angles by one 64-bin chunk each.
 __host__ __device__ inline int project_ray_blocks(const GeomDev& G) {
     return ((G.nA + 3) / 4) * ((G.nB + 63) / 64);
@@ -169,13 +169,6 @@ int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_wav
 // sum to about the same work.  Only the order of the work changes; every sum
 // and its partials index stay the same.
 std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>& tab, int n_cu);
-// R's per-step products, [nA][pitchP] in class-sorted angle order: entry
-// (a, m) is the major coordinate of step m times its factor, (yoff - m) s for
-// a vertical-class angle and (m - xoff) c for a horizontal one -- the same
-// float64 product the backprojector forms (y_i sin, x_j cos), so the weights
-// stay bit-identical.  The forward walk reads it with scalar loads instead of
-// a multiply per step.
-std::vector<double> project_ptab(const GeomDev& G, const std::vector<AngleDev>& tab);
 // Padded copy of y for R^T with each row scaled by its angle's wmax.
 void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* y,
                      float* yp);
@@ -290,7 +283,6 @@ struct SliceDev {
     double* rpd;        // float64 padded sinogram (residual)
     double* seg;        // R's per-part ray sums, [parts][nA][nB] (G.parts > 1)
     const int* pord;    // R's workgroup order (project_order)
-    const double* ptab; // R's per-step products (project_ptab)
     double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
     Scalars* sc;
     TraceDev tr;
