@@ -37,7 +37,11 @@ PEAK_VALU_OPS = 256 * 64 * 2.4e9
 # (two candidate bins, each an offset, the trapezoid weight and an
 # accumulation, plus the pixel's projection), i.e. 20 n A per call (about
 # 96 us at the issue peak for 512^2 x 720).  The lower bound of 4 lane-ops per
-# nonzero weight is reported beside it.
+# nonzero weight is reported beside it.  The kernels now issue fewer than 20
+# lane-ops per pair (R ~11, R^T ~13-15), so the line also reports the issue
+# rate the kernel's own instructions reach: VALU wave-instructions per launch
+# at this workload (rocprofv3 SQ_INSTS_VALU, profiles/counters_ct512.md; R^T:
+# mean of its two forms), 64 lane-ops each, over the live launch time.
 OPS_PER_PIXEL_ANGLE = 20
 OPS_PER_NNZ = 4
 # Bytes moved between L2 and the memory fabric per launch of the projector
@@ -46,7 +50,8 @@ OPS_PER_NNZ = 4
 # tied to the kernels as profiled; re-measure after changing them.  R^T: mean of
 # its float32 (R p) and float64 (residual) sinogram forms, one of each per loop
 # body.
-TRAFFIC_BYTES = {"project": 71.95e6, "backproject": 23.14e6}
+TRAFFIC_BYTES = {"project": 39.12e6, "backproject": 23.13e6}
+VALU_INSTR = {"project": 3.373e7, "backproject": 4.264e7}
 
 
 def log(msg):
@@ -396,6 +401,9 @@ def main():
                      "lower_bound_4_per_nonzero": {"achieved": round(achieved_nnz / 1e12, 4),
                                                    "frac": round(achieved_nnz / PEAK_VALU_OPS, 4)},
                      "traffic": TRAFFIC_BYTES[dom_name],
+                     "valu_issue": {"instr_per_launch": VALU_INSTR[dom_name],
+                                    "frac": round(VALU_INSTR[dom_name] * 64 / (dom_ms / 1e3)
+                                                  / PEAK_VALU_OPS, 4)},
                      "kernel_ms": round(dom_ms, 4), "launches": solve_ms[dom_name][1]},
         "in_solve_ms": {k: round(v, 4) for k, v in avg.items()},
         "operators_ms": {"project": round(ms_R, 4), "backproject": round(ms_RT, 4),
