@@ -550,7 +550,7 @@ static long wave_steps(const GeomDev& G, const AngleDev& A, int k0, int k1) {
         lo = std::min(lo, l);
         hi = std::max(hi, h);
     }
-    return hi > lo ? (long)(hi - lo) * A.nc : 0;
+    return hi > lo ? (long)(hi - lo) : 0;   // the split walk costs the same per step
 }
 
 std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>& tab,
