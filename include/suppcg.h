@@ -159,8 +159,10 @@ const char* sp_version(void);
  * x: [rows][cols] float32 (device, read); y: [n_angles][n_bins] (device, written). */
 int sp_project(sp_ctx* ctx, const sp_geometry* g, const float* x, float* y);
 
-/* x = R^T y, the exact transpose of sp_project's weights (same weight for
- * every (ray, pixel) pair, bit for bit), pixel-driven, no atomics (eq. 2.2).
+/* x = R^T y, the transpose of sp_project's weights, pixel-driven, no atomics
+ * (eq. 2.2).  Each (ray, pixel) weight is the same chord length sp_project
+ * uses, equal to float64 rounding (bit for bit at axis-parallel angles; R
+ * splits oblique rays band by band, R^T evaluates the trapezoid).
  * y: [n_angles][n_bins] (device, read); x: [rows][cols] (device, written). */
 int sp_backproject(sp_ctx* ctx, const sp_geometry* g, const float* y, float* x);
 

@@ -1,7 +1,7 @@
 """GPU parity of the operators (R, R^T, M, TV, S_TV) against the CPU oracle.
 
-Tolerance for R and R^T: 1e-5 relative L2 over the output (float32 weights and
-sums against float64).  Inputs are seeded; expected values come from the oracle.
+Tolerance for R and R^T: 1e-5 relative L2 over the output (float32 data and
+outputs against the float64 oracle).  Inputs are seeded; expected values come from the oracle.
 """
 import math
 
