@@ -45,7 +45,13 @@ def random_geometries(n, seed=2024):
     return out
 
 
-GEOMS = random_geometries(24)
+GEOMS = random_geometries(24) + [
+    # angles a hair away from the axes and from 45 degrees: the split walk's
+    # band shares 1/|slope| become huge or reach 1
+    OG(41, 57, 4, 75, theta0=1e-7, dtheta=math.pi / 2),
+    OG(64, 48, 6, 85, theta0=math.pi / 4 - 1e-9, dtheta=math.pi / 4),
+    OG(30, 30, 5, 47, theta0=math.pi / 2 - 3e-8, dtheta=1e-8),
+]
 
 
 def G(sp, og):
