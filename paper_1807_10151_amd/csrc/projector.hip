@@ -370,7 +370,7 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                                              double* __restrict__ outpd,
                                              double* __restrict__ partials,
                                              double* __restrict__ seg, int blk, int part) {
-    const int nag = (G.nA + 3) >> 2, nq = (G.nB + 63) >> 6;
+    const int nag = (G.nA + 3) >> 2;
     const int ag = blk % nag, q = blk / nag;
     const int ai = 4 * ag + (threadIdx.x >> 6);   // one angle per wave
     const int k = q * 64 + (threadIdx.x & 63);

@@ -232,7 +232,8 @@ __device__ __forceinline__ void tv_decide_body(int rows, int cols, const double*
         __shared__ double out[TVJ + 1];
         for (int start = TVJ; start < max_trials && chosen_s < 0; start += TVJ) {
             const int nq = min(TVJ, max_trials - start);
-            if (threadIdx.x < TVJ) lam[threadIdx.x] = threadIdx.x < nq ? trial_lambda(sc, start + threadIdx.x, tn) : 0.0;
+            if (threadIdx.x < TVJ)
+                lam[threadIdx.x] = (int)threadIdx.x < nq ? trial_lambda(sc, start + threadIdx.x, tn) : 0.0;
             __syncthreads();
             tv_trials_wg(y, tb, rows, cols, lam, nq, out, red);
             if (threadIdx.x == 0) {
