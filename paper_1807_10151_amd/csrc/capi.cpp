@@ -29,6 +29,7 @@ struct BatchState {
     int kind = -1;
     int nbmax = 1;
     int max_bins = 1;
+    int bp_px = 2;                   // R^T pixels per lane for the whole batch
     size_t lds_rows = 0, lds_cols = 0;
     std::vector<SliceDev> hs;        // host copies; per-call pointers filled in each call
     DevBuf arena, sl, items, scal, trace_d;
@@ -206,6 +207,7 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
     G.pitchXT = g->rows + 2 * PAD;
     G.pitchB = g->n_bins + 2 * PAD;
     G.parts = project_parts(g->rows, g->cols, g->n_angles, g->n_bins, c->n_cu * 32);
+    G.bp_px = backproject_px(g->rows, g->cols, c->n_cu * 32);
     const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
     tab.assign(g->n_angles, AngleDev{});
     for (int a = 0; a < g->n_angles; ++a) {
@@ -579,7 +581,7 @@ int stage_blocks(const SliceDev& S, int stage) {
     case BS_PREP: return ((G.cols + 31) / 32) * ((G.rows + 31) / 32);
     case BS_PROJECT: return project_ray_blocks(G) * G.parts;
     case BS_PROJ_COMB: return G.parts > 1 ? project_comb_blocks(G) : 0;
-    case BS_BACKPROJECT: return backproject_blocks(G);
+    case BS_BACKPROJECT: return backproject_tiles(G, G.bp_px);
     case BS_ROWS: return (G.rows + 1) / 2;
     case BS_COLS: return S.F.P ? (S.F.SP + S.F.CB - 1) / S.F.CB : 0;
     case BS_TV: return tv_blocks(G.rows, G.cols);
@@ -725,6 +727,15 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         o.pts = take((size_t)S.ntv * 8);
     }
     if (B.lds_cols > 65536) return fail(c, SP_ERR_ARG, "FFT column tile exceeds the LDS");
+    // one R^T tile shape for the whole batch: four pixels per lane when the
+    // batch's 4-pixel tiles still fill half the wave slots (the sums do not
+    // depend on it, so batched and single solves stay bitwise equal)
+    {
+        long waves4 = 0;
+        for (const SliceDev& S : B.hs) waves4 += (long)backproject_tiles(S.G, 4) * 4;
+        B.bp_px = waves4 >= (long)c->n_cu * 16 ? 4 : 2;
+        for (SliceDev& S : B.hs) S.G.bp_px = B.bp_px;
+    }
     // a fresh zero-filled arena: the pads of the padded copies must be zero
     release(B.arena);
     if ((rc = ensure(c, B.arena, total))) return rc;
@@ -818,7 +829,7 @@ void batch_stage(sp_ctx* c, int stage, int order, int wpc, double mu, double rho
     switch (stage) {
     case BS_PREP: launch_prep_b(st, sl, t, BV_XH); break;
     case BS_PROJECT: launch_project_b(st, sl, t, table(c, BS_PROJ_COMB, order, 0), true); break;
-    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, B.max_bins, false); break;
+    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, B.max_bins, false, B.bp_px); break;
     case BS_ROWS:
         launch_precond_b(st, sl, t, table(c, BS_COLS, order, wpc), B.lds_rows, B.lds_cols, mu, rho);
         break;
@@ -1577,13 +1588,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     launch_prep_b(st, sl, tprep, BV_XH);
     launch_project_b(st, sl, tproj, tcomb, true);
     launch_scalar_b(st, sl, tone, OP_F0);
-    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false);
+    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false, B.bp_px);
     batch_precond(c, mu, rho);
     launch_scalar_b(st, sl, tone, OP_BETA);
     launch_update_p_b(st, sl, tvec);
     launch_prep_b(st, sl, tprep, BV_P);
     launch_project_b(st, sl, tproj, tcomb, false);
-    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true);
+    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true, B.bp_px);
     launch_scalar_b(st, sl, tone, OP_ALPHA0);
     launch_update_x_b(st, sl, tvec);
     if ((rc = check_launch(c))) return rc;
@@ -1605,13 +1616,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         launch_prep_b(st, sl, tprep, BV_XH);
         launch_project_b(st, sl, tproj, tcomb, true);
         launch_scalar_b(st, sl, tone, OP_F);
-        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false);
+        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false, B.bp_px);
         batch_precond(c, mu, rho);
         launch_scalar_b(st, sl, tone, OP_BETA);
         launch_update_p_b(st, sl, tvec);
         launch_prep_b(st, sl, tprep, BV_P);
         launch_project_b(st, sl, tproj, tcomb, false);
-        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true);
+        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true, B.bp_px);
         launch_scalar_b(st, sl, tone, OP_ALPHA);
         launch_update_x_b(st, sl, tvec);
     };

@@ -623,12 +623,11 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, cons
 // Each lane sums two pixels of one row, (xj0, yi) and (xj1, yi): the angle's
 // uniform work (constants, yi s) is shared, the per-pixel sequence is the one
 // above.
-template <bool HORIZ, bool AXIS, int NB, bool LSK, class TY>
+template <bool HORIZ, bool AXIS, int NB, bool LSK, class TY, int PX>
 __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
                                          int beg, int end, const TY* __restrict__ yp,
                                          const double* __restrict__ skg, const double* sks,
-                                         double xj0, double xj1, double yi, double& acc0,
-                                         double& acc1) {
+                                         const double* xj, double yi, double* acc) {
     const unsigned kmax = (unsigned)(G.nB + 2 * PAD - NB);   // last padded start index
     // 1/ds held in a vector register, so the index FMA's one scalar operand
     // can be the angle's kb (an FMA reads at most one scalar register)
@@ -638,19 +637,14 @@ __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __res
     for (int a = beg; a < end; ++a) {
         const AngleDev A = ang[a];
         const TY* row = yp + (size_t)A.row * G.pitchB;
-        double t[2];
-        if (HORIZ) {
-            t[0] = fma(yi, A.s, xj0 * A.c);
-            t[1] = fma(yi, A.s, xj1 * A.c);
-        } else {
-            const double ys = yi * A.s;
-            t[0] = fma(xj0, A.c, ys);
-            t[1] = fma(xj1, A.c, ys);
-        }
-        TY v[2][NB];
-        double sk[2][NB];
+        double t[PX];
+        const double ys = yi * A.s;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < PX; ++u) t[u] = HORIZ ? fma(yi, A.s, xj[u] * A.c) : fma(xj[u], A.c, ys);
+        TY v[PX][NB];
+        double sk[PX][NB];
+#pragma unroll
+        for (int u = 0; u < PX; ++u) {
             const unsigned o = min((unsigned)(int)fma(t[u], ids, A.kb), kmax);
             const TY* pv = at(row, o);
             const double* ps = LSK ? sks + o : skg + o;
@@ -660,16 +654,18 @@ __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __res
             for (int q = 0; q < NB; ++q) sk[u][q] = ps[q];
         }
 #pragma unroll
-        for (int q = 0; q < NB; ++q)   // the sinogram rows carry wmax: y' = wmax y
-            acc0 = fma(chord_u<AXIS>(sk[0][q] - t[0], A.einv, A.inv), (double)v[0][q], acc0);
+        for (int u = 0; u < PX; ++u)   // the sinogram rows carry wmax: y' = wmax y
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-            acc1 = fma(chord_u<AXIS>(sk[1][q] - t[1], A.einv, A.inv), (double)v[1][q], acc1);
+            for (int q = 0; q < NB; ++q)
+                acc[u] = fma(chord_u<AXIS>(sk[u][q] - t[u], A.einv, A.inv), (double)v[u][q], acc[u]);
     }
 }
 
-constexpr int BP_TILE = 8;      // 8 rows x 16 columns per wave (two pixels per lane)
-constexpr int BP_TW = 16;
+// A workgroup owns a tile of 8 rows x 8 PX columns, PX pixels per lane 8
+// columns apart (PX = 2 or 4, chosen per launch).  Partial dot products are
+// kept per 8 x 16 sub-tile whatever PX is, so the result does not depend on it.
+constexpr int BP_TILE = 8;
+constexpr int BP_TW = 16;       // sub-tile width of the partials
 constexpr int BP_SPLIT = 4;     // waves per workgroup, each over a quarter of the angles
 // The bin-position table goes to LDS when it takes at most this many bytes.
 constexpr size_t BP_LDS_SK_MAX = 24 * 1024;
@@ -686,16 +682,16 @@ __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int
 // sums the w-th quarter of every angle class,
 // and the four partial sums are added in wave order through LDS.  With LSK the
 // workgroup first writes the bin-position table into the dynamic LDS `sks`.
-template <int NB, bool LSK, class TY>
+template <int NB, bool LSK, class TY, int PX>
 __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDev* __restrict__ ang,
                                                  const TY* __restrict__ yp,
                                                  const double* __restrict__ skg, double* sks,
                                                  float* __restrict__ out,
                                                  const double* __restrict__ dotv,
-                                                 double* __restrict__ partials, int bx, int by,
-                                                 int gx) {
-    __shared__ double part[BP_SPLIT][2][64];
-    __shared__ double red[4];
+                                                 double* __restrict__ partials, int bx, int by) {
+    constexpr int NS = PX / 2;   // 8 x 16 sub-tiles per tile
+    __shared__ double part[BP_SPLIT][PX][64];
+    __shared__ double red[4 * NS];
     if (LSK) {
         for (int k = threadIdx.x; k < G.nB + 2 * PAD; k += 256) sks[k] = bin_pos((double)(k - PAD), G);
         __syncthreads();
@@ -703,43 +699,55 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = by * BP_TILE + (lane >> 3);
-    const int j0 = bx * BP_TW + (lane & 7), j1 = j0 + 8;
+    const int j0 = bx * 8 * PX + (lane & 7);
     const double yi = G.yoff - (double)i;
-    double acc0 = 0.0, acc1 = 0.0;
-    const double xj0 = (double)j0 - G.xoff, xj1 = (double)j1 - G.xoff;
+    double acc[PX], xj[PX];
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+        acc[u] = 0.0;
+        xj[u] = (double)(j0 + 8 * u) - G.xoff;
+    }
     int b, e;
     split_range(G.cls[0], G.cls[1], w, b, e);
-    bp_class<false, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
+    bp_class<false, false, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[1], G.cls[2], w, b, e);
-    bp_class<true, false, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
+    bp_class<true, false, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[2], G.cls[3], w, b, e);
-    bp_class<false, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
+    bp_class<false, true, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
     split_range(G.cls[3], G.cls[4], w, b, e);
-    bp_class<true, true, NB, LSK, TY>(G, ang, b, e, yp, skg, sks, xj0, xj1, yi, acc0, acc1);
-    part[w][0][lane] = acc0;
-    part[w][1][lane] = acc1;
+    bp_class<true, true, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+#pragma unroll
+    for (int u = 0; u < PX; ++u) part[w][u][lane] = acc[u];
     __syncthreads();
-    double v = 0.0;
+    double v[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) v[q] = 0.0;
     if (w == 0) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int j = u ? j1 : j0;
+        for (int u = 0; u < PX; ++u) {
+            const int j = j0 + 8 * u;
             const double tot =
                 ((part[0][u][lane] + part[1][u][lane]) + part[2][u][lane]) + part[3][u][lane];
             const float val = (float)(tot * G.pixel);
             if (i < G.rows && j < G.cols) {
                 out[(size_t)i * G.cols + j] = val;
-                if (dotv) v += (double)val * dotv[(size_t)i * G.cols + j];
+                if (dotv) v[u / 2] += (double)val * dotv[(size_t)i * G.cols + j];
             }
         }
     }
     if (dotv) {
-        const double tot = block_sum(v, red);
-        if (threadIdx.x == 0) partials[by * gx + bx] = tot;
+        // partial of 8 x 16 sub-tile (by, NS bx + q) at by * gx16 + NS bx + q
+        block_sum_n<NS>(v, red);
+        const int gx16 = (G.cols + BP_TW - 1) / BP_TW;
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (NS * bx + q < gx16) partials[by * gx16 + NS * bx + q] = v[q];
+        }
     }
 }
 
-template <int NB, bool LSK, class TY>
+template <int NB, bool LSK, class TY, int PX>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
                                                      const TY* __restrict__ yp,
                                                      const double* __restrict__ skg,
@@ -750,8 +758,8 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
     extern __shared__ double sks[];
-    backproject_body<NB, LSK, TY>(G, ang, yp, skg, sks, out, dotv, partials, blockIdx.x,
-                                  blockIdx.y, gridDim.x);
+    backproject_body<NB, LSK, TY, PX>(G, ang, yp, skg, sks, out, dotv, partials, blockIdx.x,
+                                      blockIdx.y);
     if (ride.sc && blockIdx.x == 0 && blockIdx.y == 0) {
         if (ride.ps) scalar_body(OP_SNORM, ride.sc, ride.tr, ride.ps, ride.ns, nullptr, 0);
         if (ride.pf) scalar_body(OP_F, ride.sc, ride.tr, ride.pf, ride.nf, nullptr, 0);
@@ -761,7 +769,7 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
 // TY = float: h = R^T rp (rp = R p) with the partials of h^T p; TY = double:
 // g = R^T rpd from the float64 residual.  NB is the largest candidate count of
 // the batch (extra candidates weigh exactly 0).
-template <int NB, bool LSK, class TY>
+template <int NB, bool LSK, class TY, int PX>
 __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, ItemTable t) {
     constexpr bool normal = sizeof(TY) == sizeof(float);
     extern __shared__ double sks[];
@@ -769,13 +777,13 @@ __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
-        const int gx = (G.cols + BP_TW - 1) / BP_TW;
+        const int gx = (G.cols + 8 * PX - 1) / (8 * PX);
         const TY* yp;
         if constexpr (normal) yp = gmem(S.rp);
         else yp = gmem(S.rpd);
-        backproject_body<NB, LSK, TY>(G, cmem(S.ang), yp, gmem(S.skp), sks,
+        backproject_body<NB, LSK, TY, PX>(G, cmem(S.ang), yp, gmem(S.skp), sks,
                                       gmem(normal ? S.h : S.g), normal ? gmem(S.p) : nullptr,
-                                      normal ? gmem(S.pph) : nullptr, lin % gx, lin / gx, gx);
+                                      normal ? gmem(S.pph) : nullptr, lin % gx, lin / gx);
     });
 }
 
@@ -784,25 +792,31 @@ size_t bp_lds_bytes(int nbins) {
     return b <= BP_LDS_SK_MAX ? b : 0;
 }
 
-template <bool LSK, class TY>
-void launch_bp_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, size_t lds) {
+template <bool LSK, class TY, int PX>
+void launch_bp_b_px(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, size_t lds) {
     switch (nbmax) {
-    case 1: hipLaunchKernelGGL((kb_backproject<1, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
-    case 2: hipLaunchKernelGGL((kb_backproject<2, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
-    case 3: hipLaunchKernelGGL((kb_backproject<3, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
-    default: hipLaunchKernelGGL((kb_backproject<4, LSK, TY>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    case 1: hipLaunchKernelGGL((kb_backproject<1, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    case 2: hipLaunchKernelGGL((kb_backproject<2, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    case 3: hipLaunchKernelGGL((kb_backproject<3, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    default: hipLaunchKernelGGL((kb_backproject<4, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
     }
 }
 
+template <bool LSK, class TY>
+void launch_bp_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, size_t lds, int px) {
+    if (px == 4) launch_bp_b_px<LSK, TY, 4>(st, sl, t, nbmax, lds);
+    else launch_bp_b_px<LSK, TY, 2>(st, sl, t, nbmax, lds);
+}
+
 void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
-                          bool normal) {
+                          bool normal, int px) {
     const size_t lds = bp_lds_bytes(max_bins);
     if (normal) {
-        if (lds) launch_bp_b<true, float>(st, sl, t, nbmax, lds);
-        else launch_bp_b<false, float>(st, sl, t, nbmax, 0);
+        if (lds) launch_bp_b<true, float>(st, sl, t, nbmax, lds, px);
+        else launch_bp_b<false, float>(st, sl, t, nbmax, 0, px);
     } else {
-        if (lds) launch_bp_b<true, double>(st, sl, t, nbmax, lds);
-        else launch_bp_b<false, double>(st, sl, t, nbmax, 0);
+        if (lds) launch_bp_b<true, double>(st, sl, t, nbmax, lds, px);
+        else launch_bp_b<false, double>(st, sl, t, nbmax, 0, px);
     }
 }
 
@@ -810,17 +824,39 @@ int backproject_blocks(const GeomDev& G) {
     return ((G.cols + BP_TW - 1) / BP_TW) * ((G.rows + BP_TILE - 1) / BP_TILE);
 }
 
+int backproject_tiles(const GeomDev& G, int px) {
+    return ((G.cols + 8 * px - 1) / (8 * px)) * ((G.rows + BP_TILE - 1) / BP_TILE);
+}
+
+int backproject_px(int rows, int cols, int resident_waves) {
+    // four pixels per lane amortise more of each angle's work but need ~100
+    // VGPRs (4 waves per SIMD): take them when the 4-pixel grid still gives
+    // every SIMD four waves
+    GeomDev G{};
+    G.rows = rows;
+    G.cols = cols;
+    return (long)backproject_tiles(G, 4) * BP_SPLIT >= resident_waves / 2 ? 4 : 2;
+}
+
+template <bool LSK, class TY, int PX>
+void launch_bp_px(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp,
+                  const double* skp, float* out, const double* dotv, double* partials,
+                  const int* halt, size_t lds, const ScalarRide& ride) {
+    dim3 grid((G.cols + 8 * PX - 1) / (8 * PX), (G.rows + BP_TILE - 1) / BP_TILE);
+    switch (G.nbmax) {
+    case 1: hipLaunchKernelGGL((k_backproject<1, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    case 2: hipLaunchKernelGGL((k_backproject<2, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    case 3: hipLaunchKernelGGL((k_backproject<3, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    default: hipLaunchKernelGGL((k_backproject<4, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    }
+}
+
 template <bool LSK, class TY>
 void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp,
                const double* skp, float* out, const double* dotv, double* partials, const int* halt,
                size_t lds, const ScalarRide& ride) {
-    dim3 grid((G.cols + BP_TW - 1) / BP_TW, (G.rows + BP_TILE - 1) / BP_TILE);
-    switch (G.nbmax) {
-    case 1: hipLaunchKernelGGL((k_backproject<1, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
-    case 2: hipLaunchKernelGGL((k_backproject<2, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
-    case 3: hipLaunchKernelGGL((k_backproject<3, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
-    default: hipLaunchKernelGGL((k_backproject<4, LSK, TY>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
-    }
+    if (G.bp_px == 4) launch_bp_px<LSK, TY, 4>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
+    else launch_bp_px<LSK, TY, 2>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
 }
 
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,

@@ -49,6 +49,7 @@ struct GeomDev {
     int pitchB;         // nB + 2 PAD: row pitch of the padded sinogram
     int nbmax;          // max backprojection candidates over the angles
     int parts;          // parts each ray's step range is split into by R (1: whole rays)
+    int bp_px;          // pixels per lane of R^T (2 or 4, see backproject_px)
     int cls[5];         // angle-table class boundaries: vertical, horizontal,
                         // vertical axis, horizontal axis
 };
@@ -182,7 +183,13 @@ void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, c
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
                         const double* skp, float* out, const double* dotv, double* partials,
                         const int* halt, const ScalarRide& ride = ScalarRide{});
+// Number of R^T's float64 dot partials: one per 8 x 16 pixel sub-tile.
 int backproject_blocks(const GeomDev& G);
+// R^T workgroups (8 x 8 px pixel tiles) for px pixels per lane.
+int backproject_tiles(const GeomDev& G, int px);
+// Pixels per lane R^T uses for an image: 4 when that grid still fills half
+// the device's wave slots, else 2.  The result does not depend on it.
+int backproject_px(int rows, int cols, int resident_waves);
 
 // fft.hip
 struct FFTPlan {
@@ -334,8 +341,9 @@ __device__ __forceinline__ double* batch_vec(const SliceDev& S, int which) {
 // projector.hip
 void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which);
 void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable tc, bool residual);
+// px: pixels per lane of every slice in the launch (their G.bp_px).
 void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
-                          bool normal);
+                          bool normal, int px);
 // fft.hip (z = M g; with the partials of z^T h into pzh)
 void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTable cols,
                       size_t lds_rows, size_t lds_cols, double mu, double rho);
