@@ -50,8 +50,8 @@ OPS_PER_NNZ = 4
 # tied to the kernels as profiled; re-measure after changing them.  R^T: mean of
 # its float32 (R p) and float64 (residual) sinogram forms, one of each per loop
 # body.
-TRAFFIC_BYTES = {"project": 39.12e6, "backproject": 23.13e6}
-VALU_INSTR = {"project": 3.373e7, "backproject": 4.264e7}
+TRAFFIC_BYTES = {"project": 39.13e6, "backproject": 20.39e6}
+VALU_INSTR = {"project": 3.373e7, "backproject": 4.134e7}
 
 
 def log(msg):
