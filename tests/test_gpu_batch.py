@@ -77,6 +77,29 @@ def test_batch_equals_single_solves(sp, graph, autotune):
         print("tuning:", sp.batch_tuning(), flush=True)
 
 
+def test_batch_pixels_per_lane_keep_results(sp):
+    """The 512 x 640 slice gives the batch 1,280 four-pixel R^T tiles (5,120
+    waves, over 16 per CU on 256 CUs), so the whole batch takes four pixels per
+    lane; the 64 x 64 slice alone has 16 such tiles and takes two. R^T's
+    dot-product partials are per 8 x 16 sub-tile in one order whatever the
+    pixels per lane, so the small slice must still match its own solve bit for
+    bit (and the large one, four pixels per lane on both sides, too)."""
+    from synth import random_ellipses
+    geoms = [sp.Geometry(512, 640, 180, 900), sp.Geometry(64, 64, 90, 91)]
+    bs = []
+    for i, g in enumerate(geoms):
+        img, rng = random_ellipses(g.rows, g.cols, 5, 700 + i)
+        b = sp.sp_project(g, torch.from_numpy(img.astype(np.float32)).cuda())
+        noise = torch.from_numpy(rng.standard_normal(g.m).astype(np.float32)).cuda()
+        bs.append((b + 0.01 * float(b.max()) * noise.reshape(b.shape)).contiguous())
+    kw = dict(K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO, max_iter=6)
+    got = sp.sp_suppcg_solve_batched(geoms, bs, graph=False, autotune=False, **kw)
+    want = singles(sp, geoms, bs, **kw)
+    for i, (rb, rs) in enumerate(zip(got, want)):
+        print(f"slice {i}: k {rb.k} status {rb.status_name}", flush=True)
+        assert_same(rb, rs)
+
+
 def test_batch_cg_start_and_halting(sp):
     # M = I, K = 2, a nonzero start on some slices and an all-zero data slice
     # that breaks down at once while the others run on
