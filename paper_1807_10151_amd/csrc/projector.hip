@@ -29,9 +29,10 @@
 // columns outside the image are clamped into a zero pad and contribute 0.
 // Horizontal angles walk columns of a zero-padded transposed copy.
 //
-// Backward gather.  A lane owns two pixels of one row and loops over the
-// angles, which are sorted into four classes (vertical/horizontal x
-// oblique/axis-parallel) so the inner loop has no branch; at each angle a
+// Backward gather.  A lane owns PX (2 or 4) pixels of one row, 8 columns
+// apart, and loops over the angles, which are sorted into four classes
+// (vertical/horizontal x oblique/axis-parallel) so the inner loop has no
+// branch; at each angle a
 // pixel's nonzero bins are the NB bins after floor(kf - hb), read from a
 // zero-padded sinogram (float32, or float64 for the solvers' residual) whose
 // rows carry the angle's wmax.
@@ -620,9 +621,9 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, cons
 // pads -- in both cases every true candidate lies outside the detector.  A
 // candidate that reads a pad gets a weight evaluated at the pad's position and
 // multiplies 0.
-// Each lane sums two pixels of one row, (xj0, yi) and (xj1, yi): the angle's
-// uniform work (constants, yi s) is shared, the per-pixel sequence is the one
-// above.
+// Each lane sums PX pixels of one row, (xj[0], yi) ... (xj[PX-1], yi): the
+// angle's uniform work (constants, yi s) is shared, the per-pixel sequence is
+// the one above.
 template <bool HORIZ, bool AXIS, int NB, bool LSK, class TY, int PX>
 __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
                                          int beg, int end, const TY* __restrict__ yp,
@@ -678,7 +679,7 @@ __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int
 
 // out[i][j] = (R^T y)_{ij} from the padded sinogram yp; with dotv != nullptr
 // also the float64 partial sum of out * dotv per workgroup.  A workgroup owns
-// an 8 x 16 pixel tile (two pixels, 8 columns apart, per lane); its wave w
+// an 8 x 8PX pixel tile (PX pixels, 8 columns apart, per lane); its wave w
 // sums the w-th quarter of every angle class,
 // and the four partial sums are added in wave order through LDS.  With LSK the
 // workgroup first writes the bin-position table into the dynamic LDS `sks`.
