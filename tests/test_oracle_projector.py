@@ -11,6 +11,7 @@ import pytest
 
 from oracle import closed_form, projector, siddon
 from oracle.geometry import Geometry, angle_cos_sin, bin_positions, pixel_centres
+from oracle.geometry import angle_table as angle_table_arrays
 
 
 def clip_length(c, s, sk, x0, x1, y0, y1):
@@ -191,3 +192,58 @@ def test_column_matches_matrix():
         dense = np.zeros(g.m)
         dense[rows] = w
         assert np.max(np.abs(dense - col)) <= 1e-12
+
+
+# ---- literal geometry (Section 4.1: equally spaced angles in [0, pi), parallel
+# rays at a fixed spacing, centred on the rotation axis) ----
+
+def test_angle_table_literal():
+    _, c, s = angle_table_arrays(Geometry(3, 3, 4, 3))
+    h = math.sqrt(0.5)
+    assert list(c) == [1.0, h, 0.0, -h] and list(s) == [0.0, h, 1.0, h]
+    th = [angle_cos_sin(Geometry(3, 3, 6, 3), a)[0] for a in range(6)]
+    assert th[0] == 0.0
+    assert np.allclose(np.diff(th), math.pi / 6, rtol=0, atol=1e-15)
+    assert th[-1] + math.pi / 6 == pytest.approx(math.pi, abs=1e-15)     # [0, pi), pi excluded
+    _, c6, s6 = angle_cos_sin(Geometry(3, 3, 6, 3), 1)
+    assert c6 == pytest.approx(math.sqrt(3) / 2, abs=3e-16) and s6 == pytest.approx(0.5, abs=3e-16)
+
+
+def test_bin_positions_literal():
+    assert list(bin_positions(Geometry(2, 2, 1, 5))) == [-2.0, -1.0, 0.0, 1.0, 2.0]
+    assert list(bin_positions(Geometry(2, 2, 1, 4))) == [-1.5, -0.5, 0.5, 1.5]
+    s = bin_positions(Geometry(2, 2, 1, 4, bin_spacing=0.5, bin_offset=0.1))
+    assert np.allclose(s, [-0.65, -0.15, 0.35, 0.85], rtol=0, atol=1e-16)
+    # the paper's detector: 345 rays 0.0752 apart, the middle one through the axis
+    s = bin_positions(Geometry(243, 243, 360, 345, pixel=0.0752, bin_spacing=0.0752))
+    assert s[172] == 0.0 and s[0] == pytest.approx(-172 * 0.0752, abs=1e-13)
+
+
+def test_tiny_matrix_literal():
+    # 2 x 2 unit pixels (row 0 on top), angles 0 and pi/2, three bins at -1, 0, 1.
+    # theta = 0: the lines x = -1, 0, 1 run along the left border, the middle
+    # edge and the right border (each adjacent pixel gets half a pixel, G6);
+    # theta = pi/2: y = -1, 0, 1 along the bottom border, the middle edge, the top.
+    R, _ = projector.matrix(Geometry(2, 2, 2, 3), "siddon")
+    want = np.array([
+        [0.5, 0.0, 0.5, 0.0],     # x = -1: left column
+        [0.5, 0.5, 0.5, 0.5],     # x = 0
+        [0.0, 0.5, 0.0, 0.5],     # x = 1: right column
+        [0.0, 0.0, 0.5, 0.5],     # y = -1: bottom row (row 1)
+        [0.5, 0.5, 0.5, 0.5],     # y = 0
+        [0.5, 0.5, 0.0, 0.0],     # y = 1: top row (row 0)
+    ])
+    assert np.array_equal(R.toarray(), want)
+    # even bin count, even column count: the lines x = -1/2, 1/2 run through
+    # the pixel centres and take each pixel of their column whole
+    R, _ = projector.matrix(Geometry(3, 2, 1, 2), "siddon")
+    assert np.array_equal(R.toarray(), [[1.0, 0.0, 1.0, 0.0, 1.0, 0.0],
+                                        [0.0, 1.0, 0.0, 1.0, 0.0, 1.0]])
+    # odd column count: the same lines now lie on the edges around the centre column
+    R, _ = projector.matrix(Geometry(2, 3, 1, 2), "siddon")
+    assert np.array_equal(R.toarray(), [[0.5, 0.5, 0.0, 0.5, 0.5, 0.0],
+                                        [0.0, 0.5, 0.5, 0.0, 0.5, 0.5]])
+    # 45 degrees through the centre of a single pixel: its diagonal
+    R, _ = projector.matrix(Geometry(1, 1, 4, 1), "siddon")
+    assert R.toarray()[1, 0] == pytest.approx(math.sqrt(2), abs=1e-15)
+    assert R.toarray()[3, 0] == pytest.approx(math.sqrt(2), abs=1e-15)

@@ -130,3 +130,70 @@ def test_breakdown_on_zero_data():
     prob = suppcg.Problem(R, np.zeros(g.m), (8, 8), lambda v: precond.apply(v, 1e-3, 0.7))
     res = suppcg.suppcg(prob, np.zeros(g.n), suppcg.TVParams(1, 0.5, 0.5), n_iter=5)
     assert res.status == "breakdown" and res.k == 1
+
+
+# ---- Algorithm 1's exact step schedule on an image whose TV along t is known ----
+#
+# A lone interior spike of height h on a zero background: minus the TV gradient
+# is nonzero only at the spike (each neighbour also enters a flat square-root
+# term, so the zero rule of Section 3.1 removes it), where it equals -(2 + sqrt 2)
+# times sign(h).  Hence t = -sign(h) e_spike and TV(y + lam t) = (2 + sqrt 2) |h -
+# lam sign(h)|: trial step lam is accepted iff lam <= 2 |h| (equality included).
+# Algorithm 1 forms gamma a^l BEFORE incrementing l, so the j-th trial of an
+# inner step entered with l0 has length gamma a^(l0 + j - 1) and leaves l = l0 + j.
+
+def _spike(h, shape=(6, 7), at=(2, 3)):
+    y = np.zeros(shape)
+    y[at] = h
+    return y
+
+
+def _first_accepted(l0, gamma, a, h):
+    j = 1
+    while gamma * a ** (l0 + j - 1) > 2 * abs(h):
+        j += 1
+    return j
+
+
+@pytest.mark.parametrize("l0,gamma,a,h,want_j", [
+    (0, 1.0, 0.5, 0.1, 4),       # 1, 1/2, 1/4 rejected; 1/8 <= 0.2 accepted
+    (3, 1.0, 0.5, 0.1, 1),       # first trial 1/8
+    (0, 20.0, 0.5, 0.3, 7),      # 20 .. 0.625 rejected, 0.3125 accepted
+    (2, 3.0, 0.9, 0.05, 32),
+])
+def test_s_tv_step_schedule_on_spike(l0, gamma, a, h, want_j):
+    assert _first_accepted(l0, gamma, a, h) == want_j
+    y = _spike(h)
+    out = suppcg.s_tv(y, l0, suppcg.TVParams(K=1, a=a, gamma=gamma))
+    lam = gamma * a ** (l0 + want_j - 1)
+    assert out.trials == [want_j] and out.ell == l0 + want_j and not out.exhausted
+    want_s = np.zeros_like(y)
+    want_s[2, 3] = -lam
+    assert np.array_equal(out.s, want_s)
+    assert np.sqrt(np.sum(out.s ** 2)) == lam
+    assert out.tv_after == pytest.approx((2 + math.sqrt(2)) * abs(h - lam), rel=1e-14)
+
+
+def test_s_tv_tie_accepts_and_inner_steps_carry_l():
+    # lam = 2h exactly: TV(y + lam t) == TV(y) bit for bit, and "<=" accepts
+    out = suppcg.s_tv(_spike(0.25), 0, suppcg.TVParams(K=1, a=0.5, gamma=1.0))
+    assert out.trials == [2] and out.ell == 2 and out.s[2, 3] == -0.5
+    # K = 2: the first inner step takes 1/8 (trial 4) leaving a spike of -0.025;
+    # the second starts at l = 4: 1/16 > 0.05 rejected, 1/32 accepted (t now +e)
+    out = suppcg.s_tv(_spike(0.1), 0, suppcg.TVParams(K=2, a=0.5, gamma=1.0))
+    assert out.trials == [4, 2] and out.ell == 6
+    assert out.s[2, 3] == pytest.approx(-0.125 + 1.0 / 32, abs=0)
+    assert np.count_nonzero(out.s) == 1
+
+
+def test_suppcg_trace_records_schedule():
+    # inside Algorithm 3 the l carried between calls follows the same rule: the
+    # trace's l_{k+1} minus l_k equals the trials of loop body k, every body
+    g, R, b, prob = tiny_problem(seed=8)
+    tvp = suppcg.TVParams(K=2, a=0.5, gamma=40.0)
+    res = suppcg.suppcg(prob, np.zeros(g.n), tvp, n_iter=12)
+    prev = 0
+    for k in range(12):
+        assert res.trace["ell"][k] - prev == sum(res.trace["trials"][k])
+        prev = res.trace["ell"][k]
+    assert max(max(t) for t in res.trace["trials"]) > 1    # rejections happened
