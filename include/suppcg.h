@@ -103,13 +103,32 @@ typedef struct {
 } sp_precond;
 
 /* Solver controls.  eps: Algorithm 3's termination level (eps <= 0 disables
- * the test and runs exactly max_iter loop bodies).  flags: SP_FLAG_REPLAY makes
+ * the test and runs exactly max_iter loop bodies).  The test of step 10,
+ * f(x_{k-1/2}) <= eps, is taken at the top of each loop body, so the run that
+ * stops has completed its last U_PCG step and x_last holds x_k.
+ * flags: SP_FLAG_REPLAY makes
  * each S_TV inner step accept exactly after replay_trials[k*K + i] trials
  * (host array, max_iter*K entries; a value > max_trials means "no trial
  * accepted") instead of testing TV -- used to separate arithmetic differences
  * from control-flow differences. SP_FLAG_GRAPH captures one loop body in a
- * HIP graph and replays it. */
-enum { SP_FLAG_REPLAY = 1u, SP_FLAG_GRAPH = 2u, SP_FLAG_AUTOTUNE = 4u };
+ * HIP graph and replays it.
+ * SP_FLAG_RESUME (sp_suppcg_solve only): skip steps 1-9 and run max_iter more
+ * loop bodies from the state the context holds -- left by the previous solve
+ * on it, or put there by sp_state_load -- with x0 ignored.  The geometry, the
+ * S_TV parameters and the preconditioner must be those the state was made
+ * with (else SP_ERR_ARG); b must be the same data.  A run that stopped on the
+ * eps test continues (the test is taken again with the new eps); one that
+ * stopped on a breakdown or a non-finite value returns that status at once.
+ * A run of N bodies and one of N1 followed by a resumed run of N - N1 give
+ * bitwise the same images and scalars.
+ * SP_FLAG_ASYNC: the call enqueues the whole run and returns SP_OK without
+ * waiting; k_out is then a DEVICE int32 pointer (batched: int32[n]) that
+ * receives k when the run completes, trace must be NULL, and loop bodies
+ * after a stop are enqueued and do nothing.  sp_solve_status gives the
+ * statuses once the work is done.  The buffers passed in must stay valid
+ * until then. */
+enum { SP_FLAG_REPLAY = 1u, SP_FLAG_GRAPH = 2u, SP_FLAG_AUTOTUNE = 4u, SP_FLAG_RESUME = 8u,
+       SP_FLAG_ASYNC = 16u };
 typedef struct {
     double eps;
     int32_t max_iter;
@@ -140,6 +159,7 @@ typedef struct {
      * Rows of bodies that did not run are left untouched. */
     float* g_snap;
     int32_t g_snap_count;
+    int32_t bodies;   /* out: loop bodies this call ran (entries written) */
 } sp_trace;
 
 /* ---- context ------------------------------------------------------------ */
@@ -170,6 +190,14 @@ int sp_backproject(sp_ctx* ctx, const sp_geometry* g, const float* y, float* x);
  * criterion f(x) = ||Rx - b||^2 of Section 2.  r may equal NULL. */
 int sp_residual(sp_ctx* ctx, const sp_geometry* g, const float* x, const float* b,
                 float* r, double* f);
+
+/* grad = A x - y = R^T (R x - b), the gradient step 1 of Algorithm 2 forms
+ * (A = R^T R, y = R^T b, Section 3.3), computed as the solvers compute it:
+ * the residual R x - b is kept in float64 between the two operators.
+ * *f = ||R x - b||^2 (float64 device scalar, nullable).
+ * x: [rows][cols], b: [n_angles][n_bins], grad: [rows][cols] (device). */
+int sp_gradient(sp_ctx* ctx, const sp_geometry* g, const float* x, const float* b, float* grad,
+                double* f);
 
 /* z = M g with the preconditioner of Section 3.2 (see sp_precond).
  * g, z: [rows][cols] (device); g and z may alias. */
@@ -203,6 +231,30 @@ int sp_suppcg_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const flo
                     const sp_tv_params* tv, const sp_precond* pc, const sp_solve_params* sp,
                     float* x_out, float* x_last, int32_t* k_out, sp_trace* trace);
 
+/* ---- checkpoint / resume ------------------------------------------------------
+ * The state Algorithm 3 carries from one loop body to the next: x_k,
+ * x_{k-1/2}, p_{k-1} (float64), h_{k-1} (float32) and the scalars p^T h, l_k,
+ * k, f(x_{k-1/2}), f(x_0), the stop status and, for a learned preconditioner,
+ * whether it has been replaced by the Fourier one, together with the geometry,
+ * the S_TV parameters and the preconditioner parameters.  The learned network's
+ * weights are not part of it.
+ * sp_state_save copies the state the context holds after a single-slice solve
+ * (or an sp_state_load) to host memory: with host_blob == NULL it only writes
+ * the size needed to *bytes; else *bytes gives the blob's capacity and
+ * receives the size written (SP_ERR_ARG if too small or if the context holds
+ * no state).  It waits for the context's stream.
+ * sp_state_load puts a saved blob into a context (of this library version, on
+ * any device) so that a solve with SP_FLAG_RESUME continues from it; it
+ * validates the blob and the geometry (SP_ERR_ARG otherwise). */
+int sp_state_save(sp_ctx* ctx, void* host_blob, int64_t* bytes);
+int sp_state_load(sp_ctx* ctx, const void* host_blob, int64_t bytes);
+
+/* k and status of the slices of the last solve on ctx (count = 1 after
+ * sp_suppcg_solve, n after the batched solve): waits for the context's stream;
+ * status is SP_MAXITER, SP_CONVERGED, SP_BREAKDOWN_CONVERGED,
+ * SP_TRIALS_EXHAUSTED or SP_ERR_NONFINITE.  k and status are host arrays. */
+int sp_solve_status(sp_ctx* ctx, int32_t count, int32_t* k, int32_t* status);
+
 /* ---- batched solver -----------------------------------------------------------
  * Algorithm 3 on n independent slices of any mix of geometries, advanced in
  * lockstep: every stage of the loop body is ONE launch whose workgroups walk a
@@ -216,10 +268,11 @@ int sp_suppcg_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const flo
  *     zero image) and x_last (NULL, or n entries) likewise.
  *   pc: SP_PRECOND_RAMP or SP_PRECOND_NONE, shared by all slices.
  *   sp->flags: SP_FLAG_GRAPH captures one loop body in a HIP graph and replays
- *     it; SP_FLAG_AUTOTUNE times the launch shapes of the heavy stages (item
+ *     it; SP_FLAG_ASYNC as for sp_suppcg_solve (k_out device int32[n]);
+ *     SP_FLAG_AUTOTUNE times the launch shapes of the heavy stages (item
  *     order: slice-major or grouped by XCD; grid: one workgroup per item or a
  *     persistent 2/4/8 workgroups per CU) once per batch layout and keeps the
- *     fastest; SP_FLAG_REPLAY is not supported here.
+ *     fastest; SP_FLAG_REPLAY and SP_FLAG_RESUME are not supported here.
  *   k_out: host [n].  trace (nullable): host arrays [n][cap] and status[n].
  * Limits: 1 <= n <= 4096; each slice within the single-slice limits.
  * Returns SP_OK when every slice ended without error (per-slice SP_MAXITER /

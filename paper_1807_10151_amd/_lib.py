@@ -32,6 +32,8 @@ SP_PRECOND_LEARNED = 2
 SP_FLAG_REPLAY = 1
 SP_FLAG_GRAPH = 2
 SP_FLAG_AUTOTUNE = 4
+SP_FLAG_RESUME = 8
+SP_FLAG_ASYNC = 16
 
 SP_PROF_PROJECT = 0
 SP_PROF_BACKPROJECT = 1
@@ -72,7 +74,7 @@ class sp_trace(ctypes.Structure):
                 ("s_norm", POINTER(c_double)), ("ell", POINTER(c_int32)),
                 ("trials", POINTER(c_int32)), ("cap", c_int32),
                 ("f0", c_double), ("alpha0", c_double), ("fallbacks", c_int32),
-                ("g_snap", c_void_p), ("g_snap_count", c_int32)]
+                ("g_snap", c_void_p), ("g_snap_count", c_int32), ("bodies", c_int32)]
 
 
 class sp_batch_trace(ctypes.Structure):
@@ -89,6 +91,7 @@ _SIGS = {
     "sp_project": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
     "sp_backproject": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
     "sp_residual": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sp_gradient": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, c_void_p, c_void_p]),
     "sp_precond_apply": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(sp_precond), c_void_p, c_void_p]),
     "sp_tv": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
     "sp_tv_grad": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, c_void_p]),
@@ -102,6 +105,9 @@ _SIGS = {
                                         POINTER(sp_solve_params), POINTER(c_void_p), POINTER(c_void_p),
                                         POINTER(c_int32), POINTER(sp_batch_trace)]),
     "sp_batch_tuning": (c_int, [c_void_p, POINTER(c_int32), c_int32]),
+    "sp_state_save": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_int64)]),
+    "sp_state_load": (c_int, [c_void_p, c_void_p, ctypes.c_int64]),
+    "sp_solve_status": (c_int, [c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32)]),
     "sp_lp_create": (c_int, [c_void_p, c_int32, c_int32, POINTER(c_void_p)]),
     "sp_lp_destroy": (c_int, [c_void_p]),
     "sp_lp_num_params": (ctypes.c_int64, [c_void_p]),

@@ -157,6 +157,21 @@ def sp_residual(g: Geometry, x: torch.Tensor, b: torch.Tensor, ctx: Context | No
     return r, f
 
 
+def sp_gradient(g: Geometry, x: torch.Tensor, b: torch.Tensor, grad: torch.Tensor | None = None,
+                ctx: Context | None = None):
+    """(grad, f): grad = R^T (R x - b) with the residual kept in float64, and
+    f = ||R x - b||^2 (float64, 0-d CUDA tensor)."""
+    ctx = ctx or context(x.device.index or 0)
+    grad = _out(grad, (g.rows, g.cols), ctx.device)
+    f = torch.empty((), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    ctx._stream()
+    gc = g.c()
+    ctx._check(ctx.lib.sp_gradient(ctx.h, ctypes.byref(gc), _dev(x, g.n, "x", ctx.device),
+                                   _dev(b, g.m, "b", ctx.device), _dev(grad, g.n, "grad", ctx.device),
+                                   ctypes.c_void_p(f.data_ptr())))
+    return grad, f
+
+
 def sp_suppcg_solve_batched(geoms, bs, x0s=None, *, K: int = 1, a: float = 0.5, gamma: float = 0.5,
                             max_trials: int = 100, precond="ramp", mu: float = 1e-5,
                             rho: float = 0.8, max_iter: int = 20, eps: float = 0.0,
@@ -206,6 +221,65 @@ def sp_suppcg_solve_batched(geoms, bs, x0s=None, *, K: int = 1, a: float = 0.5, 
         tr_i = {"f_half": f_half[i, :done], "tv_half": tv_half[i, :done], "ell": ell[i, :done]} if trace else {}
         out.append(SolveResult(int(k_out[i]), x_half[i], x_last[i], int(status[i]), tr_i))
     return out
+
+
+def sp_suppcg_solve_async(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None, *,
+                          K: int = 1, a: float = 0.5, gamma: float = 0.5, max_trials: int = 100,
+                          precond="ramp", mu: float = 1e-5, rho: float = 0.8, max_iter: int = 20,
+                          eps: float = 0.0, graph: bool = True, resume: bool = False,
+                          x_half: torch.Tensor | None = None, x_last: torch.Tensor | None = None,
+                          net: "LearnedPrecond | None" = None, ctx: Context | None = None):
+    """SP_FLAG_ASYNC solve: enqueues the run and returns at once.  Returns
+    (k, x_half, x_last) with k an int32 CUDA tensor written when the run
+    completes; sp_solve_status() gives the status afterwards."""
+    ctx = ctx or context(b.device.index or 0)
+    dev = ctx.device
+    x_half = _out(x_half, (g.rows, g.cols), dev)
+    x_last = _out(x_last, (g.rows, g.cols), dev)
+    k = torch.zeros((), dtype=torch.int32, device=f"cuda:{dev}")
+    gc = g.c()
+    tvp = L.sp_tv_params(K, a, gamma, max_trials)
+    pc = _precond(precond, mu, rho, net)
+    flags = L.SP_FLAG_ASYNC | (L.SP_FLAG_GRAPH if graph else 0) | (L.SP_FLAG_RESUME if resume else 0)
+    sp = L.sp_solve_params(eps, max_iter, flags, None)
+    ctx._stream()
+    rc = ctx.lib.sp_suppcg_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
+                                 _dev(x0, g.n, "x0", dev) if x0 is not None else None,
+                                 ctypes.byref(tvp), ctypes.byref(pc), ctypes.byref(sp),
+                                 _dev(x_half, g.n, "x_half", dev), _dev(x_last, g.n, "x_last", dev),
+                                 ctypes.cast(ctypes.c_void_p(k.data_ptr()), ctypes.POINTER(ctypes.c_int32)),
+                                 None)
+    ctx._check(rc)
+    return k, x_half, x_last
+
+
+def sp_solve_status(count: int = 1, ctx: Context | None = None):
+    """(k list, status list) of the slices of the last solve (waits for it)."""
+    ctx = ctx or context(0)
+    k = (ctypes.c_int32 * count)()
+    st = (ctypes.c_int32 * count)()
+    ctx._stream()
+    ctx._check(ctx.lib.sp_solve_status(ctx.h, count, k, st))
+    return list(k), list(st)
+
+
+def sp_state_save(ctx: Context | None = None) -> bytes:
+    """Algorithm 3's carried state of the context's last single-slice solve."""
+    ctx = ctx or context(0)
+    ctx._stream()
+    size = ctypes.c_int64(0)
+    ctx._check(ctx.lib.sp_state_save(ctx.h, None, ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(size.value)
+    ctx._check(ctx.lib.sp_state_save(ctx.h, buf, ctypes.byref(size)))
+    return buf.raw[:size.value]
+
+
+def sp_state_load(blob: bytes, ctx: Context | None = None):
+    """Puts a saved state into the context (the next solve may resume from it)."""
+    ctx = ctx or context(0)
+    ctx._stream()
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    ctx._check(ctx.lib.sp_state_load(ctx.h, buf, len(blob)))
 
 
 def batch_tuning(ctx: Context | None = None) -> dict:
@@ -375,11 +449,13 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
                     eps: float = 0.0, graph: bool = False, replay=None, trace: bool = True,
                     x_half: torch.Tensor | None = None, x_last: torch.Tensor | None = None,
                     net: "LearnedPrecond | None" = None, g_snap: torch.Tensor | None = None,
-                    ctx: Context | None = None) -> SolveResult:
+                    resume: bool = False, ctx: Context | None = None) -> SolveResult:
     """Algorithm 3 (SupPCG); K = 0 gives plain PCG, precond="none" gives CG.
 
     g_snap (optional, float32 device tensor [count, rows, cols]): receives the
-    gradient g_{k+1/2} that loop body k hands to the preconditioner."""
+    gradient g_{k+1/2} that loop body k hands to the preconditioner.
+    resume: continue for max_iter more loop bodies from the state the context
+    holds (the previous solve, or state_load); x0 is ignored."""
     ctx = ctx or context(b.device.index or 0)
     dev = ctx.device
     snap_count = 0
@@ -393,7 +469,7 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
     gc = g.c()
     tvp = L.sp_tv_params(K, a, gamma, max_trials)
     pc = _precond(precond, mu, rho, net)
-    flags = (L.SP_FLAG_GRAPH if graph else 0)
+    flags = (L.SP_FLAG_GRAPH if graph else 0) | (L.SP_FLAG_RESUME if resume else 0)
     rep_arr = None
     if replay is not None:
         flags |= L.SP_FLAG_REPLAY
@@ -415,7 +491,7 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
         tr = L.sp_trace(dp(arrs["f_half"]), dp(arrs["tv_half"]), dp(arrs["alpha"]), dp(arrs["beta"]),
                         dp(arrs["s_norm"]), ip(arrs["ell"]), ip(arrs["trials"]), cap, 0.0, 0.0, 0,
                         ctypes.c_void_p(g_snap.data_ptr()) if g_snap is not None else None,
-                        snap_count)
+                        snap_count, 0)
     k_out = ctypes.c_int32(0)
     ctx._stream()
     rc = ctx.lib.sp_suppcg_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
@@ -426,7 +502,7 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
     ctx._check(rc, ok=(L.SP_MAXITER, L.SP_CONVERGED, L.SP_BREAKDOWN_CONVERGED, L.SP_TRIALS_EXHAUSTED))
     out = {}
     if tr is not None:
-        done = min(max(k_out.value - 1, 0), cap)
+        done = min(tr.bodies, cap)
         out = {key: v[:done] if key != "trials" else v[:done * max(K, 1)].reshape(done, max(K, 1))
                for key, v in arrs.items()}
         out["f0"] = tr.f0

@@ -58,13 +58,33 @@ struct sp_ctx {
     int fftP = 0;
     DevBuf tw, S;
 
-    // solver vectors and scratch
+    // solver vectors and scratch.  vx, vxh, vp, vh and scal carry Algorithm 3's
+    // state from one loop body to the next and survive the call (checkpoint /
+    // resume); the standalone operators use ox, oxh and oscal instead.
     DevBuf vx, vxh, vp;                   // float64 x_k, x_{k+1/2}, p
     DevBuf vh, vg, vz, vtb, vtmp;
+    DevBuf ox, oxh, oscal;                // sp_tv, sp_tv_grad, sp_tv_perturb
     DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc;
     DevBuf scal, trace_d, replay_d, trials_tmp;
     Scalars sc_h{};
     hipStream_t own = nullptr;   // capture stream used when the caller's stream is null
+    hipEvent_t own_ev[2] = {nullptr, nullptr};   // orders `own` against the null stream (SP_FLAG_ASYNC)
+
+    // Algorithm 3's state left by the last single-slice solve (or sp_state_load):
+    // valid while `ok`, with the parameters it was produced with.
+    struct SolverState {
+        bool ok = false;
+        sp_geometry geom{};
+        int32_t K = 0, max_trials = 0, kind = 0;
+        double a = 0.0, gamma = 0.0, mu = 0.0, rho = 0.0;
+    } st;
+    // The last solve, for sp_solve_status: 0 none, 1 single-slice, 2 batched
+    // (count slices); its eps; a graph whose launches may still be in flight
+    // (SP_FLAG_ASYNC), destroyed once the stream has drained.
+    int last_kind = 0, last_count = 0;
+    double last_eps = 0.0;
+    hipGraph_t pend_graph = nullptr;
+    hipGraphExec_t pend_exec = nullptr;
     BatchState* batch = nullptr;
     int n_cu = 0;
 
@@ -403,15 +423,44 @@ int ensure_partials(sp_ctx* c) {
     return SP_OK;
 }
 
-int upload_scalars(sp_ctx* c) {
-    HIP_TRY(c, hipMemcpyAsync(c->scal.ptr, &c->sc_h, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+int upload_scalars(sp_ctx* c, DevBuf& dst) {
+    HIP_TRY(c, hipMemcpyAsync(dst.ptr, &c->sc_h, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SP_OK;
+}
+
+// Scratch of the standalone TV operators (never the solver's state).
+int ensure_op_vectors(sp_ctx* c, size_t n) {
+    int rc;
+    if ((rc = ensure(c, c->ox, n * sizeof(double)))) return rc;
+    if ((rc = ensure(c, c->oxh, n * sizeof(double)))) return rc;
+    if ((rc = ensure(c, c->vtb, n * sizeof(float)))) return rc;
+    return ensure(c, c->oscal, sizeof(Scalars));
 }
 
 int check_launch(sp_ctx* c) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(c, SP_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return SP_OK;
+}
+
+// Status of a finished run from its scalars (Algorithm 3's outcome).
+int run_status(const Scalars& q, double eps) {
+    if (q.halt) return q.halt;
+    if (eps > 0.0 && !(q.f > eps)) return SP_CONVERGED;   // max_iter ended on the test
+    if (q.exhausted) return SP_TRIALS_EXHAUSTED;
+    return SP_MAXITER;
+}
+
+// Waits for and releases the graph an asynchronous solve left in flight.
+int drain_pending(sp_ctx* c) {
+    if (!c->pend_exec && !c->pend_graph) return SP_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->own) HIP_TRY(c, hipStreamSynchronize(c->own));
+    if (c->pend_exec) (void)hipGraphExecDestroy(c->pend_exec);
+    if (c->pend_graph) (void)hipGraphDestroy(c->pend_graph);
+    c->pend_exec = nullptr;
+    c->pend_graph = nullptr;
     return SP_OK;
 }
 
@@ -444,11 +493,10 @@ struct ProfScope {
 // One S_TV call (Algorithm 1) from x into xh, K inner steps.  With snorm the
 // partials of ||xh - x||^2 go to part_s, and unless ride_snorm (a later
 // kernel carries the step, see ScalarRide) the step norm is traced here.
-void enqueue_stv(sp_ctx* c, int K, const double* x, double* xh, bool snorm, TraceDev tr,
-                 int32_t* trials_out, bool ride_snorm = false) {
+void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, bool snorm,
+                 TraceDev tr, int32_t* trials_out, bool ride_snorm = false) {
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
-    Scalars* sc = dptr<Scalars>(c->scal);
     const int* halt = &sc->halt;
     const int nb = tv_blocks(G.rows, G.cols);
     ProfScope ps(c, SP_PROF_TV);
@@ -922,12 +970,15 @@ int sp_ctx_destroy(sp_ctx* c) {
     if (!c) return SP_ERR_ARG;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh,
+    (void)drain_pending(c);
+    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
                       &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
         release(*b);
     if (c->own) (void)hipStreamDestroy(c->own);
+    for (hipEvent_t e : c->own_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->batch) {
         for (DevBuf* b : {&c->batch->arena, &c->batch->sl, &c->batch->items, &c->batch->scal,
@@ -1174,6 +1225,26 @@ int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b,
     return check_launch(c);
 }
 
+int sp_gradient(sp_ctx* c, const sp_geometry* g, const float* x, const float* b, float* grad,
+                double* f) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !b || !grad) return fail(c, SP_ERR_ARG, "x, b and grad must be device pointers");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    const GeomDev& G = c->G;
+    // the solvers' path: the residual stays float64 between R and R^T
+    launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
+    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp), b,
+                   nullptr, 0, nullptr, dptr<double>(c->ypd), dptr<double>(c->part_f),
+                   dptr<double>(c->seg), dptr<int>(c->pord), nullptr);
+    launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->ypd), dptr<double>(c->skp),
+                       grad, nullptr, nullptr, nullptr);
+    if (f) launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
+    return check_launch(c);
+}
+
 int sp_precond_apply(sp_ctx* c, const sp_geometry* g, const sp_precond* pc, const float* gin, float* z) {
     if (!c) return SP_ERR_ARG;
     if (!gin || !z) return fail(c, SP_ERR_ARG, "g and z must be device pointers");
@@ -1194,9 +1265,9 @@ int sp_tv(sp_ctx* c, const sp_geometry* g, const float* x, double* tv) {
     int rc = setup_geometry(c, g);
     if (rc) return rc;
     if ((rc = ensure_partials(c))) return rc;
-    if ((rc = ensure_vectors(c, (size_t)g->rows * g->cols))) return rc;
-    launch_widen(c->stream, g->rows * g->cols, x, dptr<double>(c->vx));
-    launch_tv_value(c->stream, g->rows, g->cols, dptr<double>(c->vx), dptr<double>(c->part_g), nullptr);
+    if ((rc = ensure_op_vectors(c, (size_t)g->rows * g->cols))) return rc;
+    launch_widen(c->stream, g->rows * g->cols, x, dptr<double>(c->ox));
+    launch_tv_value(c->stream, g->rows, g->cols, dptr<double>(c->ox), dptr<double>(c->part_g), nullptr);
     launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), tv);
     return check_launch(c);
 }
@@ -1208,9 +1279,9 @@ int sp_tv_grad(sp_ctx* c, const sp_geometry* g, const float* x, float* tbar, dou
     int rc = setup_geometry(c, g);
     if (rc) return rc;
     if ((rc = ensure_partials(c))) return rc;
-    if ((rc = ensure_vectors(c, (size_t)g->rows * g->cols))) return rc;
-    launch_widen(c->stream, g->rows * g->cols, x, dptr<double>(c->vx));
-    launch_tv_grad(c->stream, g->rows, g->cols, dptr<double>(c->vx), tbar, dptr<double>(c->part_g), nullptr);
+    if ((rc = ensure_op_vectors(c, (size_t)g->rows * g->cols))) return rc;
+    launch_widen(c->stream, g->rows * g->cols, x, dptr<double>(c->ox));
+    launch_tv_grad(c->stream, g->rows, g->cols, dptr<double>(c->ox), tbar, dptr<double>(c->part_g), nullptr);
     if (norm2) launch_reduce(c->stream, dptr<double>(c->part_g), tv_blocks(g->rows, g->cols), norm2);
     return check_launch(c);
 }
@@ -1224,7 +1295,7 @@ int sp_tv_perturb(sp_ctx* c, const sp_geometry* g, const sp_tv_params* p, const 
     if (rc) return rc;
     if ((rc = check_tv(c, p))) return rc;
     const size_t n = (size_t)g->rows * g->cols;
-    if ((rc = ensure_vectors(c, n))) return rc;
+    if ((rc = ensure_op_vectors(c, n))) return rc;
     if ((rc = ensure_partials(c))) return rc;
     Scalars& s = c->sc_h;
     s = Scalars{};
@@ -1232,17 +1303,17 @@ int sp_tv_perturb(sp_ctx* c, const sp_geometry* g, const sp_tv_params* p, const 
     s.gamma = p->gamma;
     s.K = p->K;
     s.max_trials = p->max_trials > 0 ? p->max_trials : 100;
-    if ((rc = upload_scalars(c))) return rc;
-    Scalars* sc = dptr<Scalars>(c->scal);
+    if ((rc = upload_scalars(c, c->oscal))) return rc;
+    Scalars* sc = dptr<Scalars>(c->oscal);
     HIP_TRY(c, hipMemcpyAsync(&sc->ell, ell, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
     TraceDev tr{};
-    double* xd = dptr<double>(c->vx);
-    double* xhd = dptr<double>(c->vxh);
+    double* xd = dptr<double>(c->ox);
+    double* xhd = dptr<double>(c->oxh);
     launch_widen(c->stream, (int)n, x, xd);
     if (p->K == 0) {
         launch_copy(c->stream, (int)n, xd, xhd, nullptr);
     } else {
-        enqueue_stv(c, p->K, xd, xhd, false, tr, trials);
+        enqueue_stv(c, sc, p->K, xd, xhd, false, tr, trials);
     }
     launch_narrow(c->stream, (int)n, xhd, x_half);
     HIP_TRY(c, hipMemcpyAsync(ell, &sc->ell, sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
@@ -1262,32 +1333,58 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
                     float* x_out, float* x_last, int32_t* k_out, sp_trace* trace) {
     if (!c) return SP_ERR_ARG;
     if (!b || !x_out || !k_out || !sp) return fail(c, SP_ERR_ARG, "b, x_out, k_out and params are required");
+    const bool async = (sp->flags & SP_FLAG_ASYNC) != 0;
+    const bool resume = (sp->flags & SP_FLAG_RESUME) != 0;
+    if (async && trace) return fail(c, SP_ERR_ARG, "SP_FLAG_ASYNC returns no trace (trace must be NULL)");
     HIP_TRY(c, hipSetDevice(c->device));
     if ((sp->flags & SP_FLAG_GRAPH) && c->stream == nullptr && !c->prof) {
         // The null stream cannot be captured: run the whole solve on an owned
-        // stream, ordered after the caller's prior work (the call blocks anyway).
+        // stream, ordered after the caller's prior work and, for an
+        // asynchronous solve, with the null stream waiting on its end.
         if (!c->own) HIP_TRY(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
-        HIP_TRY(c, hipStreamSynchronize(nullptr));
+        if (!c->own_ev[0]) {
+            HIP_TRY(c, hipEventCreateWithFlags(&c->own_ev[0], hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->own_ev[1], hipEventDisableTiming));
+        }
+        HIP_TRY(c, hipEventRecord(c->own_ev[0], nullptr));
+        HIP_TRY(c, hipStreamWaitEvent(c->own, c->own_ev[0], 0));
         c->stream = c->own;
         int r = sp_suppcg_solve(c, g, b, x0, tv, pc, sp, x_out, x_last, k_out, trace);
-        (void)hipStreamSynchronize(c->own);
         c->stream = nullptr;
+        if (async) {
+            HIP_TRY(c, hipEventRecord(c->own_ev[1], c->own));
+            HIP_TRY(c, hipStreamWaitEvent(nullptr, c->own_ev[1], 0));
+        } else {
+            (void)hipStreamSynchronize(c->own);
+        }
         return r;
     }
-    int rc = setup_geometry(c, g);
+    int rc = drain_pending(c);
     if (rc) return rc;
+    if ((rc = setup_geometry(c, g))) return rc;
     if ((rc = check_precond(c, pc))) return rc;
     if ((rc = check_tv(c, tv))) return rc;
     if (sp->max_iter < 0) return fail(c, SP_ERR_ARG, "max_iter must be >= 0");
     if (!std::isfinite(sp->eps)) return fail(c, SP_ERR_ARG, "eps must be finite");
     const int K = (tv && tv->K > 0) ? tv->K : 0;
+    const int max_trials = K ? (tv->max_trials > 0 ? tv->max_trials : 100) : 0;
     const bool replay = (sp->flags & SP_FLAG_REPLAY) != 0;
     if (replay && !sp->replay_trials) return fail(c, SP_ERR_ARG, "SP_FLAG_REPLAY needs replay_trials");
+    if (resume) {
+        const sp_ctx::SolverState& S = c->st;
+        if (!S.ok) return fail(c, SP_ERR_ARG, "SP_FLAG_RESUME: the context holds no solver state");
+        if (!same_geom(S.geom, *g)) return fail(c, SP_ERR_ARG, "SP_FLAG_RESUME: geometry differs from the saved state");
+        if (S.K != K || (K && (S.a != tv->a || S.gamma != tv->gamma || S.max_trials != max_trials)))
+            return fail(c, SP_ERR_ARG, "SP_FLAG_RESUME: S_TV parameters differ from the saved state");
+        if (S.kind != pc->kind || (pc->kind != SP_PRECOND_NONE && (S.mu != pc->mu || S.rho != pc->rho)))
+            return fail(c, SP_ERR_ARG, "SP_FLAG_RESUME: preconditioner differs from the saved state");
+    }
+    c->st.ok = false;   // the buffers below are rewritten from here on
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
     if ((rc = ensure_vectors(c, n))) return rc;
     if ((rc = ensure_partials(c))) return rc;
-    if (pc->kind == SP_PRECOND_RAMP) {
+    if (pc->kind == SP_PRECOND_RAMP || pc->kind == SP_PRECOND_LEARNED) {
         FFTPlan F{};
         if ((rc = setup_fft(c, F))) return rc;
     }
@@ -1315,18 +1412,29 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         tr.replay = dptr<int32_t>(c->replay_d);
     }
     Scalars& s = c->sc_h;
-    s = Scalars{};
+    if (resume) {
+        // continue from the carried scalars (p^T h, l, k, f, ...): a new call
+        // counts its loop bodies from 0; a stop on the eps test is re-taken
+        // with this call's eps, a breakdown or non-finite stop is final
+        HIP_TRY(c, hipMemcpyAsync(&s, c->scal.ptr, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (s.halt == SP_CONVERGED) s.halt = 0;
+        s.iter = 0;
+        s.inner = 0;
+    } else {
+        s = Scalars{};
+        s.a = K ? tv->a : 0.5;
+        s.gamma = K ? tv->gamma : 0.0;
+        s.K = K;
+        s.max_trials = max_trials;
+        s.first = 1;
+        s.gate_learned = pc->kind == SP_PRECOND_LEARNED ? 1 : 0;
+        s.gate_ramp = 0;
+    }
     s.eps = sp->eps;
-    s.a = K ? tv->a : 0.5;
-    s.gamma = K ? tv->gamma : 0.0;
-    s.K = K;
-    s.max_trials = K ? (tv->max_trials > 0 ? tv->max_trials : 100) : 0;
     s.max_iter = sp->max_iter;
     s.replay = replay ? 1 : 0;
-    s.first = 1;
-    s.gate_learned = pc->kind == SP_PRECOND_LEARNED ? 1 : 0;
-    s.gate_ramp = 0;
-    if ((rc = upload_scalars(c))) return rc;
+    if ((rc = upload_scalars(c, c->scal))) return rc;
 
     hipStream_t st = c->stream;
     Scalars* sc = dptr<Scalars>(c->scal);
@@ -1351,28 +1459,30 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     double* pph = dptr<double>(c->part_ph);
     const int nf = project_blocks(G), nph = backproject_blocks(G), ngp = vec_blocks(n);
 
-    launch_widen(st, n, x0, xh);
-    launch_widen(st, n, x0, x);
-    // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
-    // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
-    launch_prep(st, G, xh, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, pord, halt);
-    launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
-    launch_backproject(st, G, ang, rpd, skp, gv, nullptr, nullptr, halt);
-    int nzh = 0;
-    if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
-    launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
-    launch_update_p(st, n, z, p, gv, sc, pgp, halt);
-    launch_prep(st, G, p, xp, xTp, halt);
-    launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, pord, halt);
-    launch_backproject(st, G, ang, rp, skp, h, p, pph, halt);
-    launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
-    launch_update_x(st, n, xh, p, x, sc, halt);
-    if ((rc = check_launch(c))) return rc;
+    if (!resume) {
+        launch_widen(st, n, x0, xh);
+        launch_widen(st, n, x0, x);
+        // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
+        // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
+        launch_prep(st, G, xh, xp, xTp, halt);
+        launch_project(st, G, ang, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, pord, halt);
+        launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
+        launch_backproject(st, G, ang, rpd, skp, gv, nullptr, nullptr, halt);
+        int nzh = 0;
+        if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
+        launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
+        launch_update_p(st, n, z, p, gv, sc, pgp, halt);
+        launch_prep(st, G, p, xp, xTp, halt);
+        launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, pord, halt);
+        launch_backproject(st, G, ang, rp, skp, h, p, pph, halt);
+        launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
+        launch_update_x(st, n, xh, p, x, sc, halt);
+        if ((rc = check_launch(c))) return rc;
+    }
 
     float* snap = (trace && trace->g_snap && trace->g_snap_count > 0) ? trace->g_snap : nullptr;
     const int snap_count = snap ? trace->g_snap_count : 0;
-    // One loop body (steps 11-14); every launch reads device state only, so
+    // One loop body (steps 10-14); every launch reads device state only, so
     // the body can be replayed from a captured graph.
     // r = R x - b goes to the float64 sinogram rpd, R p to the float32 rp
     auto project = [&](const float* bb, double* parts) {
@@ -1394,10 +1504,13 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     ride_f.nf = nf;
     ride_f.ps = K > 0 ? dptr<double>(c->part_s) : nullptr;
     ride_f.ns = tv_blocks(G.rows, G.cols);
+    const bool eps_test = sp->eps > 0.0;
     auto body = [&]() -> int {
         ProfScope ps(c, SP_PROF_ITERATION);
+        // step 10: while f(x_{k-1/2}) > eps (the test of the previous body's f)
+        if (eps_test) launch_scalar(st, OP_EPS, sc, tr, nullptr, 0, nullptr, 0);
         if (K > 0) {
-            enqueue_stv(c, K, x, xh, true, tr, nullptr, true);      // S_TV -> x_{k+1/2}
+            enqueue_stv(c, sc, K, x, xh, true, tr, nullptr, true);  // S_TV -> x_{k+1/2}
         } else {
             launch_copy(st, n, x, xh, halt);
         }
@@ -1417,7 +1530,9 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         return check_launch(c);
     };
 
-    const bool poll = sp->eps > 0.0;
+    // an asynchronous solve does not wait for the halt flag: bodies after a
+    // stop are enqueued and do nothing
+    const bool poll = eps_test && !async;
     if ((sp->flags & SP_FLAG_GRAPH) && sp->max_iter > 0 && !c->prof) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
@@ -1438,6 +1553,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         for (int it = 0; it < sp->max_iter; ++it) {
             hipError_t el = hipGraphLaunch(exec, st);
             if (el != hipSuccess) {
+                (void)hipStreamSynchronize(st);
                 (void)hipGraphExecDestroy(exec);
                 (void)hipGraphDestroy(graph);
                 return fail(c, SP_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(el));
@@ -1452,10 +1568,15 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
                 if (hh) break;
             }
         }
-        const hipError_t es = hipStreamSynchronize(st);
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        if (es != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+        if (async) {
+            c->pend_graph = graph;   // released once the stream has drained
+            c->pend_exec = exec;
+        } else {
+            const hipError_t es = hipStreamSynchronize(st);
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            if (es != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+        }
     } else {
         int32_t hh = 0;
         for (int it = 0; it < sp->max_iter; ++it) {
@@ -1467,13 +1588,34 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
             }
         }
     }
+    auto keep_state = [&]() {
+        sp_ctx::SolverState& S = c->st;
+        S.ok = true;
+        S.geom = *g;
+        S.K = K;
+        S.a = K ? tv->a : 0.0;
+        S.gamma = K ? tv->gamma : 0.0;
+        S.max_trials = max_trials;
+        S.kind = pc->kind;
+        S.mu = pc->mu;
+        S.rho = pc->rho;
+        c->last_kind = 1;
+        c->last_count = 1;
+        c->last_eps = sp->eps;
+    };
+    if (async) {
+        launch_finish(st, n, xh, x, sc, k_out);
+        launch_narrow(st, n, xh, x_out);
+        if (x_last) launch_narrow(st, n, x, x_last);
+        if ((rc = check_launch(c))) return rc;
+        keep_state();
+        return SP_OK;
+    }
     Scalars out{};
     HIP_TRY(c, hipMemcpyAsync(&out, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     *k_out = out.k;
-    int status = SP_MAXITER;
-    if (out.halt) status = out.halt;
-    else if (out.exhausted) status = SP_TRIALS_EXHAUSTED;
+    const int status = run_status(out, sp->eps);
     if (out.halt == SP_BREAKDOWN_CONVERGED && out.k > 1) {
         // the step could not be formed: x_k = x_{k-1/2}
         launch_copy(st, n, xh, x, nullptr);
@@ -1505,9 +1647,130 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         trace->f0 = out.f0;
         trace->alpha0 = out.alpha0;
         trace->fallbacks = out.fallbacks > 0 ? 1 : 0;
+        trace->bodies = out.iter;
     }
+    keep_state();
     if (out.halt == SP_ERR_NONFINITE) return fail(c, SP_ERR_NONFINITE, "non-finite value in a CG scalar");
     return status;
+}
+
+// ---- checkpoint / resume -------------------------------------------------------
+
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t version, scalars_bytes;
+    sp_geometry geom;
+    int32_t K, max_trials, kind, pad_;
+    double a, gamma, mu, rho;
+    int64_t n;
+    Scalars sc;
+};
+constexpr char STATE_MAGIC[8] = {'S', 'P', 'S', 'T', 'A', 'T', 'E', '1'};
+
+int64_t state_bytes(int64_t n) { return (int64_t)sizeof(StateHeader) + n * (3 * 8 + 4); }
+}  // namespace
+
+int sp_state_save(sp_ctx* c, void* host_blob, int64_t* bytes) {
+    if (!c) return SP_ERR_ARG;
+    if (!bytes) return fail(c, SP_ERR_ARG, "sp_state_save: bytes is required");
+    if (!c->st.ok) return fail(c, SP_ERR_ARG, "sp_state_save: the context holds no solver state");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const sp_ctx::SolverState& S = c->st;
+    const int64_t n = (int64_t)S.geom.rows * S.geom.cols;
+    const int64_t need = state_bytes(n);
+    if (!host_blob) {
+        *bytes = need;
+        return SP_OK;
+    }
+    if (*bytes < need) return fail(c, SP_ERR_ARG, "sp_state_save: the blob needs %lld bytes", (long long)need);
+    int rc = drain_pending(c);
+    if (rc) return rc;
+    StateHeader hd{};
+    std::memcpy(hd.magic, STATE_MAGIC, 8);
+    hd.version = 1;
+    hd.scalars_bytes = (int32_t)sizeof(Scalars);
+    hd.geom = S.geom;
+    hd.K = S.K;
+    hd.max_trials = S.max_trials;
+    hd.kind = S.kind;
+    hd.a = S.a;
+    hd.gamma = S.gamma;
+    hd.mu = S.mu;
+    hd.rho = S.rho;
+    hd.n = n;
+    char* out = static_cast<char*>(host_blob);
+    HIP_TRY(c, hipMemcpyAsync(&hd.sc, c->scal.ptr, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    char* v = out + sizeof(StateHeader);
+    HIP_TRY(c, hipMemcpyAsync(v, c->vx.ptr, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(v + n * 8, c->vxh.ptr, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(v + 2 * n * 8, c->vp.ptr, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(v + 3 * n * 8, c->vh.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memcpy(out, &hd, sizeof hd);
+    *bytes = need;
+    return SP_OK;
+}
+
+int sp_state_load(sp_ctx* c, const void* host_blob, int64_t bytes) {
+    if (!c) return SP_ERR_ARG;
+    if (!host_blob || bytes < (int64_t)sizeof(StateHeader))
+        return fail(c, SP_ERR_ARG, "sp_state_load: blob too short");
+    StateHeader hd;
+    std::memcpy(&hd, host_blob, sizeof hd);
+    if (std::memcmp(hd.magic, STATE_MAGIC, 8) != 0 || hd.version != 1 ||
+        hd.scalars_bytes != (int32_t)sizeof(Scalars))
+        return fail(c, SP_ERR_ARG, "sp_state_load: not a state blob of this library version");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = drain_pending(c);
+    if (rc) return rc;
+    if ((rc = setup_geometry(c, &hd.geom))) return rc;
+    const int64_t n = (int64_t)hd.geom.rows * hd.geom.cols;
+    if (hd.n != n || bytes < state_bytes(n)) return fail(c, SP_ERR_ARG, "sp_state_load: blob size mismatch");
+    c->st.ok = false;
+    if ((rc = ensure_vectors(c, (size_t)n))) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    const char* v = static_cast<const char*>(host_blob) + sizeof(StateHeader);
+    c->sc_h = hd.sc;
+    HIP_TRY(c, hipMemcpyAsync(c->scal.ptr, &c->sc_h, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->vx.ptr, v, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->vxh.ptr, v + n * 8, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->vp.ptr, v + 2 * n * 8, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->vh.ptr, v + 3 * n * 8, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    sp_ctx::SolverState& S = c->st;
+    S.geom = hd.geom;
+    S.K = hd.K;
+    S.max_trials = hd.max_trials;
+    S.kind = hd.kind;
+    S.a = hd.a;
+    S.gamma = hd.gamma;
+    S.mu = hd.mu;
+    S.rho = hd.rho;
+    S.ok = true;
+    c->last_kind = 0;
+    return SP_OK;
+}
+
+int sp_solve_status(sp_ctx* c, int32_t count, int32_t* k, int32_t* status) {
+    if (!c) return SP_ERR_ARG;
+    if (!k || !status) return fail(c, SP_ERR_ARG, "sp_solve_status: k and status are required");
+    if (c->last_kind == 0) return fail(c, SP_ERR_ARG, "sp_solve_status: no solve has run on this context");
+    if (count != c->last_count)
+        return fail(c, SP_ERR_ARG, "sp_solve_status: the last solve had %d slice(s)", c->last_count);
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = drain_pending(c);
+    if (rc) return rc;
+    std::vector<Scalars> q((size_t)count);
+    const void* src = c->last_kind == 1 ? c->scal.ptr : c->batch->scal.ptr;
+    HIP_TRY(c, hipMemcpyAsync(q.data(), src, sizeof(Scalars) * (size_t)count, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < count; ++i) {
+        k[i] = q[(size_t)i].k;
+        status[i] = run_status(q[(size_t)i], c->last_eps);
+    }
+    return SP_OK;
 }
 
 int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, const float* const* b,
@@ -1518,17 +1781,32 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     if (n < 1 || n > MAX_BATCH) return fail(c, SP_ERR_ARG, "n must be in [1, %d]", MAX_BATCH);
     if (!geoms || !b || !x_out || !k_out || !sp || !pc)
         return fail(c, SP_ERR_ARG, "geoms, b, x_out, k_out, params and preconditioner are required");
+    const bool async = (sp->flags & SP_FLAG_ASYNC) != 0;
+    if (async && trace) return fail(c, SP_ERR_ARG, "SP_FLAG_ASYNC returns no trace (trace must be NULL)");
+    if (sp->flags & SP_FLAG_RESUME)
+        return fail(c, SP_ERR_ARG, "SP_FLAG_RESUME is not supported by the batched solver");
     HIP_TRY(c, hipSetDevice(c->device));
     if ((sp->flags & SP_FLAG_GRAPH) && c->stream == nullptr) {
         if (!c->own) HIP_TRY(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
-        HIP_TRY(c, hipStreamSynchronize(nullptr));
+        if (!c->own_ev[0]) {
+            HIP_TRY(c, hipEventCreateWithFlags(&c->own_ev[0], hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->own_ev[1], hipEventDisableTiming));
+        }
+        HIP_TRY(c, hipEventRecord(c->own_ev[0], nullptr));
+        HIP_TRY(c, hipStreamWaitEvent(c->own, c->own_ev[0], 0));
         c->stream = c->own;
         int r = sp_suppcg_solve_batched(c, n, geoms, b, x0, tv, pc, sp, x_out, x_last, k_out, trace);
-        (void)hipStreamSynchronize(c->own);
         c->stream = nullptr;
+        if (async) {
+            HIP_TRY(c, hipEventRecord(c->own_ev[1], c->own));
+            HIP_TRY(c, hipStreamWaitEvent(nullptr, c->own_ev[1], 0));
+        } else {
+            (void)hipStreamSynchronize(c->own);
+        }
         return r;
     }
-    int rc;
+    int rc = drain_pending(c);
+    if (rc) return rc;
     for (int s = 0; s < n; ++s) {
         if ((rc = validate_geometry(c, &geoms[s]))) return fail(c, rc, "slice %d: %s", s, c->err.c_str());
         if (!b[s] || !x_out[s]) return fail(c, SP_ERR_ARG, "slice %d: b and x_out are required", s);
@@ -1599,8 +1877,10 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     launch_update_x_b(st, sl, tvec);
     if ((rc = check_launch(c))) return rc;
 
-    // loop body (steps 11-14)
+    // loop body (steps 10-14)
+    const bool eps_test = sp->eps > 0.0;
     auto body = [&]() {
+        if (eps_test) launch_scalar_b(st, sl, tone, OP_EPS);
         if (K > 0) {
             for (int i = 0; i < K; ++i) {
                 const int src = i == 0 ? BV_X : BV_XH;
@@ -1626,7 +1906,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         launch_scalar_b(st, sl, tone, OP_ALPHA);
         launch_update_x_b(st, sl, tvec);
     };
-    const bool poll = sp->eps > 0.0;
+    const bool poll = eps_test && !async;
     std::vector<Scalars> out(n);
     auto all_halted = [&]() -> int {
         HIP_TRY(c, hipMemcpyAsync(out.data(), B.scal.ptr, sizeof(Scalars) * (size_t)n,
@@ -1656,6 +1936,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         for (int it = 0; it < sp->max_iter; ++it) {
             hipError_t el = hipGraphLaunch(exec, st);
             if (el != hipSuccess) {
+                (void)hipStreamSynchronize(st);
                 (void)hipGraphExecDestroy(exec);
                 (void)hipGraphDestroy(graph);
                 return fail(c, SP_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(el));
@@ -1670,10 +1951,15 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
                 if (h) break;
             }
         }
-        const hipError_t es = hipStreamSynchronize(st);
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        if (es != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+        if (async) {
+            c->pend_graph = graph;   // released once the stream has drained
+            c->pend_exec = exec;
+        } else {
+            const hipError_t es = hipStreamSynchronize(st);
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            if (es != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+        }
     } else {
         for (int it = 0; it < sp->max_iter; ++it) {
             body();
@@ -1684,6 +1970,18 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
                 if (h) break;
             }
         }
+    }
+    c->last_kind = 2;
+    c->last_count = n;
+    c->last_eps = sp->eps;
+    if (async) {
+        for (int s = 0; s < n; ++s) {
+            const SliceDev& S = B.hs[s];
+            launch_finish(st, S.n, S.xh, S.x, dptr<Scalars>(B.scal) + s, k_out + s);
+            launch_narrow(st, S.n, S.xh, x_out[s]);
+            if (x_last && x_last[s]) launch_narrow(st, S.n, S.x, x_last[s]);
+        }
+        return check_launch(c);
     }
     HIP_TRY(c, hipMemcpyAsync(out.data(), B.scal.ptr, sizeof(Scalars) * (size_t)n, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
@@ -1696,9 +1994,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     for (int s = 0; s < n; ++s) {
         const Scalars& q = out[s];
         k_out[s] = q.k;
-        int status = SP_MAXITER;
-        if (q.halt) status = q.halt;
-        else if (q.exhausted) status = SP_TRIALS_EXHAUSTED;
+        const int status = run_status(q, sp->eps);
         if (q.halt == SP_BREAKDOWN_CONVERGED && q.k > 1)
             HIP_TRY(c, hipMemcpyAsync(B.hs[s].x, B.hs[s].xh, (size_t)B.hs[s].n * 8, hipMemcpyDeviceToDevice, st));
         launch_narrow(st, B.hs[s].n, B.hs[s].xh, x_out[s]);

@@ -124,8 +124,10 @@ void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, d
 
 // The alpha step (op OP_ALPHA or OP_ALPHA0) folded into the update: every
 // workgroup sums the p^T h and g^T p partials in the same order and takes the
-// same halt decision (breakdown, non-finite, eps test) that workgroup 0
-// commits; on a halt no workgroup updates x.
+// same halt decision (breakdown, non-finite) that workgroup 0 commits; on a
+// halt no workgroup updates x.  (Workgroups that start after workgroup 0 has
+// committed a halt return at the entry check; they would not have updated x
+// either.)
 __global__ __launch_bounds__(256) void k_update_x_alpha(int n, const double* __restrict__ xh,
                                                         const double* __restrict__ p,
                                                         double* __restrict__ x,
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void k_update_x_alpha(int n, const double* __r
     const double pth = reduce_partials(pph, nph, red);
     const double gp = reduce_partials(pgp, ngp, red);
     double alpha;
-    const int code = alpha_from(pth, gp, sc->eps, sc->f, alpha);
+    const int code = alpha_from(pth, gp, alpha);
     if (blockIdx.x == 0 && threadIdx.x == 0) scalar_commit(op, sc, tr, pth, gp);
     if (code) return;
     update_x_body(n, xh, p, x, alpha, blockIdx.x, gridDim.x);
@@ -199,6 +201,23 @@ __global__ __launch_bounds__(256) void k_snap(int n, const float* __restrict__ s
 
 void launch_snap(hipStream_t st, int n, const float* src, float* dst, int count, const Scalars* sc) {
     hipLaunchKernelGGL(k_snap, dim3(vec_blocks(n)), dim3(256), 0, st, n, src, dst, count, sc);
+}
+
+// End of a solve that does not return to the host in between: x_k = x_{k-1/2}
+// when the run stopped on a breakdown after the initial step (the step could
+// not be formed), and k to device memory (nullable).
+__global__ __launch_bounds__(256) void k_finish(int n, const double* __restrict__ xh,
+                                                double* __restrict__ x,
+                                                const Scalars* __restrict__ sc,
+                                                int32_t* __restrict__ k_out) {
+    if (sc->halt == SP_BREAKDOWN_CONVERGED && sc->k > 1)
+        for (int q = blockIdx.x * 256 + threadIdx.x; q < n; q += gridDim.x * 256) x[q] = xh[q];
+    if (k_out && blockIdx.x == 0 && threadIdx.x == 0) *k_out = sc->k;
+}
+
+void launch_finish(hipStream_t st, int n, const double* xh, double* x, const Scalars* sc,
+                   int32_t* k_out) {
+    hipLaunchKernelGGL(k_finish, dim3(vec_blocks(n)), dim3(256), 0, st, n, xh, x, sc, k_out);
 }
 
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int np,
@@ -301,6 +320,7 @@ __global__ __launch_bounds__(256) void kb_scalar(const SliceDev* __restrict__ sl
         case OP_ALPHA0:
         case OP_ALPHA: scalar_body(op, sc, tr, gmem(S.pph), S.nph, gmem(S.pgp), S.ngp); break;
         case OP_SNORM: scalar_body(op, sc, tr, gmem(S.pts), S.ntv, nullptr, 0); break;
+        case OP_EPS: scalar_body(op, sc, tr, nullptr, 0, nullptr, 0); break;
         default: break;
         }
     });

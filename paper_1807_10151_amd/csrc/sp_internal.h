@@ -242,6 +242,10 @@ void launch_widen(hipStream_t st, int n, const float* src, double* dst);
 void launch_narrow(hipStream_t st, int n, const double* src, float* dst);
 void launch_snap(hipStream_t st, int n, const float* src, float* dst, int count, const Scalars* sc);
 void launch_reduce(hipStream_t st, const double* partials, int np, double* out);
+// x = xh if the run stopped on a breakdown after its initial step; *k_out = k
+// (nullable): the end of a solve that does not return to the host.
+void launch_finish(hipStream_t st, int n, const double* xh, double* x, const Scalars* sc,
+                   int32_t* k_out);
 
 // learned.hip (learned preconditioner C^T diag(softplus(d)) C)
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
@@ -364,10 +368,11 @@ enum ScalarOp : int {
     OP_F = 0,        // f = sum(pa); trace / non-finite check
     OP_F0 = 1,       // f(x_0) at initialisation
     OP_BETA = 2,     // beta = sum(pa) / pth (0 on the first direction)
-    OP_ALPHA = 3,    // pth = sum(pa); alpha = -sum(pb) / pth; k++, iter++; eps test
+    OP_ALPHA = 3,    // pth = sum(pa); alpha = -sum(pb) / pth; k++, iter++
     OP_ALPHA0 = 4,   // same for the initial step (k = 1)
     OP_SNORM = 5,    // ||s_k|| into the trace
     OP_LCHECK = 6,   // learned M accepted iff g^T z = sum(pa) > 0 and finite; else fall back
+    OP_EPS = 7,      // Algorithm 3's loop test at the top of a body: halt if f <= eps (eps > 0)
 };
 void launch_scalar(hipStream_t st, int op, Scalars* sc, TraceDev tr, const double* pa, int na,
                    const double* pb, int nb);

@@ -20,10 +20,10 @@ __device__ __forceinline__ double beta_from(const Scalars* __restrict__ sc, doub
 }
 
 // Algorithm 2: alpha = -g^T p / p^T h.  Returns the halt code the step sets:
-// breakdown when p^T h = 0, non-finite values, or (eps > 0) the eps test of
-// Algorithm 3 on f(x_{k+1/2}); 0 to go on.
-__device__ __forceinline__ int alpha_from(double pth, double gp, double eps, double f,
-                                          double& alpha) {
+// breakdown when p^T h = 0, non-finite values; 0 to go on (x is then
+// updated).  Algorithm 3's termination test is not taken here: it belongs to
+// the top of the next loop body (OP_EPS), after x_{k+1} has been formed.
+__device__ __forceinline__ int alpha_from(double pth, double gp, double& alpha) {
     int code = 0;
     alpha = 0.0;
     if (pth == 0.0) {
@@ -32,7 +32,6 @@ __device__ __forceinline__ int alpha_from(double pth, double gp, double eps, dou
         alpha = -gp / pth;
         if (!finite(alpha) || !finite(pth)) code = SP_ERR_NONFINITE;
     }
-    if (code == 0 && eps > 0.0 && !(f > eps)) code = SP_CONVERGED;
     return code;
 }
 
@@ -62,7 +61,7 @@ __device__ __forceinline__ void scalar_commit(int op, Scalars* __restrict__ sc, 
     case OP_ALPHA0:
     case OP_ALPHA: {
         double alpha;
-        const int code = alpha_from(A, B, sc->eps, sc->f, alpha);
+        const int code = alpha_from(A, B, alpha);
         sc->alpha = alpha;
         sc->pth = A;
         if (op == OP_ALPHA0) {
@@ -80,6 +79,9 @@ __device__ __forceinline__ void scalar_commit(int op, Scalars* __restrict__ sc, 
     }
     case OP_SNORM:
         if (rec && tr.s_norm) tr.s_norm[it] = sqrt(A);
+        break;
+    case OP_EPS:   // Algorithm 3, step 10: stop when f(x_{k-1/2}) <= eps
+        if (sc->eps > 0.0 && !(sc->f > sc->eps)) sc->halt = SP_CONVERGED;
         break;
     case OP_LCHECK:
         if (sc->gate_learned && !(A > 0.0 && finite(A))) {

@@ -57,7 +57,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_1807_10151_amd import _lib
     structs = {"sp_geometry": _lib.sp_geometry, "sp_tv_params": _lib.sp_tv_params,
                "sp_precond": _lib.sp_precond, "sp_solve_params": _lib.sp_solve_params,
-               "sp_trace": _lib.sp_trace}
+               "sp_trace": _lib.sp_trace, "sp_batch_trace": _lib.sp_batch_trace}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "suppcg.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')

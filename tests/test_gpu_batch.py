@@ -85,7 +85,11 @@ def test_batch_pixels_per_lane_keep_results(sp):
     pixels per lane, so the small slice must still match its own solve bit for
     bit (and the large one, four pixels per lane on both sides, too)."""
     from synth import random_ellipses
-    geoms = [sp.Geometry(512, 640, 180, 900), sp.Geometry(64, 64, 90, 91)]
+    # plus two ragged slices: 522 x 520 (partial four-pixel tiles on the right
+    # and at the bottom, four pixels per lane alone too) and 37 x 53 (two
+    # alone, four in the batch)
+    geoms = [sp.Geometry(512, 640, 180, 900), sp.Geometry(64, 64, 90, 91),
+             sp.Geometry(522, 520, 90, 741), sp.Geometry(37, 53, 45, 61)]
     bs = []
     for i, g in enumerate(geoms):
         img, rng = random_ellipses(g.rows, g.cols, 5, 700 + i)
@@ -142,6 +146,27 @@ def test_batch_eps_termination(sp):
     for rb, rs in zip(got, want):
         assert_same(rb, rs)
     assert any(r.status_name == "converged" for r in got)
+
+
+def test_batch_eps_matches_oracle(sp):
+    # slice 0 = the 64 x 64 workload; its eps stop (at body 7, and at x_0)
+    # against the oracle, x_last included
+    og, img, b = workload_problem("small64")
+    R, _ = oproj.matrix(og)
+    prob = osup.Problem(R, b.astype(np.float64), (og.rows, og.cols), oracle_precond)
+    tvp = osup.TVParams(K, A, GAMMA)
+    free = osup.suppcg(prob, np.zeros(og.n), tvp, n_iter=10)
+    geoms, bs = mixed_batch(sp)
+    bs[0] = torch.from_numpy(np.ascontiguousarray(b, dtype=np.float32)).cuda()
+    for eps in (0.5 * (free.trace["f_half"][5] + free.trace["f_half"][6]), 2.0 * free.trace["f0"]):
+        ref = osup.suppcg(prob, np.zeros(og.n), tvp, n_iter=40, eps=eps)
+        got = sp.sp_suppcg_solve_batched(geoms, bs, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                                         max_iter=40, eps=eps)
+        assert ref.status == "converged" and got[0].status_name == "converged"
+        assert got[0].k == ref.k
+        assert rel_l2(got[0].x_last.cpu().numpy(), ref.x_last) <= 1e-3
+        if ref.k > 1:
+            assert rel_l2(got[0].x_half.cpu().numpy(), ref.x_half) <= 1e-3
 
 
 def test_batch_rejects_unsupported(sp):

@@ -111,6 +111,36 @@ def test_eps_termination_matches_oracle(sp, small, small_ref):
     assert ref.status == "converged" and res.status_name == "converged"
     assert res.k == ref.k
     assert rel_l2(res.x_half.cpu().numpy(), ref.x_half) <= 1e-3
+    # x_last is x_k: the last U_PCG step is completed before the loop test
+    assert rel_l2(res.x_last.cpu().numpy(), ref.x_last) <= 1e-3
+    # graph mode polls the halt flag; the result must be the same
+    resg = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                              max_iter=50, eps=eps, graph=True)
+    assert resg.k == res.k and torch.equal(resg.x_last, res.x_last)
+    assert torch.equal(resg.x_half, res.x_half)
+
+
+def test_eps_at_start_and_at_the_last_body(sp, small, small_ref):
+    og, img, b, R, prob = small
+    tvp = osup.TVParams(K, A, GAMMA)
+    # f(x_0) <= eps: steps 1-9 still form x_1; the loop never runs (k = 1,
+    # output x_{1/2} = x_0)
+    eps = 2.0 * small_ref.trace["f0"]
+    ref = osup.suppcg(prob, np.zeros(og.n), tvp, n_iter=50, eps=eps)
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                             max_iter=50, eps=eps)
+    assert ref.k == res.k == 1 and res.status_name == "converged"
+    assert not res.x_half.cpu().numpy().any()
+    assert rel_l2(res.x_last.cpu().numpy(), ref.x_last) <= 1e-4
+    # the test first holds after body 7 and max_iter = 7: converged, k = 8
+    f = small_ref.trace["f_half"]
+    eps = 0.5 * (f[5] + f[6])
+    ref = osup.suppcg(prob, np.zeros(og.n), tvp, n_iter=7, eps=eps)
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, K=K, a=A, gamma=GAMMA, mu=MU, rho=RHO,
+                             max_iter=7, eps=eps)
+    assert ref.status == "converged" and ref.k == 8
+    assert res.status_name == "converged" and res.k == 8
+    assert rel_l2(res.x_last.cpu().numpy(), ref.x_last) <= 1e-3
 
 
 def test_replay_reproduces_trials(sp, small, small_ref):
