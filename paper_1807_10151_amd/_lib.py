@@ -90,6 +90,7 @@ _SIGS = {
     "sp_last_error": (c_char_p, [c_void_p]),
     "sp_project": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
     "sp_backproject": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
+    "sp_backproject_noalloc": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
     "sp_residual": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, c_void_p, c_void_p]),
     "sp_gradient": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, c_void_p, c_void_p]),
     "sp_precond_apply": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(sp_precond), c_void_p, c_void_p]),

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsuppcg.so")
 
-SOURCES = ["projector.hip", "fft.hip", "tv.hip", "cg.hip", "learned.hip", "capi.cpp"]
+SOURCES = ["projector.hip", "fft.hip", "tv.hip", "cg.hip", "learned.hip", "noalloc.hip", "capi.cpp"]
 
 # -ffp-contract=off: the projector and backprojector must evaluate the chord
 # weight with the same instruction sequence; no implicit mul+add fusion.

@@ -45,7 +45,7 @@ struct BatchState {
 struct sp_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    std::string err;
+    char err[512] = {0};   // last failure (fixed storage: reporting an error allocates nothing)
 
     // geometry cache
     bool have_geom = false;
@@ -85,6 +85,13 @@ struct sp_ctx {
     double last_eps = 0.0;
     hipGraph_t pend_graph = nullptr;
     hipGraphExec_t pend_exec = nullptr;
+
+    // host staging of sp_backproject_noalloc's tables, sized at creation, and
+    // the event after their last upload (the next call waits on it before
+    // writing them again)
+    std::vector<AngleDev> na_tab;
+    std::vector<double> na_sk;
+    hipEvent_t na_ev = nullptr;
     BatchState* batch = nullptr;
     int n_cu = 0;
 
@@ -119,7 +126,7 @@ int fail(sp_ctx* c, int code, const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf;
+    if (c) std::memcpy(c->err, buf, sizeof buf);
     return code;
 }
 
@@ -204,8 +211,44 @@ void angle_cos_sin(const sp_geometry& g, int a, double& co, double& si) {
     }
 }
 
-// Device geometry and the class-sorted angle table of a validated geometry.
-int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<AngleDev>& tab) {
+// Chord and selection constants of angle a (snapped cos/sin, G7).
+AngleDev angle_entry(const sp_geometry& g, int a, double ds, double s0, double margin) {
+    double co, si;
+    angle_cos_sin(g, a, co, si);
+    AngleDev A{};
+    A.c = co;
+    A.s = si;
+    const double ac = std::fabs(co), as = std::fabs(si);
+    const bool axis = ac == 0.0 || as == 0.0;
+    const bool horiz = as > ac;
+    const double e = 0.5 * (ac + as);
+    const double inv = axis ? 0.0 : 1.0 / std::min(ac, as);
+    A.inv = inv;
+    A.einv = e * inv;
+    A.wmax = 1.0 / std::max(ac, as);
+    A.slope = horiz ? co / si : si / co;
+    const double hw = e / std::max(ac, as) + margin;
+    A.hw = (float)hw;
+    A.nc = (int)std::ceil(2.0 * hw);
+    const double hb = (e + margin) / ds;
+    A.nb = (int)std::ceil(2.0 * hb);
+    A.kb = -s0 / ds - hb + 1.0 + PAD;
+    A.row = a;
+    A.flags = (axis ? ANG_AXIS : 0) | (horiz ? ANG_HORIZ : 0);
+    return A;
+}
+
+// Class of an angle in the order the backprojector loops over them: vertical
+// oblique, horizontal oblique, vertical axis-parallel, horizontal axis-parallel.
+int angle_class(const AngleDev& A) {
+    const bool axis = A.flags & ANG_AXIS, horiz = A.flags & ANG_HORIZ;
+    return (axis ? 2 : 0) + (horiz ? 1 : 0);
+}
+
+// Device geometry and the class-sorted angle table (n_angles entries written
+// to tab) of a validated geometry.  Allocates nothing: the table is sorted by
+// class with a stable counting pass per class.
+int build_geometry_into(sp_ctx* c, const sp_geometry* g, GeomDev& G, AngleDev* tab) {
     G = GeomDev{};
     G.rows = g->rows;
     G.cols = g->cols;
@@ -229,57 +272,39 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
     G.parts = project_parts(g->rows, g->cols, g->n_angles, g->n_bins, c->n_cu * 32);
     G.bp_px = backproject_px(g->rows, g->cols, c->n_cu * 32);
     const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
-    tab.assign(g->n_angles, AngleDev{});
-    for (int a = 0; a < g->n_angles; ++a) {
-        double co, si;
-        angle_cos_sin(*g, a, co, si);
-        AngleDev A{};
-        A.c = co;
-        A.s = si;
-        const double ac = std::fabs(co), as = std::fabs(si);
-        const bool axis = ac == 0.0 || as == 0.0;
-        const bool horiz = as > ac;
-        const double e = 0.5 * (ac + as);
-        const double inv = axis ? 0.0 : 1.0 / std::min(ac, as);
-        A.inv = inv;
-        A.einv = e * inv;
-        A.wmax = 1.0 / std::max(ac, as);
-        A.slope = horiz ? co / si : si / co;
-        const double hw = e / std::max(ac, as) + margin;
-        A.hw = (float)hw;
-        A.nc = (int)std::ceil(2.0 * hw);
-        const double hb = (e + margin) / ds;
-        A.nb = (int)std::ceil(2.0 * hb);
-        A.kb = -s0 / ds - hb + 1.0 + PAD;
-        A.row = a;
-        A.flags = (axis ? ANG_AXIS : 0) | (horiz ? ANG_HORIZ : 0);
-        if (A.nc < 2 || A.nc > 3 || A.nb < 1 || A.nb > 4)
-            return fail(c, SP_ERR_ARG, "unsupported geometry at angle %d (nc=%d nb=%d)", a, A.nc, A.nb);
-        tab[a] = A;
-    }
-    // Sort into the classes the backprojector loops over: vertical oblique,
-    // horizontal oblique, vertical axis-parallel, horizontal axis-parallel.
-    auto cls_of = [](const AngleDev& A) {
-        const bool axis = A.flags & ANG_AXIS, horiz = A.flags & ANG_HORIZ;
-        return (axis ? 2 : 0) + (horiz ? 1 : 0);
-    };
-    std::stable_sort(tab.begin(), tab.end(),
-                     [&](const AngleDev& x, const AngleDev& y) { return cls_of(x) < cls_of(y); });
     G.nbmax = 1;
     for (int q = 0; q <= 4; ++q) G.cls[q] = 0;
-    for (const AngleDev& A : tab) {
+    for (int a = 0; a < g->n_angles; ++a) {
+        const AngleDev A = angle_entry(*g, a, ds, s0, margin);
+        if (A.nc < 2 || A.nc > 3 || A.nb < 1 || A.nb > 4)
+            return fail(c, SP_ERR_ARG, "unsupported geometry at angle %d (nc=%d nb=%d)", a, A.nc, A.nb);
         G.nbmax = std::max(G.nbmax, A.nb);
-        G.cls[cls_of(A) + 1] += 1;
+        G.cls[angle_class(A) + 1] += 1;
     }
     for (int q = 1; q <= 4; ++q) G.cls[q] += G.cls[q - 1];
+    int pos = 0;
+    for (int q = 0; q < 4; ++q)
+        for (int a = 0; a < g->n_angles; ++a) {
+            const AngleDev A = angle_entry(*g, a, ds, s0, margin);
+            if (angle_class(A) == q) tab[pos++] = A;
+        }
     return SP_OK;
+}
+
+int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<AngleDev>& tab) {
+    tab.assign(g->n_angles, AngleDev{});
+    return build_geometry_into(c, g, G, tab.data());
 }
 
 // Bin positions of the padded bin range, t[PAD + k] = s_k for
 // k = -PAD .. n_bins + PAD - 1, with the fma the kernels use.
+void bin_sk_fill(const GeomDev& G, double* t) {
+    for (int k = -PAD; k < G.nB + PAD; ++k) t[k + PAD] = std::fma((double)k, G.ds, G.s0);
+}
+
 std::vector<double> bin_sk_table(const GeomDev& G) {
     std::vector<double> t((size_t)G.nB + 2 * PAD);
-    for (int k = -PAD; k < G.nB + PAD; ++k) t[(size_t)(k + PAD)] = std::fma((double)k, G.ds, G.s0);
+    bin_sk_fill(G, t.data());
     return t;
 }
 
@@ -725,7 +750,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
     int rc;
     for (int s = 0; s < n; ++s) {
         SliceDev& S = B.hs[s];
-        if ((rc = build_geometry(c, &geoms[s], S.G, tabs[s]))) return fail(c, rc, "slice %d: %s", s, c->err.c_str());
+        if ((rc = build_geometry(c, &geoms[s], S.G, tabs[s]))) return fail(c, rc, "slice %d: %s", s, c->err);
         const GeomDev& G = S.G;
         B.nbmax = std::max(B.nbmax, G.nbmax);
         B.max_bins = std::max(B.max_bins, G.nB);
@@ -962,6 +987,14 @@ int sp_ctx_create(int device, void* hip_stream, sp_ctx** out) {
     if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         c->n_cu < 1)
         c->n_cu = 256;
+    c->na_tab.resize(NOALLOC_MAX_ANGLES);
+    c->na_sk.resize(65536 + 2 * PAD);
+    if (hipEventCreateWithFlags(&c->na_ev, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return SP_ERR_HIP;
+    }
+    void* scr = nullptr;
+    (void)noalloc_scratch(device, &scr);   // per-device lookup of the static scratch, once
     *out = c;
     return SP_OK;
 }
@@ -979,6 +1012,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     if (c->own) (void)hipStreamDestroy(c->own);
     for (hipEvent_t e : c->own_ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->na_ev) (void)hipEventDestroy(c->na_ev);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->batch) {
         for (DevBuf* b : {&c->batch->arena, &c->batch->sl, &c->batch->items, &c->batch->scal,
@@ -996,7 +1030,7 @@ int sp_ctx_set_stream(sp_ctx* c, void* hip_stream) {
     return SP_OK;
 }
 
-const char* sp_last_error(const sp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* sp_last_error(const sp_ctx* c) { return c ? c->err : "null context"; }
 
 int sp_profile_enable(sp_ctx* c, int on) {
     if (!c) return SP_ERR_ARG;
@@ -1206,6 +1240,46 @@ int sp_backproject(sp_ctx* c, const sp_geometry* g, const float* y, float* x) {
         launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp),
                            dptr<double>(c->skp), x, nullptr, nullptr, nullptr);
     }
+    return check_launch(c);
+}
+
+int sp_backproject_noalloc(sp_ctx* c, const sp_geometry* g, const float* y, float* x) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !y) return fail(c, SP_ERR_ARG, "x and y must be device pointers");
+    int rc = validate_geometry(c, g);
+    if (rc) return rc;
+    if (g->n_angles > NOALLOC_MAX_ANGLES)
+        return fail(c, SP_ERR_ARG, "sp_backproject_noalloc: at most %d angles (got %d)",
+                    NOALLOC_MAX_ANGLES, g->n_angles);
+    // scratch layout: angle table | padded bin positions | padded sinogram
+    const size_t pitchB = (size_t)g->n_bins + 2 * PAD;
+    const size_t off_sk = align256((size_t)g->n_angles * sizeof(AngleDev));
+    const size_t off_yp = off_sk + align256(pitchB * sizeof(double));
+    const size_t need = off_yp + (size_t)g->n_angles * pitchB * sizeof(float);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(c, SP_ERR_ARG,
+                    "sp_backproject_noalloc: this geometry needs %zu bytes of scratch, the static "
+                    "array holds %zu", need, NOALLOC_SCRATCH_BYTES);
+    HIP_TRY(c, hipSetDevice(c->device));
+    void* scr = nullptr;
+    hipError_t es = noalloc_scratch(c->device, &scr);
+    if (es != hipSuccess || !scr)
+        return fail(c, SP_ERR_HIP, "hipGetSymbolAddress of the scratch array: %s", hipGetErrorString(es));
+    HIP_TRY(c, hipEventSynchronize(c->na_ev));   // the previous call's uploads have read the staging
+    GeomDev G{};
+    if ((rc = build_geometry_into(c, g, G, c->na_tab.data()))) return rc;
+    bin_sk_fill(G, c->na_sk.data());
+    char* base = static_cast<char*>(scr);
+    AngleDev* ang = reinterpret_cast<AngleDev*>(base);
+    double* skp = reinterpret_cast<double*>(base + off_sk);
+    float* yp = reinterpret_cast<float*>(base + off_yp);
+    HIP_TRY(c, hipMemcpyAsync(ang, c->na_tab.data(), (size_t)g->n_angles * sizeof(AngleDev),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(skp, c->na_sk.data(), pitchB * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipEventRecord(c->na_ev, c->stream));
+    launch_pad_sino(c->stream, G, ang, y, yp);   // every entry of the rows, pads included
+    launch_backproject(c->stream, G, ang, yp, skp, x, nullptr, nullptr, nullptr);
     return check_launch(c);
 }
 
@@ -1808,7 +1882,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     int rc = drain_pending(c);
     if (rc) return rc;
     for (int s = 0; s < n; ++s) {
-        if ((rc = validate_geometry(c, &geoms[s]))) return fail(c, rc, "slice %d: %s", s, c->err.c_str());
+        if ((rc = validate_geometry(c, &geoms[s]))) return fail(c, rc, "slice %d: %s", s, c->err);
         if (!b[s] || !x_out[s]) return fail(c, SP_ERR_ARG, "slice %d: b and x_out are required", s);
     }
     if (pc->kind != SP_PRECOND_RAMP && pc->kind != SP_PRECOND_NONE)

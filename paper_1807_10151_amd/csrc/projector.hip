@@ -590,14 +590,18 @@ void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const
 }
 
 // Padded copy of a caller's sinogram for R^T, each row times its angle's wmax
-// (the scaling bp_class expects); one workgroup per entry of the angle table.
+// (the scaling bp_class expects), pads written as zeros; one workgroup per
+// entry of the angle table.
 __global__ __launch_bounds__(256) void k_pad_sino(GeomDev G, const AngleDev* __restrict__ ang,
                                                   const float* __restrict__ y,
                                                   float* __restrict__ yp) {
     const int a = ang[blockIdx.x].row;
     const double wmax = ang[blockIdx.x].wmax;
-    for (int k = threadIdx.x; k < G.nB; k += 256)
-        yp[(size_t)a * G.pitchB + PAD + k] = (float)((double)y[(size_t)a * G.nB + k] * wmax);
+    float* row = yp + (size_t)a * G.pitchB;
+    for (int k = threadIdx.x; k < G.pitchB; k += 256) {
+        const int kk = k - PAD;
+        row[k] = kk >= 0 && kk < G.nB ? (float)((double)y[(size_t)a * G.nB + kk] * wmax) : 0.0f;
+    }
 }
 
 void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* y,

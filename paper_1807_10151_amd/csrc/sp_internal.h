@@ -132,6 +132,15 @@ __device__ __forceinline__ double chord_u(double d, double einv, double inv) {
 
 __device__ __forceinline__ double bin_pos(double k, const GeomDev& G) { return fma(k, G.ds, G.s0); }
 
+// ---- allocation-free entry point (noalloc.hip) ---------------------------------
+// Bytes of the static per-GPU scratch array and the largest angle count the
+// allocation-free backprojection accepts (its host staging is sized for it).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+constexpr int NOALLOC_MAX_ANGLES = 8192;
+// Device address of the scratch array on `device` (looked up once per device,
+// with that device current); the result of that lookup.
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // ---- kernel launchers (all enqueue on `st`) ----------------------------------
 // projector.hip
 // The padded copies of the image (xp, xTp) are float64 widenings of the
