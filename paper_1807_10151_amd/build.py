@@ -13,10 +13,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsuppcg.so")
 
-SOURCES = ["projector.hip", "fft.hip", "tv.hip", "cg.hip", "learned.hip", "noalloc.hip", "capi.cpp"]
+SOURCES = ["projector.hip", "fft.hip", "tv.hip", "cg.hip", "learned.hip", "noalloc.hip",
+           "geometry.cpp", "capi.cpp"]
 
-# -ffp-contract=off: the projector and backprojector must evaluate the chord
-# weight with the same instruction sequence; no implicit mul+add fusion.
+# -ffp-contract=off: no multiply and add is fused implicitly; the fused ones
+# are the explicit fma calls, so a formula evaluated on the host and on the
+# device (the bin positions of the axis-parallel weights) rounds the same way.
 # -packed-fp32-ops: no packed FP32 instructions are generated.
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -28,7 +28,6 @@ struct BatchState {
     std::vector<sp_geometry> geoms;
     int kind = -1;
     int nbmax = 1;
-    int max_bins = 1;
     int bp_px = 2;                   // R^T pixels per lane for the whole batch
     size_t lds_rows = 0, lds_cols = 0;
     std::vector<SliceDev> hs;        // host copies; per-call pointers filled in each call
@@ -52,7 +51,7 @@ struct sp_ctx {
     sp_geometry geom{};
     GeomDev G{};
     std::vector<AngleDev> ang_h;
-    DevBuf ang, skp, xp, xTp, yp, ypd, seg, pord;
+    DevBuf ang, pwave, xp, xTp, yp, ypd, seg, pord;
 
     // preconditioner cache
     int fftP = 0;
@@ -90,7 +89,6 @@ struct sp_ctx {
     // the event after their last upload (the next call waits on it before
     // writing them again)
     std::vector<AngleDev> na_tab;
-    std::vector<double> na_sk;
     hipEvent_t na_ev = nullptr;
     BatchState* batch = nullptr;
     int n_cu = 0;
@@ -191,121 +189,17 @@ int validate_geometry(sp_ctx* c, const sp_geometry* g) {
     return SP_OK;
 }
 
-// cos/sin of angle index a, exact at multiples of pi/4.
-void angle_cos_sin(const sp_geometry& g, int a, double& co, double& si) {
-    const double dth = g.dtheta > 0.0 ? g.dtheta : M_PI / g.n_angles;
-    const double th = g.theta0 + a * dth;
-    const double q = th / (M_PI / 4.0);
-    const double m = std::nearbyint(q);
-    if (std::fabs(q - m) < 1e-12) {
-        static const double h = std::sqrt(0.5);
-        static const double tc[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
-        static const double ts[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
-        long long mi = (long long)m % 8;
-        if (mi < 0) mi += 8;
-        co = tc[mi];
-        si = ts[mi];
-    } else {
-        co = std::cos(th);
-        si = std::sin(th);
-    }
-}
-
-// Chord and selection constants of angle a (snapped cos/sin, G7).
-AngleDev angle_entry(const sp_geometry& g, int a, double ds, double s0, double margin) {
-    double co, si;
-    angle_cos_sin(g, a, co, si);
-    AngleDev A{};
-    A.c = co;
-    A.s = si;
-    const double ac = std::fabs(co), as = std::fabs(si);
-    const bool axis = ac == 0.0 || as == 0.0;
-    const bool horiz = as > ac;
-    const double e = 0.5 * (ac + as);
-    const double inv = axis ? 0.0 : 1.0 / std::min(ac, as);
-    A.inv = inv;
-    A.einv = e * inv;
-    A.wmax = 1.0 / std::max(ac, as);
-    A.slope = horiz ? co / si : si / co;
-    const double hw = e / std::max(ac, as) + margin;
-    A.hw = (float)hw;
-    A.nc = (int)std::ceil(2.0 * hw);
-    const double hb = (e + margin) / ds;
-    A.nb = (int)std::ceil(2.0 * hb);
-    A.kb = -s0 / ds - hb + 1.0 + PAD;
-    A.row = a;
-    A.flags = (axis ? ANG_AXIS : 0) | (horiz ? ANG_HORIZ : 0);
-    return A;
-}
-
-// Class of an angle in the order the backprojector loops over them: vertical
-// oblique, horizontal oblique, vertical axis-parallel, horizontal axis-parallel.
-int angle_class(const AngleDev& A) {
-    const bool axis = A.flags & ANG_AXIS, horiz = A.flags & ANG_HORIZ;
-    return (axis ? 2 : 0) + (horiz ? 1 : 0);
-}
-
-// Device geometry and the class-sorted angle table (n_angles entries written
-// to tab) of a validated geometry.  Allocates nothing: the table is sorted by
-// class with a stable counting pass per class.
+// Device geometry and class-sorted angle table (geometry.cpp), failures
+// reported on the context.
 int build_geometry_into(sp_ctx* c, const sp_geometry* g, GeomDev& G, AngleDev* tab) {
-    G = GeomDev{};
-    G.rows = g->rows;
-    G.cols = g->cols;
-    G.nA = g->n_angles;
-    G.nB = g->n_bins;
-    G.xoff = (g->cols - 1) / 2.0;
-    G.yoff = (g->rows - 1) / 2.0;
-    const double ds = g->bin_spacing / g->pixel;
-    const double s0 = (-(g->n_bins - 1) / 2.0 * g->bin_spacing + g->bin_offset) / g->pixel;
-    G.ds = ds;
-    G.s0 = s0;
-    G.inv_ds = 1.0 / ds;
-    G.pixel = g->pixel;
-    G.xoff_f = (float)G.xoff;
-    G.yoff_f = (float)G.yoff;
-    G.ds_f = (float)ds;
-    G.s0_f = (float)s0;
-    G.pitchX = g->cols + 2 * PAD;
-    G.pitchXT = g->rows + 2 * PAD;
-    G.pitchB = g->n_bins + 2 * PAD;
-    G.parts = project_parts(g->rows, g->cols, g->n_angles, g->n_bins, c->n_cu * 32);
-    G.bp_px = backproject_px(g->rows, g->cols, c->n_cu * 32);
-    const double margin = 1e-3 + 4e-7 * (double)(g->rows + g->cols + g->n_bins);
-    G.nbmax = 1;
-    for (int q = 0; q <= 4; ++q) G.cls[q] = 0;
-    for (int a = 0; a < g->n_angles; ++a) {
-        const AngleDev A = angle_entry(*g, a, ds, s0, margin);
-        if (A.nc < 2 || A.nc > 3 || A.nb < 1 || A.nb > 4)
-            return fail(c, SP_ERR_ARG, "unsupported geometry at angle %d (nc=%d nb=%d)", a, A.nc, A.nb);
-        G.nbmax = std::max(G.nbmax, A.nb);
-        G.cls[angle_class(A) + 1] += 1;
-    }
-    for (int q = 1; q <= 4; ++q) G.cls[q] += G.cls[q - 1];
-    int pos = 0;
-    for (int q = 0; q < 4; ++q)
-        for (int a = 0; a < g->n_angles; ++a) {
-            const AngleDev A = angle_entry(*g, a, ds, s0, margin);
-            if (angle_class(A) == q) tab[pos++] = A;
-        }
-    return SP_OK;
+    char msg[256];
+    const int rc = sp::build_geometry_into(g, c->n_cu, G, tab, msg, sizeof msg);
+    return rc ? fail(c, rc, "%s", msg) : SP_OK;
 }
 
 int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<AngleDev>& tab) {
     tab.assign(g->n_angles, AngleDev{});
     return build_geometry_into(c, g, G, tab.data());
-}
-
-// Bin positions of the padded bin range, t[PAD + k] = s_k for
-// k = -PAD .. n_bins + PAD - 1, with the fma the kernels use.
-void bin_sk_fill(const GeomDev& G, double* t) {
-    for (int k = -PAD; k < G.nB + PAD; ++k) t[k + PAD] = std::fma((double)k, G.ds, G.s0);
-}
-
-std::vector<double> bin_sk_table(const GeomDev& G) {
-    std::vector<double> t((size_t)G.nB + 2 * PAD);
-    bin_sk_fill(G, t.data());
-    return t;
 }
 
 int setup_geometry(sp_ctx* c, const sp_geometry* g) {
@@ -335,13 +229,14 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
         HIP_TRY(c, hipMemsetAsync(c->ypd.ptr, 0, c->ypd.bytes, c->stream));
     }
     c->ang_h = tab;
-    const std::vector<double> skt = bin_sk_table(G);
-    if ((rc = ensure(c, c->skp, skt.size() * sizeof(double)))) return rc;
-    HIP_TRY(c, hipMemcpyAsync(c->skp.ptr, skt.data(), skt.size() * sizeof(double),
+    std::vector<WaveDev> waves((size_t)G.nwaves);
+    project_waves(G, waves.data());
+    if ((rc = ensure(c, c->pwave, waves.size() * sizeof(WaveDev)))) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->pwave.ptr, waves.data(), waves.size() * sizeof(WaveDev),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->ang.ptr, tab.data(), tab.size() * sizeof(AngleDev),
                               hipMemcpyHostToDevice, c->stream));
-    const std::vector<int32_t> ord = project_order(G, tab, c->n_cu);
+    const std::vector<int32_t> ord = project_order(G, tab.data(), waves.data(), c->n_cu);
     if ((rc = ensure(c, c->pord, ord.size() * sizeof(int32_t)))) return rc;
     HIP_TRY(c, hipMemcpyAsync(c->pord.ptr, ord.data(), ord.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, c->stream));
@@ -652,7 +547,7 @@ int stage_blocks(const SliceDev& S, int stage) {
     const GeomDev& G = S.G;
     switch (stage) {
     case BS_PREP: return ((G.cols + 31) / 32) * ((G.rows + 31) / 32);
-    case BS_PROJECT: return project_ray_blocks(G) * G.parts;
+    case BS_PROJECT: return G.nwg * G.parts;
     case BS_PROJ_COMB: return G.parts > 1 ? project_comb_blocks(G) : 0;
     case BS_BACKPROJECT: return backproject_tiles(G, G.bp_px);
     case BS_ROWS: return (G.rows + 1) / 2;
@@ -738,12 +633,11 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
     for (int s = 0; s < BS_COUNT; ++s) B.order[s] = B.wpc[s] = 0;
     B.hs.assign(n, SliceDev{});
     B.nbmax = 1;
-    B.max_bins = 1;
     B.lds_rows = B.lds_cols = 0;
     std::vector<std::vector<AngleDev>> tabs(n);
     // sizes
     struct Off {
-        size_t ang, skp, pord, xp, xTp, rp, rpd, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
+        size_t ang, pwave, pord, xp, xTp, rp, rpd, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
     };
     std::vector<Off> off(n);
     size_t total = 0;
@@ -753,7 +647,6 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         if ((rc = build_geometry(c, &geoms[s], S.G, tabs[s]))) return fail(c, rc, "slice %d: %s", s, c->err);
         const GeomDev& G = S.G;
         B.nbmax = std::max(B.nbmax, G.nbmax);
-        B.max_bins = std::max(B.max_bins, G.nB);
         S.n = G.rows * G.cols;
         S.F = FFTPlan{};
         if (kind == SP_PRECOND_RAMP) {
@@ -780,8 +673,8 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
             return at;
         };
         o.ang = take(tabs[s].size() * sizeof(AngleDev));
-        o.skp = take(((size_t)G.nB + 2 * PAD) * sizeof(double));
-        o.pord = take((size_t)project_ray_blocks(G) * sizeof(int32_t));
+        o.pwave = take((size_t)G.nwaves * sizeof(WaveDev));
+        o.pord = take((size_t)G.nwg * sizeof(int32_t));
         o.xp = take((size_t)G.rows * G.pitchX * 8);
         o.xTp = take((size_t)G.cols * G.pitchXT * 8);
         o.rp = take((size_t)G.nA * G.pitchB * 4);
@@ -820,11 +713,12 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         SliceDev& S = B.hs[s];
         const Off& o = off[s];
         S.ang = reinterpret_cast<const AngleDev*>(base + o.ang);
-        S.skp = reinterpret_cast<const double*>(base + o.skp);
-        const std::vector<double> skt = bin_sk_table(S.G);
-        HIP_TRY(c, hipMemcpyAsync(base + o.skp, skt.data(), skt.size() * sizeof(double),
+        std::vector<WaveDev> waves((size_t)S.G.nwaves);
+        project_waves(S.G, waves.data());
+        S.pwave = reinterpret_cast<const WaveDev*>(base + o.pwave);
+        HIP_TRY(c, hipMemcpyAsync(base + o.pwave, waves.data(), waves.size() * sizeof(WaveDev),
                                   hipMemcpyHostToDevice, c->stream));
-        const std::vector<int32_t> ord = project_order(S.G, tabs[s], c->n_cu);
+        const std::vector<int32_t> ord = project_order(S.G, tabs[s].data(), waves.data(), c->n_cu);
         S.pord = reinterpret_cast<const int*>(base + o.pord);
         HIP_TRY(c, hipMemcpyAsync(base + o.pord, ord.data(), ord.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, c->stream));
@@ -902,7 +796,7 @@ void batch_stage(sp_ctx* c, int stage, int order, int wpc, double mu, double rho
     switch (stage) {
     case BS_PREP: launch_prep_b(st, sl, t, BV_XH); break;
     case BS_PROJECT: launch_project_b(st, sl, t, table(c, BS_PROJ_COMB, order, 0), true); break;
-    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, B.max_bins, false, B.bp_px); break;
+    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, false, B.bp_px); break;
     case BS_ROWS:
         launch_precond_b(st, sl, t, table(c, BS_COLS, order, wpc), B.lds_rows, B.lds_cols, mu, rho);
         break;
@@ -988,7 +882,6 @@ int sp_ctx_create(int device, void* hip_stream, sp_ctx** out) {
         c->n_cu < 1)
         c->n_cu = 256;
     c->na_tab.resize(NOALLOC_MAX_ANGLES);
-    c->na_sk.resize(65536 + 2 * PAD);
     if (hipEventCreateWithFlags(&c->na_ev, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return SP_ERR_HIP;
@@ -1004,7 +897,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     (void)drain_pending(c);
-    for (DevBuf* b : {&c->ang, &c->skp, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
+    for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
                       &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
@@ -1220,7 +1113,8 @@ int sp_project(sp_ctx* c, const sp_geometry* g, const float* x, float* y) {
     launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
     {
         ProfScope ps(c, SP_PROF_PROJECT);
-        launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp),
+        launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<WaveDev>(c->pwave),
+                       dptr<double>(c->xp), dptr<double>(c->xTp),
                        nullptr, y, G.nB, nullptr, nullptr, nullptr, dptr<double>(c->seg),
                        dptr<int>(c->pord), nullptr);
     }
@@ -1237,8 +1131,8 @@ int sp_backproject(sp_ctx* c, const sp_geometry* g, const float* y, float* x) {
     launch_pad_sino(c->stream, G, dptr<AngleDev>(c->ang), y, dptr<float>(c->yp));
     {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
-        launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp),
-                           dptr<double>(c->skp), x, nullptr, nullptr, nullptr);
+        launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<float>(c->yp), x, nullptr,
+                           nullptr, nullptr);
     }
     return check_launch(c);
 }
@@ -1251,10 +1145,9 @@ int sp_backproject_noalloc(sp_ctx* c, const sp_geometry* g, const float* y, floa
     if (g->n_angles > NOALLOC_MAX_ANGLES)
         return fail(c, SP_ERR_ARG, "sp_backproject_noalloc: at most %d angles (got %d)",
                     NOALLOC_MAX_ANGLES, g->n_angles);
-    // scratch layout: angle table | padded bin positions | padded sinogram
+    // scratch layout: angle table | padded sinogram
     const size_t pitchB = (size_t)g->n_bins + 2 * PAD;
-    const size_t off_sk = align256((size_t)g->n_angles * sizeof(AngleDev));
-    const size_t off_yp = off_sk + align256(pitchB * sizeof(double));
+    const size_t off_yp = align256((size_t)g->n_angles * sizeof(AngleDev));
     const size_t need = off_yp + (size_t)g->n_angles * pitchB * sizeof(float);
     if (need > NOALLOC_SCRATCH_BYTES)
         return fail(c, SP_ERR_ARG,
@@ -1268,18 +1161,14 @@ int sp_backproject_noalloc(sp_ctx* c, const sp_geometry* g, const float* y, floa
     HIP_TRY(c, hipEventSynchronize(c->na_ev));   // the previous call's uploads have read the staging
     GeomDev G{};
     if ((rc = build_geometry_into(c, g, G, c->na_tab.data()))) return rc;
-    bin_sk_fill(G, c->na_sk.data());
     char* base = static_cast<char*>(scr);
     AngleDev* ang = reinterpret_cast<AngleDev*>(base);
-    double* skp = reinterpret_cast<double*>(base + off_sk);
     float* yp = reinterpret_cast<float*>(base + off_yp);
     HIP_TRY(c, hipMemcpyAsync(ang, c->na_tab.data(), (size_t)g->n_angles * sizeof(AngleDev),
                               hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(skp, c->na_sk.data(), pitchB * sizeof(double), hipMemcpyHostToDevice,
-                              c->stream));
     HIP_TRY(c, hipEventRecord(c->na_ev, c->stream));
     launch_pad_sino(c->stream, G, ang, y, yp);   // every entry of the rows, pads included
-    launch_backproject(c->stream, G, ang, yp, skp, x, nullptr, nullptr, nullptr);
+    launch_backproject(c->stream, G, ang, yp, x, nullptr, nullptr, nullptr);
     return check_launch(c);
 }
 
@@ -1292,7 +1181,8 @@ int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b,
     if ((rc = ensure_partials(c))) return rc;
     const GeomDev& G = c->G;
     launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
-    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp), b, r,
+    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<WaveDev>(c->pwave), dptr<double>(c->xp),
+                   dptr<double>(c->xTp), b, r,
                    G.nB, nullptr, nullptr, dptr<double>(c->part_f), dptr<double>(c->seg),
                    dptr<int>(c->pord), nullptr);
     launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
@@ -1310,10 +1200,11 @@ int sp_gradient(sp_ctx* c, const sp_geometry* g, const float* x, const float* b,
     const GeomDev& G = c->G;
     // the solvers' path: the residual stays float64 between R and R^T
     launch_prep(c->stream, G, x, dptr<double>(c->xp), dptr<double>(c->xTp), nullptr);
-    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->xp), dptr<double>(c->xTp), b,
+    launch_project(c->stream, G, dptr<AngleDev>(c->ang), dptr<WaveDev>(c->pwave), dptr<double>(c->xp),
+                   dptr<double>(c->xTp), b,
                    nullptr, 0, nullptr, dptr<double>(c->ypd), dptr<double>(c->part_f),
                    dptr<double>(c->seg), dptr<int>(c->pord), nullptr);
-    launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->ypd), dptr<double>(c->skp),
+    launch_backproject(c->stream, G, dptr<AngleDev>(c->ang), dptr<double>(c->ypd),
                        grad, nullptr, nullptr, nullptr);
     if (f) launch_reduce(c->stream, dptr<double>(c->part_f), project_blocks(G), f);
     return check_launch(c);
@@ -1525,7 +1416,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     const int* pord = dptr<int>(c->pord);
     float* rp = dptr<float>(c->yp);
     double* rpd = dptr<double>(c->ypd);
-    const double* skp = dptr<double>(c->skp);
+    const WaveDev* waves = dptr<WaveDev>(c->pwave);
     const AngleDev* ang = dptr<AngleDev>(c->ang);
     double* pf = dptr<double>(c->part_f);
     double* pzh = dptr<double>(c->part_zh);
@@ -1539,16 +1430,17 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
         // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
         launch_prep(st, G, xh, xp, xTp, halt);
-        launch_project(st, G, ang, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, pord, halt);
+        launch_project(st, G, ang, waves, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, pord, halt);
         launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
-        launch_backproject(st, G, ang, rpd, skp, gv, nullptr, nullptr, halt);
+        launch_backproject(st, G, ang, rpd, gv, nullptr, nullptr, halt);
         int nzh = 0;
         if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
         launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
         launch_update_p(st, n, z, p, gv, sc, pgp, halt);
         launch_prep(st, G, p, xp, xTp, halt);
-        launch_project(st, G, ang, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, pord, halt);
-        launch_backproject(st, G, ang, rp, skp, h, p, pph, halt);
+        launch_project(st, G, ang, waves, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, pord,
+                       halt);
+        launch_backproject(st, G, ang, rp, h, p, pph, halt);
         launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
         launch_update_x(st, n, xh, p, x, sc, halt);
         if ((rc = check_launch(c))) return rc;
@@ -1561,14 +1453,14 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     // r = R x - b goes to the float64 sinogram rpd, R p to the float32 rp
     auto project = [&](const float* bb, double* parts) {
         ProfScope ps(c, SP_PROF_PROJECT);
-        launch_project(st, G, ang, xp, xTp, bb, nullptr, 0, bb ? nullptr : rp, bb ? rpd : nullptr,
+        launch_project(st, G, ang, waves, xp, xTp, bb, nullptr, 0, bb ? nullptr : rp, bb ? rpd : nullptr,
                        parts, seg, pord, halt);
     };
     auto backproject = [&](float* out, const double* dotv, double* parts,
                            const ScalarRide& ride) {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
-        if (dotv) launch_backproject(st, G, ang, rp, skp, out, dotv, parts, halt, ride);
-        else launch_backproject(st, G, ang, rpd, skp, out, dotv, parts, halt, ride);
+        if (dotv) launch_backproject(st, G, ang, rp, out, dotv, parts, halt, ride);
+        else launch_backproject(st, G, ang, rpd, out, dotv, parts, halt, ride);
     };
     // g = R^T r also carries f(x_{k+1/2}) (and the S_TV step norm when K > 0)
     ScalarRide ride_f;
@@ -1940,13 +1832,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     launch_prep_b(st, sl, tprep, BV_XH);
     launch_project_b(st, sl, tproj, tcomb, true);
     launch_scalar_b(st, sl, tone, OP_F0);
-    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false, B.bp_px);
+    launch_backproject_b(st, sl, tbp, B.nbmax, false, B.bp_px);
     batch_precond(c, mu, rho);
     launch_scalar_b(st, sl, tone, OP_BETA);
     launch_update_p_b(st, sl, tvec);
     launch_prep_b(st, sl, tprep, BV_P);
     launch_project_b(st, sl, tproj, tcomb, false);
-    launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true, B.bp_px);
+    launch_backproject_b(st, sl, tbp, B.nbmax, true, B.bp_px);
     launch_scalar_b(st, sl, tone, OP_ALPHA0);
     launch_update_x_b(st, sl, tvec);
     if ((rc = check_launch(c))) return rc;
@@ -1970,13 +1862,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         launch_prep_b(st, sl, tprep, BV_XH);
         launch_project_b(st, sl, tproj, tcomb, true);
         launch_scalar_b(st, sl, tone, OP_F);
-        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, false, B.bp_px);
+        launch_backproject_b(st, sl, tbp, B.nbmax, false, B.bp_px);
         batch_precond(c, mu, rho);
         launch_scalar_b(st, sl, tone, OP_BETA);
         launch_update_p_b(st, sl, tvec);
         launch_prep_b(st, sl, tprep, BV_P);
         launch_project_b(st, sl, tproj, tcomb, false);
-        launch_backproject_b(st, sl, tbp, B.nbmax, B.max_bins, true, B.bp_px);
+        launch_backproject_b(st, sl, tbp, B.nbmax, true, B.bp_px);
         launch_scalar_b(st, sl, tone, OP_ALPHA);
         launch_update_x_b(st, sl, tvec);
     };

@@ -3,42 +3,46 @@
 //
 // R[(a,k),(i,j)] is the length of ray (a,k) inside pixel (i,j) (the projection
 // matrix of Section 2, rays as in Section 4.1).  R^T evaluates each weight as
-// the chord length of a line through a square (projection t of the pixel
-// centre, offset d = s_k - t, the clamped trapezoid u of chord_u, times the
-// angle's wmax).  R walks each ray band by band and splits a band's path
-// length at the pixel boundary it crosses (ray_split): the same lengths in
-// exact arithmetic, equal to rounding in float64, so R^T is the adjoint of R
-// to float64 rounding (axis-parallel angles use the trapezoid in both, bit for
-// bit).  Data are float32; coordinates, weights and sums are float64 (FP64
-// FMA issues at the non-packed FP32 rate on CDNA4, and float32 angles alone
-// would move a ray by ~1e-5 pixel at radius 256).
+// the chord length of a line through a square (offset d = s_k - t of the bin
+// from the projection t of the pixel centre, the clamped trapezoid u of
+// chord_u, times the angle's wmax).  R walks each ray band by band and splits
+// a band's path length at the pixel boundary it crosses (ray_split): the same
+// lengths in exact arithmetic, equal to rounding in float64, so R^T is the
+// adjoint of R to float64 rounding (axis-parallel angles use the trapezoid in
+// both, bit for bit, with its half weight for a ray on a pixel edge).  Data
+// are float32; coordinates, weights and sums are float64 (FP64 FMA issues at
+// the non-packed FP32 rate on CDNA4, and float32 angles alone would move a ray
+// by ~1e-5 pixel at radius 256).
 //
-// Canonical projection of pixel centre (xj, yi) on the normal of angle a:
-//   |c| >= |s| ("vertical" angles):   t = fma(xj, c, yi * s)
-//   |s| >  |c| ("horizontal" angles): t = fma(yi, s, xj * c)
-// The product outside the fma is the one the axis-parallel forward walk
-// shares between the candidates of one step.
+// Gathers stay inside one zero-padded row (of the image copy, its transpose or
+// the sinogram).  R^T reads through buffer loads whose descriptor spans the
+// row, so an index past either end reads 0 in hardware; R clamps its index
+// into the row's pads.  A legitimate candidate always lies inside the row (its
+// pads included), which the host index checker verifies for every geometry it
+// is given.
 //
 // Forward walk.  For a vertical angle a ray crosses every image row; within
 // row i it meets at most two pixels, as its crossing point moves by `slope`
-// (|slope| <= 1) columns per row.  A lane owns one ray; the 64 lanes of a wave hold
-// consecutive rays of one angle and walk the union of their row ranges
-// together, so each step gathers consecutive addresses of one row.  A
-// workgroup's four waves take four consecutive angles and the same 64-bin
-// chunk, and the workgroups run in a host-computed order (project_order).  Candidate
-// columns outside the image are clamped into a zero pad and contribute 0.
-// Horizontal angles walk columns of a zero-padded transposed copy.
+// (|slope| <= 1) columns per row.  A lane owns one ray and the 64 lanes of a
+// wave walk the union of their (nonempty) row ranges together, so each step
+// gathers neighbouring addresses of one row.  R's wave table (WaveDev) gives
+// each wave its rays: 64 consecutive bins of one angle, or the last nB % 64
+// bins of consecutive angles of one class packed into full waves; a
+// workgroup's four waves are four consecutive table entries (four angles of
+// one chunk), and the workgroups run in a host-computed order
+// (project_order).  Horizontal angles walk columns of a zero-padded
+// transposed copy.
 //
 // Backward gather.  A lane owns PX (2 or 4) pixels of one row, 8 columns
 // apart, and loops over the angles, which are sorted into four classes
 // (vertical/horizontal x oblique/axis-parallel) so the inner loop has no
-// branch; at each angle a
-// pixel's nonzero bins are the NB bins after floor(kf - hb), read from a
-// zero-padded sinogram (float32, or float64 for the solvers' residual) whose
-// rows carry the angle's wmax.
+// branch; at each angle a pixel's nonzero bins are the NB bins from padded
+// index trunc(kf), read from a zero-padded sinogram (float32, or float64 for
+// the solvers' residual) whose rows carry the angle's wmax.
 #include "sp_internal.h"
 #include "sp_reduce.h"
 #include "sp_scalar.h"
+#include "sp_walk.h"
 
 #include <algorithm>
 #include <cmath>
@@ -120,116 +124,153 @@ __device__ __forceinline__ int wave_max(int v) {
     return v;
 }
 
-// Major-axis steps [lo, hi) of [0, n) where base + m * slope lies in [vlo, vhi],
-// widened by one step on each side (candidate selection only).
-__device__ __forceinline__ void step_range(double base, double slope, double vlo, double vhi, int n,
-                                           int& lo, int& hi) {
-    if (slope == 0.0) {
-        const bool in = base >= vlo && base <= vhi;
-        lo = 0;
-        hi = in ? n : 0;
-        return;
+// ---- range-checked row gathers ---------------------------------------------
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+// Descriptor word 3 of a raw gfx9 buffer (32-bit data format, no swizzle).
+constexpr int BUF_WORD3 = 0x00020000;
+
+// Buffer resource over `bytes` bytes from `row` (wave-uniform).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* row, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), (short)0, bytes, BUF_WORD3);
+}
+
+// The N elements e, e + 1, ... of a row; every element past either end of the
+// row reads 0 (e is taken as unsigned, so a negative index is past the end).
+template <class T, int N>
+__device__ __forceinline__ void row_load(__amdgpu_buffer_rsrc_t r, unsigned e, T (&v)[N]) {
+    const unsigned off = e * (unsigned)sizeof(T);
+    if constexpr (sizeof(T) == 8 && N == 2) {
+        const d2v t = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        v[0] = t.x;
+        v[1] = t.y;
+    } else if constexpr (sizeof(T) == 4 && N == 2) {
+        const f2v t = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+        v[0] = t.x;
+        v[1] = t.y;
+    } else if constexpr (sizeof(T) == 4 && N == 4) {
+        const f4v t = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            if constexpr (sizeof(T) == 8)
+                v[q] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(r, off + 8u * q, 0, 0));
+            else
+                v[q] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(r, off + 4u * q, 0, 0));
+        }
     }
-    const double t0 = (vlo - base) / slope, t1 = (vhi - base) / slope;
-    double tmin = fmin(t0, t1) - 1.0, tmax = fmax(t0, t1) + 2.0;
-    tmin = fmin(fmax(tmin, 0.0), (double)n);
-    tmax = fmin(fmax(tmax, 0.0), (double)n);
-    lo = (int)floor(tmin);
-    hi = (int)ceil(tmax);
-    if (hi < lo) hi = lo;
 }
 
-// base + o for a wave-uniform base and a 32-bit element index: the byte offset
-// is formed in 32 bits so the load can use the scalar-base addressing form.
-template <class T>
-__device__ __forceinline__ const T* at(const T* base, unsigned o) {
-    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + o * (unsigned)sizeof(T));
+// The forward walks gather with plain global loads from a row, the index
+// clamped to the row's last full window: a clamped index lands in the row's
+// zero pads, and every true candidate of such a step lies outside the image.
+// (Buffer loads, whose descriptor is rebuilt per row on the scalar unit,
+// measured 3-4% slower here; the backprojector, one row per angle, gains.)
+struct RowRef {
+    const char* p;
+    int bytes;
+};
+__device__ __forceinline__ RowRef row_ref(const void* row, int bytes) {
+    return RowRef{reinterpret_cast<const char*>(row), bytes};
+}
+template <class T, int N>
+__device__ __forceinline__ void row_load(RowRef r, unsigned e, T (&v)[N]) {
+    const unsigned emax = (unsigned)(r.bytes / (int)sizeof(T) - N);
+    e = min(e, emax);
+    const T* q = reinterpret_cast<const T*>(r.p) + e;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = q[i];
+}
+// ---- forward walk ----------------------------------------------------------
+// The wave's common step range from the lanes' own ranges: lanes without a
+// ray, or whose ray misses the image, take no part.  Then part `part` of it.
+__device__ __forceinline__ bool wave_steps_dev(int l, int h, bool valid, int nmaj, int part,
+                                               int nparts, int& lo, int& hi) {
+    if (!valid || l >= h) {
+        l = nmaj;
+        h = 0;
+    }
+    lo = __builtin_amdgcn_readfirstlane(wave_min(l));
+    hi = __builtin_amdgcn_readfirstlane(wave_max(h));
+    part_range(lo, hi, part, nparts);
+    return lo < hi;
 }
 
-// One ray's sum, or part `part` of nparts of it.  HORIZ = walk columns of the
-// transposed copy.  img points at element PAD of row 0 of the padded copy.  A
-// part covers the steps [lo + len*part/nparts, lo + len*(part+1)/nparts) of
-// the wave's common step range [lo, lo + len).
-template <bool HORIZ, bool AXIS, int NC>
-__device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, double sk,
-                                          const double* __restrict__ img, bool valid, int part,
-                                          int nparts) {
+// One axis-parallel ray's sum, or part `part` of nparts of it, with the
+// trapezoid per candidate (its half weight for a ray on a pixel edge).
+// HORIZ = walk columns of the transposed copy.  img points at element PAD of
+// row 0 of the padded copy.  Candidate q of step m is minor index
+// floor(nf_m) + 1 + q; nf carries the + 1 + PAD of the padded index, so the
+// first candidate's padded index is trunc(nf) where nf >= 0 (a negative nf
+// reads past the row's start, i.e. 0, as does any index past its end; every
+// true candidate of such a step lies outside the image).  The minor coordinate
+// of candidate q is taken from the index read -- (o + q - PAD) - xoff for
+// columns, yoff - (o + q - PAD) for rows, exact small half-integers.
+// Axis-parallel rays cross the whole image, so their waves are among the
+// longest of the launch: U steps per iteration keep U gathers in flight, as a
+// wave's walk is otherwise bound by the latency of its chain of gathers.
+template <bool HORIZ>
+__device__ __forceinline__ double ray_sum_axis(const GeomDev& G, const AngleDev& A, double sk,
+                                               const double* __restrict__ img, bool valid,
+                                               int part, int nparts) {
+    constexpr int NC = 2, U = 4;
     const int nmaj = HORIZ ? G.cols : G.rows;
-    const int nmin = HORIZ ? G.rows : G.cols;
     const int pitch = HORIZ ? G.pitchXT : G.pitchX;
-    const double fm = HORIZ ? A.s : A.c;   // factor of the per-candidate fma
-    // fractional minor index of the ray's crossing at major step 0, minus hw
-    const double start = (HORIZ ? G.yoff - (sk + G.xoff * A.c) / A.s
-                                : (sk - G.yoff * A.s) / A.c + G.xoff) - (double)A.hw;
-    int lo, hi;
-    step_range(start, A.slope, -(double)(NC + 1), (double)(nmin + 1), nmaj, lo, hi);
-    if (!valid) {
-        lo = nmaj;
-        hi = 0;
-    }
-    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
-    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
-    if (nparts > 1 && hi > lo) {
-        const int len = hi - lo;
-        const int l0 = lo + len * part / nparts;
-        hi = lo + len * (part + 1) / nparts;
-        lo = l0;
-    }
+    int l, h, lo, hi;
+    ray_steps<HORIZ>(G, A, sk, l, h);
     double acc = 0.0;
-    if (lo >= hi) return acc;
-    // Candidate q of step m is minor index floor(nf_m) + 1 + q.  nf carries the
-    // + 1 + PAD of the padded index, so the first candidate's padded index is
-    // trunc(nf) where nf >= 0.  A negative value (read as unsigned) or one past
-    // the row is clamped to omax: every read of that step then hits zero pads
-    // and, as all true candidates lie outside the image, the step contributes
-    // exactly 0.  The minor coordinate of candidate q is taken from the index
-    // actually read -- (o + q - PAD) - xoff for columns, yoff - (o + q - PAD)
-    // for rows, exact small half-integers -- which is the candidate's own
-    // coordinate whenever the read is not clamped.
-    const double* row = img - PAD;
+    if (!wave_steps_dev(l, h, valid, nmaj, part, nparts, lo, hi)) return acc;
+    const double start = walk_start<HORIZ>(G, A, sk);
+    const double fm = HORIZ ? A.s : A.c;   // factor of the per-candidate fma
     const double c2 = HORIZ ? G.yoff + (double)PAD : -(double)PAD - G.xoff;
     const double fM = HORIZ ? A.c : A.s;   // factor of the shared (major) product
     const double dM = HORIZ ? 1.0 : -1.0;  // major coordinate step
     double cM = HORIZ ? (double)lo - G.xoff : G.yoff - (double)lo;
     double nf = fma((double)lo, A.slope, start + (double)(1 + PAD));
-    const unsigned omax = (unsigned)(nmin + 2 * PAD - NC);
-    const double* rp = row + (size_t)lo * pitch;
-    // one major step: gather is issued by the caller, weights and sum here
-    auto step = [&](const double* v, unsigned o, double cMv) {
+    const int rowbytes = pitch * 8;
+    const char* rowp = reinterpret_cast<const char*>(img - PAD) + (size_t)lo * rowbytes;
+    auto step = [&](const double (&v)[NC], int o, double cMv) {
         const double P = cMv * fM;
         const double cm0 = HORIZ ? c2 - (double)o : (double)o + c2;
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             const double cm = HORIZ ? cm0 - (double)q : cm0 + (double)q;
             const double d = sk - fma(cm, fm, P);
-            acc = fma(chord_u<AXIS>(d, A.einv, A.inv), v[q], acc);
+            acc = fma(chord_u<true>(d, A.einv, A.inv), v[q], acc);
         }
     };
     int m = lo;
-    // two steps per iteration: both gathers are in flight before either step's math
-    for (; m + 1 < hi; m += 2) {
-        const unsigned o0 = min((unsigned)(int)nf, omax);
-        const unsigned o1 = min((unsigned)(int)(nf + A.slope), omax);
-        const double* p0 = at(rp, o0);
-        const double* p1 = at(rp + pitch, o1);
-        double v0[NC], v1[NC];
+    for (; m + U <= hi; m += U) {
+        int o[U];
+        double v[U][NC];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) v0[q] = p0[q];
+        for (int u = 0; u < U; ++u) {
+            o[u] = (int)nf;
+            row_load<double, NC>(row_ref(rowp + u * rowbytes, rowbytes), (unsigned)o[u], v[u]);
+            nf += A.slope;
+        }
 #pragma unroll
-        for (int q = 0; q < NC; ++q) v1[q] = p1[q];
-        step(v0, o0, cM);
-        step(v1, o1, cM + dM);
-        nf += 2.0 * A.slope;
-        cM += 2.0 * dM;
-        rp += 2 * pitch;
+        for (int u = 0; u < U; ++u) {
+            step(v[u], o[u], cM);
+            cM += dM;
+        }
+        rowp += U * rowbytes;
     }
-    if (m < hi) {
-        const unsigned o0 = min((unsigned)(int)nf, omax);
-        const double* p0 = at(rp, o0);
-        double v0[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) v0[q] = p0[q];
-        step(v0, o0, cM);
+    for (; m < hi; ++m) {
+        const int o = (int)nf;
+        double v[NC];
+        row_load<double, NC>(row_ref(rowp, rowbytes), (unsigned)o, v);
+        step(v, o, cM);
+        nf += A.slope;
+        cM += dM;
+        rowp += rowbytes;
     }
     return acc;
 }
@@ -241,81 +282,55 @@ __device__ __forceinline__ double ray_sum(const GeomDev& G, const AngleDev& A, d
 // |slope| starting at lp = b0 + m * slope (padded minor coordinate, pixel q
 // spanning [q, q + 1)), so it meets at most pixels floor(lp) and
 // floor(lp) + 1.  The share of the band's path length (wmax, applied by the
-// caller) in the first is f = clamp((floor(lp) + 1 - lp) / |slope|, 0, 1) and
-// the rest falls in the second: the exact chord lengths of the pixel model,
-// the same values chord_u * wmax gives up to rounding, with fewer operations
-// per step than evaluating the trapezoid per candidate.  Indices and the
-// step range are handled as in ray_sum: a truncated index below the row or
-// past it is clamped into the zero pads, where the pixels contribute 0.
+// caller) in the first is f = clamp((floor(lp) + 1 - lp) / |slope|, 0, 1) =
+// clamp((1 - fract(lp)) / |slope|, 0, 1) and the rest falls in the second:
+// the exact chord lengths of the pixel model, the same values chord_u * wmax
+// gives up to rounding.  lp advances by slope per step (its rounding error
+// stays ~1e-11 pixel over the longest walk).  A truncated index below the row
+// or past it reads 0, where the pixels contribute 0.  The longest waves set
+// the launch's length and their walk is bound by the latency of its chain of
+// gathers, so U steps' gathers are issued before their math.
 template <bool HORIZ>
 __device__ __forceinline__ double ray_split(const GeomDev& G, const AngleDev& A, double sk,
                                             const double* __restrict__ img, bool valid, int part,
                                             int nparts) {
     const int nmaj = HORIZ ? G.cols : G.rows;
-    const int nmin = HORIZ ? G.rows : G.cols;
     const int pitch = HORIZ ? G.pitchXT : G.pitchX;
-    const double start = (HORIZ ? G.yoff - (sk + G.xoff * A.c) / A.s
-                                : (sk - G.yoff * A.s) / A.c + G.xoff) - (double)A.hw;
-    int lo, hi;
-    step_range(start, A.slope, -(double)(A.nc + 1), (double)(nmin + 1), nmaj, lo, hi);
-    if (!valid) {
-        lo = nmaj;
-        hi = 0;
-    }
-    lo = __builtin_amdgcn_readfirstlane(wave_min(lo));
-    hi = __builtin_amdgcn_readfirstlane(wave_max(hi));
-    if (nparts > 1 && hi > lo) {
-        const int len = hi - lo;
-        const int l0 = lo + len * part / nparts;
-        hi = lo + len * (part + 1) / nparts;
-        lo = l0;
-    }
+    int l, h, lo, hi;
+    ray_steps<HORIZ>(G, A, sk, l, h);
     double acc = 0.0;
-    if (lo >= hi) return acc;
+    if (!wave_steps_dev(l, h, valid, nmaj, part, nparts, lo, hi)) return acc;
+    constexpr int U = 2;   // steps per iteration: their gathers are in flight together
     const double sig = A.slope;
     const double isg = 1.0 / fabs(sig);
-    // minor coordinate where the ray enters band 0 on its lower side, padded
-    const double b0 = (HORIZ ? G.yoff + 0.5 - (sk + (G.xoff + 0.5) * A.c) / A.s
-                             : (sk - (G.yoff + 0.5) * A.s) / A.c + G.xoff + 0.5) +
-                      fmin(sig, 0.0) + (double)PAD;
-    const unsigned omax = (unsigned)(nmin + 2 * PAD - 2);
-    const double* rp = img - PAD + (size_t)lo * pitch;
-    auto step = [&](const double* v, int fl, double lpv) {
-        const double f = fmin(fmax(fma(lpv - (double)fl, -isg, isg), 0.0), 1.0);
+    double lp = fma((double)lo, sig, split_b0<HORIZ>(G, A, sk));
+    const int rowbytes = pitch * 8;
+    const char* rowp = reinterpret_cast<const char*>(img - PAD) + (size_t)lo * rowbytes;
+    auto step = [&](const double (&v)[2], double lpv) {
+        const double f = fmin(fmax(fma(__builtin_amdgcn_fract(lpv), -isg, isg), 0.0), 1.0);
         acc += fma(f, v[0] - v[1], v[1]);
     };
-    double dm = (double)lo;
     int m = lo;
-    for (; m + 1 < hi; m += 2) {
-        const double lp0 = fma(dm, sig, b0), lp1 = lp0 + sig;
-        const int f0 = (int)lp0, f1 = (int)lp1;
-        const double* p0 = at(rp, min((unsigned)f0, omax));
-        const double* p1 = at(rp + pitch, min((unsigned)f1, omax));
-        const double v0[2] = {p0[0], p0[1]};
-        const double v1[2] = {p1[0], p1[1]};
-        step(v0, f0, lp0);
-        step(v1, f1, lp1);
-        dm += 2.0;
-        rp += 2 * pitch;
+    for (; m + U <= hi; m += U) {
+        double lpu[U], v[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            lpu[u] = lp;
+            row_load<double, 2>(row_ref(rowp + u * rowbytes, rowbytes), (unsigned)(int)lp, v[u]);
+            lp += sig;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) step(v[u], lpu[u]);
+        rowp += U * rowbytes;
     }
-    if (m < hi) {
-        const double lp0 = fma(dm, sig, b0);
-        const int f0 = (int)lp0;
-        const double* p0 = at(rp, min((unsigned)f0, omax));
-        const double v0[2] = {p0[0], p0[1]};
-        step(v0, f0, lp0);
+    for (; m < hi; ++m) {
+        double v[2];
+        row_load<double, 2>(row_ref(rowp, rowbytes), (unsigned)(int)lp, v);
+        step(v, lp);
+        lp += sig;
+        rowp += rowbytes;
     }
     return acc;
-}
-
-// Axis-parallel angles keep the per-candidate trapezoid (with its half weight
-// for a ray on a pixel edge); oblique ones split each band.
-template <bool HORIZ, bool AXIS>
-__device__ __forceinline__ double ray_sum_nc(const GeomDev& G, const AngleDev& A, double sk,
-                                             const double* __restrict__ img, bool valid,
-                                             int part, int nparts) {
-    if (AXIS) return ray_sum<HORIZ, true, 2>(G, A, sk, img, valid, part, nparts);
-    return ray_split<HORIZ>(G, A, sk, img, valid, part, nparts);
 }
 
 // Stores ray (row a, bin k): (R x)_{a,k}, or the residual r = R x - b when
@@ -351,49 +366,50 @@ __device__ __forceinline__ void project_store(const GeomDev& G, int a, double wm
     }
 }
 
-// Ray workgroups.  Wave w of virtual block blk = q * nag + ag takes angle
-// 4 ag + w of the class-sorted table and the 64 bins of chunk q, so the four
-// waves of a workgroup hold rays of nearly the same length.  Workgroup i of a
-// launch runs virtual block ord[i] (project_order: longest first, snaked over
-// the compute units).
-
-// Rays of virtual block blk.  With seg == nullptr each ray is
-// summed whole and stored by project_store (partials index blk).  Otherwise
+// Rays of ray workgroup wg: its wave w runs entry 4 wg + w of the wave table
+// (lane l one ray of it, see WaveDev).  With seg == nullptr each ray is summed
+// whole and stored by project_store (partials index wg).  Otherwise
 // (G.parts > 1) only part `part` of each ray is summed and its float64 value
-// goes to seg[(part*nA + ai)*nB + k]; the combine step adds the parts in
-// order.  Splitting the rays keeps the image rows that the resident waves
-// read close together and makes the work items shorter and more even.
+// goes to seg[(part*nA + ai)*nB + k] (ai: class-sorted table index); the
+// combine step adds the parts in order.  Splitting the rays keeps the image
+// rows that the resident waves read close together and makes the work items
+// shorter and more even.
 __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* __restrict__ ang,
+                                             const WaveDev* __restrict__ waves,
                                              const double* __restrict__ xp,
                                              const double* __restrict__ xTp,
                                              const float* __restrict__ b, float* __restrict__ out,
                                              int out_pitch, float* __restrict__ outp,
                                              double* __restrict__ outpd,
                                              double* __restrict__ partials,
-                                             double* __restrict__ seg, int blk, int part) {
-    const int nag = (G.nA + 3) >> 2;
-    const int ag = blk % nag, q = blk / nag;
-    const int ai = 4 * ag + (threadIdx.x >> 6);   // one angle per wave
-    const int k = q * 64 + (threadIdx.x & 63);
-    const bool valid = ai < G.nA && k < G.nB;
-    const AngleDev A = ang[ai < G.nA ? ai : G.nA - 1];
+                                             double* __restrict__ seg, int wg, int part) {
+    const int wi = 4 * wg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool wvalid = wi < G.nwaves;
+    const WaveDev W = waves[wvalid ? wi : 0];
+    int ai, k;
+    bool valid = wvalid && wave_ray(W, threadIdx.x & 63, G.nB, ai, k);
+    if (!valid) {   // no ray: a valid angle of the wave's class, summing nothing
+        ai = W.a0;
+        k = 0;
+    }
+    const AngleDev A = ang[ai];
+    const int flags = ang[W.a0].flags;   // the wave's class (wave-uniform)
     const double sk = bin_pos((double)k, G);
-    const bool horiz = A.flags & ANG_HORIZ, axis = A.flags & ANG_AXIS;
     const int np = seg ? G.parts : 1;
     double acc;
-    if (!horiz) {
-        acc = axis ? ray_sum_nc<false, true>(G, A, sk, xp + PAD, valid, part, np)
-                   : ray_sum_nc<false, false>(G, A, sk, xp + PAD, valid, part, np);
+    if (!(flags & ANG_HORIZ)) {
+        acc = (flags & ANG_AXIS) ? ray_sum_axis<false>(G, A, sk, xp + PAD, valid, part, np)
+                                 : ray_split<false>(G, A, sk, xp + PAD, valid, part, np);
     } else {
-        acc = axis ? ray_sum_nc<true, true>(G, A, sk, xTp + PAD, valid, part, np)
-                   : ray_sum_nc<true, false>(G, A, sk, xTp + PAD, valid, part, np);
+        acc = (flags & ANG_AXIS) ? ray_sum_axis<true>(G, A, sk, xTp + PAD, valid, part, np)
+                                 : ray_split<true>(G, A, sk, xTp + PAD, valid, part, np);
     }
     acc *= A.wmax;   // the ray sums u-weighted values (see chord_u)
     if (seg) {
         if (valid) seg[((size_t)part * G.nA + ai) * G.nB + k] = acc;
         return;
     }
-    project_store(G, A.row, A.wmax, k, valid, acc, b, out, out_pitch, outp, outpd, partials, blk);
+    project_store(G, A.row, A.wmax, k, valid, acc, b, out, out_pitch, outp, outpd, partials, wg);
 }
 
 // Sum of the parts of the rays of combine block (bx, by): angle bx of the
@@ -421,7 +437,8 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
                   by * gx + bx);
 }
 
-__global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
+__global__ __launch_bounds__(256, 8) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
+                                                 const WaveDev* __restrict__ waves,
                                                  const double* __restrict__ xp,
                                                  const double* __restrict__ xTp,
                                                  const float* __restrict__ b,
@@ -432,19 +449,20 @@ __global__ __launch_bounds__(256) void k_project(GeomDev G, const AngleDev* __re
                                                  const int* __restrict__ ord,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr,
+    project_body(G, ang, waves, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr,
                  ord[blockIdx.x], 0);
 }
 
-// grid (ray blocks, parts): blockIdx.y is the part, so the parts run in order.
-__global__ __launch_bounds__(256) void k_project_part(GeomDev G, const AngleDev* __restrict__ ang,
+// grid (ray workgroups, parts): blockIdx.y is the part, so the parts run in order.
+__global__ __launch_bounds__(256, 8) void k_project_part(GeomDev G, const AngleDev* __restrict__ ang,
+                                                      const WaveDev* __restrict__ waves,
                                                       const double* __restrict__ xp,
                                                       const double* __restrict__ xTp,
                                                       double* __restrict__ seg,
                                                       const int* __restrict__ ord,
                                                       const int* __restrict__ halt) {
     if (halt && *halt) return;
-    project_body(G, ang, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg,
+    project_body(G, ang, waves, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, nullptr, seg,
                  ord[blockIdx.x], blockIdx.y);
 }
 
@@ -462,23 +480,23 @@ __global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev*
 }
 
 // residual: rpd = R xh - b (float64) with f partials; else rp = R p.  Item
-// lin = part * project_ray_blocks(G) + i runs virtual block S.pord[i].
-__global__ __launch_bounds__(256) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
+// lin = part * G.nwg + i runs ray workgroup S.pord[i].
+__global__ __launch_bounds__(256, 8) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
                                                   int residual) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         if (G.parts > 1) {
-            const int nblk = project_ray_blocks(G);
-            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, nullptr,
-                         nullptr, nullptr, gmem(S.seg), cmem(S.pord)[lin % nblk], lin / nblk);
+            project_body(G, cmem(S.ang), cmem(S.pwave), gmem(S.xp), gmem(S.xTp), nullptr, nullptr,
+                         0, nullptr, nullptr, nullptr, gmem(S.seg), cmem(S.pord)[lin % G.nwg],
+                         lin / G.nwg);
         } else if (residual) {
-            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), gmem(S.b), nullptr, 0, nullptr,
-                         gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.pord)[lin], 0);
+            project_body(G, cmem(S.ang), cmem(S.pwave), gmem(S.xp), gmem(S.xTp), gmem(S.b), nullptr,
+                         0, nullptr, gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.pord)[lin], 0);
         } else {
-            project_body(G, cmem(S.ang), gmem(S.xp), gmem(S.xTp), nullptr, nullptr, 0, gmem(S.rp),
-                         nullptr, nullptr, nullptr, cmem(S.pord)[lin], 0);
+            project_body(G, cmem(S.ang), cmem(S.pwave), gmem(S.xp), gmem(S.xTp), nullptr, nullptr,
+                         0, gmem(S.rp), nullptr, nullptr, nullptr, cmem(S.pord)[lin], 0);
         }
     });
 }
@@ -508,85 +526,19 @@ void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable
                            residual ? 1 : 0);
 }
 
-int project_comb_blocks(const GeomDev& G) { return G.nA * ((G.nB + 255) / 256); }
-
-int project_blocks(const GeomDev& G) {
-    return G.parts > 1 ? project_comb_blocks(G) : project_ray_blocks(G);
-}
-
-int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_waves) {
-    // Large images: 8 parts keep the resident waves on a band of the float64
-    // copies (measured: 2048^2 x 2048 angles 9.3 -> 5.8 ms).
-    if ((long)rows * cols >= (1L << 21)) return 8;
-    // Otherwise split only a grid that would leave wave slots empty.
-    const long waves = (long)n_angles * ((n_bins + 63) / 64);
-    if (waves >= resident_waves) return 1;
-    const long p = (resident_waves + waves - 1) / waves;
-    return p > 4 ? 4 : (int)p;
-}
-
-// Step count of one wave of R: the union of its lanes' step ranges, found as
-// the kernel finds it (a lane's range is monotone in the bin index, so the
-// two end lanes of the chunk bound it).
-static long wave_steps(const GeomDev& G, const AngleDev& A, int k0, int k1) {
-    const bool horiz = A.flags & ANG_HORIZ;
-    const int nmaj = horiz ? G.cols : G.rows, nmin = horiz ? G.rows : G.cols;
-    int lo = nmaj, hi = 0;
-    for (int k : {k0, k1}) {
-        const double sk = std::fma((double)k, G.ds, G.s0);
-        const double start = (horiz ? G.yoff - (sk + G.xoff * A.c) / A.s
-                                    : (sk - G.yoff * A.s) / A.c + G.xoff) - (double)A.hw;
-        const double vlo = -(double)(A.nc + 1), vhi = (double)(nmin + 1);
-        int l, h;
-        if (A.slope == 0.0) {
-            l = 0;
-            h = nmaj;   // an axis-parallel chunk may straddle the image: count it whole
-        } else {
-            const double t0 = (vlo - start) / A.slope, t1 = (vhi - start) / A.slope;
-            const double tmin = std::min(std::max(std::min(t0, t1) - 1.0, 0.0), (double)nmaj);
-            const double tmax = std::min(std::max(std::max(t0, t1) + 2.0, 0.0), (double)nmaj);
-            l = (int)std::floor(tmin);
-            h = std::max(l, (int)std::ceil(tmax));
-        }
-        lo = std::min(lo, l);
-        hi = std::max(hi, h);
-    }
-    return hi > lo ? (long)(hi - lo) : 0;   // the split walk costs the same per step
-}
-
-std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>& tab,
-                                   int n_cu) {
-    const int nag = (G.nA + 3) / 4, nq = (G.nB + 63) / 64, nblk = nag * nq;
-    std::vector<long> cost((size_t)nblk, 0);
-    for (int q = 0; q < nq; ++q) {
-        const int k0 = q * 64, k1 = std::min(G.nB, k0 + 64) - 1;
-        for (int ai = 0; ai < G.nA; ++ai)
-            cost[(size_t)q * nag + ai / 4] += 16 + wave_steps(G, tab[(size_t)ai], k0, k1);
-    }
-    std::vector<int32_t> ord((size_t)nblk);
-    for (int b = 0; b < nblk; ++b) ord[(size_t)b] = b;
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
-    const int band = std::max(1, n_cu);
-    for (int b0 = band, i = 1; b0 < nblk; b0 += band, ++i)
-        if (i & 1) std::reverse(ord.begin() + b0, ord.begin() + std::min(nblk, b0 + band));
-    return ord;
-}
-
-void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
-                    const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* outpd, double* partials, double* seg, const int* ord,
+void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const WaveDev* waves,
+                    const double* xp, const double* xTp, const float* b, float* out, int out_pitch,
+                    float* outp, double* outpd, double* partials, double* seg, const int* ord,
                     const int* halt) {
-    const int nblk = project_ray_blocks(G);
     if (G.parts > 1) {
-        hipLaunchKernelGGL(k_project_part, dim3(nblk, G.parts), dim3(256), 0, st, G, ang, xp, xTp,
-                           seg, ord, halt);
+        hipLaunchKernelGGL(k_project_part, dim3(G.nwg, G.parts), dim3(256), 0, st, G, ang, waves, xp,
+                           xTp, seg, ord, halt);
         hipLaunchKernelGGL(k_project_comb, dim3(G.nA, (G.nB + 255) / 256), dim3(256), 0, st, G,
                            ang, (const double*)seg, b, out, out_pitch, outp, outpd, partials, halt);
         return;
     }
-    hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, st, G, ang, xp, xTp, b, out, out_pitch,
-                       outp, outpd, partials, ord, halt);
+    hipLaunchKernelGGL(k_project, dim3(G.nwg), dim3(256), 0, st, G, ang, waves, xp, xTp, b, out,
+                       out_pitch, outp, outpd, partials, ord, halt);
 }
 
 // Padded copy of a caller's sinogram for R^T, each row times its angle's wmax
@@ -609,71 +561,71 @@ void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, cons
     hipLaunchKernelGGL(k_pad_sino, dim3(G.nA), dim3(256), 0, st, G, ang, y, yp);
 }
 
-// Sum over the angles [beg, end) of one class for pixel (xj, yi).  The angle
-// and its sinogram row are wave-uniform (scalar loads); lanes differ only in
-// the pixel.  sk[PAD + k] = s_k = bin_pos(k) for the padded bin range (the
-// float64 values the projector computes per ray), read from LDS (LSK) or from
-// global memory, so a candidate's offset d is one subtraction.  The padded
-// sinogram rows arrive multiplied by their angle's wmax (project_store,
-// k_pad_sino), so each candidate adds u * y' with the u of chord_u: the same
-// weights as the projector's wmax * u.
+// ---- backward gather ----------------------------------------------------------
+// Sum over the angles [beg, end) of one class for pixel row yi and the PX
+// pixels xj[u] of this lane.  The angle and its sinogram row are wave-uniform
+// (scalar loads); lanes differ only in the pixel.  The padded sinogram rows
+// arrive multiplied by their angle's wmax (project_store, k_pad_sino), so each
+// candidate adds u * y' with the u of chord_u: the same weights as the
+// projector's wmax * u.
 //
-// Candidate window: bins floor(kf) + 1 .. floor(kf) + NB, kf = t / ds + kb
-// (A.kb also carries the + 1 + PAD of the padded index).  Truncation equals
-// floor for kf >= 0; a negative kf truncates to a value that, read as
-// unsigned, is either 0 or huge, and the clamp to kmax then points at zero
-// pads -- in both cases every true candidate lies outside the detector.  A
-// candidate that reads a pad gets a weight evaluated at the pad's position and
-// multiplies 0.
-// Each lane sums PX pixels of one row, (xj[0], yi) ... (xj[PX-1], yi): the
-// angle's uniform work (constants, yi s) is shared, the per-pixel sequence is
-// the one above.
-template <bool HORIZ, bool AXIS, int NB, bool LSK, class TY, int PX>
+// Candidate window: the NB bins from padded index trunc(kf), kf = t / ds + kb
+// with t = xj c + yi s (A.kb carries the - s0 / ds, the half-width hb of the
+// nonzero band plus a margin, and the + 1 + PAD of the padded index; see
+// bp_kf).  For oblique angles kf = fma(xj, c / ds, yi s / ds + kb), the
+// second term shared by the lane's pixels, and the first candidate's offset
+// s_k - t is dc - ds fract(kf) with dc = ds (1 - hb) (the same value as
+// s_k - t up to the rounding of kf, ~1e-13 pixel); the next ones follow by
+// + ds.  For axis-parallel angles the offset must be
+// exact -- a ray on a pixel edge takes half the pixel -- so s_k is formed from
+// the bin index as in bin_pos and t is exact.  A window index below the row
+// or past it reads 0 (pads and out-of-row reads), so such candidates add 0.
+template <bool AXIS, int NB, class TY, int PX>
 __device__ __forceinline__ void bp_class(const GeomDev& G, const AngleDev* __restrict__ ang,
                                          int beg, int end, const TY* __restrict__ yp,
-                                         const double* __restrict__ skg, const double* sks,
                                          const double* xj, double yi, double* acc) {
-    const unsigned kmax = (unsigned)(G.nB + 2 * PAD - NB);   // last padded start index
+    const int rowbytes = G.pitchB * (int)sizeof(TY);
     // 1/ds held in a vector register, so the index FMA's one scalar operand
     // can be the angle's kb (an FMA reads at most one scalar register)
     double ids = G.inv_ds;
     asm volatile("" : "+v"(ids));
+    double ds = G.ds;   // likewise for the offset FMA, whose addend is the angle's dc
+    asm volatile("" : "+v"(ds));
 #pragma unroll 2
     for (int a = beg; a < end; ++a) {
         const AngleDev A = ang[a];
-        const TY* row = yp + (size_t)A.row * G.pitchB;
-        double t[PX];
-        const double ys = yi * A.s;
-#pragma unroll
-        for (int u = 0; u < PX; ++u) t[u] = HORIZ ? fma(yi, A.s, xj[u] * A.c) : fma(xj[u], A.c, ys);
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(yp + (size_t)A.row * G.pitchB, rowbytes);
+        const double ys = AXIS ? yi * A.s : 0.0;
+        const double kc = AXIS ? 0.0 : bp_kc(yi, A);
         TY v[PX][NB];
-        double sk[PX][NB];
+        double d0[PX], tt[PX];
+        int oo[PX];
 #pragma unroll
         for (int u = 0; u < PX; ++u) {
-            const unsigned o = min((unsigned)(int)fma(t[u], ids, A.kb), kmax);
-            const TY* pv = at(row, o);
-            const double* ps = LSK ? sks + o : skg + o;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) v[u][q] = pv[q];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) sk[u][q] = ps[q];
+            double kf;
+            if (AXIS) {
+                tt[u] = fma(xj[u], A.c, ys);
+                kf = bp_kf(tt[u], ids, A.kb);
+            } else {
+                kf = bp_kf_oblique(xj[u], kc, A);
+            }
+            const int o = (int)kf;
+            row_load<TY, NB>(rs, (unsigned)o, v[u]);
+            if (AXIS) oo[u] = o;
+            else d0[u] = fma(__builtin_amdgcn_fract(kf), -ds, A.dc);
         }
 #pragma unroll
-        for (int u = 0; u < PX; ++u)   // the sinogram rows carry wmax: y' = wmax y
+        for (int u = 0; u < PX; ++u) {
+            double d = AXIS ? 0.0 : d0[u];
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
-                acc[u] = fma(chord_u<AXIS>(sk[u][q] - t[u], A.einv, A.inv), (double)v[u][q], acc[u]);
+            for (int q = 0; q < NB; ++q) {
+                if (AXIS) d = bin_pos((double)(oo[u] - PAD + q), G) - tt[u];
+                acc[u] = fma(chord_u<AXIS>(d, A.einv, A.inv), (double)v[u][q], acc[u]);
+                if (!AXIS) d += ds;
+            }
+        }
     }
 }
-
-// A workgroup owns a tile of 8 rows x 8 PX columns, PX pixels per lane 8
-// columns apart (PX = 2 or 4, chosen per launch).  Partial dot products are
-// kept per 8 x 16 sub-tile whatever PX is, so the result does not depend on it.
-constexpr int BP_TILE = 8;
-constexpr int BP_TW = 16;       // sub-tile width of the partials
-constexpr int BP_SPLIT = 4;     // waves per workgroup, each over a quarter of the angles
-// The bin-position table goes to LDS when it takes at most this many bytes.
-constexpr size_t BP_LDS_SK_MAX = 24 * 1024;
 
 __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int& e) {
     const int len = end - beg;
@@ -682,25 +634,19 @@ __device__ __forceinline__ void split_range(int beg, int end, int w, int& b, int
 }
 
 // out[i][j] = (R^T y)_{ij} from the padded sinogram yp; with dotv != nullptr
-// also the float64 partial sum of out * dotv per workgroup.  A workgroup owns
-// an 8 x 8PX pixel tile (PX pixels, 8 columns apart, per lane); its wave w
-// sums the w-th quarter of every angle class,
-// and the four partial sums are added in wave order through LDS.  With LSK the
-// workgroup first writes the bin-position table into the dynamic LDS `sks`.
-template <int NB, bool LSK, class TY, int PX>
+// also the float64 partial sum of out * dotv per 8 x 16 sub-tile.  A
+// workgroup owns an 8 x 8PX pixel tile (PX pixels, 8 columns apart, per lane);
+// its wave w sums the w-th quarter of every angle class, and the four partial
+// sums are added in wave order through LDS.
+template <int NB, class TY, int PX>
 __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDev* __restrict__ ang,
                                                  const TY* __restrict__ yp,
-                                                 const double* __restrict__ skg, double* sks,
                                                  float* __restrict__ out,
                                                  const double* __restrict__ dotv,
                                                  double* __restrict__ partials, int bx, int by) {
     constexpr int NS = PX / 2;   // 8 x 16 sub-tiles per tile
     __shared__ double part[BP_SPLIT][PX][64];
     __shared__ double red[4 * NS];
-    if (LSK) {
-        for (int k = threadIdx.x; k < G.nB + 2 * PAD; k += 256) sks[k] = bin_pos((double)(k - PAD), G);
-        __syncthreads();
-    }
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i = by * BP_TILE + (lane >> 3);
@@ -713,14 +659,10 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
         xj[u] = (double)(j0 + 8 * u) - G.xoff;
     }
     int b, e;
-    split_range(G.cls[0], G.cls[1], w, b, e);
-    bp_class<false, false, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
-    split_range(G.cls[1], G.cls[2], w, b, e);
-    bp_class<true, false, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
-    split_range(G.cls[2], G.cls[3], w, b, e);
-    bp_class<false, true, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
-    split_range(G.cls[3], G.cls[4], w, b, e);
-    bp_class<true, true, NB, LSK, TY, PX>(G, ang, b, e, yp, skg, sks, xj, yi, acc);
+    split_range(G.cls[0], G.cls[2], w, b, e);   // oblique angles of both orientations
+    bp_class<false, NB, TY, PX>(G, ang, b, e, yp, xj, yi, acc);
+    split_range(G.cls[2], G.cls[4], w, b, e);   // axis-parallel angles
+    bp_class<true, NB, TY, PX>(G, ang, b, e, yp, xj, yi, acc);
 #pragma unroll
     for (int u = 0; u < PX; ++u) part[w][u][lane] = acc[u];
     __syncthreads();
@@ -752,19 +694,16 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     }
 }
 
-template <int NB, bool LSK, class TY, int PX>
+template <int NB, class TY, int PX>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
                                                      const TY* __restrict__ yp,
-                                                     const double* __restrict__ skg,
                                                      float* __restrict__ out,
                                                      const double* __restrict__ dotv,
                                                      double* __restrict__ partials,
                                                      ScalarRide ride,
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
-    extern __shared__ double sks[];
-    backproject_body<NB, LSK, TY, PX>(G, ang, yp, skg, sks, out, dotv, partials, blockIdx.x,
-                                      blockIdx.y);
+    backproject_body<NB, TY, PX>(G, ang, yp, out, dotv, partials, blockIdx.x, blockIdx.y);
     if (ride.sc && blockIdx.x == 0 && blockIdx.y == 0) {
         if (ride.ps) scalar_body(OP_SNORM, ride.sc, ride.tr, ride.ps, ride.ns, nullptr, 0);
         if (ride.pf) scalar_body(OP_F, ride.sc, ride.tr, ride.pf, ride.nf, nullptr, 0);
@@ -774,10 +713,9 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
 // TY = float: h = R^T rp (rp = R p) with the partials of h^T p; TY = double:
 // g = R^T rpd from the float64 residual.  NB is the largest candidate count of
 // the batch (extra candidates weigh exactly 0).
-template <int NB, bool LSK, class TY, int PX>
+template <int NB, class TY, int PX>
 __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, ItemTable t) {
     constexpr bool normal = sizeof(TY) == sizeof(float);
-    extern __shared__ double sks[];
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
@@ -786,98 +724,57 @@ __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict
         const TY* yp;
         if constexpr (normal) yp = gmem(S.rp);
         else yp = gmem(S.rpd);
-        backproject_body<NB, LSK, TY, PX>(G, cmem(S.ang), yp, gmem(S.skp), sks,
-                                      gmem(normal ? S.h : S.g), normal ? gmem(S.p) : nullptr,
-                                      normal ? gmem(S.pph) : nullptr, lin % gx, lin / gx);
+        backproject_body<NB, TY, PX>(G, cmem(S.ang), yp, gmem(normal ? S.h : S.g),
+                                     normal ? gmem(S.p) : nullptr, normal ? gmem(S.pph) : nullptr,
+                                     lin % gx, lin / gx);
     });
 }
 
-size_t bp_lds_bytes(int nbins) {
-    const size_t b = ((size_t)nbins + 2 * PAD) * sizeof(double);
-    return b <= BP_LDS_SK_MAX ? b : 0;
-}
-
-template <bool LSK, class TY, int PX>
-void launch_bp_b_px(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, size_t lds) {
+template <class TY, int PX>
+void launch_bp_b_px(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax) {
     switch (nbmax) {
-    case 1: hipLaunchKernelGGL((kb_backproject<1, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
-    case 2: hipLaunchKernelGGL((kb_backproject<2, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
-    case 3: hipLaunchKernelGGL((kb_backproject<3, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
-    default: hipLaunchKernelGGL((kb_backproject<4, LSK, TY, PX>), dim3(t.grid), dim3(256), lds, st, sl, t); break;
+    case 1: hipLaunchKernelGGL((kb_backproject<1, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
+    case 2: hipLaunchKernelGGL((kb_backproject<2, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
+    case 3: hipLaunchKernelGGL((kb_backproject<3, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
+    default: hipLaunchKernelGGL((kb_backproject<4, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
     }
 }
 
-template <bool LSK, class TY>
-void launch_bp_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, size_t lds, int px) {
-    if (px == 4) launch_bp_b_px<LSK, TY, 4>(st, sl, t, nbmax, lds);
-    else launch_bp_b_px<LSK, TY, 2>(st, sl, t, nbmax, lds);
-}
-
-void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
-                          bool normal, int px) {
-    const size_t lds = bp_lds_bytes(max_bins);
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal,
+                          int px) {
     if (normal) {
-        if (lds) launch_bp_b<true, float>(st, sl, t, nbmax, lds, px);
-        else launch_bp_b<false, float>(st, sl, t, nbmax, 0, px);
+        if (px == 4) launch_bp_b_px<float, 4>(st, sl, t, nbmax);
+        else launch_bp_b_px<float, 2>(st, sl, t, nbmax);
     } else {
-        if (lds) launch_bp_b<true, double>(st, sl, t, nbmax, lds, px);
-        else launch_bp_b<false, double>(st, sl, t, nbmax, 0, px);
+        if (px == 4) launch_bp_b_px<double, 4>(st, sl, t, nbmax);
+        else launch_bp_b_px<double, 2>(st, sl, t, nbmax);
     }
 }
 
-int backproject_blocks(const GeomDev& G) {
-    return ((G.cols + BP_TW - 1) / BP_TW) * ((G.rows + BP_TILE - 1) / BP_TILE);
-}
-
-int backproject_tiles(const GeomDev& G, int px) {
-    return ((G.cols + 8 * px - 1) / (8 * px)) * ((G.rows + BP_TILE - 1) / BP_TILE);
-}
-
-int backproject_px(int rows, int cols, int resident_waves) {
-    // four pixels per lane amortise more of each angle's work but need ~100
-    // VGPRs (4 waves per SIMD): take them when the 4-pixel grid still gives
-    // every SIMD four waves
-    GeomDev G{};
-    G.rows = rows;
-    G.cols = cols;
-    return (long)backproject_tiles(G, 4) * BP_SPLIT >= resident_waves / 2 ? 4 : 2;
-}
-
-template <bool LSK, class TY, int PX>
-void launch_bp_px(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp,
-                  const double* skp, float* out, const double* dotv, double* partials,
-                  const int* halt, size_t lds, const ScalarRide& ride) {
+template <class TY, int PX>
+void launch_bp_px(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp, float* out,
+                  const double* dotv, double* partials, const int* halt, const ScalarRide& ride) {
     dim3 grid((G.cols + 8 * PX - 1) / (8 * PX), (G.rows + BP_TILE - 1) / BP_TILE);
     switch (G.nbmax) {
-    case 1: hipLaunchKernelGGL((k_backproject<1, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
-    case 2: hipLaunchKernelGGL((k_backproject<2, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
-    case 3: hipLaunchKernelGGL((k_backproject<3, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
-    default: hipLaunchKernelGGL((k_backproject<4, LSK, TY, PX>), grid, dim3(256), lds, st, G, ang, yp, skp, out, dotv, partials, ride, halt); break;
+    case 1: hipLaunchKernelGGL((k_backproject<1, TY, PX>), grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, ride, halt); break;
+    case 2: hipLaunchKernelGGL((k_backproject<2, TY, PX>), grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, ride, halt); break;
+    case 3: hipLaunchKernelGGL((k_backproject<3, TY, PX>), grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, ride, halt); break;
+    default: hipLaunchKernelGGL((k_backproject<4, TY, PX>), grid, dim3(256), 0, st, G, ang, yp, out, dotv, partials, ride, halt); break;
     }
-}
-
-template <bool LSK, class TY>
-void launch_bp(hipStream_t st, const GeomDev& G, const AngleDev* ang, const TY* yp,
-               const double* skp, float* out, const double* dotv, double* partials, const int* halt,
-               size_t lds, const ScalarRide& ride) {
-    if (G.bp_px == 4) launch_bp_px<LSK, TY, 4>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
-    else launch_bp_px<LSK, TY, 2>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
 }
 
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
-                        const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt, const ScalarRide& ride) {
-    const size_t lds = bp_lds_bytes(G.nB);
-    if (lds) launch_bp<true, float>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
-    else launch_bp<false, float>(st, G, ang, yp, skp, out, dotv, partials, halt, 0, ride);
+                        float* out, const double* dotv, double* partials, const int* halt,
+                        const ScalarRide& ride) {
+    if (G.bp_px == 4) launch_bp_px<float, 4>(st, G, ang, yp, out, dotv, partials, halt, ride);
+    else launch_bp_px<float, 2>(st, G, ang, yp, out, dotv, partials, halt, ride);
 }
 
 void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
-                        const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt, const ScalarRide& ride) {
-    const size_t lds = bp_lds_bytes(G.nB);
-    if (lds) launch_bp<true, double>(st, G, ang, yp, skp, out, dotv, partials, halt, lds, ride);
-    else launch_bp<false, double>(st, G, ang, yp, skp, out, dotv, partials, halt, 0, ride);
+                        float* out, const double* dotv, double* partials, const int* halt,
+                        const ScalarRide& ride) {
+    if (G.bp_px == 4) launch_bp_px<double, 4>(st, G, ang, yp, out, dotv, partials, halt, ride);
+    else launch_bp_px<double, 2>(st, G, ang, yp, out, dotv, partials, halt, ride);
 }
 
 }  // namespace sp

@@ -9,6 +9,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "../../include/suppcg.h"
+
 namespace sp {
 
 // Zero columns kept on each side of every padded image row and sinogram row.
@@ -25,8 +27,11 @@ struct alignas(16) AngleDev {
     double einv;      // e * inv with e = (|c| + |s|) / 2
     double inv;       // 1 / min(|c|, |s|)   (0 for axis-parallel angles)
     double wmax;      // 1 / max(|c|, |s|): the largest chord, the factor of u
-    double slope;     // forward walk: minor index per major step (selection only)
+    double slope;     // forward walk: minor index per major step
     double kb;        // backprojection: -s0/ds - hb + 1 + PAD, hb = e/ds + margin (selection only)
+    double dc;        // backprojection: ds (1 - hb), the offset s_k - t of a pixel's first
+                      // candidate bin when its window index kf is an integer
+    double cids, sids;  // backprojection: c / ds and s / ds (oblique window index)
     float hw;         // forward walk: half-width of the nonzero band on the minor axis + margin
     int32_t row;      // sinogram row of this angle (the table is sorted by class)
     int32_t flags;    // bit0 axis-parallel, bit1 walk columns (|s| > |c|)
@@ -43,7 +48,6 @@ struct GeomDev {
     double ds, s0;      // bin spacing and position of bin 0, pixel units
     double inv_ds;
     double pixel;       // weights are in pixel units; outputs are scaled by this
-    float xoff_f, yoff_f, ds_f, s0_f;   // float copies for candidate selection
     int pitchX;         // cols + 2 PAD: row pitch of the padded image copy
     int pitchXT;        // rows + 2 PAD: row pitch of the padded transposed copy
     int pitchB;         // nB + 2 PAD: row pitch of the padded sinogram
@@ -52,6 +56,18 @@ struct GeomDev {
     int bp_px;          // pixels per lane of R^T (2 or 4, see backproject_px)
     int cls[5];         // angle-table class boundaries: vertical, horizontal,
                         // vertical axis, horizontal axis
+    int nwaves;         // waves of R's wave table (see WaveDev)
+    int nwg;            // R's ray workgroups, four waves each: ceil(nwaves / 4)
+};
+
+// One wave of R: 64 rays, one per lane.  A full wave holds 64 consecutive bins
+// of one angle: lane l takes angle a0 and bin k0 + l.  A tail wave packs the
+// last nB % 64 bins of consecutive angles of one class: the class's tail rays,
+// angle by angle, form a stream, and lane l takes its entry k0 + l, i.e. angle
+// a0 + (k0 + l) / r and bin nB - r + (k0 + l) % r with r = nB % 64, while that
+// angle lies before aend.  Angles are indices of the class-sorted table.
+struct WaveDev {
+    int32_t a0, k0, aend, tail;
 };
 
 // Device-resident solver state.  Written only by single-workgroup kernels
@@ -124,13 +140,13 @@ struct ScalarRide {
 // axis-parallel angles wmax = 1 and u is 1 inside the pixel's column, 1/2 on
 // its edge and 0 outside.
 template <bool AXIS>
-__device__ __forceinline__ double chord_u(double d, double einv, double inv) {
+__host__ __device__ inline double chord_u(double d, double einv, double inv) {
     const double ad = fabs(d);
     if (AXIS) return ad < 0.5 ? 1.0 : (ad == 0.5 ? 0.5 : 0.0);
     return fmin(fmax(fma(-ad, inv, einv), 0.0), 1.0);
 }
 
-__device__ __forceinline__ double bin_pos(double k, const GeomDev& G) { return fma(k, G.ds, G.s0); }
+__host__ __device__ inline double bin_pos(double k, const GeomDev& G) { return fma(k, G.ds, G.s0); }
 
 // ---- allocation-free entry point (noalloc.hip) ---------------------------------
 // Bytes of the static per-GPU scratch array and the largest angle count the
@@ -154,44 +170,68 @@ void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, 
 // With G.parts > 1, seg (parts * nA * nB float64) receives the per-part sums
 // before they are combined.  outp / outpd: float32 / float64 padded sinograms
 // (nullable); the residual's float64 values feed R^T without a float32
-// rounding (its cancellation in R^T r amplifies that rounding).  ord: the
-// device copy of project_order(G, ...), the virtual block each workgroup runs.
-void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* xp,
-                    const double* xTp, const float* b, float* out, int out_pitch, float* outp,
-                    double* outpd, double* partials, double* seg, const int* ord,
+// rounding (its cancellation in R^T r amplifies that rounding).  waves: the
+// device copy of R's wave table (project_waves); ord: the device copy of
+// project_order(G, ...), the ray workgroup each launched workgroup runs.
+void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const WaveDev* waves,
+                    const double* xp, const double* xTp, const float* b, float* out, int out_pitch,
+                    float* outp, double* outpd, double* partials, double* seg, const int* ord,
                     const int* halt);
-// Workgroups of one part of R: four angles by one 64-bin chunk each.
-__host__ __device__ inline int project_ray_blocks(const GeomDev& G) {
-    return ((G.nA + 3) / 4) * ((G.nB + 63) / 64);
-}
+// Padded copy of y for R^T with each row scaled by its angle's wmax.
+void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* y,
+                     float* yp);
+// ride: scalar steps workgroup (0, 0) runs after its tile (see ScalarRide).
+void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
+                        float* out, const double* dotv, double* partials, const int* halt,
+                        const ScalarRide& ride = ScalarRide{});
+void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
+                        float* out, const double* dotv, double* partials, const int* halt,
+                        const ScalarRide& ride = ScalarRide{});
+
+// R^T's workgroup: a tile of BP_TILE rows by 8 PX columns, BP_SPLIT waves each
+// over a share of the angles; dot-product partials per BP_TILE x BP_TW sub-tile.
+constexpr int BP_TILE = 8;
+constexpr int BP_TW = 16;
+constexpr int BP_SPLIT = 4;
+
+// ---- host geometry (geometry.cpp) ------------------------------------------------
+// cos/sin of angle index a, exact at multiples of pi/4.
+void angle_cos_sin(const sp_geometry& g, int a, double& co, double& si);
+// Chord and selection constants of angle a.
+AngleDev angle_entry(const sp_geometry& g, int a, double ds, double s0, double margin);
+// 0 vertical oblique, 1 horizontal oblique, 2 vertical axis, 3 horizontal axis.
+int angle_class(const AngleDev& A);
+// Device geometry and the class-sorted angle table (n_angles entries written
+// to tab) of a validated geometry, for a device of n_cu compute units;
+// allocates nothing.  SP_ERR_ARG with a message in err for geometries the
+// kernels do not support.
+int build_geometry_into(const sp_geometry* g, int n_cu, GeomDev& G, AngleDev* tab, char* err,
+                        size_t errlen);
+// Bin positions of the padded bin range: t[PAD + k] = s_k, k = -PAD .. nB + PAD - 1.
+void bin_sk_fill(const GeomDev& G, double* t);
+// R's wave table: its size and its entries (G.nwaves of them), chunk by
+// chunk: each class's angles in groups of four for one 64-bin chunk, and in
+// the last chunk (when nB % 64 != 0) the oblique classes' packed tail waves.
+int project_wave_count(const GeomDev& G);
+void project_waves(const GeomDev& G, WaveDev* out);
+// Steps a wave of R walks: the union of its lanes' nonempty step ranges.
+long wave_steps(const GeomDev& G, const AngleDev* tab, const WaveDev& W);
+// Dispatch order of R's ray workgroups (G.nwg entries, a permutation):
+// workgroups by decreasing step count, with every other band of n_cu entries
+// reversed so the first workgroups of each compute unit sum to about the same
+// work.  Only the order of the work changes; every sum and its partials index
+// stay the same.
+std::vector<int32_t> project_order(const GeomDev& G, const AngleDev* tab, const WaveDev* waves,
+                                   int n_cu);
+// Parts R splits each ray's step range into, chosen from the geometry and the
+// device's wave slots (both the single-slice and the batched solver use it,
+// so their sums agree).
+int project_parts(int rows, int cols, int nwaves, int resident_waves);
 // Combine workgroups (G.parts > 1): one angle by one 256-bin chunk each.
 int project_comb_blocks(const GeomDev& G);
 // Number of float64 f partials R's residual form writes: one per combine
 // workgroup when the rays are split in parts, else one per ray workgroup.
 int project_blocks(const GeomDev& G);
-// Parts R splits each ray's step range into, chosen from the geometry and
-// the device's wave slots (both the single-slice and the batched solver use
-// it, so their sums agree).
-int project_parts(int rows, int cols, int n_angles, int n_bins, int resident_waves);
-// Dispatch order of R's ray workgroups (project_ray_blocks(G) entries, a
-// permutation): virtual blocks by decreasing step count, with every other
-// band of n_cu entries reversed so the first workgroups of each compute unit
-// sum to about the same work.  Only the order of the work changes; every sum
-// and its partials index stay the same.
-std::vector<int32_t> project_order(const GeomDev& G, const std::vector<AngleDev>& tab, int n_cu);
-// Padded copy of y for R^T with each row scaled by its angle's wmax.
-void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* y,
-                     float* yp);
-// skp: float64 bin positions of the padded bin range, skp[PAD + k] = s_k
-// (bin_sk_table fills it on the host with the same fma as bin_pos); used when
-// the table is too large for the backprojector's LDS copy.
-// ride: scalar steps workgroup (0, 0) runs after its tile (see ScalarRide).
-void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* yp,
-                        const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt, const ScalarRide& ride = ScalarRide{});
-void launch_backproject(hipStream_t st, const GeomDev& G, const AngleDev* ang, const double* yp,
-                        const double* skp, float* out, const double* dotv, double* partials,
-                        const int* halt, const ScalarRide& ride = ScalarRide{});
 // Number of R^T's float64 dot partials: one per 8 x 16 pixel sub-tile.
 int backproject_blocks(const GeomDev& G);
 // R^T workgroups (8 x 8 px pixel tiles) for px pixels per lane.
@@ -293,7 +333,7 @@ struct SliceDev {
     GeomDev G;
     FFTPlan F;
     const AngleDev* ang;
-    const double* skp;  // padded bin positions
+    const WaveDev* pwave;   // R's wave table
     const float* b;
     const float* x0;   // nullable: zero start
     double *xh, *x, *p;  // iterate, x_{k+1/2} and search direction (float64)
@@ -302,7 +342,7 @@ struct SliceDev {
     float* rp;          // padded sinogram (R p)
     double* rpd;        // float64 padded sinogram (residual)
     double* seg;        // R's per-part ray sums, [parts][nA][nB] (G.parts > 1)
-    const int* pord;    // R's workgroup order (project_order)
+    const int* pord;    // R's ray-workgroup order (project_order)
     double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
     Scalars* sc;
     TraceDev tr;
@@ -355,8 +395,8 @@ __device__ __forceinline__ double* batch_vec(const SliceDev& S, int which) {
 void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which);
 void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable tc, bool residual);
 // px: pixels per lane of every slice in the launch (their G.bp_px).
-void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int max_bins,
-                          bool normal, int px);
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal,
+                          int px);
 // fft.hip (z = M g; with the partials of z^T h into pzh)
 void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTable cols,
                       size_t lds_rows, size_t lds_cols, double mu, double rho);

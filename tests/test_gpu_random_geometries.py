@@ -12,7 +12,7 @@ import pytest
 
 from oracle import projector as oproj
 from oracle.geometry import Geometry as OG
-from tests._problems import rel_l2
+from tests._problems import random_geometries, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -25,24 +25,6 @@ def sp():
         pytest.skip("no GPU")
     import paper_1807_10151_amd as sp_mod
     return sp_mod
-
-
-def random_geometries(n, seed=2024):
-    rng = np.random.default_rng(seed)
-    out = []
-    for _ in range(n):
-        rows, cols = (int(v) for v in rng.integers(1, 161, 2))
-        n_angles = int(rng.integers(1, 121))
-        pixel = 1.0 if rng.random() < 0.5 else float(rng.uniform(0.5, 1.5))
-        spacing = pixel * float(rng.uniform(0.6, 1.6))
-        diag = math.hypot(rows, cols) * pixel
-        n_bins = int(rng.integers(max(1, int(0.3 * diag / spacing)), int(1.2 * diag / spacing) + 3))
-        theta0 = float(rng.uniform(0.0, math.pi))
-        dtheta = math.pi / n_angles if rng.random() < 0.5 else float(rng.uniform(0.01, 0.5))
-        offset = float(rng.uniform(-3.0, 3.0)) * spacing
-        out.append(OG(rows, cols, n_angles, n_bins, pixel=pixel, theta0=theta0, dtheta=dtheta,
-                      bin_spacing=spacing, bin_offset=offset))
-    return out
 
 
 GEOMS = random_geometries(24) + [
