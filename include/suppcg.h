@@ -189,12 +189,11 @@ int sp_backproject(sp_ctx* ctx, const sp_geometry* g, const float* y, float* x);
 /* sp_backproject for callers that cannot allocate device memory (code being
  * captured into a HIP graph, tight serving loops, harnesses that forbid
  * hipMalloc): the same x = R^T y, bit for bit, with the context's workspace
- * replaced by one static 32 MiB scratch array per GPU (the angle table, the
- * bin positions and the padded, wmax-scaled sinogram; held until the process
- * ends).  The call allocates no device or host memory.  It needs
- * n_angles <= 8192 and n_angles * 80 + (n_bins + 8) * 8 + n_angles *
- * (n_bins + 8) * 4 bytes (each of the first two rounded up to 256) to fit in
- * the 32 MiB, else SP_ERR_ARG and nothing is enqueued.  Every call on a GPU
+ * replaced by one static 32 MiB scratch array per GPU (the angle table and
+ * the padded, wmax-scaled sinogram; held until the process ends).  The call
+ * allocates no device or host memory.  It needs n_angles <= 8192 and
+ * n_angles * 96 (rounded up to 256) + n_angles * (n_bins + 8) * 4 bytes to
+ * fit in the 32 MiB, else SP_ERR_ARG and nothing is enqueued.  Every call on a GPU
  * shares that GPU's array and rewrites it whole; calls that overlap on one
  * GPU (other streams, other contexts, other threads) race and must be
  * ordered by the caller.  y: [n_angles][n_bins], x: [rows][cols] (device). */
