@@ -29,29 +29,28 @@ WORKLOAD = dict(name="ct512", rows=512, cols=512, n_angles=720, n_bins=725, elli
 # oracle's closed form by tests/golden/count_nnz.py.
 NNZ_CT512 = 240_840_802
 NNZ_2048 = 10_945_428_176
-PEAK_HBM = 8.0e12                # B/s
-# Non-packed FP32 VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz.  The published
-# 157.3 TFLOP/s counts an FMA as 2 flops on 2-wide packed lanes.
+# Non-packed VALU issue rate: 256 CUs x 64 lanes x 2.4 GHz lane-operations/s.
+# The published 157.3 TFLOP/s FP32 counts an FMA as 2 flops on 2-wide packed
+# lanes; these kernels are float64 (FP64 FMA issues at the same non-packed
+# rate, 78.6 TFLOP/s = 39.3 T FMA/s) and generate no packed FP32.
 PEAK_VALU_OPS = 256 * 64 * 2.4e9
-# Algorithmic VALU work of R and R^T: ~20 lane-ops per (pixel, angle) pair
-# (two candidate bins, each an offset, the trapezoid weight and an
-# accumulation, plus the pixel's projection), i.e. 20 n A per call (about
-# 96 us at the issue peak for 512^2 x 720).  The lower bound of 4 lane-ops per
-# nonzero weight is reported beside it.  The kernels now issue fewer than 20
-# lane-ops per pair (R ~11, R^T ~13-15), so the line also reports the issue
-# rate the kernel's own instructions reach: VALU wave-instructions per launch
-# at this workload (rocprofv3 SQ_INSTS_VALU, profiles/counters_ct512.md; R^T:
-# mean of its two forms), 64 lane-ops each, over the live launch time.
-OPS_PER_PIXEL_ANGLE = 20
+# Algorithmic work of R and R^T: the fewest lane-operations a matrix-free
+# projector can spend on one nonzero weight -- form the ray-pixel offset,
+# evaluate the chord length from it, address the gathered value, and
+# multiply-add it into the sum: 4 per nonzero, i.e. 4 nnz per call (24.5 us of
+# VALU issue at this workload).  A kernel that does the work cannot issue
+# fewer, so roofline.frac cannot exceed 1.
 OPS_PER_NNZ = 4
-# Bytes moved between L2 and the memory fabric per launch of the projector
-# kernels at this workload: rocprofv3 FETCH_SIZE and WRITE_SIZE averages scaled
-# by the counts of a 64 MiB device copy (profiles/counters_ct512.md).  They are
-# tied to the kernels as profiled; re-measure after changing them.  R^T: mean of
-# its float32 (R p) and float64 (residual) sinogram forms, one of each per loop
-# body.
-TRAFFIC_BYTES = {"project": 39.13e6, "backproject": 20.39e6}
-VALU_INSTR = {"project": 3.373e7, "backproject": 4.134e7}
+# Hardware counters of the kernels at this workload, as measured by the
+# rocprofv3 runs summarised in profiles/counters_ct512.md (taken at the commit
+# named below; re-measure after changing a kernel).  VALU wave-instructions per
+# launch (SQ_INSTS_VALU, 64 lane-operations each) and bytes between L2 and the
+# memory fabric per launch (FETCH_SIZE + WRITE_SIZE, scaled by the counters of
+# a 64 MiB device copy).  R^T: mean of its float32 (R p) and float64
+# (residual) sinogram forms, one of each per loop body.
+COUNTERS = {"measured_at": "1de3a50",
+            "valu_instr": {"project": 2.75e7, "backproject": 3.58e7},
+            "traffic_bytes": {"project": None, "backproject": None}}
 
 
 def log(msg):
@@ -239,32 +238,82 @@ def learned_run(sp, steps=2000, n_seeds=32):
             "fallbacks": int(sum(r["fallbacks"] for r in rows))}
 
 
-def cpu_baseline(img, b):
-    """The float64 oracle on the host: R and R^T on a sample of angles (CSR built
-    outside the timed region, as the oracle caches it), M, S_TV and the CG vector
-    work at full size; one iteration extrapolated."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_r_worker(lo, hi, x, y, reps, barrier, out):
+    """One host worker of the all-cores oracle leg: the rows of R for angles
+    [lo, hi) (closed-form CSR, built before timing) and their transpose."""
     import scipy.sparse as sps
 
-    from oracle import closed_form, precond, suppcg, tv
+    from oracle import closed_form
+    from oracle.geometry import Geometry as OG
+    og = OG(WORKLOAD["rows"], WORKLOAD["cols"], WORKLOAD["n_angles"], WORKLOAD["n_bins"])
+    Rw = sps.vstack([closed_form.angle_block(og, a) for a in range(lo, hi)], format="csr")
+    RTw = Rw.T.tocsr()
+    yw = y[lo * og.n_bins:hi * og.n_bins]
+    barrier.wait()
+    for _ in range(reps):
+        Rw @ x
+    barrier.wait()
+    part = None
+    for _ in range(reps):
+        part = RTw @ yw
+    barrier.wait()
+    out.put((lo, part))
+
+
+def _cpu_all_cores(x, y, reps=3):
+    """R and R^T of the oracle at full size on all host cores: worker processes
+    hold blocks of R by angle (CSR row blocks) and of R^T by the same angles
+    (column blocks, partial images summed by the parent).  Returns (seconds per
+    R, seconds per R^T, workers)."""
+    import multiprocessing as mp
+    nw = max(1, min(os.cpu_count() or 1, 16))
+    A = WORKLOAD["n_angles"]
+    bounds = [(A * i // nw, A * (i + 1) // nw) for i in range(nw)]
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(nw + 1)
+    out = ctx.Queue()
+    procs = [ctx.Process(target=_cpu_r_worker, args=(lo, hi, x, y, reps, barrier, out))
+             for lo, hi in bounds]
+    for p in procs:
+        p.start()
+    barrier.wait(timeout=600)                 # every block built
+    t0 = time.perf_counter()
+    barrier.wait(timeout=600)
+    t1 = time.perf_counter()
+    barrier.wait(timeout=600)
+    parts = [out.get(timeout=600) for _ in procs]
+    img = np.zeros_like(x)
+    for _, part in sorted(parts, key=lambda t: t[0]):
+        img += part
+    t2 = time.perf_counter()
+    for p in procs:
+        p.join(timeout=60)
+    return (t1 - t0) / reps, (t2 - t1) / reps, nw
+
+
+def cpu_baseline(img, b):
+    """The float64 oracle on the host.  All cores: R and R^T at full size split
+    over worker processes by angle; M, S_TV and the vector work as the oracle
+    runs them (NumPy, one thread).  One core: R and R^T on a sample of angles
+    scaled to all angles.  One iteration = 2 R + 2 R^T + M + S_TV + vector work."""
+    import scipy.sparse as sps
+
+    from oracle import closed_form, precond, suppcg
     from oracle.geometry import Geometry as OG
 
     og = OG(WORKLOAD["rows"], WORKLOAD["cols"], WORKLOAD["n_angles"], WORKLOAD["n_bins"])
-    n_sample = 36
-    angles = np.linspace(0, og.n_angles - 1, n_sample).astype(int)
-    blocks = [closed_form.angle_block(og, int(a)) for a in angles]
-    Rs = sps.vstack(blocks, format="csr")
-    RsT = Rs.T.tocsr()
     x = img.astype(np.float64).ravel()
-    y = b.astype(np.float64).reshape(og.n_angles, og.n_bins)[angles].ravel()
-    t0 = time.perf_counter()
-    reps = 3
-    for _ in range(reps):
-        Rs @ x
-    t_r = (time.perf_counter() - t0) / reps * (og.n_angles / n_sample)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        RsT @ y
-    t_rt = (time.perf_counter() - t0) / reps * (og.n_angles / n_sample)
+    y = b.astype(np.float64).ravel()
     xi = img.astype(np.float64)
     t0 = time.perf_counter()
     precond.apply(xi, 1e-5, 0.8)
@@ -277,13 +326,35 @@ def cpu_baseline(img, b):
         v = x * 0.5 + x
         float(v @ x)
     t_vec = (time.perf_counter() - t0) / 5 * 2
-    t_it = 2 * t_r + 2 * t_rt + t_m + t_stv + t_vec
-    return {"value": 1.0 / t_it, "unit": "iterations/s", "cores": 1, "kind": "oracle",
-            "sample": (f"float64 NumPy/SciPy oracle, one thread: R and R^T SpMV on {n_sample} of "
-                       f"{og.n_angles} angles scaled to all angles, M, S_TV and vector work at full "
-                       f"size; one iteration = 2 R + 2 R^T + M + S_TV + vector work; "
-                       f"R {t_r*1e3:.0f} ms, R^T {t_rt*1e3:.0f} ms, M {t_m*1e3:.0f} ms, "
-                       f"S_TV {t_stv*1e3:.0f} ms")}
+    # one core, sampled angles
+    n_sample = 36
+    angles = np.linspace(0, og.n_angles - 1, n_sample).astype(int)
+    Rs = sps.vstack([closed_form.angle_block(og, int(a)) for a in angles], format="csr")
+    RsT = Rs.T.tocsr()
+    ys = y.reshape(og.n_angles, og.n_bins)[angles].ravel()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Rs @ x
+    t_r1 = (time.perf_counter() - t0) / reps * (og.n_angles / n_sample)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        RsT @ ys
+    t_rt1 = (time.perf_counter() - t0) / reps * (og.n_angles / n_sample)
+    it_1 = 2 * t_r1 + 2 * t_rt1 + t_m + t_stv + t_vec
+    # all cores, full size
+    t_r, t_rt, nw = _cpu_all_cores(x, y)
+    it_n = 2 * t_r + 2 * t_rt + t_m + t_stv + t_vec
+    return {"value": round(1.0 / it_n, 4), "unit": "iterations/s", "cores": nw, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": (f"float64 NumPy/SciPy oracle at 512^2 x 720 x 725: R and R^T (closed-form "
+                       f"CSR, 240.8M nonzeros) in full on {nw} worker processes by angle block; "
+                       f"M, S_TV and vector work single-threaded as the oracle runs them; one "
+                       f"iteration = 2 R + 2 R^T + M + S_TV + vector work; R {t_r*1e3:.0f} ms, "
+                       f"R^T {t_rt*1e3:.0f} ms, M {t_m*1e3:.0f} ms, S_TV {t_stv*1e3:.0f} ms"),
+            "single_core": {"value": round(1.0 / it_1, 4), "cores": 1,
+                            "sample": (f"R and R^T on {n_sample} of {og.n_angles} angles scaled "
+                                       f"to all angles: R {t_r1*1e3:.0f} ms, R^T {t_rt1*1e3:.0f} ms")}}
 
 
 def main():
@@ -372,10 +443,18 @@ def main():
 
     bytes_equiv = 8 * NNZ_CT512 + 4 * g.n + 4 * g.m
     avg = {k: v[0] / max(v[1], 1) for k, v in solve_ms.items()}
-    dom_name = "backproject" if avg["backproject"] >= avg["project"] else "project"
-    dom_ms = avg[dom_name]
-    achieved = OPS_PER_PIXEL_ANGLE * g.n * g.n_angles / (dom_ms / 1e3)
-    achieved_nnz = OPS_PER_NNZ * NNZ_CT512 / (dom_ms / 1e3)
+    kernels = {}
+    for name in ("project", "backproject"):
+        ms = avg[name]
+        ach = OPS_PER_NNZ * NNZ_CT512 / (ms / 1e3)
+        instr = COUNTERS["valu_instr"][name]
+        kernels[name] = {"ms": round(ms, 4), "launches": solve_ms[name][1],
+                         "achieved": round(ach / 1e12, 4), "frac": round(ach / PEAK_VALU_OPS, 4),
+                         "valu_issue": {"instr_per_launch": instr,
+                                        "frac": round(instr * 64 / (ms / 1e3) / PEAK_VALU_OPS, 4)},
+                         "traffic": COUNTERS["traffic_bytes"][name]}
+    dom_name = max(kernels, key=lambda k: kernels[k]["ms"])
+    dom = kernels[dom_name]
     out = {
         "metric": "SupPCG iterations/s + R/R^T GB/s at 512\u00b2x720; time-to-target, learned vs plain",
         "value": round(value, 3),
@@ -387,7 +466,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 data; f64 iterate, search direction, CG scalars and reductions",
+        "dtype": "f64 arithmetic in R, R^T, M and the CG scalars; f32 data and sinograms",
         "data": "synthetic random-ellipse phantom (20 ellipses, seed 1), 0.5% Gaussian noise",
         "config": {"workload": "ct512: 512x512 image, 720 angles over [0,pi), 725 bins, "
                                "SupPCG K=1 a=0.5 gamma=0.5, ramp-Hamming M mu=1e-5 rho=0.8",
@@ -395,24 +474,21 @@ def main():
                    "timed_loop": "eager launches" if args.eager else "loop body replayed from a HIP graph",
                    "eager_event_timed_iterations_per_s": round(eager_value, 3)},
         "roofline": {"bound": "alu", "kernel": dom_name,
-                     "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_OPS / 1e12, 4),
-                     "unit": "T lane-ops/s (VALU, 20 per pixel-angle pair)",
-                     "frac": round(achieved / PEAK_VALU_OPS, 4),
-                     "lower_bound_4_per_nonzero": {"achieved": round(achieved_nnz / 1e12, 4),
-                                                   "frac": round(achieved_nnz / PEAK_VALU_OPS, 4)},
-                     "traffic": TRAFFIC_BYTES[dom_name],
-                     "valu_issue": {"instr_per_launch": VALU_INSTR[dom_name],
-                                    "frac": round(VALU_INSTR[dom_name] * 64 / (dom_ms / 1e3)
-                                                  / PEAK_VALU_OPS, 4)},
-                     "kernel_ms": round(dom_ms, 4), "launches": solve_ms[dom_name][1]},
+                     "achieved": dom["achieved"], "peak": round(PEAK_VALU_OPS / 1e12, 4),
+                     "unit": "T lane-ops/s (VALU; 4 per nonzero weight of R)",
+                     "frac": dom["frac"], "traffic": dom["traffic"],
+                     "kernels": kernels, "nnz": NNZ_CT512,
+                     "counters_measured_at": COUNTERS["measured_at"]},
         "in_solve_ms": {k: round(v, 4) for k, v in avg.items()},
         "operators_ms": {"project": round(ms_R, 4), "backproject": round(ms_RT, 4),
                          "precond": round(ms_M, 4)},
-        "gbps_equiv": {"bytes_per_call": bytes_equiv,
-                       "project": round(bytes_equiv / (avg["project"] / 1e3) / 1e9, 1),
-                       "backproject": round(bytes_equiv / (avg["backproject"] / 1e3) / 1e9, 1),
-                       "frac_of_8TBps_project": round(bytes_equiv / (avg["project"] / 1e3) / PEAK_HBM, 3),
-                       "frac_of_8TBps_backproject": round(bytes_equiv / (avg["backproject"] / 1e3) / PEAK_HBM, 3)},
+        # the bytes a stored-matrix (CSR) SpMV of the same R would stream per
+        # call, over the matrix-free kernels' time: an equivalence, not HBM
+        # traffic (the matrix-free kernels move a few MB per call)
+        "stored_matrix_equivalent": {
+            "bytes_per_call": bytes_equiv,
+            "project_GBps": round(bytes_equiv / (avg["project"] / 1e3) / 1e9, 1),
+            "backproject_GBps": round(bytes_equiv / (avg["backproject"] / 1e3) / 1e9, 1)},
         "solve": {"k": res.k, "status": res.status_name, "wall_s": round(wall, 4),
                   "f_last": float(res.trace["f_half"][-1]) if len(res.trace["f_half"]) else None,
                   "ell_last": int(res.trace["ell"][-1]) if len(res.trace["ell"]) else None},
