@@ -48,9 +48,9 @@ OPS_PER_NNZ = 4
 # memory fabric per launch (FETCH_SIZE + WRITE_SIZE, scaled by the counters of
 # a 64 MiB device copy).  R^T: mean of its float32 (R p) and float64
 # (residual) sinogram forms, one of each per loop body.
-COUNTERS = {"measured_at": "1de3a50",
-            "valu_instr": {"project": 2.75e7, "backproject": 3.58e7},
-            "traffic_bytes": {"project": None, "backproject": None}}
+COUNTERS = {"measured_at": "kernels of 1de3a50, profiled at 542fbec",
+            "valu_instr": {"project": 2.907e7, "backproject": 3.577e7},
+            "traffic_bytes": {"project": 40.27e6, "backproject": 20.88e6}}
 
 
 def log(msg):
