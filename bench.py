@@ -71,7 +71,9 @@ def parse():
     ap.add_argument("--learned-seeds", type=int, default=32, help="evaluation seeds from 100")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training the learned preconditioner and its time-to-target")
-    ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--batch-iters", type=int, default=50)
+    ap.add_argument("--no-quality", action="store_true", help="skip the selective-error curves")
+    ap.add_argument("--quality-iters", type=int, default=100)
     ap.add_argument("--large", action="store_true",
                     help="also run 8 slices of 2048^2 x 2048 x 2899 (about a minute of phantom setup)")
     ap.add_argument("--large-iters", type=int, default=20)
@@ -115,6 +117,59 @@ def batched_run(sp, torch, iters):
             "one_by_one_slice_iterations_per_s": round(64 * iters / t_seq, 2),
             "speedup_vs_one_by_one": round(t_seq / t_batch, 3),
             "all_k": sorted(set(r.k for r in res)), "tuning": sp.batch_tuning()}
+
+
+# Table 1's parameters per method, and the defaults of the main workload
+QUALITY_PRESETS = {
+    "table1": {"SupPCG": dict(K=40, a=1 - 1e-5, gamma=1e-2, mu=1e-5, rho=0.8),
+               "PCG": dict(K=0, mu=1e-3, rho=0.6),
+               "SupCG": dict(K=40, a=1 - 1e-5, gamma=5e-2, precond="none"),
+               "CG": dict(K=0, precond="none")},
+    "default": {"SupPCG": dict(K=1, a=0.5, gamma=0.5, mu=1e-5, rho=0.8),
+                "PCG": dict(K=0, mu=1e-5, rho=0.8),
+                "SupCG": dict(K=1, a=0.5, gamma=0.5, precond="none"),
+                "CG": dict(K=0, precond="none")},
+}
+QUALITY_WORKLOADS = {"ct512": (512, 512, 720, 725, 20, 1, 0.005),
+                     "paper243": (243, 243, 360, 345, 20, 3, 0.01)}
+
+
+def quality_run(sp, torch, iters):
+    """Iteration-wise and time-wise selective-error curves (eq. (4.1), the
+    ellipse of Section 4.2 scaled to the image width) of SupPCG, PCG, SupCG and
+    CG, each under Table 1's parameters and under the defaults, at 512^2 x 720
+    x 725 and at the paper's shape (243^2 x 360 x 345); graph-replayed loop
+    bodies, HIP events between them."""
+    from synth import noisy_data, random_ellipses, unit_noise
+    marks = sorted(set([0, 1, 2, 3, 4, 5] + list(range(10, iters + 2, 5)) + [iters + 1]))
+    out = {}
+    for wname, (rows, cols, A, B, ne, seed, frac) in QUALITY_WORKLOADS.items():
+        g = sp.Geometry(rows, cols, A, B)
+        img, rng = random_ellipses(rows, cols, ne, seed)
+        x_true = torch.from_numpy(img.astype(np.float32)).cuda()
+        b_exact = sp.sp_project(g, x_true)
+        b_np = noisy_data(b_exact.cpu().numpy().ravel(), unit_noise(rng, g.m), frac)
+        b = torch.from_numpy(b_np.astype(np.float32).reshape(A, B)).cuda()
+        res_w = {"geometry": f"{rows}x{cols}, {A} angles, {B} bins; {ne} ellipses (seed {seed}), "
+                             f"{frac * 100:g}% noise",
+                 "ellipse_semi_axes": [round(v, 3) for v in sp.paper_se_axes(g)]}
+        for pname, preset in QUALITY_PRESETS.items():
+            for method, kw in preset.items():
+                sp.sp_suppcg_solve(g, b, None, max_iter=2, graph=True, trace=False, **kw)
+                r = sp.sp_suppcg_solve(g, b, None, max_iter=iters, graph=True, se_ref=x_true,
+                                       timing=True, **kw)
+                se, t = r.trace["se"], r.trace["t_ms"]
+                kb = int(np.nanargmin(se))
+                res_w[f"{method}/{pname}"] = {
+                    "params": {k: v for k, v in kw.items()},
+                    "best": {"iteration": kb, "se": round(float(se[kb]), 6),
+                             "ms": round(float(t[kb]), 3)},
+                    "ms_total": round(float(t[-1]), 3),
+                    "curve": [[k, round(float(se[k]), 6), round(float(t[k]), 3)]
+                              for k in marks if k < len(se)]}
+        out[wname] = res_w
+    return {"iterations": iters, "curve_columns": ["iteration k", "SE(x_k)", "ms to x_k"],
+            "workloads": out}
 
 
 def large_run(sp, torch, iters):
@@ -503,6 +558,9 @@ def main():
     if args.large:
         out["large"] = large_run(sp, torch, args.large_iters)
         log("2048^2 batch done")
+    if not args.no_quality:
+        out["quality_curves"] = quality_run(sp, torch, args.quality_iters)
+        log("selective-error curves done")
     if not args.no_learned:
         out["time_to_target"] = learned_run(sp, args.learned_steps, args.learned_seeds)
         log("learned preconditioner trained and timed")

@@ -160,6 +160,24 @@ typedef struct {
     float* g_snap;
     int32_t g_snap_count;
     int32_t bodies;   /* out: loop bodies this call ran (entries written) */
+    /* Selective error of every iterate (Section 4.2, eq. 4.1), evaluated on
+     * the device inside the loop body: se_ref is the phantom (DEVICE float32
+     * [rows][cols]) or NULL to skip; se_axes and se_c give the ellipse S and
+     * C as for sp_selective_error.  se (HOST [cap], nullable): se[k-1] =
+     * SE(x_{k+1}), the iterate loop body k forms (NaN if its step could not be
+     * formed).  se0, se1 (out): SE(x_0) and SE(x_1); NaN on a resumed run,
+     * which skips steps 1-9. */
+    const float* se_ref;
+    double se_axes[2];
+    double se_c;
+    double* se;
+    double se0, se1;
+    /* Wall time (HOST [cap], nullable): t_ms[k-1] = milliseconds from the
+     * call's first launch to the end of loop body k, from HIP events on the
+     * stream between loop bodies (between graph replays with SP_FLAG_GRAPH).
+     * t1_ms (out): to the end of steps 1-9 (NaN when t_ms is NULL). */
+    double* t_ms;
+    double t1_ms;
 } sp_trace;
 
 /* ---- context ------------------------------------------------------------ */
@@ -219,6 +237,16 @@ int sp_precond_apply(sp_ctx* ctx, const sp_geometry* g, const sp_precond* pc,
 
 /* *tv = TV(x) (Section 3.1), float64 device scalar. */
 int sp_tv(sp_ctx* ctx, const sp_geometry* g, const float* x, double* tv);
+
+/* Selective error of Section 4.2, eq. (4.1): SE(x) = C sqrt(sum over S of
+ * (x_ij - ref_ij)^2), in float64.  S holds the pixels whose centres (as for R)
+ * lie in the closed centred ellipse with semi-axes axes[0] (horizontal:
+ * along a row) and axes[1] (vertical), in the geometry's length unit
+ * (HOST double[2], both > 0).  C <= 0 selects C = 1 / sqrt(sum over S of
+ * ref_ij^2), the relative error inside S (NaN when that sum is 0).  x, ref:
+ * DEVICE float32 [rows][cols]; se: DEVICE double, written on the stream. */
+int sp_selective_error(sp_ctx* ctx, const sp_geometry* g, const float* x, const float* ref,
+                       const double* axes, double C, double* se);
 
 /* t_bar = minus the gradient of TV where defined, 0 elsewhere (Section 3.1);
  * *norm2 = ||t_bar||^2 (float64 device scalar, nullable). */

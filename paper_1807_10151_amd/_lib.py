@@ -74,7 +74,10 @@ class sp_trace(ctypes.Structure):
                 ("s_norm", POINTER(c_double)), ("ell", POINTER(c_int32)),
                 ("trials", POINTER(c_int32)), ("cap", c_int32),
                 ("f0", c_double), ("alpha0", c_double), ("fallbacks", c_int32),
-                ("g_snap", c_void_p), ("g_snap_count", c_int32), ("bodies", c_int32)]
+                ("g_snap", c_void_p), ("g_snap_count", c_int32), ("bodies", c_int32),
+                ("se_ref", c_void_p), ("se_axes", c_double * 2), ("se_c", c_double),
+                ("se", POINTER(c_double)), ("se0", c_double), ("se1", c_double),
+                ("t_ms", POINTER(c_double)), ("t1_ms", c_double)]
 
 
 class sp_batch_trace(ctypes.Structure):
@@ -95,6 +98,8 @@ _SIGS = {
     "sp_gradient": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, c_void_p, c_void_p]),
     "sp_precond_apply": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(sp_precond), c_void_p, c_void_p]),
     "sp_tv": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
+    "sp_selective_error": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p,
+                                   POINTER(c_double), c_double, c_void_p]),
     "sp_tv_grad": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, c_void_p]),
     "sp_tv_perturb": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(sp_tv_params), c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -398,6 +398,34 @@ def sp_tv(g: Geometry, x: torch.Tensor, ctx: Context | None = None):
     return out
 
 
+# The paper's ellipse for the selective error: semi-axes 5 cm (horizontal) and
+# 7 cm (vertical) on a phantom 243 pixels of 0.0752 cm wide (Section 4.2);
+# other images keep the same share of their width.
+_SE_WIDTH = 243 * 0.0752
+_SE_AXES = (5.0, 7.0)
+
+
+def paper_se_axes(g: Geometry):
+    """(horizontal, vertical) semi-axes of the selective-error ellipse for g."""
+    w = g.cols * g.pixel
+    return (_SE_AXES[0] / _SE_WIDTH * w, _SE_AXES[1] / _SE_WIDTH * w)
+
+
+def sp_selective_error(g: Geometry, x: torch.Tensor, ref: torch.Tensor, axes=None, C: float = 0.0,
+                       ctx: Context | None = None):
+    """SE(x) of eq. (4.1) as a float64 0-d CUDA tensor (axes default: paper_se_axes)."""
+    ctx = ctx or context(x.device.index or 0)
+    out = torch.empty((), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    ax = paper_se_axes(g) if axes is None else tuple(float(v) for v in axes)
+    axc = (ctypes.c_double * 2)(*ax)
+    ctx._stream()
+    gc = g.c()
+    ctx._check(ctx.lib.sp_selective_error(ctx.h, ctypes.byref(gc), _dev(x, g.n, "x", ctx.device),
+                                          _dev(ref, g.n, "ref", ctx.device), axc, C,
+                                          ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
 def sp_tv_grad(g: Geometry, x: torch.Tensor, ctx: Context | None = None):
     """(t_bar, ||t_bar||^2)."""
     ctx = ctx or context(x.device.index or 0)
@@ -449,13 +477,21 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
                     eps: float = 0.0, graph: bool = False, replay=None, trace: bool = True,
                     x_half: torch.Tensor | None = None, x_last: torch.Tensor | None = None,
                     net: "LearnedPrecond | None" = None, g_snap: torch.Tensor | None = None,
-                    resume: bool = False, ctx: Context | None = None) -> SolveResult:
+                    resume: bool = False, se_ref: torch.Tensor | None = None, se_axes=None,
+                    se_c: float = 0.0, timing: bool = False,
+                    ctx: Context | None = None) -> SolveResult:
     """Algorithm 3 (SupPCG); K = 0 gives plain PCG, precond="none" gives CG.
 
     g_snap (optional, float32 device tensor [count, rows, cols]): receives the
     gradient g_{k+1/2} that loop body k hands to the preconditioner.
     resume: continue for max_iter more loop bodies from the state the context
-    holds (the previous solve, or state_load); x0 is ignored."""
+    holds (the previous solve, or state_load); x0 is ignored.
+    se_ref (optional phantom, float32 device tensor [rows, cols]): the trace
+    gets "se" = [SE(x_0), SE(x_1), SE(x_2), ...], the selective error of eq.
+    (4.1) of every iterate, over the ellipse se_axes (default: paper_se_axes)
+    with constant se_c (<= 0: relative to the phantom inside the ellipse).
+    timing: the trace gets "t_ms" = [0, t(x_1), t(x_2), ...], milliseconds
+    from the call's first launch to the moment each iterate is formed."""
     ctx = ctx or context(b.device.index or 0)
     dev = ctx.device
     snap_count = 0
@@ -482,7 +518,10 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
     cap = max(max_iter, 1)
     tr = None
     arrs = {}
-    if trace or g_snap is not None:
+    if se_ref is not None:
+        _dev(se_ref, g.n, "se_ref", dev)
+        se_axes = paper_se_axes(g) if se_axes is None else tuple(float(v) for v in se_axes)
+    if trace or g_snap is not None or se_ref is not None or timing:
         arrs = {"f_half": np.zeros(cap), "tv_half": np.zeros(cap), "alpha": np.zeros(cap),
                 "beta": np.zeros(cap), "s_norm": np.zeros(cap),
                 "ell": np.zeros(cap, dtype=np.int32), "trials": np.zeros(cap * max(K, 1), dtype=np.int32)}
@@ -492,6 +531,15 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
                         dp(arrs["s_norm"]), ip(arrs["ell"]), ip(arrs["trials"]), cap, 0.0, 0.0, 0,
                         ctypes.c_void_p(g_snap.data_ptr()) if g_snap is not None else None,
                         snap_count, 0)
+        if se_ref is not None:
+            arrs_se = np.full(cap, np.nan)
+            tr.se_ref = ctypes.c_void_p(se_ref.data_ptr())
+            tr.se_axes[0], tr.se_axes[1] = se_axes
+            tr.se_c = se_c
+            tr.se = dp(arrs_se)
+        if timing:
+            arrs_t = np.zeros(cap)
+            tr.t_ms = dp(arrs_t)
     k_out = ctypes.c_int32(0)
     ctx._stream()
     rc = ctx.lib.sp_suppcg_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
@@ -508,4 +556,8 @@ def sp_suppcg_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
         out["f0"] = tr.f0
         out["alpha0"] = tr.alpha0
         out["fallbacks"] = tr.fallbacks
+        if se_ref is not None:
+            out["se"] = np.concatenate([[tr.se0, tr.se1], arrs_se[:done]])
+        if timing:
+            out["t_ms"] = np.concatenate([[0.0, tr.t1_ms], arrs_t[:done]])
     return SolveResult(k_out.value, x_half, x_last, rc, out)

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -63,7 +64,7 @@ struct sp_ctx {
     DevBuf vx, vxh, vp;                   // float64 x_k, x_{k+1/2}, p
     DevBuf vh, vg, vz, vtb, vtmp;
     DevBuf ox, oxh, oscal;                // sp_tv, sp_tv_grad, sp_tv_perturb
-    DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc;
+    DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc, part_se;
     DevBuf scal, trace_d, replay_d, trials_tmp;
     Scalars sc_h{};
     hipStream_t own = nullptr;   // capture stream used when the caller's stream is null
@@ -339,6 +340,7 @@ int ensure_partials(sp_ctx* c) {
     if ((rc = ensure(c, c->part_t, (size_t)tv_blocks(G.rows, G.cols) * 9 * 8))) return rc;
     if ((rc = ensure(c, c->part_s, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
     if ((rc = ensure(c, c->part_misc, (size_t)vec_blocks(n) * 8))) return rc;
+    if ((rc = ensure(c, c->part_se, (size_t)vec_blocks(n) * 16))) return rc;
     if ((rc = ensure(c, c->scal, sizeof(Scalars)))) return rc;
     return SP_OK;
 }
@@ -899,7 +901,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     (void)drain_pending(c);
     for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
-                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->scal,
+                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
         release(*b);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -1237,6 +1239,22 @@ int sp_tv(sp_ctx* c, const sp_geometry* g, const float* x, double* tv) {
     return check_launch(c);
 }
 
+int sp_selective_error(sp_ctx* c, const sp_geometry* g, const float* x, const float* ref,
+                       const double* axes, double C, double* se) {
+    if (!c) return SP_ERR_ARG;
+    if (!x || !ref || !se || !axes) return fail(c, SP_ERR_ARG, "x, ref, axes and se are required");
+    if (!(axes[0] > 0.0) || !(axes[1] > 0.0) || !std::isfinite(axes[0]) || !std::isfinite(axes[1]))
+        return fail(c, SP_ERR_ARG, "ellipse semi-axes must be positive and finite");
+    if (!std::isfinite(C)) return fail(c, SP_ERR_ARG, "C must be finite");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = setup_geometry(c, g);
+    if (rc) return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    launch_se(c->stream, g->rows, g->cols, g->pixel, axes[0], axes[1], x, ref, C,
+              dptr<double>(c->part_se), se);
+    return check_launch(c);
+}
+
 int sp_tv_grad(sp_ctx* c, const sp_geometry* g, const float* x, float* tbar, double* norm2) {
     if (!c) return SP_ERR_ARG;
     if (!x || !tbar) return fail(c, SP_ERR_ARG, "x and tbar must be device pointers");
@@ -1354,10 +1372,24 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         if ((rc = setup_fft(c, F))) return rc;
     }
     const int cap = std::max(sp->max_iter, 1);
-    // trace arrays: 5 double arrays + ell + trials
-    const size_t tr_bytes = (size_t)cap * (5 * 8 + 4) + (size_t)cap * std::max(K, 1) * 4 + 64;
+    // trace arrays: 5 double arrays + ell + trials, then the selective errors
+    // (cap loop bodies, then the slots of x_0 and x_1)
+    const size_t tr_main = (size_t)cap * (5 * 8 + 4) + (size_t)cap * std::max(K, 1) * 4;
+    const size_t se_off = (tr_main + 63) & ~(size_t)63;
+    const size_t tr_bytes = se_off + (size_t)(cap + 2) * 8;
+    const bool want_se = trace && trace->se_ref;
+    if (want_se) {
+        for (double a : trace->se_axes)
+            if (!(a > 0.0) || !std::isfinite(a))
+                return fail(c, SP_ERR_ARG, "se_axes must be positive and finite");
+        if (!std::isfinite(trace->se_c)) return fail(c, SP_ERR_ARG, "se_c must be finite");
+    }
     if ((rc = ensure(c, c->trace_d, tr_bytes))) return rc;
-    HIP_TRY(c, hipMemsetAsync(c->trace_d.ptr, 0, tr_bytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->trace_d.ptr, 0, se_off, c->stream));
+    // selective errors start as NaN (0x7FF80000 in both halves is a NaN)
+    HIP_TRY(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(dptr<char>(c->trace_d) + se_off),
+                                 0x7FF80000, (size_t)(cap + 2) * 2, c->stream));
+    double* se_body = reinterpret_cast<double*>(dptr<char>(c->trace_d) + se_off);
     TraceDev tr{};
     {
         char* base = dptr<char>(c->trace_d);
@@ -1402,6 +1434,20 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     if ((rc = upload_scalars(c, c->scal))) return rc;
 
     hipStream_t st = c->stream;
+    // wall-time trace: an event at the start, after steps 1-9 and after every
+    // loop body (between graph replays in graph mode)
+    std::vector<hipEvent_t> tev;
+    struct EvGuard {
+        std::vector<hipEvent_t>& v;
+        ~EvGuard() {
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        }
+    } ev_guard{tev};
+    if (trace && trace->t_ms && !async) {
+        tev.resize((size_t)cap + 2, nullptr);
+        for (hipEvent_t& e : tev) HIP_TRY(c, hipEventCreate(&e));
+        HIP_TRY(c, hipEventRecord(tev[0], st));
+    }
     Scalars* sc = dptr<Scalars>(c->scal);
     const int* halt = &sc->halt;
     double* xh = dptr<double>(c->vxh);                  // x_{k+1/2}
@@ -1424,9 +1470,15 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     double* pph = dptr<double>(c->part_ph);
     const int nf = project_blocks(G), nph = backproject_blocks(G), ngp = vec_blocks(n);
 
+    const double se_ah = want_se ? trace->se_axes[0] : 0.0, se_av = want_se ? trace->se_axes[1] : 0.0;
+    auto se_of_x = [&](double* dst, double* dst_body, const int* hflag) {
+        launch_se(st, G.rows, G.cols, g->pixel, se_ah, se_av, x, trace->se_ref, trace->se_c,
+                  dptr<double>(c->part_se), dst, dst_body, cap, sc, hflag);
+    };
     if (!resume) {
         launch_widen(st, n, x0, xh);
         launch_widen(st, n, x0, x);
+        if (want_se) se_of_x(se_body + cap, nullptr, nullptr);                       // SE(x_0)
         // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
         // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
         launch_prep(st, G, xh, xp, xTp, halt);
@@ -1443,8 +1495,10 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         launch_backproject(st, G, ang, rp, h, p, pph, halt);
         launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
         launch_update_x(st, n, xh, p, x, sc, halt);
+        if (want_se) se_of_x(se_body + cap + 1, nullptr, halt);                      // SE(x_1)
         if ((rc = check_launch(c))) return rc;
     }
+    if (!tev.empty()) HIP_TRY(c, hipEventRecord(tev[1], st));
 
     float* snap = (trace && trace->g_snap && trace->g_snap_count > 0) ? trace->g_snap : nullptr;
     const int snap_count = snap ? trace->g_snap_count : 0;
@@ -1493,6 +1547,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         project(nullptr, nullptr);
         backproject(h, p, pph, ScalarRide{});                                     // h = A p
         launch_update_x_alpha(st, n, xh, p, x, sc, tr, pph, nph, pgp, ngp, OP_ALPHA);  // alpha; x += alpha p
+        if (want_se) se_of_x(nullptr, se_body, halt);                             // SE(x_{k+1})
         return check_launch(c);
     };
 
@@ -1518,6 +1573,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         int32_t hh = 0;
         for (int it = 0; it < sp->max_iter; ++it) {
             hipError_t el = hipGraphLaunch(exec, st);
+            if (el == hipSuccess && !tev.empty()) el = hipEventRecord(tev[2 + it], st);
             if (el != hipSuccess) {
                 (void)hipStreamSynchronize(st);
                 (void)hipGraphExecDestroy(exec);
@@ -1547,6 +1603,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         int32_t hh = 0;
         for (int it = 0; it < sp->max_iter; ++it) {
             if ((rc = body())) return rc;
+            if (!tev.empty()) HIP_TRY(c, hipEventRecord(tev[2 + it], st));
             if (poll && (it & 7) == 7) {
                 HIP_TRY(c, hipMemcpyAsync(&hh, &sc->halt, 4, hipMemcpyDeviceToHost, st));
                 HIP_TRY(c, hipStreamSynchronize(st));
@@ -1614,6 +1671,22 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         trace->alpha0 = out.alpha0;
         trace->fallbacks = out.fallbacks > 0 ? 1 : 0;
         trace->bodies = out.iter;
+        const double* hse = reinterpret_cast<const double*>(host.data() + se_off);
+        const double nan = std::numeric_limits<double>::quiet_NaN();
+        if (want_se && trace->se) std::copy(hse, hse + done, trace->se);
+        trace->se0 = want_se && !resume ? hse[cap] : nan;
+        trace->se1 = want_se && !resume ? hse[cap + 1] : nan;
+        if (!tev.empty()) {
+            float ms = 0.0f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, tev[0], tev[1]));
+            trace->t1_ms = ms;
+            for (int j = 0; j < done; ++j) {
+                HIP_TRY(c, hipEventElapsedTime(&ms, tev[0], tev[2 + j]));
+                trace->t_ms[j] = ms;
+            }
+        } else {
+            trace->t1_ms = nan;
+        }
     }
     keep_state();
     if (out.halt == SP_ERR_NONFINITE) return fail(c, SP_ERR_NONFINITE, "non-finite value in a CG scalar");

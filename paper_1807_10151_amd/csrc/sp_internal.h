@@ -296,6 +296,16 @@ void launch_reduce(hipStream_t st, const double* partials, int np, double* out);
 void launch_finish(hipStream_t st, int n, const double* xh, double* x, const Scalars* sc,
                    int32_t* k_out);
 
+// quality.hip (selective error, Section 4.2): partials hold 2 * vec_blocks(n)
+// doubles.  First form: SE of a float32 image to *dst.  Second form: SE of the
+// float64 iterate to dst_body[sc->iter - 1] (when dst_body is set and that
+// entry is below cap) or to *dst; nothing when *halt is set.
+void launch_se(hipStream_t st, int rows, int cols, double pixel, double ah, double av,
+               const float* x, const float* ref, double C, double* partials, double* dst);
+void launch_se(hipStream_t st, int rows, int cols, double pixel, double ah, double av,
+               const double* x, const float* ref, double C, double* partials, double* dst,
+               double* dst_body, int cap, const Scalars* sc, const int* halt);
+
 // learned.hip (learned preconditioner C^T diag(softplus(d)) C)
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
                  const float* Wl, const float* scale, float* out2, const int* halt, const int* run);

@@ -5,7 +5,7 @@ A v = R^T R v through the projector and backprojector, the network's forward
 and backward passes and Adam through the sp_lp_* calls, the Krylov probes
 through the solver's gradient snapshots.  This module only orchestrates.
 
-The paper defines the Fourier preconditioner of Section 3.3 (eq. 3.2) and no
+The paper defines the Fourier preconditioner of Section 3.2 (eq. 3.2) and no
 learned one; the recipe below is this library's own:
   * probes: Gaussian vectors plus Krylov vectors, the normalised gradients
     g_{k+1/2} (Algorithm 2, step 1) that the plain solver (the Fourier M)

@@ -95,3 +95,20 @@ def test_paper_axes_reproduce_the_paper_ellipse():
     ah, av = quality.paper_axes(Geometry(512, 512, 1, 1))
     assert abs(ah / 512 - 5.0 / (243 * 0.0752)) < 1e-15
     assert abs(av / ah - 1.4) < 1e-12
+
+
+def test_se_curve_of_cg_on_exact_data_reaches_zero():
+    # consistent data of a full-rank tiny system: CG on the normal equations
+    # recovers the phantom, so the curve starts at SE(0) = 1 and ends near 0
+    from oracle import projector, suppcg
+    g = Geometry(6, 6, 24, 12)
+    R, _ = projector.matrix(g)
+    rng = np.random.default_rng(3)
+    ref = rng.uniform(0.2, 1.0, (6, 6))
+    b = R @ ref.ravel()
+    prob = suppcg.Problem(R, b, (6, 6), None)
+    axes = (2.5, 2.5)
+    curve, res = quality.se_curve(g, prob, np.zeros(36), None, 80, ref, axes)
+    assert curve[0] == pytest.approx(1.0, abs=1e-15)
+    assert len(curve) == len(res.trace["x"]) + 1
+    assert curve[-1] < 1e-6
