@@ -34,6 +34,8 @@ NNZ_2048 = 10_945_428_176
 # lanes; these kernels are float64 (FP64 FMA issues at the same non-packed
 # rate, 78.6 TFLOP/s = 39.3 T FMA/s) and generate no packed FP32.
 PEAK_VALU_OPS = 256 * 64 * 2.4e9
+# HBM3E peak of one MI355X, bytes/s
+PEAK_HBM = 8e12
 # Algorithmic work of R and R^T: the fewest lane-operations a matrix-free
 # projector can spend on one nonzero weight -- form the ray-pixel offset,
 # evaluate the chord length from it, address the gathered value, and
@@ -73,6 +75,8 @@ def parse():
                     help="skip training the learned preconditioner and its time-to-target")
     ap.add_argument("--batch-iters", type=int, default=50)
     ap.add_argument("--no-quality", action="store_true", help="skip the selective-error curves")
+    ap.add_argument("--no-stored", action="store_true", help="skip the stored-matrix products")
+    ap.add_argument("--stored-sides", type=int, nargs="+", default=[64, 128, 256, 512, 1024])
     ap.add_argument("--quality-iters", type=int, default=100)
     ap.add_argument("--large", action="store_true",
                     help="also run 8 slices of 2048^2 x 2048 x 2899 (about a minute of phantom setup)")
@@ -170,6 +174,65 @@ def quality_run(sp, torch, iters):
         out[wname] = res_w
     return {"iterations": iters, "curve_columns": ["iteration k", "SE(x_k)", "ms to x_k"],
             "workloads": out}
+
+
+def stored_run(sp, torch, reps, sides):
+    """Stored-weight R and R^T (CSR in HBM, 8 bytes per nonzero per side)
+    against the matrix-free kernels, at square images of the given sides with
+    round(720 / 512 * side) angles and round(725 / 512 * side) bins (the 512^2
+    workload's shape scaled).  Times are HIP-event means over `reps` calls."""
+    from synth import random_ellipses
+    L = sp.api.L
+    ctx = sp.context(0)
+    rows_out = []
+    for side in sides:
+        A = int(round(720 / 512 * side))
+        B = int(round(725 / 512 * side))
+        g = sp.Geometry(side, side, A, B)
+        img, _ = random_ellipses(side, side, 20, 1)
+        x = torch.from_numpy(img.astype(np.float32)).cuda()
+        y = sp.sp_project(g, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = sp.StoredMatrix(g)
+        t_build = time.perf_counter() - t0
+        nnz, nbytes = M.info()
+        yo = torch.empty_like(y)
+        xo = torch.empty_like(x)
+
+        def timed(fn, kind):
+            fn()
+            ctx.profile_enable(True)
+            for _ in range(reps):
+                fn()
+            ms, cnt = ctx.profile_read(kind)
+            ctx.profile_enable(False)
+            return ms / max(cnt, 1)
+
+        ms_sR = timed(lambda: M.project(x, yo), L.SP_PROF_STORED_PROJECT)
+        ms_sRT = timed(lambda: M.backproject(y, xo), L.SP_PROF_STORED_BACKPROJECT)
+        ms_R = timed(lambda: sp.sp_project(g, x, yo), L.SP_PROF_PROJECT)
+        ms_RT = timed(lambda: sp.sp_backproject(g, y, xo), L.SP_PROF_BACKPROJECT)
+        n, m = side * side, A * B
+        # algorithmic bytes of one stored product: 8 per nonzero of the matrix
+        # side it streams, its row lengths and slice offsets, the input vector
+        # once and the output (padding entries are never read)
+        bytes_R = 8 * nnz + 4 * m + 8 * (m // 64 + 1) + 4 * n + 4 * m
+        bytes_RT = 8 * nnz + 4 * n + 8 * (n // 64 + 1) + 4 * m + 4 * n
+        rows_out.append({
+            "geometry": f"{side}x{side}, {A} angles, {B} bins", "nnz": nnz,
+            "matrix_GB_both_sides": round(nbytes / 1e9, 3), "build_s": round(t_build, 3),
+            "stored_ms": {"R": round(ms_sR, 4), "RT": round(ms_sRT, 4)},
+            "matrix_free_ms": {"R": round(ms_R, 4), "RT": round(ms_RT, 4)},
+            "stored_GBps": {"R": round(bytes_R / (ms_sR / 1e3) / 1e9, 1),
+                            "RT": round(bytes_RT / (ms_sRT / 1e3) / 1e9, 1)},
+            "stored_frac_of_8TBps": {"R": round(bytes_R / (ms_sR / 1e3) / PEAK_HBM, 4),
+                                     "RT": round(bytes_RT / (ms_sRT / 1e3) / PEAK_HBM, 4)},
+            "stored_over_matrix_free": {"R": round(ms_sR / ms_R, 3), "RT": round(ms_sRT / ms_RT, 3)}})
+        M.close()
+        del M
+        torch.cuda.synchronize()
+    return {"reps": reps, "sizes": rows_out}
 
 
 def large_run(sp, torch, iters):
@@ -558,6 +621,9 @@ def main():
     if args.large:
         out["large"] = large_run(sp, torch, args.large_iters)
         log("2048^2 batch done")
+    if not args.no_stored:
+        out["stored_matrix"] = stored_run(sp, torch, args.reps, args.stored_sides)
+        log("stored-matrix products timed")
     if not args.no_quality:
         out["quality_curves"] = quality_run(sp, torch, args.quality_iters)
         log("selective-error curves done")

@@ -378,6 +378,39 @@ int sp_lp_loss_grad(sp_ctx* ctx, sp_learned* net, int32_t rows, int32_t cols, co
 int sp_lp_adam_step(sp_ctx* ctx, sp_learned* net, const float* grad, double lr, double beta1,
                     double beta2, double eps, int32_t step);
 
+/* ---- stored matrices (Section 2, eqs. 2.1-2.2) ---------------------------------
+ * R as an explicit sparse matrix: entry (a * n_bins + k, i * cols + j) is the
+ * length of ray k of angle a inside pixel (i, j), the same lengths the
+ * matrix-free sp_project uses (float32 here, rounded from float64).  Both R
+ * (rows by ray) and R^T (rows by pixel) are kept, so each product streams its
+ * matrix once, as sliced ELLPACK with 64-row slices: int32 column indices and
+ * float32 weights, 8 bytes per stored entry (rows shorter than their slice's
+ * longest are padded; the padding is never read).  R and R^T are built from
+ * one weight function and are exact transposes; only strictly positive
+ * lengths are stored.  Within a row of R the pixels follow the major axis of
+ * the ray's walk (image rows when |cos| >= |sin|, else columns); within a row
+ * of R^T the rays increase.
+ * sp_matrix_build: builds both on the context's device (allocates about
+ * 16 bytes per nonzero plus padding; SP_ERR_ALLOC if that fails; SP_ERR_ARG
+ * for an invalid geometry or n_angles * n_bins >= 2^31) and synchronises the
+ * stream.  The matrix may be used with any context on the same device.
+ * sp_matrix_project: y = R x (x DEVICE float32 [rows][cols], y DEVICE float32
+ * [n_angles][n_bins]); sp_matrix_backproject: x = R^T y; both enqueue one
+ * launch on the context's stream and sum each row in float64 in a fixed
+ * order.
+ * sp_matrix_info: nonzeros of R and device bytes held by both sides.
+ * sp_matrix_export: copies side 0 (R) or 1 (R^T) to HOST arrays in compressed
+ * sparse row form, row_ptr [rows + 1], col [nnz], val [nnz] (each nullable);
+ * synchronises. */
+typedef struct sp_matrix sp_matrix;
+int sp_matrix_build(sp_ctx* ctx, const sp_geometry* g, sp_matrix** out);
+int sp_matrix_destroy(sp_matrix* m);
+int sp_matrix_info(const sp_matrix* m, int64_t* nnz, int64_t* bytes);
+int sp_matrix_project(sp_ctx* ctx, const sp_matrix* m, const float* x, float* y);
+int sp_matrix_backproject(sp_ctx* ctx, const sp_matrix* m, const float* y, float* x);
+int sp_matrix_export(sp_ctx* ctx, const sp_matrix* m, int side, int64_t* row_ptr, int32_t* col,
+                     float* val);
+
 /* ---- instrumentation --------------------------------------------------------- */
 /* While profiling is enabled on a context, every projector, backprojector,
  * preconditioner, S_TV and loop-body launch made through it is bracketed by
@@ -387,7 +420,8 @@ int sp_lp_adam_step(sp_ctx* ctx, sp_learned* net, const float* grad, double lr, 
  * kind since profiling was last enabled.  Events are created on the host; no
  * device memory is allocated. */
 enum { SP_PROF_PROJECT = 0, SP_PROF_BACKPROJECT = 1, SP_PROF_PRECOND = 2, SP_PROF_TV = 3,
-       SP_PROF_ITERATION = 4, SP_PROF_KINDS = 5 };
+       SP_PROF_ITERATION = 4, SP_PROF_STORED_PROJECT = 5, SP_PROF_STORED_BACKPROJECT = 6,
+       SP_PROF_KINDS = 7 };
 int sp_profile_enable(sp_ctx* ctx, int on);
 int sp_profile_read(sp_ctx* ctx, int kind, double* total_ms, int32_t* count);
 

@@ -40,6 +40,8 @@ SP_PROF_BACKPROJECT = 1
 SP_PROF_PRECOND = 2
 SP_PROF_TV = 3
 SP_PROF_ITERATION = 4
+SP_PROF_STORED_PROJECT = 5
+SP_PROF_STORED_BACKPROJECT = 6
 
 STATUS_NAMES = {
     SP_OK: "ok", SP_ERR_ARG: "invalid argument", SP_ERR_NOT_SPD: "preconditioner not SPD",
@@ -124,6 +126,12 @@ _SIGS = {
                                 c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "sp_lp_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double,
                                 c_double, c_int32]),
+    "sp_matrix_build": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(c_void_p)]),
+    "sp_matrix_destroy": (c_int, [c_void_p]),
+    "sp_matrix_info": (c_int, [c_void_p, POINTER(ctypes.c_int64), POINTER(ctypes.c_int64)]),
+    "sp_matrix_project": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sp_matrix_backproject": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sp_matrix_export": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "sp_profile_enable": (c_int, [c_void_p, c_int]),
     "sp_profile_read": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int32)]),
 }

@@ -291,6 +291,67 @@ def batch_tuning(ctx: Context | None = None) -> dict:
     return {nm: ("xcd" if arr[2 * i] else "slice", int(arr[2 * i + 1])) for i, nm in enumerate(names)}
 
 
+class StoredMatrix:
+    """R and R^T of geometry g as stored CSR matrices on the GPU (sp_matrix_*)."""
+
+    def __init__(self, g: Geometry, ctx: Context | None = None):
+        self.ctx = ctx or context(0)
+        self.g = g
+        h = ctypes.c_void_p()
+        gc = g.c()
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_matrix_build(self.ctx.h, ctypes.byref(gc), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.sp_matrix_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        """(nonzeros of R, device bytes of both sides)."""
+        nnz, nbytes = ctypes.c_int64(0), ctypes.c_int64(0)
+        self.ctx._check(self.ctx.lib.sp_matrix_info(self.h, ctypes.byref(nnz), ctypes.byref(nbytes)))
+        return nnz.value, nbytes.value
+
+    def project(self, x: torch.Tensor, y: torch.Tensor | None = None):
+        """y = R x."""
+        g = self.g
+        y = _out(y, (g.n_angles, g.n_bins), self.ctx.device)
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_matrix_project(self.ctx.h, self.h, _dev(x, g.n, "x", self.ctx.device),
+                                                       _dev(y, g.m, "y", self.ctx.device)))
+        return y
+
+    def backproject(self, y: torch.Tensor, x: torch.Tensor | None = None):
+        """x = R^T y."""
+        g = self.g
+        x = _out(x, (g.rows, g.cols), self.ctx.device)
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_matrix_backproject(self.ctx.h, self.h, _dev(y, g.m, "y", self.ctx.device),
+                                                           _dev(x, g.n, "x", self.ctx.device)))
+        return x
+
+    def export(self, side: int):
+        """(row_ptr int64, col int32, val float32) of R (side 0) or R^T (side 1), on the host."""
+        nnz, _ = self.info()
+        rows = self.g.m if side == 0 else self.g.n
+        rp = np.zeros(rows + 1, dtype=np.int64)
+        col = np.zeros(nnz, dtype=np.int32)
+        val = np.zeros(nnz, dtype=np.float32)
+        self.ctx._stream()
+        self.ctx._check(self.ctx.lib.sp_matrix_export(self.ctx.h, self.h, side, rp.ctypes.data_as(ctypes.c_void_p),
+                                                      col.ctypes.data_as(ctypes.c_void_p),
+                                                      val.ctypes.data_as(ctypes.c_void_p)))
+        return rp, col, val
+
+
 class LearnedPrecond:
     """M = C^T diag(softplus(d)) C (sp_lp_* calls); parameters live on the GPU."""
 

@@ -105,6 +105,17 @@ struct sp_ctx {
     std::vector<ProfRec> prof_recs;
 };
 
+// R and R^T stored on the device as sliced ELLPACK (side 0: R by rays, side
+// 1: R^T by pixels): slice offsets sp, row lengths len, entries col / val.
+struct sp_matrix {
+    int device = 0;
+    sp_geometry geom{};
+    int64_t rows[2] = {0, 0};
+    int64_t entries[2] = {0, 0};   // stored entries of each side, padding included
+    int64_t nnz = 0;
+    DevBuf sp[2], len[2], col[2], val[2];
+};
+
 // Learned preconditioner: parameters, Adam moments and workspace.
 struct sp_learned {
     int device = 0;
@@ -1691,6 +1702,176 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     keep_state();
     if (out.halt == SP_ERR_NONFINITE) return fail(c, SP_ERR_NONFINITE, "non-finite value in a CG scalar");
     return status;
+}
+
+// ---- stored matrices ---------------------------------------------------------------
+
+namespace {
+void matrix_free(sp_matrix* M) {
+    for (int sd = 0; sd < 2; ++sd) {
+        release(M->sp[sd]);
+        release(M->len[sd]);
+        release(M->col[sd]);
+        release(M->val[sd]);
+    }
+    delete M;
+}
+}  // namespace
+
+int sp_matrix_build(sp_ctx* c, const sp_geometry* g, sp_matrix** out) {
+    if (!c) return SP_ERR_ARG;
+    if (!out) return fail(c, SP_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = drain_pending(c);
+    if (rc) return rc;
+    if ((rc = setup_geometry(c, g))) return rc;
+    const GeomDev& G = c->G;
+    const int64_t m = (int64_t)G.nA * G.nB, n = (int64_t)G.rows * G.cols;
+    if (m >= ((int64_t)1 << 31) - 256)
+        return fail(c, SP_ERR_ARG, "stored matrices need n_angles * n_bins < 2^31");
+    // the angle table in natural order (the projectors' copy is sorted by class)
+    std::vector<AngleDev> nat((size_t)G.nA);
+    for (const AngleDev& A : c->ang_h) nat[(size_t)A.row] = A;
+    sp_matrix* M = new (std::nothrow) sp_matrix;
+    if (!M) return fail(c, SP_ERR_ALLOC, "out of host memory");
+    M->device = c->device;
+    M->geom = *g;
+    M->rows[0] = m;
+    M->rows[1] = n;
+    DevBuf natd, ssize, offs, sums;
+    struct Tmp {
+        DevBuf *a, *b, *c, *d;
+        ~Tmp() {
+            release(*a);
+            release(*b);
+            release(*c);
+            release(*d);
+        }
+    } tmp{&natd, &ssize, &offs, &sums};
+    hipStream_t st = c->stream;
+    auto bail = [&](int code) {
+        (void)hipStreamSynchronize(st);
+        matrix_free(M);
+        return code;
+    };
+    const int64_t big = std::max(m, n);
+    if ((rc = ensure(c, natd, nat.size() * sizeof(AngleDev))) ||
+        (rc = ensure(c, ssize, (size_t)((big + 63) / 64) * 4)) ||
+        (rc = ensure(c, offs, (size_t)(big + 1) * 8)) ||
+        (rc = ensure(c, sums, (size_t)scan_blocks(big) * 8)))
+        return bail(rc);
+    if (hipMemcpyAsync(natd.ptr, nat.data(), nat.size() * sizeof(AngleDev), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return bail(fail(c, SP_ERR_HIP, "copying the angle table failed"));
+    int64_t nnz_side[2] = {0, 0};
+    for (int sd = 0; sd < 2; ++sd) {
+        const int64_t rows = M->rows[sd], ns = (rows + 63) / 64;
+        if ((rc = ensure(c, M->len[sd], (size_t)rows * 4)) || (rc = ensure(c, M->sp[sd], (size_t)(ns + 1) * 8)))
+            return bail(rc);
+        int32_t* len = dptr<int32_t>(M->len[sd]);
+        launch_stored_count(st, G, dptr<AngleDev>(natd), sd == 1, len);
+        launch_scan(st, len, rows, dptr<int64_t>(offs), dptr<int64_t>(sums));          // nonzeros
+        launch_slice_sizes(st, len, rows, dptr<int32_t>(ssize));
+        launch_scan(st, dptr<int32_t>(ssize), ns, dptr<int64_t>(M->sp[sd]), dptr<int64_t>(sums));
+        if (hipMemcpyAsync(&nnz_side[sd], dptr<int64_t>(offs) + rows, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&M->entries[sd], dptr<int64_t>(M->sp[sd]) + ns, 8, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return bail(fail(c, SP_ERR_HIP, "counting the nonzeros failed: %s",
+                             hipGetErrorString(hipGetLastError())));
+        if ((rc = ensure(c, M->col[sd], (size_t)M->entries[sd] * 4)) ||
+            (rc = ensure(c, M->val[sd], (size_t)M->entries[sd] * 4)))
+            return bail(rc);
+        launch_stored_fill(st, G, dptr<AngleDev>(natd), sd == 1, dptr<int64_t>(M->sp[sd]), len,
+                           dptr<int32_t>(M->col[sd]), dptr<float>(M->val[sd]));
+    }
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(c, SP_ERR_HIP, "building the matrices: %s", hipGetErrorString(e)));
+    if (nnz_side[0] != nnz_side[1])
+        return bail(fail(c, SP_ERR_HIP, "R and R^T counts differ (%lld vs %lld)", (long long)nnz_side[0],
+                         (long long)nnz_side[1]));
+    M->nnz = nnz_side[0];
+    *out = M;
+    return SP_OK;
+}
+
+int sp_matrix_destroy(sp_matrix* M) {
+    if (!M) return SP_ERR_ARG;
+    (void)hipSetDevice(M->device);
+    (void)hipDeviceSynchronize();
+    matrix_free(M);
+    return SP_OK;
+}
+
+int sp_matrix_info(const sp_matrix* M, int64_t* nnz, int64_t* bytes) {
+    if (!M) return SP_ERR_ARG;
+    if (nnz) *nnz = M->nnz;
+    if (bytes) {
+        int64_t t = 0;
+        for (int sd = 0; sd < 2; ++sd)
+            t += (int64_t)(M->sp[sd].bytes + M->len[sd].bytes + M->col[sd].bytes + M->val[sd].bytes);
+        *bytes = t;
+    }
+    return SP_OK;
+}
+
+namespace {
+int matrix_apply(sp_ctx* c, const sp_matrix* M, int side, const float* in, float* out) {
+    if (!c) return SP_ERR_ARG;
+    if (!M || !in || !out) return fail(c, SP_ERR_ARG, "matrix, input and output are required");
+    if (M->device != c->device) return fail(c, SP_ERR_ARG, "the matrix lives on another device");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = drain_pending(c);
+    if (rc) return rc;
+    sp_matrix* W = const_cast<sp_matrix*>(M);
+    ProfScope ps(c, side ? SP_PROF_STORED_BACKPROJECT : SP_PROF_STORED_PROJECT);
+    launch_sell_spmv(c->stream, M->rows[side], dptr<int64_t>(W->sp[side]), dptr<int32_t>(W->len[side]),
+                     dptr<int32_t>(W->col[side]), dptr<float>(W->val[side]), in, out);
+    return check_launch(c);
+}
+}  // namespace
+
+int sp_matrix_project(sp_ctx* c, const sp_matrix* M, const float* x, float* y) {
+    return matrix_apply(c, M, 0, x, y);
+}
+
+int sp_matrix_backproject(sp_ctx* c, const sp_matrix* M, const float* y, float* x) {
+    return matrix_apply(c, M, 1, y, x);
+}
+
+int sp_matrix_export(sp_ctx* c, const sp_matrix* M, int side, int64_t* row_ptr, int32_t* col, float* val) {
+    if (!c) return SP_ERR_ARG;
+    if (!M || (side != 0 && side != 1)) return fail(c, SP_ERR_ARG, "matrix and side 0 or 1 are required");
+    HIP_TRY(c, hipSetDevice(c->device));
+    sp_matrix* W = const_cast<sp_matrix*>(M);
+    hipStream_t st = c->stream;
+    const int64_t rows = M->rows[side], ns = (rows + 63) / 64, ent = M->entries[side];
+    std::vector<int64_t> hsp((size_t)ns + 1);
+    std::vector<int32_t> hlen((size_t)rows), hcol, hval_bits;
+    std::vector<float> hval;
+    HIP_TRY(c, hipMemcpyAsync(hsp.data(), W->sp[side].ptr, hsp.size() * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(hlen.data(), W->len[side].ptr, hlen.size() * 4, hipMemcpyDeviceToHost, st));
+    if (col) {
+        hcol.resize((size_t)ent);
+        HIP_TRY(c, hipMemcpyAsync(hcol.data(), W->col[side].ptr, (size_t)ent * 4, hipMemcpyDeviceToHost, st));
+    }
+    if (val) {
+        hval.resize((size_t)ent);
+        HIP_TRY(c, hipMemcpyAsync(hval.data(), W->val[side].ptr, (size_t)ent * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    int64_t p = 0;
+    if (row_ptr) row_ptr[0] = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        const int64_t base = hsp[(size_t)(r >> 6)] + (r & 63);
+        for (int32_t e = 0; e < hlen[(size_t)r]; ++e, ++p) {
+            if (col) col[p] = hcol[(size_t)(base + (int64_t)e * 64)];
+            if (val) val[p] = hval[(size_t)(base + (int64_t)e * 64)];
+        }
+        if (row_ptr) row_ptr[r + 1] = p;
+    }
+    return SP_OK;
 }
 
 // ---- checkpoint / resume -------------------------------------------------------

@@ -306,6 +306,22 @@ void launch_se(hipStream_t st, int rows, int cols, double pixel, double ah, doub
                const double* x, const float* ref, double C, double* partials, double* dst,
                double* dst_body, int cap, const Scalars* sc, const int* halt);
 
+// stored.hip (R and R^T as sliced ELLPACK, 64 rows a slice).  nat: the angle
+// table in natural order.  count: nonzeros per row (pixels: R^T's rows, else
+// R's) into len; slice sizes: size[s] = 64 * the longest row of slice s;
+// scan: out[0] = 0, out[r + 1] = cnt[0] + ... + cnt[r] (sums: scan_blocks(n)
+// int64 of scratch); fill: the entries of every row at its slice offset sp.
+int scan_blocks(int64_t n);
+void launch_scan(hipStream_t st, const int32_t* cnt, int64_t n, int64_t* out, int64_t* sums);
+void launch_stored_count(hipStream_t st, const GeomDev& G, const AngleDev* nat, bool pixels,
+                         int32_t* len);
+void launch_slice_sizes(hipStream_t st, const int32_t* len, int64_t nrows, int32_t* size);
+void launch_stored_fill(hipStream_t st, const GeomDev& G, const AngleDev* nat, bool pixels,
+                        const int64_t* sp, const int32_t* len, int32_t* col, float* val);
+// y[r] = sum over row r of val * x[col] (float64 sum in a fixed order)
+void launch_sell_spmv(hipStream_t st, int64_t nrows, const int64_t* sp, const int32_t* len,
+                      const int32_t* col, const float* val, const float* x, float* y);
+
 // learned.hip (learned preconditioner C^T diag(softplus(d)) C)
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
                  const float* Wl, const float* scale, float* out2, const int* halt, const int* run);

@@ -1,0 +1,84 @@
+// The nonzeros of R (Section 2, eq. 2.1) one row at a time, for building R
+// and R^T as stored matrices: the visiting order of a ray's pixels and of a
+// pixel's rays, and the weight of each.  __host__ __device__, so the host
+// index checker replays exactly what the build kernels do.
+#pragma once
+
+#include <cmath>
+
+#include "sp_internal.h"
+
+namespace sp {
+
+__host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
+__host__ __device__ inline int imin(int a, int b) { return a < b ? a : b; }
+
+// Length (in the geometry's unit) of ray k of angle A inside pixel (i, j):
+// wmax * u with the trapezoid u of chord_u on the offset s_k - t of the
+// pixel centre's projection t (formed as the forward walk forms it).
+__host__ __device__ inline double stored_weight(const GeomDev& G, const AngleDev& A, int i, int j,
+                                                double sk) {
+    const double xj = (double)j - G.xoff, yi = G.yoff - (double)i;
+    const double t = (A.flags & ANG_HORIZ) ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
+    const double d = sk - t;
+    const double u = (A.flags & ANG_AXIS) ? chord_u<true>(d, A.einv, A.inv)
+                                          : chord_u<false>(d, A.einv, A.inv);
+    return A.wmax * u * G.pixel;
+}
+
+__host__ __device__ inline double half_band(const AngleDev& A) { return 0.5 * (fabs(A.c) + fabs(A.s)); }
+
+// Visits the nonzeros of ray (a, k) in a fixed order: major lines (image rows
+// when |cos| >= |sin|, else columns) in increasing order, and on each the
+// minor indices of the band |s_k - t| < e in increasing order.
+template <class F>
+__host__ __device__ inline void ray_nonzeros(const GeomDev& G, const AngleDev& A, int k, F&& emit) {
+    const double sk = bin_pos((double)k, G);
+    const double e = half_band(A);
+    if (!(A.flags & ANG_HORIZ)) {
+        const double hw = e / fabs(A.c);
+        for (int i = 0; i < G.rows; ++i) {
+            const double yi = G.yoff - (double)i;
+            const double xs = (sk - yi * A.s) / A.c + G.xoff;   // column coordinate of the crossing
+            const int lo = imax((int)floor(xs - hw) - 1, 0);
+            const int hi = imin((int)ceil(xs + hw) + 1, G.cols - 1);
+            for (int j = lo; j <= hi; ++j) {
+                const double w = stored_weight(G, A, i, j, sk);
+                if (w > 0.0) emit(i * G.cols + j, w);
+            }
+        }
+    } else {
+        const double hw = e / fabs(A.s);
+        for (int j = 0; j < G.cols; ++j) {
+            const double xj = (double)j - G.xoff;
+            const double ys = G.yoff - (sk - xj * A.c) / A.s;   // row coordinate of the crossing
+            const int lo = imax((int)floor(ys - hw) - 1, 0);
+            const int hi = imin((int)ceil(ys + hw) + 1, G.rows - 1);
+            for (int i = lo; i <= hi; ++i) {
+                const double w = stored_weight(G, A, i, j, sk);
+                if (w > 0.0) emit(i * G.cols + j, w);
+            }
+        }
+    }
+}
+
+// Visits the nonzeros of pixel (i, j): angles in increasing order, and for
+// each the bins of |s_k - t| < e in increasing order (ray index a * nB + k).
+template <class F>
+__host__ __device__ inline void pixel_nonzeros(const GeomDev& G, const AngleDev* nat,
+                                               int i, int j, F&& emit) {
+    const double xj = (double)j - G.xoff, yi = G.yoff - (double)i;
+    for (int a = 0; a < G.nA; ++a) {
+        const AngleDev A = nat[a];
+        const double t = (A.flags & ANG_HORIZ) ? fma(yi, A.s, xj * A.c) : fma(xj, A.c, yi * A.s);
+        const double e = half_band(A);
+        const int lo = imax((int)floor((t - e - G.s0) * G.inv_ds) - 1, 0);
+        const int hi = imin((int)ceil((t + e - G.s0) * G.inv_ds) + 1, G.nB - 1);
+        for (int k = lo; k <= hi; ++k) {
+            const double w = stored_weight(G, A, i, j, bin_pos((double)k, G));
+            if (w > 0.0) emit(a * G.nB + k, w);
+        }
+    }
+}
+
+}  // namespace sp
