@@ -13,6 +13,7 @@
 
 #include "../../include/suppcg.h"
 #include "sp_internal.h"
+#include "sp_stored.h"
 
 using namespace sp;
 
@@ -65,6 +66,7 @@ struct sp_ctx {
     DevBuf vh, vg, vz, vtb, vtmp;
     DevBuf ox, oxh, oscal;                // sp_tv, sp_tv_grad, sp_tv_perturb
     DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc, part_se;
+    DevBuf stored_xT;                     // transposed image for the stored R product
     DevBuf scal, trace_d, replay_d, trials_tmp;
     Scalars sc_h{};
     hipStream_t own = nullptr;   // capture stream used when the caller's stream is null
@@ -111,9 +113,11 @@ struct sp_matrix {
     int device = 0;
     sp_geometry geom{};
     int64_t rows[2] = {0, 0};
-    int64_t entries[2] = {0, 0};   // stored entries of each side, padding included
+    sp::SellShape shape[2] = {};
+    int64_t words[2] = {0, 0};     // 32-bit words of each side's entries, padding included
     int64_t nnz = 0;
-    DevBuf sp[2], len[2], col[2], val[2];
+    DevBuf sp[2], len[2], ent[2];
+    DevBuf segT;                   // R: 1 for angles whose rows index the transposed image
 };
 
 // Learned preconditioner: parameters, Adam moments and workspace.
@@ -912,7 +916,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     (void)drain_pending(c);
     for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
-                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->scal,
+                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->stored_xT, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
         release(*b);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -1711,9 +1715,9 @@ void matrix_free(sp_matrix* M) {
     for (int sd = 0; sd < 2; ++sd) {
         release(M->sp[sd]);
         release(M->len[sd]);
-        release(M->col[sd]);
-        release(M->val[sd]);
+        release(M->ent[sd]);
     }
+    release(M->segT);
     delete M;
 }
 }  // namespace
@@ -1739,6 +1743,8 @@ int sp_matrix_build(sp_ctx* c, const sp_geometry* g, sp_matrix** out) {
     M->geom = *g;
     M->rows[0] = m;
     M->rows[1] = n;
+    M->shape[0] = SellShape{G.nA, G.nB, (G.nB + 63) / 64};
+    M->shape[1] = SellShape{G.rows, G.cols, (G.cols + 63) / 64};
     DevBuf natd, ssize, offs, sums;
     struct Tmp {
         DevBuf *a, *b, *c, *d;
@@ -1757,34 +1763,40 @@ int sp_matrix_build(sp_ctx* c, const sp_geometry* g, sp_matrix** out) {
     };
     const int64_t big = std::max(m, n);
     if ((rc = ensure(c, natd, nat.size() * sizeof(AngleDev))) ||
-        (rc = ensure(c, ssize, (size_t)((big + 63) / 64) * 4)) ||
+        (rc = ensure(c, ssize, (size_t)std::max(M->shape[0].nseg * M->shape[0].spseg,
+                                                M->shape[1].nseg * M->shape[1].spseg) * 4)) ||
         (rc = ensure(c, offs, (size_t)(big + 1) * 8)) ||
         (rc = ensure(c, sums, (size_t)scan_blocks(big) * 8)))
         return bail(rc);
     if (hipMemcpyAsync(natd.ptr, nat.data(), nat.size() * sizeof(AngleDev), hipMemcpyHostToDevice, st) !=
         hipSuccess)
         return bail(fail(c, SP_ERR_HIP, "copying the angle table failed"));
+    std::vector<uint8_t> segT((size_t)G.nA);
+    for (int a = 0; a < G.nA; ++a) segT[(size_t)a] = (nat[(size_t)a].flags & ANG_HORIZ) ? 1 : 0;
+    if ((rc = ensure(c, M->segT, segT.size())) ||
+        hipMemcpyAsync(M->segT.ptr, segT.data(), segT.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        return bail(rc ? rc : fail(c, SP_ERR_HIP, "copying the segment table failed"));
     int64_t nnz_side[2] = {0, 0};
     for (int sd = 0; sd < 2; ++sd) {
-        const int64_t rows = M->rows[sd], ns = (rows + 63) / 64;
+        const SellShape& S = M->shape[sd];
+        const int64_t rows = M->rows[sd], ns = S.nseg * S.spseg;
         if ((rc = ensure(c, M->len[sd], (size_t)rows * 4)) || (rc = ensure(c, M->sp[sd], (size_t)(ns + 1) * 8)))
             return bail(rc);
         int32_t* len = dptr<int32_t>(M->len[sd]);
         launch_stored_count(st, G, dptr<AngleDev>(natd), sd == 1, len);
         launch_scan(st, len, rows, dptr<int64_t>(offs), dptr<int64_t>(sums));          // nonzeros
-        launch_slice_sizes(st, len, rows, dptr<int32_t>(ssize));
+        launch_slice_sizes(st, len, S, dptr<int32_t>(ssize));
         launch_scan(st, dptr<int32_t>(ssize), ns, dptr<int64_t>(M->sp[sd]), dptr<int64_t>(sums));
         if (hipMemcpyAsync(&nnz_side[sd], dptr<int64_t>(offs) + rows, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(&M->entries[sd], dptr<int64_t>(M->sp[sd]) + ns, 8, hipMemcpyDeviceToHost, st) !=
+            hipMemcpyAsync(&M->words[sd], dptr<int64_t>(M->sp[sd]) + ns, 8, hipMemcpyDeviceToHost, st) !=
                 hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return bail(fail(c, SP_ERR_HIP, "counting the nonzeros failed: %s",
                              hipGetErrorString(hipGetLastError())));
-        if ((rc = ensure(c, M->col[sd], (size_t)M->entries[sd] * 4)) ||
-            (rc = ensure(c, M->val[sd], (size_t)M->entries[sd] * 4)))
-            return bail(rc);
-        launch_stored_fill(st, G, dptr<AngleDev>(natd), sd == 1, dptr<int64_t>(M->sp[sd]), len,
-                           dptr<int32_t>(M->col[sd]), dptr<float>(M->val[sd]));
+        // padding: column 0, weight 0 (ensure zero-fills new storage)
+        if ((rc = ensure(c, M->ent[sd], (size_t)M->words[sd] * 4))) return bail(rc);
+        launch_stored_fill(st, G, S, dptr<AngleDev>(natd), sd == 1, dptr<int64_t>(M->sp[sd]), len,
+                           dptr<int32_t>(M->ent[sd]));
     }
     const hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(c, SP_ERR_HIP, "building the matrices: %s", hipGetErrorString(e)));
@@ -1810,8 +1822,8 @@ int sp_matrix_info(const sp_matrix* M, int64_t* nnz, int64_t* bytes) {
     if (bytes) {
         int64_t t = 0;
         for (int sd = 0; sd < 2; ++sd)
-            t += (int64_t)(M->sp[sd].bytes + M->len[sd].bytes + M->col[sd].bytes + M->val[sd].bytes);
-        *bytes = t;
+            t += (int64_t)(M->sp[sd].bytes + M->len[sd].bytes + M->ent[sd].bytes);
+        *bytes = t + (int64_t)M->segT.bytes;
     }
     return SP_OK;
 }
@@ -1825,9 +1837,15 @@ int matrix_apply(sp_ctx* c, const sp_matrix* M, int side, const float* in, float
     int rc = drain_pending(c);
     if (rc) return rc;
     sp_matrix* W = const_cast<sp_matrix*>(M);
+    const float* inT = nullptr;
+    if (side == 0) {
+        if ((rc = ensure(c, c->stored_xT, (size_t)M->rows[1] * 4))) return rc;
+        inT = dptr<float>(c->stored_xT);
+    }
     ProfScope ps(c, side ? SP_PROF_STORED_BACKPROJECT : SP_PROF_STORED_PROJECT);
-    launch_sell_spmv(c->stream, M->rows[side], dptr<int64_t>(W->sp[side]), dptr<int32_t>(W->len[side]),
-                     dptr<int32_t>(W->col[side]), dptr<float>(W->val[side]), in, out);
+    if (side == 0) launch_transpose(c->stream, M->geom.rows, M->geom.cols, in, dptr<float>(c->stored_xT));
+    launch_sell_spmv(c->stream, M->shape[side], dptr<int64_t>(W->sp[side]), dptr<int32_t>(W->len[side]),
+                     dptr<int32_t>(W->ent[side]), in, inT, side == 0 ? dptr<uint8_t>(W->segT) : nullptr, out);
     return check_launch(c);
 }
 }  // namespace
@@ -1846,28 +1864,37 @@ int sp_matrix_export(sp_ctx* c, const sp_matrix* M, int side, int64_t* row_ptr, 
     HIP_TRY(c, hipSetDevice(c->device));
     sp_matrix* W = const_cast<sp_matrix*>(M);
     hipStream_t st = c->stream;
-    const int64_t rows = M->rows[side], ns = (rows + 63) / 64, ent = M->entries[side];
+    const SellShape& S = M->shape[side];
+    const int64_t rows = M->rows[side], ns = S.nseg * S.spseg, words = M->words[side];
+    const int R = M->geom.rows, C = M->geom.cols;
     std::vector<int64_t> hsp((size_t)ns + 1);
-    std::vector<int32_t> hlen((size_t)rows), hcol, hval_bits;
-    std::vector<float> hval;
+    std::vector<int32_t> hlen((size_t)rows), hent;
     HIP_TRY(c, hipMemcpyAsync(hsp.data(), W->sp[side].ptr, hsp.size() * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(hlen.data(), W->len[side].ptr, hlen.size() * 4, hipMemcpyDeviceToHost, st));
-    if (col) {
-        hcol.resize((size_t)ent);
-        HIP_TRY(c, hipMemcpyAsync(hcol.data(), W->col[side].ptr, (size_t)ent * 4, hipMemcpyDeviceToHost, st));
-    }
-    if (val) {
-        hval.resize((size_t)ent);
-        HIP_TRY(c, hipMemcpyAsync(hval.data(), W->val[side].ptr, (size_t)ent * 4, hipMemcpyDeviceToHost, st));
+    if (col || val) {
+        hent.resize((size_t)words);
+        HIP_TRY(c, hipMemcpyAsync(hent.data(), W->ent[side].ptr, (size_t)words * 4, hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(c, hipStreamSynchronize(st));
+    std::vector<uint8_t> segT;
+    if (side == 0) {
+        segT.resize((size_t)S.nseg);
+        HIP_TRY(c, hipMemcpy(segT.data(), W->segT.ptr, segT.size(), hipMemcpyDeviceToHost));
+    }
     int64_t p = 0;
     if (row_ptr) row_ptr[0] = 0;
     for (int64_t r = 0; r < rows; ++r) {
-        const int64_t base = hsp[(size_t)(r >> 6)] + (r & 63);
+        const int64_t seg = r / S.lseg, k = r % S.lseg;
+        const int64_t base = hsp[(size_t)sell_slice(S, r)];
+        const int lane = sell_lane(S, r);
+        const bool tr = side == 0 && segT[(size_t)seg];
         for (int32_t e = 0; e < hlen[(size_t)r]; ++e, ++p) {
-            if (col) col[p] = hcol[(size_t)(base + (int64_t)e * 64)];
-            if (val) val[p] = hval[(size_t)(base + (int64_t)e * 64)];
+            const size_t at = (size_t)(base + sell_offset(lane, e));
+            if (col) {
+                const int32_t q = hent[at];
+                col[p] = tr ? (q % R) * C + q / R : q;   // transposed index j * rows + i
+            }
+            if (val) std::memcpy(&val[p], &hent[at + SELL_VAL], 4);
         }
         if (row_ptr) row_ptr[r + 1] = p;
     }

@@ -306,21 +306,32 @@ void launch_se(hipStream_t st, int rows, int cols, double pixel, double ah, doub
                const double* x, const float* ref, double C, double* partials, double* dst,
                double* dst_body, int cap, const Scalars* sc, const int* halt);
 
-// stored.hip (R and R^T as sliced ELLPACK, 64 rows a slice).  nat: the angle
+// stored.hip (R and R^T as sliced ELLPACK, 64 rows a slice).  Rows come in
+// nseg segments of lseg rows (R: angles of nB rays; R^T: image rows of cols
+// pixels), each split into spseg = ceil(lseg / 64) slices.  nat: the angle
 // table in natural order.  count: nonzeros per row (pixels: R^T's rows, else
-// R's) into len; slice sizes: size[s] = 64 * the longest row of slice s;
-// scan: out[0] = 0, out[r + 1] = cnt[0] + ... + cnt[r] (sums: scan_blocks(n)
-// int64 of scratch); fill: the entries of every row at its slice offset sp.
+// R's) into len; slice sizes: size[s] = 128 * the longest row of slice s
+// rounded up to a multiple of 4 (words: column indices and weights); scan:
+// out[0] = 0, out[r + 1] = cnt[0] + ... + cnt[r] (sums: scan_blocks(n) int64
+// of scratch); fill: the entries of every row at its slice offset sp in ent
+// (placement of sp_stored.h; R's near-horizontal rays with transposed pixel
+// indices).
+struct SellShape {
+    int64_t nseg, lseg, spseg;
+};
 int scan_blocks(int64_t n);
 void launch_scan(hipStream_t st, const int32_t* cnt, int64_t n, int64_t* out, int64_t* sums);
 void launch_stored_count(hipStream_t st, const GeomDev& G, const AngleDev* nat, bool pixels,
                          int32_t* len);
-void launch_slice_sizes(hipStream_t st, const int32_t* len, int64_t nrows, int32_t* size);
-void launch_stored_fill(hipStream_t st, const GeomDev& G, const AngleDev* nat, bool pixels,
-                        const int64_t* sp, const int32_t* len, int32_t* col, float* val);
-// y[r] = sum over row r of val * x[col] (float64 sum in a fixed order)
-void launch_sell_spmv(hipStream_t st, int64_t nrows, const int64_t* sp, const int32_t* len,
-                      const int32_t* col, const float* val, const float* x, float* y);
+void launch_slice_sizes(hipStream_t st, const int32_t* len, const SellShape& S, int32_t* size);
+void launch_stored_fill(hipStream_t st, const GeomDev& G, const SellShape& S, const AngleDev* nat,
+                        bool pixels, const int64_t* sp, const int32_t* len, int32_t* ent);
+// y[r] = sum over row r of val * x[col] (float64 sum in a fixed order); the
+// segments with segT[seg] = 1 gather from xT (segT nullable: none)
+void launch_sell_spmv(hipStream_t st, const SellShape& S, const int64_t* sp, const int32_t* len,
+                      const int32_t* ent, const float* x, const float* xT, const uint8_t* segT, float* y);
+// xT = x transposed (x: rows x cols)
+void launch_transpose(hipStream_t st, int rows, int cols, const float* x, float* xT);
 
 // learned.hip (learned preconditioner C^T diag(softplus(d)) C)
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,

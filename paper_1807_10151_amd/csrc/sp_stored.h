@@ -81,4 +81,18 @@ __host__ __device__ inline void pixel_nonzeros(const GeomDev& G, const AngleDev*
     }
 }
 
+// Sliced-ELL placement (64-row slices, segments start new slices, entries
+// in groups of four per lane, a group's column indices and weights side by
+// side): the slice and lane of row r, and the word offset of the column index
+// of a lane's entry e from its slice's start (its weight is SELL_VAL words
+// further).  A slice of width w (a multiple of 4) spans 128 w words.
+constexpr int SELL_VAL = 256;
+__host__ __device__ inline int64_t sell_slice(const SellShape& S, int64_t r) {
+    return (r / S.lseg) * S.spseg + (r % S.lseg) / 64;
+}
+__host__ __device__ inline int sell_lane(const SellShape& S, int64_t r) { return (int)((r % S.lseg) & 63); }
+__host__ __device__ inline int64_t sell_offset(int lane, int e) {
+    return (int64_t)(e >> 2) * 512 + 4 * lane + (e & 3);
+}
+
 }  // namespace sp

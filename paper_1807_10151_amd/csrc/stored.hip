@@ -4,12 +4,14 @@
 // rows, one per lane of a wave -- R by rays (row a * nB + k, columns pixels),
 // R^T by pixels (row i * cols + j, columns rays).  Slice s holds width_s
 // entries per row, stored entry-major ([e][lane]) from offset sp[s] (so
-// width_s = (sp[s + 1] - sp[s]) / 64), with the row's length in len[row];
-// entries past a row's length are padding and are never read.  Neighbouring
+// width_s = (sp[s + 1] - sp[s]) / 128 words: each group of four entries of
+// the 64 lanes is 256 column indices followed by their 256 weights), with the
+// row's length in len[row]; entries past a row's length are padding.  Neighbouring
 // rows of a slice are neighbouring rays of one angle (or pixels of one image
-// row), so a wave's 64 loads of an entry are contiguous and its gathers of
-// the vector land on neighbouring pixels (or bins).  Column indices are int32
-// and weights float32: a product streams 8 bytes per stored entry.
+// row), so a wave's loads of a group are one contiguous 2 KiB run and its
+// gathers of the vector land on neighbouring pixels (or bins).  Column
+// indices are int32 and weights float32: a product streams 8 bytes per
+// stored entry.
 //
 // Both matrices are built on the device from one weight function
 // (stored_weight), R ray by ray and R^T pixel by pixel, so they are exact
@@ -21,6 +23,13 @@
 
 namespace sp {
 
+// Rows are grouped in segments (one angle's rays for R, one image row's
+// pixels for R^T) of lseg rows; each segment starts a new slice, so a slice
+// never mixes angles or image rows.  Row r = seg * lseg + k sits in slice
+// seg * spseg + k / 64, lane k % 64.  A slice holds 64 lanes x width entries,
+// width a multiple of 4; lane l's entry e is at offset
+// sp[slice] + (e / 4) * 256 + 4 l + e % 4, so each lane reads its entries four
+// at a time with 16-byte loads.
 // nat: the angle table in natural order (entry a is angle a).
 __global__ __launch_bounds__(256) void k_count_rays(GeomDev G, const AngleDev* __restrict__ nat,
                                                     int32_t* __restrict__ cnt) {
@@ -31,22 +40,29 @@ __global__ __launch_bounds__(256) void k_count_rays(GeomDev G, const AngleDev* _
     cnt[r] = c;
 }
 
-__global__ __launch_bounds__(256) void k_fill_rays(GeomDev G, const AngleDev* __restrict__ nat,
+// Rays of near-horizontal angles (|sin| > |cos|, walked column by column)
+// store the transposed pixel index j * rows + i: their products gather from a
+// transposed copy of the image, where the pixels of neighbouring rays are
+// neighbours.
+__global__ __launch_bounds__(256) void k_fill_rays(GeomDev G, SellShape S, const AngleDev* __restrict__ nat,
                                                    const int64_t* __restrict__ sp,
                                                    const int32_t* __restrict__ len,
-                                                   int32_t* __restrict__ col, float* __restrict__ val) {
+                                                   int32_t* __restrict__ ent) {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= G.nA * G.nB) return;
     const int L = len[r];
-    int64_t p = sp[r >> 6] + (r & 63);
+    const AngleDev A = nat[r / G.nB];
+    const bool tr = (A.flags & ANG_HORIZ) != 0;
+    const int64_t p0 = sp[sell_slice(S, r)];
+    const int lane = sell_lane(S, r);
     int e = 0;
-    ray_nonzeros(G, nat[r / G.nB], r % G.nB, [&](int q, double w) {
+    ray_nonzeros(G, A, r % G.nB, [&](int q, double w) {
         if (e < L) {
-            col[p] = q;
-            val[p] = (float)w;
+            const int64_t p = p0 + sell_offset(lane, e);
+            ent[p] = tr ? (q % G.cols) * G.rows + q / G.cols : q;
+            ent[p + SELL_VAL] = __float_as_int((float)w);
         }
         ++e;
-        p += 64;
     });
 }
 
@@ -59,36 +75,35 @@ __global__ __launch_bounds__(256) void k_count_pixels(GeomDev G, const AngleDev*
     cnt[q] = c;
 }
 
-__global__ __launch_bounds__(256) void k_fill_pixels(GeomDev G, const AngleDev* __restrict__ nat,
+__global__ __launch_bounds__(256) void k_fill_pixels(GeomDev G, SellShape S, const AngleDev* __restrict__ nat,
                                                      const int64_t* __restrict__ sp,
                                                      const int32_t* __restrict__ len,
-                                                     int32_t* __restrict__ col, float* __restrict__ val) {
+                                                     int32_t* __restrict__ ent) {
     const int q = blockIdx.x * 256 + threadIdx.x;
     if (q >= G.rows * G.cols) return;
     const int L = len[q];
-    int64_t p = sp[q >> 6] + (q & 63);
+    const int64_t p0 = sp[sell_slice(S, q)];
+    const int lane = sell_lane(S, q);
     int e = 0;
     pixel_nonzeros(G, nat, q / G.cols, q % G.cols, [&](int r, double w) {
         if (e < L) {
-            col[p] = r;
-            val[p] = (float)w;
+            const int64_t p = p0 + sell_offset(lane, e);
+            ent[p] = r;
+            ent[p + SELL_VAL] = __float_as_int((float)w);
         }
         ++e;
-        p += 64;
     });
 }
 
-// Entries of slice s: 64 times its longest row (rows past nrows count 0).
-__global__ __launch_bounds__(256) void k_slice_sizes(const int32_t* __restrict__ len, int64_t nrows,
-                                                     int64_t nslices, int32_t* __restrict__ size) {
+// Words of slice s: 128 times its longest row rounded up to a multiple of 4.
+__global__ __launch_bounds__(256) void k_slice_sizes(const int32_t* __restrict__ len, SellShape S,
+                                                     int32_t* __restrict__ size) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= nslices) return;
+    if (s >= S.nseg * S.spseg) return;
+    const int64_t seg = s / S.spseg, k0 = (s % S.spseg) * 64;
     int w = 0;
-    for (int l = 0; l < 64; ++l) {
-        const int64_t r = s * 64 + l;
-        if (r < nrows) w = imax(w, len[r]);
-    }
-    size[s] = 64 * w;
+    for (int l = 0; l < 64 && k0 + l < S.lseg; ++l) w = imax(w, len[seg * S.lseg + k0 + l]);
+    size[s] = 128 * ((w + 3) & ~3);
 }
 
 // ---- exclusive scan of the row counts into int64 row offsets ------------------
@@ -168,71 +183,110 @@ void launch_stored_count(hipStream_t st, const GeomDev& G, const AngleDev* nat, 
     else hipLaunchKernelGGL(k_count_rays, dim3(nb), dim3(256), 0, st, G, nat, cnt);
 }
 
-void launch_slice_sizes(hipStream_t st, const int32_t* len, int64_t nrows, int32_t* size) {
-    const int64_t ns = (nrows + 63) / 64;
-    hipLaunchKernelGGL(k_slice_sizes, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, len, nrows, ns,
-                       size);
+void launch_slice_sizes(hipStream_t st, const int32_t* len, const SellShape& S, int32_t* size) {
+    const int64_t ns = S.nseg * S.spseg;
+    hipLaunchKernelGGL(k_slice_sizes, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, len, S, size);
 }
 
-void launch_stored_fill(hipStream_t st, const GeomDev& G, const AngleDev* nat, bool pixels,
-                        const int64_t* sp, const int32_t* len, int32_t* col, float* val) {
+void launch_stored_fill(hipStream_t st, const GeomDev& G, const SellShape& S, const AngleDev* nat,
+                        bool pixels, const int64_t* sp, const int32_t* len, int32_t* ent) {
     const int64_t n = pixels ? (int64_t)G.rows * G.cols : (int64_t)G.nA * G.nB;
     const int nb = (int)((n + 255) / 256);
-    if (pixels) hipLaunchKernelGGL(k_fill_pixels, dim3(nb), dim3(256), 0, st, G, nat, sp, len, col, val);
-    else hipLaunchKernelGGL(k_fill_rays, dim3(nb), dim3(256), 0, st, G, nat, sp, len, col, val);
+    if (pixels) hipLaunchKernelGGL(k_fill_pixels, dim3(nb), dim3(256), 0, st, G, S, nat, sp, len, ent);
+    else hipLaunchKernelGGL(k_fill_rays, dim3(nb), dim3(256), 0, st, G, S, nat, sp, len, ent);
 }
 
 // ---- y = A x for a stored matrix ------------------------------------------------
 // One workgroup per slice; its four waves take the four contiguous quarters of
-// the slice's entry range, lane l summing row 64 s + l over its quarter in
-// order with U entries' loads in flight; the quarters' sums are then added in
-// wave order through LDS.  The matrix streams through once, so its loads are
-// nontemporal and leave the caches to the gathered vector.
+// the slice's groups of four entries (each group read as one 16-byte load of
+// column indices and one of weights per lane), lane l summing its row over its quarter
+// in order with U groups' loads in flight; the quarters' sums are then added
+// in wave order through LDS.  Entries past a row's length (padding, column 0,
+// weight 0) add nothing: their gathered value is masked to 0.  The matrix
+// streams through once, so its loads are nontemporal and leave the caches to
+// the gathered vector.  segT (nullable): 1 for segments whose column indices
+// refer to xT, the transposed vector.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <int U>
-__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nrows, const int64_t* __restrict__ sp,
+__global__ __launch_bounds__(256) void k_sell_spmv(SellShape S, const int64_t* __restrict__ sp,
                                                    const int32_t* __restrict__ len,
-                                                   const int32_t* __restrict__ col,
-                                                   const float* __restrict__ val,
+                                                   const int32_t* __restrict__ ent,
                                                    const float* __restrict__ x,
+                                                   const float* __restrict__ xT,
+                                                   const uint8_t* __restrict__ segT,
                                                    float* __restrict__ y) {
     __shared__ double part[4][64];
     const int64_t s = blockIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t row = s * 64 + lane;
-    const int L = row < nrows ? len[row] : 0;
+    const int64_t seg = s / S.spseg, k = (s % S.spseg) * 64 + lane;
+    const bool valid = k < S.lseg;
+    const int64_t row = seg * S.lseg + k;
+    const int L = valid ? len[row] : 0;
+    const float* __restrict__ xs = (segT && segT[seg]) ? xT : x;
     const int64_t base = sp[s];
-    const int W = (int)((sp[s + 1] - base) >> 6);
-    const int e0 = W * w / 4, e1 = imin(W * (w + 1) / 4, L);
-    const int32_t* cp = col + base + lane;
-    const float* vp = val + base + lane;
+    const int NG = (int)((sp[s + 1] - base) >> 9);
+    const int g0 = NG * w / 4, g1 = imin(NG * (w + 1) / 4, (L + 3) >> 2);
+    const i32x4* cp = reinterpret_cast<const i32x4*>(ent + base) + lane;
+    const f32x4* vp = reinterpret_cast<const f32x4*>(ent + base + SELL_VAL) + lane;
     double acc = 0.0;
-    int e = e0;
-    for (; e + U <= e1; e += U) {
-        int32_t c[U];
-        float v[U];
+    int g = g0;
+    for (; g + U <= g1; g += U) {
+        i32x4 c[U];
+        f32x4 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            c[u] = __builtin_nontemporal_load(cp + (int64_t)(e + u) * 64);
-            v[u] = __builtin_nontemporal_load(vp + (int64_t)(e + u) * 64);
+            c[u] = __builtin_nontemporal_load(cp + (int64_t)(g + u) * 128);
+            v[u] = __builtin_nontemporal_load(vp + (int64_t)(g + u) * 128);
         }
-        float xv[U];
+        float xv[U][4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc = fma((double)v[u], (double)xv[u], acc);
+            for (int q = 0; q < 4; ++q) xv[u][q] = xs[c[u][q]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc = fma((double)v[u][q], 4 * (g + u) + q < L ? (double)xv[u][q] : 0.0, acc);
     }
-    for (; e < e1; ++e)
-        acc = fma((double)__builtin_nontemporal_load(vp + (int64_t)e * 64),
-                  (double)x[__builtin_nontemporal_load(cp + (int64_t)e * 64)], acc);
+    for (; g < g1; ++g) {
+        const i32x4 c = __builtin_nontemporal_load(cp + (int64_t)g * 128);
+        const f32x4 v = __builtin_nontemporal_load(vp + (int64_t)g * 128);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float xq = xs[c[q]];
+            acc = fma((double)v[q], 4 * g + q < L ? (double)xq : 0.0, acc);
+        }
+    }
     part[w][lane] = acc;
     __syncthreads();
-    if (w == 0 && row < nrows) y[row] = (float)(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+    if (w == 0 && valid) y[row] = (float)(((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
 }
 
-void launch_sell_spmv(hipStream_t st, int64_t nrows, const int64_t* sp, const int32_t* len,
-                      const int32_t* col, const float* val, const float* x, float* y) {
-    const int64_t ns = (nrows + 63) / 64;
-    hipLaunchKernelGGL(k_sell_spmv<8>, dim3((unsigned)ns), dim3(256), 0, st, nrows, sp, len, col, val, x, y);
+void launch_sell_spmv(hipStream_t st, const SellShape& S, const int64_t* sp, const int32_t* len,
+                      const int32_t* ent, const float* x, const float* xT, const uint8_t* segT, float* y) {
+    const int64_t ns = S.nseg * S.spseg;
+    hipLaunchKernelGGL(k_sell_spmv<4>, dim3((unsigned)ns), dim3(256), 0, st, S, sp, len, ent, x, xT, segT, y);
+}
+
+// xT[j * rows + i] = x[i * cols + j], through 64 x 64 LDS tiles.
+__global__ __launch_bounds__(256) void k_transpose(int rows, int cols, const float* __restrict__ x,
+                                                   float* __restrict__ xT) {
+    __shared__ float t[64][65];
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4)
+        if (i0 + r < rows && j0 + tx < cols) t[r][tx] = x[(size_t)(i0 + r) * cols + j0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4)
+        if (j0 + r < cols && i0 + tx < rows) xT[(size_t)(j0 + r) * rows + i0 + tx] = t[tx][r];
+}
+
+void launch_transpose(hipStream_t st, int rows, int cols, const float* x, float* xT) {
+    hipLaunchKernelGGL(k_transpose, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, st, rows, cols, x,
+                       xT);
 }
 
 }  // namespace sp

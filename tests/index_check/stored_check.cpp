@@ -7,7 +7,10 @@
 //     row's slot of the counted offsets),
 //   * every column index lies in [0, n) for R and [0, m) for R^T and every
 //     stored weight is positive and finite,
-//   * R^T is exactly the transpose of R (same entries, bit-identical weights).
+//   * R^T is exactly the transpose of R (same entries, bit-identical weights),
+//   * the sliced-ELL placement (slice sizes from the longest row, offsets from
+//     their scan, entry offsets of sell_offset) puts every entry of every row
+//     inside its slice and no two entries at the same place.
 // With --dump PATH the entries of R for the last geometry are written to PATH
 // as records (int32 ray, int32 pixel, float64 weight) in R's row order.
 //
@@ -85,6 +88,41 @@ int main(int argc, char** argv) {
             if (fill != cnt) {
                 std::fprintf(stderr, "VIOLATION: pixel %d counted %d filled %d\n", q, cnt, fill);
                 return 1;
+            }
+        }
+        // sliced-ELL placement of both sides
+        for (int sd = 0; sd < 2; ++sd) {
+            const SellShape S = sd == 0 ? SellShape{G.nA, G.nB, (G.nB + 63) / 64}
+                                        : SellShape{G.rows, G.cols, (G.cols + 63) / 64};
+            const int64_t rows = sd == 0 ? m : n, ns = S.nseg * S.spseg;
+            std::vector<int32_t> len((size_t)rows, 0);
+            for (const Entry& en : sd == 0 ? r_ent : t_ent) ++len[(size_t)en.row];
+            std::vector<int64_t> sp((size_t)ns + 1, 0);
+            for (int64_t sl = 0; sl < ns; ++sl) {
+                const int64_t seg = sl / S.spseg, k0 = (sl % S.spseg) * 64;
+                int w = 0;
+                for (int l = 0; l < 64 && k0 + l < S.lseg; ++l) w = imax(w, len[(size_t)(seg * S.lseg + k0 + l)]);
+                sp[(size_t)sl + 1] = sp[(size_t)sl] + 128 * ((w + 3) & ~3);
+            }
+            std::vector<unsigned char> used((size_t)sp[(size_t)ns], 0);
+            for (int64_t r = 0; r < rows; ++r) {
+                const int64_t sl = sell_slice(S, r);
+                const int lane = sell_lane(S, r);
+                if (sl < 0 || sl >= ns || lane < 0 || lane > 63 || (r % S.lseg) / 64 != sl % S.spseg) {
+                    std::fprintf(stderr, "VIOLATION: side %d row %lld slice %lld lane %d\n", sd, (long long)r,
+                                 (long long)sl, lane);
+                    return 1;
+                }
+                for (int e = 0; e < len[(size_t)r]; ++e) {
+                    const int64_t p = sp[(size_t)sl] + sell_offset(lane, e);
+                    const int64_t pv = p + SELL_VAL;
+                    if (p < sp[(size_t)sl] || pv >= sp[(size_t)sl + 1] || used[(size_t)p] || used[(size_t)pv]) {
+                        std::fprintf(stderr, "VIOLATION: side %d row %lld entry %d at %lld\n", sd, (long long)r,
+                                     e, (long long)p);
+                        return 1;
+                    }
+                    used[(size_t)p] = used[(size_t)pv] = 1;
+                }
             }
         }
         // R^T = R transposed: sort R's entries by (pixel, ray)
