@@ -115,8 +115,11 @@ def batched_run(sp, torch, iters):
     e1.record()
     torch.cuda.synchronize()
     t_seq = e0.elapsed_time(e1) / 1e3
+    shapes = {f"{g.rows}x{g.cols}x{g.n_angles}x{g.n_bins}": {"parts": p_, "px": x_}
+              for g, p_, x_ in sp.tuning_list() if g in set(geoms)}
     return {"workload": "64 slices, sides {256,384,512,768,1024} (seed 2), 1.4 x side angles, "
                         "ceil(side sqrt 2)+1 bins, SupPCG K=1, ramp-Hamming M",
+            "tuned_shapes": shapes,
             "iterations": iters, "slice_iterations_per_s": round(64 * iters / t_batch, 2),
             "one_by_one_slice_iterations_per_s": round(64 * iters / t_seq, 2),
             "speedup_vs_one_by_one": round(t_seq / t_batch, 3),
@@ -612,6 +615,13 @@ def main():
                   "ell_last": int(res.trace["ell"][-1]) if len(res.trace["ell"]) else None},
     }
     log("main solve done")
+    # the launch-shape landscape at this workload (after the timed runs, which
+    # use the default shapes; later parts of the run use the tuned ones)
+    tuned = sp.tune_shapes(g)
+    out["shape_tuning"] = {"parts": tuned["parts"], "px": tuned["px"],
+                           "R_ms_by_parts": {str(k): round(v, 4) for k, v in tuned["R_ms"].items()},
+                           "RT_ms_by_px": {str(k): round(v, 4) for k, v in tuned["RT_ms"].items()},
+                           "note": "best of 5 standalone calls each, padding/prep launch included"}
     if not args.no_batch:
         out["batched"] = batched_run(sp, torch, args.batch_iters)
         log("batched run done")

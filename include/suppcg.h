@@ -310,10 +310,12 @@ int sp_solve_status(sp_ctx* ctx, int32_t count, int32_t* k, int32_t* status);
  *   pc: SP_PRECOND_RAMP or SP_PRECOND_NONE, shared by all slices.
  *   sp->flags: SP_FLAG_GRAPH captures one loop body in a HIP graph and replays
  *     it; SP_FLAG_ASYNC as for sp_suppcg_solve (k_out device int32[n]);
- *     SP_FLAG_AUTOTUNE times the launch shapes of the heavy stages (item
- *     order: slice-major or grouped by XCD; grid: one workgroup per item or a
- *     persistent 2/4/8 workgroups per CU) once per batch layout and keeps the
- *     fastest; SP_FLAG_REPLAY and SP_FLAG_RESUME are not supported here.
+ *     SP_FLAG_AUTOTUNE first tunes the projector launch shapes (sp_tune_shapes)
+ *     of every slice geometry the shape table does not hold, then times the
+ *     dispatch of the heavy stages (item order: slice-major or grouped by
+ *     XCD; grid: one workgroup per item or a persistent 2/4/8 workgroups per
+ *     CU) once per batch layout and keeps the fastest; SP_FLAG_REPLAY and
+ *     SP_FLAG_RESUME are not supported here.
  *   k_out: host [n].  trace (nullable): host arrays [n][cap] and status[n].
  * Limits: 1 <= n <= 4096; each slice within the single-slice limits.
  * Returns SP_OK when every slice ended without error (per-slice SP_MAXITER /
@@ -377,6 +379,33 @@ int sp_lp_loss_grad(sp_ctx* ctx, sp_learned* net, int32_t rows, int32_t cols, co
  * (device float32); step counts from 1. */
 int sp_lp_adam_step(sp_ctx* ctx, sp_learned* net, const float* grad, double lr, double beta1,
                     double beta2, double eps, int32_t step);
+
+/* ---- launch shapes ------------------------------------------------------------
+ * Two launch shapes of the projector pair can be chosen per geometry: the
+ * number of parts R splits each ray's walk into (1, 2, 4 or 8; the parts'
+ * float64 sums are added in part order, so the choice changes R's results by
+ * rounding) and the pixels per lane of R^T (2 or 4; the results do not
+ * depend on it).  By default a rule of the image size and the wave slots
+ * picks them.  The choices live in one process-wide table keyed by the whole
+ * geometry; every solve, operator and batch of that geometry built after an
+ * update uses them, so single and batched solves of a geometry stay bitwise
+ * equal (a batch takes 4 pixels per lane for all slices only if all of them
+ * agree on it).  Updating the table between the two halves of a resumed run
+ * changes R's rounding between them.
+ * sp_tune_shapes: times sp_project for each part count (with the default
+ * pixels per lane) and then sp_backproject for 2 and 4 pixels per lane on the
+ * context's stream, keeps the fastest (the default wins ties within 2%), and
+ * stores it; ms (HOST double[6], nullable) receives the best-of-5 times of R
+ * at 1, 2, 4, 8 parts and of R^T at 2, 4 pixels per lane.  Synchronises.
+ * sp_tuning_set: stores a choice (parts 1..8, px 2 or 4; both 0 erases the
+ * entry); SP_ERR_ARG for other values or an invalid geometry.
+ * sp_tuning_list: *count = entries; copies up to cap of them to HOST arrays
+ * (each nullable).  sp_tuning_clear: erases all entries.  These three touch no
+ * device. */
+int sp_tune_shapes(sp_ctx* ctx, const sp_geometry* g, int32_t* parts, int32_t* px, double* ms);
+int sp_tuning_set(const sp_geometry* g, int32_t parts, int32_t px);
+int sp_tuning_list(sp_geometry* geoms, int32_t* parts, int32_t* px, int32_t cap, int32_t* count);
+int sp_tuning_clear(void);
 
 /* ---- stored matrices (Section 2, eqs. 2.1-2.2) ---------------------------------
  * R as an explicit sparse matrix: entry (a * n_bins + k, i * cols + j) is the

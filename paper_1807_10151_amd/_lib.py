@@ -126,6 +126,12 @@ _SIGS = {
                                 c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "sp_lp_adam_step": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double,
                                 c_double, c_int32]),
+    "sp_tune_shapes": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(c_int32), POINTER(c_int32),
+                               POINTER(c_double)]),
+    "sp_tuning_set": (c_int, [POINTER(sp_geometry), c_int32, c_int32]),
+    "sp_tuning_list": (c_int, [POINTER(sp_geometry), POINTER(c_int32), POINTER(c_int32), c_int32,
+                               POINTER(c_int32)]),
+    "sp_tuning_clear": (c_int, []),
     "sp_matrix_build": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(c_void_p)]),
     "sp_matrix_destroy": (c_int, [c_void_p]),
     "sp_matrix_info": (c_int, [c_void_p, POINTER(ctypes.c_int64), POINTER(ctypes.c_int64)]),

@@ -291,6 +291,72 @@ def batch_tuning(ctx: Context | None = None) -> dict:
     return {nm: ("xcd" if arr[2 * i] else "slice", int(arr[2 * i + 1])) for i, nm in enumerate(names)}
 
 
+def tune_shapes(g: Geometry, ctx: Context | None = None) -> dict:
+    """Times R's ray parts (1, 2, 4, 8) and R^T's pixels per lane (2, 4) for g on
+    the GPU and stores the fastest in the process-wide shape table."""
+    ctx = ctx or context(0)
+    parts, px = ctypes.c_int32(0), ctypes.c_int32(0)
+    ms = (ctypes.c_double * 6)()
+    gc = g.c()
+    ctx._stream()
+    ctx._check(ctx.lib.sp_tune_shapes(ctx.h, ctypes.byref(gc), ctypes.byref(parts), ctypes.byref(px), ms))
+    return {"parts": parts.value, "px": px.value,
+            "R_ms": {p_: ms[i] for i, p_ in enumerate((1, 2, 4, 8))},
+            "RT_ms": {2: ms[4], 4: ms[5]}}
+
+
+def tuning_set(g: Geometry, parts: int, px: int):
+    """Stores launch shapes for g (parts = px = 0 erases the entry)."""
+    gc = g.c()
+    rc = L.load().sp_tuning_set(ctypes.byref(gc), parts, px)
+    if rc != L.SP_OK:
+        raise SupPCGError(rc, f"sp_tuning_set rejected parts={parts} px={px}")
+
+
+def tuning_list():
+    """[(Geometry, parts, px)] of the shape table."""
+    lib = L.load()
+    cnt = ctypes.c_int32(0)
+    lib.sp_tuning_list(None, None, None, 0, ctypes.byref(cnt))
+    n = cnt.value
+    gs = (L.sp_geometry * max(n, 1))()
+    parts = (ctypes.c_int32 * max(n, 1))()
+    px = (ctypes.c_int32 * max(n, 1))()
+    lib.sp_tuning_list(gs, parts, px, n, ctypes.byref(cnt))
+    out = []
+    for i in range(min(n, cnt.value)):
+        c = gs[i]
+        out.append((Geometry(c.rows, c.cols, c.n_angles, c.n_bins, c.pixel, c.theta0,
+                             None if c.dtheta <= 0 else c.dtheta, c.bin_spacing, c.bin_offset),
+                    parts[i], px[i]))
+    return out
+
+
+def tuning_clear():
+    L.load().sp_tuning_clear()
+
+
+def tuning_save(path: str):
+    """Writes the shape table as JSON (one record per geometry)."""
+    import json
+    recs = [{"rows": g.rows, "cols": g.cols, "n_angles": g.n_angles, "n_bins": g.n_bins, "pixel": g.pixel,
+             "theta0": g.theta0, "dtheta": g.dtheta, "bin_spacing": g.bin_spacing, "bin_offset": g.bin_offset,
+             "parts": p_, "px": x_} for g, p_, x_ in tuning_list()]
+    with open(path, "w") as f:
+        json.dump({"shapes": recs}, f, indent=1)
+
+
+def tuning_load(path: str):
+    """Adds the records of a JSON file written by tuning_save to the shape table."""
+    import json
+    with open(path) as f:
+        recs = json.load(f)["shapes"]
+    for r in recs:
+        g = Geometry(r["rows"], r["cols"], r["n_angles"], r["n_bins"], r["pixel"], r["theta0"], r["dtheta"],
+                     r["bin_spacing"], r["bin_offset"])
+        tuning_set(g, int(r["parts"]), int(r["px"]))
+
+
 class StoredMatrix:
     """R and R^T of geometry g as stored CSR matrices on the GPU (sp_matrix_*)."""
 

@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -39,6 +41,7 @@ struct BatchState {
     int order[BS_COUNT] = {};        // chosen order (0 slice-major, 1 grouped by XCD)
     int wpc[BS_COUNT] = {};          // chosen workgroups per CU (0: one per item)
     bool tuned = false;
+    uint64_t epoch = 0;              // launch-shape epoch of the layout
 };
 
 }  // namespace
@@ -50,6 +53,7 @@ struct sp_ctx {
 
     // geometry cache
     bool have_geom = false;
+    uint64_t geom_epoch = 0;   // launch-shape epoch the cached tables were built at
     sp_geometry geom{};
     GeomDev G{};
     std::vector<AngleDev> ang_h;
@@ -205,12 +209,56 @@ int validate_geometry(sp_ctx* c, const sp_geometry* g) {
     return SP_OK;
 }
 
+// Launch shapes of the projector pair per geometry (sp_tune_shapes,
+// sp_tuning_set): R's ray parts and R^T's pixels per lane, process-wide.
+// Every table built for a geometry takes its entry, so single and batched
+// solves of one geometry use the same shapes; the epoch changes with every
+// update, which makes the contexts rebuild their cached tables.
+struct ShapeEntry {
+    sp_geometry g;
+    int32_t parts, px;
+};
+std::mutex g_shape_mu;
+std::vector<ShapeEntry> g_shapes;
+std::atomic<uint64_t> g_shape_epoch{1};
+
+bool shape_lookup(const sp_geometry& g, int& parts, int& px) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    for (const ShapeEntry& e : g_shapes)
+        if (same_geom(e.g, g)) {
+            parts = e.parts;
+            px = e.px;
+            return true;
+        }
+    return false;
+}
+
+// parts == 0 erases the entry
+void shape_store(const sp_geometry& g, int parts, int px) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    for (size_t i = 0; i < g_shapes.size(); ++i)
+        if (same_geom(g_shapes[i].g, g)) {
+            if (parts == 0) g_shapes.erase(g_shapes.begin() + (long)i);
+            else g_shapes[i].parts = parts, g_shapes[i].px = px;
+            ++g_shape_epoch;
+            return;
+        }
+    if (parts != 0) g_shapes.push_back(ShapeEntry{g, parts, px});
+    ++g_shape_epoch;
+}
+
 // Device geometry and class-sorted angle table (geometry.cpp), failures
-// reported on the context.
+// reported on the context; tuned launch shapes replace the defaults.
 int build_geometry_into(sp_ctx* c, const sp_geometry* g, GeomDev& G, AngleDev* tab) {
     char msg[256];
     const int rc = sp::build_geometry_into(g, c->n_cu, G, tab, msg, sizeof msg);
-    return rc ? fail(c, rc, "%s", msg) : SP_OK;
+    if (rc) return fail(c, rc, "%s", msg);
+    int parts, px;
+    if (shape_lookup(*g, parts, px)) {
+        G.parts = parts;
+        G.bp_px = px;
+    }
+    return SP_OK;
 }
 
 int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<AngleDev>& tab) {
@@ -221,7 +269,8 @@ int build_geometry(sp_ctx* c, const sp_geometry* g, GeomDev& G, std::vector<Angl
 int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     int rc = validate_geometry(c, g);
     if (rc) return rc;
-    if (c->have_geom && same_geom(c->geom, *g)) return SP_OK;
+    const uint64_t epoch = g_shape_epoch.load();
+    if (c->have_geom && same_geom(c->geom, *g) && c->geom_epoch == epoch) return SP_OK;
     GeomDev G{};
     std::vector<AngleDev> tab;
     if ((rc = build_geometry(c, g, G, tab))) return rc;
@@ -259,6 +308,7 @@ int setup_geometry(sp_ctx* c, const sp_geometry* g) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));  // host tables must outlive the copies
     c->G = G;
     c->geom = *g;
+    c->geom_epoch = epoch;
     c->have_geom = true;
     return SP_OK;
 }
@@ -639,7 +689,9 @@ ItemTable table(sp_ctx* c, int stage, int order = -1, int wpc = -1) {
 // slice's padded copies, vectors, FFT scratch, twiddles and partials, and the
 // item tables.  Kept while the geometries and preconditioner kind repeat.
 int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
+    const uint64_t epoch = g_shape_epoch.load();
     if (c->batch && c->batch->kind == kind && (int)c->batch->geoms.size() == n &&
+        c->batch->epoch == epoch &&
         std::memcmp(c->batch->geoms.data(), geoms, sizeof(sp_geometry) * (size_t)n) == 0)
         return SP_OK;
     if (!c->batch) c->batch = new BatchState();
@@ -717,6 +769,15 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         long waves4 = 0;
         for (const SliceDev& S : B.hs) waves4 += (long)backproject_tiles(S.G, 4) * 4;
         B.bp_px = waves4 >= (long)c->n_cu * 16 ? 4 : 2;
+        // tuned shapes that agree for every slice take precedence
+        int tpx = 0;
+        bool all = true;
+        for (int s = 0; s < n && all; ++s) {
+            int tp, tx;
+            if (!shape_lookup(geoms[s], tp, tx) || (tpx && tx != tpx)) all = false;
+            else tpx = tx;
+        }
+        if (all && tpx) B.bp_px = tpx;
         for (SliceDev& S : B.hs) S.G.bp_px = B.bp_px;
     }
     // a fresh zero-filled arena: the pads of the padded copies must be zero
@@ -801,6 +862,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     B.geoms.assign(geoms, geoms + n);
+    B.epoch = epoch;
     return SP_OK;
 }
 
@@ -1187,6 +1249,127 @@ int sp_backproject_noalloc(sp_ctx* c, const sp_geometry* g, const float* y, floa
     launch_pad_sino(c->stream, G, ang, y, yp);   // every entry of the rows, pads included
     launch_backproject(c->stream, G, ang, yp, x, nullptr, nullptr, nullptr);
     return check_launch(c);
+}
+
+// ---- launch-shape tuning ------------------------------------------------------------
+
+int sp_tune_shapes(sp_ctx* c, const sp_geometry* g, int32_t* parts_out, int32_t* px_out, double* ms) {
+    if (!c) return SP_ERR_ARG;
+    HIP_TRY(c, hipSetDevice(c->device));
+    int rc = drain_pending(c);
+    if (rc) return rc;
+    if ((rc = setup_geometry(c, g))) return rc;
+    const int def_parts = c->G.parts, def_px = c->G.bp_px;
+    int old_parts = 0, old_px = 0;
+    const bool had = shape_lookup(*g, old_parts, old_px);
+    DevBuf xb, yb;
+    struct Tmp {
+        DevBuf *a, *b;
+        ~Tmp() {
+            release(*a);
+            release(*b);
+        }
+    } tmp{&xb, &yb};
+    const size_t n = (size_t)g->rows * g->cols, m = (size_t)g->n_angles * g->n_bins;
+    if ((rc = ensure(c, xb, n * 4)) || (rc = ensure(c, yb, m * 4))) return rc;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, SP_ERR_HIP, "hipEventCreate failed");
+    }
+    // fastest of 5 calls after a warm-up (data values do not change the work)
+    auto time_call = [&](bool back, float& best) -> int {
+        best = 1e30f;
+        for (int r = 0; r < 6; ++r) {
+            (void)hipEventRecord(e0, c->stream);
+            const int q = back ? sp_backproject(c, g, dptr<float>(yb), dptr<float>(xb))
+                               : sp_project(c, g, dptr<float>(xb), dptr<float>(yb));
+            if (q) return q;
+            (void)hipEventRecord(e1, c->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(c, SP_ERR_HIP, "timing the launch shapes failed");
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (r > 0) best = std::min(best, t);
+        }
+        return SP_OK;
+    };
+    const int parts_c[4] = {1, 2, 4, 8}, px_c[2] = {2, 4};
+    float tr[4], tb[2];
+    int best_parts = def_parts, best_px = def_px;
+    rc = SP_OK;
+    for (int i = 0; i < 4 && !rc; ++i) {
+        shape_store(*g, parts_c[i], def_px);
+        rc = time_call(false, tr[i]);
+    }
+    if (!rc) {
+        // the default wins ties within 2%
+        float tdef = 1e30f;
+        for (int i = 0; i < 4; ++i)
+            if (parts_c[i] == def_parts) tdef = tr[i];
+        float best = tdef;
+        for (int i = 0; i < 4; ++i)
+            if (tr[i] < 0.98f * best) best = tr[i], best_parts = parts_c[i];
+    }
+    for (int i = 0; i < 2 && !rc; ++i) {
+        shape_store(*g, best_parts, px_c[i]);
+        rc = time_call(true, tb[i]);
+    }
+    if (!rc) {
+        float tdef = def_px == 4 ? tb[1] : tb[0], best = tdef;
+        for (int i = 0; i < 2; ++i)
+            if (tb[i] < 0.98f * best) best = tb[i], best_px = px_c[i];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {   // leave the cache as it was
+        if (had) shape_store(*g, old_parts, old_px);
+        else shape_store(*g, 0, 0);
+        return rc;
+    }
+    shape_store(*g, best_parts, best_px);
+    if (parts_out) *parts_out = best_parts;
+    if (px_out) *px_out = best_px;
+    if (ms) {
+        for (int i = 0; i < 4; ++i) ms[i] = tr[i];
+        for (int i = 0; i < 2; ++i) ms[4 + i] = tb[i];
+    }
+    return SP_OK;
+}
+
+int sp_tuning_set(const sp_geometry* g, int32_t parts, int32_t px) {
+    if (!g) return SP_ERR_ARG;
+    if (parts == 0 && px == 0) {
+        shape_store(*g, 0, 0);
+        return SP_OK;
+    }
+    if (parts < 1 || parts > 8 || (px != 2 && px != 4)) return SP_ERR_ARG;
+    char msg[128];
+    GeomDev G{};
+    std::vector<AngleDev> tab((size_t)std::max(g->n_angles, 1));
+    if (g->n_angles < 1 || sp::build_geometry_into(g, 256, G, tab.data(), msg, sizeof msg) != SP_OK)
+        return SP_ERR_ARG;
+    shape_store(*g, parts, px);
+    return SP_OK;
+}
+
+int sp_tuning_list(sp_geometry* geoms, int32_t* parts, int32_t* px, int32_t cap, int32_t* count) {
+    if (!count || cap < 0) return SP_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    *count = (int32_t)g_shapes.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)g_shapes.size(); ++i) {
+        if (geoms) geoms[i] = g_shapes[(size_t)i].g;
+        if (parts) parts[i] = g_shapes[(size_t)i].parts;
+        if (px) px[i] = g_shapes[(size_t)i].px;
+    }
+    return SP_OK;
+}
+
+int sp_tuning_clear(void) {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shapes.clear();
+    ++g_shape_epoch;
+    return SP_OK;
 }
 
 int sp_residual(sp_ctx* c, const sp_geometry* g, const float* x, const float* b, float* r, double* f) {
@@ -2065,6 +2248,15 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     if (sp->flags & SP_FLAG_REPLAY) return fail(c, SP_ERR_ARG, "SP_FLAG_REPLAY is not supported by the batched solver");
     if (sp->max_iter < 0) return fail(c, SP_ERR_ARG, "max_iter must be >= 0");
     if (!std::isfinite(sp->eps)) return fail(c, SP_ERR_ARG, "eps must be finite");
+    if (sp->flags & SP_FLAG_AUTOTUNE) {
+        // launch shapes of every geometry the table does not hold yet
+        for (int s = 0; s < n; ++s) {
+            int tp, tx;
+            if (shape_lookup(geoms[s], tp, tx)) continue;
+            if ((rc = sp_tune_shapes(c, &geoms[s], nullptr, nullptr, nullptr)))
+                return fail(c, rc, "slice %d: tuning its launch shapes: %s", s, c->err);
+        }
+    }
     if ((rc = batch_setup(c, n, geoms, pc->kind))) return rc;
     BatchState& B = *c->batch;
     const int K = (tv && tv->K > 0) ? tv->K : 0;
