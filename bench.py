@@ -144,9 +144,10 @@ QUALITY_WORKLOADS = {"ct512": (512, 512, 720, 725, 20, 1, 0.005),
 def quality_run(sp, torch, iters):
     """Iteration-wise and time-wise selective-error curves (eq. (4.1), the
     ellipse of Section 4.2 scaled to the image width) of SupPCG, PCG, SupCG and
-    CG, each under Table 1's parameters and under the defaults, at 512^2 x 720
-    x 725 and at the paper's shape (243^2 x 360 x 345); graph-replayed loop
-    bodies, HIP events between them."""
+    CG, each under Table 1's parameters and under the defaults, and of ART and
+    SupART under Table 1's (40 cycles), at 512^2 x 720 x 725 and at the
+    paper's shape (243^2 x 360 x 345); graph-replayed loop bodies, HIP events
+    between them."""
     from synth import noisy_data, random_ellipses, unit_noise
     marks = sorted(set([0, 1, 2, 3, 4, 5] + list(range(10, iters + 2, 5)) + [iters + 1]))
     out = {}
@@ -174,6 +175,19 @@ def quality_run(sp, torch, iters):
                     "ms_total": round(float(t[-1]), 3),
                     "curve": [[k, round(float(se[k]), 6), round(float(t[k]), 3)]
                               for k in marks if k < len(se)]}
+        # ART and SupART (Section 3.4) under Table 1's parameters
+        art_iters = min(iters, 40)
+        amarks = [k for k in marks if k <= art_iters]
+        for method, kw in (("ART", dict(K=0, r=5.0, lam=1e-2)),
+                           ("SupART", dict(K=10, a=1 - 1e-5, gamma=1e-2, r=5.0, lam=5e-2))):
+            sp.sp_supart_solve(g, b, max_iter=1, **kw)
+            r_ = sp.sp_supart_solve(g, b, max_iter=art_iters, se_ref=x_true, timing=True, **kw)
+            se, t = r_.trace["se"], r_.trace["t_ms"]
+            kb = int(np.nanargmin(se))
+            res_w[f"{method}/table1"] = {
+                "params": kw, "best": {"iteration": kb, "se": round(float(se[kb]), 6), "ms": round(float(t[kb]), 3)},
+                "ms_total": round(float(t[-1]), 3), "ms_per_cycle": round(float(t[-1]) / art_iters, 3),
+                "curve": [[k, round(float(se[k]), 6), round(float(t[k]), 3)] for k in amarks if k < len(se)]}
         out[wname] = res_w
     return {"iterations": iters, "curve_columns": ["iteration k", "SE(x_k)", "ms to x_k"],
             "workloads": out}

@@ -380,6 +380,33 @@ int sp_lp_loss_grad(sp_ctx* ctx, sp_learned* net, int32_t rows, int32_t cols, co
 int sp_lp_adam_step(sp_ctx* ctx, sp_learned* net, const float* grad, double lr, double beta1,
                     double beta2, double eps, int32_t step);
 
+/* ---- ART and SupART (Section 3.4) ---------------------------------------------
+ * ART for the Bayesian criterion of eq. (2.3), r^2 ||R x - b||^2 +
+ * ||x - mu||^2: each step projects (x, u) toward the hyperplane of one ray of
+ * the system r R (x - mu) + u = r (b - R mu) with relaxation lambda,
+ *   c = lambda (r (b_i - <R_i, x>) - u_i) / (1 + r^2 ||R_i||^2),
+ *   u_i += c, x += r c R_i^T;
+ * one iteration is a cycle through all rays, angle by angle in increasing
+ * index and, within an angle, in q phases (rays k = ph, ph + q, ... for
+ * ph = 0 .. q-1, q = floor(2 e / ds + 1e-9) + 1 with e = pixel (|cos| +
+ * |sin|) / 2): the rays of a phase touch disjoint pixels and are projected
+ * concurrently.  mu is the uniform image at the mean gray level estimated
+ * from the data, bin_spacing * sum(b) / (n_angles * rows * cols * pixel^2);
+ * x starts at x0 (DEVICE float32 [rows][cols]; NULL: mu) and u at 0; rays with
+ * R_i = 0 are skipped.  With tv->K > 0 each iteration first applies
+ * Algorithm 1 (SupART, the superiorized step of Section 3.1); tv NULL or K = 0
+ * is ART.  r > 0, 0 < lambda < 2.  sp: max_iter iterations (eps is ignored;
+ * flags: SP_FLAG_GRAPH only).  x_out (DEVICE float32) receives x after the
+ * last cycle.  trace (nullable): ell, tv_half and trials as for the solver
+ * (entry k-1: iteration k's S_TV), se[k-1] = SE(x_k) with se0 = SE(x_0), and
+ * t_ms[k-1] = milliseconds to the end of iteration k; f_half, alpha, beta,
+ * s_norm, g_snap, se1 and t1_ms are not written (se1, t1_ms: NaN).  The
+ * iterate is float64 on the device.  Returns SP_MAXITER, or
+ * SP_TRIALS_EXHAUSTED if an S_TV inner step accepted no trial. */
+int sp_supart_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const float* x0,
+                    const sp_tv_params* tv, double r, double lambda, const sp_solve_params* sp,
+                    float* x_out, sp_trace* trace);
+
 /* ---- launch shapes ------------------------------------------------------------
  * Two launch shapes of the projector pair can be chosen per geometry: the
  * number of parts R splits each ray's walk into (1, 2, 4 or 8; the parts'

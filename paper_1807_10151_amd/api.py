@@ -525,6 +525,64 @@ def sp_tv(g: Geometry, x: torch.Tensor, ctx: Context | None = None):
     return out
 
 
+@dataclass
+class ARTResult:
+    x: torch.Tensor
+    status: int
+    trace: dict = field(default_factory=dict)
+
+
+def sp_supart_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None, *, K: int = 0,
+                    a: float = 1 - 1e-5, gamma: float = 1e-2, max_trials: int = 100, r: float = 5.0,
+                    lam: float = 0.05, max_iter: int = 10, graph: bool = True, se_ref: torch.Tensor | None = None,
+                    se_axes=None, se_c: float = 0.0, timing: bool = False, x_out: torch.Tensor | None = None,
+                    ctx: Context | None = None) -> ARTResult:
+    """ART for the Bayesian criterion (K = 0) or SupART (K > 0), max_iter cycles
+    through the rays (sp_supart_solve).  The trace holds ell, tv_half and
+    trials (SupART), "se" = [SE(x_0), SE(x_1), ...] with se_ref, and
+    "t_ms" = [0, t(x_1), ...] with timing."""
+    ctx = ctx or context(b.device.index or 0)
+    dev = ctx.device
+    x_out = _out(x_out, (g.rows, g.cols), dev)
+    gc = g.c()
+    tvp = L.sp_tv_params(K, a, gamma, max_trials)
+    sp = L.sp_solve_params(0.0, max_iter, L.SP_FLAG_GRAPH if graph else 0, None)
+    cap = max(max_iter, 1)
+    dp = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ip = lambda a_: a_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    arrs = {"tv_half": np.zeros(cap), "ell": np.zeros(cap, dtype=np.int32),
+            "trials": np.zeros(cap * max(K, 1), dtype=np.int32)}
+    tr = L.sp_trace(None, dp(arrs["tv_half"]), None, None, None, ip(arrs["ell"]), ip(arrs["trials"]), cap,
+                    0.0, 0.0, 0, None, 0, 0)
+    if se_ref is not None:
+        _dev(se_ref, g.n, "se_ref", dev)
+        axes = paper_se_axes(g) if se_axes is None else tuple(float(v) for v in se_axes)
+        arrs["se"] = np.full(cap, np.nan)
+        tr.se_ref = ctypes.c_void_p(se_ref.data_ptr())
+        tr.se_axes[0], tr.se_axes[1] = axes
+        tr.se_c = se_c
+        tr.se = dp(arrs["se"])
+    if timing:
+        arrs["t_ms"] = np.zeros(cap)
+        tr.t_ms = dp(arrs["t_ms"])
+    ctx._stream()
+    rc = ctx.lib.sp_supart_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
+                                 _dev(x0, g.n, "x0", dev) if x0 is not None else None, ctypes.byref(tvp),
+                                 r, lam, ctypes.byref(sp), _dev(x_out, g.n, "x_out", dev), ctypes.byref(tr))
+    ctx._check(rc, ok=(L.SP_MAXITER, L.SP_TRIALS_EXHAUSTED))
+    done = min(tr.bodies, cap)
+    out = {}
+    if K > 0:
+        out["tv_half"] = arrs["tv_half"][:done]
+        out["ell"] = arrs["ell"][:done]
+        out["trials"] = arrs["trials"][:done * K].reshape(done, K)
+    if se_ref is not None:
+        out["se"] = np.concatenate([[tr.se0], arrs["se"][:done]])
+    if timing:
+        out["t_ms"] = np.concatenate([[0.0], arrs["t_ms"][:done]])
+    return ARTResult(x_out, rc, out)
+
+
 # The paper's ellipse for the selective error: semi-axes 5 cm (horizontal) and
 # 7 cm (vertical) on a phantom 243 pixels of 0.0752 cm wide (Section 4.2);
 # other images keep the same share of their width.

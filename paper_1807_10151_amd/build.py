@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsuppcg.so")
 
-SOURCES = ["projector.hip", "fft.hip", "tv.hip", "cg.hip", "learned.hip", "noalloc.hip", "quality.hip", "stored.hip",
+SOURCES = ["projector.hip", "fft.hip", "tv.hip", "cg.hip", "learned.hip", "noalloc.hip", "quality.hip", "stored.hip", "art.hip",
            "geometry.cpp", "capi.cpp"]
 
 # -ffp-contract=off: no multiply and add is fused implicitly; the fused ones

@@ -71,6 +71,7 @@ struct sp_ctx {
     DevBuf ox, oxh, oscal;                // sp_tv, sp_tv_grad, sp_tv_perturb
     DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc, part_se;
     DevBuf stored_xT;                     // transposed image for the stored R product
+    DevBuf art_u, art_nrm, art_sum;       // ART: auxiliary vector, ||R_i||^2, sum of b
     DevBuf scal, trace_d, replay_d, trials_tmp;
     Scalars sc_h{};
     hipStream_t own = nullptr;   // capture stream used when the caller's stream is null
@@ -978,7 +979,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     (void)drain_pending(c);
     for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
-                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->stored_xT, &c->scal,
+                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->stored_xT, &c->art_u, &c->art_nrm, &c->art_sum, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
         release(*b);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -1889,6 +1890,197 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     keep_state();
     if (out.halt == SP_ERR_NONFINITE) return fail(c, SP_ERR_NONFINITE, "non-finite value in a CG scalar");
     return status;
+}
+
+// ---- ART and SupART (Section 3.4) ---------------------------------------------------
+
+int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0,
+                    const sp_tv_params* tv, double r, double lam, const sp_solve_params* sp, float* x_out,
+                    sp_trace* trace) {
+    if (!c) return SP_ERR_ARG;
+    if (!b || !x_out || !sp) return fail(c, SP_ERR_ARG, "b, x_out and the solve parameters are required");
+    if (!(r > 0.0) || !std::isfinite(r)) return fail(c, SP_ERR_ARG, "r must be positive and finite");
+    if (!(lam > 0.0 && lam < 2.0)) return fail(c, SP_ERR_ARG, "lambda must lie in (0, 2)");
+    if (sp->max_iter < 0) return fail(c, SP_ERR_ARG, "max_iter must be >= 0");
+    if (sp->flags & ~(uint32_t)SP_FLAG_GRAPH)
+        return fail(c, SP_ERR_ARG, "only SP_FLAG_GRAPH is supported by the ART solver");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((sp->flags & SP_FLAG_GRAPH) && c->stream == nullptr && !c->prof) {
+        // the null stream cannot be captured: run on the owned stream, ordered
+        // after the caller's prior work
+        if (!c->own) HIP_TRY(c, hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+        if (!c->own_ev[0]) {
+            HIP_TRY(c, hipEventCreateWithFlags(&c->own_ev[0], hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->own_ev[1], hipEventDisableTiming));
+        }
+        HIP_TRY(c, hipEventRecord(c->own_ev[0], nullptr));
+        HIP_TRY(c, hipStreamWaitEvent(c->own, c->own_ev[0], 0));
+        c->stream = c->own;
+        const int r2 = sp_supart_solve(c, g, b, x0, tv, r, lam, sp, x_out, trace);
+        c->stream = nullptr;
+        (void)hipStreamSynchronize(c->own);
+        return r2;
+    }
+    int rc = drain_pending(c);
+    if (rc) return rc;
+    if ((rc = setup_geometry(c, g))) return rc;
+    if ((rc = check_tv(c, tv))) return rc;
+    const int K = (tv && tv->K > 0) ? tv->K : 0;
+    const GeomDev& G = c->G;
+    const int n = G.rows * G.cols, m = G.nA * G.nB;
+    c->st.ok = false;   // the solver vectors are reused below
+    if ((rc = ensure_vectors(c, n)) || (rc = ensure_partials(c))) return rc;
+    if ((rc = ensure(c, c->art_u, (size_t)m * 8)) || (rc = ensure(c, c->art_nrm, (size_t)m * 8)) ||
+        (rc = ensure(c, c->art_sum, 8)) || (rc = ensure(c, c->ox, (size_t)std::max(n, m) * 8)))
+        return rc;
+    std::vector<AngleDev> nat((size_t)G.nA);
+    for (const AngleDev& A : c->ang_h) nat[(size_t)A.row] = A;
+    DevBuf natd;
+    struct Tmp {
+        DevBuf* a;
+        ~Tmp() { release(*a); }
+    } tmp{&natd};
+    if ((rc = ensure(c, natd, nat.size() * sizeof(AngleDev)))) return rc;
+    hipStream_t st = c->stream;
+    HIP_TRY(c, hipMemcpyAsync(natd.ptr, nat.data(), nat.size() * sizeof(AngleDev), hipMemcpyHostToDevice, st));
+    const int cap = std::max(sp->max_iter, 1);
+    const size_t tr_main = (size_t)cap * (5 * 8 + 4) + (size_t)cap * std::max(K, 1) * 4;
+    const size_t se_off = (tr_main + 63) & ~(size_t)63;
+    const size_t tr_bytes = se_off + (size_t)(cap + 2) * 8;
+    const bool want_se = trace && trace->se_ref;
+    if (want_se) {
+        for (double a : trace->se_axes)
+            if (!(a > 0.0) || !std::isfinite(a)) return fail(c, SP_ERR_ARG, "se_axes must be positive and finite");
+        if (!std::isfinite(trace->se_c)) return fail(c, SP_ERR_ARG, "se_c must be finite");
+    }
+    if ((rc = ensure(c, c->trace_d, tr_bytes))) return rc;
+    HIP_TRY(c, hipMemsetAsync(c->trace_d.ptr, 0, se_off, st));
+    HIP_TRY(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(dptr<char>(c->trace_d) + se_off), 0x7FF80000,
+                                 (size_t)(cap + 2) * 2, st));
+    double* se_body = reinterpret_cast<double*>(dptr<char>(c->trace_d) + se_off);
+    TraceDev tr{};
+    {
+        char* base = dptr<char>(c->trace_d);
+        tr.f_half = reinterpret_cast<double*>(base);
+        tr.tv_half = tr.f_half + cap;
+        tr.alpha = tr.tv_half + cap;
+        tr.beta = tr.alpha + cap;
+        tr.s_norm = tr.beta + cap;
+        tr.ell = reinterpret_cast<int32_t*>(tr.s_norm + cap);
+        tr.trials = tr.ell + cap;
+        tr.cap = cap;
+    }
+    Scalars& s = c->sc_h;
+    s = Scalars{};
+    s.a = K ? tv->a : 0.5;
+    s.gamma = K ? tv->gamma : 0.0;
+    s.K = K;
+    s.max_trials = K ? (tv->max_trials > 0 ? tv->max_trials : 100) : 0;
+    s.max_iter = sp->max_iter;
+    if ((rc = upload_scalars(c, c->scal))) return rc;
+    Scalars* sc = dptr<Scalars>(c->scal);
+    const int* halt = &sc->halt;
+    double* x = dptr<double>(c->vx);
+    double* xh = dptr<double>(c->vxh);
+    double* u = dptr<double>(c->art_u);
+    double* nrm = dptr<double>(c->art_nrm);
+
+    std::vector<hipEvent_t> tev;
+    struct EvGuard {
+        std::vector<hipEvent_t>& v;
+        ~EvGuard() {
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        }
+    } ev_guard{tev};
+    if (trace && trace->t_ms) {
+        tev.resize((size_t)cap + 1, nullptr);
+        for (hipEvent_t& e : tev) HIP_TRY(c, hipEventCreate(&e));
+        HIP_TRY(c, hipEventRecord(tev[0], st));
+    }
+    launch_art_norms(st, G, dptr<AngleDev>(natd), nrm);
+    launch_art_init(st, G, b, x0, dptr<double>(c->ox), dptr<double>(c->art_sum), x, u);
+    if (want_se)
+        launch_se(st, G.rows, G.cols, g->pixel, trace->se_axes[0], trace->se_axes[1], x, trace->se_ref,
+                  trace->se_c, dptr<double>(c->part_se), se_body + cap, nullptr, 0, nullptr, nullptr);
+    if ((rc = check_launch(c))) return rc;
+    // one iteration: S_TV (SupART), then a cycle through the rays
+    auto body = [&]() -> int {
+        double* tgt = x;
+        if (K > 0) {
+            enqueue_stv(c, sc, K, x, xh, false, tr, nullptr);
+            tgt = xh;
+        }
+        launch_art_sweep(st, G, nat.data(), nrm, b, tgt, u, r, lam, halt);
+        if (K > 0) launch_copy(st, n, xh, x, halt);
+        launch_scalar(st, OP_NEXT, sc, tr, nullptr, 0, nullptr, 0);
+        if (want_se)
+            launch_se(st, G.rows, G.cols, g->pixel, trace->se_axes[0], trace->se_axes[1], x, trace->se_ref,
+                      trace->se_c, dptr<double>(c->part_se), nullptr, se_body, cap, sc, halt);
+        return check_launch(c);
+    };
+    if ((sp->flags & SP_FLAG_GRAPH) && sp->max_iter > 0 && !c->prof) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int brc = body();
+        const hipError_t ec = hipStreamEndCapture(st, &graph);
+        if (brc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return brc;
+        }
+        if (ec != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(c, SP_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        }
+        hipError_t el = hipSuccess;
+        for (int it = 0; it < sp->max_iter && el == hipSuccess; ++it) {
+            el = hipGraphLaunch(exec, st);
+            if (el == hipSuccess && !tev.empty()) el = hipEventRecord(tev[1 + it], st);
+        }
+        const hipError_t es = hipStreamSynchronize(st);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (el != hipSuccess) return fail(c, SP_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(el));
+        if (es != hipSuccess) return fail(c, SP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+    } else {
+        for (int it = 0; it < sp->max_iter; ++it) {
+            if ((rc = body())) return rc;
+            if (!tev.empty()) HIP_TRY(c, hipEventRecord(tev[1 + it], st));
+        }
+    }
+    launch_narrow(st, n, x, x_out);
+    Scalars out{};
+    HIP_TRY(c, hipMemcpyAsync(&out, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (trace) {
+        const int cnt = std::min(trace->cap, cap);
+        const int done = std::min(cnt, out.iter);
+        std::vector<char> host(tr_bytes);
+        HIP_TRY(c, hipMemcpy(host.data(), c->trace_d.ptr, tr_bytes, hipMemcpyDeviceToHost));
+        const double* htv = reinterpret_cast<const double*>(host.data()) + cap;
+        const int32_t* hell = reinterpret_cast<const int32_t*>(reinterpret_cast<const double*>(host.data()) + 5 * cap);
+        const int32_t* htr = hell + cap;
+        if (trace->tv_half && K > 0) std::copy(htv, htv + done, trace->tv_half);
+        if (trace->ell && K > 0) std::copy(hell, hell + done, trace->ell);
+        if (trace->trials && K > 0) std::copy(htr, htr + (size_t)done * K, trace->trials);
+        const double* hse = reinterpret_cast<const double*>(host.data() + se_off);
+        const double nan = std::numeric_limits<double>::quiet_NaN();
+        if (want_se && trace->se) std::copy(hse, hse + done, trace->se);
+        trace->se0 = want_se ? hse[cap] : nan;
+        trace->se1 = nan;
+        if (!tev.empty()) {
+            float ms = 0.0f;
+            for (int j = 0; j < done; ++j) {
+                HIP_TRY(c, hipEventElapsedTime(&ms, tev[0], tev[1 + j]));
+                trace->t_ms[j] = ms;
+            }
+        }
+        trace->t1_ms = nan;
+        trace->bodies = out.iter;
+    }
+    return out.exhausted ? SP_TRIALS_EXHAUSTED : SP_MAXITER;
 }
 
 // ---- stored matrices ---------------------------------------------------------------

@@ -333,6 +333,17 @@ void launch_sell_spmv(hipStream_t st, const SellShape& S, const int64_t* sp, con
 // xT = x transposed (x: rows x cols)
 void launch_transpose(hipStream_t st, int rows, int cols, const float* x, float* xT);
 
+// art.hip (ART / SupART, Section 3.4).  norms: ||R_i||^2 of every ray;
+// init: x = mu (or x0 when given), u = 0 (partials: vec_blocks(m) doubles,
+// sum_b: one double); sweep: one cycle through the rays, angle by angle and
+// phase by phase (nat_h: the HOST angle table in natural order), skipped when
+// *halt is set.
+void launch_art_norms(hipStream_t st, const GeomDev& G, const AngleDev* nat, double* nrm2);
+void launch_art_init(hipStream_t st, const GeomDev& G, const float* b, const float* x0, double* partials,
+                     double* sum_b, double* x, double* u);
+void launch_art_sweep(hipStream_t st, const GeomDev& G, const AngleDev* nat_h, const double* nrm2,
+                      const float* b, double* x, double* u, double r, double lam, const int* halt);
+
 // learned.hip (learned preconditioner C^T diag(softplus(d)) C)
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
                  const float* Wl, const float* scale, float* out2, const int* halt, const int* run);
@@ -459,6 +470,7 @@ enum ScalarOp : int {
     OP_SNORM = 5,    // ||s_k|| into the trace
     OP_LCHECK = 6,   // learned M accepted iff g^T z = sum(pa) > 0 and finite; else fall back
     OP_EPS = 7,      // Algorithm 3's loop test at the top of a body: halt if f <= eps (eps > 0)
+    OP_NEXT = 8,     // ART / SupART: the body has formed its iterate; k++, iter++
 };
 void launch_scalar(hipStream_t st, int op, Scalars* sc, TraceDev tr, const double* pa, int na,
                    const double* pb, int nb);

@@ -80,6 +80,11 @@ __device__ __forceinline__ void scalar_commit(int op, Scalars* __restrict__ sc, 
     case OP_SNORM:
         if (rec && tr.s_norm) tr.s_norm[it] = sqrt(A);
         break;
+    case OP_NEXT:
+        sc->iter = it + 1;
+        sc->k = sc->k + 1;
+        sc->inner = 0;
+        break;
     case OP_EPS:   // Algorithm 3, step 10: stop when f(x_{k-1/2}) <= eps
         if (sc->eps > 0.0 && !(sc->f > sc->eps)) sc->halt = SP_CONVERGED;
         break;

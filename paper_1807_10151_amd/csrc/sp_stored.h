@@ -28,38 +28,58 @@ __host__ __device__ inline double stored_weight(const GeomDev& G, const AngleDev
 
 __host__ __device__ inline double half_band(const AngleDev& A) { return 0.5 * (fabs(A.c) + fabs(A.s)); }
 
-// Visits the nonzeros of ray (a, k) in a fixed order: major lines (image rows
-// when |cos| >= |sin|, else columns) in increasing order, and on each the
-// minor indices of the band |s_k - t| < e in increasing order.
+// Visits the nonzeros of ray k of angle A on one major line m (image row m
+// when |cos| >= |sin|, else column m): the minor indices of the band
+// |s_k - t| < e in increasing order.
 template <class F>
-__host__ __device__ inline void ray_nonzeros(const GeomDev& G, const AngleDev& A, int k, F&& emit) {
-    const double sk = bin_pos((double)k, G);
+__host__ __device__ inline void ray_line_nonzeros(const GeomDev& G, const AngleDev& A, double sk, int m,
+                                                  F&& emit) {
     const double e = half_band(A);
     if (!(A.flags & ANG_HORIZ)) {
         const double hw = e / fabs(A.c);
-        for (int i = 0; i < G.rows; ++i) {
-            const double yi = G.yoff - (double)i;
-            const double xs = (sk - yi * A.s) / A.c + G.xoff;   // column coordinate of the crossing
-            const int lo = imax((int)floor(xs - hw) - 1, 0);
-            const int hi = imin((int)ceil(xs + hw) + 1, G.cols - 1);
-            for (int j = lo; j <= hi; ++j) {
-                const double w = stored_weight(G, A, i, j, sk);
-                if (w > 0.0) emit(i * G.cols + j, w);
-            }
+        const double yi = G.yoff - (double)m;
+        const double xs = (sk - yi * A.s) / A.c + G.xoff;   // column coordinate of the crossing
+        const int lo = imax((int)floor(xs - hw) - 1, 0);
+        const int hi = imin((int)ceil(xs + hw) + 1, G.cols - 1);
+        for (int j = lo; j <= hi; ++j) {
+            const double w = stored_weight(G, A, m, j, sk);
+            if (w > 0.0) emit(m * G.cols + j, w);
         }
     } else {
         const double hw = e / fabs(A.s);
-        for (int j = 0; j < G.cols; ++j) {
-            const double xj = (double)j - G.xoff;
-            const double ys = G.yoff - (sk - xj * A.c) / A.s;   // row coordinate of the crossing
-            const int lo = imax((int)floor(ys - hw) - 1, 0);
-            const int hi = imin((int)ceil(ys + hw) + 1, G.rows - 1);
-            for (int i = lo; i <= hi; ++i) {
-                const double w = stored_weight(G, A, i, j, sk);
-                if (w > 0.0) emit(i * G.cols + j, w);
-            }
+        const double xj = (double)m - G.xoff;
+        const double ys = G.yoff - (sk - xj * A.c) / A.s;   // row coordinate of the crossing
+        const int lo = imax((int)floor(ys - hw) - 1, 0);
+        const int hi = imin((int)ceil(ys + hw) + 1, G.rows - 1);
+        for (int i = lo; i <= hi; ++i) {
+            const double w = stored_weight(G, A, i, m, sk);
+            if (w > 0.0) emit(i * G.cols + m, w);
         }
     }
+}
+
+// Major lines of angle A: image rows when |cos| >= |sin|, else columns.
+__host__ __device__ inline int ray_lines(const GeomDev& G, const AngleDev& A) {
+    return (A.flags & ANG_HORIZ) ? G.cols : G.rows;
+}
+
+// Visits the nonzeros of ray (a, k) in a fixed order: major lines in
+// increasing order, and on each the band's minor indices in increasing order.
+template <class F>
+__host__ __device__ inline void ray_nonzeros(const GeomDev& G, const AngleDev& A, int k, F&& emit) {
+    const double sk = bin_pos((double)k, G);
+    const int nl = ray_lines(G, A);
+    for (int m = 0; m < nl; ++m) ray_line_nonzeros(G, A, sk, m, emit);
+}
+
+// ART's ray phases of angle A (Section 3.4): rays of one angle whose bin
+// indices differ by q or more touch disjoint pixels when q ds > 2 e (e =
+// half the width of a pixel's footprint on the detector), so one phase of an
+// angle is the rays k = ph, ph + q, ...; q = floor(2 e / ds + 1e-9) + 1 (the
+// 1e-9 keeps a ratio that rounds just below an integer from giving a zero
+// margin).
+__host__ __device__ inline int art_phases(const GeomDev& G, const AngleDev& A) {
+    return (int)floor(2.0 * half_band(A) / G.ds + 1e-9) + 1;
 }
 
 // Visits the nonzeros of pixel (i, j): angles in increasing order, and for
