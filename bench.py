@@ -144,8 +144,8 @@ QUALITY_WORKLOADS = {"ct512": (512, 512, 720, 725, 20, 1, 0.005),
 def quality_run(sp, torch, iters):
     """Iteration-wise and time-wise selective-error curves (eq. (4.1), the
     ellipse of Section 4.2 scaled to the image width) of SupPCG, PCG, SupCG and
-    CG, each under Table 1's parameters and under the defaults, and of ART and
-    SupART under Table 1's (40 cycles), at 512^2 x 720 x 725 and at the
+    CG, each under Table 1's parameters and under the defaults, and of ART,
+    SupART and BlobART under Table 1's (40 cycles), at 512^2 x 720 x 725 and at the
     paper's shape (243^2 x 360 x 345); graph-replayed loop bodies, HIP events
     between them."""
     from synth import noisy_data, random_ellipses, unit_noise
@@ -175,13 +175,15 @@ def quality_run(sp, torch, iters):
                     "ms_total": round(float(t[-1]), 3),
                     "curve": [[k, round(float(se[k]), 6), round(float(t[k]), 3)]
                               for k in marks if k < len(se)]}
-        # ART and SupART (Section 3.4) under Table 1's parameters
+        # ART, SupART and BlobART (Section 3.4) under Table 1's parameters
         art_iters = min(iters, 40)
         amarks = [k for k in marks if k <= art_iters]
         for method, kw in (("ART", dict(K=0, r=5.0, lam=1e-2)),
-                           ("SupART", dict(K=10, a=1 - 1e-5, gamma=1e-2, r=5.0, lam=5e-2))):
-            sp.sp_supart_solve(g, b, max_iter=1, **kw)
-            r_ = sp.sp_supart_solve(g, b, max_iter=art_iters, se_ref=x_true, timing=True, **kw)
+                           ("SupART", dict(K=10, a=1 - 1e-5, gamma=1e-2, r=5.0, lam=5e-2)),
+                           ("BlobART", dict(r=5.0, lam=1e-2))):
+            solve = sp.sp_blobart_solve if method == "BlobART" else sp.sp_supart_solve
+            solve(g, b, max_iter=1, **kw)
+            r_ = solve(g, b, max_iter=art_iters, se_ref=x_true, timing=True, **kw)
             se, t = r_.trace["se"], r_.trace["t_ms"]
             kb = int(np.nanargmin(se))
             res_w[f"{method}/table1"] = {

@@ -406,6 +406,19 @@ int sp_lp_adam_step(sp_ctx* ctx, sp_learned* net, const float* grad, double lr, 
 int sp_supart_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const float* x0,
                     const sp_tv_params* tv, double r, double lambda, const sp_solve_params* sp,
                     float* x_out, sp_trace* trace);
+/* BlobART (Section 3.4, blob basis): the same ART on the coefficients c of
+ * the image x(p) = sum_j c_j b(|p - p_j|), with generalised Kaiser-Bessel
+ * blobs b(r) = w^2 I_2(10.4 w) / I_2(10.4), w = sqrt(1 - (r/2)^2), radius 2
+ * pixels, centred on the pixel centres; the system matrix entry of ray i and
+ * blob j is the blob's line integral at the distance of centre j from ray i,
+ * 2 sqrt(2 pi / 10.4) / I_2(10.4) w^(5/2) I_(5/2)(10.4 w) (times the pixel
+ * size).  The Bayesian criterion acts on c, whose start is the uniform value
+ * whose image is the mean gray level mu; rays of an angle are taken in
+ * floor(4 / ds + 1e-9) + 1 phases (ds in pixels).  x_out and the trace's
+ * selective errors are the image sampled at the pixel centres.  Otherwise as
+ * sp_supart_solve with no S_TV. */
+int sp_blobart_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, double r, double lambda,
+                     const sp_solve_params* sp, float* x_out, sp_trace* trace);
 
 /* ---- launch shapes ------------------------------------------------------------
  * Two launch shapes of the projector pair can be chosen per geometry: the

@@ -128,6 +128,8 @@ _SIGS = {
                                 c_double, c_int32]),
     "sp_supart_solve": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p, POINTER(sp_tv_params),
                                 c_double, c_double, POINTER(sp_solve_params), c_void_p, POINTER(sp_trace)]),
+    "sp_blobart_solve": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_double, c_double,
+                                 POINTER(sp_solve_params), c_void_p, POINTER(sp_trace)]),
     "sp_tune_shapes": (c_int, [c_void_p, POINTER(sp_geometry), POINTER(c_int32), POINTER(c_int32),
                                POINTER(c_double)]),
     "sp_tuning_set": (c_int, [POINTER(sp_geometry), c_int32, c_int32]),

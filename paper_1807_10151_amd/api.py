@@ -532,15 +532,8 @@ class ARTResult:
     trace: dict = field(default_factory=dict)
 
 
-def sp_supart_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None, *, K: int = 0,
-                    a: float = 1 - 1e-5, gamma: float = 1e-2, max_trials: int = 100, r: float = 5.0,
-                    lam: float = 0.05, max_iter: int = 10, graph: bool = True, se_ref: torch.Tensor | None = None,
-                    se_axes=None, se_c: float = 0.0, timing: bool = False, x_out: torch.Tensor | None = None,
-                    ctx: Context | None = None) -> ARTResult:
-    """ART for the Bayesian criterion (K = 0) or SupART (K > 0), max_iter cycles
-    through the rays (sp_supart_solve).  The trace holds ell, tv_half and
-    trials (SupART), "se" = [SE(x_0), SE(x_1), ...] with se_ref, and
-    "t_ms" = [0, t(x_1), ...] with timing."""
+def _art_call(g, b, x0, K, a, gamma, max_trials, r, lam, max_iter, graph, se_ref, se_axes, se_c, timing, x_out,
+              ctx, blob):
     ctx = ctx or context(b.device.index or 0)
     dev = ctx.device
     x_out = _out(x_out, (g.rows, g.cols), dev)
@@ -566,9 +559,13 @@ def sp_supart_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
         arrs["t_ms"] = np.zeros(cap)
         tr.t_ms = dp(arrs["t_ms"])
     ctx._stream()
-    rc = ctx.lib.sp_supart_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
-                                 _dev(x0, g.n, "x0", dev) if x0 is not None else None, ctypes.byref(tvp),
-                                 r, lam, ctypes.byref(sp), _dev(x_out, g.n, "x_out", dev), ctypes.byref(tr))
+    if blob:
+        rc = ctx.lib.sp_blobart_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev), r, lam, ctypes.byref(sp),
+                                      _dev(x_out, g.n, "x_out", dev), ctypes.byref(tr))
+    else:
+        rc = ctx.lib.sp_supart_solve(ctx.h, ctypes.byref(gc), _dev(b, g.m, "b", dev),
+                                     _dev(x0, g.n, "x0", dev) if x0 is not None else None, ctypes.byref(tvp),
+                                     r, lam, ctypes.byref(sp), _dev(x_out, g.n, "x_out", dev), ctypes.byref(tr))
     ctx._check(rc, ok=(L.SP_MAXITER, L.SP_TRIALS_EXHAUSTED))
     done = min(tr.bodies, cap)
     out = {}
@@ -581,6 +578,29 @@ def sp_supart_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None
     if timing:
         out["t_ms"] = np.concatenate([[0.0], arrs["t_ms"][:done]])
     return ARTResult(x_out, rc, out)
+
+
+def sp_supart_solve(g: Geometry, b: torch.Tensor, x0: torch.Tensor | None = None, *, K: int = 0,
+                    a: float = 1 - 1e-5, gamma: float = 1e-2, max_trials: int = 100, r: float = 5.0,
+                    lam: float = 0.05, max_iter: int = 10, graph: bool = True, se_ref: torch.Tensor | None = None,
+                    se_axes=None, se_c: float = 0.0, timing: bool = False, x_out: torch.Tensor | None = None,
+                    ctx: Context | None = None) -> ARTResult:
+    """ART for the Bayesian criterion (K = 0) or SupART (K > 0), max_iter cycles
+    through the rays (sp_supart_solve).  The trace holds ell, tv_half and
+    trials (SupART), "se" = [SE(x_0), SE(x_1), ...] with se_ref, and
+    "t_ms" = [0, t(x_1), ...] with timing."""
+    return _art_call(g, b, x0, K, a, gamma, max_trials, r, lam, max_iter, graph, se_ref, se_axes, se_c, timing,
+                     x_out, ctx, False)
+
+
+def sp_blobart_solve(g: Geometry, b: torch.Tensor, *, r: float = 5.0, lam: float = 1e-2, max_iter: int = 10,
+                     graph: bool = True, se_ref: torch.Tensor | None = None, se_axes=None, se_c: float = 0.0,
+                     timing: bool = False, x_out: torch.Tensor | None = None,
+                     ctx: Context | None = None) -> ARTResult:
+    """BlobART (sp_blobart_solve): ART on Kaiser-Bessel blob coefficients; x is
+    the blob image at the pixel centres; trace as for sp_supart_solve."""
+    return _art_call(g, b, None, 0, 0.5, 0.0, 100, r, lam, max_iter, graph, se_ref, se_axes, se_c, timing, x_out,
+                     ctx, True)
 
 
 # The paper's ellipse for the selective error: semi-axes 5 cm (horizontal) and

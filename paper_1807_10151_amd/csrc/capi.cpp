@@ -1894,9 +1894,11 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
 
 // ---- ART and SupART (Section 3.4) ---------------------------------------------------
 
-int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0,
-                    const sp_tv_params* tv, double r, double lam, const sp_solve_params* sp, float* x_out,
-                    sp_trace* trace) {
+namespace {
+// ART (pixel basis, with S_TV when tv->K > 0) or BlobART (blob basis): the
+// iterate is the pixel image or the blob coefficients, float64 on the device.
+int art_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0, const sp_tv_params* tv,
+              double r, double lam, const sp_solve_params* sp, float* x_out, sp_trace* trace, bool blob) {
     if (!c) return SP_ERR_ARG;
     if (!b || !x_out || !sp) return fail(c, SP_ERR_ARG, "b, x_out and the solve parameters are required");
     if (!(r > 0.0) || !std::isfinite(r)) return fail(c, SP_ERR_ARG, "r must be positive and finite");
@@ -1916,7 +1918,7 @@ int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         HIP_TRY(c, hipEventRecord(c->own_ev[0], nullptr));
         HIP_TRY(c, hipStreamWaitEvent(c->own, c->own_ev[0], 0));
         c->stream = c->own;
-        const int r2 = sp_supart_solve(c, g, b, x0, tv, r, lam, sp, x_out, trace);
+        const int r2 = art_solve(c, g, b, x0, tv, r, lam, sp, x_out, trace, blob);
         c->stream = nullptr;
         (void)hipStreamSynchronize(c->own);
         return r2;
@@ -1997,10 +1999,21 @@ int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         for (hipEvent_t& e : tev) HIP_TRY(c, hipEventCreate(&e));
         HIP_TRY(c, hipEventRecord(tev[0], st));
     }
-    launch_art_norms(st, G, dptr<AngleDev>(natd), nrm);
-    launch_art_init(st, G, b, x0, dptr<double>(c->ox), dptr<double>(c->art_sum), x, u);
+    const BlobDev B = blob_constants();
+    const BlobDev* bp = blob ? &B : nullptr;
+    double divisor = 1.0;
+    if (blob) {
+        divisor = 0.0;
+        for (int di = 0; di < 5; ++di)
+            for (int dj = 0; dj < 5; ++dj) divisor += B.stencil[di][dj];
+    }
+    // the image the trace and x_out see: x itself, or the blob image in xh
+    double* img = blob ? xh : x;
+    launch_art_norms(st, G, dptr<AngleDev>(natd), bp, nrm);
+    launch_art_init(st, G, b, x0, divisor, dptr<double>(c->ox), dptr<double>(c->art_sum), x, u);
+    if (blob) launch_blob_synth(st, G.rows, G.cols, B, x, img, nullptr);
     if (want_se)
-        launch_se(st, G.rows, G.cols, g->pixel, trace->se_axes[0], trace->se_axes[1], x, trace->se_ref,
+        launch_se(st, G.rows, G.cols, g->pixel, trace->se_axes[0], trace->se_axes[1], img, trace->se_ref,
                   trace->se_c, dptr<double>(c->part_se), se_body + cap, nullptr, 0, nullptr, nullptr);
     if ((rc = check_launch(c))) return rc;
     // one iteration: S_TV (SupART), then a cycle through the rays
@@ -2010,11 +2023,12 @@ int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
             enqueue_stv(c, sc, K, x, xh, false, tr, nullptr);
             tgt = xh;
         }
-        launch_art_sweep(st, G, nat.data(), nrm, b, tgt, u, r, lam, halt);
+        launch_art_sweep(st, G, nat.data(), bp, nrm, b, tgt, u, r, lam, halt);
         if (K > 0) launch_copy(st, n, xh, x, halt);
+        if (blob) launch_blob_synth(st, G.rows, G.cols, B, x, img, halt);
         launch_scalar(st, OP_NEXT, sc, tr, nullptr, 0, nullptr, 0);
         if (want_se)
-            launch_se(st, G.rows, G.cols, g->pixel, trace->se_axes[0], trace->se_axes[1], x, trace->se_ref,
+            launch_se(st, G.rows, G.cols, g->pixel, trace->se_axes[0], trace->se_axes[1], img, trace->se_ref,
                       trace->se_c, dptr<double>(c->part_se), nullptr, se_body, cap, sc, halt);
         return check_launch(c);
     };
@@ -2050,7 +2064,7 @@ int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
             if (!tev.empty()) HIP_TRY(c, hipEventRecord(tev[1 + it], st));
         }
     }
-    launch_narrow(st, n, x, x_out);
+    launch_narrow(st, n, img, x_out);
     Scalars out{};
     HIP_TRY(c, hipMemcpyAsync(&out, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
@@ -2081,6 +2095,18 @@ int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         trace->bodies = out.iter;
     }
     return out.exhausted ? SP_TRIALS_EXHAUSTED : SP_MAXITER;
+}
+}  // namespace
+
+int sp_supart_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0,
+                    const sp_tv_params* tv, double r, double lam, const sp_solve_params* sp, float* x_out,
+                    sp_trace* trace) {
+    return art_solve(c, g, b, x0, tv, r, lam, sp, x_out, trace, false);
+}
+
+int sp_blobart_solve(sp_ctx* c, const sp_geometry* g, const float* b, double r, double lam,
+                     const sp_solve_params* sp, float* x_out, sp_trace* trace) {
+    return art_solve(c, g, b, nullptr, nullptr, r, lam, sp, x_out, trace, true);
 }
 
 // ---- stored matrices ---------------------------------------------------------------

@@ -333,16 +333,30 @@ void launch_sell_spmv(hipStream_t st, const SellShape& S, const int64_t* sp, con
 // xT = x transposed (x: rows x cols)
 void launch_transpose(hipStream_t st, int rows, int cols, const float* x, float* xT);
 
-// art.hip (ART / SupART, Section 3.4).  norms: ||R_i||^2 of every ray;
-// init: x = mu (or x0 when given), u = 0 (partials: vec_blocks(m) doubles,
-// sum_b: one double); sweep: one cycle through the rays, angle by angle and
-// phase by phase (nat_h: the HOST angle table in natural order), skipped when
-// *halt is set.
-void launch_art_norms(hipStream_t st, const GeomDev& G, const AngleDev* nat, double* nrm2);
-void launch_art_init(hipStream_t st, const GeomDev& G, const float* b, const float* x0, double* partials,
-                     double* sum_b, double* x, double* u);
-void launch_art_sweep(hipStream_t st, const GeomDev& G, const AngleDev* nat_h, const double* nrm2,
-                      const float* b, double* x, double* u, double r, double lam, const int* halt);
+// art.hip (ART / SupART / BlobART, Section 3.4).  Blob basis: generalised
+// Kaiser-Bessel blobs (order 2, alpha 10.4, radius 2 pixels) on the pixel
+// centres; cproj = a sqrt(2 pi / alpha) / I_2(alpha) scales the projection;
+// stencil[di + 2][dj + 2] = b(|(di, dj)|), the image of a unit coefficient.
+constexpr double BLOB_RADIUS = 2.0;
+constexpr double BLOB_ALPHA = 10.4;
+struct BlobDev {
+    double a, alpha, cproj;
+    double stencil[5][5];
+};
+BlobDev blob_constants();
+// norms: ||R_i||^2 of every ray (blob nullable: pixel basis); init: x = mu /
+// divisor (or x0 when given), u = 0 (partials: vec_blocks(m) doubles, sum_b:
+// one double); sweep: one cycle through the rays, angle by angle and phase
+// by phase (nat_h: the HOST angle table in natural order), skipped when
+// *halt is set; synth: img = the blob image of the coefficients c.
+void launch_art_norms(hipStream_t st, const GeomDev& G, const AngleDev* nat, const BlobDev* blob, double* nrm2);
+void launch_art_init(hipStream_t st, const GeomDev& G, const float* b, const float* x0, double divisor,
+                     double* partials, double* sum_b, double* x, double* u);
+void launch_art_sweep(hipStream_t st, const GeomDev& G, const AngleDev* nat_h, const BlobDev* blob,
+                      const double* nrm2, const float* b, double* x, double* u, double r, double lam,
+                      const int* halt);
+void launch_blob_synth(hipStream_t st, int rows, int cols, const BlobDev& B, const double* c, double* img,
+                       const int* halt);
 
 // learned.hip (learned preconditioner C^T diag(softplus(d)) C)
 void lp_conv_mid(hipStream_t st, bool trans, int B, int H, int W, const float* in, float* out,
