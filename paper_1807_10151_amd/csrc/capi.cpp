@@ -1561,6 +1561,12 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         if (S.kind != pc->kind || (pc->kind != SP_PRECOND_NONE && (S.mu != pc->mu || S.rho != pc->rho)))
             return fail(c, SP_ERR_ARG, "SP_FLAG_RESUME: preconditioner differs from the saved state");
     }
+    if (trace && trace->se_ref) {
+        for (double a : trace->se_axes)
+            if (!(a > 0.0) || !std::isfinite(a))
+                return fail(c, SP_ERR_ARG, "se_axes must be positive and finite");
+        if (!std::isfinite(trace->se_c)) return fail(c, SP_ERR_ARG, "se_c must be finite");
+    }
     c->st.ok = false;   // the buffers below are rewritten from here on
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
@@ -1577,12 +1583,6 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     const size_t se_off = (tr_main + 63) & ~(size_t)63;
     const size_t tr_bytes = se_off + (size_t)(cap + 2) * 8;
     const bool want_se = trace && trace->se_ref;
-    if (want_se) {
-        for (double a : trace->se_axes)
-            if (!(a > 0.0) || !std::isfinite(a))
-                return fail(c, SP_ERR_ARG, "se_axes must be positive and finite");
-        if (!std::isfinite(trace->se_c)) return fail(c, SP_ERR_ARG, "se_c must be finite");
-    }
     if ((rc = ensure(c, c->trace_d, tr_bytes))) return rc;
     HIP_TRY(c, hipMemsetAsync(c->trace_d.ptr, 0, se_off, c->stream));
     // selective errors start as NaN (0x7FF80000 in both halves is a NaN)
@@ -1930,6 +1930,11 @@ int art_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0, 
     const int K = (tv && tv->K > 0) ? tv->K : 0;
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols, m = G.nA * G.nB;
+    if (trace && trace->se_ref) {
+        for (double a : trace->se_axes)
+            if (!(a > 0.0) || !std::isfinite(a)) return fail(c, SP_ERR_ARG, "se_axes must be positive and finite");
+        if (!std::isfinite(trace->se_c)) return fail(c, SP_ERR_ARG, "se_c must be finite");
+    }
     c->st.ok = false;   // the solver vectors are reused below
     if ((rc = ensure_vectors(c, n)) || (rc = ensure_partials(c))) return rc;
     if ((rc = ensure(c, c->art_u, (size_t)m * 8)) || (rc = ensure(c, c->art_nrm, (size_t)m * 8)) ||
@@ -1950,11 +1955,6 @@ int art_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0, 
     const size_t se_off = (tr_main + 63) & ~(size_t)63;
     const size_t tr_bytes = se_off + (size_t)(cap + 2) * 8;
     const bool want_se = trace && trace->se_ref;
-    if (want_se) {
-        for (double a : trace->se_axes)
-            if (!(a > 0.0) || !std::isfinite(a)) return fail(c, SP_ERR_ARG, "se_axes must be positive and finite");
-        if (!std::isfinite(trace->se_c)) return fail(c, SP_ERR_ARG, "se_c must be finite");
-    }
     if ((rc = ensure(c, c->trace_d, tr_bytes))) return rc;
     HIP_TRY(c, hipMemsetAsync(c->trace_d.ptr, 0, se_off, st));
     HIP_TRY(c, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(dptr<char>(c->trace_d) + se_off), 0x7FF80000,

@@ -155,3 +155,16 @@ def test_async_batched(sp, prob):
     assert k.cpu().tolist() == [10, 10]
     for i in range(2):
         assert torch.equal(xh[i], ref[i].x_half)
+
+
+def test_rejected_call_keeps_the_state(sp, prob):
+    # a solve rejected for its trace options (ellipse semi-axes) must leave the
+    # carried state resumable
+    g, b = prob
+    straight = sp.sp_suppcg_solve(g, b, None, max_iter=8, **KW)
+    sp.sp_suppcg_solve(g, b, None, max_iter=4, **KW)
+    ref = torch.ones((g.rows, g.cols), device="cuda")
+    with pytest.raises(sp.SupPCGError):
+        sp.sp_suppcg_solve(g, b, None, max_iter=4, resume=True, se_ref=ref, se_axes=(0.0, 3.0), **KW)
+    rest = sp.sp_suppcg_solve(g, b, None, max_iter=4, resume=True, **KW)
+    assert torch.equal(rest.x_half, straight.x_half)
