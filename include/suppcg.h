@@ -187,8 +187,10 @@ int sp_ctx_create(int device, void* hip_stream, sp_ctx** out);
 int sp_ctx_destroy(sp_ctx* ctx);
 /* Changes the stream later calls enqueue on. */
 int sp_ctx_set_stream(sp_ctx* ctx, void* hip_stream);
-/* Host string describing the last failure on ctx; valid until the next call. */
+/* Host string describing the last failure on ctx; valid until the next call.
+ * sp_ctx_last_error is the same call under the context's prefix. */
 const char* sp_last_error(const sp_ctx* ctx);
+const char* sp_ctx_last_error(const sp_ctx* ctx);
 /* Library version string (host, static). */
 const char* sp_version(void);
 
@@ -361,6 +363,9 @@ int64_t sp_lp_num_params(const sp_learned* net);
 /* Copies count = num_params float32 values from / to HOST memory. */
 int sp_lp_set_params(sp_ctx* ctx, sp_learned* net, const float* theta, int64_t count);
 int sp_lp_get_params(sp_ctx* ctx, const sp_learned* net, float* theta, int64_t count);
+/* The same two calls under the names of the network's weights. */
+int sp_lp_set_weights(sp_ctx* ctx, sp_learned* net, const float* w, int64_t count);
+int sp_lp_get_weights(sp_ctx* ctx, const sp_learned* net, float* w, int64_t count);
 /* z = M u for `batch` images u, z: [batch][rows][cols] float32 (device). */
 int sp_lp_apply(sp_ctx* ctx, sp_learned* net, int32_t batch, int32_t rows, int32_t cols,
                 const float* u, float* z);

@@ -93,6 +93,7 @@ _SIGS = {
     "sp_ctx_destroy": (c_int, [c_void_p]),
     "sp_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
     "sp_last_error": (c_char_p, [c_void_p]),
+    "sp_ctx_last_error": (c_char_p, [c_void_p]),
     "sp_project": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
     "sp_backproject": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
     "sp_backproject_noalloc": (c_int, [c_void_p, POINTER(sp_geometry), c_void_p, c_void_p]),
@@ -121,6 +122,8 @@ _SIGS = {
     "sp_lp_num_params": (ctypes.c_int64, [c_void_p]),
     "sp_lp_set_params": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]),
     "sp_lp_get_params": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]),
+    "sp_lp_set_weights": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]),
+    "sp_lp_get_weights": (c_int, [c_void_p, c_void_p, POINTER(ctypes.c_float), ctypes.c_int64]),
     "sp_lp_apply": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "sp_lp_loss_grad": (c_int, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32,
                                 c_void_p, c_int32, c_int32, c_void_p, c_void_p]),

@@ -1004,6 +1004,7 @@ int sp_ctx_set_stream(sp_ctx* c, void* hip_stream) {
 }
 
 const char* sp_last_error(const sp_ctx* c) { return c ? c->err : "null context"; }
+const char* sp_ctx_last_error(const sp_ctx* c) { return sp_last_error(c); }
 
 int sp_profile_enable(sp_ctx* c, int on) {
     if (!c) return SP_ERR_ARG;
@@ -1073,6 +1074,14 @@ int sp_lp_get_params(sp_ctx* c, const sp_learned* net, float* theta, int64_t cou
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SP_OK;
+}
+
+int sp_lp_set_weights(sp_ctx* c, sp_learned* net, const float* w, int64_t count) {
+    return sp_lp_set_params(c, net, w, count);
+}
+
+int sp_lp_get_weights(sp_ctx* c, const sp_learned* net, float* w, int64_t count) {
+    return sp_lp_get_params(c, net, w, count);
 }
 
 int sp_lp_apply(sp_ctx* c, sp_learned* net, int32_t batch, int32_t rows, int32_t cols,
