@@ -17,9 +17,11 @@ with u as the auxiliary vector carried by the basic algorithm).  Readings:
 
 R1  rays are visited angle by angle in increasing angle index, and within an
     angle in q phases: rays k = ph, ph + q, ph + 2q, ... for ph = 0 .. q-1,
-    with q = floor(2 e / ds) + 1 (e = half-width of a pixel's footprint on the
-    detector for that angle, ds = bin spacing), so rays of one phase touch
-    disjoint pixels (the paper fixes no order);
+    with q = floor(2 e / ds + 1e-9) + 1 (e = half-width of a pixel's footprint
+    on the detector for that angle, ds = bin spacing), so rays of one phase touch
+    disjoint pixels (the paper fixes no order); the ratio 2e/ds gets 1e-9
+    added before the floor so that one that rounds to just below an integer
+    keeps a margin;
 R2  mu is the uniform image whose value is the mean gray level estimated
     from the data: for parallel beams each angle's data sums to the image
     integral divided by ds, so mu = ds * sum(b) / (A * n * pixel^2);
@@ -41,7 +43,7 @@ def phases(g: Geometry, a: int) -> int:
     """q of reading R1 for angle a."""
     _, c, s = angle_cos_sin(g, a)
     e = g.pixel * (abs(c) + abs(s)) / 2.0
-    return int(math.floor(2.0 * e / g.bin_spacing)) + 1
+    return int(math.floor(2.0 * e / g.bin_spacing + 1e-9)) + 1
 
 
 def ray_order(g: Geometry):
