@@ -53,6 +53,14 @@ OPS_PER_NNZ = 4
 COUNTERS = {"measured_at": "kernels of 1de3a50, profiled at 542fbec",
             "valu_instr": {"project": 2.907e7, "backproject": 3.577e7},
             "traffic_bytes": {"project": 40.27e6, "backproject": 20.88e6}}
+# The vector L1's access rate, the limit the gathers of both kernels run into
+# (profiles/memory_pipe_ct512.md, same kernels, re-taken at 462a28c):
+# TCP_TOTAL_CACHE_ACCESSES per launch and per compute unit and cycle of the
+# kernel's own run (about one access per CU and cycle is the L1's rate; R^T:
+# the mean of its two sinogram forms, as above).
+L1_ACCESS = {"measured_at": "kernels of 1de3a50, profiled at 462a28c",
+             "per_launch": {"project": 6.095e7, "backproject": 5.368e7},
+             "per_cu_per_cycle": {"project": 1.03, "backproject": 0.84}}
 
 
 def log(msg):
@@ -596,7 +604,9 @@ def main():
                          "achieved": round(ach / 1e12, 4), "frac": round(ach / PEAK_VALU_OPS, 4),
                          "valu_issue": {"instr_per_launch": instr,
                                         "frac": round(instr * 64 / (ms / 1e3) / PEAK_VALU_OPS, 4)},
-                         "traffic": COUNTERS["traffic_bytes"][name]}
+                         "traffic": COUNTERS["traffic_bytes"][name],
+                         "l1_accesses": {"per_launch": L1_ACCESS["per_launch"][name],
+                                         "per_cu_per_cycle": L1_ACCESS["per_cu_per_cycle"][name]}}
     dom_name = max(kernels, key=lambda k: kernels[k]["ms"])
     dom = kernels[dom_name]
     out = {
@@ -622,7 +632,8 @@ def main():
                      "unit": "T lane-ops/s (VALU; 4 per nonzero weight of R)",
                      "frac": dom["frac"], "traffic": dom["traffic"],
                      "kernels": kernels, "nnz": NNZ_CT512,
-                     "counters_measured_at": COUNTERS["measured_at"]},
+                     "counters_measured_at": COUNTERS["measured_at"],
+                     "l1_accesses_measured_at": L1_ACCESS["measured_at"]},
         "in_solve_ms": {k: round(v, 4) for k, v in avg.items()},
         "operators_ms": {"project": round(ms_R, 4), "backproject": round(ms_RT, 4),
                          "precond": round(ms_M, 4)},
