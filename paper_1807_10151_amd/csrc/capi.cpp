@@ -2271,6 +2271,7 @@ int sp_matrix_backproject(sp_ctx* c, const sp_matrix* M, const float* y, float* 
 int sp_matrix_export(sp_ctx* c, const sp_matrix* M, int side, int64_t* row_ptr, int32_t* col, float* val) {
     if (!c) return SP_ERR_ARG;
     if (!M || (side != 0 && side != 1)) return fail(c, SP_ERR_ARG, "matrix and side 0 or 1 are required");
+    if (M->device != c->device) return fail(c, SP_ERR_ARG, "the matrix lives on another device");
     HIP_TRY(c, hipSetDevice(c->device));
     sp_matrix* W = const_cast<sp_matrix*>(M);
     hipStream_t st = c->stream;
