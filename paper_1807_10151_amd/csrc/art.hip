@@ -201,7 +201,6 @@ __global__ __launch_bounds__(256) void k_art_phase(GeomDev G, AngleDev A, BlobDe
     const double n2 = nrm2[i];
     const double bi = (double)b[i];
     const double ui = u[i];
-    if (n2 == 0.0) return;
     __shared__ double red[4];
     const double sk = bin_pos((double)k, G);
     const int nl = ray_lines(G, A);
@@ -224,6 +223,9 @@ __global__ __launch_bounds__(256) void k_art_phase(GeomDev G, AngleDev A, BlobDe
             }
         });
     dot = block_sum(dot, red);
+    // a ray without nonzeros (n2 = 0) gathered nothing and changes nothing; the
+    // test sits after the walk so its load overlaps the gathers
+    if (n2 == 0.0) return;
     const double c = lam * (r * (bi - dot) - ui) / (1.0 + r * r * n2);
     if (threadIdx.x == 0) u[i] = ui + c;
     const double rc = r * c;
