@@ -179,16 +179,17 @@ __global__ __launch_bounds__(256) void k_sum_f(int m, const float* __restrict__ 
 }
 
 // One phase of angle A (row a of the sinogram): workgroup j projects ray
-// k = ph + q j.  Its 256 threads take the ray's major lines m = t, t + 256,
+// k = ph + q j.  Its NT threads take the ray's major lines m = t, t + NT,
 // ... for <R_i, x> (summed over the workgroup in a fixed order) and then
-// update those pixels.  With at most two lines per thread (LINES = 2: images
-// of up to 512 rows and columns) a thread keeps its pixels, weights and the
-// values it read in registers (up to 6 per line; a band |s_k - t| < e meets
-// at most 3 pixels of a line; 10 blobs, of at most 6 met) and writes
-// x + r c w without a second walk;
-// otherwise (LINES = 0, or more entries than that) it walks its lines again.
-template <bool BLOB, int LINES>
-__global__ __launch_bounds__(256) void k_art_phase(GeomDev G, AngleDev A, BlobDev B, int a, int ph, int q, int nr,
+// update those pixels.  With at most LINES lines per thread a thread keeps
+// its pixels, weights and the values it read in registers (up to 6 per line;
+// a band |s_k - t| < e meets at most 3 pixels of a line; 10 blobs, of at most
+// 6 met) and writes x + r c w without a second walk; otherwise (LINES = 0, or
+// more entries than that) it walks its lines again.  A phase holds few rays
+// (nB / q workgroups), so 512 threads per ray halve each thread's chain of
+// dependent weight evaluations and gathers.
+template <bool BLOB, int LINES, int NT>
+__global__ __launch_bounds__(NT) void k_art_phase(GeomDev G, AngleDev A, BlobDev B, int a, int ph, int q, int nr,
                                                    const double* __restrict__ nrm2,
                                                    const float* __restrict__ b, double* __restrict__ x,
                                                    double* __restrict__ u, double r, double lam,
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_art_phase(GeomDev G, AngleDev A, BlobDe
     const double n2 = nrm2[i];
     const double bi = (double)b[i];
     const double ui = u[i];
-    __shared__ double red[4];
+    __shared__ double red[NT / 64];
     const double sk = bin_pos((double)k, G);
     const int nl = ray_lines(G, A);
     double dot = 0.0;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_art_phase(GeomDev G, AngleDev A, BlobDe
     int pp[CAP > 0 ? CAP : 1];
     double ww[CAP > 0 ? CAP : 1], xv[CAP > 0 ? CAP : 1];
     int cnt = 0;
-    for (int m = threadIdx.x; m < nl; m += 256)
+    for (int m = threadIdx.x; m < nl; m += NT)
         basis_line_nonzeros<BLOB>(G, A, B, sk, m, [&](int p, double w) {
             const double v = x[p];
             dot = fma(w, v, dot);
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(256) void k_art_phase(GeomDev G, AngleDev A, BlobDe
                 ++cnt;
             }
         });
-    dot = block_sum(dot, red);
+    dot = block_sum_w<NT / 64>(dot, red);
     // a ray without nonzeros (n2 = 0) gathered nothing and changes nothing; the
     // test sits after the walk so its load overlaps the gathers
     if (n2 == 0.0) return;
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void k_art_phase(GeomDev G, AngleDev A, BlobDe
         for (int e = 0; e < CAP; ++e)
             if (e < cnt) x[pp[e]] = fma(rc, ww[e], xv[e]);
     } else {   // (a line with more nonzeros than the registers hold: walk again)
-        for (int m = threadIdx.x; m < nl; m += 256)
+        for (int m = threadIdx.x; m < nl; m += NT)
             basis_line_nonzeros<BLOB>(G, A, B, sk, m, [&](int p, double w) { x[p] = fma(rc, w, x[p]); });
     }
 }
@@ -269,22 +270,23 @@ void launch_art_sweep(hipStream_t st, const GeomDev& G, const AngleDev* nat_h, c
     for (int a = 0; a < G.nA; ++a) {
         const AngleDev& A = nat_h[a];
         const int q = blob ? art_blob_phases(G, B) : art_phases(G, A);
-        const bool regs = ray_lines(G, A) <= 512;
+        constexpr int NT = 512;
+        const bool regs = ray_lines(G, A) <= NT;
         for (int ph = 0; ph < q && ph < G.nB; ++ph) {
             const int nr = (G.nB - ph + q - 1) / q;
-            const dim3 grid(nr), blk(256);
+            const dim3 grid(nr), blk(NT);
             if (blob && regs)
-                hipLaunchKernelGGL((k_art_phase<true, 2>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b, x, u,
-                                   r, lam, halt);
+                hipLaunchKernelGGL((k_art_phase<true, 1, NT>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b, x,
+                                   u, r, lam, halt);
             else if (blob)
-                hipLaunchKernelGGL((k_art_phase<true, 0>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b, x, u,
-                                   r, lam, halt);
+                hipLaunchKernelGGL((k_art_phase<true, 0, NT>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b, x,
+                                   u, r, lam, halt);
             else if (regs)
-                hipLaunchKernelGGL((k_art_phase<false, 2>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b, x,
-                                   u, r, lam, halt);
+                hipLaunchKernelGGL((k_art_phase<false, 1, NT>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b,
+                                   x, u, r, lam, halt);
             else
-                hipLaunchKernelGGL((k_art_phase<false, 0>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b, x,
-                                   u, r, lam, halt);
+                hipLaunchKernelGGL((k_art_phase<false, 0, NT>), grid, blk, 0, st, G, A, B, a, ph, q, nr, nrm2, b,
+                                   x, u, r, lam, halt);
         }
     }
 }

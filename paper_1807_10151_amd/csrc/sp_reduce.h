@@ -1,4 +1,5 @@
-// Deterministic float64 reductions for 256-thread workgroups (4 wave64s).
+// Deterministic float64 reductions for 256-thread workgroups (4 wave64s), and
+// block_sum_w for workgroups of other sizes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,6 +23,23 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
     if (lane == 0) lds[w] = v;
     __syncthreads();
     return ((lds[0] + lds[1]) + lds[2]) + lds[3];
+}
+
+// Sum over a workgroup of NW waves (64 NW threads); the result is valid in
+// every thread.  `lds` must hold NW doubles.  Fixed order: lanes by
+// xor-butterfly, then waves 0..NW-1 in order.
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double* lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double s = lds[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) s += lds[i];
+    return s;
 }
 
 // N independent block sums with one pair of barriers: v[i] becomes exactly
