@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "sp_blob.h"
 #include "sp_internal.h"
 #include "sp_reduce.h"
 #include "sp_stored.h"
@@ -23,23 +24,13 @@
 namespace sp {
 
 // ---- blob basis -----------------------------------------------------------------
-// Modified Bessel function I_nu by its power series (host; the blob's
-// constants).
-static double bessel_i_series(double nu, double z) {
-    double term = std::pow(0.5 * z, nu) / std::tgamma(nu + 1.0), sum = term;
-    for (int k = 1; k < 200; ++k) {
-        term *= (0.25 * z * z) / ((double)k * (k + nu));
-        sum += term;
-        if (term < 1e-18 * sum) break;
-    }
-    return sum;
-}
-
 BlobDev blob_constants() {
     BlobDev B{};
     B.a = BLOB_RADIUS;
     B.alpha = BLOB_ALPHA;
-    const double i2a = bessel_i_series(2.0, B.alpha);
+    B.ntab = BLOB_TAB_N;
+    B.inv_h = BLOB_TAB_N / B.a;
+    const double i2a = blob_bessel_i(2.0, B.alpha);
     B.cproj = B.a * std::sqrt(2.0 * M_PI / B.alpha) / i2a;
     for (int di = -2; di <= 2; ++di)
         for (int dj = -2; dj <= 2; ++dj) {
@@ -48,7 +39,7 @@ BlobDev blob_constants() {
             double v = 0.0;
             if (t > 0.0) {
                 const double w = std::sqrt(t);
-                v = w * w * bessel_i_series(2.0, B.alpha * w) / i2a;
+                v = w * w * blob_bessel_i(2.0, B.alpha * w) / i2a;
             }
             B.stencil[di + 2][dj + 2] = v;
         }
@@ -56,28 +47,9 @@ BlobDev blob_constants() {
 }
 
 // p(d): the integral of the blob along a line at distance d (pixel units),
-// a sqrt(2 pi / alpha) / I_2(alpha) * w^(5/2) I_(5/2)(alpha w) with
-// w = sqrt(1 - (d/a)^2).  I_(5/2)(z) = sqrt(2 / (pi z)) ((1 + 3/z^2) sinh z -
-// (3/z) cosh z) for z >= 2; below, where that difference cancels, its series.
+// from its table (sp_blob.h).
 __device__ __forceinline__ double blob_proj(const BlobDev& B, double d) {
-    const double q = d / B.a;
-    const double t = 1.0 - q * q;
-    if (!(t > 0.0)) return 0.0;
-    const double w = sqrt(t), z = B.alpha * w;
-    double i52;
-    if (z < 2.0) {
-        const double h = 0.5 * z, h2 = h * h;
-        // (z/2)^(5/2) / Gamma(7/2), Gamma(7/2) = 15 sqrt(pi) / 8
-        double term = h * h * sqrt(h) * (8.0 / (15.0 * 1.7724538509055160273)), sum = term;
-        for (int k = 1; k < 14; ++k) {
-            term *= h2 / ((double)k * (k + 2.5));
-            sum += term;
-        }
-        i52 = sum;
-    } else {
-        i52 = sqrt(2.0 / (3.14159265358979323846 * z)) * ((1.0 + 3.0 / (z * z)) * sinh(z) - (3.0 / z) * cosh(z));
-    }
-    return B.cproj * (w * w * sqrt(w)) * i52;
+    return blob_interp(B.tab, B.ntab, B.inv_h, d);
 }
 
 // The blobs met by ray k of angle A on major line m (their centres on that

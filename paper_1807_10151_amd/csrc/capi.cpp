@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/suppcg.h"
+#include "sp_blob.h"
 #include "sp_internal.h"
 #include "sp_stored.h"
 
@@ -57,7 +58,7 @@ struct sp_ctx {
     sp_geometry geom{};
     GeomDev G{};
     std::vector<AngleDev> ang_h;
-    DevBuf ang, pwave, xp, xTp, yp, ypd, seg, pord;
+    DevBuf ang, pwave, xp, xTp, yp, ypd, seg, pord, blob_tab;
 
     // preconditioner cache
     int fftP = 0;
@@ -977,7 +978,7 @@ int sp_ctx_destroy(sp_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     (void)drain_pending(c);
-    for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
+    for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->blob_tab, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
                       &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
                       &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->stored_xT, &c->art_u, &c->art_nrm, &c->art_sum, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
@@ -2008,7 +2009,16 @@ int art_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float* x0, 
         for (hipEvent_t& e : tev) HIP_TRY(c, hipEventCreate(&e));
         HIP_TRY(c, hipEventRecord(tev[0], st));
     }
-    const BlobDev B = blob_constants();
+    BlobDev B = blob_constants();
+    if (blob) {
+        std::vector<double2> tab((size_t)B.ntab + 1);
+        blob_table_fill(B.a, B.alpha, B.cproj, B.ntab, tab.data());
+        if ((rc = ensure(c, c->blob_tab, tab.size() * sizeof(double2)))) return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->blob_tab.ptr, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice,
+                                  st));
+        HIP_TRY(c, hipStreamSynchronize(st));   // the host table must outlive the copy
+        B.tab = dptr<double2>(c->blob_tab);
+    }
     const BlobDev* bp = blob ? &B : nullptr;
     double divisor = 1.0;
     if (blob) {

@@ -336,12 +336,17 @@ void launch_transpose(hipStream_t st, int rows, int cols, const float* x, float*
 // art.hip (ART / SupART / BlobART, Section 3.4).  Blob basis: generalised
 // Kaiser-Bessel blobs (order 2, alpha 10.4, radius 2 pixels) on the pixel
 // centres; cproj = a sqrt(2 pi / alpha) / I_2(alpha) scales the projection;
-// stencil[di + 2][dj + 2] = b(|(di, dj)|), the image of a unit coefficient.
+// stencil[di + 2][dj + 2] = b(|(di, dj)|), the image of a unit coefficient;
+// tab: the device copy of the projection's table (sp_blob.h: ntab + 1
+// entries over [0, a], inv_h = ntab / a), set by the caller.
 constexpr double BLOB_RADIUS = 2.0;
 constexpr double BLOB_ALPHA = 10.4;
 struct BlobDev {
     double a, alpha, cproj;
     double stencil[5][5];
+    const double2* tab;
+    int ntab;
+    double inv_h;
 };
 BlobDev blob_constants();
 // norms: ||R_i||^2 of every ray (blob nullable: pixel basis); init: x = mu /
