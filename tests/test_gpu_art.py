@@ -67,6 +67,37 @@ def test_supart_table1_matches_oracle(sp, small):
     assert e <= 1e-5
 
 
+@pytest.fixture(scope="module")
+def paper243():
+    """The paper's shape (Section 4.1: 243^2 pixels, 360 angles, 345 bins):
+    20 random ellipses (seed 3), 1% noise, the oracle's closed-form R."""
+    from synth import noisy_data, random_ellipses, unit_noise
+    og = OG(243, 243, 360, 345)
+    img, rng = random_ellipses(243, 243, 20, 3)
+    R, _ = oproj.matrix(og)
+    b = noisy_data(R @ img.astype(np.float64).ravel(), unit_noise(rng, og.m), 0.01).astype(np.float32)
+    return og, img, b.reshape(og.n_angles, og.n_bins), R
+
+
+def test_art_and_supart_paper_shape(sp, paper243):
+    og, img, b, R = paper243
+    g = sp_geom(sp, og)
+    print("ART 243x243x360x345 r=5 lambda=0.01, 2 cycles", flush=True)
+    want = oart.supart(og, R, b.astype(np.float64), 5.0, 1e-2, 2)
+    got = sp.sp_supart_solve(g, cuda(b), K=0, r=5.0, lam=1e-2, max_iter=2)
+    e = rel_l2(got.x.cpu().numpy(), want.x)
+    print(f"ART rel_l2 {e:.3e}", flush=True)
+    assert e <= 1e-5
+    print("SupART 243x243x360x345 (10, 1-1e-5, 1e-2, 5, 5e-2), 2 cycles", flush=True)
+    tvp = TVParams(10, 1 - 1e-5, 1e-2)
+    want = oart.supart(og, R, b.astype(np.float64), 5.0, 5e-2, 2, tvp)
+    got = sp.sp_supart_solve(g, cuda(b), K=10, a=1 - 1e-5, gamma=1e-2, r=5.0, lam=5e-2, max_iter=2)
+    assert list(got.trace["ell"]) == want.trace["ell"]
+    e = rel_l2(got.x.cpu().numpy(), want.x)
+    print(f"SupART rel_l2 {e:.3e}", flush=True)
+    assert e <= 1e-5
+
+
 @pytest.mark.parametrize("og", [OG(37, 53, 45, 61, bin_spacing=0.45),
                                 OG(20, 24, 7, 33, pixel=0.7, theta0=0.1, dtheta=0.45, bin_spacing=0.6,
                                    bin_offset=0.13),
