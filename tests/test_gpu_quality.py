@@ -152,3 +152,56 @@ def test_se_curve_resumed_run(sp, small):
     assert np.isnan(se[0]) and np.isnan(se[1])
     # bodies 4..8 of the straight run, bit for bit
     np.testing.assert_array_equal(se[2:], full.trace["se"][5:])
+
+
+@pytest.fixture(scope="module")
+def paper243():
+    """The paper's shape (Section 4.1: 243^2 pixels, 360 angles, 345 bins):
+    20 random ellipses (seed 3), 1% noise, the oracle's closed-form R."""
+    from synth import noisy_data, random_ellipses, unit_noise
+    og = OG(243, 243, 360, 345)
+    img, rng = random_ellipses(243, 243, 20, 3)
+    R, _ = oproj.matrix(og)
+    b = noisy_data(R @ img.astype(np.float64).ravel(), unit_noise(rng, og.m), 0.01).astype(np.float32)
+    return og, img.astype(np.float32), b.reshape(og.n_angles, og.n_bins), R
+
+
+# Table 1's presets at the paper's shape: SupPCG, PCG, SupCG
+PAPER_FLAGS = [
+    ("SupPCG-table1", (40, 1 - 1e-5, 1e-2), (1e-5, 0.8)),
+    ("PCG-table1", None, (1e-3, 0.6)),
+    ("SupCG-table1", (40, 1 - 1e-5, 5e-2), None),
+]
+
+
+@pytest.mark.parametrize("name,tvp,pre", PAPER_FLAGS, ids=[f[0] for f in PAPER_FLAGS])
+def test_se_curve_paper_shape(sp, paper243, name, tvp, pre):
+    og, img, b, R = paper243
+    n_iter = 8
+    print(f"SE curve {name} 243x243x360x345 {n_iter} bodies", flush=True)
+    if pre is None:
+        prob = osup.Problem(R, b.astype(np.float64), (og.rows, og.cols), None)
+    else:
+        mu, rho = pre
+        prob = osup.Problem(R, b.astype(np.float64), (og.rows, og.cols),
+                            lambda v, mu=mu, rho=rho: oprecond.apply(v, mu, rho))
+    otv = osup.TVParams(*tvp) if tvp else None
+    axes = oq.paper_axes(og)
+    want, ref = oq.se_curve(og, prob, np.zeros(og.n), otv, n_iter, img, axes)
+    kw = dict(K=tvp[0], a=tvp[1], gamma=tvp[2]) if tvp else dict(K=0)
+    if pre is None:
+        kw["precond"] = "none"
+    else:
+        kw["mu"], kw["rho"] = pre
+    res = sp.sp_suppcg_solve(geom(sp, og), cuda(b), None, max_iter=n_iter, graph=True, se_ref=cuda(img), **kw)
+    if tvp:
+        assert list(res.trace["ell"]) == ref.trace["ell"]
+    got = res.trace["se"]
+    assert len(got) == len(want) == n_iter + 2
+    C = 1.0 / np.sqrt(np.sum(img.astype(np.float64)[oq.ellipse_mask(og, axes)] ** 2))
+    iterates = [np.zeros(og.n)] + list(ref.trace["x"])
+    worst = max(abs(gv - wv) / (C * np.linalg.norm(xk) + 1e-300) for gv, wv, xk in zip(got[1:], want[1:], iterates[1:]))
+    print(f"{name}: worst SE difference {worst:.3e} of C ||x_k||", flush=True)
+    for k, (gv, wv, xk) in enumerate(zip(got, want, iterates)):
+        assert abs(gv - wv) <= C * 1e-3 * np.linalg.norm(xk) + 1e-12, (k, gv, wv)
+
