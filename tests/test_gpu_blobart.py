@@ -65,6 +65,25 @@ def test_blobart_ragged_geometries(sp, og):
     assert rel_l2(got.x.cpu().numpy(), want) <= 1e-5
 
 
+def test_blobart_paper_shape(sp):
+    """One BlobART cycle at the paper's shape (243^2 x 360 x 345; Table 1: r = 5,
+    lambda = 0.01) on the data of 20 random ellipses (seed 3) with 1% noise."""
+    from oracle import projector as oproj
+    from synth import noisy_data, random_ellipses, unit_noise
+    og = OG(243, 243, 360, 345)
+    img, rng = random_ellipses(243, 243, 20, 3)
+    R, _ = oproj.matrix(og)
+    b = noisy_data(R @ img.astype(np.float64).ravel(), unit_noise(rng, og.m), 0.01).astype(np.float32)
+    print("BlobART 243x243x360x345: building the oracle's blob matrix (~40 s)", flush=True)
+    Rb = oblob.system_matrix(og)
+    _, want, _ = oblob.blob_art(og, Rb, b.astype(np.float64), 5.0, 1e-2, 1)
+    got = sp.sp_blobart_solve(sp_geom(sp, og), cuda(b.reshape(og.n_angles, og.n_bins)), r=5.0, lam=1e-2,
+                              max_iter=1)
+    e = rel_l2(got.x.cpu().numpy(), want)
+    print(f"BlobART paper shape rel_l2 {e:.3e}", flush=True)
+    assert e <= 1e-5
+
+
 def test_blobart_graph_equals_eager(sp):
     og, img, b = workload_problem("small64")
     g = sp_geom(sp, og)
