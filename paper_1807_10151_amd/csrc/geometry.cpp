@@ -80,38 +80,39 @@ int geom_fail(char* err, size_t n, const char* fmt, ...) {
 }
 }  // namespace
 
-int project_wave_count(const GeomDev& G) {
-    const int r = G.nB % 64, full = G.nB / 64;
-    long w = 0;
-    for (int q = 0; q < 4; ++q) {
-        const long na = G.cls[q + 1] - G.cls[q];
-        if (q >= 2 || r == 0) w += na * ((G.nB + 63) / 64);    // axis classes are not packed
-        else w += na * full + (na * r + 63) / 64;
-    }
-    return (int)w;
-}
+int project_wave_count(const GeomDev& G) { return project_waves(G, nullptr); }
 
-void project_waves(const GeomDev& G, WaveDev* out) {
-    // Chunk-major: for each 64-bin chunk, every class's angles in groups of
-    // four (a workgroup: four neighbouring angles of one chunk, whose rays
-    // cross nearly the same pixels); in the last, partial chunk the oblique
-    // classes' tails are packed.  The dispatch order sorts workgroups by
-    // cost and keeps this order among equal costs, so workgroups that run
-    // side by side on the GPU read neighbouring parts of the image.
-    const int r = G.nB % 64, full = G.nB / 64, nch = (G.nB + 63) / 64;
+int project_waves(const GeomDev& G, WaveDev* out) {
+    // Oblique classes: waves of WAVE_ANGLES angles by WAVE_BINS bins, a
+    // workgroup's four waves the four 16-bin sub-chunks of one 64-bin chunk
+    // for the same four neighbouring angles (rays that cross nearly the same
+    // pixels), chunk by chunk; then the classes' packed tails (the last
+    // nB % WAVE_BINS bins).  Axis-parallel classes: waves of 64 bins of one
+    // angle.  The dispatch order sorts workgroups by cost and keeps this
+    // order among equal costs, so workgroups that run side by side on the GPU
+    // read neighbouring parts of the image.
+    const int r = G.nB % WAVE_BINS, full = G.nB / WAVE_BINS;
     int w = 0;
-    for (int c = 0; c < nch; ++c)
-        for (int q = 0; q < 4; ++q) {
+    auto put = [&](const WaveDev& W) {
+        if (out) out[w] = W;
+        ++w;
+    };
+    for (int c = 0; c < full; c += 4)
+        for (int q = 0; q < 2; ++q) {
             const int a0 = G.cls[q], a1 = G.cls[q + 1];
-            const bool pack = q < 2 && r != 0;
-            if (pack && c == full) {
-                const long stream = (long)(a1 - a0) * r;
-                for (long e = 0; e < stream; e += 64) out[w++] = WaveDev{a0, (int)e, a1, 1};
-                continue;
-            }
-            for (int g0 = a0; g0 < a1; g0 += 4)
-                for (int a = g0; a < std::min(a1, g0 + 4); ++a) out[w++] = WaveDev{a, 64 * c, a1, 0};
+            for (int g0 = a0; g0 < a1; g0 += WAVE_ANGLES)
+                for (int j = c; j < std::min(full, c + 4); ++j) put(WaveDev{g0, WAVE_BINS * j, a1, WAVE_BLOCK});
         }
+    for (int q = 0; q < 2; ++q) {
+        const int a0 = G.cls[q], a1 = G.cls[q + 1];
+        if (r == 0) continue;
+        const int stream = (a1 - a0) * r;
+        for (int e = 0; e < stream; e += 64) put(WaveDev{a0, e, a1, WAVE_TAIL});
+    }
+    for (int q = 2; q < 4; ++q)
+        for (int a = G.cls[q]; a < G.cls[q + 1]; ++a)
+            for (int k0 = 0; k0 < G.nB; k0 += 64) put(WaveDev{a, k0, a + 1, WAVE_ROW});
+    return w;
 }
 
 int project_parts(int rows, int cols, int nwaves, int resident_waves) {
@@ -217,7 +218,7 @@ long wave_steps(const GeomDev& G, const AngleDev* tab, const WaveDev& W) {
         hi = std::max(hi, h);
         return true;
     };
-    if (W.tail) {
+    if (W.tail != WAVE_ROW) {
         for (int l = 0; l < 64; ++l) add(l);
     } else {
         // the rays of one angle that meet the image are consecutive bins, and a

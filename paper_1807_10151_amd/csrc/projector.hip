@@ -26,11 +26,13 @@
 // (|slope| <= 1) columns per row.  A lane owns one ray and the 64 lanes of a
 // wave walk the union of their (nonempty) row ranges together, so each step
 // gathers neighbouring addresses of one row.  R's wave table (WaveDev) gives
-// each wave its rays: 64 consecutive bins of one angle, or the last nB % 64
-// bins of consecutive angles of one class packed into full waves; a
-// workgroup's four waves are four consecutive table entries (four angles of
-// one chunk), and the workgroups run in a host-computed order
-// (project_order).  Horizontal angles walk columns of a zero-padded
+// each wave its rays: 16 consecutive bins of four neighbouring angles (rays
+// whose image extents differ little, so few lane-steps fall outside a lane's
+// own ray), the last nB % 16 bins of consecutive angles of one class packed
+// into full waves, or 64 bins of one axis-parallel angle; a workgroup's four
+// waves are four consecutive table entries (the four 16-bin parts of one
+// 64-bin chunk of the same angles), and the workgroups run in a
+// host-computed order (project_order).  Horizontal angles walk columns of a zero-padded
 // transposed copy.
 //
 // Backward gather.  A lane owns PX (2 or 4) pixels of one row, 8 columns

@@ -60,12 +60,21 @@ struct GeomDev {
     int nwg;            // R's ray workgroups, four waves each: ceil(nwaves / 4)
 };
 
-// One wave of R: 64 rays, one per lane.  A full wave holds 64 consecutive bins
-// of one angle: lane l takes angle a0 and bin k0 + l.  A tail wave packs the
-// last nB % 64 bins of consecutive angles of one class: the class's tail rays,
-// angle by angle, form a stream, and lane l takes its entry k0 + l, i.e. angle
-// a0 + (k0 + l) / r and bin nB - r + (k0 + l) % r with r = nB % 64, while that
-// angle lies before aend.  Angles are indices of the class-sorted table.
+// One wave of R: 64 rays, one per lane, of one angle class.  Kinds (`tail`):
+//  WAVE_BLOCK: WAVE_ANGLES consecutive angles by WAVE_BINS consecutive bins:
+//    lane l takes angle a0 + l / WAVE_BINS and bin k0 + l % WAVE_BINS, while
+//    that angle lies before aend (a wave of 64 consecutive bins of one angle
+//    would walk the union of rays whose image extents differ more);
+//  WAVE_TAIL: the last r = nB % WAVE_BINS bins of consecutive angles of one
+//    class, packed: the class's tail rays, angle by angle, form a stream, and
+//    lane l takes its entry k0 + l, i.e. angle a0 + (k0 + l) / r and bin
+//    nB - r + (k0 + l) % r, while that angle lies before aend;
+//  WAVE_ROW: 64 consecutive bins of one angle (lane l: angle a0, bin k0 + l),
+//    for the axis-parallel classes (one or two angles).
+// Angles are indices of the class-sorted table.
+constexpr int WAVE_BINS = 16;
+constexpr int WAVE_ANGLES = 4;
+enum WaveKind : int32_t { WAVE_BLOCK = 0, WAVE_TAIL = 1, WAVE_ROW = 2 };
 struct WaveDev {
     int32_t a0, k0, aend, tail;
 };
@@ -209,11 +218,12 @@ int build_geometry_into(const sp_geometry* g, int n_cu, GeomDev& G, AngleDev* ta
                         size_t errlen);
 // Bin positions of the padded bin range: t[PAD + k] = s_k, k = -PAD .. nB + PAD - 1.
 void bin_sk_fill(const GeomDev& G, double* t);
-// R's wave table: its size and its entries (G.nwaves of them), chunk by
-// chunk: each class's angles in groups of four for one 64-bin chunk, and in
-// the last chunk (when nB % 64 != 0) the oblique classes' packed tail waves.
+// R's wave table: its size and its entries (G.nwaves of them; see WaveDev):
+// the oblique classes' four-angle by 16-bin blocks, 64-bin chunk by chunk,
+// then their packed tail waves, then the axis-parallel classes' 64-bin waves.
 int project_wave_count(const GeomDev& G);
-void project_waves(const GeomDev& G, WaveDev* out);
+// Writes the entries when out != nullptr; returns their number.
+int project_waves(const GeomDev& G, WaveDev* out);
 // Steps a wave of R walks: the union of its lanes' nonempty step ranges.
 long wave_steps(const GeomDev& G, const AngleDev* tab, const WaveDev& W);
 // Dispatch order of R's ray workgroups (G.nwg entries, a permutation):

@@ -10,14 +10,20 @@
 namespace sp {
 
 // Ray of lane `lane` of wave W: index ai of the class-sorted angle table and
-// bin k; false for a lane past the end of its tail stream or of the bins.
+// bin k; false for a lane past the end of its class, its tail stream or the
+// bins.
 __host__ __device__ inline bool wave_ray(const WaveDev& W, int lane, int nB, int& ai, int& k) {
-    if (!W.tail) {
+    if (W.tail == WAVE_BLOCK) {
+        ai = W.a0 + lane / WAVE_BINS;
+        k = W.k0 + lane % WAVE_BINS;
+        return ai < W.aend && k < nB;
+    }
+    if (W.tail == WAVE_ROW) {
         ai = W.a0;
         k = W.k0 + lane;
         return k < nB;
     }
-    const int r = nB & 63;
+    const int r = nB % WAVE_BINS;
     const int e = W.k0 + lane;
     ai = W.a0 + e / r;
     k = nB - r + e % r;
