@@ -50,17 +50,17 @@ OPS_PER_NNZ = 4
 # memory fabric per launch (FETCH_SIZE + WRITE_SIZE, scaled by the counters of
 # a 64 MiB device copy).  R^T: mean of its float32 (R p) and float64
 # (residual) sinogram forms, one of each per loop body.
-COUNTERS = {"measured_at": "kernels of 1de3a50, profiled at 542fbec",
-            "valu_instr": {"project": 2.907e7, "backproject": 3.577e7},
-            "traffic_bytes": {"project": 40.27e6, "backproject": 20.88e6}}
+COUNTERS = {"measured_at": "kernels of 1d7046e",
+            "valu_instr": {"project": 2.683e7, "backproject": 3.576e7},
+            "traffic_bytes": {"project": 39.96e6, "backproject": 20.78e6}}
 # The vector L1's access rate, the limit the gathers of both kernels run into
-# (profiles/memory_pipe_ct512.md, same kernels, re-taken at 462a28c):
+# (profiles/memory_pipe_ct512.md, same kernels):
 # TCP_TOTAL_CACHE_ACCESSES per launch and per compute unit and cycle of the
 # kernel's own run (about one access per CU and cycle is the L1's rate; R^T:
 # the mean of its two sinogram forms, as above).
-L1_ACCESS = {"measured_at": "kernels of 1de3a50, profiled at 462a28c",
-             "per_launch": {"project": 6.095e7, "backproject": 5.368e7},
-             "per_cu_per_cycle": {"project": 1.03, "backproject": 0.84}}
+L1_ACCESS = {"measured_at": "kernels of 1d7046e",
+             "per_launch": {"project": 5.691e7, "backproject": 5.368e7},
+             "per_cu_per_cycle": {"project": 1.01, "backproject": 0.84}}
 
 
 def log(msg):
