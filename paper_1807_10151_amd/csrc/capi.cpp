@@ -69,6 +69,7 @@ struct sp_ctx {
     // resume); the standalone operators use ox, oxh and oscal instead.
     DevBuf vx, vxh, vp;                   // float64 x_k, x_{k+1/2}, p
     DevBuf vh, vg, vz, vtb, vtmp;
+    DevBuf vtb2, stv_y;                   // S_TV ping-pong: second t_bar (float), iterate (float64)
     DevBuf ox, oxh, oscal;                // sp_tv, sp_tv_grad, sp_tv_perturb
     DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc, part_se;
     DevBuf stored_xT;                     // transposed image for the stored R product
@@ -388,9 +389,9 @@ int check_tv(sp_ctx* c, const sp_tv_params* p) {
 
 int ensure_vectors(sp_ctx* c, size_t n) {
     int rc;
-    for (DevBuf* b : {&c->vh, &c->vg, &c->vz, &c->vtb, &c->vtmp})
+    for (DevBuf* b : {&c->vh, &c->vg, &c->vz, &c->vtb, &c->vtb2, &c->vtmp})
         if ((rc = ensure(c, *b, n * sizeof(float)))) return rc;
-    for (DevBuf* b : {&c->vx, &c->vxh, &c->vp})
+    for (DevBuf* b : {&c->vx, &c->vxh, &c->vp, &c->stv_y})
         if ((rc = ensure(c, *b, n * sizeof(double)))) return rc;
     return SP_OK;
 }
@@ -424,6 +425,8 @@ int ensure_op_vectors(sp_ctx* c, size_t n) {
     if ((rc = ensure(c, c->ox, n * sizeof(double)))) return rc;
     if ((rc = ensure(c, c->oxh, n * sizeof(double)))) return rc;
     if ((rc = ensure(c, c->vtb, n * sizeof(float)))) return rc;
+    if ((rc = ensure(c, c->vtb2, n * sizeof(float)))) return rc;
+    if ((rc = ensure(c, c->stv_y, n * sizeof(double)))) return rc;
     return ensure(c, c->oscal, sizeof(Scalars));
 }
 
@@ -482,6 +485,10 @@ struct ProfScope {
 // One S_TV call (Algorithm 1) from x into xh, K inner steps.  With snorm the
 // partials of ||xh - x||^2 go to part_s, and unless ride_snorm (a later
 // kernel carries the step, see ScalarRide) the step norm is traced here.
+// Between two inner steps one launch applies the step and forms the next
+// t_bar; the iterates then alternate between xh and stv_y (and t_bar
+// between vtb and vtb2) so that it never reads what it writes, and the last
+// step lands in xh.  With x aliasing xh the steps run unfused.
 void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, bool snorm,
                  TraceDev tr, int32_t* trials_out, bool ride_snorm = false) {
     const GeomDev& G = c->G;
@@ -489,16 +496,31 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
     const int* halt = &sc->halt;
     const int nb = tv_blocks(G.rows, G.cols);
     ProfScope ps(c, SP_PROF_TV);
+    const bool fuse = K > 1 && x != xh && c->stv_y.bytes >= (size_t)n * sizeof(double) &&
+                      c->vtb2.bytes >= (size_t)n * sizeof(float);
+    const double* src = x;
+    float* tb = dptr<float>(c->vtb);
+    launch_tv_grad(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), halt);
     for (int i = 0; i < K; ++i) {
-        const double* src = i == 0 ? x : xh;
-        launch_tv_grad(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), halt);
-        launch_tv_trials(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), nb,
-                         sc, 4, dptr<double>(c->part_t), halt);
-        launch_tv_decide(c->stream, G.rows, G.cols, src, dptr<float>(c->vtb), dptr<double>(c->part_g), nb,
+        launch_tv_trials(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), nb, sc, 4,
+                         dptr<double>(c->part_t), halt);
+        launch_tv_decide(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), nb,
                          dptr<double>(c->part_t), nb, 4, sc, tr, trials_out, halt);
         const bool last = i == K - 1;
-        launch_tv_apply(c->stream, n, src, xh, dptr<float>(c->vtb), sc, (last && snorm) ? x : nullptr,
-                        dptr<double>(c->part_s), halt);
+        if (last || !fuse) {
+            launch_tv_apply(c->stream, n, src, xh, tb, sc, (last && snorm) ? x : nullptr,
+                            dptr<double>(c->part_s), halt);
+            src = xh;
+            if (!last) launch_tv_grad(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), halt);
+        } else {
+            // iterate i + 1 goes to xh when K - 1 - (i + 1) is even, so iterate K - 1 is in xh
+            double* dst = (K - 2 - i) % 2 == 0 ? xh : dptr<double>(c->stv_y);
+            float* tbn = tb == dptr<float>(c->vtb) ? dptr<float>(c->vtb2) : dptr<float>(c->vtb);
+            launch_tv_apply_grad(c->stream, G.rows, G.cols, src, dst, tb, tbn, sc, dptr<double>(c->part_g),
+                                 halt);
+            src = dst;
+            tb = tbn;
+        }
     }
     if (snorm && !ride_snorm)
         launch_scalar(c->stream, OP_SNORM, sc, tr, dptr<double>(c->part_s), nb, nullptr, 0);

@@ -278,6 +278,12 @@ void launch_tv_apply(hipStream_t st, int n, const double* src, double* dst, cons
                      const Scalars* sc, const double* xk, double* partials, const int* halt);
 void launch_tv_value(hipStream_t st, int rows, int cols, const double* y, double* partials,
                      const int* halt);
+// dst = src + lam tb_in, then tb_out = t_bar(dst) and its ||.||^2 partials
+// (k_tv_apply followed by k_tv_grad, bit for bit); no overlap between dst and
+// src or between tb_out and tb_in.
+void launch_tv_apply_grad(hipStream_t st, int rows, int cols, const double* src, double* dst,
+                          const float* tb_in, float* tb_out, const Scalars* sc, double* partials,
+                          const int* halt);
 
 // cg.hip (p, x and x_{k+1/2} in float64; g, z, h float32)
 int vec_blocks(int n);

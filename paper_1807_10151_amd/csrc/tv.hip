@@ -20,32 +20,36 @@ namespace sp {
 
 constexpr int TVJ = 4;   // trials evaluated per pass (the first is accepted in most loop bodies)
 
-// t_bar at pixel p = (i, j) of a rows x cols float64 image, evaluated in
-// float64 and rounded to float32 (reading: the partial derivative is
-// undefined when a square-root term it enters is zero).
-__device__ __forceinline__ float tv_neg_grad(const double* __restrict__ y, int rows, int cols,
-                                             int i, int j, size_t p) {
-    const double v = y[p];
+// t_bar at pixel p = (i, j) of a rows x cols float64 image whose value at q
+// is y(q), evaluated in float64 and rounded to float32 (reading: the partial
+// derivative is undefined when a square-root term it enters is zero).
+template <class Y>
+__device__ __forceinline__ float tv_neg_grad_at(Y&& y, int rows, int cols, int i, int j, size_t p) {
+    const double v = y(p);
     double gsum = 0.0;
     bool bad = false;
     if (i < rows - 1 && j < cols - 1) {          // T_{i,j}
-        const double dv = v - y[p + cols], dh = v - y[p + 1];
+        const double dv = v - y(p + cols), dh = v - y(p + 1);
         if (dv == 0.0 && dh == 0.0) bad = true;
         else gsum += (dv + dh) / sqrt(dv * dv + dh * dh);
     }
     if (i >= 1 && j < cols - 1) {                // T_{i-1,j}
-        const double u = y[p - cols];
-        const double dv = u - v, dh = u - y[p - cols + 1];
+        const double u = y(p - cols);
+        const double dv = u - v, dh = u - y(p - cols + 1);
         if (dv == 0.0 && dh == 0.0) bad = true;
         else gsum -= dv / sqrt(dv * dv + dh * dh);
     }
     if (i < rows - 1 && j >= 1) {                // T_{i,j-1}
-        const double u = y[p - 1];
-        const double dv = u - y[p - 1 + cols], dh = u - v;
+        const double u = y(p - 1);
+        const double dv = u - y(p - 1 + cols), dh = u - v;
         if (dv == 0.0 && dh == 0.0) bad = true;
         else gsum -= dh / sqrt(dv * dv + dh * dh);
     }
     return bad ? 0.0f : (float)(-gsum);
+}
+__device__ __forceinline__ float tv_neg_grad(const double* __restrict__ y, int rows, int cols,
+                                             int i, int j, size_t p) {
+    return tv_neg_grad_at([&](size_t q) { return y[q]; }, rows, cols, i, j, p);
 }
 
 __device__ __forceinline__ void tv_grad_body(int rows, int cols, const double* __restrict__ y,
@@ -340,6 +344,44 @@ void launch_tv_apply(hipStream_t st, int n, const double* src, double* dst, cons
                      const Scalars* sc, const double* xk, double* partials, const int* halt) {
     hipLaunchKernelGGL(k_tv_apply, dim3((n + 255) / 256), dim3(256), 0, st, n, src, dst, tb, sc, xk,
                        partials, halt);
+}
+
+// One S_TV inner step's update followed by the next step's gradient, in one
+// launch: dst = src + lam tb_in (as k_tv_apply) and tb_out = t_bar(dst) with
+// the partials of ||tb_out||^2 (as k_tv_grad).  A thread forms dst at its
+// pixel and at the neighbours its t_bar reads, with the same fma, so the
+// values are those of the two launches bit for bit; dst and src (and tb_in
+// and tb_out) must not overlap.
+__global__ __launch_bounds__(256) void k_tv_apply_grad(int rows, int cols, const double* __restrict__ src,
+                                                       double* __restrict__ dst,
+                                                       const float* __restrict__ tb_in,
+                                                       float* __restrict__ tb_out,
+                                                       const Scalars* __restrict__ sc,
+                                                       double* __restrict__ partials,
+                                                       const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    __shared__ double red[4];
+    const double lam = sc->lam;
+    const size_t n = (size_t)rows * cols;
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double sq = 0.0;
+    if (p < n) {
+        auto y = [&](size_t q) { return fma(lam, (double)tb_in[q], src[q]); };
+        dst[p] = y(p);
+        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+        const float t = tv_neg_grad_at(y, rows, cols, i, j, p);
+        tb_out[p] = t;
+        sq = (double)t * (double)t;
+    }
+    const double tot = block_sum(sq, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+void launch_tv_apply_grad(hipStream_t st, int rows, int cols, const double* src, double* dst,
+                          const float* tb_in, float* tb_out, const Scalars* sc, double* partials,
+                          const int* halt) {
+    hipLaunchKernelGGL(k_tv_apply_grad, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, src, dst,
+                       tb_in, tb_out, sc, partials, halt);
 }
 
 __global__ __launch_bounds__(256) void k_tv_value(int rows, int cols, const double* __restrict__ y,

@@ -120,6 +120,22 @@ def test_batch_cg_start_and_halting(sp):
         assert_same(rb, rs)
 
 
+@pytest.mark.parametrize("K", [3, 4, 5])
+def test_batch_inner_steps_match_single(sp, K):
+    # several S_TV inner steps per body: the single-slice solver applies each
+    # step and forms the next t_bar in one launch, alternating two iterate
+    # buffers (odd and even K end on either), while the batched solver keeps
+    # separate launches; both must give the same bits (a = 0.7 and gamma = 3
+    # reject trials in the early bodies)
+    geoms, bs = mixed_batch(sp)
+    kw = dict(K=K, a=0.7, gamma=3.0, mu=MU, rho=RHO, max_iter=6)
+    print(f"K {K}", flush=True)
+    got = sp.sp_suppcg_solve_batched(geoms, bs, graph=True, **kw)
+    want = singles(sp, geoms, bs, graph=True, **kw)
+    for rb, rs in zip(got, want):
+        assert_same(rb, rs)
+
+
 def test_batch_slice_matches_oracle(sp):
     # the 64 x 64 workload inside a mixed batch, 20 iterations, against the
     # float64 oracle (same bar as the single-slice solver)
