@@ -36,8 +36,10 @@
  *    x_k, x_{k+1/2}, the search direction p and the residual r = R x - b are
  *    float64 (their float32 rounding, repeated every iteration and amplified
  *    by the cancellation in R^T r, is what moves a float32 iterate away from
- *    the float64 one); the gradient g, M g, h = A p, the TV direction and
- *    R p are float32.  Images passed in and out are float32.
+ *    the float64 one); so are R z and R p, through which the solvers take
+ *    Algorithm 2's h = A p (z^T h = (R z)^T (R p), p^T h = ||R p||^2; h itself
+ *    is never formed).  The gradient g, M g and the TV direction are float32.
+ *    Images passed in and out are float32.
  */
 #ifndef SUPPCG_H
 #define SUPPCG_H
@@ -276,7 +278,8 @@ int sp_suppcg_solve(sp_ctx* ctx, const sp_geometry* g, const float* b, const flo
 
 /* ---- checkpoint / resume ------------------------------------------------------
  * The state Algorithm 3 carries from one loop body to the next: x_k,
- * x_{k-1/2}, p_{k-1} (float64), h_{k-1} (float32) and the scalars p^T h, l_k,
+ * x_{k-1/2}, p_{k-1} (float64), h_{k-1} in the form the solver keeps it,
+ * q = R p_{k-1} (n_angles x n_bins float64; h = R^T q), and the scalars p^T h, l_k,
  * k, f(x_{k-1/2}), f(x_0), the stop status and, for a learned preconditioner,
  * whether it has been replaced by the Fourier one, together with the geometry,
  * the S_TV parameters and the preconditioner parameters.  The learned network's

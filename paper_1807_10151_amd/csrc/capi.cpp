@@ -64,14 +64,15 @@ struct sp_ctx {
     int fftP = 0;
     DevBuf tw, S;
 
-    // solver vectors and scratch.  vx, vxh, vp, vh and scal carry Algorithm 3's
+    // solver vectors and scratch.  vx, vxh, vp, vq and scal carry Algorithm 3's
     // state from one loop body to the next and survive the call (checkpoint /
     // resume); the standalone operators use ox, oxh and oscal instead.
     DevBuf vx, vxh, vp;                   // float64 x_k, x_{k+1/2}, p
-    DevBuf vh, vg, vz, vtb, vtmp;
+    DevBuf vq, vw;                        // float64 q = R p and w = R z (nA x nB)
+    DevBuf vg, vz, vtb, vtmp;
     DevBuf vtb2, stv_y;                   // S_TV ping-pong: second t_bar (float), iterate (float64)
     DevBuf ox, oxh, oscal;                // sp_tv, sp_tv_grad, sp_tv_perturb
-    DevBuf part_f, part_zh, part_gp, part_ph, part_g, part_t, part_s, part_misc, part_se;
+    DevBuf part_f, part_zh, part_gp, part_qq, part_g, part_t, part_s, part_misc, part_se;
     DevBuf stored_xT;                     // transposed image for the stored R product
     DevBuf art_u, art_nrm, art_sum;       // ART: auxiliary vector, ||R_i||^2, sum of b
     DevBuf scal, trace_d, replay_d, trials_tmp;
@@ -387,12 +388,17 @@ int check_tv(sp_ctx* c, const sp_tv_params* p) {
     return SP_OK;
 }
 
+// Solver vectors of n pixels (and the nA x nB ray vectors of the context's
+// geometry).
 int ensure_vectors(sp_ctx* c, size_t n) {
     int rc;
-    for (DevBuf* b : {&c->vh, &c->vg, &c->vz, &c->vtb, &c->vtb2, &c->vtmp})
+    const size_t m = (size_t)c->G.nA * c->G.nB;
+    for (DevBuf* b : {&c->vg, &c->vz, &c->vtb, &c->vtb2, &c->vtmp})
         if ((rc = ensure(c, *b, n * sizeof(float)))) return rc;
     for (DevBuf* b : {&c->vx, &c->vxh, &c->vp, &c->stv_y})
         if ((rc = ensure(c, *b, n * sizeof(double)))) return rc;
+    for (DevBuf* b : {&c->vq, &c->vw})
+        if ((rc = ensure(c, *b, m * sizeof(double)))) return rc;
     return SP_OK;
 }
 
@@ -401,7 +407,7 @@ int ensure_partials(sp_ctx* c) {
     const int n = G.rows * G.cols;
     int rc;
     if ((rc = ensure(c, c->part_f, (size_t)project_blocks(G) * 8))) return rc;
-    if ((rc = ensure(c, c->part_ph, (size_t)backproject_blocks(G) * 8))) return rc;
+    if ((rc = ensure(c, c->part_qq, (size_t)vec_blocks(G.nA * G.nB) * 8))) return rc;
     if ((rc = ensure(c, c->part_zh, (size_t)std::max((G.rows + 1) / 2, vec_blocks(n)) * 8))) return rc;
     if ((rc = ensure(c, c->part_gp, (size_t)vec_blocks(n) * 8))) return rc;
     if ((rc = ensure(c, c->part_g, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
@@ -645,6 +651,7 @@ int stage_blocks(const SliceDev& S, int stage) {
     case BS_COLS: return S.F.P ? (S.F.SP + S.F.CB - 1) / S.F.CB : 0;
     case BS_TV: return tv_blocks(G.rows, G.cols);
     case BS_VEC: return vec_blocks(S.n);
+    case BS_PQ: return vec_blocks(std::max(S.n, S.m));
     default: return 1;
     }
 }
@@ -659,6 +666,7 @@ double item_cost(const SliceDev& S, int stage) {
     case BS_ROWS:
     case BS_COLS: return S.F.P ? (double)S.F.P * S.F.logP : 0.0;
     case BS_VEC: return (double)S.n / std::max(1, vec_blocks(S.n));
+    case BS_PQ: return (double)(S.n + S.m) / std::max(1, vec_blocks(std::max(S.n, S.m)));
     default: return 1.0;
     }
 }
@@ -730,7 +738,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
     std::vector<std::vector<AngleDev>> tabs(n);
     // sizes
     struct Off {
-        size_t ang, pwave, pord, xp, xTp, rp, rpd, seg, dvec, vec, S, tw, pf, pzh, pgp, pph, ptg, ptt, pts;
+        size_t ang, pwave, pord, xp, xTp, rpd, seg, dvec, vec, sq, S, tw, pf, pgp, pqq, ptg, ptt, pts;
     };
     std::vector<Off> off(n);
     size_t total = 0;
@@ -754,11 +762,11 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
             B.lds_rows = std::max(B.lds_rows, fft_lds_bytes(P, 1));
             B.lds_cols = std::max(B.lds_cols, fft_lds_bytes(P, S.F.CB));
         }
+        S.m = G.nA * G.nB;
         S.nf = project_blocks(G);
-        S.nph = backproject_blocks(G);
         S.ngp = vec_blocks(S.n);
+        S.nqq = vec_blocks(S.m);
         S.ntv = tv_blocks(G.rows, G.cols);
-        S.nzh = kind == SP_PRECOND_RAMP ? (G.rows + 1) / 2 : vec_blocks(S.n);
         Off& o = off[s];
         auto take = [&](size_t bytes) {
             const size_t at = total;
@@ -770,17 +778,16 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         o.pord = take((size_t)G.nwg * sizeof(int32_t));
         o.xp = take((size_t)G.rows * G.pitchX * 8);
         o.xTp = take((size_t)G.cols * G.pitchXT * 8);
-        o.rp = take((size_t)G.nA * G.pitchB * 4);
         o.rpd = take((size_t)G.nA * G.pitchB * 8);
         o.seg = take(G.parts > 1 ? (size_t)G.parts * G.nA * G.nB * 8 : 0);
         o.dvec = take((size_t)S.n * 8 * 3);  // x, x_half, p (float64)
-        o.vec = take((size_t)S.n * 4 * 4);   // h, g, z, t_bar
+        o.vec = take((size_t)S.n * 4 * 3);   // g, z, t_bar
+        o.sq = take((size_t)S.m * 8 * 2);    // q = R p, w = R z
         o.S = kind == SP_PRECOND_RAMP ? take((size_t)G.rows * S.F.SP * sizeof(double2)) : 0;
         o.tw = kind == SP_PRECOND_RAMP ? take((size_t)(S.F.P / 2) * sizeof(double2)) : 0;
         o.pf = take((size_t)S.nf * 8);
-        o.pzh = take((size_t)std::max(S.nzh, S.ngp) * 8);
         o.pgp = take((size_t)S.ngp * 8);
-        o.pph = take((size_t)S.nph * 8);
+        o.pqq = take((size_t)S.nqq * 8);
         o.ptg = take((size_t)S.ntv * 8);
         o.ptt = take((size_t)S.ntv * 9 * 8);
         o.pts = take((size_t)S.ntv * 8);
@@ -827,7 +834,6 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         S.xp = reinterpret_cast<double*>(base + o.xp);
         S.xTp = reinterpret_cast<double*>(base + o.xTp);
-        S.rp = reinterpret_cast<float*>(base + o.rp);
         S.rpd = reinterpret_cast<double*>(base + o.rpd);
         S.seg = S.G.parts > 1 ? reinterpret_cast<double*>(base + o.seg) : nullptr;
         double* dv = reinterpret_cast<double*>(base + o.dvec);
@@ -835,10 +841,11 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         S.xh = dv + (size_t)S.n;
         S.p = dv + 2 * (size_t)S.n;
         float* v = reinterpret_cast<float*>(base + o.vec);
-        S.h = v;
-        S.g = v + (size_t)S.n;
-        S.z = v + 2 * (size_t)S.n;
-        S.tb = v + 3 * (size_t)S.n;
+        S.g = v;
+        S.z = v + (size_t)S.n;
+        S.tb = v + 2 * (size_t)S.n;
+        S.q = reinterpret_cast<double*>(base + o.sq);
+        S.w = S.q + (size_t)S.m;
         if (kind == SP_PRECOND_RAMP) {
             S.F.S = reinterpret_cast<double2*>(base + o.S);
             S.F.tw = reinterpret_cast<const double2*>(base + o.tw);
@@ -852,9 +859,8 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
             HIP_TRY(c, hipStreamSynchronize(c->stream));
         }
         S.pf = reinterpret_cast<double*>(base + o.pf);
-        S.pzh = reinterpret_cast<double*>(base + o.pzh);
         S.pgp = reinterpret_cast<double*>(base + o.pgp);
-        S.pph = reinterpret_cast<double*>(base + o.pph);
+        S.pqq = reinterpret_cast<double*>(base + o.pqq);
         S.ptg = reinterpret_cast<double*>(base + o.ptg);
         S.ptt = reinterpret_cast<double*>(base + o.ptt);
         S.pts = reinterpret_cast<double*>(base + o.pts);
@@ -899,7 +905,7 @@ void batch_stage(sp_ctx* c, int stage, int order, int wpc, double mu, double rho
     switch (stage) {
     case BS_PREP: launch_prep_b(st, sl, t, BV_XH); break;
     case BS_PROJECT: launch_project_b(st, sl, t, table(c, BS_PROJ_COMB, order, 0), true); break;
-    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, false, B.bp_px); break;
+    case BS_BACKPROJECT: launch_backproject_b(st, sl, t, B.nbmax, B.bp_px); break;
     case BS_ROWS:
         launch_precond_b(st, sl, t, table(c, BS_COLS, order, wpc), B.lds_rows, B.lds_cols, mu, rho);
         break;
@@ -954,7 +960,7 @@ int batch_tune(sp_ctx* c, double mu, double rho) {
     return check_launch(c);
 }
 
-// Preconditioner stage of the batched solver: z = M g with z^T h partials.
+// Preconditioner stage of the batched solver: z = M g.
 void batch_precond(sp_ctx* c, double mu, double rho) {
     BatchState& B = *c->batch;
     const SliceDev* sl = dptr<SliceDev>(B.sl);
@@ -962,7 +968,7 @@ void batch_precond(sp_ctx* c, double mu, double rho) {
         launch_precond_b(c->stream, sl, table(c, BS_ROWS), table(c, BS_COLS), B.lds_rows, B.lds_cols,
                          mu, rho);
     else
-        launch_dot_zh_b(c->stream, sl, table(c, BS_VEC));
+        launch_copy_gz_b(c->stream, sl, table(c, BS_VEC));
 }
 }  // namespace
 
@@ -1000,9 +1006,9 @@ int sp_ctx_destroy(sp_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     (void)drain_pending(c);
-    for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->blob_tab, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vh, &c->ox, &c->oxh, &c->oscal,
-                      &c->vg, &c->vz, &c->vtb, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
-                      &c->part_ph, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->stored_xT, &c->art_u, &c->art_nrm, &c->art_sum, &c->scal,
+    for (DevBuf* b : {&c->ang, &c->pwave, &c->xp, &c->xTp, &c->yp, &c->ypd, &c->seg, &c->pord, &c->blob_tab, &c->tw, &c->S, &c->vx, &c->vxh, &c->vp, &c->vq, &c->vw, &c->ox, &c->oxh, &c->oscal,
+                      &c->vg, &c->vz, &c->vtb, &c->vtb2, &c->stv_y, &c->vtmp, &c->part_f, &c->part_zh, &c->part_gp,
+                      &c->part_qq, &c->part_g, &c->part_t, &c->part_s, &c->part_misc, &c->part_se, &c->stored_xT, &c->art_u, &c->art_nrm, &c->art_sum, &c->scal,
                       &c->trace_d, &c->replay_d, &c->trials_tmp})
         release(*b);
     if (c->own) (void)hipStreamDestroy(c->own);
@@ -1684,22 +1690,23 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     double* xh = dptr<double>(c->vxh);                  // x_{k+1/2}
     double* x = dptr<double>(c->vx);                    // x_k
     double* p = dptr<double>(c->vp);
-    float* h = dptr<float>(c->vh);
+    double* q = dptr<double>(c->vq);                    // R p
+    double* w = dptr<double>(c->vw);                    // R z
     float* gv = dptr<float>(c->vg);
     float* z = dptr<float>(c->vz);
     double* xp = dptr<double>(c->xp);
     double* xTp = dptr<double>(c->xTp);
     double* seg = dptr<double>(c->seg);
     const int* pord = dptr<int>(c->pord);
-    float* rp = dptr<float>(c->yp);
     double* rpd = dptr<double>(c->ypd);
     const WaveDev* waves = dptr<WaveDev>(c->pwave);
     const AngleDev* ang = dptr<AngleDev>(c->ang);
     double* pf = dptr<double>(c->part_f);
     double* pzh = dptr<double>(c->part_zh);
     double* pgp = dptr<double>(c->part_gp);
-    double* pph = dptr<double>(c->part_ph);
-    const int nf = project_blocks(G), nph = backproject_blocks(G), ngp = vec_blocks(n);
+    double* pqq = dptr<double>(c->part_qq);
+    const int m = G.nA * G.nB;
+    const int nf = project_blocks(G), nqq = vec_blocks(m), ngp = vec_blocks(n);
 
     const double se_ah = want_se ? trace->se_axes[0] : 0.0, se_av = want_se ? trace->se_axes[1] : 0.0;
     auto se_of_x = [&](double* dst, double* dst_body, const int* hflag) {
@@ -1711,21 +1718,19 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         launch_widen(st, n, x0, x);
         if (want_se) se_of_x(se_body + cap, nullptr, nullptr);                       // SE(x_0)
         // Algorithm 3, steps 1-9 (x_{1/2} = x_0; g_0 = A x_0 - y; z_0 = M g_0;
-        // p_0 = -z_0; h_0 = A p_0; alpha; x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
+        // p_0 = -z_0; h_0 = A p_0, carried as q = R p_0 = -R z_0; alpha;
+        // x_1 = x_0 + alpha p_0; k = 1; l_1 = 0).
         launch_prep(st, G, xh, xp, xTp, halt);
         launch_project(st, G, ang, waves, xp, xTp, b, nullptr, 0, nullptr, rpd, pf, seg, pord, halt);
         launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
         launch_backproject(st, G, ang, rpd, gv, nullptr, nullptr, halt);
         int nzh = 0;
         if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
-        launch_scalar(st, OP_BETA, sc, tr, nullptr, 0, nullptr, 0);
-        launch_update_p(st, n, z, p, gv, sc, pgp, halt);
-        launch_prep(st, G, p, xp, xTp, halt);
-        launch_project(st, G, ang, waves, xp, xTp, nullptr, nullptr, 0, rp, nullptr, nullptr, seg, pord,
-                       halt);
-        launch_backproject(st, G, ang, rp, h, p, pph, halt);
-        launch_scalar(st, OP_ALPHA0, sc, tr, pph, nph, pgp, ngp);
-        launch_update_x(st, n, xh, p, x, sc, halt);
+        launch_prep(st, G, z, xp, xTp, halt);
+        launch_project(st, G, ang, waves, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, pf, seg, pord,
+                       halt, q, w);                                                // w = R z_0
+        launch_update_pq_beta(st, n, m, z, p, gv, w, q, sc, tr, pf, nf, pgp, pqq);   // p_0, q
+        launch_update_x_alpha(st, n, xh, p, x, sc, tr, pqq, nqq, pgp, ngp, OP_ALPHA0);
         if (want_se) se_of_x(se_body + cap + 1, nullptr, halt);                      // SE(x_1)
         if ((rc = check_launch(c))) return rc;
     }
@@ -1735,17 +1740,17 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     const int snap_count = snap ? trace->g_snap_count : 0;
     // One loop body (steps 10-14); every launch reads device state only, so
     // the body can be replayed from a captured graph.
-    // r = R x - b goes to the float64 sinogram rpd, R p to the float32 rp
-    auto project = [&](const float* bb, double* parts) {
+    // r = R x - b goes to the float64 sinogram rpd with the f partials in pf;
+    // w = R z to the float64 w with the partials of w^T q in pf
+    auto project = [&](const float* bb) {
         ProfScope ps(c, SP_PROF_PROJECT);
-        launch_project(st, G, ang, waves, xp, xTp, bb, nullptr, 0, bb ? nullptr : rp, bb ? rpd : nullptr,
-                       parts, seg, pord, halt);
+        if (bb) launch_project(st, G, ang, waves, xp, xTp, bb, nullptr, 0, nullptr, rpd, pf, seg, pord, halt);
+        else launch_project(st, G, ang, waves, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, pf, seg, pord,
+                            halt, q, w);
     };
-    auto backproject = [&](float* out, const double* dotv, double* parts,
-                           const ScalarRide& ride) {
+    auto backproject = [&](float* out, const ScalarRide& ride) {
         ProfScope ps(c, SP_PROF_BACKPROJECT);
-        if (dotv) launch_backproject(st, G, ang, rp, out, dotv, parts, halt, ride);
-        else launch_backproject(st, G, ang, rpd, out, dotv, parts, halt, ride);
+        launch_backproject(st, G, ang, rpd, out, nullptr, nullptr, halt, ride);
     };
     // g = R^T r also carries f(x_{k+1/2}) (and the S_TV step norm when K > 0)
     ScalarRide ride_f;
@@ -1765,19 +1770,18 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         } else {
             launch_copy(st, n, x, xh, halt);
         }
-        // U_PCG(x_{k+1/2}, p_{k-1}, h_{k-1})
+        // U_PCG(x_{k+1/2}, p_{k-1}, h_{k-1}), h_{k-1} carried as q = R p_{k-1}
         launch_prep(st, G, xh, xp, xTp, halt);
-        project(b, pf);                                                           // r = R x - b
-        backproject(gv, nullptr, nullptr, ride_f);                    // g = R^T r, f(x_{k+1/2})
+        project(b);                                                               // r = R x - b
+        backproject(gv, ride_f);                                      // g = R^T r, f(x_{k+1/2})
         if (snap) launch_snap(st, n, gv, snap, snap_count, sc);
         int nz = 0;
-        int r2 = enqueue_precond(c, pc, gv, z, h, pzh, nz, true);                    // z = M g
+        int r2 = enqueue_precond(c, pc, gv, z, nullptr, pzh, nz, true);              // z = M g
         if (r2) return r2;
-        launch_update_p_beta(st, n, z, p, gv, sc, tr, pzh, nz, pgp);       // beta; p = -z + beta p
-        launch_prep(st, G, p, xp, xTp, halt);
-        project(nullptr, nullptr);
-        backproject(h, p, pph, ScalarRide{});                                     // h = A p
-        launch_update_x_alpha(st, n, xh, p, x, sc, tr, pph, nph, pgp, ngp, OP_ALPHA);  // alpha; x += alpha p
+        launch_prep(st, G, z, xp, xTp, halt);
+        project(nullptr);                                              // w = R z, z^T h = w^T q
+        launch_update_pq_beta(st, n, m, z, p, gv, w, q, sc, tr, pf, nf, pgp, pqq);  // beta; p, q
+        launch_update_x_alpha(st, n, xh, p, x, sc, tr, pqq, nqq, pgp, ngp, OP_ALPHA);  // alpha; x += alpha p
         if (want_se) se_of_x(nullptr, se_body, halt);                             // SE(x_{k+1})
         return check_launch(c);
     };
@@ -2358,7 +2362,10 @@ struct StateHeader {
 };
 constexpr char STATE_MAGIC[8] = {'S', 'P', 'S', 'T', 'A', 'T', 'E', '1'};
 
-int64_t state_bytes(int64_t n) { return (int64_t)sizeof(StateHeader) + n * (3 * 8 + 4); }
+// Header, then x_k, x_{k-1/2}, p_{k-1} (n float64 each) and q = R p_{k-1}
+// (m = nA nB float64).
+int64_t state_bytes(int64_t n, int64_t m) { return (int64_t)sizeof(StateHeader) + n * 3 * 8 + m * 8; }
+constexpr int32_t STATE_VERSION = 2;
 }  // namespace
 
 int sp_state_save(sp_ctx* c, void* host_blob, int64_t* bytes) {
@@ -2368,7 +2375,8 @@ int sp_state_save(sp_ctx* c, void* host_blob, int64_t* bytes) {
     HIP_TRY(c, hipSetDevice(c->device));
     const sp_ctx::SolverState& S = c->st;
     const int64_t n = (int64_t)S.geom.rows * S.geom.cols;
-    const int64_t need = state_bytes(n);
+    const int64_t m = (int64_t)S.geom.n_angles * S.geom.n_bins;
+    const int64_t need = state_bytes(n, m);
     if (!host_blob) {
         *bytes = need;
         return SP_OK;
@@ -2378,7 +2386,7 @@ int sp_state_save(sp_ctx* c, void* host_blob, int64_t* bytes) {
     if (rc) return rc;
     StateHeader hd{};
     std::memcpy(hd.magic, STATE_MAGIC, 8);
-    hd.version = 1;
+    hd.version = STATE_VERSION;
     hd.scalars_bytes = (int32_t)sizeof(Scalars);
     hd.geom = S.geom;
     hd.K = S.K;
@@ -2395,7 +2403,7 @@ int sp_state_save(sp_ctx* c, void* host_blob, int64_t* bytes) {
     HIP_TRY(c, hipMemcpyAsync(v, c->vx.ptr, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(v + n * 8, c->vxh.ptr, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(v + 2 * n * 8, c->vp.ptr, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(v + 3 * n * 8, c->vh.ptr, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(v + 3 * n * 8, c->vq.ptr, (size_t)m * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     std::memcpy(out, &hd, sizeof hd);
     *bytes = need;
@@ -2408,7 +2416,7 @@ int sp_state_load(sp_ctx* c, const void* host_blob, int64_t bytes) {
         return fail(c, SP_ERR_ARG, "sp_state_load: blob too short");
     StateHeader hd;
     std::memcpy(&hd, host_blob, sizeof hd);
-    if (std::memcmp(hd.magic, STATE_MAGIC, 8) != 0 || hd.version != 1 ||
+    if (std::memcmp(hd.magic, STATE_MAGIC, 8) != 0 || hd.version != STATE_VERSION ||
         hd.scalars_bytes != (int32_t)sizeof(Scalars))
         return fail(c, SP_ERR_ARG, "sp_state_load: not a state blob of this library version");
     HIP_TRY(c, hipSetDevice(c->device));
@@ -2416,7 +2424,8 @@ int sp_state_load(sp_ctx* c, const void* host_blob, int64_t bytes) {
     if (rc) return rc;
     if ((rc = setup_geometry(c, &hd.geom))) return rc;
     const int64_t n = (int64_t)hd.geom.rows * hd.geom.cols;
-    if (hd.n != n || bytes < state_bytes(n)) return fail(c, SP_ERR_ARG, "sp_state_load: blob size mismatch");
+    const int64_t m = (int64_t)hd.geom.n_angles * hd.geom.n_bins;
+    if (hd.n != n || bytes < state_bytes(n, m)) return fail(c, SP_ERR_ARG, "sp_state_load: blob size mismatch");
     c->st.ok = false;
     if ((rc = ensure_vectors(c, (size_t)n))) return rc;
     if ((rc = ensure_partials(c))) return rc;
@@ -2426,7 +2435,7 @@ int sp_state_load(sp_ctx* c, const void* host_blob, int64_t bytes) {
     HIP_TRY(c, hipMemcpyAsync(c->vx.ptr, v, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->vxh.ptr, v + n * 8, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->vp.ptr, v + 2 * n * 8, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->vh.ptr, v + 3 * n * 8, (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->vq.ptr, v + 3 * n * 8, (size_t)m * 8, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     sp_ctx::SolverState& S = c->st;
     S.geom = hd.geom;
@@ -2560,18 +2569,17 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     // Algorithm 3, steps 1-9, every slice in each launch
     const ItemTable tprep = table(c, BS_PREP), tproj = table(c, BS_PROJECT),
                     tbp = table(c, BS_BACKPROJECT), tvec = table(c, BS_VEC), ttv = table(c, BS_TV),
-                    tone = table(c, BS_SLICE, 0, 0),
+                    tone = table(c, BS_SLICE, 0, 0), tpq = table(c, BS_PQ),
                     tcomb = table(c, BS_PROJ_COMB, B.order[BS_PROJECT], 0);
     launch_prep_b(st, sl, tprep, BV_XH);
     launch_project_b(st, sl, tproj, tcomb, true);
     launch_scalar_b(st, sl, tone, OP_F0);
-    launch_backproject_b(st, sl, tbp, B.nbmax, false, B.bp_px);
+    launch_backproject_b(st, sl, tbp, B.nbmax, B.bp_px);
     batch_precond(c, mu, rho);
+    launch_prep_b(st, sl, tprep, BV_Z);
+    launch_project_b(st, sl, tproj, tcomb, false);                // w = R z
     launch_scalar_b(st, sl, tone, OP_BETA);
-    launch_update_p_b(st, sl, tvec);
-    launch_prep_b(st, sl, tprep, BV_P);
-    launch_project_b(st, sl, tproj, tcomb, false);
-    launch_backproject_b(st, sl, tbp, B.nbmax, true, B.bp_px);
+    launch_update_pq_b(st, sl, tpq);                             // p = -z, q = R p = -w
     launch_scalar_b(st, sl, tone, OP_ALPHA0);
     launch_update_x_b(st, sl, tvec);
     if ((rc = check_launch(c))) return rc;
@@ -2595,13 +2603,12 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         launch_prep_b(st, sl, tprep, BV_XH);
         launch_project_b(st, sl, tproj, tcomb, true);
         launch_scalar_b(st, sl, tone, OP_F);
-        launch_backproject_b(st, sl, tbp, B.nbmax, false, B.bp_px);
+        launch_backproject_b(st, sl, tbp, B.nbmax, B.bp_px);
         batch_precond(c, mu, rho);
+        launch_prep_b(st, sl, tprep, BV_Z);
+        launch_project_b(st, sl, tproj, tcomb, false);            // w = R z, (R z)^T q
         launch_scalar_b(st, sl, tone, OP_BETA);
-        launch_update_p_b(st, sl, tvec);
-        launch_prep_b(st, sl, tprep, BV_P);
-        launch_project_b(st, sl, tproj, tcomb, false);
-        launch_backproject_b(st, sl, tbp, B.nbmax, true, B.bp_px);
+        launch_update_pq_b(st, sl, tpq);
         launch_scalar_b(st, sl, tone, OP_ALPHA);
         launch_update_x_b(st, sl, tvec);
     };

@@ -2,8 +2,14 @@
 // Algorithm 2 (U_PCG):  beta = z^T h / p^T h,  p <- -z + beta p,
 // alpha = -g^T p / p^T h,  x <- x + alpha p.
 //
-// The iterate x, x_{k+1/2} and the direction p are float64 vectors; g, z and
-// h are float32.  Dot products are float64 partial sums per workgroup (fixed
+// h = A p = R^T R p enters Algorithm 2 only through the two dot products
+// z^T h = (R z)^T (R p) and p^T h = ||R p||^2, so the solvers never form it:
+// they keep q = R p (nA x nB rays, float64) by the direction's own recurrence
+// q <- -R z + beta q, which costs one projection of z per loop body in place
+// of a projection and a backprojection of p.
+//
+// The iterate x, x_{k+1/2}, the direction p and q are float64 vectors; g and z
+// are float32.  Dot products are float64 partial sums per workgroup (fixed
 // order); a single
 // workgroup (k_scalar) sums them and updates the device-resident scalars, so a
 // loop body needs no host synchronisation and can be captured in a graph.
@@ -42,62 +48,72 @@ void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* p
     hipLaunchKernelGGL(k_dot, dim3(vec_blocks(n)), dim3(256), 0, st, n, a, b, partials, halt);
 }
 
-// p <- -z + beta p, partials of g^T p (new p).  Virtual block bx of a grid of
-// gx blocks (grid-stride over n).
-__device__ __forceinline__ void update_p_body(int n, const float* __restrict__ z,
-                                              double* __restrict__ p, const float* __restrict__ g,
-                                              double beta, double* __restrict__ partials, int bx,
-                                              int gx) {
+// Virtual block bx of vec_blocks(max(n, m)):
+//   bx < vec_blocks(n): p <- -z + beta p over its grid-stride share of the n
+//     pixels, with the partial of g^T p (new p) in pgp[bx];
+//   bx < vec_blocks(m): q <- -w + beta q over its share of the m rays
+//     (w = R z, q = R p), with the partial of q^T q in pqq[bx].
+// The first direction (no previous p) is p = -z, q = -w.
+__device__ __forceinline__ void update_pq_body(int n, int m, const float* __restrict__ z,
+                                               double* __restrict__ p, const float* __restrict__ g,
+                                               const double* __restrict__ w,
+                                               double* __restrict__ q, double beta, bool first,
+                                               double* __restrict__ pgp, double* __restrict__ pqq,
+                                               int bx) {
     __shared__ double red[4];
-    double acc = 0.0;
-    for (int q = bx * 256 + threadIdx.x; q < n; q += gx * 256) {
-        const double v = fma(beta, p[q], -(double)z[q]);
-        p[q] = v;
-        acc += (double)g[q] * v;
+    const int gp = vec_blocks_dev(n), gq = vec_blocks_dev(m);
+    if (bx < gp) {
+        double acc = 0.0;
+        for (int i = bx * 256 + threadIdx.x; i < n; i += gp * 256) {
+            const double v = first ? -(double)z[i] : fma(beta, p[i], -(double)z[i]);
+            p[i] = v;
+            acc += (double)g[i] * v;
+        }
+        const double tot = block_sum(acc, red);
+        if (threadIdx.x == 0) pgp[bx] = tot;
     }
-    const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[bx] = tot;
+    if (bx < gq) {
+        double acc = 0.0;
+        for (int i = bx * 256 + threadIdx.x; i < m; i += gq * 256) {
+            const double v = first ? -w[i] : fma(beta, q[i], -w[i]);
+            q[i] = v;
+            acc += v * v;
+        }
+        const double tot = block_sum(acc, red);
+        if (threadIdx.x == 0) pqq[bx] = tot;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_update_p(int n, const float* __restrict__ z,
-                                                  double* __restrict__ p,
-                                                  const float* __restrict__ g,
-                                                  const Scalars* __restrict__ sc,
-                                                  double* __restrict__ partials,
-                                                  const int* __restrict__ halt) {
-    if (halt && *halt) return;
-    update_p_body(n, z, p, g, sc->beta, partials, blockIdx.x, gridDim.x);
-}
+int pq_blocks(int n, int m) { return vec_blocks(n > m ? n : m); }
 
-void launch_update_p(hipStream_t st, int n, const float* z, double* p, const float* g,
-                     const Scalars* sc, double* partials, const int* halt) {
-    hipLaunchKernelGGL(k_update_p, dim3(vec_blocks(n)), dim3(256), 0, st, n, z, p, g, sc, partials,
-                       halt);
-}
-
-// The beta step folded into the update: every workgroup sums the z^T h
-// partials in the same fixed order, so all use the beta that workgroup 0
-// commits to the scalars (and trace).  A non-finite beta halts without an
+// The beta step folded into the update: every workgroup sums the (R z)^T q
+// partials (pdot) in the same fixed order, so all use the beta that workgroup
+// 0 commits to the scalars (and trace).  A non-finite beta halts without an
 // update, as the separate scalar step would.
-__global__ __launch_bounds__(256) void k_update_p_beta(int n, const float* __restrict__ z,
-                                                       double* __restrict__ p,
-                                                       const float* __restrict__ g,
-                                                       Scalars* __restrict__ sc, TraceDev tr,
-                                                       const double* __restrict__ pzh, int nz,
-                                                       double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_update_pq_beta(int n, int m, const float* __restrict__ z,
+                                                        double* __restrict__ p,
+                                                        const float* __restrict__ g,
+                                                        const double* __restrict__ w,
+                                                        double* __restrict__ q,
+                                                        Scalars* __restrict__ sc, TraceDev tr,
+                                                        const double* __restrict__ pdot, int ndot,
+                                                        double* __restrict__ pgp,
+                                                        double* __restrict__ pqq) {
     if (sc->halt) return;
     __shared__ double red[4];
-    const double A = pzh ? reduce_partials(pzh, nz, red) : 0.0;
+    const double A = reduce_partials(pdot, ndot, red);
     const double beta = beta_from(sc, A);
+    const bool first = sc->first != 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) scalar_commit(OP_BETA, sc, tr, A, 0.0);
     if (!finite(beta)) return;
-    update_p_body(n, z, p, g, beta, partials, blockIdx.x, gridDim.x);
+    update_pq_body(n, m, z, p, g, w, q, beta, first, pgp, pqq, blockIdx.x);
 }
 
-void launch_update_p_beta(hipStream_t st, int n, const float* z, double* p, const float* g,
-                          Scalars* sc, TraceDev tr, const double* pzh, int nz, double* partials) {
-    hipLaunchKernelGGL(k_update_p_beta, dim3(vec_blocks(n)), dim3(256), 0, st, n, z, p, g, sc, tr,
-                       pzh, nz, partials);
+void launch_update_pq_beta(hipStream_t st, int n, int m, const float* z, double* p, const float* g,
+                           const double* w, double* q, Scalars* sc, TraceDev tr, const double* pdot,
+                           int ndot, double* pgp, double* pqq) {
+    hipLaunchKernelGGL(k_update_pq_beta, dim3(pq_blocks(n, m)), dim3(256), 0, st, n, m, z, p, g, w, q,
+                       sc, tr, pdot, ndot, pgp, pqq);
 }
 
 // x <- xh + alpha p
@@ -123,7 +139,7 @@ void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, d
 }
 
 // The alpha step (op OP_ALPHA or OP_ALPHA0) folded into the update: every
-// workgroup sums the p^T h and g^T p partials in the same order and takes the
+// workgroup sums the p^T h (= q^T q) and g^T p partials in the same order and takes the
 // same halt decision (breakdown, non-finite) that workgroup 0 commits; on a
 // halt no workgroup updates x.  (Workgroups that start after workgroup 0 has
 // committed a halt return at the entry check; they would not have updated x
@@ -268,12 +284,14 @@ __global__ __launch_bounds__(256) void kb_init(const SliceDev* __restrict__ sl, 
     });
 }
 
-__global__ __launch_bounds__(256) void kb_update_p(const SliceDev* __restrict__ sl, ItemTable t) {
+// The p and q updates with the beta that OP_BETA committed.
+__global__ __launch_bounds__(256) void kb_update_pq(const SliceDev* __restrict__ sl, ItemTable t) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
-        if (gmem(S.sc)->halt) return;
-        update_p_body(S.n, gmem(S.z), gmem(S.p), gmem(S.g), gmem(S.sc)->beta, gmem(S.pgp), lin,
-                      vec_blocks_dev(S.n));
+        const Scalars* sc = gmem(S.sc);
+        if (sc->halt) return;
+        update_pq_body(S.n, S.m, gmem(S.z), gmem(S.p), gmem(S.g), gmem(S.w), gmem(S.q), sc->beta,
+                       sc->first != 0, gmem(S.pgp), gmem(S.pqq), lin);
     });
 }
 
@@ -286,24 +304,15 @@ __global__ __launch_bounds__(256) void kb_update_x(const SliceDev* __restrict__ 
     });
 }
 
-// M = I: z = g and the partials of z^T h.
-__global__ __launch_bounds__(256) void kb_dot_zh(const SliceDev* __restrict__ sl, ItemTable t) {
-    __shared__ double red[4];
+// M = I: z = g.
+__global__ __launch_bounds__(256) void kb_copy_gz(const SliceDev* __restrict__ sl, ItemTable t) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const int gx = vec_blocks_dev(S.n);
         const float* g = gmem(S.g);
-        const float* h = gmem(S.h);
         float* z = gmem(S.z);
-        double acc = 0.0;
-        for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) {
-            const float v = g[q];
-            z[q] = v;
-            acc += (double)v * (double)h[q];
-        }
-        const double tot = block_sum(acc, red);
-        if (threadIdx.x == 0) gmem(S.pzh)[lin] = tot;
+        for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) z[q] = g[q];
     });
 }
 
@@ -316,9 +325,9 @@ __global__ __launch_bounds__(256) void kb_scalar(const SliceDev* __restrict__ sl
         switch (op) {
         case OP_F0:
         case OP_F: scalar_body(op, sc, tr, gmem(S.pf), S.nf, nullptr, 0); break;
-        case OP_BETA: scalar_body(op, sc, tr, gmem(S.pzh), S.nzh, nullptr, 0); break;
+        case OP_BETA: scalar_body(op, sc, tr, gmem(S.pf), S.nf, nullptr, 0); break;
         case OP_ALPHA0:
-        case OP_ALPHA: scalar_body(op, sc, tr, gmem(S.pph), S.nph, gmem(S.pgp), S.ngp); break;
+        case OP_ALPHA: scalar_body(op, sc, tr, gmem(S.pqq), S.nqq, gmem(S.pgp), S.ngp); break;
         case OP_SNORM: scalar_body(op, sc, tr, gmem(S.pts), S.ntv, nullptr, 0); break;
         case OP_EPS: scalar_body(op, sc, tr, nullptr, 0, nullptr, 0); break;
         default: break;
@@ -332,14 +341,14 @@ void launch_copy_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, int
 void launch_init_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
     hipLaunchKernelGGL(kb_init, dim3(t.grid), dim3(256), 0, st, sl, t);
 }
-void launch_update_p_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
-    hipLaunchKernelGGL(kb_update_p, dim3(t.grid), dim3(256), 0, st, sl, t);
+void launch_update_pq_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
+    hipLaunchKernelGGL(kb_update_pq, dim3(t.grid), dim3(256), 0, st, sl, t);
 }
 void launch_update_x_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
     hipLaunchKernelGGL(kb_update_x, dim3(t.grid), dim3(256), 0, st, sl, t);
 }
-void launch_dot_zh_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
-    hipLaunchKernelGGL(kb_dot_zh, dim3(t.grid), dim3(256), 0, st, sl, t);
+void launch_copy_gz_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
+    hipLaunchKernelGGL(kb_copy_gz, dim3(t.grid), dim3(256), 0, st, sl, t);
 }
 void launch_scalar_b(hipStream_t st, const SliceDev* sl, ItemTable t, int op) {
     hipLaunchKernelGGL(kb_scalar, dim3(t.grid), dim3(256), 0, st, sl, t, op);

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__
     rows_inv_body(F, z, dotv, partials, buf, blockIdx.x);
 }
 
-// Batched: z = M g per slice, partials of z^T h into pzh.
+// Batched: z = M g per slice.
 __global__ __launch_bounds__(512) void kb_rows_fwd(const SliceDev* __restrict__ sl, ItemTable t) {
     extern __shared__ double2 buf[];
     for_items(t, [&](int s, int lin) {
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void kb_rows_inv(const SliceDev* __restrict__ 
         FFTPlan F = S.F;
         F.S = gmem(F.S);
         F.tw = cmem(F.tw);
-        rows_inv_body(F, gmem(S.z), gmem(S.h), gmem(S.pzh), buf, lin);
+        rows_inv_body(F, gmem(S.z), nullptr, nullptr, buf, lin);
     });
 }
 

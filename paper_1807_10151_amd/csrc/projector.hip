@@ -95,7 +95,8 @@ __global__ __launch_bounds__(256) void kb_prep(const SliceDev* __restrict__ sl, 
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = (G.cols + 31) / 32;
-        prep_body(G, batch_vec(S, which), gmem(S.xp), gmem(S.xTp), lin % gx, lin / gx);
+        if (which == BV_Z) prep_body(G, (const float*)gmem(S.z), gmem(S.xp), gmem(S.xTp), lin % gx, lin / gx);
+        else prep_body(G, (const double*)batch_vec(S, which), gmem(S.xp), gmem(S.xTp), lin % gx, lin / gx);
     });
 }
 
@@ -335,34 +336,41 @@ __device__ __forceinline__ double ray_split(const GeomDev& G, const AngleDev& A,
     return acc;
 }
 
-// Stores ray (row a, bin k): (R x)_{a,k}, or the residual r = R x - b when
+// Stores ray (row a, bin k): v = (R x)_{a,k}, or the residual r = R x - b when
 // b != nullptr, with the float64 sum of r^2 over the workgroup in
 // partials[pidx].  The value goes, rounded to float32, to out[a*out_pitch + k];
 // the padded sinograms that feed R^T get it times the angle's wmax (see
 // bp_class), rounded to float32 in outp[a*pitchB + PAD + k] and unrounded in
-// the float64 outpd (each nullable).
+// the float64 outpd (each nullable).  With dq (and no b), the workgroup's sum
+// of v dq[a*nB + k] goes to partials[pidx] instead; wout (nullable) receives v
+// unrounded at a*nB + k.
 __device__ __forceinline__ void project_store(const GeomDev& G, int a, double wmax, int k,
                                               bool valid, double acc,
                                               const float* __restrict__ b, float* __restrict__ out,
                                               int out_pitch, float* __restrict__ outp,
                                               double* __restrict__ outpd,
-                                              double* __restrict__ partials, int pidx) {
+                                              double* __restrict__ partials, int pidx,
+                                              const double* __restrict__ dq,
+                                              double* __restrict__ wout) {
     __shared__ double red[4];
     double r2 = 0.0;
     if (valid) {
         double v;
+        const size_t i = (size_t)a * G.nB + k;
         if (b) {
-            v = fma(acc, G.pixel, -(double)b[(size_t)a * G.nB + k]);
+            v = fma(acc, G.pixel, -(double)b[i]);
             r2 = v * v;
         } else {
             v = acc * G.pixel;
+            if (dq) r2 = v * dq[i];
         }
         if (out) out[(size_t)a * out_pitch + k] = (float)v;
+        if (wout) wout[i] = v;
         const double vs = v * wmax;
         if (outp) outp[(size_t)a * G.pitchB + PAD + k] = (float)vs;
         if (outpd) outpd[(size_t)a * G.pitchB + PAD + k] = vs;
     }
-    if (b) {
+    if (b || dq) {
         const double tot = block_sum(r2, red);
         if (threadIdx.x == 0) partials[pidx] = tot;
     }
@@ -384,7 +392,9 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
                                              int out_pitch, float* __restrict__ outp,
                                              double* __restrict__ outpd,
                                              double* __restrict__ partials,
-                                             double* __restrict__ seg, int wg, int part) {
+                                             double* __restrict__ seg, int wg, int part,
+                                             const double* __restrict__ dq = nullptr,
+                                             double* __restrict__ wout = nullptr) {
     const int wi = 4 * wg + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool wvalid = wi < G.nwaves;
     const WaveDev W = waves[wvalid ? wi : 0];
@@ -411,7 +421,8 @@ __device__ __forceinline__ void project_body(const GeomDev& G, const AngleDev* _
         if (valid) seg[((size_t)part * G.nA + ai) * G.nB + k] = acc;
         return;
     }
-    project_store(G, A.row, A.wmax, k, valid, acc, b, out, out_pitch, outp, outpd, partials, wg);
+    project_store(G, A.row, A.wmax, k, valid, acc, b, out, out_pitch, outp, outpd, partials, wg, dq,
+                  wout);
 }
 
 // Sum of the parts of the rays of combine block (bx, by): angle bx of the
@@ -424,7 +435,8 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
                                                   float* __restrict__ outp,
                                                   double* __restrict__ outpd,
                                                   double* __restrict__ partials, int bx, int by,
-                                                  int gx) {
+                                                  int gx, const double* __restrict__ dq = nullptr,
+                                                  double* __restrict__ wout = nullptr) {
     const int a = ang[bx].row;
     const double wmax = ang[bx].wmax;
     const int k = by * 256 + threadIdx.x;
@@ -436,7 +448,7 @@ __device__ __forceinline__ void project_comb_body(const GeomDev& G, const AngleD
         for (int j = 0; j < G.parts; ++j) acc += v[j * stride];
     }
     project_store(G, a, wmax, k, valid, acc, b, out, out_pitch, outp, outpd, partials,
-                  by * gx + bx);
+                  by * gx + bx, dq, wout);
 }
 
 __global__ __launch_bounds__(256, 8) void k_project(GeomDev G, const AngleDev* __restrict__ ang,
@@ -449,10 +461,12 @@ __global__ __launch_bounds__(256, 8) void k_project(GeomDev G, const AngleDev* _
                                                  double* __restrict__ outpd,
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ ord,
-                                                 const int* __restrict__ halt) {
+                                                 const int* __restrict__ halt,
+                                                 const double* __restrict__ dq,
+                                                 double* __restrict__ wout) {
     if (halt && *halt) return;
     project_body(G, ang, waves, xp, xTp, b, out, out_pitch, outp, outpd, partials, nullptr,
-                 ord[blockIdx.x], 0);
+                 ord[blockIdx.x], 0, dq, wout);
 }
 
 // grid (ray workgroups, parts): blockIdx.y is the part, so the parts run in order.
@@ -475,14 +489,17 @@ __global__ __launch_bounds__(256) void k_project_comb(GeomDev G, const AngleDev*
                                                       float* __restrict__ outp,
                                                       double* __restrict__ outpd,
                                                       double* __restrict__ partials,
-                                                      const int* __restrict__ halt) {
+                                                      const int* __restrict__ halt,
+                                                      const double* __restrict__ dq,
+                                                      double* __restrict__ wout) {
     if (halt && *halt) return;
     project_comb_body(G, ang, seg, b, out, out_pitch, outp, outpd, partials, blockIdx.x,
-                      blockIdx.y, gridDim.x);
+                      blockIdx.y, gridDim.x, dq, wout);
 }
 
-// residual: rpd = R xh - b (float64) with f partials; else rp = R p.  Item
-// lin = part * G.nwg + i runs ray workgroup S.pord[i].
+// residual: rpd = R xh - b (float64) with f partials; else w = R z (float64)
+// with the partials of w^T q, both into pf.  Item lin = part * G.nwg + i runs
+// ray workgroup S.pord[i].
 __global__ __launch_bounds__(256, 8) void kb_project(const SliceDev* __restrict__ sl, ItemTable t,
                                                   int residual) {
     for_items(t, [&](int s, int lin) {
@@ -498,7 +515,8 @@ __global__ __launch_bounds__(256, 8) void kb_project(const SliceDev* __restrict_
                          0, nullptr, gmem(S.rpd), gmem(S.pf), nullptr, cmem(S.pord)[lin], 0);
         } else {
             project_body(G, cmem(S.ang), cmem(S.pwave), gmem(S.xp), gmem(S.xTp), nullptr, nullptr,
-                         0, gmem(S.rp), nullptr, nullptr, nullptr, cmem(S.pord)[lin], 0);
+                         0, nullptr, nullptr, gmem(S.pf), nullptr, cmem(S.pord)[lin], 0, gmem(S.q),
+                         gmem(S.w));
         }
     });
 }
@@ -515,8 +533,8 @@ __global__ __launch_bounds__(256) void kb_project_comb(const SliceDev* __restric
             project_comb_body(G, cmem(S.ang), gmem(S.seg), gmem(S.b), nullptr, 0, nullptr,
                               gmem(S.rpd), gmem(S.pf), lin % gx, lin / gx, gx);
         else
-            project_comb_body(G, cmem(S.ang), gmem(S.seg), nullptr, nullptr, 0, gmem(S.rp), nullptr,
-                              nullptr, lin % gx, lin / gx, gx);
+            project_comb_body(G, cmem(S.ang), gmem(S.seg), nullptr, nullptr, 0, nullptr, nullptr,
+                              gmem(S.pf), lin % gx, lin / gx, gx, gmem(S.q), gmem(S.w));
     });
 }
 
@@ -531,16 +549,17 @@ void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const WaveDev* waves,
                     const double* xp, const double* xTp, const float* b, float* out, int out_pitch,
                     float* outp, double* outpd, double* partials, double* seg, const int* ord,
-                    const int* halt) {
+                    const int* halt, const double* dq, double* wout) {
     if (G.parts > 1) {
         hipLaunchKernelGGL(k_project_part, dim3(G.nwg, G.parts), dim3(256), 0, st, G, ang, waves, xp,
                            xTp, seg, ord, halt);
         hipLaunchKernelGGL(k_project_comb, dim3(G.nA, (G.nB + 255) / 256), dim3(256), 0, st, G,
-                           ang, (const double*)seg, b, out, out_pitch, outp, outpd, partials, halt);
+                           ang, (const double*)seg, b, out, out_pitch, outp, outpd, partials, halt,
+                           dq, wout);
         return;
     }
     hipLaunchKernelGGL(k_project, dim3(G.nwg), dim3(256), 0, st, G, ang, waves, xp, xTp, b, out,
-                       out_pitch, outp, outpd, partials, ord, halt);
+                       out_pitch, outp, outpd, partials, ord, halt, dq, wout);
 }
 
 // Padded copy of a caller's sinogram for R^T, each row times its angle's wmax
@@ -712,45 +731,33 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
     }
 }
 
-// TY = float: h = R^T rp (rp = R p) with the partials of h^T p; TY = double:
 // g = R^T rpd from the float64 residual.  NB is the largest candidate count of
 // the batch (extra candidates weigh exactly 0).
-template <int NB, class TY, int PX>
+template <int NB, int PX>
 __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, ItemTable t) {
-    constexpr bool normal = sizeof(TY) == sizeof(float);
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
         const int gx = (G.cols + 8 * PX - 1) / (8 * PX);
-        const TY* yp;
-        if constexpr (normal) yp = gmem(S.rp);
-        else yp = gmem(S.rpd);
-        backproject_body<NB, TY, PX>(G, cmem(S.ang), yp, gmem(normal ? S.h : S.g),
-                                     normal ? gmem(S.p) : nullptr, normal ? gmem(S.pph) : nullptr,
-                                     lin % gx, lin / gx);
+        backproject_body<NB, double, PX>(G, cmem(S.ang), gmem(S.rpd), gmem(S.g), nullptr, nullptr,
+                                         lin % gx, lin / gx);
     });
 }
 
-template <class TY, int PX>
+template <int PX>
 void launch_bp_b_px(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax) {
     switch (nbmax) {
-    case 1: hipLaunchKernelGGL((kb_backproject<1, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
-    case 2: hipLaunchKernelGGL((kb_backproject<2, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
-    case 3: hipLaunchKernelGGL((kb_backproject<3, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
-    default: hipLaunchKernelGGL((kb_backproject<4, TY, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
+    case 1: hipLaunchKernelGGL((kb_backproject<1, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
+    case 2: hipLaunchKernelGGL((kb_backproject<2, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
+    case 3: hipLaunchKernelGGL((kb_backproject<3, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
+    default: hipLaunchKernelGGL((kb_backproject<4, PX>), dim3(t.grid), dim3(256), 0, st, sl, t); break;
     }
 }
 
-void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal,
-                          int px) {
-    if (normal) {
-        if (px == 4) launch_bp_b_px<float, 4>(st, sl, t, nbmax);
-        else launch_bp_b_px<float, 2>(st, sl, t, nbmax);
-    } else {
-        if (px == 4) launch_bp_b_px<double, 4>(st, sl, t, nbmax);
-        else launch_bp_b_px<double, 2>(st, sl, t, nbmax);
-    }
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int px) {
+    if (px == 4) launch_bp_b_px<4>(st, sl, t, nbmax);
+    else launch_bp_b_px<2>(st, sl, t, nbmax);
 }
 
 template <class TY, int PX>

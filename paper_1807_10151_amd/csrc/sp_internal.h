@@ -182,10 +182,12 @@ void launch_prep(hipStream_t st, const GeomDev& G, const double* x, double* xp, 
 // rounding (its cancellation in R^T r amplifies that rounding).  waves: the
 // device copy of R's wave table (project_waves); ord: the device copy of
 // project_order(G, ...), the ray workgroup each launched workgroup runs.
+// With dq (nA x nB float64, b == nullptr) the partials are those of
+// (R x)^T dq, and wout (nA x nB float64, nullable) receives R x unrounded.
 void launch_project(hipStream_t st, const GeomDev& G, const AngleDev* ang, const WaveDev* waves,
                     const double* xp, const double* xTp, const float* b, float* out, int out_pitch,
                     float* outp, double* outpd, double* partials, double* seg, const int* ord,
-                    const int* halt);
+                    const int* halt, const double* dq = nullptr, double* wout = nullptr);
 // Padded copy of y for R^T with each row scaled by its angle's wmax.
 void launch_pad_sino(hipStream_t st, const GeomDev& G, const AngleDev* ang, const float* y,
                      float* yp);
@@ -289,14 +291,17 @@ void launch_tv_apply_grad(hipStream_t st, int rows, int cols, const double* src,
 int vec_blocks(int n);
 void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* partials,
                 const int* halt);
-void launch_update_p(hipStream_t st, int n, const float* z, double* p, const float* g,
-                     const Scalars* sc, double* partials, const int* halt);
 void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, double* x,
                      const Scalars* sc, const int* halt);
 // Forms with the beta / alpha scalar step folded in (ops OP_BETA, OP_ALPHA or
 // OP_ALPHA0 of launch_scalar): one launch instead of two, same values.
-void launch_update_p_beta(hipStream_t st, int n, const float* z, double* p, const float* g,
-                          Scalars* sc, TraceDev tr, const double* pzh, int nz, double* partials);
+// p <- -z + beta p (partials of g^T p) and q <- -w + beta q over the m rays
+// (partials of q^T q, vec_blocks(m) of them), with the beta step (OP_BETA,
+// (R z)^T q from the ndot partials pdot) folded in; pq_blocks(n, m) workgroups.
+int pq_blocks(int n, int m);
+void launch_update_pq_beta(hipStream_t st, int n, int m, const float* z, double* p, const float* g,
+                           const double* w, double* q, Scalars* sc, TraceDev tr, const double* pdot,
+                           int ndot, double* pgp, double* pqq);
 void launch_update_x_alpha(hipStream_t st, int n, const double* xh, const double* p, double* x,
                            Scalars* sc, TraceDev tr, const double* pph, int nph, const double* pgp,
                            int ngp, int op);
@@ -420,23 +425,23 @@ struct SliceDev {
     const float* b;
     const float* x0;   // nullable: zero start
     double *xh, *x, *p;  // iterate, x_{k+1/2} and search direction (float64)
-    float *h, *g, *z, *tb;
+    float *g, *z, *tb;
+    double *q, *w;      // R p and R z, nA x nB (float64)
     double *xp, *xTp;   // float64 padded copies
-    float* rp;          // padded sinogram (R p)
     double* rpd;        // float64 padded sinogram (residual)
     double* seg;        // R's per-part ray sums, [parts][nA][nB] (G.parts > 1)
     const int* pord;    // R's ray-workgroup order (project_order)
-    double *pf, *pzh, *pgp, *pph, *ptg, *ptt, *pts;
+    double *pf, *pgp, *pqq, *ptg, *ptt, *pts;   // pf: f, then (R z)^T q
     Scalars* sc;
     TraceDev tr;
-    int n, nf, nph, ngp, nzh, ntv;
+    int n, m, nf, ngp, nqq, ntv;   // m = nA nB rays
 };
 
 // Stage selectors of the batched kernels.
-enum BatchVec : int { BV_XH = 0, BV_X = 1, BV_P = 2 };
+enum BatchVec : int { BV_XH = 0, BV_X = 1, BV_P = 2, BV_Z = 3 };   // BV_Z: the float32 z
 enum BatchStage : int {
     BS_PREP = 0, BS_PROJECT, BS_BACKPROJECT, BS_ROWS, BS_COLS, BS_TV, BS_VEC, BS_SLICE, BS_PROJ_COMB,
-    BS_COUNT
+    BS_PQ, BS_COUNT
 };
 struct ItemTable {
     const uint32_t* items;
@@ -476,11 +481,12 @@ __device__ __forceinline__ double* batch_vec(const SliceDev& S, int which) {
 
 // projector.hip
 void launch_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int which);
+// residual: rpd = R xh - b with the f partials in pf; else w = R z (from the
+// prepared z) with the (R z)^T q partials in pf.
 void launch_project_b(hipStream_t st, const SliceDev* sl, ItemTable t, ItemTable tc, bool residual);
 // px: pixels per lane of every slice in the launch (their G.bp_px).
-void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, bool normal,
-                          int px);
-// fft.hip (z = M g; with the partials of z^T h into pzh)
+void launch_backproject_b(hipStream_t st, const SliceDev* sl, ItemTable t, int nbmax, int px);
+// fft.hip (z = M g)
 void launch_precond_b(hipStream_t st, const SliceDev* sl, ItemTable rows, ItemTable cols,
                       size_t lds_rows, size_t lds_cols, double mu, double rho);
 // tv.hip
@@ -491,9 +497,9 @@ void launch_tv_apply_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src,
 // cg.hip
 void launch_copy_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, int dst);
 void launch_init_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // xh = x = x0 (or 0)
-void launch_update_p_b(hipStream_t st, const SliceDev* sl, ItemTable t);
+void launch_update_pq_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // BS_PQ items
 void launch_update_x_b(hipStream_t st, const SliceDev* sl, ItemTable t);
-void launch_dot_zh_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // g -> z copy + z^T h
+void launch_copy_gz_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // M = I: z = g
 void launch_scalar_b(hipStream_t st, const SliceDev* sl, ItemTable t, int op);
 
 enum ScalarOp : int {

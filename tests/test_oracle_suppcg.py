@@ -197,3 +197,48 @@ def test_suppcg_trace_records_schedule():
         assert res.trace["ell"][k] - prev == sum(res.trace["trials"][k])
         prev = res.trace["ell"][k]
     assert max(max(t) for t in res.trace["trials"]) > 1    # rejections happened
+
+
+def _suppcg_ray_form(prob, x0, tvp, n_iter):
+    """Algorithm 3 with h = A p never formed: Algorithm 2 uses h only in
+    z^T h = (R z)^T (R p) and p^T h = ||R p||^2, and R p follows the direction
+    update, R p <- -R z + beta R p.  Test-local, float64, the order of
+    operations of the GPU solvers (which keep q = R p)."""
+    x = np.asarray(x0, dtype=np.float64).ravel()
+    g = prob.RT @ (prob.R @ x - prob.b)
+    z = prob.apply_M(g)
+    p = -z
+    q = -(prob.R @ z)
+    qq = float(q @ q)
+    x = x + (-float(g @ p) / qq) * p
+    ell, xs, betas = 0, [], []
+    for _ in range(n_iter):
+        st = suppcg.s_tv(x.reshape(prob.shape), ell, tvp)
+        ell = st.ell
+        x_half = x + st.s.ravel()
+        g = prob.RT @ (prob.R @ x_half - prob.b)
+        z = prob.apply_M(g)
+        w = prob.R @ z
+        beta = float(w @ q) / qq
+        p = -z + beta * p
+        q = -w + beta * q
+        qq = float(q @ q)
+        x = x_half + (-float(g @ p) / qq) * p
+        xs.append(x_half)
+        betas.append(beta)
+    return xs, betas
+
+
+def test_h_enters_algorithm2_only_through_its_dot_products():
+    # Algorithm 2's h = A p is needed only for beta's numerator z^T h and the
+    # denominator p^T h; carrying R p instead gives the same iterates up to
+    # rounding, with no drift over a superiorized run with rejections
+    g, R, b, prob = tiny_problem(seed=3, shape=(12, 10), A=24, B=17)
+    tvp = suppcg.TVParams(1, 0.7, 3.0)
+    ref = suppcg.suppcg(prob, np.zeros(g.n), tvp, n_iter=30, record_vectors=True)
+    xs, betas = _suppcg_ray_form(prob, np.zeros(g.n), tvp, 30)
+    for k in range(30):
+        xr = ref.trace["x_half_v"][k + 1]
+        assert np.linalg.norm(xs[k] - xr) <= 1e-10 * np.linalg.norm(xr), k
+        assert betas[k] == pytest.approx(ref.trace["beta"][k], rel=1e-8, abs=1e-14)
+    assert sum(sum(t) for t in ref.trace["trials"]) > 30   # trials were rejected
