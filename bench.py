@@ -3,9 +3,10 @@
 Workload: 512x512 image, 720 angles over [0, pi), 725 unit bins; random-ellipse
 phantom (20 ellipses, seed 1) with 0.5% Gaussian noise; K = 1, a = 0.5,
 gamma = 0.5 (first trial step 0.5^k), ramp-Hamming preconditioner
-(mu = 1e-5, rho = 0.8).  One step = one SupPCG iteration (S_TV + U_PCG: two
-projections R, two backprojections R^T, one preconditioner apply, TV work and
-the CG updates).  Prints one JSON line.
+(mu = 1e-5, rho = 0.8).  One step = one SupPCG iteration (S_TV + U_PCG: the
+projections R x_{k+1/2} and R z, one backprojection R^T, one preconditioner
+apply, TV work and the CG updates; U_PCG's h = A p enters through R p, which
+the solver carries).  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu]
 """
@@ -48,18 +49,18 @@ OPS_PER_NNZ = 4
 # named below; re-measure after changing a kernel).  VALU wave-instructions per
 # launch (SQ_INSTS_VALU, 64 lane-operations each) and bytes between L2 and the
 # memory fabric per launch (FETCH_SIZE + WRITE_SIZE, scaled by the counters of
-# a 64 MiB device copy).  R^T: mean of its float32 (R p) and float64
-# (residual) sinogram forms, one of each per loop body.
-COUNTERS = {"measured_at": "kernels of 1d7046e",
-            "valu_instr": {"project": 2.683e7, "backproject": 3.576e7},
-            "traffic_bytes": {"project": 39.96e6, "backproject": 20.78e6}}
+# a 64 MiB device copy).  R^T: its float64 (residual) sinogram form, the one
+# the loop body runs.
+COUNTERS = {"measured_at": "kernels of e21385c",
+            "valu_instr": {"project": 2.696e7, "backproject": 3.273e7},
+            "traffic_bytes": {"project": 43.25e6, "backproject": 25.48e6}}
 # The vector L1's access rate, the limit the gathers of both kernels run into
 # (profiles/memory_pipe_ct512.md, same kernels):
 # TCP_TOTAL_CACHE_ACCESSES per launch and per compute unit and cycle of the
 # kernel's own run (about one access per CU and cycle is the L1's rate; R^T:
-# the mean of its two sinogram forms, as above).
-L1_ACCESS = {"measured_at": "kernels of 1d7046e",
-             "per_launch": {"project": 5.691e7, "backproject": 5.368e7},
+# its float64 form, as above).
+L1_ACCESS = {"measured_at": "kernels of e21385c",
+             "per_launch": {"project": 5.702e7, "backproject": 5.58e7},
              "per_cu_per_cycle": {"project": 1.01, "backproject": 0.84}}
 
 
