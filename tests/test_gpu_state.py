@@ -168,3 +168,41 @@ def test_rejected_call_keeps_the_state(sp, prob):
         sp.sp_suppcg_solve(g, b, None, max_iter=4, resume=True, se_ref=ref, se_axes=(0.0, 3.0), **KW)
     rest = sp.sp_suppcg_solve(g, b, None, max_iter=4, resume=True, **KW)
     assert torch.equal(rest.x_half, straight.x_half)
+
+
+def _blob_vectors(blob, n, m):
+    # layout after the header: x_k, x_{k-1/2}, p_{k-1} (n float64 each), then
+    # q = R p_{k-1} (m float64)
+    head = len(blob) - 3 * n * 8 - m * 8
+    v = np.frombuffer(blob, dtype=np.float64, offset=head)
+    return v[2 * n:3 * n], v[3 * n:3 * n + m]
+
+
+@pytest.mark.parametrize("kw,bodies", [(dict(K=1, a=A, gamma=GAMMA, mu=MU, rho=RHO), 60),
+                                       (dict(KW), 40),
+                                       (dict(K=0, precond="none"), 30)])
+def test_carried_ray_vector_is_projection_of_direction(sp, prob, kw, bodies):
+    # the solver keeps Algorithm 2's h = R^T R p through q = R p, updated by
+    # the direction's recurrence; after many bodies q must still be the
+    # projection of the saved direction p (float64 R of the oracle), with no
+    # drift beyond rounding
+    from oracle import projector as oproj
+    og, _, _ = workload_problem("small64")
+    g, b = prob
+    res = sp.sp_suppcg_solve(g, b, None, max_iter=bodies, graph=True, **kw)
+    assert res.k == bodies + 1
+    p, q = _blob_vectors(sp.sp_state_save(), og.n, og.m)
+    R, _ = oproj.matrix(og)
+    rp = R @ p
+    err = np.linalg.norm(q - rp) / np.linalg.norm(rp)
+    print(f"{kw}: ||q - R p|| / ||R p|| = {err:.2e} after {bodies} bodies", flush=True)
+    assert err <= 1e-9
+
+
+def test_state_blob_size(sp, prob):
+    og, _, _ = workload_problem("small64")
+    g, b = prob
+    sp.sp_suppcg_solve(g, b, None, max_iter=2, **KW)
+    blob = sp.sp_state_save()
+    head = len(blob) - 3 * og.n * 8 - og.m * 8
+    assert 0 < head < 4096 and head % 8 == 0
