@@ -412,7 +412,8 @@ int ensure_partials(sp_ctx* c) {
     if ((rc = ensure(c, c->part_gp, (size_t)vec_blocks(n) * 8))) return rc;
     if ((rc = ensure(c, c->part_g, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
     if ((rc = ensure(c, c->part_t, (size_t)tv_blocks(G.rows, G.cols) * 9 * 8))) return rc;
-    if ((rc = ensure(c, c->part_s, (size_t)tv_blocks(G.rows, G.cols) * 8))) return rc;
+    if ((rc = ensure(c, c->part_s, (size_t)std::max(tv_blocks(G.rows, G.cols), tv_prep_tiles(G.rows, G.cols)) * 8)))
+        return rc;
     if ((rc = ensure(c, c->part_misc, (size_t)vec_blocks(n) * 8))) return rc;
     if ((rc = ensure(c, c->part_se, (size_t)vec_blocks(n) * 16))) return rc;
     if ((rc = ensure(c, c->scal, sizeof(Scalars)))) return rc;
@@ -494,9 +495,12 @@ struct ProfScope {
 // Between two inner steps one launch applies the step and forms the next
 // t_bar; the iterates then alternate between xh and stv_y (and t_bar
 // between vtb and vtb2) so that it never reads what it writes, and the last
-// step lands in xh.  With x aliasing xh the steps run unfused.
+// step lands in xh.  With x aliasing xh the steps run unfused.  With xp the
+// last step also writes R's padded copies of xh to xp / xTp, and the step norm
+// partials are per 32 x 32 tile (tv_prep_tiles).
 void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, bool snorm,
-                 TraceDev tr, int32_t* trials_out, bool ride_snorm = false) {
+                 TraceDev tr, int32_t* trials_out, bool ride_snorm = false, double* xp = nullptr,
+                 double* xTp = nullptr) {
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
     const int* halt = &sc->halt;
@@ -513,7 +517,10 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
         launch_tv_decide(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), nb,
                          dptr<double>(c->part_t), nb, 4, sc, tr, trials_out, halt);
         const bool last = i == K - 1;
-        if (last || !fuse) {
+        if (last && xp) {
+            launch_tv_apply_prep(c->stream, G, src, xh, tb, sc, snorm ? x : nullptr, dptr<double>(c->part_s),
+                                 xp, xTp, halt);
+        } else if (last || !fuse) {
             launch_tv_apply(c->stream, n, src, xh, tb, sc, (last && snorm) ? x : nullptr,
                             dptr<double>(c->part_s), halt);
             src = xh;
@@ -529,7 +536,8 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
         }
     }
     if (snorm && !ride_snorm)
-        launch_scalar(c->stream, OP_SNORM, sc, tr, dptr<double>(c->part_s), nb, nullptr, 0);
+        launch_scalar(c->stream, OP_SNORM, sc, tr, dptr<double>(c->part_s),
+                      xp ? tv_prep_tiles(G.rows, G.cols) : nb, nullptr, 0);
 }
 
 // z = M g with the partial dots z^T dotv (dotv nullable).
@@ -767,6 +775,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         S.ngp = vec_blocks(S.n);
         S.nqq = vec_blocks(S.m);
         S.ntv = tv_blocks(G.rows, G.cols);
+        S.nsn = tv_prep_tiles(G.rows, G.cols);
         Off& o = off[s];
         auto take = [&](size_t bytes) {
             const size_t at = total;
@@ -790,7 +799,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         o.pqq = take((size_t)S.nqq * 8);
         o.ptg = take((size_t)S.ntv * 8);
         o.ptt = take((size_t)S.ntv * 9 * 8);
-        o.pts = take((size_t)S.ntv * 8);
+        o.pts = take((size_t)std::max(S.ntv, S.nsn) * 8);
     }
     if (B.lds_cols > 65536) return fail(c, SP_ERR_ARG, "FFT column tile exceeds the LDS");
     // one R^T tile shape for the whole batch: four pixels per lane when the
@@ -1759,19 +1768,19 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
     ride_f.pf = pf;
     ride_f.nf = nf;
     ride_f.ps = K > 0 ? dptr<double>(c->part_s) : nullptr;
-    ride_f.ns = tv_blocks(G.rows, G.cols);
+    ride_f.ns = tv_prep_tiles(G.rows, G.cols);   // the step norm's partials come from the fused last step
     const bool eps_test = sp->eps > 0.0;
     auto body = [&]() -> int {
         ProfScope ps(c, SP_PROF_ITERATION);
         // step 10: while f(x_{k-1/2}) > eps (the test of the previous body's f)
         if (eps_test) launch_scalar(st, OP_EPS, sc, tr, nullptr, 0, nullptr, 0);
+        // S_TV -> x_{k+1/2} (K = 0: x_{k+1/2} = x_k), written with R's padded copies
         if (K > 0) {
-            enqueue_stv(c, sc, K, x, xh, true, tr, nullptr, true);  // S_TV -> x_{k+1/2}
+            enqueue_stv(c, sc, K, x, xh, true, tr, nullptr, true, xp, xTp);
         } else {
-            launch_copy(st, n, x, xh, halt);
+            launch_tv_apply_prep(st, G, x, xh, nullptr, sc, nullptr, nullptr, xp, xTp, halt);
         }
         // U_PCG(x_{k+1/2}, p_{k-1}, h_{k-1}), h_{k-1} carried as q = R p_{k-1}
-        launch_prep(st, G, xh, xp, xTp, halt);
         project(b);                                                               // r = R x - b
         backproject(gv, ride_f);                                      // g = R^T r, f(x_{k+1/2})
         if (snap) launch_snap(st, n, gv, snap, snap_count, sc);
@@ -2594,13 +2603,13 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
                 launch_tv_grad_b(st, sl, ttv, src);
                 launch_tv_trials_b(st, sl, ttv, src);
                 launch_tv_decide_b(st, sl, tone, src);
-                launch_tv_apply_b(st, sl, ttv, src, i == K - 1);
+                if (i == K - 1) launch_tv_apply_prep_b(st, sl, tprep, src, false, true);   // + R's copies
+                else launch_tv_apply_b(st, sl, ttv, src, false);
             }
             launch_scalar_b(st, sl, tone, OP_SNORM);
         } else {
-            launch_copy_b(st, sl, tvec, BV_X, BV_XH);
+            launch_tv_apply_prep_b(st, sl, tprep, BV_X, true, false);   // x_{k+1/2} = x_k, R's copies
         }
-        launch_prep_b(st, sl, tprep, BV_XH);
         launch_project_b(st, sl, tproj, tcomb, true);
         launch_scalar_b(st, sl, tone, OP_F);
         launch_backproject_b(st, sl, tbp, B.nbmax, B.bp_px);

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void kb_scalar(const SliceDev* __restrict__ sl
         case OP_BETA: scalar_body(op, sc, tr, gmem(S.pf), S.nf, nullptr, 0); break;
         case OP_ALPHA0:
         case OP_ALPHA: scalar_body(op, sc, tr, gmem(S.pqq), S.nqq, gmem(S.pgp), S.ngp); break;
-        case OP_SNORM: scalar_body(op, sc, tr, gmem(S.pts), S.ntv, nullptr, 0); break;
+        case OP_SNORM: scalar_body(op, sc, tr, gmem(S.pts), S.nsn, nullptr, 0); break;
         case OP_EPS: scalar_body(op, sc, tr, nullptr, 0, nullptr, 0); break;
         default: break;
         }

@@ -283,6 +283,13 @@ void launch_tv_value(hipStream_t st, int rows, int cols, const double* y, double
 // dst = src + lam tb_in, then tb_out = t_bar(dst) and its ||.||^2 partials
 // (k_tv_apply followed by k_tv_grad, bit for bit); no overlap between dst and
 // src or between tb_out and tb_in.
+// The last update with R's padded copies of dst (prep's xp, xTp layout):
+// dst = src + lam tb, or dst = src with tb == nullptr; with xk the partials of
+// ||dst - xk||^2, one per 32 x 32 tile (tv_prep_tiles of them).
+int tv_prep_tiles(int rows, int cols);
+void launch_tv_apply_prep(hipStream_t st, const GeomDev& G, const double* src, double* dst,
+                          const float* tb, const Scalars* sc, const double* xk, double* partials,
+                          double* xp, double* xTp, const int* halt);
 void launch_tv_apply_grad(hipStream_t st, int rows, int cols, const double* src, double* dst,
                           const float* tb_in, float* tb_out, const Scalars* sc, double* partials,
                           const int* halt);
@@ -434,7 +441,7 @@ struct SliceDev {
     double *pf, *pgp, *pqq, *ptg, *ptt, *pts;   // pf: f, then (R z)^T q
     Scalars* sc;
     TraceDev tr;
-    int n, m, nf, ngp, nqq, ntv;   // m = nA nB rays
+    int n, m, nf, ngp, nqq, ntv, nsn;   // m = nA nB rays; nsn: tiles of the ||s_k|| partials
 };
 
 // Stage selectors of the batched kernels.
@@ -494,6 +501,9 @@ void launch_tv_grad_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src);
 void launch_tv_trials_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src);
 void launch_tv_decide_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src);
 void launch_tv_apply_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, bool snorm);
+// BS_PREP items: x_{k+1/2} with R's padded copies (see launch_tv_apply_prep).
+void launch_tv_apply_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, bool copy,
+                            bool snorm);
 // cg.hip
 void launch_copy_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, int dst);
 void launch_init_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // xh = x = x0 (or 0)

@@ -346,6 +346,75 @@ void launch_tv_apply(hipStream_t st, int n, const double* src, double* dst, cons
                        partials, halt);
 }
 
+// S_TV's last update written also to R's padded copies: for the 32 x 32 tile
+// (bx, by), dst = src + lam t_bar (tb != nullptr; as k_tv_apply) or dst = src
+// (tb == nullptr: the K = 0 copy), the padded copy xp and the padded
+// transposed copy xTp of dst (as R's prep), and with xk the tile's sum of
+// (dst - xk)^2 in partials[by * tiles_x + bx].  dst may alias src.
+__device__ __forceinline__ void tv_apply_prep_body(const GeomDev& G, const double* src, double* dst,
+                                                   const float* __restrict__ tb,
+                                                   const Scalars* __restrict__ sc,
+                                                   const double* __restrict__ xk,
+                                                   double* __restrict__ partials,
+                                                   double* __restrict__ xp, double* __restrict__ xTp,
+                                                   int bx, int by) {
+    __shared__ double tile[32][33];
+    __shared__ double red[4];
+    const double lam = tb ? sc->lam : 0.0;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int j = bx * 32 + tx;
+    double s2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int i = by * 32 + ty + r;
+        double v = 0.0;
+        if (i < G.rows && j < G.cols) {
+            const size_t p = (size_t)i * G.cols + j;
+            v = tb ? fma(lam, (double)tb[p], src[p]) : src[p];
+            dst[p] = v;
+            xp[(size_t)i * G.pitchX + PAD + j] = v;
+            if (xk) {
+                const double d = v - xk[p];
+                s2 += d * d;
+            }
+        }
+        tile[ty + r][tx] = v;
+    }
+    __syncthreads();
+    const int ii = by * 32 + tx;
+#pragma unroll
+    for (int r = 0; r < 32; r += 8) {
+        const int jj = bx * 32 + ty + r;
+        if (ii < G.rows && jj < G.cols) xTp[(size_t)jj * G.pitchXT + PAD + ii] = tile[tx][ty + r];
+    }
+    if (xk) {
+        const double tot = block_sum(s2, red);
+        if (threadIdx.x == 0) partials[by * ((G.cols + 31) / 32) + bx] = tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tv_apply_prep(GeomDev G, const double* src, double* dst,
+                                                       const float* __restrict__ tb,
+                                                       const Scalars* __restrict__ sc,
+                                                       const double* __restrict__ xk,
+                                                       double* __restrict__ partials,
+                                                       double* __restrict__ xp,
+                                                       double* __restrict__ xTp,
+                                                       const int* __restrict__ halt) {
+    if (halt && *halt) return;
+    tv_apply_prep_body(G, src, dst, tb, sc, xk, partials, xp, xTp, blockIdx.x, blockIdx.y);
+}
+
+int tv_prep_tiles(int rows, int cols) { return ((cols + 31) / 32) * ((rows + 31) / 32); }
+
+void launch_tv_apply_prep(hipStream_t st, const GeomDev& G, const double* src, double* dst,
+                          const float* tb, const Scalars* sc, const double* xk, double* partials,
+                          double* xp, double* xTp, const int* halt) {
+    dim3 grid((G.cols + 31) / 32, (G.rows + 31) / 32);
+    hipLaunchKernelGGL(k_tv_apply_prep, grid, dim3(256), 0, st, G, src, dst, tb, sc, xk, partials, xp,
+                       xTp, halt);
+}
+
 // One S_TV inner step's update followed by the next step's gradient, in one
 // launch: dst = src + lam tb_in (as k_tv_apply) and tb_out = t_bar(dst) with
 // the partials of ||tb_out||^2 (as k_tv_grad).  A thread forms dst at its
@@ -446,6 +515,27 @@ __global__ __launch_bounds__(256) void kb_tv_apply(const SliceDev* __restrict__ 
         tv_apply_body(S.n, batch_vec(S, src), gmem(S.xh), gmem(S.tb), gmem(S.sc),
                       snorm ? gmem(S.x) : nullptr, gmem(S.pts), lin);
     });
+}
+
+// BS_PREP items: the last update (tb: t_bar; else the K = 0 copy of x) with
+// R's padded copies, and with snorm the ||x_{k+1/2} - x_k||^2 tile partials.
+__global__ __launch_bounds__(256) void kb_tv_apply_prep(const SliceDev* __restrict__ sl, ItemTable t,
+                                                        int src, int copy, int snorm) {
+    for_items(t, [&](int s, int lin) {
+        const SliceDev& S = sl[s];
+        if (gmem(S.sc)->halt) return;
+        const GeomDev G = S.G;
+        const int gx = (G.cols + 31) / 32;
+        tv_apply_prep_body(G, batch_vec(S, src), gmem(S.xh), copy ? nullptr : gmem(S.tb), gmem(S.sc),
+                           snorm ? gmem(S.x) : nullptr, gmem(S.pts), gmem(S.xp), gmem(S.xTp), lin % gx,
+                           lin / gx);
+    });
+}
+
+void launch_tv_apply_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, bool copy,
+                            bool snorm) {
+    hipLaunchKernelGGL(kb_tv_apply_prep, dim3(t.grid), dim3(256), 0, st, sl, t, src, copy ? 1 : 0,
+                       snorm ? 1 : 0);
 }
 
 void launch_tv_grad_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src) {
