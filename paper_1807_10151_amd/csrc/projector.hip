@@ -724,7 +724,19 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
                                                      ScalarRide ride,
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
-    backproject_body<NB, TY, PX>(G, ang, yp, out, dotv, partials, blockIdx.x, blockIdx.y);
+    // Workgroups go to the 8 XCDs round-robin in launch order (id mod 8).
+    // When the tile grid splits into 4 x 2 equal regions, XCD q takes region
+    // (q mod 4, q / 4), row by row: a compact image region projects onto a
+    // narrow band of each sinogram row, so each XCD's L2 holds fewer windows
+    // (the tiles' sums do not depend on the order).
+    int bx = blockIdx.x, by = blockIdx.y;
+    if ((gridDim.x & 3) == 0 && (gridDim.y & 1) == 0) {
+        const int id = blockIdx.y * gridDim.x + blockIdx.x, q = id & 7, jj = id >> 3;
+        const int rw = gridDim.x >> 2, rh = gridDim.y >> 1;
+        bx = (q & 3) * rw + jj % rw;
+        by = (q >> 2) * rh + jj / rw;
+    }
+    backproject_body<NB, TY, PX>(G, ang, yp, out, dotv, partials, bx, by);
     if (ride.sc && blockIdx.x == 0 && blockIdx.y == 0) {
         if (ride.ps) scalar_body(OP_SNORM, ride.sc, ride.tr, ride.ps, ride.ns, nullptr, 0);
         if (ride.pf) scalar_body(OP_F, ride.sc, ride.tr, ride.pf, ride.nf, nullptr, 0);
