@@ -715,6 +715,23 @@ __device__ __forceinline__ void backproject_body(const GeomDev& G, const AngleDe
     }
 }
 
+// Tile (bx, by) of the gx x gy tile grid that launch-order workgroup `id`
+// takes.  Workgroups go to the 8 XCDs round-robin in launch order (id mod 8);
+// when the grid splits into 4 x 2 equal regions, XCD q takes region
+// (q mod 4, q / 4), row by row: a compact image region projects onto a narrow
+// band of each sinogram row, so each XCD's L2 holds fewer windows.  Otherwise
+// row-major.  The tiles' sums do not depend on the order.
+__device__ __forceinline__ void bp_tile_of(int id, int gx, int gy, int& bx, int& by) {
+    if ((gx & 3) == 0 && (gy & 1) == 0) {
+        const int q = id & 7, jj = id >> 3, rw = gx >> 2, rh = gy >> 1;
+        bx = (q & 3) * rw + jj % rw;
+        by = (q >> 2) * rh + jj / rw;
+    } else {
+        bx = id % gx;
+        by = id / gx;
+    }
+}
+
 template <int NB, class TY, int PX>
 __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* __restrict__ ang,
                                                      const TY* __restrict__ yp,
@@ -724,18 +741,8 @@ __global__ __launch_bounds__(256) void k_backproject(GeomDev G, const AngleDev* 
                                                      ScalarRide ride,
                                                      const int* __restrict__ halt) {
     if (halt && *halt) return;
-    // Workgroups go to the 8 XCDs round-robin in launch order (id mod 8).
-    // When the tile grid splits into 4 x 2 equal regions, XCD q takes region
-    // (q mod 4, q / 4), row by row: a compact image region projects onto a
-    // narrow band of each sinogram row, so each XCD's L2 holds fewer windows
-    // (the tiles' sums do not depend on the order).
-    int bx = blockIdx.x, by = blockIdx.y;
-    if ((gridDim.x & 3) == 0 && (gridDim.y & 1) == 0) {
-        const int id = blockIdx.y * gridDim.x + blockIdx.x, q = id & 7, jj = id >> 3;
-        const int rw = gridDim.x >> 2, rh = gridDim.y >> 1;
-        bx = (q & 3) * rw + jj % rw;
-        by = (q >> 2) * rh + jj / rw;
-    }
+    int bx, by;
+    bp_tile_of(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x, gridDim.y, bx, by);
     backproject_body<NB, TY, PX>(G, ang, yp, out, dotv, partials, bx, by);
     if (ride.sc && blockIdx.x == 0 && blockIdx.y == 0) {
         if (ride.ps) scalar_body(OP_SNORM, ride.sc, ride.tr, ride.ps, ride.ns, nullptr, 0);
@@ -751,9 +758,9 @@ __global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const GeomDev G = S.G;
-        const int gx = (G.cols + 8 * PX - 1) / (8 * PX);
-        backproject_body<NB, double, PX>(G, cmem(S.ang), gmem(S.rpd), gmem(S.g), nullptr, nullptr,
-                                         lin % gx, lin / gx);
+        int bx, by;
+        bp_tile_of(lin, (G.cols + 8 * PX - 1) / (8 * PX), (G.rows + BP_TILE - 1) / BP_TILE, bx, by);
+        backproject_body<NB, double, PX>(G, cmem(S.ang), gmem(S.rpd), gmem(S.g), nullptr, nullptr, bx, by);
     });
 }
 
