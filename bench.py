@@ -51,15 +51,15 @@ OPS_PER_NNZ = 4
 # memory fabric per launch (FETCH_SIZE + WRITE_SIZE, scaled by the counters of
 # a 64 MiB device copy).  R^T: its float64 (residual) sinogram form, the one
 # the loop body runs.
-COUNTERS = {"measured_at": "kernels of e21385c",
-            "valu_instr": {"project": 2.696e7, "backproject": 3.273e7},
-            "traffic_bytes": {"project": 43.25e6, "backproject": 25.48e6}}
+COUNTERS = {"measured_at": "kernels of fa5dc61",
+            "valu_instr": {"project": 2.696e7, "backproject": 3.275e7},
+            "traffic_bytes": {"project": 43.22e6, "backproject": 14.46e6}}
 # The vector L1's access rate, the limit the gathers of both kernels run into
 # (profiles/memory_pipe_ct512.md, same kernels):
 # TCP_TOTAL_CACHE_ACCESSES per launch and per compute unit and cycle of the
 # kernel's own run (about one access per CU and cycle is the L1's rate; R^T:
 # its float64 form, as above).
-L1_ACCESS = {"measured_at": "kernels of e21385c",
+L1_ACCESS = {"measured_at": "kernels of fa5dc61",
              "per_launch": {"project": 5.702e7, "backproject": 5.58e7},
              "per_cu_per_cycle": {"project": 1.01, "backproject": 0.84}}
 
