@@ -515,7 +515,7 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
         launch_tv_trials(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), nb, sc, 4,
                          dptr<double>(c->part_t), halt);
         launch_tv_decide(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), nb,
-                         dptr<double>(c->part_t), nb, 4, sc, tr, trials_out, halt);
+                         dptr<double>(c->part_t), tv_trial_blocks(G.rows, G.cols), 4, sc, tr, trials_out, halt);
         const bool last = i == K - 1;
         if (last && xp) {
             launch_tv_apply_prep(c->stream, G, src, xh, tb, sc, snorm ? x : nullptr, dptr<double>(c->part_s),
@@ -658,6 +658,7 @@ int stage_blocks(const SliceDev& S, int stage) {
     case BS_ROWS: return (G.rows + 1) / 2;
     case BS_COLS: return S.F.P ? (S.F.SP + S.F.CB - 1) / S.F.CB : 0;
     case BS_TV: return tv_blocks(G.rows, G.cols);
+    case BS_TVT: return tv_trial_blocks(G.rows, G.cols);
     case BS_VEC: return vec_blocks(S.n);
     case BS_PQ: return vec_blocks(std::max(S.n, S.m));
     default: return 1;
@@ -775,6 +776,7 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         S.ngp = vec_blocks(S.n);
         S.nqq = vec_blocks(S.m);
         S.ntv = tv_blocks(G.rows, G.cols);
+        S.ntt = tv_trial_blocks(G.rows, G.cols);
         S.nsn = tv_prep_tiles(G.rows, G.cols);
         Off& o = off[s];
         auto take = [&](size_t bytes) {
@@ -920,7 +922,7 @@ void batch_stage(sp_ctx* c, int stage, int order, int wpc, double mu, double rho
         break;
     case BS_TV:
         launch_tv_grad_b(st, sl, t, BV_X);
-        launch_tv_trials_b(st, sl, t, BV_X);
+        launch_tv_trials_b(st, sl, table(c, BS_TVT, order, wpc), BV_X);
         break;
     case BS_VEC: launch_update_x_b(st, sl, t); break;
     default: break;
@@ -961,6 +963,10 @@ int batch_tune(sp_ctx* c, double mu, double rho) {
         if (stage == BS_ROWS) {
             B.order[BS_COLS] = B.order[BS_ROWS];
             B.wpc[BS_COLS] = B.wpc[BS_ROWS];
+        }
+        if (stage == BS_TV) {   // the trials launch is timed with the TV stage
+            B.order[BS_TVT] = B.order[BS_TV];
+            B.wpc[BS_TVT] = B.wpc[BS_TV];
         }
     }
     (void)hipEventDestroy(e0);
@@ -2578,6 +2584,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     // Algorithm 3, steps 1-9, every slice in each launch
     const ItemTable tprep = table(c, BS_PREP), tproj = table(c, BS_PROJECT),
                     tbp = table(c, BS_BACKPROJECT), tvec = table(c, BS_VEC), ttv = table(c, BS_TV),
+                    ttvt = table(c, BS_TVT),
                     tone = table(c, BS_SLICE, 0, 0), tpq = table(c, BS_PQ),
                     tcomb = table(c, BS_PROJ_COMB, B.order[BS_PROJECT], 0);
     launch_prep_b(st, sl, tprep, BV_XH);
@@ -2601,7 +2608,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
             for (int i = 0; i < K; ++i) {
                 const int src = i == 0 ? BV_X : BV_XH;
                 launch_tv_grad_b(st, sl, ttv, src);
-                launch_tv_trials_b(st, sl, ttv, src);
+                launch_tv_trials_b(st, sl, ttvt, src);
                 launch_tv_decide_b(st, sl, tone, src);
                 if (i == K - 1) launch_tv_apply_prep_b(st, sl, tprep, src, false, true);   // + R's copies
                 else launch_tv_apply_b(st, sl, ttv, src, false);

@@ -270,6 +270,7 @@ size_t fft_lds_bytes(int P, int ncol);
 void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
                     const int* halt);
 int tv_blocks(int rows, int cols);
+int tv_trial_blocks(int rows, int cols);   // workgroups (and trial partials) of launch_tv_trials
 void launch_tv_trials(hipStream_t st, int rows, int cols, const double* y, const float* tb,
                       const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
                       const int* halt);
@@ -441,14 +442,14 @@ struct SliceDev {
     double *pf, *pgp, *pqq, *ptg, *ptt, *pts;   // pf: f, then (R z)^T q
     Scalars* sc;
     TraceDev tr;
-    int n, m, nf, ngp, nqq, ntv, nsn;   // m = nA nB rays; nsn: tiles of the ||s_k|| partials
+    int n, m, nf, ngp, nqq, ntv, ntt, nsn;   // m = nA nB rays; ntt: trial partials; nsn: tiles of the ||s_k|| partials
 };
 
 // Stage selectors of the batched kernels.
 enum BatchVec : int { BV_XH = 0, BV_X = 1, BV_P = 2, BV_Z = 3 };   // BV_Z: the float32 z
 enum BatchStage : int {
     BS_PREP = 0, BS_PROJECT, BS_BACKPROJECT, BS_ROWS, BS_COLS, BS_TV, BS_VEC, BS_SLICE, BS_PROJ_COMB,
-    BS_PQ, BS_COUNT
+    BS_PQ, BS_TVT, BS_COUNT
 };
 struct ItemTable {
     const uint32_t* items;

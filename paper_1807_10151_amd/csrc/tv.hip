@@ -5,7 +5,9 @@
 //                per-workgroup partials of ||t_bar||^2;
 //   k_tv_trials  TV(y) and TV(y + lam_j t_bar) for the next J trial step
 //                lengths lam_j = gamma a^(l + j) / ||t_bar|| in one pass, each as
-//                per-workgroup float64 partials;
+//                per-workgroup float64 partials (TV_TPX pixels per thread, so
+//                few workgroups re-read the ||t_bar||^2 partials and the
+//                decision sums few partials);
 //   k_tv_decide  one workgroup: sums the partials in a fixed order, takes the
 //                first trial with TV(trial) <= TV(y) (Algorithm 1's "until"),
 //                advances l by the trials used, records the step; if none of the
@@ -19,6 +21,7 @@
 namespace sp {
 
 constexpr int TVJ = 4;   // trials evaluated per pass (the first is accepted in most loop bodies)
+constexpr int TV_TPX = 4;   // pixels per thread of the trials kernel
 
 // t_bar at pixel p = (i, j) of a rows x cols float64 image whose value at q
 // is y(q), evaluated in float64 and rounded to float32 (reading: the partial
@@ -78,6 +81,9 @@ __global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const doubl
 }
 
 int tv_blocks(int rows, int cols) { return (int)(((size_t)rows * cols + 255) / 256); }
+int tv_trial_blocks(int rows, int cols) {
+    return (int)(((size_t)rows * cols + 256 * TV_TPX - 1) / (256 * TV_TPX));
+}
 
 void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
                     const int* halt) {
@@ -127,10 +133,13 @@ __device__ __forceinline__ void tv_trials_body(int rows, int cols, const double*
 #pragma unroll
     for (int q = 0; q <= TVJ; ++q) acc[q] = 0.0;
     const size_t n = (size_t)rows * cols;
-    const size_t p = (size_t)bx * 256 + threadIdx.x;
-    if (p < n) {
-        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
-        if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam_r, TVJ, acc);
+#pragma unroll
+    for (int r = 0; r < TV_TPX; ++r) {
+        const size_t p = ((size_t)bx * TV_TPX + r) * 256 + threadIdx.x;
+        if (p < n) {
+            const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+            if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam_r, TVJ, acc);
+        }
     }
     __shared__ double redn[4 * (TVJ + 1)];
     block_sum_n<TVJ + 1>(acc, redn);
@@ -154,7 +163,7 @@ void launch_tv_trials(hipStream_t st, int rows, int cols, const double* y, const
                       const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
                       const int* halt) {
     (void)J;
-    hipLaunchKernelGGL(k_tv_trials, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
+    hipLaunchKernelGGL(k_tv_trials, dim3(tv_trial_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
                        gpart, ngpart, sc, tpart, halt);
 }
 
@@ -503,7 +512,7 @@ __global__ __launch_bounds__(256) void kb_tv_decide(const SliceDev* __restrict__
         if (gmem(S.sc)->halt) return;
         const TraceDev tr = S.tr;
         tv_decide_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), S.ntv,
-                       gmem(S.ptt), S.ntv, gmem(S.sc), tr, nullptr);
+                       gmem(S.ptt), S.ntt, gmem(S.sc), tr, nullptr);
     });
 }
 
