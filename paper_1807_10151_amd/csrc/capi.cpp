@@ -504,7 +504,8 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
     const int* halt = &sc->halt;
-    const int nb = tv_blocks(G.rows, G.cols);
+    // partials of ||t_bar||^2 (first inner step / later ones) and of the trials
+    const int nb0 = tv_blocks(G.rows, G.cols), nb1 = tv_grad_blocks(G.rows, G.cols), nt = tv_tpx_blocks(G.rows, G.cols);
     ProfScope ps(c, SP_PROF_TV);
     const bool fuse = K > 1 && x != xh && c->stv_y.bytes >= (size_t)n * sizeof(double) &&
                       c->vtb2.bytes >= (size_t)n * sizeof(float);
@@ -512,10 +513,11 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
     float* tb = dptr<float>(c->vtb);
     launch_tv_grad(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), halt);
     for (int i = 0; i < K; ++i) {
+        const int nb = i == 0 ? nb0 : nb1;
         launch_tv_trials(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), nb, sc, 4,
                          dptr<double>(c->part_t), halt);
         launch_tv_decide(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), nb,
-                         dptr<double>(c->part_t), tv_trial_blocks(G.rows, G.cols), 4, sc, tr, trials_out, halt);
+                         dptr<double>(c->part_t), nt, 4, sc, tr, trials_out, halt);
         const bool last = i == K - 1;
         if (last && xp) {
             launch_tv_apply_prep(c->stream, G, src, xh, tb, sc, snorm ? x : nullptr, dptr<double>(c->part_s),
@@ -524,7 +526,7 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
             launch_tv_apply(c->stream, n, src, xh, tb, sc, (last && snorm) ? x : nullptr,
                             dptr<double>(c->part_s), halt);
             src = xh;
-            if (!last) launch_tv_grad(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), halt);
+            if (!last) launch_tv_grad(c->stream, G.rows, G.cols, src, tb, dptr<double>(c->part_g), halt, true);
         } else {
             // iterate i + 1 goes to xh when K - 1 - (i + 1) is even, so iterate K - 1 is in xh
             double* dst = (K - 2 - i) % 2 == 0 ? xh : dptr<double>(c->stv_y);
@@ -537,7 +539,7 @@ void enqueue_stv(sp_ctx* c, Scalars* sc, int K, const double* x, double* xh, boo
     }
     if (snorm && !ride_snorm)
         launch_scalar(c->stream, OP_SNORM, sc, tr, dptr<double>(c->part_s),
-                      xp ? tv_prep_tiles(G.rows, G.cols) : nb, nullptr, 0);
+                      xp ? tv_prep_tiles(G.rows, G.cols) : nb0, nullptr, 0);
 }
 
 // z = M g with the partial dots z^T dotv (dotv nullable).
@@ -658,7 +660,8 @@ int stage_blocks(const SliceDev& S, int stage) {
     case BS_ROWS: return (G.rows + 1) / 2;
     case BS_COLS: return S.F.P ? (S.F.SP + S.F.CB - 1) / S.F.CB : 0;
     case BS_TV: return tv_blocks(G.rows, G.cols);
-    case BS_TVT: return tv_trial_blocks(G.rows, G.cols);
+    case BS_TVT: return tv_tpx_blocks(G.rows, G.cols);
+    case BS_TVG: return tv_grad_blocks(G.rows, G.cols);
     case BS_VEC: return vec_blocks(S.n);
     case BS_PQ: return vec_blocks(std::max(S.n, S.m));
     default: return 1;
@@ -776,7 +779,8 @@ int batch_setup(sp_ctx* c, int n, const sp_geometry* geoms, int kind) {
         S.ngp = vec_blocks(S.n);
         S.nqq = vec_blocks(S.m);
         S.ntv = tv_blocks(G.rows, G.cols);
-        S.ntt = tv_trial_blocks(G.rows, G.cols);
+        S.ntt = tv_tpx_blocks(G.rows, G.cols);
+        S.ntg = tv_grad_blocks(G.rows, G.cols);
         S.nsn = tv_prep_tiles(G.rows, G.cols);
         Off& o = off[s];
         auto take = [&](size_t bytes) {
@@ -965,8 +969,8 @@ int batch_tune(sp_ctx* c, double mu, double rho) {
             B.wpc[BS_COLS] = B.wpc[BS_ROWS];
         }
         if (stage == BS_TV) {   // the trials launch is timed with the TV stage
-            B.order[BS_TVT] = B.order[BS_TV];
-            B.wpc[BS_TVT] = B.wpc[BS_TV];
+            B.order[BS_TVT] = B.order[BS_TVG] = B.order[BS_TV];
+            B.wpc[BS_TVT] = B.wpc[BS_TVG] = B.wpc[BS_TV];
         }
     }
     (void)hipEventDestroy(e0);
@@ -2584,7 +2588,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
     // Algorithm 3, steps 1-9, every slice in each launch
     const ItemTable tprep = table(c, BS_PREP), tproj = table(c, BS_PROJECT),
                     tbp = table(c, BS_BACKPROJECT), tvec = table(c, BS_VEC), ttv = table(c, BS_TV),
-                    ttvt = table(c, BS_TVT),
+                    ttvt = table(c, BS_TVT), ttvg = table(c, BS_TVG),
                     tone = table(c, BS_SLICE, 0, 0), tpq = table(c, BS_PQ),
                     tcomb = table(c, BS_PROJ_COMB, B.order[BS_PROJECT], 0);
     launch_prep_b(st, sl, tprep, BV_XH);
@@ -2607,7 +2611,7 @@ int sp_suppcg_solve_batched(sp_ctx* c, int32_t n, const sp_geometry* geoms, cons
         if (K > 0) {
             for (int i = 0; i < K; ++i) {
                 const int src = i == 0 ? BV_X : BV_XH;
-                launch_tv_grad_b(st, sl, ttv, src);
+                launch_tv_grad_b(st, sl, i == 0 ? ttv : ttvg, src);   // the item count follows src
                 launch_tv_trials_b(st, sl, ttvt, src);
                 launch_tv_decide_b(st, sl, tone, src);
                 if (i == K - 1) launch_tv_apply_prep_b(st, sl, tprep, src, false, true);   // + R's copies

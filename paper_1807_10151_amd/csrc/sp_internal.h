@@ -267,10 +267,16 @@ int precond_dot_blocks(const FFTPlan& F);
 size_t fft_lds_bytes(int P, int ncol);
 
 // tv.hip (images y, x_{k+1/2} and x_k in float64; t_bar float32)
+// t_bar and its ||.||^2 partials: tv_blocks of them for an S_TV call's first
+// inner step (later = false), tv_grad_blocks for later ones.
 void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
-                    const int* halt);
+                    const int* halt, bool later = false);
 int tv_blocks(int rows, int cols);
-int tv_trial_blocks(int rows, int cols);   // workgroups (and trial partials) of launch_tv_trials
+// Workgroups (and partials) of the t_bar launches after an S_TV call's first
+// inner step (k_tv_grad with later, k_tv_apply_grad: the ||t_bar||^2 partials)
+// and of the trials launch (the trial partials).
+int tv_grad_blocks(int rows, int cols);
+int tv_tpx_blocks(int rows, int cols);
 void launch_tv_trials(hipStream_t st, int rows, int cols, const double* y, const float* tb,
                       const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
                       const int* halt);
@@ -442,14 +448,14 @@ struct SliceDev {
     double *pf, *pgp, *pqq, *ptg, *ptt, *pts;   // pf: f, then (R z)^T q
     Scalars* sc;
     TraceDev tr;
-    int n, m, nf, ngp, nqq, ntv, ntt, nsn;   // m = nA nB rays; ntt: trial partials; nsn: tiles of the ||s_k|| partials
+    int n, m, nf, ngp, nqq, ntv, ntg, ntt, nsn;   // m = nA nB rays; ntg / ntt: t_bar / trial partials; nsn: ||s_k|| tiles
 };
 
 // Stage selectors of the batched kernels.
 enum BatchVec : int { BV_XH = 0, BV_X = 1, BV_P = 2, BV_Z = 3 };   // BV_Z: the float32 z
 enum BatchStage : int {
     BS_PREP = 0, BS_PROJECT, BS_BACKPROJECT, BS_ROWS, BS_COLS, BS_TV, BS_VEC, BS_SLICE, BS_PROJ_COMB,
-    BS_PQ, BS_TVT, BS_COUNT
+    BS_PQ, BS_TVT, BS_TVG, BS_COUNT
 };
 struct ItemTable {
     const uint32_t* items;

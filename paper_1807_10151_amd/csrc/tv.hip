@@ -2,7 +2,9 @@
 //
 // One S_TV inner step is four launches:
 //   k_tv_grad    t_bar (minus the TV gradient where defined, 0 elsewhere) and
-//                per-workgroup partials of ||t_bar||^2;
+//                per-workgroup partials of ||t_bar||^2 (one pixel per thread
+//                for an S_TV call's first step, TV_GPX for later ones, whose
+//                t_bar the single-slice solver forms in k_tv_apply_grad);
 //   k_tv_trials  TV(y) and TV(y + lam_j t_bar) for the next J trial step
 //                lengths lam_j = gamma a^(l + j) / ||t_bar|| in one pass, each as
 //                per-workgroup float64 partials (TV_TPX pixels per thread, so
@@ -22,6 +24,7 @@ namespace sp {
 
 constexpr int TVJ = 4;   // trials evaluated per pass (the first is accepted in most loop bodies)
 constexpr int TV_TPX = 4;   // pixels per thread of the trials kernel
+constexpr int TV_GPX = 4;   // pixels per thread of t_bar after the first inner step
 
 // t_bar at pixel p = (i, j) of a rows x cols float64 image whose value at q
 // is y(q), evaluated in float64 and rounded to float32 (reading: the partial
@@ -57,16 +60,18 @@ __device__ __forceinline__ float tv_neg_grad(const double* __restrict__ y, int r
 
 __device__ __forceinline__ void tv_grad_body(int rows, int cols, const double* __restrict__ y,
                                              float* __restrict__ tb, double* __restrict__ partials,
-                                             int bx) {
+                                             int bx, int gpx) {
     __shared__ double red[4];
     const size_t n = (size_t)rows * cols;
-    const size_t p = (size_t)bx * 256 + threadIdx.x;
     double sq = 0.0;
-    if (p < n) {
-        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
-        const float t = tv_neg_grad(y, rows, cols, i, j, p);
-        tb[p] = t;
-        sq = (double)t * (double)t;
+    for (int r = 0; r < gpx; ++r) {
+        const size_t p = ((size_t)bx * gpx + r) * 256 + threadIdx.x;
+        if (p < n) {
+            const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+            const float t = tv_neg_grad(y, rows, cols, i, j, p);
+            tb[p] = t;
+            sq += (double)t * (double)t;
+        }
     }
     const double tot = block_sum(sq, red);
     if (partials && threadIdx.x == 0) partials[bx] = tot;
@@ -74,21 +79,25 @@ __device__ __forceinline__ void tv_grad_body(int rows, int cols, const double* _
 
 __global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const double* __restrict__ y,
                                                  float* __restrict__ tb,
-                                                 double* __restrict__ partials,
+                                                 double* __restrict__ partials, int gpx,
                                                  const int* __restrict__ halt) {
     if (halt && *halt) return;
-    tv_grad_body(rows, cols, y, tb, partials, blockIdx.x);
+    tv_grad_body(rows, cols, y, tb, partials, blockIdx.x, gpx);
 }
 
 int tv_blocks(int rows, int cols) { return (int)(((size_t)rows * cols + 255) / 256); }
-int tv_trial_blocks(int rows, int cols) {
+int tv_grad_blocks(int rows, int cols) {
+    return (int)(((size_t)rows * cols + 256 * TV_GPX - 1) / (256 * TV_GPX));
+}
+int tv_tpx_blocks(int rows, int cols) {
     return (int)(((size_t)rows * cols + 256 * TV_TPX - 1) / (256 * TV_TPX));
 }
 
 void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
-                    const int* halt) {
-    hipLaunchKernelGGL(k_tv_grad, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
-                       partials, halt);
+                    const int* halt, bool later) {
+    const int gpx = later ? TV_GPX : 1;
+    hipLaunchKernelGGL(k_tv_grad, dim3(later ? tv_grad_blocks(rows, cols) : tv_blocks(rows, cols)), dim3(256),
+                       0, st, rows, cols, y, tb, partials, gpx, halt);
 }
 
 // TV terms of pixel p for the base image (q = 0) and nq trial steps lam[0..nq).
@@ -163,7 +172,7 @@ void launch_tv_trials(hipStream_t st, int rows, int cols, const double* y, const
                       const double* gpart, int ngpart, Scalars* sc, int J, double* tpart,
                       const int* halt) {
     (void)J;
-    hipLaunchKernelGGL(k_tv_trials, dim3(tv_trial_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
+    hipLaunchKernelGGL(k_tv_trials, dim3(tv_tpx_blocks(rows, cols)), dim3(256), 0, st, rows, cols, y, tb,
                        gpart, ngpart, sc, tpart, halt);
 }
 
@@ -441,15 +450,18 @@ __global__ __launch_bounds__(256) void k_tv_apply_grad(int rows, int cols, const
     __shared__ double red[4];
     const double lam = sc->lam;
     const size_t n = (size_t)rows * cols;
-    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    auto y = [&](size_t q) { return fma(lam, (double)tb_in[q], src[q]); };
     double sq = 0.0;
-    if (p < n) {
-        auto y = [&](size_t q) { return fma(lam, (double)tb_in[q], src[q]); };
-        dst[p] = y(p);
-        const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
-        const float t = tv_neg_grad_at(y, rows, cols, i, j, p);
-        tb_out[p] = t;
-        sq = (double)t * (double)t;
+#pragma unroll
+    for (int r = 0; r < TV_GPX; ++r) {   // the pixels and partial layout of k_tv_grad
+        const size_t p = ((size_t)blockIdx.x * TV_GPX + r) * 256 + threadIdx.x;
+        if (p < n) {
+            dst[p] = y(p);
+            const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
+            const float t = tv_neg_grad_at(y, rows, cols, i, j, p);
+            tb_out[p] = t;
+            sq += (double)t * (double)t;
+        }
     }
     const double tot = block_sum(sq, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -458,7 +470,7 @@ __global__ __launch_bounds__(256) void k_tv_apply_grad(int rows, int cols, const
 void launch_tv_apply_grad(hipStream_t st, int rows, int cols, const double* src, double* dst,
                           const float* tb_in, float* tb_out, const Scalars* sc, double* partials,
                           const int* halt) {
-    hipLaunchKernelGGL(k_tv_apply_grad, dim3(tv_blocks(rows, cols)), dim3(256), 0, st, rows, cols, src, dst,
+    hipLaunchKernelGGL(k_tv_apply_grad, dim3(tv_grad_blocks(rows, cols)), dim3(256), 0, st, rows, cols, src, dst,
                        tb_in, tb_out, sc, partials, halt);
 }
 
@@ -493,7 +505,8 @@ __global__ __launch_bounds__(256) void kb_tv_grad(const SliceDev* __restrict__ s
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
-        tv_grad_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), lin);
+        tv_grad_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), lin,
+                     src == BV_X ? 1 : TV_GPX);   // the first inner step reads x
     });
 }
 
@@ -501,7 +514,7 @@ __global__ __launch_bounds__(256) void kb_tv_trials(const SliceDev* __restrict__
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
-        tv_trials_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), S.ntv,
+        tv_trials_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), src == BV_X ? S.ntv : S.ntg,
                        gmem(S.sc), gmem(S.ptt), lin);
     });
 }
@@ -511,7 +524,7 @@ __global__ __launch_bounds__(256) void kb_tv_decide(const SliceDev* __restrict__
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         const TraceDev tr = S.tr;
-        tv_decide_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), S.ntv,
+        tv_decide_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), src == BV_X ? S.ntv : S.ntg,
                        gmem(S.ptt), S.ntt, gmem(S.sc), tr, nullptr);
     });
 }
