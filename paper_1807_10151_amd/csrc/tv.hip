@@ -3,13 +3,13 @@
 // One S_TV inner step is four launches:
 //   k_tv_grad    t_bar (minus the TV gradient where defined, 0 elsewhere) and
 //                per-workgroup partials of ||t_bar||^2 (one pixel per thread
-//                for an S_TV call's first step, TV_GPX for later ones, whose
+//                for an S_TV call's first step, tv_px for later ones, whose
 //                t_bar the single-slice solver forms in k_tv_apply_grad);
 //   k_tv_trials  TV(y) and TV(y + lam_j t_bar) for the next J trial step
 //                lengths lam_j = gamma a^(l + j) / ||t_bar|| in one pass, each as
-//                per-workgroup float64 partials (TV_TPX pixels per thread, so
-//                few workgroups re-read the ||t_bar||^2 partials and the
-//                decision sums few partials);
+//                per-workgroup float64 partials (tv_px pixels per thread: on
+//                large images fewer workgroups re-read the ||t_bar||^2
+//                partials and the decision sums fewer partials);
 //   k_tv_decide  one workgroup: sums the partials in a fixed order, takes the
 //                first trial with TV(trial) <= TV(y) (Algorithm 1's "until"),
 //                advances l by the trials used, records the step; if none of the
@@ -23,8 +23,10 @@
 namespace sp {
 
 constexpr int TVJ = 4;   // trials evaluated per pass (the first is accepted in most loop bodies)
-constexpr int TV_TPX = 4;   // pixels per thread of the trials kernel
-constexpr int TV_GPX = 4;   // pixels per thread of t_bar after the first inner step
+// Pixels per thread of the trials and of t_bar after an S_TV call's first
+// inner step: 4 from 2^18 pixels up (at least one workgroup per compute unit),
+// else 1.
+__host__ __device__ __forceinline__ int tv_px(size_t n) { return n >= ((size_t)1 << 18) ? 4 : 1; }
 
 // t_bar at pixel p = (i, j) of a rows x cols float64 image whose value at q
 // is y(q), evaluated in float64 and rounded to float32 (reading: the partial
@@ -87,15 +89,17 @@ __global__ __launch_bounds__(256) void k_tv_grad(int rows, int cols, const doubl
 
 int tv_blocks(int rows, int cols) { return (int)(((size_t)rows * cols + 255) / 256); }
 int tv_grad_blocks(int rows, int cols) {
-    return (int)(((size_t)rows * cols + 256 * TV_GPX - 1) / (256 * TV_GPX));
+    const size_t n = (size_t)rows * cols;
+    return (int)((n + 256 * tv_px(n) - 1) / (256 * tv_px(n)));
 }
 int tv_tpx_blocks(int rows, int cols) {
-    return (int)(((size_t)rows * cols + 256 * TV_TPX - 1) / (256 * TV_TPX));
+    const size_t n = (size_t)rows * cols;
+    return (int)((n + 256 * tv_px(n) - 1) / (256 * tv_px(n)));
 }
 
 void launch_tv_grad(hipStream_t st, int rows, int cols, const double* y, float* tb, double* partials,
                     const int* halt, bool later) {
-    const int gpx = later ? TV_GPX : 1;
+    const int gpx = later ? tv_px((size_t)rows * cols) : 1;
     hipLaunchKernelGGL(k_tv_grad, dim3(later ? tv_grad_blocks(rows, cols) : tv_blocks(rows, cols)), dim3(256),
                        0, st, rows, cols, y, tb, partials, gpx, halt);
 }
@@ -142,9 +146,9 @@ __device__ __forceinline__ void tv_trials_body(int rows, int cols, const double*
 #pragma unroll
     for (int q = 0; q <= TVJ; ++q) acc[q] = 0.0;
     const size_t n = (size_t)rows * cols;
-#pragma unroll
-    for (int r = 0; r < TV_TPX; ++r) {
-        const size_t p = ((size_t)bx * TV_TPX + r) * 256 + threadIdx.x;
+    const int px = tv_px(n);
+    for (int r = 0; r < px; ++r) {
+        const size_t p = ((size_t)bx * px + r) * 256 + threadIdx.x;
         if (p < n) {
             const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
             if (i < rows - 1 && j < cols - 1) tv_terms<TVJ>(y, tb, cols, p, lam_r, TVJ, acc);
@@ -452,9 +456,9 @@ __global__ __launch_bounds__(256) void k_tv_apply_grad(int rows, int cols, const
     const size_t n = (size_t)rows * cols;
     auto y = [&](size_t q) { return fma(lam, (double)tb_in[q], src[q]); };
     double sq = 0.0;
-#pragma unroll
-    for (int r = 0; r < TV_GPX; ++r) {   // the pixels and partial layout of k_tv_grad
-        const size_t p = ((size_t)blockIdx.x * TV_GPX + r) * 256 + threadIdx.x;
+    const int px = tv_px(n);
+    for (int r = 0; r < px; ++r) {   // the pixels and partial layout of a later k_tv_grad
+        const size_t p = ((size_t)blockIdx.x * px + r) * 256 + threadIdx.x;
         if (p < n) {
             dst[p] = y(p);
             const int i = (int)(p / cols), j = (int)(p - (size_t)i * cols);
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(256) void kb_tv_grad(const SliceDev* __restrict__ s
         const SliceDev& S = sl[s];
         if (gmem(S.sc)->halt) return;
         tv_grad_body(S.G.rows, S.G.cols, batch_vec(S, src), gmem(S.tb), gmem(S.ptg), lin,
-                     src == BV_X ? 1 : TV_GPX);   // the first inner step reads x
+                     src == BV_X ? 1 : tv_px((size_t)S.n));   // the first inner step reads x
     });
 }
 
