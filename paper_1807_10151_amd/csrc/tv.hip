@@ -17,9 +17,10 @@
 //   k_tv_apply   y <- y + lam t_bar (and ||s_k||^2 partials on the last step).
 // The single-slice solver fuses two pairs: between inner steps the update and
 // the next t_bar are one launch (k_tv_apply_grad), and the last update also
-// writes R's padded copies of x_{k+1/2} (k_tv_apply_prep).  Every fused kernel
-// repeats the arithmetic of the separate ones, so results are bitwise those of
-// the batched solver, which keeps the launches separate.
+// writes R's padded copies of x_{k+1/2} (k_tv_apply_prep; the batched solver
+// runs the same body).  k_tv_apply_grad repeats the arithmetic of the two
+// launches it replaces, so results are bitwise those of the batched solver,
+// which keeps them separate.
 // Trial TVs are evaluated in float64 directly on y + lam t_bar (the trial image
 // is never rounded to float32), so the acceptance test sees the step itself.
 #include "sp_internal.h"
