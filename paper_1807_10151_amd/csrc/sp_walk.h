@@ -103,4 +103,21 @@ __host__ __device__ inline double bp_kf_oblique(double xj, double kc, const Angl
     return fma(xj, A.cids, kc);
 }
 
+// Tile (bx, by) of R^T's gx x gy tile grid that launch-order workgroup `id`
+// takes.  Workgroups go to the 8 XCDs round-robin in launch order (id mod 8);
+// when the grid splits into 4 x 2 equal regions, XCD q takes region
+// (q mod 4, q / 4), row by row: a compact image region projects onto a narrow
+// band of each sinogram row, so each XCD's L2 holds fewer windows.  Otherwise
+// row-major.  The tiles' sums do not depend on the order.
+__host__ __device__ inline void bp_tile_of(int id, int gx, int gy, int& bx, int& by) {
+    if ((gx & 3) == 0 && (gy & 1) == 0) {
+        const int q = id & 7, jj = id >> 3, rw = gx >> 2, rh = gy >> 1;
+        bx = (q & 3) * rw + jj % rw;
+        by = (q >> 2) * rh + jj / rw;
+    } else {
+        bx = id % gx;
+        by = id / gx;
+    }
+}
+
 }  // namespace sp

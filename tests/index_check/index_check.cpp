@@ -199,9 +199,37 @@ static bool check_backward(const GeomDev& G, const std::vector<AngleDev>& tab, i
     return true;
 }
 
+// R^T's tile order (bp_tile_of): in every gx x gy grid each launch-order
+// workgroup takes a tile inside the grid and every tile is taken exactly once.
+static bool check_tile_order(int& grids) {
+    std::vector<std::pair<int, int>> shapes;
+    for (int gx = 1; gx <= 72; ++gx)
+        for (int gy = 1; gy <= 160; ++gy) shapes.push_back({gx, gy});
+    for (auto s : {std::make_pair(64, 256), std::make_pair(128, 256), std::make_pair(64, 512),
+                   std::make_pair(32, 128), std::make_pair(16, 64)})
+        shapes.push_back(s);
+    for (auto [gx, gy] : shapes) {
+        std::vector<char> seen((size_t)gx * gy, 0);
+        for (int id = 0; id < gx * gy; ++id) {
+            int bx = -1, by = -1;
+            bp_tile_of(id, gx, gy, bx, by);
+            if (bx < 0 || bx >= gx || by < 0 || by >= gy || seen[(size_t)by * gx + bx]++) {
+                std::printf("tile order %dx%d: workgroup %d -> (%d, %d) out of the grid or taken twice\n", gx, gy,
+                            id, bx, by);
+                return false;
+            }
+        }
+        ++grids;
+    }
+    return true;
+}
+
 int main() {
     char line[512];
     int count = 0;
+    int grids = 0;
+    if (!check_tile_order(grids)) return 1;
+    std::printf("tile order: ok (%d grids)\n", grids);
     while (std::fgets(line, sizeof line, stdin)) {
         sp_geometry g{};
         int rs = 1, ps = 1;

@@ -79,3 +79,4 @@ def test_projector_indices_stay_in_rows_and_cover_every_crossing(checker):
     print(res.stdout[-4000:])
     assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
     assert f"checked {len(geometries())} geometries" in res.stdout
+    assert "tile order: ok" in res.stdout
