@@ -600,9 +600,12 @@ int lp_enqueue_apply(sp_ctx* c, sp_learned* net, int B, int H, int W, const floa
 
 // z = M g (partial dots z^T dotv when dotv != NULL).  In the solver
 // (solver = true) every launch honours the halt flag, and a learned M is
-// checked (g^T z > 0 and finite) with the Fourier M as fallback.
+// checked (g^T z > 0 and finite) with the Fourier M as fallback.  With xp,
+// R's padded copies of z (xp, xTp) are written too: by the Fourier M's last
+// kernel, else by a prep launch.
 int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, const float* dotv,
-                    double* partials, int& nparts, bool solver) {
+                    double* partials, int& nparts, bool solver, double* xp = nullptr,
+                    double* xTp = nullptr) {
     const GeomDev& G = c->G;
     const int n = G.rows * G.cols;
     Scalars* sc = dptr<Scalars>(c->scal);
@@ -610,6 +613,7 @@ int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, c
     if (pc->kind == SP_PRECOND_NONE) {
         if (g != z) launch_copy(c->stream, n, g, z, halt);
         if (dotv) launch_dot(c->stream, n, z, dotv, partials, halt);
+        if (xp) launch_prep(c->stream, G, z, xp, xTp, halt);
         nparts = vec_blocks(n);
         return SP_OK;
     }
@@ -630,12 +634,14 @@ int enqueue_precond(sp_ctx* c, const sp_precond* pc, const float* g, float* z, c
             launch_precond(c->stream, F, pc->mu, pc->rho, g, z, nullptr, nullptr, halt, &sc->gate_ramp);
         }
         if (dotv) launch_dot(c->stream, n, z, dotv, partials, halt);
+        if (xp) launch_prep(c->stream, G, z, xp, xTp, halt);
         nparts = vec_blocks(n);
         return SP_OK;
     }
     {
         ProfScope ps(c, SP_PROF_PRECOND);
-        launch_precond(c->stream, F, pc->mu, pc->rho, g, z, dotv, partials, halt);
+        launch_precond(c->stream, F, pc->mu, pc->rho, g, z, dotv, partials, halt, nullptr, xp ? &G : nullptr,
+                       xp, xTp);
     }
     nparts = precond_dot_blocks(F);
     return SP_OK;
@@ -1744,8 +1750,7 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         launch_scalar(st, OP_F0, sc, tr, pf, nf, nullptr, 0);
         launch_backproject(st, G, ang, rpd, gv, nullptr, nullptr, halt);
         int nzh = 0;
-        if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true))) return rc;
-        launch_prep(st, G, z, xp, xTp, halt);
+        if ((rc = enqueue_precond(c, pc, gv, z, nullptr, pzh, nzh, true, xp, xTp))) return rc;   // + R's copies of z
         launch_project(st, G, ang, waves, xp, xTp, nullptr, nullptr, 0, nullptr, nullptr, pf, seg, pord,
                        halt, q, w);                                                // w = R z_0
         launch_update_pq_beta(st, n, m, z, p, gv, w, q, sc, tr, pf, nf, pgp, pqq);   // p_0, q
@@ -1795,9 +1800,8 @@ int sp_suppcg_solve(sp_ctx* c, const sp_geometry* g, const float* b, const float
         backproject(gv, ride_f);                                      // g = R^T r, f(x_{k+1/2})
         if (snap) launch_snap(st, n, gv, snap, snap_count, sc);
         int nz = 0;
-        int r2 = enqueue_precond(c, pc, gv, z, nullptr, pzh, nz, true);              // z = M g
+        int r2 = enqueue_precond(c, pc, gv, z, nullptr, pzh, nz, true, xp, xTp);  // z = M g, R's copies of z
         if (r2) return r2;
-        launch_prep(st, G, z, xp, xTp, halt);
         project(nullptr);                                              // w = R z, z^T h = w^T q
         launch_update_pq_beta(st, n, m, z, p, gv, w, q, sc, tr, pf, nf, pgp, pqq);  // beta; p, q
         launch_update_x_alpha(st, n, xh, p, x, sc, tr, pqq, nqq, pgp, ngp, OP_ALPHA);  // alpha; x += alpha p

@@ -266,9 +266,15 @@ __global__ __launch_bounds__(512) void k_cols(FFTPlan F, double mu, double rho, 
     cols_body(F, mu, rho, buf, blockIdx.x);
 }
 
+// With xp, z is also written to R's padded float64 copies (xp row-major with
+// row pitch pitchX, xTp transposed with pitch pitchXT, both PAD-offset), as
+// R's prep would write them.
 __device__ __forceinline__ void rows_inv_body(const FFTPlan& F, float* __restrict__ z,
                                               const float* __restrict__ dotv,
-                                              double* __restrict__ partials, double2* raw, int bx) {
+                                              double* __restrict__ partials, double2* raw, int bx,
+                                              double* __restrict__ xp = nullptr,
+                                              double* __restrict__ xTp = nullptr, int pitchX = 0,
+                                              int pitchXT = 0) {
     const LdsBuf buf{raw, fft_lds_shift(F.P, 1)};
     double* red = reinterpret_cast<double*>(raw);   // reused after the transform is read
     const int r0 = 2 * bx, r1 = r0 + 1;
@@ -300,10 +306,18 @@ __device__ __forceinline__ void rows_inv_body(const FFTPlan& F, float* __restric
         const float a = (float)(v.x * scale);
         z[(size_t)r0 * F.cols + j] = a;
         if (dotv) dot += (double)a * (double)dotv[(size_t)r0 * F.cols + j];
+        if (xp) {
+            xp[(size_t)r0 * pitchX + PAD + j] = (double)a;
+            xTp[(size_t)j * pitchXT + PAD + r0] = (double)a;
+        }
         if (has1) {
             const float bv = (float)(v.y * scale);
             z[(size_t)r1 * F.cols + j] = bv;
             if (dotv) dot += (double)bv * (double)dotv[(size_t)r1 * F.cols + j];
+            if (xp) {
+                xp[(size_t)r1 * pitchX + PAD + j] = (double)bv;
+                xTp[(size_t)j * pitchXT + PAD + r1] = (double)bv;
+            }
         }
     }
     if (dotv) {
@@ -315,11 +329,13 @@ __device__ __forceinline__ void rows_inv_body(const FFTPlan& F, float* __restric
 __global__ __launch_bounds__(256) void k_rows_inv(FFTPlan F, float* __restrict__ z, const int* __restrict__ run,
                                                   const float* __restrict__ dotv,
                                                   double* __restrict__ partials,
-                                                  const int* __restrict__ halt) {
+                                                  const int* __restrict__ halt,
+                                                  double* __restrict__ xp, double* __restrict__ xTp,
+                                                  int pitchX, int pitchXT) {
     if (halt && *halt) return;
     if (run && !*run) return;
     extern __shared__ double2 buf[];
-    rows_inv_body(F, z, dotv, partials, buf, blockIdx.x);
+    rows_inv_body(F, z, dotv, partials, buf, blockIdx.x, xp, xTp, pitchX, pitchXT);
 }
 
 // Batched: z = M g per slice.
@@ -374,14 +390,16 @@ size_t fft_lds_bytes(int P, int ncol) {
 }
 
 void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, const float* g,
-                    float* z, const float* dotv, double* partials, const int* halt, const int* run) {
+                    float* z, const float* dotv, double* partials, const int* halt, const int* run,
+                    const GeomDev* G, double* xp, double* xTp) {
     const int nrow = (F.rows + 1) / 2;
     const size_t row_lds = fft_lds_bytes(F.P, 1);
     hipLaunchKernelGGL(k_rows_fwd, dim3(nrow), dim3(512), row_lds, st, F, g, run, halt);
     const int ncb = (F.SP + F.CB - 1) / F.CB;
     hipLaunchKernelGGL(k_cols, dim3(ncb), dim3(512), fft_lds_bytes(F.P, F.CB), st, F, mu, rho, run,
                        halt);
-    hipLaunchKernelGGL(k_rows_inv, dim3(nrow), dim3(256), row_lds, st, F, z, run, dotv, partials, halt);
+    hipLaunchKernelGGL(k_rows_inv, dim3(nrow), dim3(256), row_lds, st, F, z, run, dotv, partials, halt,
+                       G ? xp : nullptr, G ? xTp : nullptr, G ? G->pitchX : 0, G ? G->pitchXT : 0);
 }
 
 }  // namespace sp

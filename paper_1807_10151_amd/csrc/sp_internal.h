@@ -258,9 +258,12 @@ struct FFTPlan {
     double2* S;           // [rows][SP] complex float64 scratch
     const double2* tw;    // [P/2] twiddles exp(-2 pi i k / P)
 };
+// With G, z is also written to R's padded copies xp / xTp of geometry G (as
+// launch_prep of z would write them).
 void launch_precond(hipStream_t st, const FFTPlan& F, double mu, double rho, const float* g,
                     float* z, const float* dotv, double* partials, const int* halt,
-                    const int* run = nullptr);
+                    const int* run = nullptr, const GeomDev* G = nullptr, double* xp = nullptr,
+                    double* xTp = nullptr);
 int precond_dot_blocks(const FFTPlan& F);
 // Dynamic LDS of an FFT workgroup holding ncol length-P transforms (plus the
 // twiddle table when it fits).
