@@ -124,20 +124,6 @@ __device__ __forceinline__ void update_x_body(int n, const double* __restrict__ 
         x[q] = fma(alpha, p[q], xh[q]);
 }
 
-__global__ __launch_bounds__(256) void k_update_x(int n, const double* __restrict__ xh,
-                                                  const double* __restrict__ p,
-                                                  double* __restrict__ x,
-                                                  const Scalars* __restrict__ sc,
-                                                  const int* __restrict__ halt) {
-    if (halt && *halt) return;
-    update_x_body(n, xh, p, x, sc->alpha, blockIdx.x, gridDim.x);
-}
-
-void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, double* x,
-                     const Scalars* sc, const int* halt) {
-    hipLaunchKernelGGL(k_update_x, dim3(vec_blocks(n)), dim3(256), 0, st, n, xh, p, x, sc, halt);
-}
-
 // The alpha step (op OP_ALPHA or OP_ALPHA0) folded into the update: every
 // workgroup sums the p^T h (= q^T q) and g^T p partials in the same order and takes the
 // same halt decision (breakdown, non-finite) that workgroup 0 commits; on a
@@ -260,18 +246,6 @@ void launch_scalar(hipStream_t st, int op, Scalars* sc, TraceDev tr, const doubl
 }
 
 // ---- batched forms (one item table entry per virtual block of each slice) ----
-__global__ __launch_bounds__(256) void kb_copy(const SliceDev* __restrict__ sl, ItemTable t, int src,
-                                               int dst) {
-    for_items(t, [&](int s, int lin) {
-        const SliceDev& S = sl[s];
-        if (gmem(S.sc)->halt) return;
-        const double* a = batch_vec(S, src);
-        double* d = batch_vec(S, dst);
-        const int gx = vec_blocks_dev(S.n);
-        for (int q = lin * 256 + threadIdx.x; q < S.n; q += gx * 256) d[q] = a[q];
-    });
-}
-
 __global__ __launch_bounds__(256) void kb_init(const SliceDev* __restrict__ sl, ItemTable t) {
     for_items(t, [&](int s, int lin) {
         const SliceDev& S = sl[s];
@@ -335,9 +309,6 @@ __global__ __launch_bounds__(256) void kb_scalar(const SliceDev* __restrict__ sl
     });
 }
 
-void launch_copy_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, int dst) {
-    hipLaunchKernelGGL(kb_copy, dim3(t.grid), dim3(256), 0, st, sl, t, src, dst);
-}
 void launch_init_b(hipStream_t st, const SliceDev* sl, ItemTable t) {
     hipLaunchKernelGGL(kb_init, dim3(t.grid), dim3(256), 0, st, sl, t);
 }

@@ -131,9 +131,6 @@ int backproject_tiles(const GeomDev& G, int px) {
     return ((G.cols + 8 * px - 1) / (8 * px)) * ((G.rows + BP_TILE - 1) / BP_TILE);
 }
 
-int backproject_blocks(const GeomDev& G) {
-    return ((G.cols + BP_TW - 1) / BP_TW) * ((G.rows + BP_TILE - 1) / BP_TILE);
-}
 
 int backproject_px(int rows, int cols, int resident_waves) {
     // four pixels per lane amortise more of each angle's work but need more

@@ -245,7 +245,6 @@ int project_comb_blocks(const GeomDev& G);
 // workgroup when the rays are split in parts, else one per ray workgroup.
 int project_blocks(const GeomDev& G);
 // Number of R^T's float64 dot partials: one per 8 x 16 pixel sub-tile.
-int backproject_blocks(const GeomDev& G);
 // R^T workgroups (8 x 8 px pixel tiles) for px pixels per lane.
 int backproject_tiles(const GeomDev& G, int px);
 // Pixels per lane R^T uses for an image: 4 when that grid still fills half
@@ -308,8 +307,6 @@ void launch_tv_apply_grad(hipStream_t st, int rows, int cols, const double* src,
 int vec_blocks(int n);
 void launch_dot(hipStream_t st, int n, const float* a, const float* b, double* partials,
                 const int* halt);
-void launch_update_x(hipStream_t st, int n, const double* xh, const double* p, double* x,
-                     const Scalars* sc, const int* halt);
 // Forms with the beta / alpha scalar step folded in (ops OP_BETA, OP_ALPHA or
 // OP_ALPHA0 of launch_scalar): one launch instead of two, same values.
 // p <- -z + beta p (partials of g^T p) and q <- -w + beta q over the m rays
@@ -515,7 +512,6 @@ void launch_tv_apply_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src,
 void launch_tv_apply_prep_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, bool copy,
                             bool snorm);
 // cg.hip
-void launch_copy_b(hipStream_t st, const SliceDev* sl, ItemTable t, int src, int dst);
 void launch_init_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // xh = x = x0 (or 0)
 void launch_update_pq_b(hipStream_t st, const SliceDev* sl, ItemTable t);   // BS_PQ items
 void launch_update_x_b(hipStream_t st, const SliceDev* sl, ItemTable t);
