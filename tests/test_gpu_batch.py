@@ -136,6 +136,28 @@ def test_batch_inner_steps_match_single(sp, K):
         assert_same(rb, rs)
 
 
+def test_batch_inner_steps_match_single_large_slice(sp):
+    # from 2^18 pixels up the t_bar launches after an S_TV call's first inner
+    # step and the trials take four pixels per thread, in the single solver's
+    # fused update-and-t_bar kernel as in the batched t_bar kernel: a 512^2
+    # slice next to a small one, K = 3 with rejected trials, bit for bit
+    from synth import random_ellipses
+    geoms = [sp.Geometry(512, 512, 720, 725), sp.Geometry(64, 64, 90, 91)]
+    bs = []
+    for i, g in enumerate(geoms):
+        img, rng = random_ellipses(g.rows, g.cols, 8, 400 + i)
+        b = sp.sp_project(g, torch.from_numpy(img.astype(np.float32)).cuda())
+        noise = torch.from_numpy(rng.standard_normal(g.m).astype(np.float32)).cuda()
+        bs.append((b + 0.01 * float(b.max()) * noise.reshape(b.shape)).contiguous())
+    kw = dict(K=3, a=0.5, gamma=300.0, mu=MU, rho=RHO, max_iter=4)
+    got = sp.sp_suppcg_solve_batched(geoms, bs, graph=True, **kw)
+    want = singles(sp, geoms, bs, graph=True, **kw)
+    for rb, rs in zip(got, want):
+        print(f"k {rb.k}, ell {list(rb.trace['ell'])}", flush=True)
+        assert_same(rb, rs)
+        assert int(rb.trace["ell"][-1]) > 3 * 4   # trials were rejected
+
+
 def test_batch_slice_matches_oracle(sp):
     # the 64 x 64 workload inside a mixed batch, 20 iterations, against the
     # float64 oracle (same bar as the single-slice solver)
